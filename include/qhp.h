@@ -1,0 +1,191 @@
+/*
+ * qhp.h -- C ABI of the MI355X ring-polymer MD / adaptive quantum thermal bath library.
+ *
+ * Method: Ple, Mauger, Adjoua, Jaffrelot-Inizan, Lagardere, Huppert & Piquemal,
+ * "Routine Molecular Dynamics Simulations Including Nuclear Quantum Effects: from Force
+ * Fields to Machine Learning Potentials" (2022).
+ *
+ * A ring polymer of P replicas ("beads") of an N-atom system of flexible 3-site waters.
+ * Bead positions x_i (i = 0..P-1) are propagated in scaled normal modes (Sec. "Ring-Polymer
+ * Molecular Dynamics": eqs. isomorphism_RPMD, matrix_free_RP, beads_positions,
+ * force_normal_modes) with the BAOAB splitting of the TRPMD equations of motion
+ * (Sec. "Integration Scheme", eq. RPMD_EOM). For P = 1 the coloured-noise adaptive quantum
+ * thermal bath may replace the white noise (Secs. "Adaptive Quantum Thermal Bath", "adQTB":
+ * eqs. eq_langevin, Cff_qtb, QTB_spectra; SIMPLE adaptation and the gamma_min clamp).
+ *
+ * Units are the caller's, as long as they are consistent; the library is written for
+ * Angstrom, fs, e, kcal/mol, with masses in kcal/mol * fs^2 / Angstrom^2.
+ *
+ * Layouts at the boundary (row-major, FP64):
+ *   positions, velocities, forces  [P][N][3]
+ *   per-bead energies              [P][QHP_NTERMS]
+ * Molecules are three consecutive atoms O, H, H (atom 3w is the oxygen of water w).
+ *
+ * Ownership: the caller owns every pointer it passes. The library copies what it needs
+ * before returning from qhp_create and keeps no caller pointer afterwards. Arrays passed
+ * to the other calls are read or written during the call only; `mem_kind` says whether
+ * they are host memory (QHP_MEM_HOST) or device memory on the context's GPU
+ * (QHP_MEM_DEVICE). All GPU work is queued on the context's stream; calls that return
+ * data to host memory synchronise that stream, calls writing device memory do not
+ * (use qhp_sync).
+ *
+ * Errors: every call returns QHP_OK (0) or a negative code; qhp_last_error(ctx) gives a
+ * message for the last failure on that context. No C++ exception crosses this ABI.
+ * A context must be used from one host thread at a time.
+ */
+#ifndef QHP_H
+#define QHP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define QHP_OK            0
+#define QHP_EINVAL       -1   /* bad argument (null pointer, sizes, cutoff >= L/2, ...)   */
+#define QHP_ENOMEM       -2   /* device allocation failed or a capacity was exceeded      */
+#define QHP_EDEVICE      -3   /* HIP runtime error; the HIP message is in qhp_last_error  */
+#define QHP_ENONFINITE   -4   /* non-finite input or state                                */
+#define QHP_EUNSUPPORTED -5   /* valid request this build does not implement             */
+
+/* memory kinds */
+#define QHP_MEM_HOST   0
+#define QHP_MEM_DEVICE 1
+
+/* precision of the real-space pair interactions (everything else is FP64) */
+#define QHP_FP64        0
+#define QHP_FP32_PAIRS  1   /* pair forces in FP32 from FP64 displacements; FP64 sums */
+
+/* execution layout */
+#define QHP_BATCHED 0   /* all beads of a step in one launch per kernel, bead innermost */
+#define QHP_PLAIN   1   /* one launch per bead and kernel, as a per-replica MD code   */
+
+/* thermostat */
+#define QHP_TRPMD 0     /* white-noise Langevin on every normal mode                 */
+#define QHP_ADQTB 1     /* adaptive quantum thermal bath (requires P = 1)             */
+
+/* per-bead energy terms */
+#define QHP_E_BOND       0
+#define QHP_E_ANGLE      1
+#define QHP_E_COUL_REAL  2
+#define QHP_E_LJ         3
+#define QHP_E_COUL_EXCL  4
+#define QHP_E_COUL_SELF  5
+#define QHP_E_COUL_RECIP 6
+#define QHP_NTERMS       7
+
+/* Parameters of a run. Host pointers; copied by qhp_create. */
+typedef struct qhp_params {
+  int32_t n_atoms;          /* N, a multiple of 3                                         */
+  int32_t n_beads;          /* P in 1..64                                                 */
+  double box[3];            /* orthorhombic box edges                                     */
+  int32_t n_types;          /* atom types (1..8)                                          */
+  const int32_t* type;      /* [N] type of each atom                                      */
+  const double* mass;       /* [N] mass; must be equal within a type                      */
+  const double* charge;     /* [N]                                                        */
+  const double* lj_sigma;   /* [n_types]; pair sigma = (s_i + s_j) / 2                    */
+  const double* lj_epsilon; /* [n_types]; pair epsilon = sqrt(e_i e_j)                    */
+  double bond_r0, bond_k;          /* E = k/2 (r - r0)^2 for both O-H bonds              */
+  double angle_theta0, angle_k;    /* E = k/2 (theta - theta0)^2 for H-O-H (radians)     */
+  double coulomb;           /* Coulomb constant C in E = C q_i q_j / r                    */
+  double ewald_alpha;       /* Ewald splitting parameter alpha                            */
+  double cutoff;            /* real-space cutoff rc (< half the smallest box edge)        */
+  double skin;              /* neighbour-list skin: r_list = rc + skin                    */
+  int32_t pme_grid[3];      /* SPME grid; powers of two in 8..256, each >= 2*pme_order    */
+  int32_t pme_order;        /* B-spline order n in 3..8                                   */
+  int32_t precision;        /* QHP_FP64 | QHP_FP32_PAIRS                                  */
+  int32_t exec;             /* QHP_BATCHED | QHP_PLAIN                                    */
+  int32_t thermostat;       /* QHP_TRPMD | QHP_ADQTB                                      */
+  double dt;                /* time step                                                  */
+  double kT;                /* k_B T                                                      */
+  double hbar;              /* reduced Planck constant                                    */
+  double gamma_centroid;    /* TRPMD: centroid friction gamma_0                          */
+  double trpmd_c;           /* TRPMD: internal-mode friction max(gamma_0, c * omega_n)   */
+  uint64_t seed;            /* Philox-4x64-10 key word 0                                  */
+  double qtb_gamma0;        /* adQTB: friction gamma_0                                   */
+  int32_t qtb_nseg;         /* adQTB: segment length N_seg (power of two, 16..4096)      */
+  double qtb_adapt_rate;    /* adQTB: SIMPLE rate A_gamma (same for every type)          */
+  double qtb_gamma_min_frac;/* adQTB: gamma_min = frac * gamma_0 (paper default 0.01)    */
+  int32_t qtb_classical;    /* adQTB test switch: Theta(omega) = kT (white-noise limit)  */
+  int32_t nbr_capacity;     /* neighbours per atom kept; 0 = sized from density          */
+} qhp_params;
+
+typedef struct qhp_ctx qhp_ctx;
+
+/* Create a context on the current HIP device. `stream` is a hipStream_t (NULL = the
+ * null stream); all work of the context is queued on it. Validates `p` (QHP_EINVAL),
+ * allocates device state (QHP_ENOMEM) and precomputes the normal-mode transfer matrix,
+ * mode frequencies, thermostat and A-block coefficients and the SPME influence function.
+ * The state is undefined until qhp_set_state. */
+int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out);
+int qhp_destroy(qhp_ctx* ctx);
+
+/* Stateless evaluation of V on every bead (eq. PI_potential summands): `pos` [P][N][3]
+ * -> `energy` [P][QHP_NTERMS] (nullable) and `forces` = -grad V [P][N][3] (nullable).
+ * Builds the centroid neighbour list of these positions (Sec. "Massively Parallel
+ * Implementation": neighbours are found on ring-polymer centroids and shared by all
+ * beads). Does not touch the propagated state. */
+int qhp_eval(qhp_ctx* ctx, const double* pos, double* energy, double* forces, int mem_kind);
+
+/* Set the propagated state from bead positions and bead velocities [P][N][3] and the
+ * step counter (which indexes the noise streams). Computes the normal modes
+ * Q = T^T x / sqrt(P), P_n = m T^T v / sqrt(P) and the forces of this state; for adQTB
+ * `step` must be a multiple of N_seg, gamma is reset to gamma_0 and the coloured noise
+ * of the current segment is generated. */
+int qhp_set_state(qhp_ctx* ctx, const double* pos, const double* vel, int64_t step, int mem_kind);
+
+/* Read the state back as bead positions and velocities [P][N][3] (either nullable). */
+int qhp_get_state(qhp_ctx* ctx, double* pos, double* vel, int64_t* step, int mem_kind);
+
+/* Advance `nsteps` BAOAB steps (B(dt/2) A(dt/2) O(dt) A(dt/2) B(dt/2), one force
+ * evaluation each). For adQTB the spectra, SIMPLE adaptation, clamp and the next noise
+ * segment are computed after the last step of every segment. `energy` (nullable)
+ * receives the per-bead energies of the final state [P][QHP_NTERMS]. Returns QHP_ENOMEM
+ * if the neighbour capacity was exceeded during the call (the state is then invalid),
+ * QHP_ENONFINITE if the state became non-finite. */
+int qhp_step(qhp_ctx* ctx, int32_t nsteps, double* energy, int mem_kind);
+
+/* Kinetic energy sum_n P_n^2 / 2m and free ring-polymer spring energy
+ * sum_n m omega_n^2 Q_n^2 / 2 of the current state (host outputs). */
+int qhp_mode_energies(qhp_ctx* ctx, double* kinetic, double* spring);
+
+/* The centroid pair list of the last build, canonical form: pairs (i, j), i < j,
+ * different molecules, sorted by i then j, written to `pairs` [*npairs][2] (host).
+ * If `capacity` (in pairs) is too small, *npairs is set and QHP_ENOMEM returned. */
+int qhp_nlist_export(qhp_ctx* ctx, int32_t* pairs, int64_t capacity, int64_t* npairs);
+
+/* Gaussian noise as the kernels draw it (Philox-4x64-10, key (seed, stream), Box-Muller):
+ * stream 5 = TRPMD O-step noise of step `step`, out [P][N][3] indexed [mode][atom][xyz];
+ * stream 6 = adQTB white noise of global step `step`, out [N][3]. Device computation,
+ * host output. */
+int qhp_noise_export(qhp_ctx* ctx, int32_t stream, int64_t step, double* out);
+
+/* adQTB: gamma_z(omega_k), k = 0..N_seg, for every type: [n_types][N_seg + 1] (host). */
+int qhp_qtb_get_gamma(qhp_ctx* ctx, double* gamma);
+int qhp_qtb_set_gamma(qhp_ctx* ctx, const double* gamma);
+/* adQTB: the coloured noise of the current segment [N_seg][N][3] and the type-averaged
+ * Delta_FDT of the last completed segment [n_types][N_seg + 1] (host outputs). */
+int qhp_qtb_get_noise(qhp_ctx* ctx, double* noise);
+int qhp_qtb_get_delta(qhp_ctx* ctx, double* delta);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around every launch
+ * of the selected kernel class (0 = off). qhp_profile_read returns the summed milliseconds
+ * and the number of launches since enabling. */
+#define QHP_PROF_OFF    0
+#define QHP_PROF_PAIR   1
+#define QHP_PROF_SPREAD 2
+#define QHP_PROF_FFT    3
+#define QHP_PROF_GATHER 4
+#define QHP_PROF_NM     5
+int qhp_profile(qhp_ctx* ctx, int which);
+int qhp_profile_read(qhp_ctx* ctx, double* ms, int64_t* launches);
+
+int qhp_sync(qhp_ctx* ctx);
+const char* qhp_last_error(qhp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QHP_H */

@@ -1,0 +1,168 @@
+"""Per-bead potential V(x) of the flexible 3-site water model and its gradient.
+
+The paper leaves V to the force field (Sec. "Massively Parallel Implementation": the
+force evaluation is done independently on each bead). The model here is the one the
+workloads fix: harmonic O-H bonds and H-O-H angle, Ewald electrostatics (real space with
+erfc screening inside the cutoff, reciprocal space by SPME in ``oracle/spme.py``, the
+self term and the correction for the three excluded intramolecular pairs) and an O-O
+Lennard-Jones term, all pairs truncated at the cutoff with no shift or tail.
+
+Neighbour pairs are found on ring-polymer *centroids*: two atoms are neighbours for every
+bead if their centroids are (Sec. "Massively Parallel Implementation"). The list is
+defined here by brute force: all intermolecular (i < j) with minimum-image centroid
+distance squared strictly below r_list^2, the squared distance evaluated as
+dx - L rint(dx / L) per axis then dx*dx + dy*dy + dz*dz, with no fused operations.
+
+Energies are returned per term in the order
+[bond, angle, coulomb_real, lennard_jones, coulomb_excluded, coulomb_self, coulomb_recip].
+"""
+import math
+
+import numpy as np
+from scipy.special import erf, erfc
+
+from . import spme as _spme
+
+TERMS = ("bond", "angle", "coul_real", "lj", "coul_excl", "coul_self", "coul_recip")
+
+
+def min_image(d, box):
+    """Minimum-image displacement, axis by axis, round-half-even."""
+    return d - box * np.rint(d / box)
+
+
+def pair_list(centroids, box, r_list, n_per_mol=3):
+    """Brute-force centroid pair list: sorted (i, j) with i < j, different molecules."""
+    N = len(centroids)
+    mol = np.arange(N) // n_per_mol
+    r2max = r_list * r_list
+    I_all, J_all = [], []
+    chunk = max(1, 4_000_000 // max(N, 1))
+    for i0 in range(0, N, chunk):
+        i = np.arange(i0, min(N, i0 + chunk))
+        d = centroids[None, :, :] - centroids[i, None, :]
+        d = d - box * np.rint(d / box)
+        d2 = d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]
+        d2 = d2 + d[..., 2] * d[..., 2]
+        ii, jj = np.nonzero(d2 < r2max)
+        ii = i[ii]
+        keep = (jj > ii) & (mol[jj] != mol[ii])
+        I_all.append(ii[keep]); J_all.append(jj[keep])
+    I = np.concatenate(I_all); J = np.concatenate(J_all)
+    order = np.lexsort((J, I))
+    return np.stack([I[order], J[order]], axis=1).astype(np.int64)
+
+
+def centroids_of(pos):
+    """Centroid of each atom's beads: beads summed in bead order, then divided by P."""
+    c = pos[0].copy()
+    for b in range(1, pos.shape[0]):
+        c = c + pos[b]
+    return c / pos.shape[0]
+
+
+def real_space(x, pairs, charge, types, sigma, eps, box, alpha, rc, coulomb):
+    """Ewald real-space Coulomb and O-O LJ over listed pairs whose bead distance < rc."""
+    i, j = pairs[:, 0], pairs[:, 1]
+    d = min_image(x[j] - x[i], box)
+    r2 = np.einsum("ij,ij->i", d, d)
+    m = r2 < rc * rc
+    i, j, d, r2 = i[m], j[m], d[m], r2[m]
+    r = np.sqrt(r2)
+    qq = coulomb * charge[i] * charge[j]
+    e_c = qq * erfc(alpha * r) / r
+    # dE/dr for the screened Coulomb pair
+    de_c = -qq * (erfc(alpha * r) / r2 + 2.0 * alpha / math.sqrt(math.pi) * np.exp(-alpha * alpha * r2) / r)
+    s = 0.5 * (sigma[types[i]] + sigma[types[j]])
+    e = np.sqrt(eps[types[i]] * eps[types[j]])
+    sr6 = (s * s / r2) ** 3
+    e_lj = 4.0 * e * (sr6 * sr6 - sr6)
+    de_lj = 4.0 * e * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r
+    # gradient wrt x_j is dE/dr * d/r, wrt x_i the opposite
+    gj = ((de_c + de_lj) / r)[:, None] * d
+    grad = np.zeros_like(x)
+    np.add.at(grad, j, gj)
+    np.add.at(grad, i, -gj)
+    return e_c.sum(), e_lj.sum(), grad
+
+
+def intramolecular(x, box, r0, kb, theta0, ktheta):
+    """Harmonic O-H bonds and H-O-H angle of every water (atoms 3w, 3w+1, 3w+2 = O, H, H)."""
+    O, H1, H2 = x[0::3], x[1::3], x[2::3]
+    grad = np.zeros_like(x)
+    e_bond = 0.0
+    unit = []
+    lens = []
+    for k, H in ((1, H1), (2, H2)):
+        d = min_image(H - O, box)
+        r = np.linalg.norm(d, axis=1)
+        e_bond += (0.5 * kb * (r - r0) ** 2).sum()
+        g = (kb * (r - r0) / r)[:, None] * d       # dE/dx_H
+        grad[k::3] += g
+        grad[0::3] -= g
+        unit.append(d / r[:, None]); lens.append(r)
+    u1, u2 = unit
+    r1, r2 = lens
+    cos = np.clip(np.einsum("ij,ij->i", u1, u2), -1.0, 1.0)
+    th = np.arccos(cos)
+    e_angle = (0.5 * ktheta * (th - theta0) ** 2).sum()
+    dE_dth = ktheta * (th - theta0)
+    sin = np.sqrt(1.0 - cos * cos)
+    # d theta / d x_H1 = -(u2 - cos u1) / (r1 sin)
+    g1 = (-dE_dth / (r1 * sin))[:, None] * (u2 - cos[:, None] * u1)
+    g2 = (-dE_dth / (r2 * sin))[:, None] * (u1 - cos[:, None] * u2)
+    grad[1::3] += g1
+    grad[2::3] += g2
+    grad[0::3] -= g1 + g2
+    return e_bond, e_angle, grad
+
+
+def excluded_correction(x, charge, box, alpha, coulomb):
+    """Remove the screened-Gaussian interaction of the 3 intramolecular pairs that the
+    reciprocal sum includes: -C q_a q_b erf(alpha r) / r per pair."""
+    grad = np.zeros_like(x)
+    e_tot = 0.0
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        d = min_image(x[b::3] - x[a::3], box)
+        r2 = np.einsum("ij,ij->i", d, d)
+        r = np.sqrt(r2)
+        qq = coulomb * charge[a::3] * charge[b::3]
+        e_tot += (-qq * erf(alpha * r) / r).sum()
+        de = -qq * (2.0 * alpha / math.sqrt(math.pi) * np.exp(-alpha * alpha * r2) / r - erf(alpha * r) / r2)
+        g = (de / r)[:, None] * d
+        grad[b::3] += g
+        grad[a::3] -= g
+    return e_tot, grad
+
+
+def self_energy(charge, alpha, coulomb):
+    """Ewald self term -C alpha / sqrt(pi) sum q^2."""
+    return -coulomb * alpha / math.sqrt(math.pi) * float(np.sum(charge * charge))
+
+
+def bead_potential(x, s, pairs):
+    """All terms of V at one bead configuration x [N][3] -> (energies[7], grad [N][3])."""
+    box = s.box
+    e_b, e_a, g_in = intramolecular(x, box, s.bond_r0, s.bond_k, s.angle_theta0, s.angle_k)
+    e_c, e_lj, g_rs = real_space(x, pairs, s.charge, s.types, s.lj_sigma, s.lj_epsilon,
+                                 box, s.ewald_alpha, s.cutoff, s.coulomb)
+    e_x, g_x = excluded_correction(x, s.charge, box, s.ewald_alpha, s.coulomb)
+    e_s = self_energy(s.charge, s.ewald_alpha, s.coulomb)
+    e_r, g_r = _spme.spme(x, s.charge, box, s.pme_grid, s.pme_order, s.ewald_alpha, s.coulomb)
+    E = np.array([e_b, e_a, e_c, e_lj, e_x, e_s, e_r])
+    return E, g_in + g_rs + g_x + g_r
+
+
+def evaluate(pos, s, r_list=None):
+    """Energies [P][7] and forces -grad V [P][N][3] of every bead, pair list built on the
+    centroids of ``pos`` with r_list = cutoff + skin (or the given r_list)."""
+    if r_list is None:
+        r_list = s.cutoff + s.skin
+    pairs = pair_list(centroids_of(pos), s.box, r_list)
+    P = pos.shape[0]
+    E = np.zeros((P, len(TERMS)))
+    F = np.zeros_like(pos)
+    for b in range(P):
+        E[b], g = bead_potential(pos[b], s, pairs)
+        F[b] = -g
+    return E, F
