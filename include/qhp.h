@@ -38,6 +38,12 @@
 
 #include <stdint.h>
 
+#if defined(__GNUC__)
+#define QHP_API __attribute__((visibility("default")))
+#else
+#define QHP_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -119,25 +125,25 @@ typedef struct qhp_ctx qhp_ctx;
  * allocates device state (QHP_ENOMEM) and precomputes the normal-mode transfer matrix,
  * mode frequencies, thermostat and A-block coefficients and the SPME influence function.
  * The state is undefined until qhp_set_state. */
-int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out);
-int qhp_destroy(qhp_ctx* ctx);
+QHP_API int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out);
+QHP_API int qhp_destroy(qhp_ctx* ctx);
 
 /* Stateless evaluation of V on every bead (eq. PI_potential summands): `pos` [P][N][3]
  * -> `energy` [P][QHP_NTERMS] (nullable) and `forces` = -grad V [P][N][3] (nullable).
  * Builds the centroid neighbour list of these positions (Sec. "Massively Parallel
  * Implementation": neighbours are found on ring-polymer centroids and shared by all
  * beads). Does not touch the propagated state. */
-int qhp_eval(qhp_ctx* ctx, const double* pos, double* energy, double* forces, int mem_kind);
+QHP_API int qhp_eval(qhp_ctx* ctx, const double* pos, double* energy, double* forces, int mem_kind);
 
 /* Set the propagated state from bead positions and bead velocities [P][N][3] and the
  * step counter (which indexes the noise streams). Computes the normal modes
  * Q = T^T x / sqrt(P), P_n = m T^T v / sqrt(P) and the forces of this state; for adQTB
  * `step` must be a multiple of N_seg, gamma is reset to gamma_0 and the coloured noise
  * of the current segment is generated. */
-int qhp_set_state(qhp_ctx* ctx, const double* pos, const double* vel, int64_t step, int mem_kind);
+QHP_API int qhp_set_state(qhp_ctx* ctx, const double* pos, const double* vel, int64_t step, int mem_kind);
 
 /* Read the state back as bead positions and velocities [P][N][3] (either nullable). */
-int qhp_get_state(qhp_ctx* ctx, double* pos, double* vel, int64_t* step, int mem_kind);
+QHP_API int qhp_get_state(qhp_ctx* ctx, double* pos, double* vel, int64_t* step, int mem_kind);
 
 /* Advance `nsteps` BAOAB steps (B(dt/2) A(dt/2) O(dt) A(dt/2) B(dt/2), one force
  * evaluation each). For adQTB the spectra, SIMPLE adaptation, clamp and the next noise
@@ -145,30 +151,30 @@ int qhp_get_state(qhp_ctx* ctx, double* pos, double* vel, int64_t* step, int mem
  * receives the per-bead energies of the final state [P][QHP_NTERMS]. Returns QHP_ENOMEM
  * if the neighbour capacity was exceeded during the call (the state is then invalid),
  * QHP_ENONFINITE if the state became non-finite. */
-int qhp_step(qhp_ctx* ctx, int32_t nsteps, double* energy, int mem_kind);
+QHP_API int qhp_step(qhp_ctx* ctx, int32_t nsteps, double* energy, int mem_kind);
 
 /* Kinetic energy sum_n P_n^2 / 2m and free ring-polymer spring energy
  * sum_n m omega_n^2 Q_n^2 / 2 of the current state (host outputs). */
-int qhp_mode_energies(qhp_ctx* ctx, double* kinetic, double* spring);
+QHP_API int qhp_mode_energies(qhp_ctx* ctx, double* kinetic, double* spring);
 
 /* The centroid pair list of the last build, canonical form: pairs (i, j), i < j,
  * different molecules, sorted by i then j, written to `pairs` [*npairs][2] (host).
  * If `capacity` (in pairs) is too small, *npairs is set and QHP_ENOMEM returned. */
-int qhp_nlist_export(qhp_ctx* ctx, int32_t* pairs, int64_t capacity, int64_t* npairs);
+QHP_API int qhp_nlist_export(qhp_ctx* ctx, int32_t* pairs, int64_t capacity, int64_t* npairs);
 
 /* Gaussian noise as the kernels draw it (Philox-4x64-10, key (seed, stream), Box-Muller):
  * stream 5 = TRPMD O-step noise of step `step`, out [P][N][3] indexed [mode][atom][xyz];
  * stream 6 = adQTB white noise of global step `step`, out [N][3]. Device computation,
  * host output. */
-int qhp_noise_export(qhp_ctx* ctx, int32_t stream, int64_t step, double* out);
+QHP_API int qhp_noise_export(qhp_ctx* ctx, int32_t stream, int64_t step, double* out);
 
 /* adQTB: gamma_z(omega_k), k = 0..N_seg, for every type: [n_types][N_seg + 1] (host). */
-int qhp_qtb_get_gamma(qhp_ctx* ctx, double* gamma);
-int qhp_qtb_set_gamma(qhp_ctx* ctx, const double* gamma);
+QHP_API int qhp_qtb_get_gamma(qhp_ctx* ctx, double* gamma);
+QHP_API int qhp_qtb_set_gamma(qhp_ctx* ctx, const double* gamma);
 /* adQTB: the coloured noise of the current segment [N_seg][N][3] and the type-averaged
  * Delta_FDT of the last completed segment [n_types][N_seg + 1] (host outputs). */
-int qhp_qtb_get_noise(qhp_ctx* ctx, double* noise);
-int qhp_qtb_get_delta(qhp_ctx* ctx, double* delta);
+QHP_API int qhp_qtb_get_noise(qhp_ctx* ctx, double* noise);
+QHP_API int qhp_qtb_get_delta(qhp_ctx* ctx, double* delta);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around every launch
  * of the selected kernel class (0 = off). qhp_profile_read returns the summed milliseconds
@@ -179,11 +185,11 @@ int qhp_qtb_get_delta(qhp_ctx* ctx, double* delta);
 #define QHP_PROF_FFT    3
 #define QHP_PROF_GATHER 4
 #define QHP_PROF_NM     5
-int qhp_profile(qhp_ctx* ctx, int which);
-int qhp_profile_read(qhp_ctx* ctx, double* ms, int64_t* launches);
+QHP_API int qhp_profile(qhp_ctx* ctx, int which);
+QHP_API int qhp_profile_read(qhp_ctx* ctx, double* ms, int64_t* launches);
 
-int qhp_sync(qhp_ctx* ctx);
-const char* qhp_last_error(qhp_ctx* ctx);
+QHP_API int qhp_sync(qhp_ctx* ctx);
+QHP_API const char* qhp_last_error(qhp_ctx* ctx);
 
 #ifdef __cplusplus
 }

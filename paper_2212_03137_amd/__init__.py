@@ -1,0 +1,262 @@
+"""Python binding of libqhp (the MI355X ring-polymer MD / adaptive QTB library).
+
+Argument marshalling only: every computation runs in the HIP kernels behind the C ABI
+declared in ``include/qhp.h``. Importing this package fails loudly when the compiled
+library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqhp.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+MEM_HOST, MEM_DEVICE = 0, 1
+FP64, FP32_PAIRS = 0, 1
+BATCHED, PLAIN = 0, 1
+TRPMD, ADQTB = 0, 1
+NTERMS = 7
+TERMS = ("bond", "angle", "coul_real", "lj", "coul_excl", "coul_self", "coul_recip")
+PROF = {"off": 0, "pair": 1, "spread": 2, "fft": 3, "gather": 4, "nm": 5}
+
+EXPORTS = ("qhp_create", "qhp_destroy", "qhp_eval", "qhp_set_state", "qhp_get_state",
+           "qhp_step", "qhp_mode_energies", "qhp_nlist_export", "qhp_noise_export",
+           "qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta",
+           "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error")
+
+
+class QhpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qhp error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_atoms", C.c_int32), ("n_beads", C.c_int32), ("box", C.c_double * 3),
+        ("n_types", C.c_int32), ("type", C.POINTER(C.c_int32)), ("mass", C.POINTER(C.c_double)),
+        ("charge", C.POINTER(C.c_double)), ("lj_sigma", C.POINTER(C.c_double)),
+        ("lj_epsilon", C.POINTER(C.c_double)),
+        ("bond_r0", C.c_double), ("bond_k", C.c_double),
+        ("angle_theta0", C.c_double), ("angle_k", C.c_double),
+        ("coulomb", C.c_double), ("ewald_alpha", C.c_double), ("cutoff", C.c_double),
+        ("skin", C.c_double), ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32),
+        ("precision", C.c_int32), ("exec", C.c_int32), ("thermostat", C.c_int32),
+        ("dt", C.c_double), ("kT", C.c_double), ("hbar", C.c_double),
+        ("gamma_centroid", C.c_double), ("trpmd_c", C.c_double), ("seed", C.c_uint64),
+        ("qtb_gamma0", C.c_double), ("qtb_nseg", C.c_int32), ("qtb_adapt_rate", C.c_double),
+        ("qtb_gamma_min_frac", C.c_double), ("qtb_classical", C.c_int32),
+        ("nbr_capacity", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libqhp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: build it with "
+                          "`python -m paper_2212_03137_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, I, D, vp = C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p
+    lib.qhp_create.argtypes = [C.POINTER(Params), vp, C.POINTER(vp)]
+    lib.qhp_destroy.argtypes = [vp]
+    lib.qhp_eval.argtypes = [vp, vp, vp, vp, I]
+    lib.qhp_set_state.argtypes = [vp, vp, vp, C.c_int64, I]
+    lib.qhp_get_state.argtypes = [vp, vp, vp, C.POINTER(C.c_int64), I]
+    lib.qhp_step.argtypes = [vp, C.c_int32, vp, I]
+    lib.qhp_mode_energies.argtypes = [vp, D, D]
+    lib.qhp_nlist_export.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.qhp_noise_export.argtypes = [vp, C.c_int32, C.c_int64, vp]
+    for f in ("qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta"):
+        getattr(lib, f).argtypes = [vp, vp]
+    lib.qhp_profile.argtypes = [vp, I]
+    lib.qhp_profile_read.argtypes = [vp, D, C.POINTER(C.c_int64)]
+    lib.qhp_sync.argtypes = [vp]
+    lib.qhp_last_error.argtypes = [vp]
+    lib.qhp_last_error.restype = C.c_char_p
+    for f in EXPORTS:
+        if f != "qhp_last_error":
+            getattr(lib, f).restype = I
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(a.data_ptr())      # torch tensor on the device
+
+
+class Context:
+    """One simulation context (owns the device state of P beads of N atoms)."""
+
+    def __init__(self, *, n_atoms, n_beads, box, types, mass, charge, lj_sigma, lj_epsilon,
+                 bond_r0, bond_k, angle_theta0, angle_k, coulomb, ewald_alpha, cutoff, skin,
+                 pme_grid, pme_order, dt, kT, hbar, gamma_centroid=0.0, trpmd_c=2.0, seed=0,
+                 precision=FP64, exec_mode=BATCHED, thermostat=TRPMD, qtb_gamma0=0.0,
+                 qtb_nseg=1024, qtb_adapt_rate=0.0, qtb_gamma_min_frac=0.01, qtb_classical=False,
+                 nbr_capacity=0, stream=None):
+        self._lib = load()
+        self.N, self.P = int(n_atoms), int(n_beads)
+        self.n_types = len(lj_sigma)
+        self.nseg = int(qtb_nseg)
+        self._keep = [np.ascontiguousarray(types, dtype=np.int32),
+                      np.ascontiguousarray(mass, dtype=np.float64),
+                      np.ascontiguousarray(charge, dtype=np.float64),
+                      np.ascontiguousarray(lj_sigma, dtype=np.float64),
+                      np.ascontiguousarray(lj_epsilon, dtype=np.float64)]
+        t, m, q, s, e = self._keep
+        p = Params()
+        p.n_atoms, p.n_beads = self.N, self.P
+        p.box = (C.c_double * 3)(*[float(v) for v in box])
+        p.n_types = self.n_types
+        p.type = t.ctypes.data_as(C.POINTER(C.c_int32))
+        p.mass = m.ctypes.data_as(C.POINTER(C.c_double))
+        p.charge = q.ctypes.data_as(C.POINTER(C.c_double))
+        p.lj_sigma = s.ctypes.data_as(C.POINTER(C.c_double))
+        p.lj_epsilon = e.ctypes.data_as(C.POINTER(C.c_double))
+        p.bond_r0, p.bond_k, p.angle_theta0, p.angle_k = bond_r0, bond_k, angle_theta0, angle_k
+        p.coulomb, p.ewald_alpha, p.cutoff, p.skin = coulomb, ewald_alpha, cutoff, skin
+        p.pme_grid = (C.c_int32 * 3)(*[int(k) for k in pme_grid])
+        p.pme_order = pme_order
+        p.precision, p.exec, p.thermostat = precision, exec_mode, thermostat
+        p.dt, p.kT, p.hbar = dt, kT, hbar
+        p.gamma_centroid, p.trpmd_c, p.seed = gamma_centroid, trpmd_c, int(seed)
+        p.qtb_gamma0, p.qtb_nseg, p.qtb_adapt_rate = qtb_gamma0, self.nseg, qtb_adapt_rate
+        p.qtb_gamma_min_frac, p.qtb_classical = qtb_gamma_min_frac, int(bool(qtb_classical))
+        p.nbr_capacity = nbr_capacity
+        self.params = p
+        h = C.c_void_p()
+        rc = self._lib.qhp_create(C.byref(p), C.c_void_p(stream) if stream else None, C.byref(h))
+        if rc != OK:
+            raise QhpError(rc, "qhp_create failed")
+        self._h = h
+
+    @classmethod
+    def from_system(cls, s, **kw):
+        """Build from any object carrying the fields of ``synth.System``."""
+        args = dict(n_atoms=s.n_atoms, n_beads=s.n_beads, box=s.box, types=s.types, mass=s.mass,
+                    charge=s.charge, lj_sigma=s.lj_sigma, lj_epsilon=s.lj_epsilon,
+                    bond_r0=s.bond_r0, bond_k=s.bond_k, angle_theta0=s.angle_theta0,
+                    angle_k=s.angle_k, coulomb=s.coulomb, ewald_alpha=s.ewald_alpha,
+                    cutoff=s.cutoff, skin=s.skin, pme_grid=s.pme_grid, pme_order=s.pme_order,
+                    dt=s.dt, kT=s.kT, hbar=s.hbar, gamma_centroid=s.gamma_centroid,
+                    trpmd_c=s.trpmd_c, seed=s.seed, qtb_gamma0=s.qtb_gamma0,
+                    qtb_nseg=s.qtb_nseg, qtb_adapt_rate=s.qtb_adapt_rate,
+                    qtb_gamma_min_frac=s.qtb_gamma_min_frac)
+        args.update(kw)
+        return cls(**args)
+
+    # ------------------------------------------------------------------------------
+    def _check(self, rc):
+        if rc != OK:
+            raise QhpError(rc, self._lib.qhp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.qhp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------------------
+    def eval(self, pos):
+        """Per-bead energies [P][7] and forces -grad V [P][N][3] (host arrays)."""
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        E = np.zeros((self.P, NTERMS))
+        F = np.zeros((self.P, self.N, 3))
+        self._check(self._lib.qhp_eval(self._h, _ptr(pos), _ptr(E), _ptr(F), MEM_HOST))
+        return E, F
+
+    def set_state(self, pos, vel, step=0):
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        self._check(self._lib.qhp_set_state(self._h, _ptr(pos), _ptr(vel), int(step), MEM_HOST))
+
+    def get_state(self):
+        pos = np.zeros((self.P, self.N, 3))
+        vel = np.zeros((self.P, self.N, 3))
+        st = C.c_int64()
+        self._check(self._lib.qhp_get_state(self._h, _ptr(pos), _ptr(vel), C.byref(st), MEM_HOST))
+        return pos, vel, st.value
+
+    def step(self, n=1, energy=False):
+        E = np.zeros((self.P, NTERMS)) if energy else None
+        self._check(self._lib.qhp_step(self._h, int(n), _ptr(E), MEM_HOST))
+        return E
+
+    def mode_energies(self):
+        k, s = C.c_double(), C.c_double()
+        self._check(self._lib.qhp_mode_energies(self._h, C.byref(k), C.byref(s)))
+        return k.value, s.value
+
+    def nlist(self):
+        n = C.c_int64()
+        self._check(self._lib.qhp_nlist_export(self._h, None, 0, C.byref(n)))
+        out = np.zeros((n.value, 2), dtype=np.int32)
+        self._check(self._lib.qhp_nlist_export(self._h, _ptr(out), n.value, C.byref(n)))
+        return out.astype(np.int64)
+
+    def noise(self, stream, step):
+        rows = self.P if stream == 5 else 1
+        out = np.zeros((rows, self.N, 3))
+        self._check(self._lib.qhp_noise_export(self._h, int(stream), int(step), _ptr(out)))
+        return out if stream == 5 else out[0]
+
+    def qtb_gamma(self):
+        out = np.zeros((self.n_types, self.nseg + 1))
+        self._check(self._lib.qhp_qtb_get_gamma(self._h, _ptr(out)))
+        return out
+
+    def qtb_set_gamma(self, g):
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        self._check(self._lib.qhp_qtb_set_gamma(self._h, _ptr(g)))
+
+    def qtb_noise(self):
+        out = np.zeros((self.nseg, self.N, 3))
+        self._check(self._lib.qhp_qtb_get_noise(self._h, _ptr(out)))
+        return out
+
+    def qtb_delta(self):
+        out = np.zeros((self.n_types, self.nseg + 1))
+        self._check(self._lib.qhp_qtb_get_delta(self._h, _ptr(out)))
+        return out
+
+    def profile(self, which):
+        self._check(self._lib.qhp_profile(self._h, PROF[which] if isinstance(which, str) else which))
+
+    def profile_read(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self._lib.qhp_profile_read(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def sync(self):
+        self._check(self._lib.qhp_sync(self._h))
+
+    # device-memory variants (torch tensors on the context's device)
+    def step_device(self, n, energy_tensor=None):
+        self._check(self._lib.qhp_step(self._h, int(n), _ptr(energy_tensor), MEM_DEVICE))
+
+    def eval_device(self, pos, energy, forces):
+        self._check(self._lib.qhp_eval(self._h, _ptr(pos), _ptr(energy), _ptr(forces), MEM_DEVICE))

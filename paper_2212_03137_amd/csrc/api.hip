@@ -1,0 +1,611 @@
+// C ABI of the library: context set-up, host-side precomputation (normal-mode transfer
+// matrix and coefficients, SPME influence function, cell stencils), the force pipeline,
+// stepping, and state and diagnostic transfers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <set>
+
+#include "qhp_internal.h"
+
+hipError_t qtb_build_kernels(qhp_ctx* c);
+
+int qhp_fail(qhp_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+void prof_begin(qhp_ctx* c, int which, hipEvent_t* ev) {
+  *ev = nullptr;
+  if (c->prof_which != which) return;
+  if (hipEventCreate(ev) != hipSuccess) { *ev = nullptr; return; }
+  (void)hipEventRecord(*ev, c->stream);
+}
+
+void prof_end(qhp_ctx* c, int which, hipEvent_t ev) {
+  if (c->prof_which != which || !ev) return;
+  hipEvent_t e2;
+  if (hipEventCreate(&e2) != hipSuccess) return;
+  (void)hipEventRecord(e2, c->stream);
+  c->ev_pending.emplace_back(ev, e2);
+}
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Free ring-polymer modes: T[j][n] real Fourier basis (column 0 = 1/sqrt(P); pairs of
+// cos/sin columns for 1 <= k < P/2 with frequency 2 (P / beta hbar) sin(pi k / P); the
+// alternating column last for even P), the eigenvectors of the cyclic second-difference
+// matrix of eq. matrix_free_RP in order of increasing frequency.
+void normal_modes(int P, double beta, double hbar, std::vector<double>& T, std::vector<double>& w) {
+  T.assign((size_t)P * P, 0.0);
+  w.assign(P, 0.0);
+  const double wP = P / (beta * hbar);
+  for (int j = 0; j < P; ++j) T[j * P + 0] = 1.0 / std::sqrt((double)P);
+  for (int k = 1; 2 * k < P; ++k) {
+    for (int j = 0; j < P; ++j) {
+      const double ang = 2.0 * M_PI * j * k / P;
+      T[j * P + 2 * k - 1] = std::sqrt(2.0 / P) * std::cos(ang);
+      T[j * P + 2 * k] = std::sqrt(2.0 / P) * std::sin(ang);
+    }
+    w[2 * k - 1] = w[2 * k] = 2.0 * wP * std::sin(M_PI * k / P);
+  }
+  if (P % 2 == 0 && P > 1) {
+    for (int j = 0; j < P; ++j) T[j * P + P - 1] = ((j % 2) ? -1.0 : 1.0) / std::sqrt((double)P);
+    w[P - 1] = 2.0 * wP;
+  }
+}
+
+// Cardinal B-spline M_n at integer points 1..n-1 (recursion of Essmann et al. 1995).
+double bspline_at(int n, double x) {
+  if (n == 2) return (x >= 0 && x <= 2) ? 1.0 - std::fabs(x - 1.0) : 0.0;
+  return x / (n - 1) * bspline_at(n - 1, x) + (n - x) / (n - 1) * bspline_at(n - 1, x - 1.0);
+}
+
+// |b(m)|^2 = 1 / |sum_{k=0}^{n-2} M_n(k+1) e^{2 pi i m k / K}|^2; a vanishing denominator
+// (odd n, m = K/2) takes the neighbouring value.
+std::vector<double> bmod(int K, int n) {
+  std::vector<double> out(K);
+  for (int m = 0; m < K; ++m) {
+    double re = 0, im = 0;
+    for (int k = 0; k <= n - 2; ++k) {
+      const double Mk = bspline_at(n, k + 1.0);
+      re += Mk * std::cos(2.0 * M_PI * m * k / K);
+      im += Mk * std::sin(2.0 * M_PI * m * k / K);
+    }
+    const double den = re * re + im * im;
+    out[m] = den < 1e-10 ? out[m > 0 ? m - 1 : 0] : 1.0 / den;
+  }
+  return out;
+}
+
+void free_all(qhp_ctx* c) {
+  void* ptrs[] = {c->T, c->mode_c, c->mode_s_w, c->mode_ws, c->mode_c1, c->mode_c2, c->mode_w2,
+                  c->d_type, c->d_mass, c->d_charge, c->d_sqrt_mkT, c->d_sigma, c->d_eps,
+                  c->Q, c->Pa, c->x, c->g, c->cent, c->cref, c->coff, c->cwrap, c->xf, c->ctrl,
+                  c->cell_of, c->cell_count, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
+                  c->nnbr, c->grid, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
+                  c->io_a, c->io_b, c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
+                  c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.d_tmass, c->qtb.d_inv_count,
+                  c->qtb.tw2, c->qtb.tw4};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto& pr : c->ev_pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+  c->ev_pending.clear();
+}
+
+hipError_t upload_twiddles(double2** dst, int L) {
+  std::vector<double2> t(L);
+  for (int m = 0; m < L; ++m) t[m] = make_double2(std::cos(2.0 * M_PI * m / L), -std::sin(2.0 * M_PI * m / L));
+  hipError_t e = dalloc(dst, L);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, t.data(), L * sizeof(double2), hipMemcpyHostToDevice);
+}
+
+int validate(const qhp_params* p, std::string& why) {
+  auto bad = [&](const std::string& s) { why = s; return QHP_EINVAL; };
+  if (!p) return bad("null params");
+  if (p->n_atoms < 3 || p->n_atoms % 3) return bad("n_atoms must be a positive multiple of 3");
+  if (p->n_atoms >= (1 << 26)) return bad("n_atoms must be < 2^26");
+  if (p->n_beads < 1 || p->n_beads > 64) return bad("n_beads must be in 1..64");
+  if (!pow2(p->n_beads)) { why = "n_beads must be a power of two"; return QHP_EUNSUPPORTED; }
+  if (!p->type || !p->mass || !p->charge || !p->lj_sigma || !p->lj_epsilon) return bad("null array");
+  if (p->n_types < 1 || p->n_types > QHP_MAX_TYPES) return bad("n_types must be in 1..8");
+  for (int d = 0; d < 3; ++d)
+    if (!(p->box[d] > 0) || !std::isfinite(p->box[d])) return bad("box edges must be positive");
+  const double Lmin = std::min(p->box[0], std::min(p->box[1], p->box[2]));
+  if (!(p->cutoff > 0) || !(p->cutoff < 0.5 * Lmin)) return bad("cutoff must be in (0, L/2)");
+  if (!(p->skin >= 0)) return bad("skin must be >= 0");
+  if (!(p->ewald_alpha > 0) || !(p->coulomb > 0)) return bad("alpha and coulomb must be positive");
+  if (p->pme_order != 4 && p->pme_order != 5 && p->pme_order != 6 && p->pme_order != 8) {
+    why = "pme_order must be 4, 5, 6 or 8";
+    return p->pme_order >= 3 && p->pme_order <= 8 ? QHP_EUNSUPPORTED : QHP_EINVAL;
+  }
+  for (int d = 0; d < 3; ++d) {
+    const int K = p->pme_grid[d];
+    if (!pow2(K) || K < 8 || K > 256) return bad("pme_grid must be powers of two in 8..256");
+    if (K < 2 * p->pme_order) return bad("pme_grid must be >= 2 * pme_order");
+  }
+  if (p->precision != QHP_FP64 && p->precision != QHP_FP32_PAIRS) return bad("precision");
+  if (p->exec != QHP_BATCHED && p->exec != QHP_PLAIN) return bad("exec");
+  if (p->thermostat != QHP_TRPMD && p->thermostat != QHP_ADQTB) return bad("thermostat");
+  if (!(p->dt > 0) || !(p->kT > 0) || !(p->hbar > 0)) return bad("dt, kT and hbar must be positive");
+  if (p->thermostat == QHP_TRPMD && (!(p->gamma_centroid >= 0) || !(p->trpmd_c >= 0)))
+    return bad("friction must be >= 0");
+  for (int i = 0; i < p->n_atoms; ++i) {
+    if (p->type[i] < 0 || p->type[i] >= p->n_types) return bad("atom type out of range");
+    if (!(p->mass[i] > 0) || !std::isfinite(p->charge[i])) return bad("masses > 0, finite charges");
+  }
+  if (p->thermostat == QHP_ADQTB) {
+    if (p->n_beads != 1) return bad("adQTB requires n_beads = 1");
+    if (!pow2(p->qtb_nseg) || p->qtb_nseg < 16 || p->qtb_nseg > 1024)
+      return bad("qtb_nseg must be a power of two in 16..1024");
+    if (!(p->qtb_gamma0 > 0) || !(p->qtb_gamma_min_frac >= 0)) return bad("qtb gamma");
+    for (int i = 0; i < p->n_atoms; ++i)
+      for (int j = 0; j < i; ++j)
+        if (p->type[i] == p->type[j] && p->mass[i] != p->mass[j])
+          return bad("adQTB needs one mass per atom type");
+  }
+  return QHP_OK;
+}
+
+}  // namespace
+
+#define TRY(call)                                                              \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      std::string m_ = std::string(#call) + ": " + hipGetErrorString(e_);      \
+      free_all(c); delete c;                                                   \
+      return e_ == hipErrorOutOfMemory ? QHP_ENOMEM : QHP_EDEVICE;             \
+    }                                                                          \
+  } while (0)
+
+extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
+  if (!out) return QHP_EINVAL;
+  *out = nullptr;
+  std::string why;
+  int v = validate(p, why);
+  if (v != QHP_OK) return v;
+  qhp_ctx* c = new (std::nothrow) qhp_ctx();
+  if (!c) return QHP_ENOMEM;
+  c->p = *p;
+  c->stream = (hipStream_t)stream;
+  const int N = p->n_atoms, P = p->n_beads;
+  c->N = N; c->P = P; c->NW = N / 3; c->Pc = P == 1 ? 1 : P / 2;
+  c->type.assign(p->type, p->type + N);
+  c->mass.assign(p->mass, p->mass + N);
+  c->charge.assign(p->charge, p->charge + N);
+  c->sigma.assign(p->lj_sigma, p->lj_sigma + p->n_types);
+  c->eps.assign(p->lj_epsilon, p->lj_epsilon + p->n_types);
+  for (int d = 0; d < 3; ++d) c->K[d] = p->pme_grid[d];
+  const bool plain = p->exec == QHP_PLAIN;
+  const int Pc_grid = plain ? 1 : c->Pc;
+  for (int d = 0; d < 3; ++d) {
+    const long series = (long)c->K[0] * c->K[1] * c->K[2] * Pc_grid / c->K[d];
+    if (series % (4096 / c->K[d])) {
+      delete c;
+      return QHP_EUNSUPPORTED;
+    }
+  }
+
+  // ---- normal modes and per-mode coefficients (host, FP64) ----
+  std::vector<double> T, w;
+  normal_modes(P, 1.0 / p->kT, p->hbar, T, w);
+  c->h_omega = w;
+  const double h = 0.5 * p->dt;
+  std::vector<double> mc(P), msw(P), mws(P), mc1(P), mc2(P), mw2(P);
+  for (int n = 0; n < P; ++n) {
+    mc[n] = std::cos(w[n] * h);
+    msw[n] = w[n] > 0 ? std::sin(w[n] * h) / w[n] : h;
+    mws[n] = w[n] * std::sin(w[n] * h);
+    const double gam = std::max(p->gamma_centroid, p->trpmd_c * w[n]);
+    mc1[n] = std::exp(-gam * p->dt);
+    mc2[n] = std::sqrt(1.0 - mc1[n] * mc1[n]);
+    mw2[n] = w[n] * w[n];
+  }
+  auto up = [&](double** dst, const std::vector<double>& src) -> hipError_t {
+    hipError_t e = dalloc(dst, src.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice);
+  };
+  TRY(up(&c->T, T));
+  TRY(up(&c->mode_c, mc)); TRY(up(&c->mode_s_w, msw)); TRY(up(&c->mode_ws, mws));
+  TRY(up(&c->mode_c1, mc1)); TRY(up(&c->mode_c2, mc2)); TRY(up(&c->mode_w2, mw2));
+
+  // ---- per-atom data ----
+  std::vector<double> smkT(N);
+  for (int i = 0; i < N; ++i) smkT[i] = std::sqrt(c->mass[i] * p->kT);
+  TRY(dalloc(&c->d_type, N));
+  TRY(hipMemcpy(c->d_type, c->type.data(), N * sizeof(int), hipMemcpyHostToDevice));
+  TRY(up(&c->d_mass, c->mass)); TRY(up(&c->d_charge, c->charge)); TRY(up(&c->d_sqrt_mkT, smkT));
+  TRY(up(&c->d_sigma, c->sigma)); TRY(up(&c->d_eps, c->eps));
+  double q2 = 0;
+  for (int i = 0; i < N; ++i) q2 += c->charge[i] * c->charge[i];
+  c->self_energy = -p->coulomb * p->ewald_alpha / std::sqrt(M_PI) * q2;
+
+  // ---- state ----
+  const size_t NP3 = (size_t)3 * N * P;
+  TRY(dalloc(&c->Q, NP3)); TRY(dalloc(&c->Pa, NP3)); TRY(dalloc(&c->x, NP3)); TRY(dalloc(&c->g, NP3));
+  TRY(dalloc(&c->cent, N)); TRY(dalloc(&c->cref, N)); TRY(dalloc(&c->coff, N)); TRY(dalloc(&c->cwrap, N));
+  TRY(dalloc(&c->xf, (size_t)N * P));
+  TRY(dalloc(&c->io_a, NP3)); TRY(dalloc(&c->io_b, NP3));
+  TRY(dalloc(&c->energy, (size_t)P * QHP_NTERMS));
+  TRY(hipMemset(c->energy, 0, (size_t)P * QHP_NTERMS * sizeof(double)));
+  TRY(hipMemset(c->cref, 0, N * sizeof(double4)));
+  TRY(hipMemset(c->coff, 0, N * sizeof(double4)));
+
+  // ---- neighbour list: cells of edge >= r_list (a small margin keeps rounding of the
+  //      fractional coordinate from skipping a cell) and their distinct neighbour cells ----
+  c->rlist = p->cutoff + p->skin;
+  for (int d = 0; d < 3; ++d) {
+    int n = std::max(1, (int)std::floor(p->box[d] / c->rlist));
+    while (n > 1 && p->box[d] / n < c->rlist * (1.0 + 1e-9)) --n;
+    c->nc[d] = n;
+  }
+  c->ncell = c->nc[0] * c->nc[1] * c->nc[2];
+  std::vector<int> st((size_t)c->ncell * 27, -1);
+  for (int a = 0; a < c->nc[0]; ++a)
+    for (int b = 0; b < c->nc[1]; ++b)
+      for (int e = 0; e < c->nc[2]; ++e) {
+        std::set<int> s;
+        for (int da = -1; da <= 1; ++da)
+          for (int db = -1; db <= 1; ++db)
+            for (int de = -1; de <= 1; ++de) {
+              const int ia = (a + da + c->nc[0]) % c->nc[0], ib = (b + db + c->nc[1]) % c->nc[1],
+                        ie = (e + de + c->nc[2]) % c->nc[2];
+              s.insert((ia * c->nc[1] + ib) * c->nc[2] + ie);
+            }
+        int k = 0;
+        const int id = (a * c->nc[1] + b) * c->nc[2] + e;
+        for (int v2 : s) st[(size_t)id * 27 + k++] = v2;
+      }
+  TRY(dalloc(&c->stencil, st.size()));
+  TRY(hipMemcpy(c->stencil, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice));
+  const double V = p->box[0] * p->box[1] * p->box[2];
+  if (p->nbr_capacity > 0) {
+    c->cap = p->nbr_capacity;
+  } else {
+    const double expect = 4.0 / 3.0 * M_PI * c->rlist * c->rlist * c->rlist * N / V;
+    c->cap = (int)std::ceil(1.4 * expect + 64);
+    c->cap = (c->cap + 31) / 32 * 32;
+  }
+  c->cap = std::min(c->cap, N);
+  TRY(dalloc(&c->ctrl, 1));
+  TRY(hipMemset(c->ctrl, 0, sizeof(NlCtrl)));
+  TRY(dalloc(&c->cell_of, N)); TRY(dalloc(&c->cell_count, c->ncell));
+  TRY(dalloc(&c->cell_start, c->ncell + 1)); TRY(dalloc(&c->cell_atoms, N));
+  TRY(dalloc(&c->nbr, (size_t)c->cap * N)); TRY(dalloc(&c->nnbr, N));
+  TRY(hipMemset(c->nnbr, 0, N * sizeof(int)));
+
+  // ---- SPME: influence function G(m) and FFT twiddles ----
+  const size_t KKK = (size_t)c->K[0] * c->K[1] * c->K[2];
+  TRY(dalloc(&c->grid, KKK * Pc_grid));
+  {
+    std::vector<double> b0 = bmod(c->K[0], p->pme_order), b1 = bmod(c->K[1], p->pme_order),
+                        b2 = bmod(c->K[2], p->pme_order);
+    std::vector<double> G(KKK);
+    const double a2 = p->ewald_alpha * p->ewald_alpha;
+    for (int i = 0; i < c->K[0]; ++i)
+      for (int j = 0; j < c->K[1]; ++j)
+        for (int k = 0; k < c->K[2]; ++k) {
+          const double m0 = (i <= c->K[0] / 2 ? i : i - c->K[0]) / p->box[0];
+          const double m1 = (j <= c->K[1] / 2 ? j : j - c->K[1]) / p->box[1];
+          const double m2 = (k <= c->K[2] / 2 ? k : k - c->K[2]) / p->box[2];
+          const double msq = m0 * m0 + m1 * m1 + m2 * m2;
+          G[((size_t)i * c->K[1] + j) * c->K[2] + k] =
+              msq > 0 ? p->coulomb / (M_PI * V) * std::exp(-M_PI * M_PI * msq / a2) / msq * b0[i] * b1[j] * b2[k]
+                      : 0.0;
+        }
+    TRY(up(&c->influence, G));
+  }
+  for (int d = 0; d < 3; ++d) TRY(upload_twiddles(&c->tw[d], c->K[d]));
+
+  // ---- adQTB ----
+  if (p->thermostat == QHP_ADQTB) {
+    QtbState& q = c->qtb;
+    q.nseg = p->qtb_nseg;
+    const int nk = p->n_types * (q.nseg + 1);
+    TRY(dalloc(&q.gamma, nk)); TRY(dalloc(&q.dsum, nk)); TRY(dalloc(&q.dbar, nk));
+    TRY(hipMemset(q.dbar, 0, nk * sizeof(double)));
+    TRY(dalloc(&q.hhat, (size_t)p->n_types * 4 * q.nseg));
+    TRY(dalloc(&q.noise, (size_t)q.nseg * 3 * N));
+    TRY(dalloc(&q.vrec, (size_t)q.nseg * 3 * N));
+    TRY(upload_twiddles(&q.tw2, 2 * q.nseg));
+    TRY(upload_twiddles(&q.tw4, 4 * q.nseg));
+    std::vector<double> tm(p->n_types, 1.0), ic(p->n_types, 0.0);
+    for (int z = 0; z < p->n_types; ++z) q.type_count[z] = 0;
+    for (int i = 0; i < N; ++i) { tm[c->type[i]] = c->mass[i]; q.type_count[c->type[i]]++; }
+    for (int z = 0; z < p->n_types; ++z) ic[z] = q.type_count[z] ? 1.0 / (3.0 * q.type_count[z]) : 0.0;
+    TRY(up(&q.d_tmass, tm)); TRY(up(&q.d_inv_count, ic));
+    q.c1 = std::exp(-p->qtb_gamma0 * p->dt);
+    q.osd = std::sqrt((1.0 - q.c1 * q.c1) * p->dt / (2.0 * p->qtb_gamma0));
+  }
+  *out = c;
+  return QHP_OK;
+}
+
+extern "C" int qhp_destroy(qhp_ctx* c) {
+  if (!c) return QHP_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return QHP_OK;
+}
+
+// Bonded + exclusion (initialise grad V), centroid pair list, real space, SPME.
+int forces_all(qhp_ctx* c, bool energy, bool from_step) {
+  QHP_HIP(c, launch_nlist(c, from_step));
+  if (c->p.exec == QHP_PLAIN) {
+    for (int b = 0; b < c->P; ++b) {
+      QHP_HIP(c, launch_bonded(c, energy, b));
+      QHP_HIP(c, launch_pair(c, energy, b));
+      QHP_HIP(c, launch_spme(c, energy, b));
+    }
+  } else {
+    QHP_HIP(c, launch_bonded(c, energy, -1));
+    QHP_HIP(c, launch_pair(c, energy, -1));
+    QHP_HIP(c, launch_spme(c, energy, -1));
+  }
+  return QHP_OK;
+}
+
+static int copy_in(qhp_ctx* c, const double* src, int mem_kind, double* dst_internal) {
+  const size_t n = (size_t)c->P * c->N * 3;
+  if (mem_kind == QHP_MEM_HOST) {
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(src[i])) return qhp_fail(c, QHP_ENONFINITE, "non-finite input");
+    QHP_HIP(c, hipMemcpyAsync(c->io_a, src, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    QHP_HIP(c, launch_transpose_in(c, c->io_a, dst_internal));
+  } else {
+    QHP_HIP(c, launch_transpose_in(c, src, dst_internal));
+  }
+  return QHP_OK;
+}
+
+static int copy_out_energy(qhp_ctx* c, double* energy, int mem_kind) {
+  if (!energy) return QHP_OK;
+  const size_t n = (size_t)c->P * QHP_NTERMS * sizeof(double);
+  if (mem_kind == QHP_MEM_HOST) {
+    QHP_HIP(c, hipMemcpyAsync(energy, c->energy, n, hipMemcpyDeviceToHost, c->stream));
+    QHP_HIP(c, hipStreamSynchronize(c->stream));
+  } else {
+    QHP_HIP(c, hipMemcpyAsync(energy, c->energy, n, hipMemcpyDeviceToDevice, c->stream));
+  }
+  return QHP_OK;
+}
+
+static int check_ctrl(qhp_ctx* c) {
+  NlCtrl h;
+  QHP_HIP(c, hipMemcpyAsync(&h, c->ctrl, sizeof(NlCtrl), hipMemcpyDeviceToHost, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  if (h.overflow)
+    return qhp_fail(c, QHP_ENOMEM, "neighbour capacity " + std::to_string(c->cap) +
+                                       " exceeded (max count " + std::to_string(h.max_count) +
+                                       "); raise nbr_capacity");
+  if (h.nonfinite) return qhp_fail(c, QHP_ENONFINITE, "state became non-finite");
+  return QHP_OK;
+}
+
+extern "C" int qhp_eval(qhp_ctx* c, const double* pos, double* energy, double* forces, int mem_kind) {
+  if (!c || !pos) return qhp_fail(c, QHP_EINVAL, "null argument");
+  int r = copy_in(c, pos, mem_kind, c->x);
+  if (r) return r;
+  QHP_HIP(c, launch_centroid_of_beads(c));
+  // the pair kernel's FP32 path reads the wrapped centroids written by the build
+  if ((r = forces_all(c, energy != nullptr, false))) return r;
+  if (forces) {
+    const size_t n = (size_t)c->P * c->N * 3;
+    if (mem_kind == QHP_MEM_HOST) {
+      QHP_HIP(c, launch_transpose_out(c, c->g, c->io_a, -1.0));
+      QHP_HIP(c, hipMemcpyAsync(forces, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    } else {
+      QHP_HIP(c, launch_transpose_out(c, c->g, forces, -1.0));
+    }
+  }
+  if ((r = copy_out_energy(c, energy, mem_kind))) return r;
+  if (mem_kind == QHP_MEM_HOST) return check_ctrl(c);
+  return QHP_OK;
+}
+
+extern "C" int qhp_set_state(qhp_ctx* c, const double* pos, const double* vel, int64_t step, int mem_kind) {
+  if (!c || !pos || !vel) return qhp_fail(c, QHP_EINVAL, "null argument");
+  if (step < 0) return qhp_fail(c, QHP_EINVAL, "step must be >= 0");
+  if (c->p.thermostat == QHP_ADQTB && step % c->qtb.nseg)
+    return qhp_fail(c, QHP_EINVAL, "adQTB state must start at a segment boundary");
+  // bead positions and velocities in the bead-innermost layout, whatever exec is
+  const int exec = c->p.exec;
+  c->p.exec = QHP_BATCHED;
+  int r = copy_in(c, pos, mem_kind, c->io_b);
+  if (!r) r = copy_in(c, vel, mem_kind, c->g);
+  c->p.exec = exec;
+  if (r) return r;
+  QHP_HIP(c, launch_beads_to_modes(c, c->io_b, c->g));
+  // bead positions in the context's layout for the first force evaluation
+  r = copy_in(c, pos, mem_kind, c->x);
+  if (r) return r;
+  QHP_HIP(c, launch_centroid_of_beads(c));
+  if ((r = forces_all(c, false, false))) return r;
+  QHP_HIP(c, launch_kick_back(c));          // store Pa = P - (dt/2) f
+  c->step = step;
+  if (c->p.thermostat == QHP_ADQTB) {
+    QHP_HIP(c, qtb_reset_gamma(c));
+    QHP_HIP(c, launch_qtb_generate(c, step / c->qtb.nseg));
+  }
+  c->have_state = true;
+  return check_ctrl(c);
+}
+
+extern "C" int qhp_get_state(qhp_ctx* c, double* pos, double* vel, int64_t* step, int mem_kind) {
+  if (!c) return QHP_EINVAL;
+  if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
+  if (step) *step = c->step;
+  if (!pos && !vel) return QHP_OK;
+  const size_t n = (size_t)c->P * c->N * 3;
+  if (mem_kind == QHP_MEM_HOST) {
+    QHP_HIP(c, launch_state_out(c, pos ? c->io_a : nullptr, vel ? c->io_b : nullptr));
+    if (pos) QHP_HIP(c, hipMemcpyAsync(pos, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (vel) QHP_HIP(c, hipMemcpyAsync(vel, c->io_b, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    QHP_HIP(c, hipStreamSynchronize(c->stream));
+  } else {
+    QHP_HIP(c, launch_state_out(c, pos, vel));
+  }
+  return QHP_OK;
+}
+
+extern "C" int qhp_step(qhp_ctx* c, int32_t nsteps, double* energy, int mem_kind) {
+  if (!c) return QHP_EINVAL;
+  if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
+  if (nsteps < 0) return qhp_fail(c, QHP_EINVAL, "nsteps must be >= 0");
+  const bool qtb = c->p.thermostat == QHP_ADQTB;
+  for (int s = 0; s < nsteps; ++s) {
+    hipEvent_t ev = nullptr;
+    prof_begin(c, QHP_PROF_NM, &ev);
+    QHP_HIP(c, launch_nm_step(c));
+    prof_end(c, QHP_PROF_NM, ev);
+    int r = forces_all(c, energy != nullptr && s == nsteps - 1, true);
+    if (r) return r;
+    c->step += 1;
+    if (qtb && c->step % c->qtb.nseg == 0) {
+      QHP_HIP(c, launch_qtb_adapt(c));
+      QHP_HIP(c, launch_qtb_generate(c, c->step / c->qtb.nseg));
+    }
+  }
+  int r = copy_out_energy(c, nsteps > 0 ? energy : nullptr, mem_kind);
+  if (r) return r;
+  return check_ctrl(c);
+}
+
+extern "C" int qhp_mode_energies(qhp_ctx* c, double* kinetic, double* spring) {
+  if (!c || !kinetic || !spring) return QHP_EINVAL;
+  if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
+  QHP_HIP(c, launch_zero(c, c->io_a, 2 * sizeof(double)));
+  QHP_HIP(c, launch_mode_energies(c, c->io_a));
+  double h[2];
+  QHP_HIP(c, hipMemcpyAsync(h, c->io_a, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  *kinetic = h[0];
+  *spring = h[1];
+  return QHP_OK;
+}
+
+extern "C" int qhp_nlist_export(qhp_ctx* c, int32_t* pairs, int64_t capacity, int64_t* npairs) {
+  if (!c || !npairs) return QHP_EINVAL;
+  const int N = c->N;
+  std::vector<int> nn(N), nb((size_t)c->cap * N);
+  QHP_HIP(c, hipMemcpyAsync(nn.data(), c->nnbr, N * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  QHP_HIP(c, hipMemcpyAsync(nb.data(), c->nbr, nb.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  std::vector<std::pair<int, int>> out;
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < nn[i]; ++k) {
+      const int j = nb[(size_t)k * N + i] & 0x3FFFFFF;
+      if (j > i) out.emplace_back(i, j);
+    }
+  std::sort(out.begin(), out.end());
+  *npairs = (int64_t)out.size();
+  if (!pairs) return QHP_OK;
+  if ((int64_t)out.size() > capacity) return qhp_fail(c, QHP_ENOMEM, "pairs buffer too small");
+  for (size_t k = 0; k < out.size(); ++k) { pairs[2 * k] = out[k].first; pairs[2 * k + 1] = out[k].second; }
+  return QHP_OK;
+}
+
+extern "C" int qhp_noise_export(qhp_ctx* c, int32_t stream, int64_t step, double* out) {
+  if (!c || !out) return QHP_EINVAL;
+  if (stream != 5 && stream != 6) return qhp_fail(c, QHP_EINVAL, "stream must be 5 or 6");
+  if (step < 0) return qhp_fail(c, QHP_EINVAL, "step must be >= 0");
+  const size_t n = (size_t)(stream == 5 ? c->P : 1) * c->N * 3;
+  QHP_HIP(c, launch_noise_export(c, stream, step, c->io_a));
+  QHP_HIP(c, hipMemcpyAsync(out, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  return QHP_OK;
+}
+
+extern "C" int qhp_qtb_get_gamma(qhp_ctx* c, double* gamma) {
+  if (!c || !gamma) return QHP_EINVAL;
+  if (c->p.thermostat != QHP_ADQTB) return qhp_fail(c, QHP_EINVAL, "not an adQTB context");
+  const size_t n = (size_t)c->p.n_types * (c->qtb.nseg + 1) * sizeof(double);
+  QHP_HIP(c, hipMemcpyAsync(gamma, c->qtb.gamma, n, hipMemcpyDeviceToHost, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  return QHP_OK;
+}
+
+extern "C" int qhp_qtb_set_gamma(qhp_ctx* c, const double* gamma) {
+  if (!c || !gamma) return QHP_EINVAL;
+  if (c->p.thermostat != QHP_ADQTB) return qhp_fail(c, QHP_EINVAL, "not an adQTB context");
+  const size_t n = (size_t)c->p.n_types * (c->qtb.nseg + 1) * sizeof(double);
+  QHP_HIP(c, hipMemcpyAsync(c->qtb.gamma, gamma, n, hipMemcpyHostToDevice, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  if (c->have_state) QHP_HIP(c, launch_qtb_generate(c, c->step / c->qtb.nseg));
+  return QHP_OK;
+}
+
+extern "C" int qhp_qtb_get_noise(qhp_ctx* c, double* noise) {
+  if (!c || !noise) return QHP_EINVAL;
+  if (c->p.thermostat != QHP_ADQTB) return qhp_fail(c, QHP_EINVAL, "not an adQTB context");
+  // device layout [t][3][N] -> boundary [t][N][3]
+  const int N = c->N, S = c->qtb.nseg;
+  std::vector<double> tmp((size_t)S * 3 * N);
+  QHP_HIP(c, hipMemcpyAsync(tmp.data(), c->qtb.noise, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  for (int t = 0; t < S; ++t)
+    for (int a = 0; a < N; ++a)
+      for (int d = 0; d < 3; ++d) noise[((size_t)t * N + a) * 3 + d] = tmp[((size_t)t * 3 + d) * N + a];
+  return QHP_OK;
+}
+
+extern "C" int qhp_qtb_get_delta(qhp_ctx* c, double* delta) {
+  if (!c || !delta) return QHP_EINVAL;
+  if (c->p.thermostat != QHP_ADQTB) return qhp_fail(c, QHP_EINVAL, "not an adQTB context");
+  const size_t n = (size_t)c->p.n_types * (c->qtb.nseg + 1) * sizeof(double);
+  QHP_HIP(c, hipMemcpyAsync(delta, c->qtb.dbar, n, hipMemcpyDeviceToHost, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  return QHP_OK;
+}
+
+extern "C" int qhp_profile(qhp_ctx* c, int which) {
+  if (!c) return QHP_EINVAL;
+  if (which < 0 || which > QHP_PROF_NM) return qhp_fail(c, QHP_EINVAL, "profile class");
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  for (auto& pr : c->ev_pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+  c->ev_pending.clear();
+  c->prof_which = which;
+  c->prof_ms = 0;
+  c->prof_launches = 0;
+  return QHP_OK;
+}
+
+extern "C" int qhp_profile_read(qhp_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return QHP_EINVAL;
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  for (auto& pr : c->ev_pending) {
+    float t = 0;
+    if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) c->prof_ms += t;
+    c->prof_launches += 1;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  c->ev_pending.clear();
+  *ms = c->prof_ms;
+  *launches = c->prof_launches;
+  return QHP_OK;
+}
+
+extern "C" int qhp_sync(qhp_ctx* c) {
+  if (!c) return QHP_EINVAL;
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  return QHP_OK;
+}
+
+extern "C" const char* qhp_last_error(qhp_ctx* c) { return c ? c->err.c_str() : "null context"; }

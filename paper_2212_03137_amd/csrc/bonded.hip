@@ -1,0 +1,161 @@
+// Intramolecular terms of the flexible 3-site water and the Ewald corrections that do not
+// involve other molecules: harmonic O-H bonds, harmonic H-O-H angle, and removal of the
+// screened interaction of the three excluded intramolecular pairs,
+// -C q_a q_b erf(alpha r) / r, that the reciprocal sum contains. This kernel *initialises*
+// grad V of every bead; the pair and SPME kernels add to it.
+// Lane (w, b): water w at bead b; 256 / P waters per block.
+#include "qhp_internal.h"
+
+namespace {
+
+constexpr int NT = 256;
+
+struct BondArgs {
+  int N, NW;
+  const double* x; double* g;
+  const double* charge;
+  double L[3], invL[3];
+  double r0, kb, th0, kth, alpha, coulomb;
+  double* energy;
+};
+
+template <int P>
+QHP_DEV void reduce_energy_by_bead(double* sred, int tid, double v, double* dst) {
+  constexpr int AT = NT / P;
+  sred[tid] = v;
+  __syncthreads();
+  for (int s = AT / 2; s > 0; s >>= 1) {
+    if (tid / P < s) sred[tid] += sred[tid + s * P];
+    __syncthreads();
+  }
+  if (tid < P) atomicAdd(dst + tid * QHP_NTERMS, sred[tid]);
+  __syncthreads();
+}
+
+template <int P, bool ENERGY>
+__global__ __launch_bounds__(NT) void k_bonded(BondArgs A) {
+  constexpr int AT = NT / P;
+  __shared__ double sred[NT];
+  const int tid = threadIdx.x, b = tid % P;
+  const int w = blockIdx.x * AT + tid / P;
+  double eb = 0, ea = 0, ex = 0;
+  if (w < A.NW) {
+    const int N = A.N;
+    double X[3][3], G[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int d = 0; d < 3; ++d) {
+        X[k][d] = A.x[(d * N + 3 * w + k) * P + b];
+        G[k][d] = 0.0;
+      }
+    double u[2][3], r[2];
+    for (int h = 0; h < 2; ++h) {
+      double dd[3];
+      for (int d = 0; d < 3; ++d) {
+        dd[d] = X[h + 1][d] - X[0][d];
+        dd[d] -= A.L[d] * rint(dd[d] * A.invL[d]);
+      }
+      r[h] = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+      const double dr = r[h] - A.r0;
+      if (ENERGY) eb += 0.5 * A.kb * dr * dr;
+      const double s = A.kb * dr / r[h];
+      for (int d = 0; d < 3; ++d) {
+        u[h][d] = dd[d] / r[h];
+        G[h + 1][d] += s * dd[d];
+        G[0][d] -= s * dd[d];
+      }
+    }
+    double cs = u[0][0] * u[1][0] + u[0][1] * u[1][1] + u[0][2] * u[1][2];
+    cs = fmin(1.0, fmax(-1.0, cs));
+    const double th = acos(cs), sn = sqrt(1.0 - cs * cs);
+    const double dth = th - A.th0;
+    if (ENERGY) ea = 0.5 * A.kth * dth * dth;
+    const double de = A.kth * dth;
+    for (int d = 0; d < 3; ++d) {
+      const double g1 = -de / (r[0] * sn) * (u[1][d] - cs * u[0][d]);
+      const double g2 = -de / (r[1] * sn) * (u[0][d] - cs * u[1][d]);
+      G[1][d] += g1;
+      G[2][d] += g2;
+      G[0][d] -= g1 + g2;
+    }
+    const double c2a = 2.0 * A.alpha / sqrt(M_PI);
+    const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+    for (int e = 0; e < 3; ++e) {
+      double dd[3];
+      for (int d = 0; d < 3; ++d) {
+        dd[d] = X[pb[e]][d] - X[pa[e]][d];
+        dd[d] -= A.L[d] * rint(dd[d] * A.invL[d]);
+      }
+      const double r2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+      const double rr = sqrt(r2);
+      const double qq = A.coulomb * A.charge[3 * w + pa[e]] * A.charge[3 * w + pb[e]];
+      const double erfv = erf(A.alpha * rr);
+      if (ENERGY) ex += -qq * erfv / rr;
+      const double dEdr = -qq * (c2a * exp(-A.alpha * A.alpha * r2) / rr - erfv / r2);
+      const double s = dEdr / rr;
+      for (int d = 0; d < 3; ++d) {
+        G[pb[e]][d] += s * dd[d];
+        G[pa[e]][d] -= s * dd[d];
+      }
+    }
+    for (int k = 0; k < 3; ++k)
+      for (int d = 0; d < 3; ++d) A.g[(d * N + 3 * w + k) * P + b] = G[k][d];
+  }
+  if (ENERGY) {
+    reduce_energy_by_bead<P>(sred, tid, eb, A.energy + QHP_E_BOND);
+    reduce_energy_by_bead<P>(sred, tid, ea, A.energy + QHP_E_ANGLE);
+    reduce_energy_by_bead<P>(sred, tid, ex, A.energy + QHP_E_COUL_EXCL);
+  }
+}
+
+__global__ void k_energy_init(double* energy, int P, double self) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < P * QHP_NTERMS) energy[i] = (i % QHP_NTERMS == QHP_E_COUL_SELF) ? self : 0.0;
+}
+
+__global__ void k_zero(double* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+}  // namespace
+
+#define QHP_SWITCH_P(P, CALL)                          \
+  switch (P) {                                         \
+    case 1: { constexpr int PP = 1; CALL; } break;     \
+    case 2: { constexpr int PP = 2; CALL; } break;     \
+    case 4: { constexpr int PP = 4; CALL; } break;     \
+    case 8: { constexpr int PP = 8; CALL; } break;     \
+    case 16: { constexpr int PP = 16; CALL; } break;   \
+    case 32: { constexpr int PP = 32; CALL; } break;   \
+    case 64: { constexpr int PP = 64; CALL; } break;   \
+    default: return hipErrorInvalidValue;              \
+  }
+
+hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead) {
+  BondArgs A;
+  const int N = c->N;
+  const bool plain = bead >= 0;
+  A.N = N; A.NW = c->NW;
+  A.x = plain ? c->x + (size_t)bead * 3 * N : c->x;
+  A.g = plain ? c->g + (size_t)bead * 3 * N : c->g;
+  A.charge = c->d_charge;
+  for (int d = 0; d < 3; ++d) { A.L[d] = c->p.box[d]; A.invL[d] = 1.0 / c->p.box[d]; }
+  A.r0 = c->p.bond_r0; A.kb = c->p.bond_k; A.th0 = c->p.angle_theta0; A.kth = c->p.angle_k;
+  A.alpha = c->p.ewald_alpha; A.coulomb = c->p.coulomb;
+  A.energy = c->energy + (plain ? (size_t)bead * QHP_NTERMS : 0);
+  const int P = plain ? 1 : c->P;
+  if (energy && bead <= 0)
+    hipLaunchKernelGGL(k_energy_init, 1, 512, 0, c->stream, c->energy, c->P, c->self_energy);
+  const unsigned nb = (unsigned)((c->NW + NT / P - 1) / (NT / P));
+  QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_bonded<PP, true>), nb, NT, 0, c->stream, A);
+               else hipLaunchKernelGGL((k_bonded<PP, false>), nb, NT, 0, c->stream, A));
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(qhp_ctx* c, void* ptr, size_t bytes) {
+  const size_t n = bytes / sizeof(double);
+  const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero, nb, 256, 0, c->stream, (double*)ptr, n);
+  return hipGetLastError();
+}

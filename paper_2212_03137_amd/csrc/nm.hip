@@ -1,0 +1,433 @@
+// Normal-mode propagation of the ring polymer (Sec. "Integration Scheme"): the fused
+// B A O A kernel with the mode -> bead transform (eq. beads_positions) and the projection
+// of bead forces on modes (eq. force_normal_modes), plus the state conversions at the
+// boundary.
+//
+// Lane layout: a 256-thread block holds 256/P atoms; lane (a, n) owns mode n of atom a
+// for x, y and z. The bead-axis contractions (T^T g and T Q, both P x P) go through LDS:
+// at P = 32 they are 2 x 32 x 32 FMAs per lane and the kernel stays bound by HBM.
+//
+// Persistent state between steps: Q, Pa (momenta after the A-O-A of the last step, i.e.
+// before its final half kick) and g = grad V at the current beads. A step therefore
+// starts with P = Pa + dt * f(g): the previous step's final B and this step's first B,
+// which use the same forces.
+#include "qhp_internal.h"
+
+namespace {
+
+constexpr int NT = 256;
+
+struct NmArgs {
+  int N;
+  double* Q; double* Pa; double* x; const double* g;
+  const double* T; const double* cc; const double* csw; const double* cws;
+  const double* c1; const double* c2;
+  const double* mass; const double* sqrt_mkT; const double* charge;
+  double4* cent; const double4* cref; const double4* coff; double4* cwrap; float4* xf;
+  NlCtrl* ctrl;
+  double dt, h;
+  uint64_t seed; uint64_t step;
+  // adQTB
+  const double* noise; double* vrec; int tseg; double qc1, qosd;
+};
+
+template <int P, bool BEADMAJOR>
+QHP_DEV int gidx(int N, int d, int a, int b) {
+  return BEADMAJOR ? (b * 3 + d) * N + a : (d * N + a) * P + b;
+}
+
+QHP_DEV double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+template <int P, bool QTB, bool BEADMAJOR, bool F32>
+__global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
+  constexpr int AT = NT / P;
+  __shared__ double sT[P * P];
+  __shared__ double sh[AT][3][P];
+  const int tid = threadIdx.x;
+  const int al = tid / P, n = tid % P;
+  const int a = blockIdx.x * AT + al;
+  for (int k = tid; k < P * P; k += NT) sT[k] = A.T[k];
+  const bool live = a < A.N;
+  double gv[3] = {0, 0, 0};
+  if (live)
+    for (int d = 0; d < 3; ++d) gv[d] = A.g[gidx<P, BEADMAJOR>(A.N, d, a, n)];
+  for (int d = 0; d < 3; ++d) sh[al][d][n] = gv[d];
+  __syncthreads();
+
+  const double rsP = 1.0 / sqrt((double)P);
+  double q[3], p[3];
+  double m = 1.0, cc = A.cc[n], csw = A.csw[n], cws = A.cws[n];
+  int bad = 0;
+  if (live) {
+    m = A.mass[a];
+    const double im = 1.0 / m;
+    double xi[3] = {0, 0, 0};
+    if (!QTB) qhp::gauss3(A.seed, qhp::STREAM_RPMD_O, A.step, (uint64_t)a, (uint64_t)n, xi);
+    for (int d = 0; d < 3; ++d) {
+      double f = 0;
+#pragma unroll 8
+      for (int i = 0; i < P; ++i) f += sT[i * P + n] * sh[al][d][i];
+      f = -f * rsP;
+      const int gi = (d * A.N + a) * P + n;
+      double pp = A.Pa[gi] + A.dt * f;
+      double qq = A.Q[gi];
+      // A(h): exact free ring-polymer evolution of mode n
+      double q1 = cc * qq + csw * im * pp;
+      double p1 = -m * cws * qq + cc * pp;
+      // O(dt)
+      if (QTB) {
+        const int ni = (A.tseg * 3 + d) * A.N + a;
+        const double pb = p1;
+        p1 = A.qc1 * p1 + A.qosd * A.noise[ni];
+        A.vrec[ni] = 0.5 * (pb + p1) * im;
+      } else {
+        p1 = A.c1[n] * p1 + A.c2[n] * A.sqrt_mkT[a] * xi[d];
+      }
+      // A(h)
+      q[d] = cc * q1 + csw * im * p1;
+      p[d] = -m * cws * q1 + cc * p1;
+      A.Q[gi] = q[d];
+      A.Pa[gi] = p[d];
+      if (!isfinite(q[d]) || !isfinite(p[d])) bad = 1;
+    }
+  }
+  __syncthreads();
+  if (live)
+    for (int d = 0; d < 3; ++d) sh[al][d][n] = q[d];
+  __syncthreads();
+
+  // beads from modes: lane index n now stands for bead i = n
+  double db2 = 0, dc2 = 0;
+  if (live) {
+    const double sP = sqrt((double)P);
+    double xb[3], c[3];
+    for (int d = 0; d < 3; ++d) {
+      double s = 0;
+#pragma unroll 8
+      for (int k = 1; k < P; ++k) s += sT[n * P + k] * sh[al][d][k];
+      c[d] = sh[al][d][0];
+      xb[d] = c[d] + sP * s;
+      A.x[gidx<P, BEADMAJOR>(A.N, d, a, n)] = xb[d];
+      if (!isfinite(xb[d])) bad = 1;
+    }
+    const double dx = xb[0] - c[0], dy = xb[1] - c[1], dz = xb[2] - c[2];
+    db2 = dx * dx + dy * dy + dz * dz;
+    if (F32) A.xf[a * P + n] = make_float4((float)dx, (float)dy, (float)dz, (float)A.charge[a]);
+    if (n == 0) {
+      A.cent[a] = make_double4(c[0], c[1], c[2], 0.0);
+      const double4 o = A.coff[a];
+      A.cwrap[a] = make_double4(c[0] - o.x, c[1] - o.y, c[2] - o.z, 0.0);
+      const double4 r = A.cref[a];
+      const double ex = c[0] - r.x, ey = c[1] - r.y, ez = c[2] - r.z;
+      dc2 = ex * ex + ey * ey + ez * ez;
+    }
+  }
+  db2 = wave_max(db2);
+  dc2 = wave_max(dc2);
+  if ((tid & 63) == 0) {
+    atomicMax(&A.ctrl->max_db2, qhp::dbits(db2));
+    atomicMax(&A.ctrl->max_dc2, qhp::dbits(dc2));
+  }
+  if (bad) A.ctrl->nonfinite = 1;
+}
+
+// Q = T^T x / sqrt(P), Pm = m T^T v / sqrt(P); inputs bead-innermost [3][N][P].
+template <int P>
+__global__ __launch_bounds__(NT) void k_to_modes(int N, const double* xb, const double* vb,
+                                                 const double* T, const double* mass,
+                                                 double* Q, double* Pm) {
+  constexpr int AT = NT / P;
+  __shared__ double sT[P * P];
+  __shared__ double sx[AT][6][P];
+  const int tid = threadIdx.x, al = tid / P, n = tid % P, a = blockIdx.x * AT + al;
+  for (int k = tid; k < P * P; k += NT) sT[k] = T[k];
+  const bool live = a < N;
+  for (int d = 0; d < 3; ++d) {
+    sx[al][d][n] = live ? xb[(d * N + a) * P + n] : 0.0;
+    sx[al][3 + d][n] = live ? vb[(d * N + a) * P + n] : 0.0;
+  }
+  __syncthreads();
+  if (!live) return;
+  const double rsP = 1.0 / sqrt((double)P);
+  const double m = mass[a];
+  for (int d = 0; d < 3; ++d) {
+    double sq = 0, sv = 0;
+    for (int i = 0; i < P; ++i) {
+      sq += sT[i * P + n] * sx[al][d][i];
+      sv += sT[i * P + n] * sx[al][3 + d][i];
+    }
+    Q[(d * N + a) * P + n] = sq * rsP;
+    Pm[(d * N + a) * P + n] = m * sv * rsP;
+  }
+}
+
+// Pa += s * f with f = -T^T g / sqrt(P) (g in the context's layout).
+template <int P, bool BEADMAJOR>
+__global__ __launch_bounds__(NT) void k_kick(int N, double* Pa, const double* g, const double* T,
+                                             double s) {
+  constexpr int AT = NT / P;
+  __shared__ double sT[P * P];
+  __shared__ double sg[AT][3][P];
+  const int tid = threadIdx.x, al = tid / P, n = tid % P, a = blockIdx.x * AT + al;
+  for (int k = tid; k < P * P; k += NT) sT[k] = T[k];
+  const bool live = a < N;
+  for (int d = 0; d < 3; ++d) sg[al][d][n] = live ? g[gidx<P, BEADMAJOR>(N, d, a, n)] : 0.0;
+  __syncthreads();
+  if (!live) return;
+  const double rsP = 1.0 / sqrt((double)P);
+  for (int d = 0; d < 3; ++d) {
+    double f = 0;
+    for (int i = 0; i < P; ++i) f += sT[i * P + n] * sg[al][d][i];
+    Pa[(d * N + a) * P + n] += s * (-f * rsP);
+  }
+}
+
+// Bead positions and velocities [P][N][3] from (Q, Pa + h f).
+template <int P, bool BEADMAJOR>
+__global__ __launch_bounds__(NT) void k_state_out(int N, const double* Q, const double* Pa,
+                                                  const double* g, const double* T,
+                                                  const double* mass, double h, double* xo,
+                                                  double* vo) {
+  constexpr int AT = NT / P;
+  __shared__ double sT[P * P];
+  __shared__ double sh[AT][6][P];
+  const int tid = threadIdx.x, al = tid / P, n = tid % P, a = blockIdx.x * AT + al;
+  for (int k = tid; k < P * P; k += NT) sT[k] = T[k];
+  const bool live = a < N;
+  for (int d = 0; d < 3; ++d) sh[al][3 + d][n] = live ? g[gidx<P, BEADMAJOR>(N, d, a, n)] : 0.0;
+  __syncthreads();
+  const double rsP = 1.0 / sqrt((double)P), sP = sqrt((double)P);
+  double pn[3] = {0, 0, 0}, qn[3] = {0, 0, 0};
+  if (live)
+    for (int d = 0; d < 3; ++d) {
+      double f = 0;
+      for (int i = 0; i < P; ++i) f += sT[i * P + n] * sh[al][3 + d][i];
+      pn[d] = Pa[(d * N + a) * P + n] + h * (-f * rsP);
+      qn[d] = Q[(d * N + a) * P + n];
+    }
+  __syncthreads();
+  for (int d = 0; d < 3; ++d) { sh[al][d][n] = qn[d]; sh[al][3 + d][n] = pn[d]; }
+  __syncthreads();
+  if (!live) return;
+  const double im = 1.0 / mass[a];
+  for (int d = 0; d < 3; ++d) {
+    double sx = 0, sv = 0;
+    for (int k = 0; k < P; ++k) {
+      sx += sT[n * P + k] * sh[al][d][k];
+      sv += sT[n * P + k] * sh[al][3 + d][k];
+    }
+    if (xo) xo[((size_t)n * N + a) * 3 + d] = sP * sx;
+    if (vo) vo[((size_t)n * N + a) * 3 + d] = sP * sv * im;
+  }
+}
+
+// kinetic sum (Pa + h f)^2 / 2m and spring sum m w^2 Q^2 / 2 -> out[0], out[1]
+template <int P, bool BEADMAJOR>
+__global__ __launch_bounds__(NT) void k_mode_energy(int N, const double* Q, const double* Pa,
+                                                    const double* g, const double* T,
+                                                    const double* mass, const double* w2,
+                                                    double h, double* out) {
+  constexpr int AT = NT / P;
+  __shared__ double sT[P * P];
+  __shared__ double sg[AT][3][P];
+  const int tid = threadIdx.x, al = tid / P, n = tid % P, a = blockIdx.x * AT + al;
+  for (int k = tid; k < P * P; k += NT) sT[k] = T[k];
+  const bool live = a < N;
+  for (int d = 0; d < 3; ++d) sg[al][d][n] = live ? g[gidx<P, BEADMAJOR>(N, d, a, n)] : 0.0;
+  __syncthreads();
+  double ek = 0, es = 0;
+  if (live) {
+    const double rsP = 1.0 / sqrt((double)P), m = mass[a];
+    for (int d = 0; d < 3; ++d) {
+      double f = 0;
+      for (int i = 0; i < P; ++i) f += sT[i * P + n] * sg[al][d][i];
+      const double pn = Pa[(d * N + a) * P + n] + h * (-f * rsP);
+      const double qn = Q[(d * N + a) * P + n];
+      ek += pn * pn / (2.0 * m);
+      es += 0.5 * m * w2[n] * qn * qn;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) { ek += __shfl_xor(ek, o); es += __shfl_xor(es, o); }
+  if ((tid & 63) == 0) { atomicAdd(out, ek); atomicAdd(out + 1, es); }
+}
+
+// centroid of given beads (bead-innermost or bead-major x): beads summed in order, / P
+template <int P, bool BEADMAJOR>
+__global__ void k_centroid_beads(int N, const double* x, double4* cent, float4* xf,
+                                 const double* charge) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  double c[3];
+  for (int d = 0; d < 3; ++d) {
+    double s = x[gidx<P, BEADMAJOR>(N, d, a, 0)];
+    for (int b = 1; b < P; ++b) s = s + x[gidx<P, BEADMAJOR>(N, d, a, b)];
+    c[d] = s / (double)P;
+  }
+  cent[a] = make_double4(c[0], c[1], c[2], 0.0);
+  if (xf)
+    for (int b = 0; b < P; ++b)
+      xf[a * P + b] = make_float4((float)(x[gidx<P, BEADMAJOR>(N, 0, a, b)] - c[0]),
+                                  (float)(x[gidx<P, BEADMAJOR>(N, 1, a, b)] - c[1]),
+                                  (float)(x[gidx<P, BEADMAJOR>(N, 2, a, b)] - c[2]),
+                                  (float)charge[a]);
+}
+
+// boundary [P][N][3] <-> internal layout
+template <bool BEADMAJOR>
+__global__ void k_transpose_in(int N, int P, const double* src, double* dst) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)P * N * 3) return;
+  const int d = i % 3, a = (i / 3) % N, b = i / (3 * (size_t)N);
+  const size_t o = BEADMAJOR ? ((size_t)b * 3 + d) * N + a : ((size_t)d * N + a) * P + b;
+  dst[o] = src[i];
+}
+
+template <bool BEADMAJOR>
+__global__ void k_transpose_out(int N, int P, const double* src, double* dst, double scale) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)P * N * 3) return;
+  const int d = i % 3, a = (i / 3) % N, b = i / (3 * (size_t)N);
+  const size_t o = BEADMAJOR ? ((size_t)b * 3 + d) * N + a : ((size_t)d * N + a) * P + b;
+  dst[i] = scale * src[o];
+}
+
+}  // namespace
+
+#define QHP_SWITCH_P(P, CALL)                          \
+  switch (P) {                                         \
+    case 1: { constexpr int PP = 1; CALL; } break;     \
+    case 2: { constexpr int PP = 2; CALL; } break;     \
+    case 4: { constexpr int PP = 4; CALL; } break;     \
+    case 8: { constexpr int PP = 8; CALL; } break;     \
+    case 16: { constexpr int PP = 16; CALL; } break;   \
+    case 32: { constexpr int PP = 32; CALL; } break;   \
+    case 64: { constexpr int PP = 64; CALL; } break;   \
+    default: return hipErrorInvalidValue;              \
+  }
+
+static inline unsigned nblocks_atoms(int N, int P) { return (unsigned)((N + (NT / P) - 1) / (NT / P)); }
+
+hipError_t launch_nm_step(qhp_ctx* c) {
+  NmArgs A;
+  A.N = c->N; A.Q = c->Q; A.Pa = c->Pa; A.x = c->x; A.g = c->g; A.T = c->T;
+  A.cc = c->mode_c; A.csw = c->mode_s_w; A.cws = c->mode_ws; A.c1 = c->mode_c1; A.c2 = c->mode_c2;
+  A.mass = c->d_mass; A.sqrt_mkT = c->d_sqrt_mkT; A.charge = c->d_charge;
+  A.cent = c->cent; A.cref = c->cref; A.coff = c->coff; A.cwrap = c->cwrap; A.xf = c->xf; A.ctrl = c->ctrl;
+  A.dt = c->p.dt; A.h = 0.5 * c->p.dt; A.seed = c->p.seed; A.step = (uint64_t)c->step;
+  const bool qtb = c->p.thermostat == QHP_ADQTB;
+  A.noise = c->qtb.noise; A.vrec = c->qtb.vrec;
+  A.tseg = qtb ? (int)(c->step % c->qtb.nseg) : 0;
+  A.qc1 = c->qtb.c1; A.qosd = c->qtb.osd;
+  const bool bm = c->p.exec == QHP_PLAIN;
+  const bool f32 = c->p.precision == QHP_FP32_PAIRS && !bm;
+  const unsigned nb = nblocks_atoms(c->N, c->P);
+  if (qtb) {
+    if (c->P != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_nm_step<1, true, false, false>), nb, NT, 0, c->stream, A);
+    return hipGetLastError();
+  }
+#define NM_CALL                                                                            \
+  if (bm) hipLaunchKernelGGL((k_nm_step<PP, false, true, false>), nb, NT, 0, c->stream, A); \
+  else if (f32) hipLaunchKernelGGL((k_nm_step<PP, false, false, true>), nb, NT, 0, c->stream, A); \
+  else hipLaunchKernelGGL((k_nm_step<PP, false, false, false>), nb, NT, 0, c->stream, A);
+  QHP_SWITCH_P(c->P, NM_CALL);
+#undef NM_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_beads_to_modes(qhp_ctx* c, const double* xb, const double* vb) {
+  const unsigned nb = nblocks_atoms(c->N, c->P);
+  QHP_SWITCH_P(c->P, hipLaunchKernelGGL((k_to_modes<PP>), nb, NT, 0, c->stream, c->N, xb, vb,
+                                        c->T, c->d_mass, c->Q, c->Pa));
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_back(qhp_ctx* c) {
+  const unsigned nb = nblocks_atoms(c->N, c->P);
+  const bool bm = c->p.exec == QHP_PLAIN;
+  const double s = -0.5 * c->p.dt;
+  QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_kick<PP, true>), nb, NT, 0, c->stream, c->N,
+                                                 c->Pa, c->g, c->T, s);
+               else hipLaunchKernelGGL((k_kick<PP, false>), nb, NT, 0, c->stream, c->N, c->Pa,
+                                       c->g, c->T, s));
+  return hipGetLastError();
+}
+
+hipError_t launch_state_out(qhp_ctx* c, double* xo, double* vo) {
+  const unsigned nb = nblocks_atoms(c->N, c->P);
+  const bool bm = c->p.exec == QHP_PLAIN;
+  const double h = 0.5 * c->p.dt;
+  QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_state_out<PP, true>), nb, NT, 0, c->stream,
+                                                 c->N, c->Q, c->Pa, c->g, c->T, c->d_mass, h, xo, vo);
+               else hipLaunchKernelGGL((k_state_out<PP, false>), nb, NT, 0, c->stream, c->N, c->Q,
+                                       c->Pa, c->g, c->T, c->d_mass, h, xo, vo));
+  return hipGetLastError();
+}
+
+hipError_t launch_mode_energies(qhp_ctx* c, double* out2) {
+  const unsigned nb = nblocks_atoms(c->N, c->P);
+  const bool bm = c->p.exec == QHP_PLAIN;
+  const double h = 0.5 * c->p.dt;
+  QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_mode_energy<PP, true>), nb, NT, 0, c->stream,
+                                                 c->N, c->Q, c->Pa, c->g, c->T, c->d_mass,
+                                                 c->mode_w2, h, out2);
+               else hipLaunchKernelGGL((k_mode_energy<PP, false>), nb, NT, 0, c->stream, c->N,
+                                       c->Q, c->Pa, c->g, c->T, c->d_mass, c->mode_w2, h, out2));
+  return hipGetLastError();
+}
+
+hipError_t launch_centroid_of_beads(qhp_ctx* c) {
+  const bool bm = c->p.exec == QHP_PLAIN;
+  float4* xf = (c->p.precision == QHP_FP32_PAIRS && !bm) ? c->xf : nullptr;
+  const unsigned nb = (c->N + 127) / 128;
+  QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_centroid_beads<PP, true>), nb, 128, 0,
+                                                 c->stream, c->N, c->x, c->cent, xf, c->d_charge);
+               else hipLaunchKernelGGL((k_centroid_beads<PP, false>), nb, 128, 0, c->stream, c->N,
+                                       c->x, c->cent, xf, c->d_charge));
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_in(qhp_ctx* c, const double* src, double* dst) {
+  const size_t n = (size_t)c->P * c->N * 3;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (c->p.exec == QHP_PLAIN)
+    hipLaunchKernelGGL(k_transpose_in<true>, nb, 256, 0, c->stream, c->N, c->P, src, dst);
+  else
+    hipLaunchKernelGGL(k_transpose_in<false>, nb, 256, 0, c->stream, c->N, c->P, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_out(qhp_ctx* c, const double* src, double* dst, double scale) {
+  const size_t n = (size_t)c->P * c->N * 3;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (c->p.exec == QHP_PLAIN)
+    hipLaunchKernelGGL(k_transpose_out<true>, nb, 256, 0, c->stream, c->N, c->P, src, dst, scale);
+  else
+    hipLaunchKernelGGL(k_transpose_out<false>, nb, 256, 0, c->stream, c->N, c->P, src, dst, scale);
+  return hipGetLastError();
+}
+
+namespace {
+// The Gaussians the kernels draw: stream 5 -> [mode][atom][xyz] of one step,
+// stream 6 -> [atom][xyz] of the adQTB white noise at counter c0.
+__global__ void k_noise(uint64_t seed, uint64_t stream, uint64_t c0, int N, int P, double* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * P) return;
+  const int a = t % N, n = t / N;
+  double g[3];
+  if (stream == qhp::STREAM_RPMD_O) qhp::gauss3(seed, stream, c0, (uint64_t)a, (uint64_t)n, g);
+  else qhp::gauss3(seed, stream, c0, (uint64_t)a, 0ull, g);
+  for (int d = 0; d < 3; ++d) out[((size_t)n * N + a) * 3 + d] = g[d];
+}
+}  // namespace
+
+hipError_t launch_noise_export(qhp_ctx* c, int stream, int64_t step, double* out) {
+  const int P = stream == 5 ? c->P : 1;
+  const uint64_t c0 = stream == 5 ? (uint64_t)step : (uint64_t)(step + c->p.qtb_nseg);
+  hipLaunchKernelGGL(k_noise, (c->N * P + 255) / 256, 256, 0, c->stream, c->p.seed,
+                     (uint64_t)stream, c0, c->N, P, out);
+  return hipGetLastError();
+}

@@ -1,0 +1,276 @@
+// Internal declarations of the MI355X ring-polymer MD library: device state, launch
+// helpers and the device-side counter-based Gaussian generator.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qhp.h"
+
+#define QHP_MAX_TYPES 8
+
+// ---------------------------------------------------------------------------------------
+// Device layout (all FP64 unless noted; "bead innermost"):
+//   Q, Pa, x, g        [3][N][P]   mode amplitudes, momenta, bead positions, grad V
+//   cent, cref         [N] double4 centroid now / at the last neighbour-list build
+//   cwrap              [N] double4 centroid in the frame wrapped at the last build
+//   nbr                [cap][N]    int32 neighbour j of atom i at nbr[k*N + i] (full list)
+//   grid               [K0][K1][K2][Pc] double2, bead b in component b%2 of complex b/2
+// In plain mode x and g are bead-major [P][3][N] and each bead is evaluated alone.
+// ---------------------------------------------------------------------------------------
+
+struct NlCtrl {               // device-side control block of the neighbour list
+  unsigned long long max_dc2; // max |centroid - centroid at build|^2 (bit pattern)
+  unsigned long long max_db2; // max |bead - centroid|^2 (bit pattern)
+  int do_build;               // this step rebuilds
+  int force_build;            // host request
+  int overflow;               // a neighbour count exceeded the capacity
+  int nonfinite;              // a non-finite coordinate or momentum was seen
+  int max_count;              // largest neighbour count of the last build
+  int n_builds;               // builds so far
+};
+
+struct QtbState {
+  int nseg;
+  double* gamma = nullptr;    // [n_types][nseg+1]
+  double2* hhat = nullptr;    // [n_types][4 nseg]  DFT of the embedded kernel h
+  double2* hker = nullptr;    // [n_types][2 nseg]  scratch: H then h
+  double* noise = nullptr;    // [nseg][3][N] coloured force of the current segment
+  double* vrec = nullptr;     // [nseg][3][N] recorded O-midpoint velocities
+  double* dsum = nullptr;     // [n_types][nseg+1] summed Delta_FDT of the running segment
+  double* dbar = nullptr;     // [n_types][nseg+1] type-averaged Delta_FDT of the last segment
+  double* d_tmass = nullptr;  // [n_types]
+  double* d_inv_count = nullptr; // [n_types] 1 / (3 * atoms of the type)
+  double2* tw2 = nullptr;     // twiddles of length 2 nseg
+  double2* tw4 = nullptr;     // twiddles of length 4 nseg
+  int type_count[QHP_MAX_TYPES];
+  double type_mass[QHP_MAX_TYPES];
+  double c1, osd;             // O step: p <- c1 p + osd F
+};
+
+struct qhp_ctx {
+  qhp_params p;
+  int N, P, NW, Pc;           // atoms, beads, waters, complex grid batch
+  hipStream_t stream;
+  std::string err;
+  bool have_state = false;
+  int64_t step = 0;
+
+  // host copies of per-atom data
+  std::vector<int32_t> type;
+  std::vector<double> mass, charge, sigma, eps;
+
+  // normal modes
+  double* T = nullptr;        // [P][P] T[bead][mode]
+  double* mode_c = nullptr;   // [P] cos(w h)
+  double* mode_s_w = nullptr; // [P] sin(w h)/w   (h for the centroid)
+  double* mode_ws = nullptr;  // [P] w sin(w h)
+  double* mode_c1 = nullptr;  // [P] exp(-gamma_n dt)
+  double* mode_c2 = nullptr;  // [P] sqrt(1 - c1^2)
+  double* mode_w2 = nullptr;  // [P] w^2 (spring energy)
+  std::vector<double> h_omega;
+
+  // per-atom device arrays
+  int* d_type = nullptr;
+  double* d_mass = nullptr;
+  double* d_charge = nullptr;
+  double* d_sqrt_mkT = nullptr;
+  double* d_sigma = nullptr;
+  double* d_eps = nullptr;
+
+  // state
+  double *Q = nullptr, *Pa = nullptr, *x = nullptr, *g = nullptr;
+  double4* cent = nullptr;
+  double4* cref = nullptr;
+  double4* coff = nullptr;    // [N] L * floor(c / L) per axis at the last build
+  double4* cwrap = nullptr;   // [N] centroid - coff (continuous between builds)
+  float4* xf = nullptr;       // FP32-pair mode: per bead (x - c) and charge, [N][P]
+
+  // neighbour list
+  NlCtrl* ctrl = nullptr;
+  int* cell_of = nullptr;     // [N]
+  int* cell_count = nullptr;  // [ncell]
+  int* cell_start = nullptr;  // [ncell + 1]
+  int* cell_atoms = nullptr;  // [N]
+  int* stencil = nullptr;     // [ncell][27] distinct neighbour cells, -1 padded
+  int* nbr = nullptr;         // [cap][N]
+  int* nnbr = nullptr;        // [N]
+  int cap = 0, nc[3] = {1, 1, 1}, ncell = 1;
+  double rlist = 0;
+
+  // SPME
+  int K[3];
+  double2* grid = nullptr;    // [K0][K1][K2][Pc] (plain: [K0][K1][K2])
+  double* influence = nullptr;// [K0][K1][K2]
+  double2* tw[3] = {nullptr, nullptr, nullptr};
+
+  // energies
+  double* energy = nullptr;   // [P][QHP_NTERMS]
+  double self_energy = 0;
+
+  // scratch for boundary transposes
+  double* io_a = nullptr;     // [P][N][3]
+  double* io_b = nullptr;
+
+  QtbState qtb;
+
+  // profiling
+  int prof_which = 0;
+  double prof_ms = 0;
+  int64_t prof_launches = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+};
+
+// ---------------------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------------------
+int qhp_fail(qhp_ctx* c, int code, const std::string& msg);
+#define QHP_HIP(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return qhp_fail((ctx), QHP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// profiling brackets around the launches of one kernel class
+void prof_begin(qhp_ctx* c, int which, hipEvent_t* ev);
+void prof_end(qhp_ctx* c, int which, hipEvent_t ev);
+
+// ---------------------------------------------------------------------------------------
+// launchers implemented in the kernel files (all enqueue on c->stream, return hipError_t)
+// ---------------------------------------------------------------------------------------
+hipError_t launch_beads_to_modes(qhp_ctx* c, const double* xb, const double* vb);
+hipError_t launch_nm_step(qhp_ctx* c);
+hipError_t launch_state_out(qhp_ctx* c, double* xb, double* vb);
+hipError_t launch_kick_back(qhp_ctx* c);
+hipError_t launch_mode_energies(qhp_ctx* c, double* out2);
+hipError_t launch_transpose_in(qhp_ctx* c, const double* src, double* dst);
+hipError_t launch_transpose_out(qhp_ctx* c, const double* src, double* dst, double scale);
+hipError_t launch_centroid_of_beads(qhp_ctx* c);
+
+hipError_t launch_nlist(qhp_ctx* c, bool from_step);
+hipError_t launch_zero(qhp_ctx* c, void* ptr, size_t bytes);
+hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead);
+hipError_t launch_pair(qhp_ctx* c, bool energy, int bead);
+hipError_t launch_spme(qhp_ctx* c, bool energy, int bead);
+hipError_t launch_noise_export(qhp_ctx* c, int stream, int64_t step, double* out);
+
+hipError_t launch_qtb_generate(qhp_ctx* c, int64_t seg);
+hipError_t launch_qtb_adapt(qhp_ctx* c);
+hipError_t qtb_reset_gamma(qhp_ctx* c);
+
+int forces_all(qhp_ctx* c, bool energy, bool from_step);
+
+// ---------------------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------------------
+#define QHP_DEV __device__ __forceinline__
+
+namespace qhp {
+
+// Philox-4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+QHP_DEV void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0;
+    const uint64_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += W0; k1 += W1;
+  }
+}
+
+// The Gaussian transform below is written with IEEE +,-,*,/ and sqrt only, in a fixed
+// order and without contraction, so that every machine produces the same bits:
+//   ln u = e ln2 + 2 atanh((m-1)/(m+1)) with the atanh Taylor series;
+//   sin/cos(2 pi u) by exact reduction on u and Taylor series on [-pi/4, pi/4].
+#pragma clang fp contract(off)
+QHP_DEV double u53(uint64_t x) {
+  return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+QHP_DEV double exact_log(double u) {
+  int e;
+  double m = frexp(u, &e);
+  if (m < 0.7071067811865476) { m = m * 2.0; e -= 1; }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double s2 = s * s;
+  double p = 1.0 / 23.0;
+  p = p * s2 + 1.0 / 21.0;
+  p = p * s2 + 1.0 / 19.0;
+  p = p * s2 + 1.0 / 17.0;
+  p = p * s2 + 1.0 / 15.0;
+  p = p * s2 + 1.0 / 13.0;
+  p = p * s2 + 1.0 / 11.0;
+  p = p * s2 + 1.0 / 9.0;
+  p = p * s2 + 1.0 / 7.0;
+  p = p * s2 + 1.0 / 5.0;
+  p = p * s2 + 1.0 / 3.0;
+  p = p * s2 + 1.0;
+  const double r = (2.0 * s) * p;
+  return (double)e * 0.6931471805599453 + r;
+}
+
+// factorials as exact doubles; coefficients (-1)^k/(2k+1)! and (-1)^k/(2k)!
+QHP_DEV void exact_sincos_2pi(double u, double* sn, double* cs) {
+  const double q = rint(4.0 * u);
+  const double r = u - q * 0.25;
+  const double th = 6.283185307179586 * r;
+  const double t = th * th;
+  double sp = 1.0 / 355687428096000.0;            // +1/17!
+  sp = sp * t + (-1.0 / 1307674368000.0);         // -1/15!
+  sp = sp * t + (1.0 / 6227020800.0);             // +1/13!
+  sp = sp * t + (-1.0 / 39916800.0);              // -1/11!
+  sp = sp * t + (1.0 / 362880.0);                 // +1/9!
+  sp = sp * t + (-1.0 / 5040.0);                  // -1/7!
+  sp = sp * t + (1.0 / 120.0);                    // +1/5!
+  sp = sp * t + (-1.0 / 6.0);                     // -1/3!
+  sp = sp * t + 1.0;
+  const double s = th * sp;
+  double cp = -1.0 / 6402373705728000.0;          // -1/18!
+  cp = cp * t + (1.0 / 20922789888000.0);         // +1/16!
+  cp = cp * t + (-1.0 / 87178291200.0);           // -1/14!
+  cp = cp * t + (1.0 / 479001600.0);              // +1/12!
+  cp = cp * t + (-1.0 / 3628800.0);               // -1/10!
+  cp = cp * t + (1.0 / 40320.0);                  // +1/8!
+  cp = cp * t + (-1.0 / 720.0);                   // -1/6!
+  cp = cp * t + (1.0 / 24.0);                     // +1/4!
+  cp = cp * t + (-1.0 / 2.0);                     // -1/2!
+  cp = cp * t + 1.0;
+  const int qi = ((int)q) & 3;
+  if (qi == 0) { *sn = s; *cs = cp; }
+  else if (qi == 1) { *sn = cp; *cs = -s; }
+  else if (qi == 2) { *sn = -s; *cs = -cp; }
+  else { *sn = -cp; *cs = s; }
+}
+
+// Three standard normals from counter (c0, c1, c2, 0) under key (seed, stream):
+// Box-Muller on words (0,1) -> (cos, sin), then words (2,3) -> cos.
+QHP_DEV void gauss3(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1, uint64_t c2,
+                    double* g) {
+  uint64_t c[4] = {c0, c1, c2, 0ull};
+  philox4x64(c, seed, stream);
+  double sn, cs;
+  const double r0 = sqrt(-2.0 * exact_log(u53(c[0])));
+  exact_sincos_2pi(u53(c[1]), &sn, &cs);
+  g[0] = r0 * cs;
+  g[1] = r0 * sn;
+  const double r1 = sqrt(-2.0 * exact_log(u53(c[2])));
+  exact_sincos_2pi(u53(c[3]), &sn, &cs);
+  g[2] = r1 * cs;
+}
+#pragma clang fp contract(fast)
+
+constexpr uint64_t STREAM_RPMD_O = 5;
+constexpr uint64_t STREAM_QTB_WHITE = 6;
+
+QHP_DEV unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+}  // namespace qhp

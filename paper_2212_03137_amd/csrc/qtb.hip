@@ -1,0 +1,268 @@
+// Adaptive quantum thermal bath on classical beads (P = 1): segmented coloured-noise
+// generation, spectra, FDT deviation and SIMPLE adaptation (Secs. "adQTB",
+// "Colored Noise Generation", "Computation of the adQTB Spectra and Adaptation Procedure").
+//
+// Frequency grid omega_k = pi k / (N_seg dt), k = 0..N_seg. For atom type z:
+//   H_k = sqrt(2 m_z gamma_z(omega_k) Theta(omega_k) / dt), Theta(0) = kT,
+//   h_j = (1/2N_seg) sum_k H_k exp(2 pi i j k / 2N_seg), j = -N_seg .. N_seg-1 (H even),
+//   F_t = sum_j h_j w_{t-j}: the white noise of the previous, current and next segment
+//   enters segment s. It is evaluated as a circular convolution of length 4 N_seg, which
+//   is exact here because the kernel support (2 N_seg) plus the window (3 N_seg) never
+//   wraps onto the outputs kept (the middle N_seg).
+// White noise: Philox key (seed, 6), counter (global step + N_seg, atom, 0, 0), Gaussians
+// x, y, z. Spectra at the end of a segment: X_k = DFT of the segment zero-padded to
+// 2 N_seg, C_XY = (dt/N_seg) X conj(Y), Delta = m gamma C_vv - Re C_vF, averaged over the
+// degrees of freedom of each type; gamma <- max(gamma_min, gamma - A_gamma Delta).
+#include "qhp_internal.h"
+
+namespace {
+
+constexpr int NT = 256;
+
+QHP_DEV double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Single-block Stockham FFT of runtime length L (power of two) between two LDS buffers.
+// tw[m] = exp(-2 pi i m / L). Returns the buffer holding the result.
+QHP_DEV double2* fft_rt(double2* a, double2* b, int L, bool inv, const double2* tw) {
+  for (int Ns = 1; Ns < L;) {
+    const int R = (L / Ns >= 4) ? 4 : 2;
+    const int nb = L / R;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+      const int k = j % Ns;
+      double2 v[4];
+      for (int r = 0; r < R; ++r) {
+        v[r] = a[j + r * nb];
+        if (r) {
+          double2 t = tw[r * k * (L / (Ns * R))];
+          if (inv) t.y = -t.y;
+          v[r] = cmul(v[r], t);
+        }
+      }
+      const int idx = (j / Ns) * Ns * R + k;
+      if (R == 4) {
+        const double2 t0 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+        const double2 t1 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+        const double2 t2 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+        const double2 t3 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+        const double2 jt3 = inv ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
+        b[idx] = make_double2(t0.x + t2.x, t0.y + t2.y);
+        b[idx + 2 * Ns] = make_double2(t0.x - t2.x, t0.y - t2.y);
+        b[idx + Ns] = make_double2(t1.x + jt3.x, t1.y + jt3.y);
+        b[idx + 3 * Ns] = make_double2(t1.x - jt3.x, t1.y - jt3.y);
+      } else {
+        b[idx] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
+        b[idx + Ns] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
+      }
+    }
+    __syncthreads();
+    double2* t = a; a = b; b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+struct KerArgs {
+  int nseg;
+  const double* gamma;    // [T][nseg+1]
+  const double* tmass;    // [T]
+  double kT, hbar, dt;
+  int classical;
+  const double2* tw2; const double2* tw4;
+  double2* hhat;          // [T][4 nseg]
+};
+
+// one block per type: H -> h (inverse DFT of length 2N) -> embed -> DFT of length 4N
+__global__ __launch_bounds__(NT) void k_qtb_kernel(KerArgs A) {
+  extern __shared__ double2 lds[];
+  const int z = blockIdx.x, N = A.nseg, L2 = 2 * N, L4 = 4 * N;
+  double2* a = lds;
+  double2* b = lds + L4;
+  const double m = A.tmass[z];
+  const double* gz = A.gamma + (size_t)z * (N + 1);
+  for (int k = threadIdx.x; k < L2; k += blockDim.x) {
+    const int kk = k <= N ? k : L2 - k;
+    const double om = M_PI * kk / (N * A.dt);
+    double th = A.kT;
+    if (!A.classical && kk > 0) {
+      const double x = A.hbar * om;
+      th = 0.5 * x / tanh(0.5 * x / A.kT);
+    }
+    a[k] = make_double2(sqrt(2.0 * m * gz[kk] * th / A.dt), 0.0);
+  }
+  __syncthreads();
+  double2* h = fft_rt(a, b, L2, true, A.tw2);       // unnormalised inverse
+  double2* o = (h == a) ? b : a;
+  for (int l = threadIdx.x; l < L4; l += blockDim.x) {
+    double v = 0.0;
+    if (l < N) v = h[l].x;                    // j = l
+    else if (l >= 3 * N) v = h[l - 2 * N].x;  // j = l - 4N, stored at 2N + j
+    o[l] = make_double2(v / L2, 0.0);
+  }
+  __syncthreads();
+  double2* other = (o == a) ? b : a;
+  double2* H = fft_rt(o, other, L4, false, A.tw4);
+  for (int l = threadIdx.x; l < L4; l += blockDim.x) A.hhat[(size_t)z * L4 + l] = H[l];
+}
+
+struct GenArgs {
+  int N, nseg;
+  uint64_t seed;
+  int64_t seg;
+  const int* type;
+  const double2* hhat;
+  const double2* tw4;
+  double* noise;          // [nseg][3][N]
+};
+
+// one block per (atom, slot): slot 0 carries x + i y, slot 1 carries z
+__global__ __launch_bounds__(NT) void k_qtb_generate(GenArgs A) {
+  extern __shared__ double2 lds[];
+  const int a = blockIdx.x >> 1, slot = blockIdx.x & 1;
+  const int Ns = A.nseg, L4 = 4 * Ns;
+  double2* u = lds;
+  double2* v = lds + L4;
+  const uint64_t c0 = (uint64_t)(A.seg * Ns);   // counter of window sample 0
+  for (int l = threadIdx.x; l < L4; l += blockDim.x) {
+    double2 w = make_double2(0.0, 0.0);
+    if (l < 3 * Ns) {
+      double gs[3];
+      qhp::gauss3(A.seed, qhp::STREAM_QTB_WHITE, c0 + (uint64_t)l, (uint64_t)a, 0ull, gs);
+      w = slot == 0 ? make_double2(gs[0], gs[1]) : make_double2(gs[2], 0.0);
+    }
+    u[l] = w;
+  }
+  __syncthreads();
+  double2* W = fft_rt(u, v, L4, false, A.tw4);
+  const double2* Hz = A.hhat + (size_t)A.type[a] * L4;
+  for (int l = threadIdx.x; l < L4; l += blockDim.x) W[l] = cmul(W[l], Hz[l]);
+  __syncthreads();
+  double2* other = (W == u) ? v : u;
+  double2* C = fft_rt(W, other, L4, true, A.tw4);
+  const double inv = 1.0 / L4;
+  for (int t = threadIdx.x; t < Ns; t += blockDim.x) {
+    const double2 f = C[Ns + t];
+    if (slot == 0) {
+      A.noise[((size_t)t * 3 + 0) * A.N + a] = f.x * inv;
+      A.noise[((size_t)t * 3 + 1) * A.N + a] = f.y * inv;
+    } else {
+      A.noise[((size_t)t * 3 + 2) * A.N + a] = f.x * inv;
+    }
+  }
+}
+
+struct SpecArgs {
+  int N, nseg, ntypes, dofs_per_block;
+  const int* type;
+  const double* mass;
+  const double* gamma;
+  const double* vrec; const double* noise;
+  const double2* tw2;
+  double dt;
+  double* dsum;           // [T][nseg+1]
+};
+
+__global__ __launch_bounds__(NT) void k_qtb_spectra(SpecArgs A) {
+  extern __shared__ double2 lds[];
+  const int Ns = A.nseg, L2 = 2 * Ns;
+  double2* u = lds;
+  double2* v = lds + L2;
+  double* acc = (double*)(lds + 2 * L2);     // [T][nseg+1]
+  for (int k = threadIdx.x; k < A.ntypes * (Ns + 1); k += blockDim.x) acc[k] = 0.0;
+  const int ndof = 3 * A.N;
+  const int d0 = blockIdx.x * A.dofs_per_block;
+  const double sc = A.dt / Ns;
+  for (int dof = d0; dof < min(ndof, d0 + A.dofs_per_block); ++dof) {
+    const int d = dof % 3, a = dof / 3;
+    for (int t = threadIdx.x; t < L2; t += blockDim.x) {
+      double2 z = make_double2(0.0, 0.0);
+      if (t < Ns) {
+        const size_t i = ((size_t)t * 3 + d) * A.N + a;
+        z = make_double2(A.vrec[i], A.noise[i]);
+      }
+      u[t] = z;
+    }
+    __syncthreads();
+    double2* Z = fft_rt(u, v, L2, false, A.tw2);
+    const int ty = A.type[a];
+    const double m = A.mass[a];
+    const double* gz = A.gamma + (size_t)ty * (Ns + 1);
+    for (int k = threadIdx.x; k <= Ns; k += blockDim.x) {
+      const double2 zk = Z[k], zm = Z[(L2 - k) % L2];
+      // V = (Z_k + conj Z_-k) / 2, F = (Z_k - conj Z_-k) / 2i
+      const double vr = 0.5 * (zk.x + zm.x), vi = 0.5 * (zk.y - zm.y);
+      const double fr = 0.5 * (zk.y + zm.y), fi = -0.5 * (zk.x - zm.x);
+      const double cvv = sc * (vr * vr + vi * vi);
+      const double cvf = sc * (vr * fr + vi * fi);       // Re(V conj F)
+      acc[ty * (Ns + 1) + k] += m * gz[k] * cvv - cvf;
+    }
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < A.ntypes * (Ns + 1); k += blockDim.x)
+    if (acc[k] != 0.0) atomicAdd(A.dsum + k, acc[k]);
+}
+
+// gamma <- max(gamma_min, gamma - A Delta_bar); keep Delta_bar for export; clear sums
+__global__ void k_qtb_adapt(int n, int nseg, double* gamma, double* dsum, double* dbar,
+                            const double* inv_count, double rate, double gmin) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = dsum[i] * inv_count[i / (nseg + 1)];
+  dbar[i] = d;
+  gamma[i] = fmax(gmin, gamma[i] - rate * d);
+  dsum[i] = 0.0;
+}
+
+__global__ void k_fill(double* p, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t qtb_build_kernels(qhp_ctx* c) {
+  QtbState& q = c->qtb;
+  KerArgs A;
+  A.nseg = q.nseg; A.gamma = q.gamma; A.tmass = q.d_tmass; A.kT = c->p.kT; A.hbar = c->p.hbar;
+  A.dt = c->p.dt; A.classical = c->p.qtb_classical; A.tw2 = q.tw2; A.tw4 = q.tw4; A.hhat = q.hhat;
+  const size_t lds = (size_t)8 * q.nseg * sizeof(double2);
+  hipLaunchKernelGGL(k_qtb_kernel, c->p.n_types, NT, lds, c->stream, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_qtb_generate(qhp_ctx* c, int64_t seg) {
+  QtbState& q = c->qtb;
+  hipError_t e = qtb_build_kernels(c);
+  if (e != hipSuccess) return e;
+  GenArgs A;
+  A.N = c->N; A.nseg = q.nseg; A.seed = c->p.seed; A.seg = seg; A.type = c->d_type;
+  A.hhat = q.hhat; A.tw4 = q.tw4; A.noise = q.noise;
+  const size_t lds = (size_t)8 * q.nseg * sizeof(double2);
+  hipLaunchKernelGGL(k_qtb_generate, 2 * c->N, NT, lds, c->stream, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_qtb_adapt(qhp_ctx* c) {
+  QtbState& q = c->qtb;
+  SpecArgs A;
+  A.N = c->N; A.nseg = q.nseg; A.ntypes = c->p.n_types; A.dofs_per_block = 32;
+  A.type = c->d_type; A.mass = c->d_mass; A.gamma = q.gamma; A.vrec = q.vrec; A.noise = q.noise;
+  A.tw2 = q.tw2; A.dt = c->p.dt; A.dsum = q.dsum;
+  const int nb = (3 * c->N + A.dofs_per_block - 1) / A.dofs_per_block;
+  const size_t lds = (size_t)4 * q.nseg * sizeof(double2) +
+                     (size_t)c->p.n_types * (q.nseg + 1) * sizeof(double);
+  hipLaunchKernelGGL(k_qtb_spectra, nb, NT, lds, c->stream, A);
+  const int n = c->p.n_types * (q.nseg + 1);
+  hipLaunchKernelGGL(k_qtb_adapt, (n + 255) / 256, 256, 0, c->stream, n, q.nseg, q.gamma, q.dsum,
+                     q.dbar, q.d_inv_count, c->p.qtb_adapt_rate,
+                     c->p.qtb_gamma_min_frac * c->p.qtb_gamma0);
+  return hipGetLastError();
+}
+
+hipError_t qtb_reset_gamma(qhp_ctx* c) {
+  const int n = c->p.n_types * (c->qtb.nseg + 1);
+  hipLaunchKernelGGL(k_fill, (n + 255) / 256, 256, 0, c->stream, c->qtb.gamma, n, c->p.qtb_gamma0);
+  hipLaunchKernelGGL(k_fill, (n + 255) / 256, 256, 0, c->stream, c->qtb.dsum, n, 0.0);
+  return hipGetLastError();
+}

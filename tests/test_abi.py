@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every entry point the header declares; argument
+validation happens before any device call, so it is testable without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "qhp.h")).read()
+    return sorted(set(re.findall(r"QHP_API\s+(?:int|const char\*)\s+(qhp_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_surface():
+    import paper_2212_03137_amd as q
+    assert sorted(q.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    import paper_2212_03137_amd as q
+    if not os.path.exists(q.LIB_PATH):
+        pytest.skip("libqhp.so not built")
+    lib = ctypes.CDLL(q.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_params_struct_matches_header_fields():
+    import paper_2212_03137_amd as q
+    src = open(os.path.join(ROOT, "include", "qhp.h")).read()
+    body = src[src.index("typedef struct qhp_params {"):src.index("} qhp_params;")]
+    fields = re.findall(r"^\s*(?:const\s+)?[\w]+\**\s+\**([\w, ]+?)(?:\[\d\])?;", body, flags=re.M)
+    names = []
+    for f in fields:
+        names += [n.strip() for n in f.split(",")]
+    assert names == [f[0] for f in q.Params._fields_]
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(cutoff=7.0), -1),            # rc >= L/2 for a 12.42 A box
+    (dict(n_beads=3), -5),             # not a power of two
+    (dict(pme_order=7), -5),
+    (dict(pme_grid=(16, 16, 12)), -1),
+    (dict(exec_mode=7), -1),
+])
+def test_invalid_parameters_rejected_before_device_use(change, code):
+    import paper_2212_03137_amd as q
+    if not os.path.exists(q.LIB_PATH):
+        pytest.skip("libqhp.so not built")
+    s = synth.small_rpmd()
+    with pytest.raises(q.QhpError) as e:
+        q.Context.from_system(s, **change)
+    assert e.value.code == code

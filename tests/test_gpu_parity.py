@@ -1,0 +1,215 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Bars: bit-exact for the Philox/Gaussian noise streams and the centroid neighbour list;
+forces <= 1e-11 (max abs error over RMS force) and per-term energies <= 1e-11 relative in
+FP64; <= 1e-5 relative RMS for FP32 pairs (the tolerances of the workload definition).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import has_gpu, medium_box, oracle_grad_fn, rel_max, rel_rms
+from oracle import forces as ofo
+from oracle import philox as oph
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not has_gpu(), reason="needs a HIP device")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ctx_for(s, **kw):
+    import paper_2212_03137_amd as q
+    return q.Context.from_system(s, **kw)
+
+
+# ---------------------------------------------------------------------------- noise
+@pytest.mark.parametrize("P,N", [(1, 7), (8, 192), (32, 333)])
+def test_rpmd_noise_bit_exact(P, N):
+    s = synth.water_box(N // 3, P, 20.0, seed=3)
+    say("noise", P, N)
+    with ctx_for(s) as c:
+        for step in (0, 1, 12345, 2 ** 40 + 7):
+            got = c.noise(5, step)
+            ref = oph.rpmd_noise(s.seed, step, N, P)
+            assert np.array_equal(got, ref), (step, np.abs(got - ref).max())
+
+
+def test_qtb_white_noise_bit_exact():
+    s = synth.water_box(20, 1, 20.0, seed=4, qtb_gamma0=0.02, qtb_nseg=64)
+    with ctx_for(s) as c:
+        for tau in (-64, -1, 0, 5, 1000):
+            got = c.noise(6, tau)
+            ref = oph.qtb_white(s.seed, tau, 1, 60, 64)[0]
+            assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------------------- list
+@pytest.mark.parametrize("n_w,L,P,rc", [(64, 12.42, 8, 6.0), (216, 18.7, 2, 6.5),
+                                        (343, 21.8, 4, 8.0), (4096, 49.7, 1, 9.0)])
+def test_neighbour_list_bit_exact(n_w, L, P, rc):
+    s = synth.water_box(n_w, P, L, seed=n_w, cutoff=rc, pme_grid=16 if L < 15 else 32,
+                        pme_order=4)
+    say("nlist", n_w, L, P)
+    with ctx_for(s) as c:
+        c.eval(s.pos)
+        got = c.nlist()
+    ref = ofo.pair_list(ofo.centroids_of(s.pos), s.box, s.cutoff + s.skin)
+    assert got.shape == ref.shape and np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------------------- forces
+def _oracle_eval(s, beads=None):
+    pos = s.pos if beads is None else s.pos
+    return ofo.evaluate(pos, s)
+
+
+@pytest.fixture(scope="module")
+def small():
+    s = synth.small_rpmd()
+    return s, ofo.evaluate(s.pos, s)
+
+
+@pytest.fixture(scope="module")
+def medium():
+    s = medium_box()
+    return s, ofo.evaluate(s.pos, s)
+
+
+def _check_fp64(E, F, Eref, Fref):
+    assert rel_max(F, Fref) <= 1e-11, rel_max(F, Fref)
+    scale = np.abs(Eref).max(axis=0) + 1e-300
+    err = np.abs(E - Eref) / scale
+    assert err.max() <= 1e-11, err.max(axis=0)
+
+
+def test_eval_fp64_small(small):
+    s, (Eref, Fref) = small
+    say("eval fp64 small")
+    with ctx_for(s) as c:
+        E, F = c.eval(s.pos)
+    _check_fp64(E, F, Eref, Fref)
+
+
+def test_eval_fp64_medium_batched_and_plain(medium):
+    import paper_2212_03137_amd as q
+    s, (Eref, Fref) = medium
+    say("eval fp64 medium")
+    with ctx_for(s) as c:
+        E, F = c.eval(s.pos)
+    _check_fp64(E, F, Eref, Fref)
+    with ctx_for(s, exec_mode=q.PLAIN) as c:
+        E2, F2 = c.eval(s.pos)
+    _check_fp64(E2, F2, Eref, Fref)
+
+
+def test_eval_fp32_pairs_medium(medium):
+    import paper_2212_03137_amd as q
+    s, (Eref, Fref) = medium
+    say("eval fp32 medium")
+    with ctx_for(s, precision=q.FP32_PAIRS) as c:
+        E, F = c.eval(s.pos)
+    assert rel_rms(F, Fref) <= 1e-5, rel_rms(F, Fref)
+    # everything but the real-space pair terms is still FP64
+    for t in (0, 1, 4, 5, 6):
+        assert np.abs(E[:, t] - Eref[:, t]).max() <= 1e-11 * np.abs(Eref[:, t]).max()
+    for t in (2, 3):
+        assert np.abs(E[:, t] - Eref[:, t]).max() <= 1e-5 * np.abs(Eref[:, t]).max()
+
+
+# ---------------------------------------------------------------------------- dynamics
+def _oracle_rpmd(s):
+    from oracle import rpmd
+    R = rpmd.RPMD(s.n_beads, s.mass, s.kT, s.hbar, s.dt, s.gamma_centroid, s.trpmd_c, s.seed,
+                  oracle_grad_fn(s))
+    R.set_state(s.pos, s.vel)
+    return R
+
+
+def test_state_round_trip(small):
+    s, _ = small
+    with ctx_for(s) as c:
+        c.set_state(s.pos, s.vel, 17)
+        x, v, st = c.get_state()
+    assert st == 17
+    assert np.abs(x - s.pos).max() < 1e-12 * np.abs(s.pos).max()
+    assert np.abs(v - s.vel).max() < 1e-12 * np.abs(s.vel).max()
+
+
+@pytest.mark.parametrize("nsteps", [1, 100])
+def test_rpmd_trajectory_small(small, nsteps):
+    s, _ = small
+    say("rpmd trajectory", nsteps)
+    R = _oracle_rpmd(s)
+    R.step(nsteps)
+    xr, vr, _ = R.get_state()
+    with ctx_for(s) as c:
+        c.set_state(s.pos, s.vel, 0)
+        E = c.step(nsteps, energy=True)
+        x, v, st = c.get_state()
+        kin, spr = c.mode_energies()
+    assert st == nsteps
+    tol = 1e-11 if nsteps == 1 else 1e-8
+    assert np.abs(x - xr).max() / np.abs(xr).max() < tol
+    assert np.abs(v - vr).max() / np.abs(vr).max() < tol * 100
+    assert np.abs(E - R.E).max() / np.abs(R.E).max() < tol * 100
+    assert math.isclose(kin, R.kinetic(), rel_tol=tol * 100)
+    assert math.isclose(spr, R.spring(), rel_tol=tol * 100)
+
+
+def test_rpmd_trajectory_plain_fp64_equals_batched(small):
+    import paper_2212_03137_amd as q
+    s, _ = small
+    with ctx_for(s) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(20)
+        x1, v1, _ = c.get_state()
+    with ctx_for(s, exec_mode=q.PLAIN) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(20)
+        x2, v2, _ = c.get_state()
+    assert np.abs(x1 - x2).max() / np.abs(x1).max() < 1e-11
+
+
+# ---------------------------------------------------------------------------- full size
+@pytest.fixture(scope="module")
+def large():
+    return synth.large_rpmd()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_box_forces_on_sampled_beads(large, precision):
+    """4,096 waters, P = 32, in the launch configuration the benchmark times; the oracle
+    evaluates beads 0, 13 and 31 in full."""
+    import paper_2212_03137_amd as q
+    s = large
+    say("large eval", precision)
+    prec = q.FP64 if precision == "fp64" else q.FP32_PAIRS
+    with ctx_for(s, precision=prec) as c:
+        E, F = c.eval(s.pos)
+        pairs_gpu = c.nlist()
+    pairs = ofo.pair_list(ofo.centroids_of(s.pos), s.box, s.cutoff + s.skin)
+    assert np.array_equal(pairs_gpu, pairs)
+    for b in (0, 13, 31):
+        Eb, g = ofo.bead_potential(s.pos[b], s, pairs)
+        if precision == "fp64":
+            assert rel_max(F[b], -g) <= 1e-11
+            assert np.abs(E[b] - Eb).max() <= 1e-11 * np.abs(Eb).max()
+        else:
+            assert rel_rms(F[b], -g) <= 1e-5
+
+
+def test_large_box_step_stays_finite_and_rebuilds(large):
+    import paper_2212_03137_amd as q
+    s = large
+    with ctx_for(s, precision=q.FP32_PAIRS) as c:
+        c.set_state(s.pos, s.vel, 0)
+        E = c.step(20, energy=True)
+        x, v, st = c.get_state()
+    assert st == 20 and np.all(np.isfinite(x)) and np.all(np.isfinite(E))
