@@ -524,7 +524,9 @@ extern "C" int qhp_nlist_export(qhp_ctx* c, int32_t* pairs, int64_t capacity, in
 extern "C" int qhp_noise_export(qhp_ctx* c, int32_t stream, int64_t step, double* out) {
   if (!c || !out) return QHP_EINVAL;
   if (stream != 5 && stream != 6) return qhp_fail(c, QHP_EINVAL, "stream must be 5 or 6");
-  if (step < 0) return qhp_fail(c, QHP_EINVAL, "step must be >= 0");
+  if (stream == 5 && step < 0) return qhp_fail(c, QHP_EINVAL, "step must be >= 0");
+  if (stream == 6 && step + c->p.qtb_nseg < 0)
+    return qhp_fail(c, QHP_EINVAL, "white-noise step must be >= -N_seg");
   const size_t n = (size_t)(stream == 5 ? c->P : 1) * c->N * 3;
   QHP_HIP(c, launch_noise_export(c, stream, step, c->io_a));
   QHP_HIP(c, hipMemcpyAsync(out, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));

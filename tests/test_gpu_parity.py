@@ -30,9 +30,10 @@ def ctx_for(s, **kw):
 
 
 # ---------------------------------------------------------------------------- noise
-@pytest.mark.parametrize("P,N", [(1, 7), (8, 192), (32, 333)])
-def test_rpmd_noise_bit_exact(P, N):
-    s = synth.water_box(N // 3, P, 20.0, seed=3)
+@pytest.mark.parametrize("P,NW", [(1, 3), (8, 64), (32, 111)])
+def test_rpmd_noise_bit_exact(P, NW):
+    s = synth.water_box(NW, P, 20.0, seed=3)
+    N = s.n_atoms
     say("noise", P, N)
     with ctx_for(s) as c:
         for step in (0, 1, 12345, 2 ** 40 + 7):
