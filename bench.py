@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the ring-polymer MD hot path on one MI355X.
+
+Workload: 4,096 flexible 3-site waters (12,288 atoms) in a 49.7 A cube, rc 9 A, SPME 64^3
+order 5, P = 32 beads, 300 K, dt 0.5 fs: one step = normal-mode BAOAB + centroid-list
+check/rebuild + bonded + real-space pairs + SPME on all 32 beads. The headline `value` is
+the bead-batched path with FP32 pair forces (ns/day); the plain path (one launch per bead,
+all FP64) and the batched FP64 path are timed beside it on the same input. Inputs are
+seeded and synthetic and resident on the GPU before the timed region starts.
+
+    python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+# Algorithmic work per launch of each kernel class (definitions in DESIGN.md, "Roofline").
+#   pair   : FP32 flops; 30 per in-range pair-bead interaction (each pair once) and 8 per
+#            centroid-list candidate pair-bead test
+#   spread : bytes; bead positions read once + every grid value written once
+#   fft    : bytes; the complex grid read and written once by each of the 5 passes
+#   gather : bytes; grid read once + positions read + gradient read and written
+#   nm     : bytes; Q, P, grad V read, Q, P, x and the FP32 offsets written
+FLOPS_PER_PAIR = 30.0
+FLOPS_PER_CANDIDATE = 8.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--plain-steps", type=int, default=None,
+                    help="steps for the plain FP64 comparison (default: --steps)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip plain and batched FP64")
+    ap.add_argument("--breakdown", action="store_true", help="print per-kernel-class times")
+    return ap.parse_args()
+
+
+def pair_counts(s):
+    """In-range pair-bead interactions (each pair once) and candidate pair-bead tests of the
+    initial configuration, from a periodic k-d tree on every bead."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    L = float(s.box[0])
+    mol = np.arange(s.n_atoms) // 3
+    inrange = 0
+    for b in range(s.n_beads):
+        w = np.mod(s.pos[b], L)
+        w[w >= L] = 0.0
+        pr = cKDTree(w, boxsize=L).query_pairs(s.cutoff, output_type="ndarray")
+        inrange += int(np.count_nonzero(mol[pr[:, 0]] != mol[pr[:, 1]]))
+    c = s.pos.mean(axis=0)
+    w = np.mod(c, L)
+    w[w >= L] = 0.0
+    pr = cKDTree(w, boxsize=L).query_pairs(s.cutoff + s.skin, output_type="ndarray")
+    cand = int(np.count_nonzero(mol[pr[:, 0]] != mol[pr[:, 1]])) * s.n_beads
+    return inrange, cand
+
+
+def algorithmic_work(cls, s, counts):
+    N, P = s.n_atoms, s.n_beads
+    K = s.pme_grid
+    grid = K[0] * K[1] * K[2] * P * 8           # bytes of all bead grids (FP64)
+    xb = 3 * N * P * 8
+    if cls == "pair":
+        inr, cand = counts
+        return "flops", FLOPS_PER_PAIR * inr + FLOPS_PER_CANDIDATE * cand
+    if cls == "spread":
+        return "bytes", xb + grid
+    if cls == "fft":
+        return "bytes", 5 * 2 * grid
+    if cls == "gather":
+        return "bytes", grid + xb + 2 * xb
+    if cls == "nm":
+        return "bytes", 6 * xb + N * P * 16
+    raise ValueError(cls)
+
+
+def cpu_baseline(s, budget_s=20.0):
+    """The oracle as it stands, on a bounded sample: the centroid pair list and the full
+    per-bead potential of as many beads as fit in about `budget_s` seconds."""
+    import resource
+    from oracle import forces as ofo
+    t0 = time.perf_counter()
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    pairs = ofo.pair_list(ofo.centroids_of(s.pos), s.box, s.cutoff + s.skin)
+    t_list = time.perf_counter() - t0
+    nb = 0
+    t_beads = 0.0
+    while nb < s.n_beads and (nb < 1 or t_list + t_beads < budget_s):
+        t1 = time.perf_counter()
+        ofo.bead_potential(s.pos[nb], s, pairs)
+        t_beads += time.perf_counter() - t1
+        nb += 1
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    step_s = t_list + t_beads / nb * s.n_beads          # one list build + all beads
+    return {
+        "value": s.n_atoms * s.n_beads / step_s,
+        "unit": "bead*atom-steps/s",
+        "cores": max(1, round(cpu / wall)),
+        "kind": "oracle",
+        "sample": (f"numpy FP64 oracle: centroid pair list + potential and forces of {nb} of "
+                   f"{s.n_beads} beads of the 4,096-water box ({wall:.1f} s), scaled to one "
+                   f"step of all beads ({step_s:.1f} s/step)"),
+        "ns_per_day": 86400.0 / step_s * s.dt * 1e-6,
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2212_03137_amd as q
+
+    s = synth.large_rpmd()
+    stream = torch.cuda.current_stream().cuda_stream
+    dt = s.dt
+
+    def make(prec, ex):
+        c = q.Context.from_system(s, precision=prec, exec_mode=ex, stream=stream)
+        c.set_state(s.pos, s.vel, 0)
+        return c
+
+    def timed(c, steps, prof=None):
+        if prof:
+            c.profile(prof)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(steps)                 # one call: K steps, one host sync at the end
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        pr = c.profile_read() if prof else None
+        if prof:
+            c.profile("off")
+        return t, pr
+
+    # --- which kernel class dominates the batched FP32-pair step (short untimed pass) ---
+    main_ctx = make(q.FP32_PAIRS, q.BATCHED)
+    main_ctx.step(args.warmup)
+    classes = ["pair", "spread", "fft", "gather", "nm"]
+    per_class = {}
+    for cl in classes:
+        _, (ms, n) = timed(main_ctx, 20, cl)
+        per_class[cl] = ms / 20.0
+    dominant = max(per_class, key=per_class.get)
+    if args.breakdown:
+        print(json.dumps({"breakdown_ms_per_step": per_class}), file=sys.stderr)
+
+    # --- timed region: exactly K steps, events around the dominant kernel class ---
+    t, (dom_ms, dom_n) = timed(main_ctx, args.steps, dominant)
+    main_ctx.close()
+    ms_step = t / args.steps * 1e3
+    steps_per_s = args.steps / t
+    ns_day = steps_per_s * dt * 86400.0 * 1e-6
+    bas = steps_per_s * s.n_atoms * s.n_beads
+
+    counts = pair_counts(s)
+    kind, work = algorithmic_work(dominant, s, counts)
+    # one event pair brackets one step's launch(es) of the class (the 5 FFT passes count
+    # as one unit of work)
+    avg_s = dom_ms / dom_n * 1e-3 if dom_n else float("nan")
+    if kind == "bytes":
+        achieved = work / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        achieved = work / avg_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dominant
+    roof["avg_launch_ms"] = dom_ms / dom_n if dom_n else None
+
+    out = {
+        "metric": "ns/day & bead·atom-steps/s, 4096-water RPMD P=32; batched vs plain",
+        "value": ns_day,
+        "unit": "ns/day",
+        "bead_atom_steps_per_s": bas,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pairs + f64",
+        "data": "synthetic (seeded jittered-lattice water, thermal ring polymers)",
+        "config": {"workload": "water4096_P32: 4,096 flexible 3-site waters, 49.7 A cube, "
+                               "rc 9 A, SPME 64^3 order 5, P=32, 300 K, dt 0.5 fs, "
+                               "bead-batched FP32-pair path",
+                   "n_atoms": s.n_atoms, "n_beads": s.n_beads, "parallelism": "single GPU"},
+        "roofline": roof,
+        "breakdown_ms_per_step": per_class,
+    }
+
+    if not args.no_compare:
+        comp = {}
+        for name, prec, ex in (("batched_fp64", q.FP64, q.BATCHED), ("plain_fp64", q.FP64, q.PLAIN)):
+            c = make(prec, ex)
+            c.step(args.warmup)
+            k = args.plain_steps or args.steps
+            tt, _ = timed(c, k)
+            c.close()
+            sps = k / tt
+            comp[name] = {"ns_per_day": sps * dt * 86400e-6, "ms_per_step": tt / k * 1e3,
+                          "bead_atom_steps_per_s": sps * s.n_atoms * s.n_beads, "steps": k}
+        out["compare"] = comp
+        out["speedup_vs_plain_fp64"] = ns_day / comp["plain_fp64"]["ns_per_day"]
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

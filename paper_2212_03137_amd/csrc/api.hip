@@ -18,17 +18,28 @@ int qhp_fail(qhp_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
+// Events come from a pool that grows on demand and is recycled by qhp_profile_read, so a
+// timed loop only records events.
+static hipEvent_t pool_event(qhp_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
 void prof_begin(qhp_ctx* c, int which, hipEvent_t* ev) {
   *ev = nullptr;
   if (c->prof_which != which) return;
-  if (hipEventCreate(ev) != hipSuccess) { *ev = nullptr; return; }
-  (void)hipEventRecord(*ev, c->stream);
+  *ev = pool_event(c);
+  if (*ev) (void)hipEventRecord(*ev, c->stream);
 }
 
 void prof_end(qhp_ctx* c, int which, hipEvent_t ev) {
   if (c->prof_which != which || !ev) return;
-  hipEvent_t e2;
-  if (hipEventCreate(&e2) != hipSuccess) return;
+  hipEvent_t e2 = pool_event(c);
+  if (!e2) return;
   (void)hipEventRecord(e2, c->stream);
   c->ev_pending.emplace_back(ev, e2);
 }
@@ -101,7 +112,8 @@ void free_all(qhp_ctx* c) {
                   c->qtb.tw2, c->qtb.tw4};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  for (auto& pr : c->ev_pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
   c->ev_pending.clear();
 }
 
@@ -580,8 +592,8 @@ extern "C" int qhp_profile(qhp_ctx* c, int which) {
   if (!c) return QHP_EINVAL;
   if (which < 0 || which > QHP_PROF_NM) return qhp_fail(c, QHP_EINVAL, "profile class");
   QHP_HIP(c, hipStreamSynchronize(c->stream));
-  for (auto& pr : c->ev_pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
   c->ev_pending.clear();
+  c->ev_used = 0;
   c->prof_which = which;
   c->prof_ms = 0;
   c->prof_launches = 0;
@@ -595,10 +607,9 @@ extern "C" int qhp_profile_read(qhp_ctx* c, double* ms, int64_t* launches) {
     float t = 0;
     if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) c->prof_ms += t;
     c->prof_launches += 1;
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
   }
   c->ev_pending.clear();
+  c->ev_used = 0;
   *ms = c->prof_ms;
   *launches = c->prof_launches;
   return QHP_OK;

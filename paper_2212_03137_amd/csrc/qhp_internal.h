@@ -122,6 +122,7 @@ struct qhp_ctx {
   double prof_ms = 0;
   int64_t prof_launches = 0;
   std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
 };
 
