@@ -162,6 +162,10 @@ QHP_API int qhp_mode_energies(qhp_ctx* ctx, double* kinetic, double* spring);
  * If `capacity` (in pairs) is too small, *npairs is set and QHP_ENOMEM returned. */
 QHP_API int qhp_nlist_export(qhp_ctx* ctx, int32_t* pairs, int64_t capacity, int64_t* npairs);
 
+/* Neighbour-list bookkeeping: number of list builds since qhp_create, the largest
+ * neighbour count of the last build and the per-atom capacity (host outputs). */
+QHP_API int qhp_nlist_stats(qhp_ctx* ctx, int64_t* builds, int32_t* max_count, int32_t* capacity);
+
 /* Gaussian noise as the kernels draw it (Philox-4x64-10, key (seed, stream), Box-Muller):
  * stream 5 = TRPMD O-step noise of step `step`, out [P][N][3] indexed [mode][atom][xyz];
  * stream 6 = adQTB white noise of global step `step`, out [N][3]. Device computation,

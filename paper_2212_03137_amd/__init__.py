@@ -24,7 +24,7 @@ TERMS = ("bond", "angle", "coul_real", "lj", "coul_excl", "coul_self", "coul_rec
 PROF = {"off": 0, "pair": 1, "spread": 2, "fft": 3, "gather": 4, "nm": 5}
 
 EXPORTS = ("qhp_create", "qhp_destroy", "qhp_eval", "qhp_set_state", "qhp_get_state",
-           "qhp_step", "qhp_mode_energies", "qhp_nlist_export", "qhp_noise_export",
+           "qhp_step", "qhp_mode_energies", "qhp_nlist_export", "qhp_nlist_stats", "qhp_noise_export",
            "qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta",
            "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error")
 
@@ -75,6 +75,8 @@ def load():
     lib.qhp_step.argtypes = [vp, C.c_int32, vp, I]
     lib.qhp_mode_energies.argtypes = [vp, D, D]
     lib.qhp_nlist_export.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.qhp_nlist_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]
     lib.qhp_noise_export.argtypes = [vp, C.c_int32, C.c_int64, vp]
     for f in ("qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta"):
         getattr(lib, f).argtypes = [vp, vp]
@@ -217,6 +219,11 @@ class Context:
         out = np.zeros((n.value, 2), dtype=np.int32)
         self._check(self._lib.qhp_nlist_export(self._h, _ptr(out), n.value, C.byref(n)))
         return out.astype(np.int64)
+
+    def nlist_stats(self):
+        b, m, cap = C.c_int64(), C.c_int32(), C.c_int32()
+        self._check(self._lib.qhp_nlist_stats(self._h, C.byref(b), C.byref(m), C.byref(cap)))
+        return {"builds": b.value, "max_count": m.value, "capacity": cap.value}
 
     def noise(self, stream, step):
         rows = self.P if stream == 5 else 1

