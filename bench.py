@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip plain and batched FP64")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel-class times")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of graphs")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for hardware counters: a 256 MiB device copy (calibration), then "
+                         "--steps launched steps of the batched FP32-pair path; no JSON")
     return ap.parse_args()
 
 
@@ -135,8 +139,8 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     dt = s.dt
 
-    def make(prec, ex):
-        c = q.Context.from_system(s, precision=prec, exec_mode=ex, stream=stream)
+    def make(prec, ex, graph=not args.no_graph):
+        c = q.Context.from_system(s, precision=prec, exec_mode=ex, stream=stream, use_graph=graph)
         c.set_state(s.pos, s.vel, 0)
         return c
 
@@ -153,6 +157,21 @@ def main():
             c.profile("off")
         return t, pr
 
+    if args.pmc_probe:
+        # a plain copy of known size (256 MiB read, 256 MiB written) to scale the
+        # FETCH_SIZE / WRITE_SIZE counters, then launched steps of the timed path
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        c = make(q.FP32_PAIRS, q.BATCHED, graph=False)
+        c.step(args.warmup)
+        c.step(args.steps)
+        c.close()
+        torch.cuda.synchronize()
+        print("pmc probe done", file=sys.stderr)
+        return
+
     # --- which kernel class dominates the batched FP32-pair step (short untimed pass) ---
     main_ctx = make(q.FP32_PAIRS, q.BATCHED)
     main_ctx.step(args.warmup)
@@ -165,13 +184,16 @@ def main():
     if args.breakdown:
         print(json.dumps({"breakdown_ms_per_step": per_class}), file=sys.stderr)
 
-    # --- timed region: exactly K steps, events around the dominant kernel class ---
-    t, (dom_ms, dom_n) = timed(main_ctx, args.steps, dominant)
-    main_ctx.close()
+    # --- timed region: exactly K steps (each step one graph replay) ---
+    t, _ = timed(main_ctx, args.steps)
     ms_step = t / args.steps * 1e3
     steps_per_s = args.steps / t
     ns_day = steps_per_s * dt * 86400.0 * 1e-6
     bas = steps_per_s * s.n_atoms * s.n_beads
+    # --- the same K steps launched kernel by kernel, HIP events around the dominant class
+    #     on the context's stream (graph replays carry no per-kernel events) ---
+    t_prof, (dom_ms, dom_n) = timed(main_ctx, args.steps, dominant)
+    main_ctx.close()
 
     counts = pair_counts(s)
     kind, work = algorithmic_work(dominant, s, counts)
@@ -189,6 +211,8 @@ def main():
     roof["traffic"] = None
     roof["kernel"] = dominant
     roof["avg_launch_ms"] = dom_ms / dom_n if dom_n else None
+    roof["launches"] = dom_n
+    roof["profiled_region_ms_per_step"] = t_prof / args.steps * 1e3
 
     out = {
         "metric": "ns/day & bead·atom-steps/s, 4096-water RPMD P=32; batched vs plain",

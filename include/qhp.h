@@ -116,12 +116,13 @@ typedef struct qhp_params {
   double qtb_gamma_min_frac;/* adQTB: gamma_min = frac * gamma_0 (paper default 0.01)    */
   int32_t qtb_classical;    /* adQTB test switch: Theta(omega) = kT (white-noise limit)  */
   int32_t nbr_capacity;     /* neighbours per atom kept; 0 = sized from density          */
+  int32_t use_graph;        /* 1: replay each step as one captured HIP graph; 0: launch   */
 } qhp_params;
 
 typedef struct qhp_ctx qhp_ctx;
 
-/* Create a context on the current HIP device. `stream` is a hipStream_t (NULL = the
- * null stream); all work of the context is queued on it. Validates `p` (QHP_EINVAL),
+/* Create a context on the current HIP device. `stream` is a hipStream_t; all work of the
+ * context is queued on it (NULL: the library creates a private non-blocking stream). Validates `p` (QHP_EINVAL),
  * allocates device state (QHP_ENOMEM) and precomputes the normal-mode transfer matrix,
  * mode frequencies, thermostat and A-block coefficients and the SPME influence function.
  * The state is undefined until qhp_set_state. */

@@ -11,7 +11,7 @@ Neighbour pairs are found on ring-polymer *centroids*: two atoms are neighbours 
 bead if their centroids are (Sec. "Massively Parallel Implementation"). The list is
 defined here by brute force: all intermolecular (i < j) with minimum-image centroid
 distance squared strictly below r_list^2, the squared distance evaluated as
-dx - L rint(dx / L) per axis then dx*dx + dy*dy + dz*dz, with no fused operations.
+dx - L rint(dx * (1/L)) per axis then (dx*dx + dy*dy) + dz*dz, with no fused operations.
 
 Energies are returned per term in the order
 [bond, angle, coulomb_real, lennard_jones, coulomb_excluded, coulomb_self, coulomb_recip].
@@ -32,16 +32,22 @@ def min_image(d, box):
 
 
 def pair_list(centroids, box, r_list, n_per_mol=3):
-    """Brute-force centroid pair list: sorted (i, j) with i < j, different molecules."""
+    """Brute-force centroid pair list: sorted (i, j) with i < j, different molecules.
+
+    Canonical arithmetic (a reading: the paper fixes no rounding): d = c_j - c_i,
+    d <- d - L rint(d * (1/L)) per axis with 1/L rounded once, d2 = (dx*dx + dy*dy) + dz*dz,
+    kept when d2 < r_list * r_list.
+    """
     N = len(centroids)
     mol = np.arange(N) // n_per_mol
     r2max = r_list * r_list
+    inv = 1.0 / box
     I_all, J_all = [], []
     chunk = max(1, 4_000_000 // max(N, 1))
     for i0 in range(0, N, chunk):
         i = np.arange(i0, min(N, i0 + chunk))
         d = centroids[None, :, :] - centroids[i, None, :]
-        d = d - box * np.rint(d / box)
+        d = d - box * np.rint(d * inv)
         d2 = d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]
         d2 = d2 + d[..., 2] * d[..., 2]
         ii, jj = np.nonzero(d2 < r2max)

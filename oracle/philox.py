@@ -137,14 +137,16 @@ def rpmd_noise(seed, step, n_atoms, n_beads):
     return g[..., :3]
 
 
-def qtb_white(seed, tau0, n_steps, n_atoms, nseg):
-    """adQTB white noise w[t][atom][xyz] for global steps tau0 .. tau0+n_steps-1.
+def qtb_white(seed, tau0, n_steps, n_atoms, nseg, atoms=None):
+    """adQTB white noise w[t][atom][xyz] for global steps tau0 .. tau0+n_steps-1 (all atoms,
+    or the given atom indices).
 
     Counter (tau + nseg, atom, 0, 0) so that the window of the first segment, which
     reaches back one segment before step 0, still has a non-negative counter.
     """
     tau = np.arange(tau0, tau0 + n_steps, dtype=np.int64) + nseg
     assert tau.min() >= 0
+    idx = np.arange(n_atoms) if atoms is None else np.asarray(atoms)
     g = gaussians4(seed, STREAM_QTB_WHITE, tau.astype(np.uint64)[:, None],
-                   np.arange(n_atoms, dtype=np.uint64)[None, :], np.uint64(0))
+                   idx.astype(np.uint64)[None, :], np.uint64(0))
     return g[..., :3]

@@ -105,13 +105,17 @@ void free_all(qhp_ctx* c) {
   void* ptrs[] = {c->T, c->mode_c, c->mode_s_w, c->mode_ws, c->mode_c1, c->mode_c2, c->mode_w2,
                   c->d_type, c->d_mass, c->d_charge, c->d_sqrt_mkT, c->d_sigma, c->d_eps,
                   c->Q, c->Pa, c->x, c->g, c->cent, c->cref, c->coff, c->cwrap, c->xf, c->ctrl,
-                  c->cell_of, c->cell_count, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
-                  c->nnbr, c->bmax, c->grid, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
+                  c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
+                  c->nnbr, c->bmax, c->grid, c->tile_nbr, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
                   c->io_a, c->io_b, c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.d_tmass, c->qtb.d_inv_count,
                   c->qtb.tw2, c->qtb.tw4};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  c->step_exec = nullptr;
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  c->stream = nullptr;
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   c->ev_pool.clear();
   c->ev_pending.clear();
@@ -194,6 +198,15 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   if (!c) return QHP_ENOMEM;
   c->p = *p;
   c->stream = (hipStream_t)stream;
+  if (!c->stream) {
+    // a private stream (default priority): the null stream cannot be captured into a graph
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return QHP_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  c->use_graph = p->use_graph != 0;
   const int N = p->n_atoms, P = p->n_beads;
   c->N = N; c->P = P; c->NW = N / 3; c->Pc = P == 1 ? 1 : P / 2;
   c->type.assign(p->type, p->type + N);
@@ -258,30 +271,34 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   TRY(hipMemset(c->cref, 0, N * sizeof(double4)));
   TRY(hipMemset(c->coff, 0, N * sizeof(double4)));
 
-  // ---- neighbour list: cells of edge >= r_list (a small margin keeps rounding of the
-  //      fractional coordinate from skipping a cell) and their distinct neighbour cells ----
+  // ---- neighbour list: cells of edge >= r_list / 2 (a small margin keeps rounding of the
+  //      fractional coordinate from skipping a cell) and their distinct neighbour cells
+  //      within two cells per axis ----
   c->rlist = p->cutoff + p->skin;
+  const double half = 0.5 * c->rlist;
   for (int d = 0; d < 3; ++d) {
-    int n = std::max(1, (int)std::floor(p->box[d] / c->rlist));
-    while (n > 1 && p->box[d] / n < c->rlist * (1.0 + 1e-9)) --n;
+    int n = std::max(1, (int)std::floor(p->box[d] / half));
+    while (n > 1 && p->box[d] / n < half * (1.0 + 1e-9)) --n;
     c->nc[d] = n;
   }
   c->ncell = c->nc[0] * c->nc[1] * c->nc[2];
-  std::vector<int> st((size_t)c->ncell * 27, -1);
+  c->nst = 125;
+  std::vector<int> st((size_t)c->ncell * c->nst, -1);
   for (int a = 0; a < c->nc[0]; ++a)
     for (int b = 0; b < c->nc[1]; ++b)
       for (int e = 0; e < c->nc[2]; ++e) {
         std::set<int> s;
-        for (int da = -1; da <= 1; ++da)
-          for (int db = -1; db <= 1; ++db)
-            for (int de = -1; de <= 1; ++de) {
-              const int ia = (a + da + c->nc[0]) % c->nc[0], ib = (b + db + c->nc[1]) % c->nc[1],
-                        ie = (e + de + c->nc[2]) % c->nc[2];
+        for (int da = -2; da <= 2; ++da)
+          for (int db = -2; db <= 2; ++db)
+            for (int de = -2; de <= 2; ++de) {
+              const int ia = ((a + da) % c->nc[0] + c->nc[0]) % c->nc[0];
+              const int ib = ((b + db) % c->nc[1] + c->nc[1]) % c->nc[1];
+              const int ie = ((e + de) % c->nc[2] + c->nc[2]) % c->nc[2];
               s.insert((ia * c->nc[1] + ib) * c->nc[2] + ie);
             }
         int k = 0;
         const int id = (a * c->nc[1] + b) * c->nc[2] + e;
-        for (int v2 : s) st[(size_t)id * 27 + k++] = v2;
+        for (int v2 : s) st[(size_t)id * c->nst + k++] = v2;
       }
   TRY(dalloc(&c->stencil, st.size()));
   TRY(hipMemcpy(c->stencil, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -297,9 +314,9 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   TRY(dalloc(&c->ctrl, 1));
   c->n_bmax = (N + 255) / 256 * 64;      // >= blocks of the normal-mode kernel for any P
   TRY(dalloc(&c->bmax, c->n_bmax));
-  TRY(hipMemset(c->bmax, 0, c->n_bmax * sizeof(double2)));
+  TRY(hipMemset(c->bmax, 0, c->n_bmax * sizeof(double4)));
   TRY(hipMemset(c->ctrl, 0, sizeof(NlCtrl)));
-  TRY(dalloc(&c->cell_of, N)); TRY(dalloc(&c->cell_count, c->ncell));
+  TRY(dalloc(&c->cell_of, N)); TRY(dalloc(&c->cell_count, c->ncell)); TRY(dalloc(&c->cell_fill, c->ncell));
   TRY(dalloc(&c->cell_start, c->ncell + 1)); TRY(dalloc(&c->cell_atoms, N));
   TRY(dalloc(&c->nbr, (size_t)c->cap * N)); TRY(dalloc(&c->nnbr, N));
   TRY(hipMemset(c->nnbr, 0, N * sizeof(int)));
@@ -326,6 +343,31 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     TRY(up(&c->influence, G));
   }
   for (int d = 0; d < 3; ++d) TRY(upload_twiddles(&c->tw[d], c->K[d]));
+  {
+    // 8^3-point spreading tiles and their distinct neighbours (one tile either way)
+    int nt[3];
+    for (int d = 0; d < 3; ++d) nt[d] = c->K[d] / 8;
+    c->ntiles = nt[0] * nt[1] * nt[2];
+    std::vector<int> tn((size_t)c->ntiles * 27, -1);
+    for (int a = 0; a < nt[0]; ++a)
+      for (int b = 0; b < nt[1]; ++b)
+        for (int e = 0; e < nt[2]; ++e) {
+          std::set<int> s;
+          for (int da = -1; da <= 1; ++da)
+            for (int db = -1; db <= 1; ++db)
+              for (int de = -1; de <= 1; ++de)
+                s.insert((((a + da + nt[0]) % nt[0]) * nt[1] + (b + db + nt[1]) % nt[1]) * nt[2] +
+                         (e + de + nt[2]) % nt[2]);
+          int k = 0;
+          for (int v2 : s) tn[(size_t)((a * nt[1] + b) * nt[2] + e) * 27 + k++] = v2;
+        }
+    TRY(dalloc(&c->tile_nbr, tn.size()));
+    TRY(hipMemcpy(c->tile_nbr, tn.data(), tn.size() * sizeof(int), hipMemcpyHostToDevice));
+    TRY(dalloc(&c->tile_of, N)); TRY(dalloc(&c->tile_atoms, N));
+    TRY(dalloc(&c->tile_count, c->ntiles)); TRY(dalloc(&c->tile_fill, c->ntiles));
+    TRY(dalloc(&c->tile_start, c->ntiles + 1));
+    TRY(hipMemset(c->tile_count, 0, c->ntiles * sizeof(int)));
+  }
 
   // ---- adQTB ----
   if (p->thermostat == QHP_ADQTB) {
@@ -410,6 +452,9 @@ static int check_ctrl(qhp_ctx* c) {
                                        " exceeded (max count " + std::to_string(h.max_count) +
                                        "); raise nbr_capacity");
   if (h.nonfinite) return qhp_fail(c, QHP_ENONFINITE, "state became non-finite");
+  if (h.spread_margin)
+    return qhp_fail(c, QHP_EUNSUPPORTED,
+                    "a bead is further from its centroid than the SPME tile margin allows");
   return QHP_OK;
 }
 
@@ -454,6 +499,11 @@ extern "C" int qhp_set_state(qhp_ctx* c, const double* pos, const double* vel, i
   if ((r = forces_all(c, false, false))) return r;
   QHP_HIP(c, launch_kick_back(c));          // store Pa = P - (dt/2) f
   c->step = step;
+  {
+    long long st = step;
+    QHP_HIP(c, hipMemcpyAsync(&c->ctrl->step, &st, sizeof(st), hipMemcpyHostToDevice, c->stream));
+    QHP_HIP(c, hipStreamSynchronize(c->stream));
+  }
   if (c->p.thermostat == QHP_ADQTB) {
     QHP_HIP(c, qtb_reset_gamma(c));
     QHP_HIP(c, launch_qtb_generate(c, step / c->qtb.nseg));
@@ -479,18 +529,51 @@ extern "C" int qhp_get_state(qhp_ctx* c, double* pos, double* vel, int64_t* step
   return QHP_OK;
 }
 
+// One propagation step: B A O A (normal modes), then bonded, list check/rebuild, pairs
+// and SPME at the new beads.
+static int one_step(qhp_ctx* c, bool energy) {
+  hipEvent_t ev = nullptr;
+  prof_begin(c, QHP_PROF_NM, &ev);
+  QHP_HIP(c, launch_nm_step(c));
+  prof_end(c, QHP_PROF_NM, ev);
+  return forces_all(c, energy, true);
+}
+
+// Capture one step (without energies) as a HIP graph on the context's stream.
+static int capture_step(qhp_ctx* c) {
+  hipGraph_t g = nullptr;
+  QHP_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int r = one_step(c, false);
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (r) { if (g) (void)hipGraphDestroy(g); return r; }
+  if (e != hipSuccess) return qhp_fail(c, QHP_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->step_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->step_exec = nullptr;
+    return qhp_fail(c, QHP_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  return QHP_OK;
+}
+
 extern "C" int qhp_step(qhp_ctx* c, int32_t nsteps, double* energy, int mem_kind) {
   if (!c) return QHP_EINVAL;
   if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
   if (nsteps < 0) return qhp_fail(c, QHP_EINVAL, "nsteps must be >= 0");
   const bool qtb = c->p.thermostat == QHP_ADQTB;
   for (int s = 0; s < nsteps; ++s) {
-    hipEvent_t ev = nullptr;
-    prof_begin(c, QHP_PROF_NM, &ev);
-    QHP_HIP(c, launch_nm_step(c));
-    prof_end(c, QHP_PROF_NM, ev);
-    int r = forces_all(c, energy != nullptr && s == nsteps - 1, true);
-    if (r) return r;
+    const bool want_e = energy != nullptr && s == nsteps - 1;
+    const bool graph = c->use_graph && !want_e && c->prof_which == QHP_PROF_OFF;
+    if (graph) {
+      if (!c->step_exec) {
+        int r = capture_step(c);
+        if (r) return r;
+      }
+      QHP_HIP(c, hipGraphLaunch(c->step_exec, c->stream));
+    } else {
+      int r = one_step(c, want_e);
+      if (r) return r;
+    }
     c->step += 1;
     if (qtb && c->step % c->qtb.nseg == 0) {
       QHP_HIP(c, launch_qtb_adapt(c));
@@ -525,7 +608,7 @@ extern "C" int qhp_nlist_export(qhp_ctx* c, int32_t* pairs, int64_t capacity, in
   std::vector<std::pair<int, int>> out;
   for (int i = 0; i < N; ++i)
     for (int k = 0; k < nn[i]; ++k) {
-      const int j = nb[(size_t)k * N + i] & 0x3FFFFFF;
+      const int j = nb[(size_t)i * c->cap + k] & 0x3FFFFFF;
       if (j > i) out.emplace_back(i, j);
     }
   std::sort(out.begin(), out.end());

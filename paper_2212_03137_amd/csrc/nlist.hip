@@ -2,170 +2,241 @@
 // computed on ring-polymer centroids; if two centroids are neighbours, all their beads
 // are). One list serves every bead of every step until the skin is used up.
 //
-// Build: cells of edge >= r_list on the centroids (wrapped fractional coordinate x n_c,
-// floored, clamped to n_c - 1), a deterministic fill of each cell in atom order, then for
-// every atom a scan of the distinct neighbouring cells. A pair (i, j) of different
+// Build: cells of edge >= r_list / 2 on the centroids (wrapped fractional coordinate x n_c,
+// floored, clamped to n_c - 1); each cell's atoms in increasing atom order; one block per
+// cell stages the atoms of its (up to) 5 x 5 x 5 distinct neighbouring cells in LDS and
+// every wavefront scans them for one atom i of the cell. A pair (i, j) of different
 // molecules is kept when the minimum-image centroid distance squared is < r_list^2,
-// evaluated as dx - L rint(dx / L) per axis and dx*dx + dy*dy, then + dz*dz, without
+// evaluated as d - L rint(d * (1/L)) per axis and (dx*dx + dy*dy) + dz*dz without
 // contraction, so the list is reproducible bit for bit.
 //
-// Entry k of atom i is nbr[k * N + i] = j | (sx+1) << 26 | (sy+1) << 28 | (sz+1) << 30
+// Row i of the list (nbr[i * cap + k]) holds j | (sx+1) << 26 | (sy+1) << 28 | (sz+1) << 30,
 // with s the image shift between the two centroids in the frame wrapped at build time
 // (each centroid minus L floor(c / L)); the pair kernel reuses it on the wrapped
 // centroids, which stay continuous until the next build.
 //
-// Rebuild rule, checked on the device every step: rebuild when
-// 2 (max centroid displacement since the build + max bead-centroid distance) > skin.
+// Rebuild rule, checked on the device every step: rebuild unless
+// 2 (max centroid displacement since the build + max bead-centroid distance) <= skin.
 #include "qhp_internal.h"
 
 namespace {
 
+constexpr int MAXM = 2560;        // neighbourhood atoms staged per chunk
+constexpr int MAXC = 512;         // atoms of one cell handled by one block
+
 struct NlArgs {
-  int N, cap, ncell, nc0, nc1, nc2;
-  double L0, L1, L2, rl2, skin;
+  int N, cap, ncell, nc0, nc1, nc2, nst;
+  double L0, L1, L2, iL0, iL1, iL2, rl2, skin;
   const double4* cent; double4* cref; double4* coff; double4* cwrap;
-  int* cell_of; int* cell_count; int* cell_start; int* cell_atoms;
+  int* cell_of; int* cell_count; int* cell_fill; int* cell_start; int* cell_atoms;
   const int* stencil; int* nbr; int* nnbr;
   NlCtrl* ctrl;
-  const double2* bmax;
+  const double4* bmax;
   int n_bmax;
 };
 
 __global__ __launch_bounds__(256) void k_nl_check(NlArgs A, int force) {
-  __shared__ double s0[256], s1[256];
+  __shared__ double sm[4][256];
   __shared__ int go;
-  double a0 = 0.0, a1 = 0.0;
-  if (!force)
-    for (int k = threadIdx.x; k < A.n_bmax; k += blockDim.x) {
-      const double2 v = A.bmax[k];
-      a0 = fmax(a0, v.x);
-      a1 = fmax(a1, v.y);
-    }
-  s0[threadIdx.x] = a0;
-  s1[threadIdx.x] = a1;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < A.n_bmax; k += blockDim.x) {
+    const double4 v = A.bmax[k];
+    a[0] = fmax(a[0], v.x); a[1] = fmax(a[1], v.y); a[2] = fmax(a[2], v.z); a[3] = fmax(a[3], v.w);
+  }
+  for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] = a[q];
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + st]);
-      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + st]);
-    }
+    if (threadIdx.x < st)
+      for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] = fmax(sm[q][threadIdx.x], sm[q][threadIdx.x + st]);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     NlCtrl* c = A.ctrl;
-    const double dc = sqrt(s0[0]), db = sqrt(s1[0]);
+    const double dc = sqrt(sm[0][0]), db = sqrt(sm[1][0]);
     const int b = force || c->force_build || !(2.0 * (dc + db) <= A.skin);
     c->do_build = b;
     c->force_build = 0;
+    if (!force) c->step += 1;       // a propagation step's forces: the step is done
+    c->spread_m = (int)sm[2][0];
+    if (sm[3][0] != 0.0) c->spread_margin = 1;
     if (b) { c->n_builds += 1; c->max_count = 0; }
     go = b;
   }
   __syncthreads();
   if (go)
-    for (int k = threadIdx.x; k < A.ncell; k += blockDim.x) A.cell_count[k] = 0;
+    for (int k = threadIdx.x; k < A.ncell; k += blockDim.x) { A.cell_count[k] = 0; A.cell_fill[k] = 0; }
 }
 
 #pragma clang fp contract(off)
-QHP_DEV int cell_coord(double x, double L, int n) {
-  double f = x / L;
+QHP_DEV int cell_coord(double x, double iL, int n) {
+  double f = x * iL;
   f = f - floor(f);
   if (!isfinite(f)) return 0;
-  int i = (int)(f * (double)n);
+  const int i = (int)(f * (double)n);
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
+
+QHP_DEV double wrapped(double x, double L, double iL) { return x - L * floor(x * iL); }
 
 __global__ void k_nl_assign(NlArgs A) {
   if (!A.ctrl->do_build) return;
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= A.N) return;
   const double4 c = A.cent[a];
-  const int id = (cell_coord(c.x, A.L0, A.nc0) * A.nc1 + cell_coord(c.y, A.L1, A.nc1)) * A.nc2 +
-                 cell_coord(c.z, A.L2, A.nc2);
+  const int id = (cell_coord(c.x, A.iL0, A.nc0) * A.nc1 + cell_coord(c.y, A.iL1, A.nc1)) * A.nc2 +
+                 cell_coord(c.z, A.iL2, A.nc2);
   A.cell_of[a] = id;
   A.cref[a] = c;
-  const double4 o = make_double4(A.L0 * floor(c.x / A.L0), A.L1 * floor(c.y / A.L1),
-                                 A.L2 * floor(c.z / A.L2), 0.0);
-  A.coff[a] = o;
-  A.cwrap[a] = make_double4(c.x - o.x, c.y - o.y, c.z - o.z, 0.0);
+  const double4 w = make_double4(wrapped(c.x, A.L0, A.iL0), wrapped(c.y, A.L1, A.iL1),
+                                 wrapped(c.z, A.L2, A.iL2), 0.0);
+  A.cwrap[a] = w;
+  A.coff[a] = make_double4(c.x - w.x, c.y - w.y, c.z - w.z, 0.0);
   atomicAdd(&A.cell_count[id], 1);
 }
 
-__global__ void k_nl_scan(NlArgs A) {
+// exclusive scan of the cell counts (one block)
+__global__ __launch_bounds__(256) void k_nl_scan(NlArgs A) {
   if (!A.ctrl->do_build) return;
-  if (threadIdx.x == 0) {
-    int s = 0;
-    for (int k = 0; k < A.ncell; ++k) { A.cell_start[k] = s; s += A.cell_count[k]; }
-    A.cell_start[A.ncell] = s;
-  }
-}
-
-// one block per cell: gather that cell's atoms in increasing atom order
-__global__ __launch_bounds__(256) void k_nl_fill(NlArgs A) {
-  if (!A.ctrl->do_build) return;
-  __shared__ int wsum[4];
-  __shared__ int base;
-  const int cell = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) base = A.cell_start[cell];
+  __shared__ int part[256];
+  const int t = threadIdx.x;
+  const int per = (A.ncell + 255) / 256;
+  const int b0 = min(A.ncell, t * per), b1 = min(A.ncell, b0 + per);
+  int s = 0;
+  for (int k = b0; k < b1; ++k) s += A.cell_count[k];
+  part[t] = s;
   __syncthreads();
-  for (int a0 = 0; a0 < A.N; a0 += 256) {
-    const int a = a0 + tid;
-    const bool in = a < A.N && A.cell_of[a] == cell;
-    const unsigned long long m = __ballot(in);
-    const int before = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[w] = __popcll(m);
-    __syncthreads();
-    int off = base;
-    for (int k = 0; k < w; ++k) off += wsum[k];
-    if (in) A.cell_atoms[off + before] = a;
-    __syncthreads();
-    if (tid == 0) base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int k = 0; k < 256; ++k) { const int v = part[k]; part[k] = acc; acc += v; }
+    A.cell_start[A.ncell] = acc;
+  }
+  __syncthreads();
+  int acc = part[t];
+  for (int k = b0; k < b1; ++k) { A.cell_start[k] = acc; acc += A.cell_count[k]; }
+}
+
+__global__ void k_nl_scatter(NlArgs A) {
+  if (!A.ctrl->do_build) return;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= A.N) return;
+  const int id = A.cell_of[a];
+  const int slot = atomicAdd(&A.cell_fill[id], 1);
+  A.cell_atoms[A.cell_start[id] + slot] = a;
+}
+
+// order each cell's atoms by index: one wavefront per cell, rank of every element by
+// counting the smaller ones (cells hold a few tens of atoms; larger cells loop)
+__global__ __launch_bounds__(256) void k_nl_sort(NlArgs A) {
+  if (!A.ctrl->do_build) return;
+  __shared__ int buf[4][MAXC];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cell = blockIdx.x * 4 + wv;
+  if (cell >= A.ncell) return;
+  int* v = A.cell_atoms + A.cell_start[cell];
+  const int n = A.cell_start[cell + 1] - A.cell_start[cell];
+  if (n > MAXC) { if (lane == 0) A.ctrl->overflow = 1; return; }
+  for (int k = lane; k < n; k += 64) buf[wv][k] = v[k];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int k = lane; k < n; k += 64) {
+    const int key = buf[wv][k];
+    int rank = 0;
+    for (int q = 0; q < n; ++q) rank += buf[wv][q] < key;
+    v[rank] = key;
   }
 }
 
-__global__ __launch_bounds__(128) void k_nl_build(NlArgs A) {
+__global__ __launch_bounds__(256) void k_nl_build(NlArgs A) {
   if (!A.ctrl->do_build) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.N) return;
-  const double4 ci = A.cent[i];
-  const double4 wi = make_double4(ci.x - A.L0 * floor(ci.x / A.L0), ci.y - A.L1 * floor(ci.y / A.L1),
-                                  ci.z - A.L2 * floor(ci.z / A.L2), 0.0);
-  const int mi = i / 3;
-  const int* st = A.stencil + A.cell_of[i] * 27;
-  int cnt = 0;
-  for (int s = 0; s < 27; ++s) {
-    const int cell = st[s];
-    if (cell < 0) break;
-    const int e = A.cell_start[cell + 1];
-    for (int k = A.cell_start[cell]; k < e; ++k) {
-      const int j = A.cell_atoms[k];
-      if (j / 3 == mi) continue;
-      const double4 cj = A.cent[j];
-      double dx = cj.x - ci.x, dy = cj.y - ci.y, dz = cj.z - ci.z;
-      dx = dx - A.L0 * rint(dx / A.L0);
-      dy = dy - A.L1 * rint(dy / A.L1);
-      dz = dz - A.L2 * rint(dz / A.L2);
-      double d2 = dx * dx + dy * dy;
-      d2 = d2 + dz * dz;
-      if (d2 < A.rl2) {
-        if (cnt < A.cap) {
-          // image shift in the frame wrapped at this build: both wrapped centroids lie in
-          // [0, L), so the shift is -1, 0 or +1 per axis
-          const double wx = cj.x - A.L0 * floor(cj.x / A.L0) - wi.x;
-          const double wy = cj.y - A.L1 * floor(cj.y / A.L1) - wi.y;
-          const double wz = cj.z - A.L2 * floor(cj.z / A.L2) - wi.z;
-          const int sx = -(int)rint(wx / A.L0), sy = -(int)rint(wy / A.L1), sz = -(int)rint(wz / A.L2);
-          const unsigned code = (unsigned)j | ((unsigned)(sx + 1) << 26) |
-                                ((unsigned)(sy + 1) << 28) | ((unsigned)(sz + 1) << 30);
-          A.nbr[(size_t)cnt * A.N + i] = (int)code;
-        }
-        ++cnt;
-      }
-    }
+  __shared__ double sx[MAXM], sy[MAXM], sz[MAXM];
+  __shared__ int sj[MAXM];
+  __shared__ int sofs[126];
+  __shared__ int scnt[MAXC];
+  __shared__ int sbeg[126];
+  const int cell = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int* st = A.stencil + (size_t)cell * A.nst;
+  // sizes and first entries of the neighbouring cells, loaded in parallel, then a prefix sum
+  if (tid < A.nst) {
+    const int c = st[tid];
+    sbeg[tid] = c >= 0 ? A.cell_start[c] : 0;
+    sofs[tid + 1] = c >= 0 ? A.cell_start[c + 1] - A.cell_start[c] : 0;
   }
-  A.nnbr[i] = cnt < A.cap ? cnt : A.cap;
-  if (cnt > A.cap) A.ctrl->overflow = 1;
-  atomicMax(&A.ctrl->max_count, cnt);
+  __syncthreads();
+  if (tid == 0) {
+    sofs[0] = 0;
+    for (int k = 1; k <= A.nst; ++k) sofs[k] += sofs[k - 1];
+  }
+  const int c0 = A.cell_start[cell], nin = A.cell_start[cell + 1] - c0;
+  if (nin > MAXC) {                       // cannot happen at liquid densities
+    if (tid == 0) A.ctrl->overflow = 1;
+    return;
+  }
+  for (int k = tid; k < nin; k += blockDim.x) scnt[k] = 0;
+  __syncthreads();
+  const int M = sofs[A.nst];
+  for (int base = 0; base < M; base += MAXM) {
+    const int len = min(MAXM, M - base);
+    for (int p = tid; p < len; p += blockDim.x) {
+      // neighbouring cell k holding concatenated position base + p (binary search)
+      const int gp = base + p;
+      int lo = 0, hi = A.nst;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sofs[mid] <= gp) lo = mid; else hi = mid;
+      }
+      const int j = A.cell_atoms[sbeg[lo] + (gp - sofs[lo])];
+      const double4 cj = A.cent[j];
+      sx[p] = cj.x; sy[p] = cj.y; sz[p] = cj.z; sj[p] = j;
+    }
+    __syncthreads();
+    for (int ii = wv; ii < nin; ii += 4) {
+      const int i = A.cell_atoms[c0 + ii];
+      const double4 ci = A.cent[i];
+      const double wx = wrapped(ci.x, A.L0, A.iL0), wy = wrapped(ci.y, A.L1, A.iL1),
+                   wz = wrapped(ci.z, A.L2, A.iL2);
+      const int mi = i / 3;
+      int cnt = scnt[ii];
+      for (int p0 = 0; p0 < len; p0 += 64) {
+        const int p = p0 + lane;
+        bool keep = false;
+        unsigned code = 0;
+        if (p < len) {
+          const int j = sj[p];
+          double dx = sx[p] - ci.x, dy = sy[p] - ci.y, dz = sz[p] - ci.z;
+          dx = dx - A.L0 * rint(dx * A.iL0);
+          dy = dy - A.L1 * rint(dy * A.iL1);
+          dz = dz - A.L2 * rint(dz * A.iL2);
+          double d2 = dx * dx + dy * dy;
+          d2 = d2 + dz * dz;
+          keep = (j / 3 != mi) && (d2 < A.rl2);
+          if (keep) {
+            // image shift of the two centroids in the frame wrapped at this build
+            const int sxi = -(int)rint((wrapped(sx[p], A.L0, A.iL0) - wx) * A.iL0);
+            const int syi = -(int)rint((wrapped(sy[p], A.L1, A.iL1) - wy) * A.iL1);
+            const int szi = -(int)rint((wrapped(sz[p], A.L2, A.iL2) - wz) * A.iL2);
+            code = (unsigned)j | ((unsigned)(sxi + 1) << 26) | ((unsigned)(syi + 1) << 28) |
+                   ((unsigned)(szi + 1) << 30);
+          }
+        }
+        const unsigned long long m = __ballot(keep);
+        if (keep) {
+          const int slot = cnt + __popcll(m & ((1ull << lane) - 1ull));
+          if (slot < A.cap) A.nbr[(size_t)i * A.cap + slot] = (int)code;
+        }
+        cnt += __popcll(m);
+      }
+      if (lane == 0) scnt[ii] = cnt;
+    }
+    __syncthreads();
+  }
+  for (int ii = tid; ii < nin; ii += blockDim.x) {
+    const int i = A.cell_atoms[c0 + ii];
+    const int cnt = scnt[ii];
+    A.nnbr[i] = cnt < A.cap ? cnt : A.cap;
+    if (cnt > A.cap) A.ctrl->overflow = 1;
+    atomicMax(&A.ctrl->max_count, cnt);
+  }
 }
 #pragma clang fp contract(fast)
 
@@ -173,17 +244,20 @@ __global__ __launch_bounds__(128) void k_nl_build(NlArgs A) {
 
 hipError_t launch_nlist(qhp_ctx* c, bool from_step) {
   NlArgs A;
-  A.N = c->N; A.cap = c->cap; A.ncell = c->ncell;
+  A.N = c->N; A.cap = c->cap; A.ncell = c->ncell; A.nst = c->nst;
   A.nc0 = c->nc[0]; A.nc1 = c->nc[1]; A.nc2 = c->nc[2];
   A.L0 = c->p.box[0]; A.L1 = c->p.box[1]; A.L2 = c->p.box[2];
+  A.iL0 = 1.0 / A.L0; A.iL1 = 1.0 / A.L1; A.iL2 = 1.0 / A.L2;
   A.rl2 = c->rlist * c->rlist; A.skin = c->p.skin;
-  A.cent = c->cent; A.cref = c->cref; A.coff = c->coff; A.cwrap = c->cwrap; A.cell_of = c->cell_of; A.cell_count = c->cell_count;
+  A.cent = c->cent; A.cref = c->cref; A.coff = c->coff; A.cwrap = c->cwrap;
+  A.cell_of = c->cell_of; A.cell_count = c->cell_count; A.cell_fill = c->cell_fill;
   A.cell_start = c->cell_start; A.cell_atoms = c->cell_atoms; A.stencil = c->stencil;
   A.nbr = c->nbr; A.nnbr = c->nnbr; A.ctrl = c->ctrl; A.bmax = c->bmax; A.n_bmax = c->n_bmax;
   hipLaunchKernelGGL(k_nl_check, 1, 256, 0, c->stream, A, from_step ? 0 : 1);
   hipLaunchKernelGGL(k_nl_assign, (c->N + 255) / 256, 256, 0, c->stream, A);
-  hipLaunchKernelGGL(k_nl_scan, 1, 64, 0, c->stream, A);
-  hipLaunchKernelGGL(k_nl_fill, c->ncell, 256, 0, c->stream, A);
-  hipLaunchKernelGGL(k_nl_build, (c->N + 127) / 128, 128, 0, c->stream, A);
+  hipLaunchKernelGGL(k_nl_scan, 1, 256, 0, c->stream, A);
+  hipLaunchKernelGGL(k_nl_scatter, (c->N + 255) / 256, 256, 0, c->stream, A);
+  hipLaunchKernelGGL(k_nl_sort, (c->ncell + 3) / 4, 256, 0, c->stream, A);
+  hipLaunchKernelGGL(k_nl_build, c->ncell, 256, 0, c->stream, A);
   return hipGetLastError();
 }

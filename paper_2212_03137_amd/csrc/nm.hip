@@ -25,11 +25,13 @@ struct NmArgs {
   const double* mass; const double* sqrt_mkT; const double* charge;
   double4* cent; const double4* cref; const double4* coff; double4* cwrap; float4* xf;
   NlCtrl* ctrl;
-  double2* bmax;
+  double4* bmax;
+  double KoL[3];
+  int K[3], order;
   double dt, h;
-  uint64_t seed; uint64_t step;
+  uint64_t seed;
   // adQTB
-  const double* noise; double* vrec; int tseg; double qc1, qosd;
+  const double* noise; double* vrec; int nseg; double qc1, qosd;
 };
 
 template <int P, bool BEADMAJOR>
@@ -52,6 +54,7 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
   const int a = blockIdx.x * AT + al;
   for (int k = tid; k < P * P; k += NT) sT[k] = A.T[k];
   const bool live = a < A.N;
+  const uint64_t step = (uint64_t)A.ctrl->step;       // advanced by the list check
   double gv[3] = {0, 0, 0};
   if (live)
     for (int d = 0; d < 3; ++d) gv[d] = A.g[gidx<P, BEADMAJOR>(A.N, d, a, n)];
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
     m = A.mass[a];
     const double im = 1.0 / m;
     double xi[3] = {0, 0, 0};
-    if (!QTB) qhp::gauss3(A.seed, qhp::STREAM_RPMD_O, A.step, (uint64_t)a, (uint64_t)n, xi);
+    if (!QTB) qhp::gauss3(A.seed, qhp::STREAM_RPMD_O, step, (uint64_t)a, (uint64_t)n, xi);
     for (int d = 0; d < 3; ++d) {
       double f = 0;
 #pragma unroll 8
@@ -80,7 +83,7 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
       double p1 = -m * cws * qq + cc * pp;
       // O(dt)
       if (QTB) {
-        const int ni = (A.tseg * 3 + d) * A.N + a;
+        const int ni = ((int)(step % (uint64_t)A.nseg) * 3 + d) * A.N + a;
         const double pb = p1;
         p1 = A.qc1 * p1 + A.qosd * A.noise[ni];
         A.vrec[ni] = 0.5 * (pb + p1) * im;
@@ -102,6 +105,7 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
 
   // beads from modes: lane index n now stands for bead i = n
   double db2 = 0, dc2 = 0;
+  int moff = 0, mbad = 0;
   if (live) {
     const double sP = sqrt((double)P);
     double xb[3], c[3];
@@ -116,6 +120,12 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
     }
     const double dx = xb[0] - c[0], dy = xb[1] - c[1], dz = xb[2] - c[2];
     db2 = dx * dx + dy * dy + dz * dz;
+    for (int d = 0; d < 3; ++d) {
+      const int dl = qhp::base_diff(qhp::base_of(xb[d], A.KoL[d], A.K[d]),
+                                    qhp::base_of(c[d], A.KoL[d], A.K[d]), A.K[d]);
+      moff = max(moff, dl < 0 ? -dl : dl);
+      if (dl > QHP_TB || dl < A.order - 1 - QHP_TB) mbad = 1;
+    }
     if (F32) A.xf[a * P + n] = make_float4((float)dx, (float)dy, (float)dz, (float)A.charge[a]);
     if (n == 0) {
       A.cent[a] = make_double4(c[0], c[1], c[2], 0.0);
@@ -126,16 +136,19 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
       dc2 = ex * ex + ey * ey + ez * ez;
     }
   }
-  // block maxima for the neighbour-list check (no same-address atomics)
-  __shared__ double sm[2][NT / 64];
+  // block maxima for the neighbour-list check and the SPME tile margin (no atomics)
+  __shared__ double sm[4][NT / 64];
   db2 = wave_max(db2);
   dc2 = wave_max(dc2);
-  if ((tid & 63) == 0) { sm[0][tid >> 6] = dc2; sm[1][tid >> 6] = db2; }
+  const double mo = wave_max((double)moff), mb = wave_max((double)mbad);
+  if ((tid & 63) == 0) { sm[0][tid >> 6] = dc2; sm[1][tid >> 6] = db2; sm[2][tid >> 6] = mo; sm[3][tid >> 6] = mb; }
   __syncthreads();
   if (tid == 0) {
-    double a0 = sm[0][0], a1 = sm[1][0];
-    for (int w = 1; w < NT / 64; ++w) { a0 = fmax(a0, sm[0][w]); a1 = fmax(a1, sm[1][w]); }
-    A.bmax[blockIdx.x] = make_double2(a0, a1);
+    double a0 = sm[0][0], a1 = sm[1][0], a2 = sm[2][0], a3 = sm[3][0];
+    for (int w = 1; w < NT / 64; ++w) {
+      a0 = fmax(a0, sm[0][w]); a1 = fmax(a1, sm[1][w]); a2 = fmax(a2, sm[2][w]); a3 = fmax(a3, sm[3][w]);
+    }
+    A.bmax[blockIdx.x] = make_double4(a0, a1, a2, a3);
   }
   if (bad) A.ctrl->nonfinite = 1;
 }
@@ -260,25 +273,52 @@ __global__ __launch_bounds__(NT) void k_mode_energy(int N, const double* Q, cons
   if ((tid & 63) == 0) { atomicAdd(out, ek); atomicAdd(out + 1, es); }
 }
 
-// centroid of given beads (bead-innermost or bead-major x): beads summed in order, / P
+// centroid of given beads (bead-innermost or bead-major x): beads summed in order, / P;
+// also the block maxima of the bead-centroid distance and grid-base offset
+struct CentArgs {
+  int N;
+  const double* x; double4* cent; float4* xf; const double* charge;
+  double4* bmax;
+  double KoL[3];
+  int K[3], order;
+};
+
 template <int P, bool BEADMAJOR>
-__global__ void k_centroid_beads(int N, const double* x, double4* cent, float4* xf,
-                                 const double* charge) {
+__global__ __launch_bounds__(128) void k_centroid_beads(CentArgs A) {
+  __shared__ double sm[3][2];
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= N) return;
-  double c[3];
-  for (int d = 0; d < 3; ++d) {
-    double s = x[gidx<P, BEADMAJOR>(N, d, a, 0)];
-    for (int b = 1; b < P; ++b) s = s + x[gidx<P, BEADMAJOR>(N, d, a, b)];
-    c[d] = s / (double)P;
+  double db2 = 0;
+  int moff = 0, mbad = 0;
+  if (a < A.N) {
+    double c[3];
+    for (int d = 0; d < 3; ++d) {
+      double s = A.x[gidx<P, BEADMAJOR>(A.N, d, a, 0)];
+      for (int b = 1; b < P; ++b) s = s + A.x[gidx<P, BEADMAJOR>(A.N, d, a, b)];
+      c[d] = s / (double)P;
+    }
+    A.cent[a] = make_double4(c[0], c[1], c[2], 0.0);
+    for (int b = 0; b < P; ++b) {
+      double xb[3];
+      for (int d = 0; d < 3; ++d) xb[d] = A.x[gidx<P, BEADMAJOR>(A.N, d, a, b)];
+      const double dx = xb[0] - c[0], dy = xb[1] - c[1], dz = xb[2] - c[2];
+      db2 = fmax(db2, dx * dx + dy * dy + dz * dz);
+      if (A.xf) A.xf[a * P + b] = make_float4((float)dx, (float)dy, (float)dz, (float)A.charge[a]);
+      if (!BEADMAJOR)
+        for (int d = 0; d < 3; ++d) {
+          const int dl = qhp::base_diff(qhp::base_of(xb[d], A.KoL[d], A.K[d]),
+                                        qhp::base_of(c[d], A.KoL[d], A.K[d]), A.K[d]);
+          moff = max(moff, dl < 0 ? -dl : dl);
+          if (dl > QHP_TB || dl < A.order - 1 - QHP_TB) mbad = 1;
+        }
+    }
   }
-  cent[a] = make_double4(c[0], c[1], c[2], 0.0);
-  if (xf)
-    for (int b = 0; b < P; ++b)
-      xf[a * P + b] = make_float4((float)(x[gidx<P, BEADMAJOR>(N, 0, a, b)] - c[0]),
-                                  (float)(x[gidx<P, BEADMAJOR>(N, 1, a, b)] - c[1]),
-                                  (float)(x[gidx<P, BEADMAJOR>(N, 2, a, b)] - c[2]),
-                                  (float)charge[a]);
+  db2 = wave_max(db2);
+  const double mo = wave_max((double)moff), mb = wave_max((double)mbad);
+  if ((threadIdx.x & 63) == 0) { sm[0][threadIdx.x >> 6] = db2; sm[1][threadIdx.x >> 6] = mo; sm[2][threadIdx.x >> 6] = mb; }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    A.bmax[blockIdx.x] = make_double4(0.0, fmax(sm[0][0], sm[0][1]), fmax(sm[1][0], sm[1][1]),
+                                      fmax(sm[2][0], sm[2][1]));
 }
 
 // boundary [P][N][3] <-> internal layout
@@ -322,10 +362,12 @@ hipError_t launch_nm_step(qhp_ctx* c) {
   A.cc = c->mode_c; A.csw = c->mode_s_w; A.cws = c->mode_ws; A.c1 = c->mode_c1; A.c2 = c->mode_c2;
   A.mass = c->d_mass; A.sqrt_mkT = c->d_sqrt_mkT; A.charge = c->d_charge;
   A.cent = c->cent; A.cref = c->cref; A.coff = c->coff; A.cwrap = c->cwrap; A.xf = c->xf; A.ctrl = c->ctrl; A.bmax = c->bmax;
-  A.dt = c->p.dt; A.h = 0.5 * c->p.dt; A.seed = c->p.seed; A.step = (uint64_t)c->step;
+  for (int d = 0; d < 3; ++d) { A.K[d] = c->K[d]; A.KoL[d] = c->K[d] / c->p.box[d]; }
+  A.order = c->p.pme_order;
+  A.dt = c->p.dt; A.h = 0.5 * c->p.dt; A.seed = c->p.seed;
   const bool qtb = c->p.thermostat == QHP_ADQTB;
   A.noise = c->qtb.noise; A.vrec = c->qtb.vrec;
-  A.tseg = qtb ? (int)(c->step % c->qtb.nseg) : 0;
+  A.nseg = qtb ? c->qtb.nseg : 1;
   A.qc1 = c->qtb.c1; A.qosd = c->qtb.osd;
   const bool bm = c->p.exec == QHP_PLAIN;
   const bool f32 = c->p.precision == QHP_FP32_PAIRS && !bm;
@@ -388,12 +430,15 @@ hipError_t launch_mode_energies(qhp_ctx* c, double* out2) {
 
 hipError_t launch_centroid_of_beads(qhp_ctx* c) {
   const bool bm = c->p.exec == QHP_PLAIN;
-  float4* xf = (c->p.precision == QHP_FP32_PAIRS && !bm) ? c->xf : nullptr;
+  CentArgs A;
+  A.N = c->N; A.x = c->x; A.cent = c->cent; A.charge = c->d_charge; A.bmax = c->bmax;
+  A.xf = (c->p.precision == QHP_FP32_PAIRS && !bm) ? c->xf : nullptr;
+  for (int d = 0; d < 3; ++d) { A.K[d] = c->K[d]; A.KoL[d] = c->K[d] / c->p.box[d]; }
+  A.order = c->p.pme_order;
   const unsigned nb = (c->N + 127) / 128;
-  QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_centroid_beads<PP, true>), nb, 128, 0,
-                                                 c->stream, c->N, c->x, c->cent, xf, c->d_charge);
-               else hipLaunchKernelGGL((k_centroid_beads<PP, false>), nb, 128, 0, c->stream, c->N,
-                                       c->x, c->cent, xf, c->d_charge));
+  c->n_bmax = (int)nb;
+  QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_centroid_beads<PP, true>), nb, 128, 0, c->stream, A);
+               else hipLaunchKernelGGL((k_centroid_beads<PP, false>), nb, 128, 0, c->stream, A));
   return hipGetLastError();
 }
 

@@ -2,22 +2,36 @@
 // and Lennard-Jones 4 eps ((s/r)^12 - (s/r)^6) over centroid-list pairs whose *bead*
 // distance is below the cutoff (plain truncation), for every bead at once.
 //
-// Lane layout: a 64-lane wavefront covers 64/P atoms i and all P beads; lane (i, b) walks
-// the full neighbour list of atom i (each j index is shared by the P lanes of i) and owns
-// grad_i at bead b, so no atomics are needed. Each pair is evaluated from both ends.
+// Lane layout: one wavefront per atom i. Its 64 lanes are S = 64/P neighbour slots times
+// the P beads; lane (s, b) takes neighbours s, s+S, ... of atom i at bead b and owns
+// grad_i at bead b, so no atomics are needed (each pair is evaluated from both ends).
+// The neighbour row is consumed 64 entries at a time: lane l decodes entry l once (index,
+// type, charge, FP64 centroid difference with the stored image shift) into LDS, and the
+// bead lanes then read it from there, so the per-pair FP64 work is not repeated per bead.
 //
-// FP32-pair mode: the displacement is formed in FP64 as (wrapped centroid difference +
-// stored image shift), rounded once to FP32, and the per-bead offsets from the centroids
-// (kept in FP32) are added; distances, erfc/exp and the force scalar are FP32; forces are
-// summed in FP32 over chunks of 32 neighbours and then in FP64; energies in FP64.
-// The stored shift is the bead's minimum image for every pair within the cutoff whenever
-// 2 (rc + skin) < L (see the rebuild rule in the neighbour list); otherwise the FP64 path
-// is used. The FP64 path takes each bead's own minimum image.
+// FP32-pair mode: the displacement is the FP64 wrapped-centroid difference plus image
+// shift, rounded once to FP32, plus the FP32 bead offsets from the centroids; distance,
+// erfc, exp and the force scalar are FP32; each lane sums forces in FP32 over one chunk
+// of neighbours, then in FP64; energies in FP64. erfc(x) = exp(-x^2) t Q(t) with
+// t = 1/(1 + p x) (Hastings' form; p and Q fitted by gen_erfc_fit.py, relative error
+// 3e-8), sharing exp(-x^2) with the force term. The stored shift is the bead's minimum
+// image for every pair within the cutoff whenever 2 (rc + skin) < L (neighbour-list
+// rebuild rule); otherwise the FP64 path is used, which takes each bead's own minimum
+// image.
+//
+// Blocks are remapped so that each of the 8 XCDs works on a contiguous range of atoms
+// (a slab of the box in lattice order), keeping its neighbours' data in its own L2.
 #include "qhp_internal.h"
 
 namespace {
 
 constexpr int NT = 256;
+constexpr int WPB = NT / 64;      // atoms (wavefronts) per block
+
+// p = 0.418649012, max relative error of exp(x^2) erfc(x) on [0, 6]: 2.94e-08
+constexpr float ERFC_P = 0.418649012f;
+constexpr float ERFC_Q[8] = {0.235933458f, 0.240632992f, 0.183633505f, 0.301421722f,
+                             -0.189258145f, 0.502240173f, -0.351184483f, 0.0765808055f};
 
 struct PairArgs {
   int N, cap;
@@ -32,132 +46,169 @@ struct PairArgs {
   double lj_s6[QHP_MAX_TYPES * QHP_MAX_TYPES];
   double lj_e4[QHP_MAX_TYPES * QHP_MAX_TYPES];
   int ntypes;
+  int nblocks;            // logical blocks
   double* energy;         // [P][NTERMS] (plain: the bead's row)
 };
 
+QHP_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// physical block -> logical block so that XCD k (blocks k, k+8, ...) gets a contiguous range
+QHP_DEV int xcd_block(int bid, int nphys) { return (bid & 7) * (nphys >> 3) + (bid >> 3); }
+
+// sum over the S slots of a wavefront; lanes 0..P-1 end up with their bead's total
 template <int P>
-QHP_DEV void reduce_energy_by_bead(double* sred, int tid, double v, double* dst) {
-  constexpr int AT = NT / P;
-  sred[tid] = v;
-  __syncthreads();
-  for (int s = AT / 2; s > 0; s >>= 1) {
-    if (tid / P < s) sred[tid] += sred[tid + s * P];
-    __syncthreads();
+QHP_DEV double slot_sum(double v) {
+#pragma unroll
+  for (int o = P; o < 64; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int P, bool ENERGY>
+QHP_DEV void flush(const PairArgs& A, int i, int lane, double gx, double gy, double gz,
+                   double ec, double elj) {
+  gx = slot_sum<P>(gx); gy = slot_sum<P>(gy); gz = slot_sum<P>(gz);
+  if (ENERGY) { ec = slot_sum<P>(ec); elj = slot_sum<P>(elj); }
+  if (lane < P) {
+    const int N = A.N;
+    A.g[(0 * (size_t)N + i) * P + lane] += gx;
+    A.g[(1 * (size_t)N + i) * P + lane] += gy;
+    A.g[(2 * (size_t)N + i) * P + lane] += gz;
+    if (ENERGY) {
+      atomicAdd(A.energy + lane * QHP_NTERMS + QHP_E_COUL_REAL, 0.5 * ec);
+      atomicAdd(A.energy + lane * QHP_NTERMS + QHP_E_LJ, 0.5 * elj);
+    }
   }
-  if (tid < P) atomicAdd(dst + tid * QHP_NTERMS, sred[tid]);
-  __syncthreads();
 }
 
 template <int P, bool ENERGY>
 __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
-  constexpr int AT = NT / P;
-  __shared__ double sred[NT];
-  const int tid = threadIdx.x, b = tid % P;
-  const int i = blockIdx.x * AT + tid / P;
-  const bool live = i < A.N;
+  constexpr int S = 64 / P;
+  __shared__ int sj[WPB][64];
+  __shared__ double sq[WPB][64];
+  __shared__ double2 slj[WPB][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, s = lane / P, b = lane % P;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int i = lb * WPB + wv;
+  if (lb >= A.nblocks || i >= A.N) return;       // whole wavefront leaves together
+  const int N = A.N;
+  const double xi = A.x[(0 * (size_t)N + i) * P + b], yi = A.x[(1 * (size_t)N + i) * P + b],
+               zi = A.x[(2 * (size_t)N + i) * P + b];
+  const double qi = A.coulomb * A.charge[i];
+  const int ti = A.type[i];
+  const double c2a = 2.0 * A.alpha / sqrt(M_PI);
+  const int nn = A.nnbr[i];
+  const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
-  if (live) {
-    const int N = A.N;
-    const double xi = A.x[(0 * N + i) * P + b], yi = A.x[(1 * N + i) * P + b],
-                 zi = A.x[(2 * N + i) * P + b];
-    const double qi = A.coulomb * A.charge[i];
-    const int ti = A.type[i];
-    const double c2a = 2.0 * A.alpha / sqrt(M_PI);
-    const int nn = A.nnbr[i];
-    for (int k = 0; k < nn; ++k) {
-      const unsigned e = (unsigned)A.nbr[(size_t)k * N + i];
-      const int j = e & 0x3FFFFFF;
-      double dx = A.x[(0 * N + j) * P + b] - xi;
-      double dy = A.x[(1 * N + j) * P + b] - yi;
-      double dz = A.x[(2 * N + j) * P + b] - zi;
+  for (int k0 = 0; k0 < nn; k0 += 64) {
+    const int cnt = min(64, nn - k0);
+    if (lane < cnt) {
+      const int j = row[k0 + lane] & 0x3FFFFFF;
+      sj[wv][lane] = j;
+      sq[wv][lane] = qi * A.charge[j];
+      const int tp = ti * A.ntypes + A.type[j];
+      slj[wv][lane] = make_double2(A.lj_e4[tp], A.lj_s6[tp]);
+    }
+    wave_sync();
+    for (int t = s; t < cnt; t += S) {
+      const int j = sj[wv][t];
+      double dx = A.x[(0 * (size_t)N + j) * P + b] - xi;
+      double dy = A.x[(1 * (size_t)N + j) * P + b] - yi;
+      double dz = A.x[(2 * (size_t)N + j) * P + b] - zi;
       dx -= A.L[0] * rint(dx * A.invL[0]);
       dy -= A.L[1] * rint(dy * A.invL[1]);
       dz -= A.L[2] * rint(dz * A.invL[2]);
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (r2 < A.rc2) {
         const double r = sqrt(r2), ir = 1.0 / r, ir2 = ir * ir;
-        const double qq = qi * A.charge[j];
+        const double qq = sq[wv][t];
         const double erfcv = erfc(A.alpha * r);
-        double s = qq * (erfcv * ir + c2a * exp(-A.alpha * A.alpha * r2)) * ir2;
+        double sc = qq * (erfcv * ir + c2a * exp(-A.alpha * A.alpha * r2)) * ir2;
         if (ENERGY) ec += qq * erfcv * ir;
-        const int tp = ti * A.ntypes + A.type[j];
-        const double e4 = A.lj_e4[tp];
+        const double2 lj = slj[wv][t];
+        const double e4 = lj.x;
         if (e4 != 0.0) {
-          const double s6 = A.lj_s6[tp] * ir2 * ir2 * ir2;
-          s += e4 * (12.0 * s6 * s6 - 6.0 * s6) * ir2;
+          const double s6 = lj.y * ir2 * ir2 * ir2;
+          sc += e4 * (12.0 * s6 * s6 - 6.0 * s6) * ir2;
           if (ENERGY) elj += e4 * (s6 * s6 - s6);
         }
-        gx += s * dx; gy += s * dy; gz += s * dz;
+        gx += sc * dx; gy += sc * dy; gz += sc * dz;
       }
     }
-    A.g[(0 * N + i) * P + b] += gx;
-    A.g[(1 * N + i) * P + b] += gy;
-    A.g[(2 * N + i) * P + b] += gz;
+    wave_sync();
   }
-  if (ENERGY) {
-    reduce_energy_by_bead<P>(sred, tid, 0.5 * ec, A.energy + QHP_E_COUL_REAL);
-    reduce_energy_by_bead<P>(sred, tid, 0.5 * elj, A.energy + QHP_E_LJ);
-  }
+  flush<P, ENERGY>(A, i, lane, gx, gy, gz, ec, elj);
 }
 
 template <int P, bool ENERGY>
 __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
-  constexpr int AT = NT / P;
-  __shared__ double sred[NT];
-  const int tid = threadIdx.x, b = tid % P;
-  const int i = blockIdx.x * AT + tid / P;
-  const bool live = i < A.N;
+  constexpr int S = 64 / P;
+  __shared__ float4 scd[WPB][64];   // centroid difference (x, y, z) and q_i q_j C
+  __shared__ float2 slj[WPB][64];   // 4 eps_ij and sigma_ij^6 of the pair
+  __shared__ int sj[WPB][64];       // j
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, s = lane / P, b = lane % P;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int i = lb * WPB + wv;
+  if (lb >= A.nblocks || i >= A.N) return;       // whole wavefront leaves together
+  const float4 oi = A.xf[(size_t)i * P + b];
+  const double4 ci = A.cwrap[i];
+  const double qi = A.coulomb * A.charge[i];
+  const int ti = A.type[i];
+  const float alpha = (float)A.alpha;
+  const float kexp = (float)(-A.alpha * A.alpha * 1.4426950408889634);  // -alpha^2 log2(e)
+  const float c2a = (float)(2.0 * A.alpha / sqrt(M_PI));
+  const float rc2 = (float)A.rc2;
+  const int nn = A.nnbr[i];
+  const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
-  if (live) {
-    const int N = A.N;
-    const float4 oi = A.xf[(size_t)i * P + b];
-    const double4 ci = A.cwrap[i];
-    const float qi = (float)(A.coulomb * A.charge[i]);
-    const int ti = A.type[i];
-    const float alpha = (float)A.alpha, a2 = (float)(A.alpha * A.alpha);
-    const float c2a = (float)(2.0 * A.alpha / sqrt(M_PI));
-    const float rc2 = (float)A.rc2;
-    const int nn = A.nnbr[i];
-    for (int k0 = 0; k0 < nn; k0 += 32) {
-      float fx = 0.f, fy = 0.f, fz = 0.f;
-      const int k1 = min(nn, k0 + 32);
-      for (int k = k0; k < k1; ++k) {
-        const unsigned e = (unsigned)A.nbr[(size_t)k * N + i];
-        const int j = e & 0x3FFFFFF;
-        const double4 cj = A.cwrap[j];
-        const float cx = (float)((cj.x - ci.x) + A.L[0] * (double)((int)((e >> 26) & 3) - 1));
-        const float cy = (float)((cj.y - ci.y) + A.L[1] * (double)((int)((e >> 28) & 3) - 1));
-        const float cz = (float)((cj.z - ci.z) + A.L[2] * (double)((int)((e >> 30) & 3) - 1));
-        const float4 oj = A.xf[(size_t)j * P + b];
-        const float dx = cx + (oj.x - oi.x), dy = cy + (oj.y - oi.y), dz = cz + (oj.z - oi.z);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < rc2) {
-          const float ir = rsqrtf(r2), ir2 = ir * ir;
-          const float r = r2 * ir;
-          const float qq = qi * oj.w;
-          const float erfcv = erfcf(alpha * r);
-          float s = qq * (erfcv * ir + c2a * expf(-a2 * r2)) * ir2;
-          if (ENERGY) ec += (double)(qq * erfcv * ir);
-          const int tp = ti * A.ntypes + A.type[j];
-          const float e4 = (float)A.lj_e4[tp];
-          if (e4 != 0.f) {
-            const float s6 = (float)A.lj_s6[tp] * ir2 * ir2 * ir2;
-            s += e4 * (12.f * s6 * s6 - 6.f * s6) * ir2;
-            if (ENERGY) elj += (double)(e4 * (s6 * s6 - s6));
-          }
-          fx += s * dx; fy += s * dy; fz += s * dz;
-        }
-      }
-      gx += (double)fx; gy += (double)fy; gz += (double)fz;
+  for (int k0 = 0; k0 < nn; k0 += 64) {
+    const int cnt = min(64, nn - k0);
+    if (lane < cnt) {
+      const unsigned e = (unsigned)row[k0 + lane];
+      const int j = e & 0x3FFFFFF;
+      const double4 cj = A.cwrap[j];
+      const float cx = (float)((cj.x - ci.x) + A.L[0] * (double)((int)((e >> 26) & 3) - 1));
+      const float cy = (float)((cj.y - ci.y) + A.L[1] * (double)((int)((e >> 28) & 3) - 1));
+      const float cz = (float)((cj.z - ci.z) + A.L[2] * (double)((int)((e >> 30) & 3) - 1));
+      scd[wv][lane] = make_float4(cx, cy, cz, (float)(qi * A.charge[j]));
+      const int tp = ti * A.ntypes + A.type[j];
+      slj[wv][lane] = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
+      sj[wv][lane] = j;
     }
-    A.g[(0 * N + i) * P + b] += gx;
-    A.g[(1 * N + i) * P + b] += gy;
-    A.g[(2 * N + i) * P + b] += gz;
+    wave_sync();
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    for (int t = s; t < cnt; t += S) {
+      const float4 cd = scd[wv][t];
+      const float4 oj = A.xf[(size_t)sj[wv][t] * P + b];
+      const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < rc2) {
+        const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir;
+        const float x = alpha * (r2 * ir);
+        const float tt = __builtin_amdgcn_rcpf(1.0f + ERFC_P * x);
+        float q = ERFC_Q[7];
+#pragma unroll
+        for (int k = 6; k >= 0; --k) q = q * tt + ERFC_Q[k];
+        const float ex = __builtin_amdgcn_exp2f(kexp * r2);       // exp(-alpha^2 r^2)
+        const float erfcv = tt * q * ex;
+        float sc = cd.w * ir2 * (erfcv * ir + c2a * ex);
+        if (ENERGY) ec += (double)(cd.w * erfcv * ir);
+        const float2 lj = slj[wv][t];
+        if (lj.x != 0.f) {
+          const float s6 = lj.y * ir2 * ir2 * ir2;
+          sc += lj.x * (12.f * s6 * s6 - 6.f * s6) * ir2;
+          if (ENERGY) elj += (double)(lj.x * (s6 * s6 - s6));
+        }
+        fx += sc * dx; fy += sc * dy; fz += sc * dz;
+      }
+    }
+    gx += (double)fx; gy += (double)fy; gz += (double)fz;
+    wave_sync();
   }
-  if (ENERGY) {
-    reduce_energy_by_bead<P>(sred, tid, 0.5 * ec, A.energy + QHP_E_COUL_REAL);
-    reduce_energy_by_bead<P>(sred, tid, 0.5 * elj, A.energy + QHP_E_LJ);
-  }
+  flush<P, ENERGY>(A, i, lane, gx, gy, gz, ec, elj);
 }
 
 }  // namespace
@@ -195,7 +246,8 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead) {
     }
   A.energy = c->energy + (plain ? (size_t)bead * QHP_NTERMS : 0);
   const int P = plain ? 1 : c->P;
-  const unsigned nb = (unsigned)((N + NT / P - 1) / (NT / P));
+  A.nblocks = (N + WPB - 1) / WPB;
+  const unsigned nb = (unsigned)((A.nblocks + 7) / 8 * 8);
   const double Lmin = fmin(c->p.box[0], fmin(c->p.box[1], c->p.box[2]));
   const bool minimg = !(2.0 * (c->p.cutoff + c->p.skin) < Lmin);
   const bool f32 = c->p.precision == QHP_FP32_PAIRS && !plain && !minimg;

@@ -17,18 +17,21 @@
 //   Q, Pa, x, g        [3][N][P]   mode amplitudes, momenta, bead positions, grad V
 //   cent, cref         [N] double4 centroid now / at the last neighbour-list build
 //   cwrap              [N] double4 centroid in the frame wrapped at the last build
-//   nbr                [cap][N]    int32 neighbour j of atom i at nbr[k*N + i] (full list)
+//   nbr                [N][cap]    int32 neighbour k of atom i at nbr[i*cap + k] (full list)
 //   grid               [K0][K1][K2][Pc] double2, bead b in component b%2 of complex b/2
 // In plain mode x and g are bead-major [P][3][N] and each bead is evaluated alone.
 // ---------------------------------------------------------------------------------------
 
-struct NlCtrl {               // device-side control block of the neighbour list
+struct NlCtrl {               // device-side control block (neighbour list, step counter)
+  long long step;             // MD step of the next normal-mode kernel
   int do_build;               // this step rebuilds
   int force_build;            // host request
   int overflow;               // a neighbour count exceeded the capacity
   int nonfinite;              // a non-finite coordinate or momentum was seen
   int max_count;              // largest neighbour count of the last build
   int n_builds;               // builds so far
+  int spread_margin;          // a bead left the SPME tile margin of its centroid
+  int spread_m;               // largest bead-centroid grid-base offset this step
 };
 
 struct QtbState {
@@ -53,6 +56,9 @@ struct qhp_ctx {
   qhp_params p;
   int N, P, NW, Pc;           // atoms, beads, waters, complex grid batch
   hipStream_t stream;
+  bool own_stream = false;    // created here because the caller passed none
+  hipGraphExec_t step_exec = nullptr;   // one captured MD step (no energies)
+  bool use_graph = true;
   std::string err;
   bool have_state = false;
   int64_t step = 0;
@@ -89,22 +95,30 @@ struct qhp_ctx {
 
   // neighbour list
   NlCtrl* ctrl = nullptr;
-  double2* bmax = nullptr;    // per normal-mode block: (max |dc|^2, max |db|^2) this step
+  double4* bmax = nullptr;    // per block: (max |dc|^2, max |db|^2, max base offset, bad)
   int n_bmax = 0;             // entries written by the last normal-mode launch
   int* cell_of = nullptr;     // [N]
   int* cell_count = nullptr;  // [ncell]
+  int* cell_fill = nullptr;   // [ncell]
   int* cell_start = nullptr;  // [ncell + 1]
   int* cell_atoms = nullptr;  // [N]
-  int* stencil = nullptr;     // [ncell][27] distinct neighbour cells, -1 padded
-  int* nbr = nullptr;         // [cap][N]
+  int* stencil = nullptr;     // [ncell][nst] distinct neighbour cells, -1 padded
+  int* nbr = nullptr;         // [N][cap]
   int* nnbr = nullptr;        // [N]
-  int cap = 0, nc[3] = {1, 1, 1}, ncell = 1;
+  int cap = 0, nc[3] = {1, 1, 1}, ncell = 1, nst = 125;
   double rlist = 0;
 
   // SPME
   int K[3];
   double2* grid = nullptr;    // [K0][K1][K2][Pc] (plain: [K0][K1][K2])
   double* influence = nullptr;// [K0][K1][K2]
+  int ntiles = 0;             // 8^3-point spreading tiles
+  int* tile_of = nullptr;     // [N]
+  int* tile_count = nullptr;  // [ntiles]
+  int* tile_fill = nullptr;   // [ntiles]
+  int* tile_start = nullptr;  // [ntiles + 1]
+  int* tile_atoms = nullptr;  // [N]
+  int* tile_nbr = nullptr;    // [ntiles][27] distinct neighbouring tiles, -1 padded
   double2* tw[3] = {nullptr, nullptr, nullptr};
 
   // energies
@@ -125,6 +139,10 @@ struct qhp_ctx {
   size_t ev_used = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
 };
+
+// SPME spreading tiles: TB^3 grid points; a bead's grid base may differ from its centroid's
+// by at most TB points above and TB - order + 1 below (checked every step).
+constexpr int QHP_TB = 8;
 
 // ---------------------------------------------------------------------------------------
 // error plumbing
@@ -273,5 +291,22 @@ constexpr uint64_t STREAM_RPMD_O = 5;
 constexpr uint64_t STREAM_QTB_WHITE = 6;
 
 QHP_DEV unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+// wrapped grid coordinate u = K * frac(x / L) in [0, K] and its integer base
+QHP_DEV double grid_coord(double x, double KoL, int K) {
+  const double u = x * KoL;
+  return u - (double)K * floor(u * (1.0 / (double)K));
+}
+QHP_DEV int base_of(double x, double KoL, int K) {
+  const double fl = floor(grid_coord(x, KoL, K));
+  return isfinite(fl) ? min(max((int)fl, 0), K) : 0;
+}
+// signed difference of two grid bases, wrapped into [-K/2, K/2]
+QHP_DEV int base_diff(int a, int b, int K) {
+  int d = a - b;
+  if (d > K / 2) d -= K;
+  if (d < -K / 2) d += K;
+  return d;
+}
 
 }  // namespace qhp

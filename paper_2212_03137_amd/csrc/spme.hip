@@ -71,34 +71,6 @@ QHP_DEV void stencil(const double* xb, const double* L, const int* K, int* i0, d
 
 QHP_DEV int wrapk(int k, int K) { return k < 0 ? k + K : (k >= K ? k - K : k); }
 
-template <int P, int ORDER>
-__global__ __launch_bounds__(NT) void k_spread(SpmeArgs A) {
-  const int tid = blockIdx.x * NT + threadIdx.x;
-  const int a = tid / P, b = tid % P;
-  if (a >= A.N) return;
-  double xb[3];
-  for (int d = 0; d < 3; ++d) xb[d] = A.x[(d * A.N + a) * P + b];
-  const int K[3] = {A.K0, A.K1, A.K2};
-  int i0[3];
-  double w[3][ORDER], dw[3][ORDER];
-  stencil<ORDER>(xb, A.L, K, i0, w, dw);
-  const double q = A.charge[a];
-  for (int t0 = 0; t0 < ORDER; ++t0) {
-    const int k0 = wrapk(i0[0] - t0, A.K0);
-    const double w0 = q * w[0][t0];
-    for (int t1 = 0; t1 < ORDER; ++t1) {
-      const int k1 = wrapk(i0[1] - t1, A.K1);
-      const double w01 = w0 * w[1][t1];
-      double* row = A.grid + ((size_t)(k0 * A.K1 + k1) * A.K2) * A.Pc2 + b;
-#pragma unroll
-      for (int t2 = 0; t2 < ORDER; ++t2) {
-        const int k2 = wrapk(i0[2] - t2, A.K2);
-        unsafeAtomicAdd(row + (size_t)k2 * A.Pc2, w01 * w[2][t2]);
-      }
-    }
-  }
-}
-
 template <int P, int ORDER, bool ENERGY>
 __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
   __shared__ double sred[NT];
@@ -151,6 +123,199 @@ __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
   }
 }
 
+// ------------------------------- owner-computes spreading ------------------------------
+// The grid is cut into TB^3-point tiles. Atoms are binned every step by the tile of their
+// centroid's stencil base; one block per (tile, group of GB beads) accumulates in LDS the
+// contributions of the atoms binned in the tile and its 26 neighbours and writes the tile
+// once. This is exact as long as no bead's base index differs from its centroid's by more
+// than TB points above or TB - n + 1 below, which the binning kernel checks (error flag).
+constexpr int TB = QHP_TB;
+
+struct TileArgs {
+  int N, P, K0, K1, K2, nt0, nt1, nt2, order;
+  const double* x;            // [3][N][P]
+  const double4* cent;        // centroids (batched) or null (P = 1: the bead itself)
+  double L[3], KoL[3];
+  int* tile_of; int* tile_count; int* tile_fill; int* tile_start; int* tile_atoms;
+  int ntiles;
+};
+
+using qhp::base_of;
+using qhp::grid_coord;
+
+// bin every atom by the tile of its centroid's grid base (P = 1: of the bead itself)
+__global__ __launch_bounds__(256) void k_tile_bin(TileArgs A) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= A.N) return;
+  const int K[3] = {A.K0, A.K1, A.K2};
+  int bc[3];
+  for (int d = 0; d < 3; ++d) {
+    const double cd = A.cent ? (&A.cent[a].x)[d] : A.x[(size_t)d * A.N + a];
+    bc[d] = base_of(cd, A.KoL[d], K[d]) % K[d];
+  }
+  const int t = (bc[0] / TB * A.nt1 + bc[1] / TB) * A.nt2 + bc[2] / TB;
+  A.tile_of[a] = t;
+  atomicAdd(&A.tile_count[t], 1);
+}
+
+__global__ __launch_bounds__(256) void k_tile_scan(TileArgs A) {
+  __shared__ int part[256];
+  const int t = threadIdx.x;
+  const int per = (A.ntiles + 255) / 256;
+  const int b0 = min(A.ntiles, t * per), b1 = min(A.ntiles, b0 + per);
+  int s = 0;
+  for (int k = b0; k < b1; ++k) s += A.tile_count[k];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int k = 0; k < 256; ++k) { const int v = part[k]; part[k] = acc; acc += v; }
+    A.tile_start[A.ntiles] = acc;
+  }
+  __syncthreads();
+  int acc = part[t];
+  for (int k = b0; k < b1; ++k) {
+    A.tile_start[k] = acc;
+    acc += A.tile_count[k];
+    A.tile_fill[k] = 0;
+    A.tile_count[k] = 0;        // consumed; ready for the next binning
+  }
+}
+
+__global__ void k_tile_scatter(TileArgs A) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= A.N) return;
+  const int t = A.tile_of[a];
+  const int slot = atomicAdd(&A.tile_fill[t], 1);
+  A.tile_atoms[A.tile_start[t] + slot] = a;
+}
+
+struct TSpreadArgs {
+  int N, P, K0, K1, K2, nt1, nt2, Pc2;
+  const double* x; double* grid; const double* charge;
+  const double4* cent;        // centroids (null for P = 1: the bead itself)
+  double L[3], KoL[3];        // box and K / L per axis
+  const NlCtrl* ctrl;         // spread_m: largest bead-centroid base offset this step
+  const int* tile_start; const int* tile_atoms; const int* tile_nbr;   // [ntiles][27]
+};
+
+// in-tile range of the stencil points base - t, t = 0..ORDER-1, along one axis:
+// lo = (base - ORDER + 1 - t0) mod K is the tile-relative position of the lowest point
+template <int ORDER>
+QHP_DEV int tile_lo(int base, int t0, int K) {
+  int r = base - (ORDER - 1) - t0;
+  r %= K;
+  return r < 0 ? r + K : r;
+}
+
+template <int ORDER, int GB>
+__global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
+  constexpr int CAP = 512;                 // compacted atoms per round
+  __shared__ double acc[TB * TB * TB * GB];
+  __shared__ int cand[CAP];
+  __shared__ int ncand;
+  const int tile = blockIdx.x, grp = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
+  for (int k = tid; k < TB * TB * TB * GB; k += NT) acc[k] = 0.0;
+  const int T2 = tile % A.nt2, T1 = (tile / A.nt2) % A.nt1, T0 = tile / (A.nt2 * A.nt1);
+  const int K[3] = {A.K0, A.K1, A.K2};
+  const int t0[3] = {T0 * TB, T1 * TB, T2 * TB};
+  const int P = A.P;
+  const int m = A.cent ? A.ctrl->spread_m : 0;
+  int src_k = 0, src_q = 0;                // scan position over the neighbouring tiles
+  for (;;) {
+    // 1) collect up to CAP atoms whose centroid stencil, widened by m points, reaches the tile
+    if (tid == 0) ncand = 0;
+    __syncthreads();
+    bool more = false;
+    while (src_k < 27) {
+      const int src = A.tile_nbr[tile * 27 + src_k];
+      if (src < 0) { src_k = 27; break; }
+      const int s0 = A.tile_start[src], n = A.tile_start[src + 1] - s0;
+      if (src_q >= n) { ++src_k; src_q = 0; continue; }
+      const int q = src_q + tid;
+      bool hit = false;
+      int a = -1;
+      if (q < n) {
+        a = A.tile_atoms[s0 + q];
+        hit = true;
+        if (A.cent) {
+          const double4 c = A.cent[a];
+          const double cc[3] = {c.x, c.y, c.z};
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const int bc = base_of(cc[d], A.KoL[d], K[d]);
+            const int lo = tile_lo<ORDER>(bc - m, t0[d], K[d]);
+            if (!(lo < TB || lo > K[d] - (ORDER + 2 * m) || K[d] <= TB)) hit = false;
+          }
+        }
+      }
+      const unsigned long long bal = __ballot(hit);
+      int off = 0;
+      if (lane == 0 && bal) off = atomicAdd(&ncand, __popcll(bal));
+      off = __shfl(off, 0);
+      if (hit) cand[off + __popcll(bal & ((1ull << lane) - 1ull))] = a;
+      src_q += NT;
+      __syncthreads();
+      if (ncand > CAP - NT) { more = true; break; }
+    }
+    const int nc = ncand;
+    // 2) every compacted atom at every bead of the group: spline weights, in-tile points
+    for (int it = tid; it < nc * GB; it += NT) {
+      const int a = cand[it / GB], b = grp * GB + it % GB, bl = it % GB;
+      double fr[3];
+      int lo[3];
+      bool hit = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double u = grid_coord(A.x[((size_t)d * A.N + a) * P + b], A.KoL[d], K[d]);
+        const double fl = floor(u);
+        const int base = isfinite(fl) ? min(max((int)fl, 0), K[d]) : 0;
+        fr[d] = u - fl;
+        lo[d] = tile_lo<ORDER>(base, t0[d], K[d]);
+        if (!(lo[d] < TB || lo[d] > K[d] - ORDER || K[d] <= TB)) hit = false;
+      }
+      if (!hit) continue;
+      double w[3][ORDER], dw[3][ORDER];
+      int rel[3][ORDER];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        bspline<ORDER>(fr[d], w[d], dw[d]);
+#pragma unroll
+        for (int t = 0; t < ORDER; ++t) {
+          // stencil point base - t sits at tile-relative position lo + ORDER - 1 - t (mod K)
+          int r = lo[d] + ORDER - 1 - t;
+          if (r >= K[d]) r -= K[d];
+          rel[d][t] = r < TB ? r : -1;
+        }
+      }
+      const double qa = A.charge[a];
+#pragma unroll
+      for (int ta = 0; ta < ORDER; ++ta) {
+        if (rel[0][ta] < 0) continue;
+        const double wa = qa * w[0][ta];
+#pragma unroll
+        for (int tb = 0; tb < ORDER; ++tb) {
+          if (rel[1][tb] < 0) continue;
+          const double wab = wa * w[1][tb];
+          double* row = acc + (rel[0][ta] * TB + rel[1][tb]) * TB * GB + bl;
+#pragma unroll
+          for (int tc = 0; tc < ORDER; ++tc)
+            if (rel[2][tc] >= 0) atomicAdd(row + rel[2][tc] * GB, wab * w[2][tc]);
+        }
+      }
+    }
+    __syncthreads();
+    if (!more) break;
+  }
+  for (int k = tid; k < TB * TB * TB * GB; k += NT) {
+    const int bb = k % GB, pt = k / GB;
+    const int r2 = pt % TB, r1 = (pt / TB) % TB, r0 = pt / (TB * TB);
+    const size_t g = ((size_t)((t0[0] + r0) * A.K1 + (t0[1] + r1)) * A.K2 + (t0[2] + r2)) * A.Pc2;
+    A.grid[g + grp * GB + bb] = acc[k];
+    if (P == 1) A.grid[g + 1] = 0.0;
+  }
+}
+
 // ------------------------------- LDS Stockham FFT -------------------------------------
 QHP_DEV double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -158,11 +323,24 @@ QHP_DEV double2 cmul(double2 a, double2 b) {
 QHP_DEV double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 QHP_DEV double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
-// Element e of series s lives at buf[e * NS + s]; NS * K = 4096.
+// radix-4 DFT in registers (forward: exp(-2 pi i / 4) = -i)
+template <bool INV>
+QHP_DEV void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
+  const double2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  const double2 t2 = cadd(a1, a3), t3 = csub(a1, a3);
+  const double2 jt3 = INV ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, jt3);
+  a3 = csub(t1, jt3);
+}
+
+// Element e of series s lives at buf[e * NS + s]; NS * K = 4096. Stockham stages of
+// radix 8 while at least 8 points remain per sub-transform, then 4, then 2.
 template <int K, int NS, bool INV, int NSTRIDE>
 QHP_DEV void fft_stages(double2* buf, const double2* tw, int tid) {
   if constexpr (NSTRIDE < K) {
-    constexpr int R = (K / NSTRIDE >= 4) ? 4 : 2;
+    constexpr int R = (K / NSTRIDE >= 8) ? 8 : ((K / NSTRIDE >= 4) ? 4 : 2);
     constexpr int BPT = NS * K / R / NT;
     double2 v[BPT][R];
 #pragma unroll
@@ -182,23 +360,31 @@ QHP_DEV void fft_stages(double2* buf, const double2* tw, int tid) {
         if (INV) t.y = -t.y;
         v[i][r] = cmul(v[i][r], t);
       }
-      double2 y[R];
-      if constexpr (R == 4) {
-        const double2 t0 = cadd(v[i][0], v[i][2]), t1 = csub(v[i][0], v[i][2]);
-        const double2 t2 = cadd(v[i][1], v[i][3]), t3 = csub(v[i][1], v[i][3]);
-        // -i * t3 (forward) or +i * t3 (inverse)
-        const double2 jt3 = INV ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
-        y[0] = cadd(t0, t2);
-        y[2] = csub(t0, t2);
-        y[1] = cadd(t1, jt3);
-        y[3] = csub(t1, jt3);
+      if constexpr (R == 8) {
+        // two radix-4 transforms of the even and odd inputs, joined by W8^q
+        dft4<INV>(v[i][0], v[i][2], v[i][4], v[i][6]);
+        dft4<INV>(v[i][1], v[i][3], v[i][5], v[i][7]);
+        const double h = 0.70710678118654752440;
+        const double sg = INV ? 1.0 : -1.0;       // W8 = (1 + sg i) / sqrt(2)
+        const double2 o0 = v[i][1];
+        const double2 o1 = cmul(v[i][3], make_double2(h, sg * h));
+        const double2 o2 = cmul(v[i][5], make_double2(0.0, sg));
+        const double2 o3 = cmul(v[i][7], make_double2(-h, sg * h));
+        const double2 e0 = v[i][0], e1 = v[i][2], e2 = v[i][4], e3 = v[i][6];
+        v[i][0] = cadd(e0, o0); v[i][4] = csub(e0, o0);
+        v[i][1] = cadd(e1, o1); v[i][5] = csub(e1, o1);
+        v[i][2] = cadd(e2, o2); v[i][6] = csub(e2, o2);
+        v[i][3] = cadd(e3, o3); v[i][7] = csub(e3, o3);
+      } else if constexpr (R == 4) {
+        dft4<INV>(v[i][0], v[i][1], v[i][2], v[i][3]);
       } else {
-        y[0] = cadd(v[i][0], v[i][1]);
-        y[1] = csub(v[i][0], v[i][1]);
+        const double2 a = v[i][0], b2 = v[i][1];
+        v[i][0] = cadd(a, b2);
+        v[i][1] = csub(a, b2);
       }
       const int idx = (j / NSTRIDE) * NSTRIDE * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(idx + r * NSTRIDE) * NS + s] = y[r];
+      for (int r = 0; r < R; ++r) buf[(idx + r * NSTRIDE) * NS + s] = v[i][r];
     }
     __syncthreads();
     fft_stages<K, NS, INV, NSTRIDE * R>(buf, tw, tid);
@@ -320,15 +506,45 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead) {
   A.grid = (double*)c->grid; A.charge = c->d_charge;
   for (int d = 0; d < 3; ++d) A.L[d] = c->p.box[d];
   A.energy = c->energy + (plain ? (size_t)bead * QHP_NTERMS : 0);
-  const size_t gbytes = (size_t)c->K[0] * c->K[1] * c->K[2] * pc * sizeof(double2);
-  hipError_t e = launch_zero(c, c->grid, gbytes);
-  if (e != hipSuccess) return e;
   const unsigned nb = (unsigned)(((size_t)N * P + NT - 1) / NT);
   hipEvent_t ev = nullptr;
   prof_begin(c, QHP_PROF_SPREAD, &ev);
-  QHP_SWITCH_P(P, QHP_SWITCH_ORDER(c->p.pme_order,
-               hipLaunchKernelGGL((k_spread<PP, OO>), nb, NT, 0, c->stream, A)));
+  {
+    TileArgs T;
+    T.N = N; T.P = P; T.K0 = c->K[0]; T.K1 = c->K[1]; T.K2 = c->K[2];
+    T.nt0 = c->K[0] / TB; T.nt1 = c->K[1] / TB; T.nt2 = c->K[2] / TB; T.order = c->p.pme_order;
+    T.x = A.x; T.cent = plain ? nullptr : c->cent;
+    for (int d = 0; d < 3; ++d) { T.L[d] = c->p.box[d]; T.KoL[d] = c->K[d] / c->p.box[d]; }
+    T.tile_of = c->tile_of; T.tile_count = c->tile_count; T.tile_fill = c->tile_fill;
+    T.tile_start = c->tile_start; T.tile_atoms = c->tile_atoms; T.ntiles = c->ntiles;
+    hipLaunchKernelGGL(k_tile_bin, (N + 255) / 256, 256, 0, c->stream, T);
+    hipLaunchKernelGGL(k_tile_scan, 1, 256, 0, c->stream, T);
+    hipLaunchKernelGGL(k_tile_scatter, (N + 255) / 256, 256, 0, c->stream, T);
+    TSpreadArgs S;
+    S.N = N; S.P = P; S.K0 = c->K[0]; S.K1 = c->K[1]; S.K2 = c->K[2];
+    S.nt1 = T.nt1; S.nt2 = T.nt2; S.Pc2 = 2 * pc;
+    S.x = A.x; S.grid = A.grid; S.charge = c->d_charge;
+    S.cent = plain ? nullptr : c->cent;
+    S.ctrl = c->ctrl;
+    for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
+    S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms; S.tile_nbr = c->tile_nbr;
+    const int gbeads = P < 8 ? P : 8;
+    const dim3 grid(c->ntiles, P / gbeads);
+#define SPREAD_CALL(GBV)                                                                     \
+    QHP_SWITCH_ORDER(c->p.pme_order,                                                         \
+                     hipLaunchKernelGGL((k_spread_tiles<OO, GBV>), grid, NT, 0, c->stream, S))
+    switch (gbeads) {
+      case 1: SPREAD_CALL(1); break;
+      case 2: SPREAD_CALL(2); break;
+      case 4: SPREAD_CALL(4); break;
+      case 8: SPREAD_CALL(8); break;
+      default: SPREAD_CALL(16); break;
+    }
+#undef SPREAD_CALL
+  }
   prof_end(c, QHP_PROF_SPREAD, ev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   prof_begin(c, QHP_PROF_FFT, &ev);
   if ((e = fft_pass(c, 0, 0, pc)) != hipSuccess) return e;
   if ((e = fft_pass(c, 1, 0, pc)) != hipSuccess) return e;

@@ -230,3 +230,17 @@ def test_rebuild_rule_holds_over_a_trajectory(large):
     say("nlist stats after 200 steps", st)
     assert 1 < st["builds"] < 120
     assert st["max_count"] <= st["capacity"]
+
+
+def test_graph_replay_equals_eager_launches(small):
+    """The captured-graph step and the launched step are the same kernels in the same
+    order: trajectories agree to rounding (SPME accumulation order aside)."""
+    s, _ = small
+    out = []
+    for g in (True, False):
+        with ctx_for(s, use_graph=g) as c:
+            c.set_state(s.pos, s.vel, 0)
+            c.step(30)
+            out.append(c.get_state())
+    assert out[0][2] == out[1][2] == 30
+    assert np.abs(out[0][0] - out[1][0]).max() / np.abs(out[1][0]).max() < 1e-12
