@@ -58,6 +58,7 @@ __global__ __launch_bounds__(256) void k_nl_check(NlArgs A, int force) {
     c->force_build = 0;
     if (!force) c->step += 1;       // a propagation step's forces: the step is done
     c->spread_m = (int)sm[2][0];
+    c->max_db = db;
     if (sm[3][0] != 0.0) c->spread_margin = 1;
     if (b) { c->n_builds += 1; c->max_count = 0; }
     go = b;

@@ -44,15 +44,35 @@ QHP_DEV double wave_max(double v) {
   return v;
 }
 
+// sum_i M[i * P + n] * v[i] over i = I0..P-1 with four independent partial sums
+template <int P, int I0 = 0>
+QHP_DEV double contract_col(const double* M, const double* v, int n) {
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int i = I0;
+#pragma unroll
+  for (; i + 4 <= P; i += 4) {
+    s0 += M[(i + 0) * P + n] * v[i + 0];
+    s1 += M[(i + 1) * P + n] * v[i + 1];
+    s2 += M[(i + 2) * P + n] * v[i + 2];
+    s3 += M[(i + 3) * P + n] * v[i + 3];
+  }
+#pragma unroll
+  for (; i < P; ++i) s0 += M[i * P + n] * v[i];
+  return (s0 + s1) + (s2 + s3);
+}
+
 template <int P, bool QTB, bool BEADMAJOR, bool F32>
 __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
   constexpr int AT = NT / P;
-  __shared__ double sT[P * P];
-  __shared__ double sh[AT][3][P];
+  constexpr int PP = P + 1;          // padding: the atoms of a wavefront hit different banks
+  __shared__ double sT[P * P];       // T[i][n] at i * P + n
+  __shared__ double sTt[P * P];      // T[n][k] at k * P + n (lane-contiguous for x = T Q)
+  __shared__ double sh[AT][3][PP];
   const int tid = threadIdx.x;
   const int al = tid / P, n = tid % P;
   const int a = blockIdx.x * AT + al;
   for (int k = tid; k < P * P; k += NT) sT[k] = A.T[k];
+  for (int k = tid; k < P * P; k += NT) sTt[(k % P) * P + k / P] = A.T[k];
   const bool live = a < A.N;
   const uint64_t step = (uint64_t)A.ctrl->step;       // advanced by the list check
   double gv[3] = {0, 0, 0};
@@ -71,10 +91,7 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
     double xi[3] = {0, 0, 0};
     if (!QTB) qhp::gauss3(A.seed, qhp::STREAM_RPMD_O, step, (uint64_t)a, (uint64_t)n, xi);
     for (int d = 0; d < 3; ++d) {
-      double f = 0;
-#pragma unroll 8
-      for (int i = 0; i < P; ++i) f += sT[i * P + n] * sh[al][d][i];
-      f = -f * rsP;
+      const double f = -contract_col<P>(sT, sh[al][d], n) * rsP;
       const int gi = (d * A.N + a) * P + n;
       double pp = A.Pa[gi] + A.dt * f;
       double qq = A.Q[gi];
@@ -110,9 +127,8 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
     const double sP = sqrt((double)P);
     double xb[3], c[3];
     for (int d = 0; d < 3; ++d) {
-      double s = 0;
-#pragma unroll 8
-      for (int k = 1; k < P; ++k) s += sT[n * P + k] * sh[al][d][k];
+      // x_n = Q_0 + sqrt(P) sum_{k>=1} T[n][k] Q_k (the k = 0 term enters as Q_0 itself)
+      const double s = contract_col<P, 1>(sTt, sh[al][d], n);
       c[d] = sh[al][d][0];
       xb[d] = c[d] + sP * s;
       A.x[gidx<P, BEADMAJOR>(A.N, d, a, n)] = xb[d];

@@ -47,6 +47,7 @@ struct PairArgs {
   double lj_e4[QHP_MAX_TYPES * QHP_MAX_TYPES];
   int ntypes;
   int nblocks;            // logical blocks
+  const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
   double* energy;         // [P][NTERMS] (plain: the bead's row)
 };
 
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
   constexpr int S = 64 / P;
   __shared__ float4 scd[WPB][64];   // centroid difference (x, y, z) and q_i q_j C
   __shared__ float2 slj[WPB][64];   // 4 eps_ij and sigma_ij^6 of the pair
-  __shared__ int sj[WPB][64];       // j
+  __shared__ int sj[WPB][64];       // j * P (element offset of atom j's beads)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, s = lane / P, b = lane % P;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int i = lb * WPB + wv;
@@ -161,28 +162,44 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
   const float kexp = (float)(-A.alpha * A.alpha * 1.4426950408889634);  // -alpha^2 log2(e)
   const float c2a = (float)(2.0 * A.alpha / sqrt(M_PI));
   const float rc2 = (float)A.rc2;
+  // no bead of a pair whose centroids are further apart than rc + 2 max|bead - centroid|
+  // can be within the cutoff (small margin for the FP32 rounding of the difference)
+  const double reach = sqrt(A.rc2) + 2.0 * A.ctrl->max_db + 1e-3;
+  const float reach2 = (float)(reach * reach);
   const int nn = A.nnbr[i];
   const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
   for (int k0 = 0; k0 < nn; k0 += 64) {
-    const int cnt = min(64, nn - k0);
-    if (lane < cnt) {
+    bool keep = false;
+    float4 cdv;
+    float2 ljv;
+    int jp = 0;
+    if (k0 + lane < nn) {
       const unsigned e = (unsigned)row[k0 + lane];
       const int j = e & 0x3FFFFFF;
       const double4 cj = A.cwrap[j];
       const float cx = (float)((cj.x - ci.x) + A.L[0] * (double)((int)((e >> 26) & 3) - 1));
       const float cy = (float)((cj.y - ci.y) + A.L[1] * (double)((int)((e >> 28) & 3) - 1));
       const float cz = (float)((cj.z - ci.z) + A.L[2] * (double)((int)((e >> 30) & 3) - 1));
-      scd[wv][lane] = make_float4(cx, cy, cz, (float)(qi * A.charge[j]));
+      keep = cx * cx + cy * cy + cz * cz < reach2;
+      cdv = make_float4(cx, cy, cz, (float)(qi * A.charge[j]));
       const int tp = ti * A.ntypes + A.type[j];
-      slj[wv][lane] = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
-      sj[wv][lane] = j;
+      ljv = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
+      jp = j * P;
     }
+    const unsigned long long bal = __ballot(keep);
+    if (keep) {
+      const int slot = __popcll(bal & ((1ull << lane) - 1ull));
+      scd[wv][slot] = cdv;
+      slj[wv][slot] = ljv;
+      sj[wv][slot] = jp;
+    }
+    const int cnt = __popcll(bal);
     wave_sync();
     float fx = 0.f, fy = 0.f, fz = 0.f;
     for (int t = s; t < cnt; t += S) {
       const float4 cd = scd[wv][t];
-      const float4 oj = A.xf[(size_t)sj[wv][t] * P + b];
+      const float4 oj = A.xf[sj[wv][t] + b];
       const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
       const float r2 = dx * dx + dy * dy + dz * dz;
       if (r2 < rc2) {
@@ -245,6 +262,7 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead) {
       A.lj_e4[a * A.ntypes + b] = 4.0 * e;
     }
   A.energy = c->energy + (plain ? (size_t)bead * QHP_NTERMS : 0);
+  A.ctrl = c->ctrl;
   const int P = plain ? 1 : c->P;
   A.nblocks = (N + WPB - 1) / WPB;
   const unsigned nb = (unsigned)((A.nblocks + 7) / 8 * 8);

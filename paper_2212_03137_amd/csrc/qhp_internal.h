@@ -32,6 +32,7 @@ struct NlCtrl {               // device-side control block (neighbour list, step
   int n_builds;               // builds so far
   int spread_margin;          // a bead left the SPME tile margin of its centroid
   int spread_m;               // largest bead-centroid grid-base offset this step
+  double max_db;              // largest bead-centroid distance this step
 };
 
 struct QtbState {

@@ -22,6 +22,8 @@ constexpr int NT = 256;
 
 struct SpmeArgs {
   int N;
+  int nblocks;             // logical blocks of the gather
+  const int* order;        // atoms in tile order (spatially compact blocks)
   int K0, K1, K2;
   int Pc2;                 // doubles per grid point (2 * complex slots)
   const double* x; double* g;
@@ -71,11 +73,16 @@ QHP_DEV void stencil(const double* xb, const double* L, const int* K, int* i0, d
 
 QHP_DEV int wrapk(int k, int K) { return k < 0 ? k + K : (k >= K ? k - K : k); }
 
+// physical block -> logical block so that XCD k (blocks k, k+8, ...) gets a contiguous range
+QHP_DEV int xcd_block(int bid, int nphys) { return (bid & 7) * (nphys >> 3) + (bid >> 3); }
+
 template <int P, int ORDER, bool ENERGY>
 __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
   __shared__ double sred[NT];
-  const int tid = blockIdx.x * NT + threadIdx.x;
-  const int a = tid / P, b = tid % P;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int tid = lb * NT + threadIdx.x;
+  const int k = tid / P, b = tid % P;
+  const int a = (lb < A.nblocks && k < A.N) ? A.order[k] : A.N;
   double e = 0;
   if (a < A.N) {
     double xb[3];
@@ -210,10 +217,11 @@ QHP_DEV int tile_lo(int base, int t0, int K) {
 
 template <int ORDER, int GB>
 __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
-  constexpr int CAP = 512;                 // compacted atoms per round
+  constexpr int CAP = 1024;                // compacted atoms per round
   __shared__ double acc[TB * TB * TB * GB];
   __shared__ int cand[CAP];
   __shared__ int ncand;
+  __shared__ int tofs[28], tbeg[27];
   const int tile = blockIdx.x, grp = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
   for (int k = tid; k < TB * TB * TB * GB; k += NT) acc[k] = 0.0;
   const int T2 = tile % A.nt2, T1 = (tile / A.nt2) % A.nt1, T0 = tile / (A.nt2 * A.nt1);
@@ -221,22 +229,35 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
   const int t0[3] = {T0 * TB, T1 * TB, T2 * TB};
   const int P = A.P;
   const int m = A.cent ? A.ctrl->spread_m : 0;
-  int src_k = 0, src_q = 0;                // scan position over the neighbouring tiles
+  // the atoms of the (up to) 27 neighbouring tiles, concatenated
+  if (tid < 27) {
+    const int src = A.tile_nbr[tile * 27 + tid];
+    tbeg[tid] = src >= 0 ? A.tile_start[src] : 0;
+    tofs[tid + 1] = src >= 0 ? A.tile_start[src + 1] - A.tile_start[src] : 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    tofs[0] = 0;
+    for (int k = 1; k <= 27; ++k) tofs[k] += tofs[k - 1];
+  }
+  __syncthreads();
+  const int total = tofs[27];
+  int pos = 0;
   for (;;) {
-    // 1) collect up to CAP atoms whose centroid stencil, widened by m points, reaches the tile
+    // 1) collect atoms whose centroid stencil, widened by m points, reaches the tile
     if (tid == 0) ncand = 0;
     __syncthreads();
-    bool more = false;
-    while (src_k < 27) {
-      const int src = A.tile_nbr[tile * 27 + src_k];
-      if (src < 0) { src_k = 27; break; }
-      const int s0 = A.tile_start[src], n = A.tile_start[src + 1] - s0;
-      if (src_q >= n) { ++src_k; src_q = 0; continue; }
-      const int q = src_q + tid;
+    while (pos < total && ncand <= CAP - NT) {
+      const int p = pos + tid;
       bool hit = false;
       int a = -1;
-      if (q < n) {
-        a = A.tile_atoms[s0 + q];
+      if (p < total) {
+        int lo = 0, hi = 27;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (tofs[mid] <= p) lo = mid; else hi = mid;
+        }
+        a = A.tile_atoms[tbeg[lo] + (p - tofs[lo])];
         hit = true;
         if (A.cent) {
           const double4 c = A.cent[a];
@@ -244,8 +265,8 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
             const int bc = base_of(cc[d], A.KoL[d], K[d]);
-            const int lo = tile_lo<ORDER>(bc - m, t0[d], K[d]);
-            if (!(lo < TB || lo > K[d] - (ORDER + 2 * m) || K[d] <= TB)) hit = false;
+            const int l0 = tile_lo<ORDER>(bc - m, t0[d], K[d]);
+            if (!(l0 < TB || l0 > K[d] - (ORDER + 2 * m) || K[d] <= TB)) hit = false;
           }
         }
       }
@@ -254,10 +275,10 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
       if (lane == 0 && bal) off = atomicAdd(&ncand, __popcll(bal));
       off = __shfl(off, 0);
       if (hit) cand[off + __popcll(bal & ((1ull << lane) - 1ull))] = a;
-      src_q += NT;
+      pos += NT;
       __syncthreads();
-      if (ncand > CAP - NT) { more = true; break; }
     }
+    const bool more = pos < total;
     const int nc = ncand;
     // 2) every compacted atom at every bead of the group: spline weights, in-tile points
     for (int it = tid; it < nc * GB; it += NT) {
@@ -395,8 +416,8 @@ struct FftArgs {
   double2* grid;
   const double2* tw;       // [K] exp(-2 pi i m / K)
   const double* G;         // influence [K0][K1][K2] (fused z pass)
-  long inner;              // complex elements below the axis (stride of the axis)
-  int pc;                  // complex slots per grid point
+  int lgI;                 // log2 of the complex elements below the axis (its stride)
+  int lgpc;                // log2 of the complex slots per grid point
   int efast;               // load order
 };
 
@@ -408,13 +429,16 @@ __global__ __launch_bounds__(NT) void k_fft_pass(FftArgs A) {
   __shared__ double2 stw[K];
   const int tid = threadIdx.x;
   for (int m = tid; m < K; m += NT) stw[m] = A.tw[m];
+  constexpr int LGK = __builtin_ctz(K);
   const long m0 = (long)blockIdx.x * NS;
-  const long I = A.inner;
+  const int lgI = A.lgI;
+  const long Imask = (1l << lgI) - 1;
+  // series m, element e -> (m / I) * K * I + (m % I) + e * I, with I a power of two
   for (int l = tid; l < 4096; l += NT) {
-    const int e = A.efast ? l % K : l / NS;
-    const int s = A.efast ? l / K : l % NS;
+    const int e = A.efast ? (l & (K - 1)) : (l >> __builtin_ctz(NS));
+    const int s = A.efast ? (l >> LGK) : (l & (NS - 1));
     const long m = m0 + s;
-    buf[e * NS + s] = A.grid[(m / I) * (K * I) + (m % I) + (long)e * I];
+    buf[e * NS + s] = A.grid[((m >> lgI) << (lgI + LGK)) + (m & Imask) + ((long)e << lgI)];
   }
   __syncthreads();
   if (MODE == 1) {
@@ -424,8 +448,8 @@ __global__ __launch_bounds__(NT) void k_fft_pass(FftArgs A) {
   }
   if (MODE == 2) {
     for (int l = tid; l < 4096; l += NT) {
-      const int e = l / NS, s = l % NS;
-      const long p = (m0 + s) / A.pc;
+      const int e = l >> __builtin_ctz(NS), s = l & (NS - 1);
+      const long p = (m0 + s) >> A.lgpc;
       const double gv = A.G[p * K + e];
       double2 v = buf[e * NS + s];
       v.x *= gv; v.y *= gv;
@@ -435,10 +459,10 @@ __global__ __launch_bounds__(NT) void k_fft_pass(FftArgs A) {
     fft_stages<K, NS, true, 1>(buf, stw, tid);
   }
   for (int l = tid; l < 4096; l += NT) {
-    const int e = A.efast ? l % K : l / NS;
-    const int s = A.efast ? l / K : l % NS;
+    const int e = A.efast ? (l & (K - 1)) : (l >> __builtin_ctz(NS));
+    const int s = A.efast ? (l >> LGK) : (l & (NS - 1));
     const long m = m0 + s;
-    A.grid[(m / I) * (K * I) + (m % I) + (long)e * I] = buf[e * NS + s];
+    A.grid[((m >> lgI) << (lgI + LGK)) + (m & Imask) + ((long)e << lgI)] = buf[e * NS + s];
   }
 }
 
@@ -485,7 +509,8 @@ static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc) {
   const int NS = 4096 / K;
   if (series % NS) return hipErrorInvalidValue;
   FftArgs A;
-  A.grid = c->grid; A.tw = c->tw[axis]; A.G = c->influence; A.inner = inner; A.pc = pc;
+  A.grid = c->grid; A.tw = c->tw[axis]; A.G = c->influence;
+  A.lgI = __builtin_ctzl((unsigned long)inner); A.lgpc = __builtin_ctz((unsigned)pc);
   A.efast = inner < 16;
   const unsigned nb = (unsigned)(series / NS);
   if (mode == 0) { QHP_SWITCH_K(K, hipLaunchKernelGGL((k_fft_pass<KK, 0>), nb, NT, 0, c->stream, A)); }
@@ -501,6 +526,7 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead) {
   const int N = c->N;
   SpmeArgs A;
   A.N = N; A.K0 = c->K[0]; A.K1 = c->K[1]; A.K2 = c->K[2]; A.Pc2 = 2 * pc;
+  A.order = c->tile_atoms;
   A.x = plain ? c->x + (size_t)bead * 3 * N : c->x;
   A.g = plain ? c->g + (size_t)bead * 3 * N : c->g;
   A.grid = (double*)c->grid; A.charge = c->d_charge;
@@ -553,9 +579,11 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead) {
   if ((e = fft_pass(c, 0, 1, pc)) != hipSuccess) return e;
   prof_end(c, QHP_PROF_FFT, ev);
   prof_begin(c, QHP_PROF_GATHER, &ev);
+  A.nblocks = (int)nb;
+  const unsigned nb8 = (nb + 7) / 8 * 8;
   QHP_SWITCH_P(P, QHP_SWITCH_ORDER(c->p.pme_order,
-               if (energy) hipLaunchKernelGGL((k_gather<PP, OO, true>), nb, NT, 0, c->stream, A);
-               else hipLaunchKernelGGL((k_gather<PP, OO, false>), nb, NT, 0, c->stream, A)));
+               if (energy) hipLaunchKernelGGL((k_gather<PP, OO, true>), nb8, NT, 0, c->stream, A);
+               else hipLaunchKernelGGL((k_gather<PP, OO, false>), nb8, NT, 0, c->stream, A)));
   prof_end(c, QHP_PROF_GATHER, ev);
   return hipGetLastError();
 }
