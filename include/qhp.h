@@ -99,8 +99,8 @@ typedef struct qhp_params {
   double ewald_alpha;       /* Ewald splitting parameter alpha                            */
   double cutoff;            /* real-space cutoff rc (< half the smallest box edge)        */
   double skin;              /* neighbour-list skin: r_list = rc + skin                    */
-  int32_t pme_grid[3];      /* SPME grid; powers of two in 8..256, each >= 2*pme_order    */
-  int32_t pme_order;        /* B-spline order n in 3..8                                   */
+  int32_t pme_grid[3];      /* SPME grid; powers of two in 8..128, each >= 2*pme_order    */
+  int32_t pme_order;        /* B-spline order n: 4, 5, 6 or 8 (3 and 7: EUNSUPPORTED)    */
   int32_t precision;        /* QHP_FP64 | QHP_FP32_PAIRS                                  */
   int32_t exec;             /* QHP_BATCHED | QHP_PLAIN                                    */
   int32_t thermostat;       /* QHP_TRPMD | QHP_ADQTB                                      */
@@ -111,7 +111,7 @@ typedef struct qhp_params {
   double trpmd_c;           /* TRPMD: internal-mode friction max(gamma_0, c * omega_n)   */
   uint64_t seed;            /* Philox-4x64-10 key word 0                                  */
   double qtb_gamma0;        /* adQTB: friction gamma_0                                   */
-  int32_t qtb_nseg;         /* adQTB: segment length N_seg (power of two, 16..4096)      */
+  int32_t qtb_nseg;         /* adQTB: segment length N_seg (power of two, 16..1024)      */
   double qtb_adapt_rate;    /* adQTB: SIMPLE rate A_gamma (same for every type)          */
   double qtb_gamma_min_frac;/* adQTB: gamma_min = frac * gamma_0 (paper default 0.01)    */
   int32_t qtb_classical;    /* adQTB test switch: Theta(omega) = kT (white-noise limit)  */
@@ -122,9 +122,12 @@ typedef struct qhp_params {
 typedef struct qhp_ctx qhp_ctx;
 
 /* Create a context on the current HIP device. `stream` is a hipStream_t; all work of the
- * context is queued on it (NULL: the library creates a private non-blocking stream). Validates `p` (QHP_EINVAL),
- * allocates device state (QHP_ENOMEM) and precomputes the normal-mode transfer matrix,
- * mode frequencies, thermostat and A-block coefficients and the SPME influence function.
+ * context is queued on it (NULL: the library creates a private non-blocking stream).
+ * Validates `p` (QHP_EINVAL; QHP_EUNSUPPORTED for valid settings this build does not run:
+ * B-spline order 3 or 7, or more cells plus SPME tiles than the per-step bookkeeping block
+ * holds in LDS, 2*(cells + (K0/8)(K1/8)(K2/8)) <= 24576), allocates device state
+ * (QHP_ENOMEM) and precomputes the normal-mode transfer matrix, mode frequencies,
+ * thermostat and A-block coefficients and the SPME influence function.
  * The state is undefined until qhp_set_state. */
 QHP_API int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out);
 QHP_API int qhp_destroy(qhp_ctx* ctx);

@@ -150,7 +150,7 @@ int validate(const qhp_params* p, std::string& why) {
   }
   for (int d = 0; d < 3; ++d) {
     const int K = p->pme_grid[d];
-    if (!pow2(K) || K < 8 || K > 256) return bad("pme_grid must be powers of two in 8..256");
+    if (!pow2(K) || K < 8 || K > 128) return bad("pme_grid must be powers of two in 8..128");
     if (K < 2 * p->pme_order) return bad("pme_grid must be >= 2 * pme_order");
   }
   if (p->precision != QHP_FP64 && p->precision != QHP_FP32_PAIRS) return bad("precision");
@@ -311,6 +311,11 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     c->cap = (c->cap + 31) / 32 * 32;
   }
   c->cap = std::min(c->cap, N);
+  if ((size_t)(2 * c->ncell + 2 * (c->K[0] / 8) * (c->K[1] / 8) * (c->K[2] / 8)) * sizeof(int) >
+      96 * 1024) {
+    free_all(c); delete c;
+    return QHP_EUNSUPPORTED;      // the per-step prep block keeps its counters in LDS
+  }
   TRY(dalloc(&c->ctrl, 1));
   c->n_bmax = (N + 255) / 256 * 64;      // >= blocks of the normal-mode kernel for any P
   TRY(dalloc(&c->bmax, c->n_bmax));

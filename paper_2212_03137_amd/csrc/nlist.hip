@@ -3,12 +3,12 @@
 // are). One list serves every bead of every step until the skin is used up.
 //
 // Build: cells of edge >= r_list / 2 on the centroids (wrapped fractional coordinate x n_c,
-// floored, clamped to n_c - 1); each cell's atoms in increasing atom order; one block per
+// floored, clamped to n_c - 1); one block per
 // cell stages the atoms of its (up to) 5 x 5 x 5 distinct neighbouring cells in LDS and
 // every wavefront scans them for one atom i of the cell. A pair (i, j) of different
 // molecules is kept when the minimum-image centroid distance squared is < r_list^2,
 // evaluated as d - L rint(d * (1/L)) per axis and (dx*dx + dy*dy) + dz*dz without
-// contraction, so the list is reproducible bit for bit.
+// contraction, so the set of pairs is reproducible bit for bit (the order of a row is not).
 //
 // Row i of the list (nbr[i * cap + k]) holds j | (sx+1) << 26 | (sy+1) << 28 | (sz+1) << 30,
 // with s the image shift between the two centroids in the frame wrapped at build time
@@ -125,27 +125,107 @@ __global__ void k_nl_scatter(NlArgs A) {
   A.cell_atoms[A.cell_start[id] + slot] = a;
 }
 
-// order each cell's atoms by index: one wavefront per cell, rank of every element by
-// counting the smaller ones (cells hold a few tens of atoms; larger cells loop)
-__global__ __launch_bounds__(256) void k_nl_sort(NlArgs A) {
-  if (!A.ctrl->do_build) return;
-  __shared__ int buf[4][MAXC];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int cell = blockIdx.x * 4 + wv;
-  if (cell >= A.ncell) return;
-  int* v = A.cell_atoms + A.cell_start[cell];
-  const int n = A.cell_start[cell + 1] - A.cell_start[cell];
-  if (n > MAXC) { if (lane == 0) A.ctrl->overflow = 1; return; }
-  for (int k = lane; k < n; k += 64) buf[wv][k] = v[k];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int k = lane; k < n; k += 64) {
-    const int key = buf[wv][k];
-    int rank = 0;
-    for (int q = 0; q < n; ++q) rank += buf[wv][q] < key;
-    v[rank] = key;
+// One block per step (batched path): reduce the per-block maxima of the normal-mode (or
+// centroid) kernel and decide the rebuild; bin every atom into its SPME tile by the grid
+// base of its centroid (counts, offsets, scatter, all in LDS); on a rebuild, assign the
+// centroid cells and scatter the atoms into them. The cell order within a cell is not
+// significant (the exported list is canonical).
+struct PrepArgs {
+  NlArgs nl;
+  int ntiles, nt1, nt2, K0, K1, K2;
+  double KoL0, KoL1, KoL2;
+  int* tile_of; int* tile_start; int* tile_atoms;
+};
+
+__global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
+  extern __shared__ int lds[];
+  NlArgs& A = B.nl;
+  int* tcount = lds;                          // [ntiles]
+  int* tfill = lds + B.ntiles;                // [ntiles]
+  int* ccount = lds + 2 * B.ntiles;           // [ncell]
+  int* cfill = ccount + A.ncell;              // [ncell]
+  __shared__ double sm[4][1024];
+  __shared__ int go;
+  __shared__ int part[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // ---- 1. rebuild decision and step bookkeeping ----
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = tid; k < A.n_bmax; k += nt) {
+    const double4 v = A.bmax[k];
+    a[0] = fmax(a[0], v.x); a[1] = fmax(a[1], v.y); a[2] = fmax(a[2], v.z); a[3] = fmax(a[3], v.w);
   }
+  for (int q = 0; q < 4; ++q) sm[q][tid] = a[q];
+  for (int k = tid; k < B.ntiles; k += nt) tcount[k] = 0;
+  for (int k = tid; k < A.ncell; k += nt) ccount[k] = 0;
+  __syncthreads();
+  for (int st = nt / 2; st > 0; st >>= 1) {
+    if (tid < st)
+      for (int q = 0; q < 4; ++q) sm[q][tid] = fmax(sm[q][tid], sm[q][tid + st]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    NlCtrl* c = A.ctrl;
+    const double dc = sqrt(sm[0][0]), db = sqrt(sm[1][0]);
+    const int b = force || c->force_build || !(2.0 * (dc + db) <= A.skin);
+    c->do_build = b;
+    c->force_build = 0;
+    if (!force) c->step += 1;       // a propagation step's forces: the step is done
+    c->spread_m = (int)sm[2][0];
+    c->max_db = db;
+    if (sm[3][0] != 0.0) c->spread_margin = 1;
+    if (b) { c->n_builds += 1; c->max_count = 0; }
+    go = b;
+  }
+  // ---- 2. SPME tiles ----
+  const int K[3] = {B.K0, B.K1, B.K2};
+  const double KoL[3] = {B.KoL0, B.KoL1, B.KoL2};
+  for (int i = tid; i < A.N; i += nt) {
+    const double4 c = A.cent[i];
+    const double cc[3] = {c.x, c.y, c.z};
+    int bc[3];
+    for (int d = 0; d < 3; ++d) bc[d] = qhp::base_of(cc[d], KoL[d], K[d]) % K[d];
+    const int t = (bc[0] / QHP_TB * B.nt1 + bc[1] / QHP_TB) * B.nt2 + bc[2] / QHP_TB;
+    B.tile_of[i] = t;
+    atomicAdd(&tcount[t], 1);
+  }
+  __syncthreads();
+  // exclusive scan of a count array of length n by the block (per-thread chunks)
+  auto scan = [&](const int* cnt, int* start_g, int* fill, int n) {
+    const int per = (n + nt - 1) / nt;
+    const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+    int s = 0;
+    for (int k = b0; k < b1; ++k) s += cnt[k];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+      int acc = 0;
+      for (int k = 0; k < nt; ++k) { const int v = part[k]; part[k] = acc; acc += v; }
+      start_g[n] = acc;
+    }
+    __syncthreads();
+    int acc = part[tid];
+    for (int k = b0; k < b1; ++k) { start_g[k] = acc; fill[k] = acc; acc += cnt[k]; }
+    __syncthreads();
+  };
+  scan(tcount, B.tile_start, tfill, B.ntiles);
+  for (int i = tid; i < A.N; i += nt) B.tile_atoms[atomicAdd(&tfill[B.tile_of[i]], 1)] = i;
+  // ---- 3. centroid cells of a rebuild ----
+  if (!go) return;
+  for (int i = tid; i < A.N; i += nt) {
+    const double4 c = A.cent[i];
+    const int id = (cell_coord(c.x, A.iL0, A.nc0) * A.nc1 + cell_coord(c.y, A.iL1, A.nc1)) * A.nc2 +
+                   cell_coord(c.z, A.iL2, A.nc2);
+    A.cell_of[i] = id;
+    A.cref[i] = c;
+    const double4 w = make_double4(wrapped(c.x, A.L0, A.iL0), wrapped(c.y, A.L1, A.iL1),
+                                   wrapped(c.z, A.L2, A.iL2), 0.0);
+    A.cwrap[i] = w;
+    A.coff[i] = make_double4(c.x - w.x, c.y - w.y, c.z - w.z, 0.0);
+    atomicAdd(&ccount[id], 1);
+  }
+  __syncthreads();
+  scan(ccount, A.cell_start, cfill, A.ncell);
+  for (int i = tid; i < A.N; i += nt) A.cell_atoms[atomicAdd(&cfill[A.cell_of[i]], 1)] = i;
 }
 
 __global__ __launch_bounds__(256) void k_nl_build(NlArgs A) {
@@ -243,7 +323,7 @@ __global__ __launch_bounds__(256) void k_nl_build(NlArgs A) {
 
 }  // namespace
 
-hipError_t launch_nlist(qhp_ctx* c, bool from_step) {
+static NlArgs nl_args(qhp_ctx* c) {
   NlArgs A;
   A.N = c->N; A.cap = c->cap; A.ncell = c->ncell; A.nst = c->nst;
   A.nc0 = c->nc[0]; A.nc1 = c->nc[1]; A.nc2 = c->nc[2];
@@ -254,11 +334,30 @@ hipError_t launch_nlist(qhp_ctx* c, bool from_step) {
   A.cell_of = c->cell_of; A.cell_count = c->cell_count; A.cell_fill = c->cell_fill;
   A.cell_start = c->cell_start; A.cell_atoms = c->cell_atoms; A.stencil = c->stencil;
   A.nbr = c->nbr; A.nnbr = c->nnbr; A.ctrl = c->ctrl; A.bmax = c->bmax; A.n_bmax = c->n_bmax;
+  return A;
+}
+
+size_t prep_lds_bytes(const qhp_ctx* c) { return (size_t)(2 * c->ntiles + 2 * c->ncell) * sizeof(int); }
+
+// Batched path: one prep block (decision, SPME tiles, cells of a rebuild), then the build.
+// Plain path: the decision and cells by separate kernels (tiles are binned per bead).
+hipError_t launch_nlist(qhp_ctx* c, bool from_step) {
+  NlArgs A = nl_args(c);
+  if (c->p.exec != QHP_PLAIN) {
+    PrepArgs B;
+    B.nl = A;
+    B.ntiles = c->ntiles; B.nt1 = c->K[1] / QHP_TB; B.nt2 = c->K[2] / QHP_TB;
+    B.K0 = c->K[0]; B.K1 = c->K[1]; B.K2 = c->K[2];
+    B.KoL0 = c->K[0] / c->p.box[0]; B.KoL1 = c->K[1] / c->p.box[1]; B.KoL2 = c->K[2] / c->p.box[2];
+    B.tile_of = c->tile_of; B.tile_start = c->tile_start; B.tile_atoms = c->tile_atoms;
+    hipLaunchKernelGGL(k_prep, 1, 1024, prep_lds_bytes(c), c->stream, B, from_step ? 0 : 1);
+    hipLaunchKernelGGL(k_nl_build, c->ncell, 256, 0, c->stream, A);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_nl_check, 1, 256, 0, c->stream, A, from_step ? 0 : 1);
   hipLaunchKernelGGL(k_nl_assign, (c->N + 255) / 256, 256, 0, c->stream, A);
   hipLaunchKernelGGL(k_nl_scan, 1, 256, 0, c->stream, A);
   hipLaunchKernelGGL(k_nl_scatter, (c->N + 255) / 256, 256, 0, c->stream, A);
-  hipLaunchKernelGGL(k_nl_sort, (c->ncell + 3) / 4, 256, 0, c->stream, A);
   hipLaunchKernelGGL(k_nl_build, c->ncell, 256, 0, c->stream, A);
   return hipGetLastError();
 }

@@ -197,9 +197,7 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
     const int cnt = __popcll(bal);
     wave_sync();
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int t = s; t < cnt; t += S) {
-      const float4 cd = scd[wv][t];
-      const float4 oj = A.xf[sj[wv][t] + b];
+    auto interact = [&](const float4 cd, const float4 oj, const float2 lj) {
       const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
       const float r2 = dx * dx + dy * dy + dz * dz;
       if (r2 < rc2) {
@@ -213,7 +211,6 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
         const float erfcv = tt * q * ex;
         float sc = cd.w * ir2 * (erfcv * ir + c2a * ex);
         if (ENERGY) ec += (double)(cd.w * erfcv * ir);
-        const float2 lj = slj[wv][t];
         if (lj.x != 0.f) {
           const float s6 = lj.y * ir2 * ir2 * ir2;
           sc += lj.x * (12.f * s6 * s6 - 6.f * s6) * ir2;
@@ -221,7 +218,18 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
         }
         fx += sc * dx; fy += sc * dy; fz += sc * dz;
       }
+    };
+    // four neighbours per lane per iteration: their loads are all issued before the math
+    int t = s;
+    for (; t + 3 * S < cnt; t += 4 * S) {
+      const float4 o0 = A.xf[sj[wv][t] + b], o1 = A.xf[sj[wv][t + S] + b];
+      const float4 o2 = A.xf[sj[wv][t + 2 * S] + b], o3 = A.xf[sj[wv][t + 3 * S] + b];
+      interact(scd[wv][t], o0, slj[wv][t]);
+      interact(scd[wv][t + S], o1, slj[wv][t + S]);
+      interact(scd[wv][t + 2 * S], o2, slj[wv][t + 2 * S]);
+      interact(scd[wv][t + 3 * S], o3, slj[wv][t + 3 * S]);
     }
+    for (; t < cnt; t += S) interact(scd[wv][t], A.xf[sj[wv][t] + b], slj[wv][t]);
     gx += (double)fx; gy += (double)fy; gz += (double)fz;
     wave_sync();
   }

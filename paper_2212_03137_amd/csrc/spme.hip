@@ -94,6 +94,7 @@ __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
     double f0 = 0, f1 = 0, f2 = 0;
     for (int t0 = 0; t0 < ORDER; ++t0) {
       const int k0 = wrapk(i0[0] - t0, A.K0);
+#pragma unroll
       for (int t1 = 0; t1 < ORDER; ++t1) {
         const int k1 = wrapk(i0[1] - t1, A.K1);
         const double* row = A.grid + ((size_t)(k0 * A.K1 + k1) * A.K2) * A.Pc2 + b;
@@ -543,9 +544,11 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead) {
     for (int d = 0; d < 3; ++d) { T.L[d] = c->p.box[d]; T.KoL[d] = c->K[d] / c->p.box[d]; }
     T.tile_of = c->tile_of; T.tile_count = c->tile_count; T.tile_fill = c->tile_fill;
     T.tile_start = c->tile_start; T.tile_atoms = c->tile_atoms; T.ntiles = c->ntiles;
-    hipLaunchKernelGGL(k_tile_bin, (N + 255) / 256, 256, 0, c->stream, T);
-    hipLaunchKernelGGL(k_tile_scan, 1, 256, 0, c->stream, T);
-    hipLaunchKernelGGL(k_tile_scatter, (N + 255) / 256, 256, 0, c->stream, T);
+    if (plain) {   // batched: the prep kernel of the neighbour-list stage has binned the atoms
+      hipLaunchKernelGGL(k_tile_bin, (N + 255) / 256, 256, 0, c->stream, T);
+      hipLaunchKernelGGL(k_tile_scan, 1, 256, 0, c->stream, T);
+      hipLaunchKernelGGL(k_tile_scatter, (N + 255) / 256, 256, 0, c->stream, T);
+    }
     TSpreadArgs S;
     S.N = N; S.P = P; S.K0 = c->K[0]; S.K1 = c->K[1]; S.K2 = c->K[2];
     S.nt1 = T.nt1; S.nt2 = T.nt2; S.Pc2 = 2 * pc;
