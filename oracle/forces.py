@@ -172,3 +172,41 @@ def evaluate(pos, s, r_list=None):
         E[b], g = bead_potential(pos[b], s, pairs)
         F[b] = -g
     return E, F
+
+
+def evaluate_fast(pos, s):
+    """The quickly varying part V_f of the potential (Sec. "Multi-timestep Methods", eq.
+    splitting_sf): O-H bonds and H-O-H angles of every bead. -> (E [P][7], grad [P][N][3]),
+    with the other terms' columns zero."""
+    P = pos.shape[0]
+    E = np.zeros((P, len(TERMS)))
+    G = np.zeros_like(pos)
+    for b in range(P):
+        e_b, e_a, G[b] = intramolecular(pos[b], s.box, s.bond_r0, s.bond_k, s.angle_theta0,
+                                        s.angle_k)
+        E[b, 0], E[b, 1] = e_b, e_a
+    return E, G
+
+
+def evaluate_slow(pos, s, r_list=None):
+    """The slowly varying part V_s = V - V_f: real-space Coulomb and LJ over the centroid
+    list, exclusion correction, self term and reciprocal sum, for every bead of ``pos``
+    (the contracted beads under ring-polymer contraction; their centroid is the full
+    polymer's). -> (E [P][7] with the bond and angle columns zero, grad [P][N][3])."""
+    if r_list is None:
+        r_list = s.cutoff + s.skin
+    pairs = pair_list(centroids_of(pos), s.box, r_list)
+    P = pos.shape[0]
+    E = np.zeros((P, len(TERMS)))
+    G = np.zeros_like(pos)
+    for b in range(P):
+        x = pos[b]
+        e_c, e_lj, g_rs = real_space(x, pairs, s.charge, s.types, s.lj_sigma, s.lj_epsilon,
+                                     s.box, s.ewald_alpha, s.cutoff, s.coulomb)
+        e_x, g_x = excluded_correction(x, s.charge, s.box, s.ewald_alpha, s.coulomb)
+        e_s = self_energy(s.charge, s.ewald_alpha, s.coulomb)
+        e_r, g_r = _spme.spme(x, s.charge, s.box, s.pme_grid, s.pme_order, s.ewald_alpha,
+                              s.coulomb)
+        E[b] = [0.0, 0.0, e_c, e_lj, e_x, e_s, e_r]
+        G[b] = g_rs + g_x + g_r
+    return E, G
