@@ -117,6 +117,16 @@ typedef struct qhp_params {
   int32_t qtb_classical;    /* adQTB test switch: Theta(omega) = kT (white-noise limit)  */
   int32_t nbr_capacity;     /* neighbours per atom kept; 0 = sized from density          */
   int32_t use_graph;        /* 1: replay each step as one captured HIP graph; 0: launch   */
+  /* Multiple time stepping with ring-polymer contraction (Sec. "Multi-timestep Methods"):
+   * V = V_f + V_s with V_f = O-H bonds + H-O-H angles on the P beads and V_s = every other
+   * term on P~ contracted beads, the samples at j/P~ of the trigonometric interpolant
+   * through the P~ lowest modes (the paper's contraction equation; for even P~ < P the
+   * last kept cosine mode enters with weight sqrt(2), so that band-limited polymers are
+   * reproduced exactly). BAOAB-RESPA: one outer step is Bs(n dt/2) [Bf(dt/2) A(dt/2)
+   * O(dt) A(dt/2) Bf(dt/2)]^n Bs(n dt/2) with n = respa_nalt. Both need exec =
+   * QHP_BATCHED and thermostat = QHP_TRPMD (else QHP_EUNSUPPORTED). */
+  int32_t rpc_beads;        /* P~: a power of two <= P; 0 = P (no contraction)          */
+  int32_t respa_nalt;       /* n: inner steps per outer step, 1..64; 0 = 1               */
 } qhp_params;
 
 typedef struct qhp_ctx qhp_ctx;
@@ -136,12 +146,14 @@ QHP_API int qhp_destroy(qhp_ctx* ctx);
  * -> `energy` [P][QHP_NTERMS] (nullable) and `forces` = -grad V [P][N][3] (nullable).
  * Builds the centroid neighbour list of these positions (Sec. "Massively Parallel
  * Implementation": neighbours are found on ring-polymer centroids and shared by all
- * beads). Does not touch the propagated state. */
+ * beads). The full potential on all P beads, whatever rpc_beads and respa_nalt are.
+ * Does not change the propagated state (a later step rebuilds the list if it must). */
 QHP_API int qhp_eval(qhp_ctx* ctx, const double* pos, double* energy, double* forces, int mem_kind);
 
 /* Set the propagated state from bead positions and bead velocities [P][N][3] and the
  * step counter (which indexes the noise streams). Computes the normal modes
- * Q = T^T x / sqrt(P), P_n = m T^T v / sqrt(P) and the forces of this state; for adQTB
+ * Q = T^T x / sqrt(P), P_n = m T^T v / sqrt(P) and the forces of this state (under
+ * RESPA / contraction: V_f on the beads and V_s on the contracted beads); for adQTB
  * `step` must be a multiple of N_seg, gamma is reset to gamma_0 and the coloured noise
  * of the current segment is generated. */
 QHP_API int qhp_set_state(qhp_ctx* ctx, const double* pos, const double* vel, int64_t step, int mem_kind);
@@ -154,7 +166,12 @@ QHP_API int qhp_get_state(qhp_ctx* ctx, double* pos, double* vel, int64_t* step,
  * segment are computed after the last step of every segment. `energy` (nullable)
  * receives the per-bead energies of the final state [P][QHP_NTERMS]. Returns QHP_ENOMEM
  * if the neighbour capacity was exceeded during the call (the state is then invalid),
- * QHP_ENONFINITE if the state became non-finite. */
+ * QHP_ENONFINITE if the state became non-finite.
+ * With respa_nalt = n > 1 or rpc_beads = P~ < P, `nsteps` counts outer steps of n inner
+ * steps each; the step counter (qhp_get_state, noise counter) counts inner steps. The
+ * energies are then: bond and angle columns on the P beads, the other columns on rows
+ * 0..P~-1 (the contracted beads) and zero below, so that the estimator of the contraction
+ * equation is sum(bond, angle)/P + sum(others)/P~. */
 QHP_API int qhp_step(qhp_ctx* ctx, int32_t nsteps, double* energy, int mem_kind);
 
 /* Kinetic energy sum_n P_n^2 / 2m and free ring-polymer spring energy

@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("qtb_gamma0", C.c_double), ("qtb_nseg", C.c_int32), ("qtb_adapt_rate", C.c_double),
         ("qtb_gamma_min_frac", C.c_double), ("qtb_classical", C.c_int32),
         ("nbr_capacity", C.c_int32), ("use_graph", C.c_int32),
+        ("rpc_beads", C.c_int32), ("respa_nalt", C.c_int32),
     ]
 
 
@@ -108,7 +109,7 @@ class Context:
                  pme_grid, pme_order, dt, kT, hbar, gamma_centroid=0.0, trpmd_c=2.0, seed=0,
                  precision=FP64, exec_mode=BATCHED, thermostat=TRPMD, qtb_gamma0=0.0,
                  qtb_nseg=1024, qtb_adapt_rate=0.0, qtb_gamma_min_frac=0.01, qtb_classical=False,
-                 nbr_capacity=0, use_graph=True, stream=None):
+                 nbr_capacity=0, use_graph=True, rpc_beads=0, respa_nalt=1, stream=None):
         self._lib = load()
         self.N, self.P = int(n_atoms), int(n_beads)
         self.n_types = len(lj_sigma)
@@ -139,6 +140,7 @@ class Context:
         p.qtb_gamma_min_frac, p.qtb_classical = qtb_gamma_min_frac, int(bool(qtb_classical))
         p.nbr_capacity = nbr_capacity
         p.use_graph = int(bool(use_graph))
+        p.rpc_beads, p.respa_nalt = int(rpc_beads), int(respa_nalt)
         self.params = p
         h = C.c_void_p()
         rc = self._lib.qhp_create(C.byref(p), C.c_void_p(stream) if stream else None, C.byref(h))

@@ -107,7 +107,7 @@ void free_all(qhp_ctx* c) {
                   c->Q, c->Pa, c->x, c->g, c->cent, c->cref, c->coff, c->cwrap, c->xf, c->ctrl,
                   c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
                   c->nnbr, c->bmax, c->grid, c->tile_nbr, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
-                  c->io_a, c->io_b, c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
+                  c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.d_tmass, c->qtb.d_inv_count,
                   c->qtb.tw2, c->qtb.tw4};
   for (void* p : ptrs)
@@ -136,6 +136,10 @@ int validate(const qhp_params* p, std::string& why) {
   if (p->n_atoms >= (1 << 26)) return bad("n_atoms must be < 2^26");
   if (p->n_beads < 1 || p->n_beads > 64) return bad("n_beads must be in 1..64");
   if (!pow2(p->n_beads)) { why = "n_beads must be a power of two"; return QHP_EUNSUPPORTED; }
+  if ((long long)p->n_atoms * p->n_beads > (1ll << 27)) {
+    why = "n_atoms * n_beads must be <= 2^27 (32-bit byte offsets of the bead arrays)";
+    return QHP_EUNSUPPORTED;
+  }
   if (!p->type || !p->mass || !p->charge || !p->lj_sigma || !p->lj_epsilon) return bad("null array");
   if (p->n_types < 1 || p->n_types > QHP_MAX_TYPES) return bad("n_types must be in 1..8");
   for (int d = 0; d < 3; ++d)
@@ -162,6 +166,17 @@ int validate(const qhp_params* p, std::string& why) {
   for (int i = 0; i < p->n_atoms; ++i) {
     if (p->type[i] < 0 || p->type[i] >= p->n_types) return bad("atom type out of range");
     if (!(p->mass[i] > 0) || !std::isfinite(p->charge[i])) return bad("masses > 0, finite charges");
+  }
+  if (p->rpc_beads < 0 || p->rpc_beads > p->n_beads || (p->rpc_beads > 0 && !pow2(p->rpc_beads)))
+    return bad("rpc_beads must be 0 or a power of two <= n_beads");
+  if (p->respa_nalt < 0 || p->respa_nalt > 64) return bad("respa_nalt must be in 0..64");
+  {
+    const int ps = p->rpc_beads > 0 ? p->rpc_beads : p->n_beads;
+    const int na = p->respa_nalt > 0 ? p->respa_nalt : 1;
+    if ((ps < p->n_beads || na > 1) && (p->exec != QHP_BATCHED || p->thermostat != QHP_TRPMD)) {
+      why = "ring-polymer contraction and RESPA need exec = QHP_BATCHED and thermostat = QHP_TRPMD";
+      return QHP_EUNSUPPORTED;
+    }
   }
   if (p->thermostat == QHP_ADQTB) {
     if (p->n_beads != 1) return bad("adQTB requires n_beads = 1");
@@ -265,8 +280,24 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   TRY(dalloc(&c->Q, NP3)); TRY(dalloc(&c->Pa, NP3)); TRY(dalloc(&c->x, NP3)); TRY(dalloc(&c->g, NP3));
   TRY(dalloc(&c->cent, N)); TRY(dalloc(&c->cref, N)); TRY(dalloc(&c->coff, N)); TRY(dalloc(&c->cwrap, N));
   TRY(dalloc(&c->xf, (size_t)N * P));
-  TRY(dalloc(&c->io_a, NP3)); TRY(dalloc(&c->io_b, NP3));
+  TRY(dalloc(&c->io_a, NP3)); TRY(dalloc(&c->io_b, NP3)); TRY(dalloc(&c->g_eval, NP3));
   TRY(dalloc(&c->energy, (size_t)P * QHP_NTERMS));
+  // ---- multiple time stepping / ring-polymer contraction ----
+  c->Ps = p->rpc_beads > 0 ? p->rpc_beads : P;
+  c->nalt = p->respa_nalt > 0 ? p->respa_nalt : 1;
+  c->respa = c->Ps < P || c->nalt > 1;
+  if (c->respa) {
+    const int Ps = c->Ps;
+    TRY(dalloc(&c->xs, (size_t)3 * N * Ps)); TRY(dalloc(&c->gs, (size_t)3 * N * Ps));
+    TRY(dalloc(&c->xfs, (size_t)N * Ps)); TRY(dalloc(&c->pa_tmp, NP3));
+    // C = T of Ps beads; for even Ps < P its alternating column carries the cosine mode of
+    // harmonic Ps/2 of the full polymer, whose samples at j/Ps are sqrt(2) (-1)^j Q
+    std::vector<double> Tc, wc;
+    normal_modes(Ps, 1.0 / p->kT, p->hbar, Tc, wc);
+    if (Ps % 2 == 0 && Ps < P)
+      for (int j = 0; j < Ps; ++j) Tc[j * Ps + Ps - 1] *= std::sqrt(2.0);
+    TRY(up(&c->Cs, Tc));
+  }
   TRY(hipMemset(c->energy, 0, (size_t)P * QHP_NTERMS * sizeof(double)));
   TRY(hipMemset(c->cref, 0, N * sizeof(double4)));
   TRY(hipMemset(c->coff, 0, N * sizeof(double4)));
@@ -406,6 +437,27 @@ extern "C" int qhp_destroy(qhp_ctx* c) {
   return QHP_OK;
 }
 
+BeadSet full_beads(qhp_ctx* c) {
+  return BeadSet{c->P, c->Pc, c->x, c->g, c->xf, c->energy, QHP_TERMS_ALL};
+}
+
+// V_f (bonds and angles) on the P beads: initialises c->g
+static int fast_forces(qhp_ctx* c, bool energy) {
+  BeadSet f{c->P, c->Pc, c->x, c->g, c->xf, c->energy, QHP_TERMS_BONDED};
+  QHP_HIP(c, launch_bonded(c, energy, -1, &f));
+  return QHP_OK;
+}
+
+// V_s (exclusion correction, real space, SPME) on the contracted beads: initialises c->gs
+static int slow_forces(qhp_ctx* c, bool energy, bool from_step) {
+  QHP_HIP(c, launch_nlist(c, from_step));
+  BeadSet sl{c->Ps, c->Ps == 1 ? 1 : c->Ps / 2, c->xs, c->gs, c->xfs, c->energy, QHP_TERMS_EXCL};
+  QHP_HIP(c, launch_bonded(c, energy, -1, &sl));
+  QHP_HIP(c, launch_pair(c, energy, -1, &sl));
+  QHP_HIP(c, launch_spme(c, energy, -1, &sl));
+  return QHP_OK;
+}
+
 // Bonded + exclusion (initialise grad V), centroid pair list, real space, SPME.
 int forces_all(qhp_ctx* c, bool energy, bool from_step) {
   QHP_HIP(c, launch_nlist(c, from_step));
@@ -468,15 +520,18 @@ extern "C" int qhp_eval(qhp_ctx* c, const double* pos, double* energy, double* f
   int r = copy_in(c, pos, mem_kind, c->x);
   if (r) return r;
   QHP_HIP(c, launch_centroid_of_beads(c));
-  // the pair kernel's FP32 path reads the wrapped centroids written by the build
-  if ((r = forces_all(c, energy != nullptr, false))) return r;
+  // the gradient goes to scratch: c->g holds the propagated state's forces
+  std::swap(c->g, c->g_eval);
+  r = forces_all(c, energy != nullptr, false);
+  std::swap(c->g, c->g_eval);
+  if (r) return r;
   if (forces) {
     const size_t n = (size_t)c->P * c->N * 3;
     if (mem_kind == QHP_MEM_HOST) {
-      QHP_HIP(c, launch_transpose_out(c, c->g, c->io_a, -1.0));
+      QHP_HIP(c, launch_transpose_out(c, c->g_eval, c->io_a, -1.0));
       QHP_HIP(c, hipMemcpyAsync(forces, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     } else {
-      QHP_HIP(c, launch_transpose_out(c, c->g, forces, -1.0));
+      QHP_HIP(c, launch_transpose_out(c, c->g_eval, forces, -1.0));
     }
   }
   if ((r = copy_out_energy(c, energy, mem_kind))) return r;
@@ -500,9 +555,18 @@ extern "C" int qhp_set_state(qhp_ctx* c, const double* pos, const double* vel, i
   // bead positions in the context's layout for the first force evaluation
   r = copy_in(c, pos, mem_kind, c->x);
   if (r) return r;
-  QHP_HIP(c, launch_centroid_of_beads(c));
-  if ((r = forces_all(c, false, false))) return r;
-  QHP_HIP(c, launch_kick_back(c));          // store Pa = P - (dt/2) f
+  if (c->respa) {
+    // V_f on the beads, V_s on the contracted beads; Pa = P - (dt/2) f_f - (n dt/2) f_s
+    QHP_HIP(c, launch_contract(c));
+    if ((r = fast_forces(c, false))) return r;
+    if ((r = slow_forces(c, false, false))) return r;
+    QHP_HIP(c, launch_kick_back(c));
+    QHP_HIP(c, launch_kick_slow(c, c->Pa, c->Pa, -0.5 * c->nalt * c->p.dt));
+  } else {
+    QHP_HIP(c, launch_centroid_of_beads(c));
+    if ((r = forces_all(c, false, false))) return r;
+    QHP_HIP(c, launch_kick_back(c));          // store Pa = P - (dt/2) f
+  }
   c->step = step;
   {
     long long st = step;
@@ -523,25 +587,43 @@ extern "C" int qhp_get_state(qhp_ctx* c, double* pos, double* vel, int64_t* step
   if (step) *step = c->step;
   if (!pos && !vel) return QHP_OK;
   const size_t n = (size_t)c->P * c->N * 3;
+  const double* pa = c->Pa;
+  if (c->respa) {          // momenta with the pending slow kick (n dt/2) f_s
+    QHP_HIP(c, launch_kick_slow(c, c->pa_tmp, c->Pa, 0.5 * c->nalt * c->p.dt));
+    pa = c->pa_tmp;
+  }
   if (mem_kind == QHP_MEM_HOST) {
-    QHP_HIP(c, launch_state_out(c, pos ? c->io_a : nullptr, vel ? c->io_b : nullptr));
+    QHP_HIP(c, launch_state_out(c, pos ? c->io_a : nullptr, vel ? c->io_b : nullptr, pa));
     if (pos) QHP_HIP(c, hipMemcpyAsync(pos, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (vel) QHP_HIP(c, hipMemcpyAsync(vel, c->io_b, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     QHP_HIP(c, hipStreamSynchronize(c->stream));
   } else {
-    QHP_HIP(c, launch_state_out(c, pos, vel));
+    QHP_HIP(c, launch_state_out(c, pos, vel, pa));
   }
   return QHP_OK;
 }
 
 // One propagation step: B A O A (normal modes), then bonded, list check/rebuild, pairs
-// and SPME at the new beads.
+// and SPME at the new beads. Under RESPA / contraction one outer step: n inner steps
+// (kick with dt f_f, plus n dt f_s in the first; A O A; V_f at the new beads), then V_s
+// at the contracted beads of the last.
 static int one_step(qhp_ctx* c, bool energy) {
   hipEvent_t ev = nullptr;
-  prof_begin(c, QHP_PROF_NM, &ev);
-  QHP_HIP(c, launch_nm_step(c));
-  prof_end(c, QHP_PROF_NM, ev);
-  return forces_all(c, energy, true);
+  if (!c->respa) {
+    prof_begin(c, QHP_PROF_NM, &ev);
+    QHP_HIP(c, launch_nm_step(c, 0, 0.0, true));
+    prof_end(c, QHP_PROF_NM, ev);
+    return forces_all(c, energy, true);
+  }
+  for (int k = 0; k < c->nalt; ++k) {
+    const bool last = k == c->nalt - 1;
+    prof_begin(c, QHP_PROF_NM, &ev);
+    QHP_HIP(c, launch_nm_step(c, k, k == 0 ? c->nalt * c->p.dt : 0.0, last));
+    prof_end(c, QHP_PROF_NM, ev);
+    int r = fast_forces(c, energy && last);
+    if (r) return r;
+  }
+  return slow_forces(c, energy, true);
 }
 
 // Capture one step (without energies) as a HIP graph on the context's stream.
@@ -579,7 +661,7 @@ extern "C" int qhp_step(qhp_ctx* c, int32_t nsteps, double* energy, int mem_kind
       int r = one_step(c, want_e);
       if (r) return r;
     }
-    c->step += 1;
+    c->step += c->nalt;
     if (qtb && c->step % c->qtb.nseg == 0) {
       QHP_HIP(c, launch_qtb_adapt(c));
       QHP_HIP(c, launch_qtb_generate(c, c->step / c->qtb.nseg));
@@ -594,7 +676,12 @@ extern "C" int qhp_mode_energies(qhp_ctx* c, double* kinetic, double* spring) {
   if (!c || !kinetic || !spring) return QHP_EINVAL;
   if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
   QHP_HIP(c, launch_zero(c, c->io_a, 2 * sizeof(double)));
-  QHP_HIP(c, launch_mode_energies(c, c->io_a));
+  const double* pa = c->Pa;
+  if (c->respa) {
+    QHP_HIP(c, launch_kick_slow(c, c->pa_tmp, c->Pa, 0.5 * c->nalt * c->p.dt));
+    pa = c->pa_tmp;
+  }
+  QHP_HIP(c, launch_mode_energies(c, c->io_a, pa));
   double h[2];
   QHP_HIP(c, hipMemcpyAsync(h, c->io_a, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   QHP_HIP(c, hipStreamSynchronize(c->stream));

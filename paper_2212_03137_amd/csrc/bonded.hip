@@ -2,7 +2,9 @@
 // involve other molecules: harmonic O-H bonds, harmonic H-O-H angle, and removal of the
 // screened interaction of the three excluded intramolecular pairs,
 // -C q_a q_b erf(alpha r) / r, that the reciprocal sum contains. This kernel *initialises*
-// grad V of every bead; the pair and SPME kernels add to it.
+// grad V of every bead of its bead set; the pair and SPME kernels add to it. Under
+// multiple time stepping the bonds and angles (V_f) and the exclusion correction (with
+// the rest of V_s) run on different bead sets: TERMS selects which.
 // Lane (w, b): water w at bead b; 256 / P waters per block.
 #include "qhp_internal.h"
 
@@ -32,7 +34,7 @@ QHP_DEV void reduce_energy_by_bead(double* sred, int tid, double v, double* dst)
   __syncthreads();
 }
 
-template <int P, bool ENERGY>
+template <int P, bool ENERGY, int TERMS>
 __global__ __launch_bounds__(NT) void k_bonded(BondArgs A) {
   constexpr int AT = NT / P;
   __shared__ double sred[NT];
@@ -48,6 +50,7 @@ __global__ __launch_bounds__(NT) void k_bonded(BondArgs A) {
         G[k][d] = 0.0;
       }
     double u[2][3], r[2];
+    if (TERMS & QHP_TERMS_BONDED) {
     for (int h = 0; h < 2; ++h) {
       double dd[3];
       for (int d = 0; d < 3; ++d) {
@@ -77,6 +80,8 @@ __global__ __launch_bounds__(NT) void k_bonded(BondArgs A) {
       G[2][d] += g2;
       G[0][d] -= g1 + g2;
     }
+    }
+    if (TERMS & QHP_TERMS_EXCL) {
     const double c2a = 2.0 * A.alpha / sqrt(M_PI);
     const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
     for (int e = 0; e < 3; ++e) {
@@ -97,19 +102,22 @@ __global__ __launch_bounds__(NT) void k_bonded(BondArgs A) {
         G[pa[e]][d] -= s * dd[d];
       }
     }
+    }
     for (int k = 0; k < 3; ++k)
       for (int d = 0; d < 3; ++d) A.g[(d * N + 3 * w + k) * P + b] = G[k][d];
   }
-  if (ENERGY) {
+  if (ENERGY && (TERMS & QHP_TERMS_BONDED)) {
     reduce_energy_by_bead<P>(sred, tid, eb, A.energy + QHP_E_BOND);
     reduce_energy_by_bead<P>(sred, tid, ea, A.energy + QHP_E_ANGLE);
-    reduce_energy_by_bead<P>(sred, tid, ex, A.energy + QHP_E_COUL_EXCL);
   }
+  if (ENERGY && (TERMS & QHP_TERMS_EXCL)) reduce_energy_by_bead<P>(sred, tid, ex, A.energy + QHP_E_COUL_EXCL);
 }
 
-__global__ void k_energy_init(double* energy, int P, double self) {
+// zero [rows][NTERMS] and put the self term on the first self_rows rows
+__global__ void k_energy_init(double* energy, int rows, int self_rows, double self) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < P * QHP_NTERMS) energy[i] = (i % QHP_NTERMS == QHP_E_COUL_SELF) ? self : 0.0;
+  if (i < rows * QHP_NTERMS)
+    energy[i] = (i % QHP_NTERMS == QHP_E_COUL_SELF && i / QHP_NTERMS < self_rows) ? self : 0.0;
 }
 
 __global__ void k_zero(double* p, size_t n) {
@@ -132,24 +140,37 @@ __global__ void k_zero(double* p, size_t n) {
     default: return hipErrorInvalidValue;              \
   }
 
-hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead) {
+hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   BondArgs A;
   const int N = c->N;
   const bool plain = bead >= 0;
+  const BeadSet B = bs ? *bs : full_beads(c);
   A.N = N; A.NW = c->NW;
-  A.x = plain ? c->x + (size_t)bead * 3 * N : c->x;
-  A.g = plain ? c->g + (size_t)bead * 3 * N : c->g;
+  A.x = plain ? c->x + (size_t)bead * 3 * N : B.x;
+  A.g = plain ? c->g + (size_t)bead * 3 * N : B.g;
   A.charge = c->d_charge;
   for (int d = 0; d < 3; ++d) { A.L[d] = c->p.box[d]; A.invL[d] = 1.0 / c->p.box[d]; }
   A.r0 = c->p.bond_r0; A.kb = c->p.bond_k; A.th0 = c->p.angle_theta0; A.kth = c->p.angle_k;
   A.alpha = c->p.ewald_alpha; A.coulomb = c->p.coulomb;
-  A.energy = c->energy + (plain ? (size_t)bead * QHP_NTERMS : 0);
-  const int P = plain ? 1 : c->P;
-  if (energy && bead <= 0)
-    hipLaunchKernelGGL(k_energy_init, 1, 512, 0, c->stream, c->energy, c->P, c->self_energy);
+  A.energy = (plain ? c->energy : B.energy) + (plain ? (size_t)bead * QHP_NTERMS : 0);
+  const int P = plain ? 1 : B.P;
+  const int terms = plain ? QHP_TERMS_ALL : B.terms;
+  // the launch that carries the bonds initialises the energy rows of the whole step; under
+  // contraction the self term belongs to the contracted beads only
+  if (energy && bead <= 0 && (terms & QHP_TERMS_BONDED)) {
+    const int rows = plain ? c->P : B.P;
+    const int self_rows = terms == QHP_TERMS_ALL ? rows : c->Ps;
+    hipLaunchKernelGGL(k_energy_init, (rows * QHP_NTERMS + 511) / 512, 512, 0, c->stream,
+                       plain ? c->energy : B.energy, rows, self_rows, c->self_energy);
+  }
   const unsigned nb = (unsigned)((c->NW + NT / P - 1) / (NT / P));
-  QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_bonded<PP, true>), nb, NT, 0, c->stream, A);
-               else hipLaunchKernelGGL((k_bonded<PP, false>), nb, NT, 0, c->stream, A));
+#define BONDED_CALL(TT)                                                                           \
+  QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_bonded<PP, true, TT>), nb, NT, 0, c->stream, A); \
+               else hipLaunchKernelGGL((k_bonded<PP, false, TT>), nb, NT, 0, c->stream, A))
+  if (terms == QHP_TERMS_BONDED) { BONDED_CALL(QHP_TERMS_BONDED); }
+  else if (terms == QHP_TERMS_EXCL) { BONDED_CALL(QHP_TERMS_EXCL); }
+  else { BONDED_CALL(QHP_TERMS_ALL); }
+#undef BONDED_CALL
   return hipGetLastError();
 }
 

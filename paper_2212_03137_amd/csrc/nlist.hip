@@ -26,6 +26,7 @@ constexpr int MAXC = 512;         // atoms of one cell handled by one block
 
 struct NlArgs {
   int N, cap, ncell, nc0, nc1, nc2, nst;
+  int nadv;                   // steps a propagation advances (inner steps of one outer step)
   double L0, L1, L2, iL0, iL1, iL2, rl2, skin;
   const double4* cent; double4* cref; double4* coff; double4* cwrap;
   int* cell_of; int* cell_count; int* cell_fill; int* cell_start; int* cell_atoms;
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(256) void k_nl_check(NlArgs A, int force) {
     const int b = force || c->force_build || !(2.0 * (dc + db) <= A.skin);
     c->do_build = b;
     c->force_build = 0;
-    if (!force) c->step += 1;       // a propagation step's forces: the step is done
+    if (!force) c->step += A.nadv;  // a propagation step's forces: the step is done
     c->spread_m = (int)sm[2][0];
     c->max_db = db;
     if (sm[3][0] != 0.0) c->spread_margin = 1;
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
     const int b = force || c->force_build || !(2.0 * (dc + db) <= A.skin);
     c->do_build = b;
     c->force_build = 0;
-    if (!force) c->step += 1;       // a propagation step's forces: the step is done
+    if (!force) c->step += A.nadv;  // a propagation step's forces: the step is done
     c->spread_m = (int)sm[2][0];
     c->max_db = db;
     if (sm[3][0] != 0.0) c->spread_margin = 1;
@@ -334,6 +335,7 @@ static NlArgs nl_args(qhp_ctx* c) {
   A.cell_of = c->cell_of; A.cell_count = c->cell_count; A.cell_fill = c->cell_fill;
   A.cell_start = c->cell_start; A.cell_atoms = c->cell_atoms; A.stencil = c->stencil;
   A.nbr = c->nbr; A.nnbr = c->nnbr; A.ctrl = c->ctrl; A.bmax = c->bmax; A.n_bmax = c->n_bmax;
+  A.nadv = c->nalt;
   return A;
 }
 

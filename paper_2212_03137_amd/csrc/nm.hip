@@ -5,7 +5,8 @@
 //
 // Lane layout: a 256-thread block holds 256/P atoms; lane (a, n) owns mode n of atom a
 // for x, y and z. The bead-axis contractions (T^T g and T Q, both P x P) go through LDS:
-// at P = 32 they are 2 x 32 x 32 FMAs per lane and the kernel stays bound by HBM.
+// at P = 32 they are 2 x 3 x 32 FMAs per lane, fed by paired (16-byte) LDS reads, and the
+// kernel stays bound by HBM.
 //
 // Persistent state between steps: Q, Pa (momenta after the A-O-A of the last step, i.e.
 // before its final half kick) and g = grad V at the current beads. A step therefore
@@ -32,6 +33,13 @@ struct NmArgs {
   uint64_t seed;
   // adQTB
   const double* noise; double* vrec; int nseg; double qc1, qosd;
+  // multiple time stepping / ring-polymer contraction
+  const double* gs;        // [3][N][Ps] grad V_s at the contracted beads
+  const double* Cs;        // [Ps][Ps] contraction matrix C[j][n]
+  double* xs;              // [3][N][Ps] contracted beads (written when emit)
+  float4* xfs;             // [N][Ps]
+  int Ps, step_off, emit;
+  double slow_h;           // factor of the slow kick this inner step (0: none)
 };
 
 template <int P, bool BEADMAJOR>
@@ -44,44 +52,90 @@ QHP_DEV double wave_max(double v) {
   return v;
 }
 
-// sum_i M[i * P + n] * v[i] over i = I0..P-1 with four independent partial sums
-template <int P, int I0 = 0>
-QHP_DEV double contract_col(const double* M, const double* v, int n) {
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  int i = I0;
+// out[d] = sum_i m_i v[d][i] for the three Cartesian rows v[d] of one atom, where m is the
+// lane's vector of matrix entries stored in pairs (m_2j, m_2j+1) at M2[j * P + n]. One paired
+// LDS read of m serves all three rows; the rows are read in pairs too, at the same address
+// for every lane of the atom (a broadcast).
+template <int P>
+QHP_DEV void contract3(const double2* M2, const double (*v)[P + 2], int n, double* out) {
+  if constexpr (P == 1) {
+    for (int d = 0; d < 3; ++d) out[d] = reinterpret_cast<const double*>(M2)[0] * v[d][0];
+  } else {
+    double s[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll 4
+    for (int j = 0; j < P / 2; ++j) {
+      const double2 t = M2[j * P + n];
 #pragma unroll
-  for (; i + 4 <= P; i += 4) {
-    s0 += M[(i + 0) * P + n] * v[i + 0];
-    s1 += M[(i + 1) * P + n] * v[i + 1];
-    s2 += M[(i + 2) * P + n] * v[i + 2];
-    s3 += M[(i + 3) * P + n] * v[i + 3];
+      for (int d = 0; d < 3; ++d) {
+        const double2 w = *reinterpret_cast<const double2*>(&v[d][2 * j]);
+        s[d][0] += t.x * w.x;
+        s[d][1] += t.y * w.y;
+      }
+    }
+    for (int d = 0; d < 3; ++d) out[d] = s[d][0] + s[d][1];
   }
-#pragma unroll
-  for (; i < P; ++i) s0 += M[i * P + n] * v[i];
-  return (s0 + s1) + (s2 + s3);
 }
 
-template <int P, bool QTB, bool BEADMAJOR, bool F32>
+// RESPA: the kick adds slow_h * f_s on the modes n < Ps (f_s = -C^T g_s / sqrt(Ps)), the
+// noise counter is the outer step's plus step_off, x is written for the bonded terms, and
+// only when emit are the contracted beads, their FP32 offsets, the centroids and the
+// block maxima (of the contracted beads) written.
+template <int P, bool QTB, bool BEADMAJOR, bool F32, bool RESPA = false>
 __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
   constexpr int AT = NT / P;
-  constexpr int PP = P + 1;          // padding: the atoms of a wavefront hit different banks
-  __shared__ double sT[P * P];       // T[i][n] at i * P + n
-  __shared__ double sTt[P * P];      // T[n][k] at k * P + n (lane-contiguous for x = T Q)
-  __shared__ double sh[AT][3][PP];
+  constexpr int PP = P + 2;          // row stride: 16-byte aligned rows; the atoms of a
+                                     // wavefront read different banks
+  constexpr int PH = P > 1 ? P / 2 : 1;
+  __shared__ double2 sTc[PH * P];    // (T[2j][n], T[2j+1][n]) at j * P + n: column n of T
+  __shared__ double2 sTr[PH * P];    // (T[n][2j], T[n][2j+1]) at j * P + n: row n, T[n][0] -> 0
+  __shared__ __align__(16) double sh[AT][3][PP];
+  __shared__ double sC[RESPA ? P * P : 1];       // C[j][n] at j * Ps + n
+  __shared__ double sgs[RESPA ? AT : 1][3][RESPA ? P : 1];
   const int tid = threadIdx.x;
   const int al = tid / P, n = tid % P;
   const int a = blockIdx.x * AT + al;
-  for (int k = tid; k < P * P; k += NT) sT[k] = A.T[k];
-  for (int k = tid; k < P * P; k += NT) sTt[(k % P) * P + k / P] = A.T[k];
+  const int Ps = RESPA ? A.Ps : P;
+  if (RESPA) {
+    for (int k = tid; k < Ps * Ps; k += NT) sC[k] = A.Cs[k];
+    if (A.slow_h != 0.0)
+      for (int d = 0; d < 3; ++d)
+        sgs[al][d][n] = (a < A.N && n < Ps) ? A.gs[(d * A.N + a) * Ps + n] : 0.0;
+  }
+  for (int k = tid; k < PH * P; k += NT) {
+    const int j = k / P, m = k % P;
+    if (P == 1) {
+      sTc[0] = make_double2(A.T[0], 0.0);
+      sTr[0] = make_double2(0.0, 0.0);
+    } else {
+      sTc[k] = make_double2(A.T[(2 * j) * P + m], A.T[(2 * j + 1) * P + m]);
+      sTr[k] = make_double2(j == 0 ? 0.0 : A.T[m * P + 2 * j], A.T[m * P + 2 * j + 1]);
+    }
+  }
   const bool live = a < A.N;
-  const uint64_t step = (uint64_t)A.ctrl->step;       // advanced by the list check
-  double gv[3] = {0, 0, 0};
+  // advanced by the list check (by the inner steps of an outer step under RESPA)
+  const uint64_t step = (uint64_t)A.ctrl->step + (RESPA ? (uint64_t)A.step_off : 0ull);
+  double gv[3] = {0, 0, 0}, q0[3] = {0, 0, 0}, p0[3] = {0, 0, 0};
   if (live)
-    for (int d = 0; d < 3; ++d) gv[d] = A.g[gidx<P, BEADMAJOR>(A.N, d, a, n)];
+    for (int d = 0; d < 3; ++d) {
+      const int gi = (d * A.N + a) * P + n;
+      gv[d] = A.g[gidx<P, BEADMAJOR>(A.N, d, a, n)];
+      q0[d] = A.Q[gi];
+      p0[d] = A.Pa[gi];
+    }
   for (int d = 0; d < 3; ++d) sh[al][d][n] = gv[d];
   __syncthreads();
-
+  double fT[3];
+  contract3<P>(sTc, sh[al], n, fT);
   const double rsP = 1.0 / sqrt((double)P);
+  double fsl[3] = {0.0, 0.0, 0.0};
+  if (RESPA && A.slow_h != 0.0 && n < Ps) {
+    const double rsPs = 1.0 / sqrt((double)Ps);
+    for (int d = 0; d < 3; ++d) {
+      double acc = 0.0;
+      for (int j = 0; j < Ps; ++j) acc += sC[j * Ps + n] * sgs[al][d][j];
+      fsl[d] = -acc * rsPs * A.slow_h;
+    }
+  }
   double q[3], p[3];
   double m = 1.0, cc = A.cc[n], csw = A.csw[n], cws = A.cws[n];
   int bad = 0;
@@ -91,10 +145,11 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
     double xi[3] = {0, 0, 0};
     if (!QTB) qhp::gauss3(A.seed, qhp::STREAM_RPMD_O, step, (uint64_t)a, (uint64_t)n, xi);
     for (int d = 0; d < 3; ++d) {
-      const double f = -contract_col<P>(sT, sh[al][d], n) * rsP;
+      const double f = -fT[d] * rsP;
       const int gi = (d * A.N + a) * P + n;
-      double pp = A.Pa[gi] + A.dt * f;
-      double qq = A.Q[gi];
+      double pp = p0[d] + A.dt * f;
+      if (RESPA) pp += fsl[d];
+      double qq = q0[d];
       // A(h): exact free ring-polymer evolution of mode n
       double q1 = cc * qq + csw * im * pp;
       double p1 = -m * cws * qq + cc * pp;
@@ -123,27 +178,49 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
   // beads from modes: lane index n now stands for bead i = n
   double db2 = 0, dc2 = 0;
   int moff = 0, mbad = 0;
+  const bool emit = !RESPA || A.emit;
   if (live) {
     const double sP = sqrt((double)P);
-    double xb[3], c[3];
+    double xb[3], c[3], sx[3];
+    // x_n = Q_0 + sqrt(P) sum_{k>=1} T[n][k] Q_k (the k = 0 term enters as Q_0 itself)
+    contract3<P>(sTr, sh[al], n, sx);
     for (int d = 0; d < 3; ++d) {
-      // x_n = Q_0 + sqrt(P) sum_{k>=1} T[n][k] Q_k (the k = 0 term enters as Q_0 itself)
-      const double s = contract_col<P, 1>(sTt, sh[al][d], n);
+      const double s = sx[d];
       c[d] = sh[al][d][0];
       xb[d] = c[d] + sP * s;
       A.x[gidx<P, BEADMAJOR>(A.N, d, a, n)] = xb[d];
       if (!isfinite(xb[d])) bad = 1;
     }
-    const double dx = xb[0] - c[0], dy = xb[1] - c[1], dz = xb[2] - c[2];
-    db2 = dx * dx + dy * dy + dz * dz;
-    for (int d = 0; d < 3; ++d) {
-      const int dl = qhp::base_diff(qhp::base_of(xb[d], A.KoL[d], A.K[d]),
-                                    qhp::base_of(c[d], A.KoL[d], A.K[d]), A.K[d]);
-      moff = max(moff, dl < 0 ? -dl : dl);
-      if (dl > QHP_TB || dl < A.order - 1 - QHP_TB) mbad = 1;
+    // the bead set of the slow forces: the beads themselves, or (RESPA) lanes j < Ps hold
+    // the contracted beads x~_j = Q_0 + sqrt(Ps) sum_{k=1}^{Ps-1} C[j][k] Q_k
+    bool own = emit;
+    if (RESPA && emit) {
+      own = n < Ps;
+      if (own) {
+        const double sPs = sqrt((double)Ps);
+        for (int d = 0; d < 3; ++d) {
+          double acc = 0.0;
+          for (int k = 1; k < Ps; ++k) acc += sC[n * Ps + k] * sh[al][d][k];
+          xb[d] = c[d] + sPs * acc;
+          A.xs[(d * A.N + a) * Ps + n] = xb[d];
+          if (!isfinite(xb[d])) bad = 1;
+        }
+      }
     }
-    if (F32) A.xf[a * P + n] = make_float4((float)dx, (float)dy, (float)dz, (float)A.charge[a]);
-    if (n == 0) {
+    if (own) {
+      const double dx = xb[0] - c[0], dy = xb[1] - c[1], dz = xb[2] - c[2];
+      db2 = dx * dx + dy * dy + dz * dz;
+      for (int d = 0; d < 3; ++d) {
+        const int dl = qhp::base_diff(qhp::base_of(xb[d], A.KoL[d], A.K[d]),
+                                      qhp::base_of(c[d], A.KoL[d], A.K[d]), A.K[d]);
+        moff = max(moff, dl < 0 ? -dl : dl);
+        if (dl > QHP_TB || dl < A.order - 1 - QHP_TB) mbad = 1;
+      }
+      const float4 o4 = make_float4((float)dx, (float)dy, (float)dz, (float)A.charge[a]);
+      if (F32 && !RESPA) A.xf[a * P + n] = o4;
+      if (F32 && RESPA) A.xfs[a * Ps + n] = o4;
+    }
+    if (emit && n == 0) {
       A.cent[a] = make_double4(c[0], c[1], c[2], 0.0);
       const double4 o = A.coff[a];
       A.cwrap[a] = make_double4(c[0] - o.x, c[1] - o.y, c[2] - o.z, 0.0);
@@ -151,6 +228,10 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
       const double ex = c[0] - r.x, ey = c[1] - r.y, ez = c[2] - r.z;
       dc2 = ex * ex + ey * ey + ez * ez;
     }
+  }
+  if (!emit) {                       // an inner step without slow forces after it
+    if (bad) A.ctrl->nonfinite = 1;
+    return;
   }
   // block maxima for the neighbour-list check and the SPME tile margin (no atomics)
   __shared__ double sm[4][NT / 64];
@@ -289,6 +370,30 @@ __global__ __launch_bounds__(NT) void k_mode_energy(int N, const double* Q, cons
   if ((tid & 63) == 0) { atomicAdd(out, ek); atomicAdd(out + 1, es); }
 }
 
+// dst = src + s * f_s on the modes n < Ps, f_s = -(1/sqrt(Ps)) sum_j C[j][n] g_s(j) (the slow
+// forces of ring-polymer contraction); the other modes are copied.
+template <int P>
+__global__ __launch_bounds__(NT) void k_kick_slow(int N, int Ps, double* dst, const double* src,
+                                                  const double* gs, const double* C, double s) {
+  constexpr int AT = NT / P;
+  __shared__ double sC[P * P];
+  __shared__ double sg[AT][3][P];
+  const int tid = threadIdx.x, al = tid / P, n = tid % P, a = blockIdx.x * AT + al;
+  for (int k = tid; k < Ps * Ps; k += NT) sC[k] = C[k];
+  const bool live = a < N;
+  for (int d = 0; d < 3; ++d) sg[al][d][n] = (live && n < Ps) ? gs[(d * N + a) * Ps + n] : 0.0;
+  __syncthreads();
+  if (!live) return;
+  const double rsPs = 1.0 / sqrt((double)Ps);
+  for (int d = 0; d < 3; ++d) {
+    double f = 0.0;
+    if (n < Ps)
+      for (int j = 0; j < Ps; ++j) f += sC[j * Ps + n] * sg[al][d][j];
+    const int i = (d * N + a) * P + n;
+    dst[i] = src[i] + s * (-f * rsPs);
+  }
+}
+
 // centroid of given beads (bead-innermost or bead-major x): beads summed in order, / P;
 // also the block maxima of the bead-centroid distance and grid-base offset
 struct CentArgs {
@@ -337,6 +442,54 @@ __global__ __launch_bounds__(128) void k_centroid_beads(CentArgs A) {
                                       fmax(sm[2][0], sm[2][1]));
 }
 
+// Contracted beads of the state (modes A.x = Q): x~_j = Q_0 + sqrt(Ps) sum_{k>=1} C[j][k] Q_k,
+// their FP32 offsets, the centroids Q_0 and the block maxima of the contracted beads (the
+// same bookkeeping as the emitting step of the normal-mode kernel).
+template <int P>
+__global__ __launch_bounds__(NT) void k_contract(CentArgs A, int Ps, const double* C, double* xs) {
+  constexpr int AT = NT / P;
+  __shared__ double sC[P * P];
+  __shared__ double sq[AT][3][P];
+  __shared__ double sm[3][NT / 64];
+  const int tid = threadIdx.x, al = tid / P, n = tid % P, a = blockIdx.x * AT + al;
+  for (int k = tid; k < Ps * Ps; k += NT) sC[k] = C[k];
+  const bool live = a < A.N;
+  for (int d = 0; d < 3; ++d) sq[al][d][n] = live ? A.x[(d * A.N + a) * P + n] : 0.0;
+  __syncthreads();
+  double db2 = 0;
+  int moff = 0, mbad = 0;
+  if (live && n < Ps) {
+    const double sPs = sqrt((double)Ps);
+    double xb[3], c[3];
+    for (int d = 0; d < 3; ++d) {
+      double acc = 0.0;
+      for (int k = 1; k < Ps; ++k) acc += sC[n * Ps + k] * sq[al][d][k];
+      c[d] = sq[al][d][0];
+      xb[d] = c[d] + sPs * acc;
+      xs[(d * A.N + a) * Ps + n] = xb[d];
+    }
+    const double dx = xb[0] - c[0], dy = xb[1] - c[1], dz = xb[2] - c[2];
+    db2 = dx * dx + dy * dy + dz * dz;
+    if (A.xf) A.xf[a * Ps + n] = make_float4((float)dx, (float)dy, (float)dz, (float)A.charge[a]);
+    for (int d = 0; d < 3; ++d) {
+      const int dl = qhp::base_diff(qhp::base_of(xb[d], A.KoL[d], A.K[d]),
+                                    qhp::base_of(c[d], A.KoL[d], A.K[d]), A.K[d]);
+      moff = max(moff, dl < 0 ? -dl : dl);
+      if (dl > QHP_TB || dl < A.order - 1 - QHP_TB) mbad = 1;
+    }
+    if (n == 0) A.cent[a] = make_double4(c[0], c[1], c[2], 0.0);
+  }
+  db2 = wave_max(db2);
+  const double mo = wave_max((double)moff), mb = wave_max((double)mbad);
+  if ((tid & 63) == 0) { sm[0][tid >> 6] = db2; sm[1][tid >> 6] = mo; sm[2][tid >> 6] = mb; }
+  __syncthreads();
+  if (tid == 0) {
+    double b0 = sm[0][0], b1 = sm[1][0], b2 = sm[2][0];
+    for (int w = 1; w < NT / 64; ++w) { b0 = fmax(b0, sm[0][w]); b1 = fmax(b1, sm[1][w]); b2 = fmax(b2, sm[2][w]); }
+    A.bmax[blockIdx.x] = make_double4(0.0, b0, b1, b2);
+  }
+}
+
 // boundary [P][N][3] <-> internal layout
 template <bool BEADMAJOR>
 __global__ void k_transpose_in(int N, int P, const double* src, double* dst) {
@@ -372,7 +525,7 @@ __global__ void k_transpose_out(int N, int P, const double* src, double* dst, do
 
 static inline unsigned nblocks_atoms(int N, int P) { return (unsigned)((N + (NT / P) - 1) / (NT / P)); }
 
-hipError_t launch_nm_step(qhp_ctx* c) {
+hipError_t launch_nm_step(qhp_ctx* c, int inner, double slow_h, bool emit) {
   NmArgs A;
   A.N = c->N; A.Q = c->Q; A.Pa = c->Pa; A.x = c->x; A.g = c->g; A.T = c->T;
   A.cc = c->mode_c; A.csw = c->mode_s_w; A.cws = c->mode_ws; A.c1 = c->mode_c1; A.c2 = c->mode_c2;
@@ -385,10 +538,18 @@ hipError_t launch_nm_step(qhp_ctx* c) {
   A.noise = c->qtb.noise; A.vrec = c->qtb.vrec;
   A.nseg = qtb ? c->qtb.nseg : 1;
   A.qc1 = c->qtb.c1; A.qosd = c->qtb.osd;
+  A.gs = c->gs; A.Cs = c->Cs; A.xs = c->xs; A.xfs = c->xfs; A.Ps = c->Ps;
+  A.step_off = inner; A.emit = emit ? 1 : 0; A.slow_h = slow_h;
   const bool bm = c->p.exec == QHP_PLAIN;
   const bool f32 = c->p.precision == QHP_FP32_PAIRS && !bm;
   const unsigned nb = nblocks_atoms(c->N, c->P);
   c->n_bmax = (int)nb;
+  if (c->respa) {
+    if (bm || qtb) return hipErrorInvalidValue;
+    QHP_SWITCH_P(c->P, if (f32) hipLaunchKernelGGL((k_nm_step<PP, false, false, true, true>), nb, NT, 0, c->stream, A);
+                       else hipLaunchKernelGGL((k_nm_step<PP, false, false, false, true>), nb, NT, 0, c->stream, A));
+    return hipGetLastError();
+  }
   if (qtb) {
     if (c->P != 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_nm_step<1, true, false, false>), nb, NT, 0, c->stream, A);
@@ -421,26 +582,46 @@ hipError_t launch_kick_back(qhp_ctx* c) {
   return hipGetLastError();
 }
 
-hipError_t launch_state_out(qhp_ctx* c, double* xo, double* vo) {
+hipError_t launch_state_out(qhp_ctx* c, double* xo, double* vo, const double* pa) {
   const unsigned nb = nblocks_atoms(c->N, c->P);
   const bool bm = c->p.exec == QHP_PLAIN;
   const double h = 0.5 * c->p.dt;
   QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_state_out<PP, true>), nb, NT, 0, c->stream,
-                                                 c->N, c->Q, c->Pa, c->g, c->T, c->d_mass, h, xo, vo);
+                                                 c->N, c->Q, pa, c->g, c->T, c->d_mass, h, xo, vo);
                else hipLaunchKernelGGL((k_state_out<PP, false>), nb, NT, 0, c->stream, c->N, c->Q,
-                                       c->Pa, c->g, c->T, c->d_mass, h, xo, vo));
+                                       pa, c->g, c->T, c->d_mass, h, xo, vo));
   return hipGetLastError();
 }
 
-hipError_t launch_mode_energies(qhp_ctx* c, double* out2) {
+hipError_t launch_mode_energies(qhp_ctx* c, double* out2, const double* pa) {
   const unsigned nb = nblocks_atoms(c->N, c->P);
   const bool bm = c->p.exec == QHP_PLAIN;
   const double h = 0.5 * c->p.dt;
   QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_mode_energy<PP, true>), nb, NT, 0, c->stream,
-                                                 c->N, c->Q, c->Pa, c->g, c->T, c->d_mass,
+                                                 c->N, c->Q, pa, c->g, c->T, c->d_mass,
                                                  c->mode_w2, h, out2);
                else hipLaunchKernelGGL((k_mode_energy<PP, false>), nb, NT, 0, c->stream, c->N,
-                                       c->Q, c->Pa, c->g, c->T, c->d_mass, c->mode_w2, h, out2));
+                                       c->Q, pa, c->g, c->T, c->d_mass, c->mode_w2, h, out2));
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_slow(qhp_ctx* c, double* dst, const double* src, double s) {
+  const unsigned nb = nblocks_atoms(c->N, c->P);
+  QHP_SWITCH_P(c->P, hipLaunchKernelGGL((k_kick_slow<PP>), nb, NT, 0, c->stream, c->N, c->Ps,
+                                        dst, src, c->gs, c->Cs, s));
+  return hipGetLastError();
+}
+
+hipError_t launch_contract(qhp_ctx* c) {
+  CentArgs A;
+  A.N = c->N; A.x = c->Q; A.cent = c->cent; A.charge = c->d_charge; A.bmax = c->bmax;
+  A.xf = c->p.precision == QHP_FP32_PAIRS ? c->xfs : nullptr;
+  for (int d = 0; d < 3; ++d) { A.K[d] = c->K[d]; A.KoL[d] = c->K[d] / c->p.box[d]; }
+  A.order = c->p.pme_order;
+  const unsigned nb = nblocks_atoms(c->N, c->P);
+  c->n_bmax = (int)nb;
+  QHP_SWITCH_P(c->P, hipLaunchKernelGGL((k_contract<PP>), nb, NT, 0, c->stream, A, c->Ps,
+                                        c->Cs, c->xs));
   return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ struct PairArgs {
   double lj_s6[QHP_MAX_TYPES * QHP_MAX_TYPES];
   double lj_e4[QHP_MAX_TYPES * QHP_MAX_TYPES];
   int ntypes;
+  int lj_any[QHP_MAX_TYPES];  // type t has a non-zero LJ epsilon with some type
   int nblocks;            // logical blocks
   const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
   double* energy;         // [P][NTERMS] (plain: the bead's row)
@@ -144,12 +145,55 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
   flush<P, ENERGY>(A, i, lane, gx, gy, gz, ec, elj);
 }
 
+// One chunk of compacted neighbours for the lane (slot s, bead b): neighbours s, s+S, ...
+// LJ = false when atom i's type has no LJ partner (a wavefront-uniform choice).
+template <int P, bool ENERGY, bool LJ>
+QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, const unsigned* sj,
+                   int cnt, int s, unsigned boff, float4 oi, float rc2, float alpha, float kexp,
+                   float c2a, float& fx, float& fy, float& fz, double& ec, double& elj) {
+  constexpr int S = 64 / P;
+  const char* xf = reinterpret_cast<const char*>(A.xf);
+  auto load = [&](int t) { return *reinterpret_cast<const float4*>(xf + (sj[t] + boff)); };
+  auto interact = [&](const float4 cd, const float4 oj, const float2 lj) {
+    const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < rc2) {
+      const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir;
+      const float x = alpha * (r2 * ir);
+      const float tt = __builtin_amdgcn_rcpf(1.0f + ERFC_P * x);
+      float q = ERFC_Q[7];
+#pragma unroll
+      for (int k = 6; k >= 0; --k) q = q * tt + ERFC_Q[k];
+      const float ex = __builtin_amdgcn_exp2f(kexp * r2);       // exp(-alpha^2 r^2)
+      const float erfcv = tt * q * ex;
+      float sc = cd.w * ir2 * (erfcv * ir + c2a * ex);
+      if (ENERGY) ec += (double)(cd.w * erfcv * ir);
+      if (LJ) {
+        const float s6 = lj.y * ir2 * ir2 * ir2;
+        sc += lj.x * (12.f * s6 * s6 - 6.f * s6) * ir2;
+        if (ENERGY) elj += (double)(lj.x * (s6 * s6 - s6));
+      }
+      fx += sc * dx; fy += sc * dy; fz += sc * dz;
+    }
+  };
+  // four neighbours per lane per iteration: their loads are all issued before the math
+  int t = s;
+  for (; t + 3 * S < cnt; t += 4 * S) {
+    const float4 o0 = load(t), o1 = load(t + S), o2 = load(t + 2 * S), o3 = load(t + 3 * S);
+    interact(scd[t], o0, slj[t]);
+    interact(scd[t + S], o1, slj[t + S]);
+    interact(scd[t + 2 * S], o2, slj[t + 2 * S]);
+    interact(scd[t + 3 * S], o3, slj[t + 3 * S]);
+  }
+  for (; t < cnt; t += S) interact(scd[t], load(t), slj[t]);
+}
+
 template <int P, bool ENERGY>
 __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
   constexpr int S = 64 / P;
   __shared__ float4 scd[WPB][64];   // centroid difference (x, y, z) and q_i q_j C
   __shared__ float2 slj[WPB][64];   // 4 eps_ij and sigma_ij^6 of the pair
-  __shared__ int sj[WPB][64];       // j * P (element offset of atom j's beads)
+  __shared__ unsigned sj[WPB][64];  // byte offset of atom j's bead-0 FP32 offset
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, s = lane / P, b = lane % P;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int i = lb * WPB + wv;
@@ -157,7 +201,10 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
   const float4 oi = A.xf[(size_t)i * P + b];
   const double4 ci = A.cwrap[i];
   const double qi = A.coulomb * A.charge[i];
-  const int ti = A.type[i];
+  const int ti = __builtin_amdgcn_readfirstlane(A.type[i]);
+  // hydrogen-like atoms (no LJ partner): the whole wavefront skips the LJ arithmetic
+  const bool ilj = __builtin_amdgcn_readfirstlane(A.lj_any[ti]) != 0;
+  const unsigned boff = (unsigned)b * (unsigned)sizeof(float4);
   const float alpha = (float)A.alpha;
   const float kexp = (float)(-A.alpha * A.alpha * 1.4426950408889634);  // -alpha^2 log2(e)
   const float c2a = (float)(2.0 * A.alpha / sqrt(M_PI));
@@ -173,7 +220,7 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
     bool keep = false;
     float4 cdv;
     float2 ljv;
-    int jp = 0;
+    unsigned jp = 0;
     if (k0 + lane < nn) {
       const unsigned e = (unsigned)row[k0 + lane];
       const int j = e & 0x3FFFFFF;
@@ -185,7 +232,7 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
       cdv = make_float4(cx, cy, cz, (float)(qi * A.charge[j]));
       const int tp = ti * A.ntypes + A.type[j];
       ljv = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
-      jp = j * P;
+      jp = (unsigned)j * (unsigned)(P * sizeof(float4));
     }
     const unsigned long long bal = __ballot(keep);
     if (keep) {
@@ -197,39 +244,10 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
     const int cnt = __popcll(bal);
     wave_sync();
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    auto interact = [&](const float4 cd, const float4 oj, const float2 lj) {
-      const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
-      const float r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 < rc2) {
-        const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir;
-        const float x = alpha * (r2 * ir);
-        const float tt = __builtin_amdgcn_rcpf(1.0f + ERFC_P * x);
-        float q = ERFC_Q[7];
-#pragma unroll
-        for (int k = 6; k >= 0; --k) q = q * tt + ERFC_Q[k];
-        const float ex = __builtin_amdgcn_exp2f(kexp * r2);       // exp(-alpha^2 r^2)
-        const float erfcv = tt * q * ex;
-        float sc = cd.w * ir2 * (erfcv * ir + c2a * ex);
-        if (ENERGY) ec += (double)(cd.w * erfcv * ir);
-        if (lj.x != 0.f) {
-          const float s6 = lj.y * ir2 * ir2 * ir2;
-          sc += lj.x * (12.f * s6 * s6 - 6.f * s6) * ir2;
-          if (ENERGY) elj += (double)(lj.x * (s6 * s6 - s6));
-        }
-        fx += sc * dx; fy += sc * dy; fz += sc * dz;
-      }
-    };
-    // four neighbours per lane per iteration: their loads are all issued before the math
-    int t = s;
-    for (; t + 3 * S < cnt; t += 4 * S) {
-      const float4 o0 = A.xf[sj[wv][t] + b], o1 = A.xf[sj[wv][t + S] + b];
-      const float4 o2 = A.xf[sj[wv][t + 2 * S] + b], o3 = A.xf[sj[wv][t + 3 * S] + b];
-      interact(scd[wv][t], o0, slj[wv][t]);
-      interact(scd[wv][t + S], o1, slj[wv][t + S]);
-      interact(scd[wv][t + 2 * S], o2, slj[wv][t + 2 * S]);
-      interact(scd[wv][t + 3 * S], o3, slj[wv][t + 3 * S]);
-    }
-    for (; t < cnt; t += S) interact(scd[wv][t], A.xf[sj[wv][t] + b], slj[wv][t]);
+    if (ilj) chunk<P, ENERGY, true>(A, scd[wv], slj[wv], sj[wv], cnt, s, boff, oi, rc2, alpha,
+                                    kexp, c2a, fx, fy, fz, ec, elj);
+    else chunk<P, ENERGY, false>(A, scd[wv], slj[wv], sj[wv], cnt, s, boff, oi, rc2, alpha,
+                                 kexp, c2a, fx, fy, fz, ec, elj);
     gx += (double)fx; gy += (double)fy; gz += (double)fz;
     wave_sync();
   }
@@ -250,14 +268,15 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
     default: return hipErrorInvalidValue;              \
   }
 
-hipError_t launch_pair(qhp_ctx* c, bool energy, int bead) {
+hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   PairArgs A;
   const int N = c->N;
   A.N = N; A.cap = c->cap;
   const bool plain = bead >= 0;
-  A.x = plain ? c->x + (size_t)bead * 3 * N : c->x;
-  A.g = plain ? c->g + (size_t)bead * 3 * N : c->g;
-  A.cwrap = c->cwrap; A.xf = c->xf; A.nbr = c->nbr; A.nnbr = c->nnbr;
+  const BeadSet B = bs ? *bs : full_beads(c);
+  A.x = plain ? c->x + (size_t)bead * 3 * N : B.x;
+  A.g = plain ? c->g + (size_t)bead * 3 * N : B.g;
+  A.cwrap = c->cwrap; A.xf = B.xf; A.nbr = c->nbr; A.nnbr = c->nnbr;
   A.charge = c->d_charge; A.type = c->d_type;
   for (int d = 0; d < 3; ++d) { A.L[d] = c->p.box[d]; A.invL[d] = 1.0 / c->p.box[d]; }
   A.rc2 = c->p.cutoff * c->p.cutoff; A.alpha = c->p.ewald_alpha; A.coulomb = c->p.coulomb;
@@ -269,9 +288,14 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead) {
       A.lj_s6[a * A.ntypes + b] = s * s * s * s * s * s;
       A.lj_e4[a * A.ntypes + b] = 4.0 * e;
     }
-  A.energy = c->energy + (plain ? (size_t)bead * QHP_NTERMS : 0);
+  for (int a = 0; a < QHP_MAX_TYPES; ++a) {
+    A.lj_any[a] = 0;
+    for (int b = 0; a < c->p.n_types && b < c->p.n_types; ++b)
+      if (A.lj_e4[a * A.ntypes + b] != 0.0) A.lj_any[a] = 1;
+  }
+  A.energy = plain ? c->energy + (size_t)bead * QHP_NTERMS : B.energy;
   A.ctrl = c->ctrl;
-  const int P = plain ? 1 : c->P;
+  const int P = plain ? 1 : B.P;
   A.nblocks = (N + WPB - 1) / WPB;
   const unsigned nb = (unsigned)((A.nblocks + 7) / 8 * 8);
   const double Lmin = fmin(c->p.box[0], fmin(c->p.box[1], c->p.box[2]));

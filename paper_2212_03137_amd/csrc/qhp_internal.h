@@ -35,6 +35,21 @@ struct NlCtrl {               // device-side control block (neighbour list, step
   double max_db;              // largest bead-centroid distance this step
 };
 
+// The beads a force launch works on: the full ring polymer, or its contraction (V_s under
+// ring-polymer contraction), or a scratch gradient target (stateless evaluation).
+struct BeadSet {
+  int P;                      // beads (a power of two)
+  int Pc;                     // complex SPME grid slots, max(1, P / 2)
+  const double* x;            // [3][N][P]
+  double* g;                  // [3][N][P] grad V (initialised by launch_bonded)
+  const float4* xf;           // [N][P] FP32 bead - centroid offsets and charge
+  double* energy;             // [P][QHP_NTERMS]
+  int terms;                  // QHP_TERMS_* for launch_bonded
+};
+#define QHP_TERMS_BONDED 1    // O-H bonds and H-O-H angles (V_f)
+#define QHP_TERMS_EXCL   2    // intramolecular Ewald exclusion correction (part of V_s)
+#define QHP_TERMS_ALL    3
+
 struct QtbState {
   int nseg;
   double* gamma = nullptr;    // [n_types][nseg+1]
@@ -58,7 +73,7 @@ struct qhp_ctx {
   int N, P, NW, Pc;           // atoms, beads, waters, complex grid batch
   hipStream_t stream;
   bool own_stream = false;    // created here because the caller passed none
-  hipGraphExec_t step_exec = nullptr;   // one captured MD step (no energies)
+  hipGraphExec_t step_exec = nullptr;   // one captured (outer) MD step (no energies)
   bool use_graph = true;
   std::string err;
   bool have_state = false;
@@ -130,6 +145,16 @@ struct qhp_ctx {
   double* io_a = nullptr;     // [P][N][3]
   double* io_b = nullptr;
 
+  // multiple time stepping and ring-polymer contraction
+  bool respa = false;         // rpc_beads < P or respa_nalt > 1
+  int Ps = 0, nalt = 1;       // contracted beads, inner steps per outer step
+  double* xs = nullptr;       // [3][N][Ps] contracted beads
+  double* gs = nullptr;       // [3][N][Ps] grad V_s there
+  float4* xfs = nullptr;      // [N][Ps]
+  double* Cs = nullptr;       // [Ps][Ps] contraction matrix C[j][n]
+  double* pa_tmp = nullptr;   // [3][N][P] scratch momenta
+  double* g_eval = nullptr;   // [3][N][P] gradient target of qhp_eval
+
   QtbState qtb;
 
   // profiling
@@ -164,19 +189,30 @@ void prof_end(qhp_ctx* c, int which, hipEvent_t ev);
 // launchers implemented in the kernel files (all enqueue on c->stream, return hipError_t)
 // ---------------------------------------------------------------------------------------
 hipError_t launch_beads_to_modes(qhp_ctx* c, const double* xb, const double* vb);
-hipError_t launch_nm_step(qhp_ctx* c);
-hipError_t launch_state_out(qhp_ctx* c, double* xb, double* vb);
+// inner: index of the inner step in its outer step; slow_h: factor of the slow kick in this
+// inner step (0 or n dt); emit: write the bead set of the slow forces (centroids, list
+// and tile bookkeeping inputs); without RESPA (0, 0, true).
+hipError_t launch_nm_step(qhp_ctx* c, int inner, double slow_h, bool emit);
+// dst = src + s * f_s on the modes n < Ps (f_s from gs); the other modes are copied
+hipError_t launch_kick_slow(qhp_ctx* c, double* dst, const double* src, double s);
+// pa: the stored momenta to report from (c->Pa, or Pa plus the pending slow kick)
+hipError_t launch_state_out(qhp_ctx* c, double* xb, double* vb, const double* pa);
 hipError_t launch_kick_back(qhp_ctx* c);
-hipError_t launch_mode_energies(qhp_ctx* c, double* out2);
+hipError_t launch_mode_energies(qhp_ctx* c, double* out2, const double* pa);
+// contracted beads, their FP32 offsets, centroids and block maxima from the modes Q
+hipError_t launch_contract(qhp_ctx* c);
 hipError_t launch_transpose_in(qhp_ctx* c, const double* src, double* dst);
 hipError_t launch_transpose_out(qhp_ctx* c, const double* src, double* dst, double scale);
 hipError_t launch_centroid_of_beads(qhp_ctx* c);
 
 hipError_t launch_nlist(qhp_ctx* c, bool from_step);
 hipError_t launch_zero(qhp_ctx* c, void* ptr, size_t bytes);
-hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead);
-hipError_t launch_pair(qhp_ctx* c, bool energy, int bead);
-hipError_t launch_spme(qhp_ctx* c, bool energy, int bead);
+// bead >= 0: one bead of the plain (bead-major) layout; bead < 0: the bead set `bs`
+// (nullptr: the full ring polymer of the context)
+hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);
+hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);
+hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);
+BeadSet full_beads(qhp_ctx* c);
 hipError_t launch_noise_export(qhp_ctx* c, int stream, int64_t step, double* out);
 
 hipError_t launch_qtb_generate(qhp_ctx* c, int64_t seg);

@@ -520,19 +520,20 @@ static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc) {
   return hipGetLastError();
 }
 
-hipError_t launch_spme(qhp_ctx* c, bool energy, int bead) {
+hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   const bool plain = bead >= 0;
-  const int P = plain ? 1 : c->P;
-  const int pc = plain ? 1 : c->Pc;
+  const BeadSet B = bs ? *bs : full_beads(c);
+  const int P = plain ? 1 : B.P;
+  const int pc = plain ? 1 : B.Pc;
   const int N = c->N;
   SpmeArgs A;
   A.N = N; A.K0 = c->K[0]; A.K1 = c->K[1]; A.K2 = c->K[2]; A.Pc2 = 2 * pc;
   A.order = c->tile_atoms;
-  A.x = plain ? c->x + (size_t)bead * 3 * N : c->x;
-  A.g = plain ? c->g + (size_t)bead * 3 * N : c->g;
+  A.x = plain ? c->x + (size_t)bead * 3 * N : B.x;
+  A.g = plain ? c->g + (size_t)bead * 3 * N : B.g;
   A.grid = (double*)c->grid; A.charge = c->d_charge;
   for (int d = 0; d < 3; ++d) A.L[d] = c->p.box[d];
-  A.energy = c->energy + (plain ? (size_t)bead * QHP_NTERMS : 0);
+  A.energy = plain ? c->energy + (size_t)bead * QHP_NTERMS : B.energy;
   const unsigned nb = (unsigned)(((size_t)N * P + NT - 1) / NT);
   hipEvent_t ev = nullptr;
   prof_begin(c, QHP_PROF_SPREAD, &ev);
