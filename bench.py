@@ -35,6 +35,27 @@ FLOPS_PER_PAIR = 30.0
 FLOPS_PER_CANDIDATE = 8.0
 
 
+def measured_traffic(cls):
+    """HBM bytes per launch of the class's kernel from the committed FETCH_SIZE / WRITE_SIZE
+    counter record (profiles/traffic_<class>_water4096_P32.json), scaled by the copy
+    calibration; None when there is no record or the kernel's sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{cls}_water4096_P32.json")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None, "kernel sources changed since the counters were taken"
+    b = (rec["fetch_size_kib_per_dispatch"] * 1024 * rec["fetch_scale"]
+         + rec["write_size_kib_per_dispatch"] * 1024 * rec["write_scale"])
+    return b, os.path.relpath(path, ROOT)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,7 +229,8 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"], roof["traffic_source"] = measured_traffic(dominant)
+    roof["traffic_unit"] = "HBM bytes per launch"
     roof["kernel"] = dominant
     roof["avg_launch_ms"] = dom_ms / dom_n if dom_n else None
     roof["launches"] = dom_n
