@@ -138,6 +138,42 @@ struct PrepArgs {
   int* tile_of; int* tile_start; int* tile_atoms;
 };
 
+// Exclusive prefix sum over the block of one value per thread (wavefront shuffles, then
+// the wavefront totals); *total receives the sum of all values.
+QHP_DEV int block_exclusive_scan(int v, int* swave, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) swave[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    int t = lane < nw ? swave[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(t, o);
+      if (lane >= o) t += y;
+    }
+    if (lane < nw) swave[lane] = t;       // inclusive over wavefronts
+  }
+  __syncthreads();
+  const int before = w > 0 ? swave[w - 1] : 0;
+  *total = swave[nw - 1];
+  __syncthreads();                        // swave is reused by the next scan
+  return before + x - v;
+}
+
+QHP_DEV double wave_fmax(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+constexpr int PREP_REG = 16;              // atoms per thread whose bins stay in registers
+
 __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
   extern __shared__ int lds[];
   NlArgs& A = B.nl;
@@ -145,88 +181,116 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
   int* tfill = lds + B.ntiles;                // [ntiles]
   int* ccount = lds + 2 * B.ntiles;           // [ncell]
   int* cfill = ccount + A.ncell;              // [ncell]
-  __shared__ double sm[4][1024];
+  __shared__ double sm[4][16];
+  __shared__ int swave[16];
   __shared__ int go;
-  __shared__ int part[1024];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6;
   // ---- 1. rebuild decision and step bookkeeping ----
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k = tid; k < A.n_bmax; k += nt) {
     const double4 v = A.bmax[k];
     a[0] = fmax(a[0], v.x); a[1] = fmax(a[1], v.y); a[2] = fmax(a[2], v.z); a[3] = fmax(a[3], v.w);
   }
-  for (int q = 0; q < 4; ++q) sm[q][tid] = a[q];
+  for (int q = 0; q < 4; ++q) a[q] = wave_fmax(a[q]);
+  if (lane == 0)
+    for (int q = 0; q < 4; ++q) sm[q][wv] = a[q];
   for (int k = tid; k < B.ntiles; k += nt) tcount[k] = 0;
   for (int k = tid; k < A.ncell; k += nt) ccount[k] = 0;
   __syncthreads();
-  for (int st = nt / 2; st > 0; st >>= 1) {
-    if (tid < st)
-      for (int q = 0; q < 4; ++q) sm[q][tid] = fmax(sm[q][tid], sm[q][tid + st]);
-    __syncthreads();
-  }
   if (tid == 0) {
+    double m[4] = {sm[0][0], sm[1][0], sm[2][0], sm[3][0]};
+    for (int w = 1; w < nt / 64; ++w)
+      for (int q = 0; q < 4; ++q) m[q] = fmax(m[q], sm[q][w]);
     NlCtrl* c = A.ctrl;
-    const double dc = sqrt(sm[0][0]), db = sqrt(sm[1][0]);
+    const double dc = sqrt(m[0]), db = sqrt(m[1]);
     const int b = force || c->force_build || !(2.0 * (dc + db) <= A.skin);
     c->do_build = b;
     c->force_build = 0;
     if (!force) c->step += A.nadv;  // a propagation step's forces: the step is done
-    c->spread_m = (int)sm[2][0];
+    c->spread_m = (int)m[2];
     c->max_db = db;
-    if (sm[3][0] != 0.0) c->spread_margin = 1;
+    if (m[3] != 0.0) c->spread_margin = 1;
     if (b) { c->n_builds += 1; c->max_count = 0; }
     go = b;
   }
+  // Each thread bins a contiguous run of atoms: neighbouring lanes then hold atoms a few
+  // molecules apart, which mostly fall in different bins (fewer same-address LDS atomics),
+  // and the bins of the first PREP_REG atoms stay in registers for the scatter.
+  const int per = (A.N + nt - 1) / nt;
+  const int i0 = min(A.N, tid * per), i1 = min(A.N, i0 + per);
+  const bool spill = per > PREP_REG;
   // ---- 2. SPME tiles ----
   const int K[3] = {B.K0, B.K1, B.K2};
   const double KoL[3] = {B.KoL0, B.KoL1, B.KoL2};
-  for (int i = tid; i < A.N; i += nt) {
-    const double4 c = A.cent[i];
+  auto tile_of = [&](const double4 c) {
     const double cc[3] = {c.x, c.y, c.z};
     int bc[3];
     for (int d = 0; d < 3; ++d) bc[d] = qhp::base_of(cc[d], KoL[d], K[d]) % K[d];
-    const int t = (bc[0] / QHP_TB * B.nt1 + bc[1] / QHP_TB) * B.nt2 + bc[2] / QHP_TB;
+    return (bc[0] / QHP_TB * B.nt1 + bc[1] / QHP_TB) * B.nt2 + bc[2] / QHP_TB;
+  };
+  int reg[PREP_REG];
+#pragma unroll
+  for (int kb = 0; kb < PREP_REG; kb += 8) {     // eight loads in flight, then the bins
+    double4 cv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (i0 + kb + k < i1) cv[k] = A.cent[i0 + kb + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (i0 + kb + k < i1) {
+        reg[kb + k] = tile_of(cv[k]);
+        atomicAdd(&tcount[reg[kb + k]], 1);
+      }
+  }
+  for (int i = i0 + PREP_REG; i < i1; ++i) {
+    const int t = tile_of(A.cent[i]);
     B.tile_of[i] = t;
     atomicAdd(&tcount[t], 1);
   }
   __syncthreads();
   // exclusive scan of a count array of length n by the block (per-thread chunks)
   auto scan = [&](const int* cnt, int* start_g, int* fill, int n) {
-    const int per = (n + nt - 1) / nt;
-    const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+    const int pc = (n + nt - 1) / nt;
+    const int b0 = min(n, tid * pc), b1 = min(n, b0 + pc);
     int s = 0;
     for (int k = b0; k < b1; ++k) s += cnt[k];
-    part[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-      int acc = 0;
-      for (int k = 0; k < nt; ++k) { const int v = part[k]; part[k] = acc; acc += v; }
-      start_g[n] = acc;
-    }
-    __syncthreads();
-    int acc = part[tid];
+    int total;
+    int acc = block_exclusive_scan(s, swave, &total);
     for (int k = b0; k < b1; ++k) { start_g[k] = acc; fill[k] = acc; acc += cnt[k]; }
+    if (tid == 0) start_g[n] = total;
     __syncthreads();
   };
   scan(tcount, B.tile_start, tfill, B.ntiles);
-  for (int i = tid; i < A.N; i += nt) B.tile_atoms[atomicAdd(&tfill[B.tile_of[i]], 1)] = i;
+#pragma unroll
+  for (int k = 0; k < PREP_REG; ++k)
+    if (i0 + k < i1) B.tile_atoms[atomicAdd(&tfill[reg[k]], 1)] = i0 + k;
+  if (spill)
+    for (int i = i0 + PREP_REG; i < i1; ++i) B.tile_atoms[atomicAdd(&tfill[B.tile_of[i]], 1)] = i;
   // ---- 3. centroid cells of a rebuild ----
   if (!go) return;
-  for (int i = tid; i < A.N; i += nt) {
+  auto cell_bin = [&](int i) {
     const double4 c = A.cent[i];
     const int id = (cell_coord(c.x, A.iL0, A.nc0) * A.nc1 + cell_coord(c.y, A.iL1, A.nc1)) * A.nc2 +
                    cell_coord(c.z, A.iL2, A.nc2);
-    A.cell_of[i] = id;
     A.cref[i] = c;
     const double4 w = make_double4(wrapped(c.x, A.L0, A.iL0), wrapped(c.y, A.L1, A.iL1),
                                    wrapped(c.z, A.L2, A.iL2), 0.0);
     A.cwrap[i] = w;
     A.coff[i] = make_double4(c.x - w.x, c.y - w.y, c.z - w.z, 0.0);
     atomicAdd(&ccount[id], 1);
-  }
+    return id;
+  };
+#pragma unroll
+  for (int k = 0; k < PREP_REG; ++k)
+    if (i0 + k < i1) reg[k] = cell_bin(i0 + k);
+  for (int i = i0 + PREP_REG; i < i1; ++i) A.cell_of[i] = cell_bin(i);
   __syncthreads();
   scan(ccount, A.cell_start, cfill, A.ncell);
-  for (int i = tid; i < A.N; i += nt) A.cell_atoms[atomicAdd(&cfill[A.cell_of[i]], 1)] = i;
+#pragma unroll
+  for (int k = 0; k < PREP_REG; ++k)
+    if (i0 + k < i1) A.cell_atoms[atomicAdd(&cfill[reg[k]], 1)] = i0 + k;
+  if (spill)
+    for (int i = i0 + PREP_REG; i < i1; ++i) A.cell_atoms[atomicAdd(&cfill[A.cell_of[i]], 1)] = i;
 }
 
 __global__ __launch_bounds__(256) void k_nl_build(NlArgs A) {
