@@ -232,12 +232,18 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   for (int d = 0; d < 3; ++d) c->K[d] = p->pme_grid[d];
   const bool plain = p->exec == QHP_PLAIN;
   const int Pc_grid = plain ? 1 : c->Pc;
-  for (int d = 0; d < 3; ++d) {
-    const long series = (long)c->K[0] * c->K[1] * c->K[2] * Pc_grid / c->K[d];
-    if (series % (4096 / c->K[d])) {
-      delete c;
-      return QHP_EUNSUPPORTED;
-    }
+  {
+    // every FFT pass must split into whole blocks, for the beads and the contracted beads
+    const int ps = p->rpc_beads > 0 ? p->rpc_beads : P;
+    const int pcs[2] = {Pc_grid, ps == 1 ? 1 : ps / 2};
+    for (int pc : pcs)
+      for (int d = 0; d < 3; ++d) {
+        const long series = (long)c->K[0] * c->K[1] * c->K[2] * pc / c->K[d];
+        if (series % (QHP_FFT_E / c->K[d])) {
+          delete c;
+          return QHP_EUNSUPPORTED;
+        }
+      }
   }
 
   // ---- normal modes and per-mode coefficients (host, FP64) ----

@@ -70,13 +70,7 @@ __global__ __launch_bounds__(256) void k_nl_check(NlArgs A, int force) {
 }
 
 #pragma clang fp contract(off)
-QHP_DEV int cell_coord(double x, double iL, int n) {
-  double f = x * iL;
-  f = f - floor(f);
-  if (!isfinite(f)) return 0;
-  const int i = (int)(f * (double)n);
-  return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
+using qhp::cell_coord;
 
 QHP_DEV double wrapped(double x, double L, double iL) { return x - L * floor(x * iL); }
 
@@ -90,7 +84,7 @@ __global__ void k_nl_assign(NlArgs A) {
   A.cell_of[a] = id;
   A.cref[a] = c;
   const double4 w = make_double4(wrapped(c.x, A.L0, A.iL0), wrapped(c.y, A.L1, A.iL1),
-                                 wrapped(c.z, A.L2, A.iL2), 0.0);
+                                 wrapped(c.z, A.L2, A.iL2), c.w);
   A.cwrap[a] = w;
   A.coff[a] = make_double4(c.x - w.x, c.y - w.y, c.z - w.z, 0.0);
   atomicAdd(&A.cell_count[id], 1);
@@ -127,9 +121,10 @@ __global__ void k_nl_scatter(NlArgs A) {
 }
 
 // One block per step (batched path): reduce the per-block maxima of the normal-mode (or
-// centroid) kernel and decide the rebuild; bin every atom into its SPME tile by the grid
-// base of its centroid (counts, offsets, scatter, all in LDS); on a rebuild, assign the
-// centroid cells and scatter the atoms into them. The cell order within a cell is not
+// centroid) kernel and decide the rebuild; bin every atom into the SPME tile of its
+// centroid (counts, offsets, scatter, all in LDS); on a rebuild, scatter the atoms into
+// their centroid cells. The kernels that write the centroids also write each centroid's
+// tile and cell, so this block only counts and scatters. The order within a cell is not
 // significant (the exported list is canonical).
 struct PrepArgs {
   NlArgs nl;
@@ -219,34 +214,15 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
   const int per = (A.N + nt - 1) / nt;
   const int i0 = min(A.N, tid * per), i1 = min(A.N, i0 + per);
   const bool spill = per > PREP_REG;
-  // ---- 2. SPME tiles ----
-  const int K[3] = {B.K0, B.K1, B.K2};
-  const double KoL[3] = {B.KoL0, B.KoL1, B.KoL2};
-  auto tile_of = [&](const double4 c) {
-    const double cc[3] = {c.x, c.y, c.z};
-    int bc[3];
-    for (int d = 0; d < 3; ++d) bc[d] = qhp::base_of(cc[d], KoL[d], K[d]) % K[d];
-    return (bc[0] / QHP_TB * B.nt1 + bc[1] / QHP_TB) * B.nt2 + bc[2] / QHP_TB;
-  };
+  // ---- 2. SPME tiles (each centroid's tile was written with the centroid) ----
   int reg[PREP_REG];
 #pragma unroll
-  for (int kb = 0; kb < PREP_REG; kb += 8) {     // eight loads in flight, then the bins
-    double4 cv[8];
+  for (int k = 0; k < PREP_REG; ++k)
+    if (i0 + k < i1) reg[k] = B.tile_of[i0 + k];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (i0 + kb + k < i1) cv[k] = A.cent[i0 + kb + k];
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (i0 + kb + k < i1) {
-        reg[kb + k] = tile_of(cv[k]);
-        atomicAdd(&tcount[reg[kb + k]], 1);
-      }
-  }
-  for (int i = i0 + PREP_REG; i < i1; ++i) {
-    const int t = tile_of(A.cent[i]);
-    B.tile_of[i] = t;
-    atomicAdd(&tcount[t], 1);
-  }
+  for (int k = 0; k < PREP_REG; ++k)
+    if (i0 + k < i1) atomicAdd(&tcount[reg[k]], 1);
+  for (int i = i0 + PREP_REG; i < i1; ++i) atomicAdd(&tcount[B.tile_of[i]], 1);
   __syncthreads();
   // exclusive scan of a count array of length n by the block (per-thread chunks)
   auto scan = [&](const int* cnt, int* start_g, int* fill, int n) {
@@ -268,22 +244,23 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
     for (int i = i0 + PREP_REG; i < i1; ++i) B.tile_atoms[atomicAdd(&tfill[B.tile_of[i]], 1)] = i;
   // ---- 3. centroid cells of a rebuild ----
   if (!go) return;
-  auto cell_bin = [&](int i) {
+  // the cell of each centroid was written with it; record the build frame
+  auto cell_bin = [&](int i, int id) {
     const double4 c = A.cent[i];
-    const int id = (cell_coord(c.x, A.iL0, A.nc0) * A.nc1 + cell_coord(c.y, A.iL1, A.nc1)) * A.nc2 +
-                   cell_coord(c.z, A.iL2, A.nc2);
     A.cref[i] = c;
     const double4 w = make_double4(wrapped(c.x, A.L0, A.iL0), wrapped(c.y, A.L1, A.iL1),
-                                   wrapped(c.z, A.L2, A.iL2), 0.0);
+                                   wrapped(c.z, A.L2, A.iL2), c.w);   // w: bead spread
     A.cwrap[i] = w;
     A.coff[i] = make_double4(c.x - w.x, c.y - w.y, c.z - w.z, 0.0);
     atomicAdd(&ccount[id], 1);
-    return id;
   };
 #pragma unroll
   for (int k = 0; k < PREP_REG; ++k)
-    if (i0 + k < i1) reg[k] = cell_bin(i0 + k);
-  for (int i = i0 + PREP_REG; i < i1; ++i) A.cell_of[i] = cell_bin(i);
+    if (i0 + k < i1) reg[k] = A.cell_of[i0 + k];
+#pragma unroll
+  for (int k = 0; k < PREP_REG; ++k)
+    if (i0 + k < i1) cell_bin(i0 + k, reg[k]);
+  for (int i = i0 + PREP_REG; i < i1; ++i) cell_bin(i, A.cell_of[i]);
   __syncthreads();
   scan(ccount, A.cell_start, cfill, A.ncell);
 #pragma unroll
@@ -401,6 +378,17 @@ static NlArgs nl_args(qhp_ctx* c) {
   A.nbr = c->nbr; A.nnbr = c->nnbr; A.ctrl = c->ctrl; A.bmax = c->bmax; A.n_bmax = c->n_bmax;
   A.nadv = c->nalt;
   return A;
+}
+
+qhp::BinGeom bin_geom(const qhp_ctx* c) {
+  qhp::BinGeom G;
+  G.tile_of = c->tile_of; G.cell_of = c->cell_of;
+  for (int d = 0; d < 3; ++d) {
+    G.K[d] = c->K[d]; G.KoL[d] = c->K[d] / c->p.box[d];
+    G.nc[d] = c->nc[d]; G.iL[d] = 1.0 / c->p.box[d];
+  }
+  G.nt1 = c->K[1] / QHP_TB; G.nt2 = c->K[2] / QHP_TB;
+  return G;
 }
 
 size_t prep_lds_bytes(const qhp_ctx* c) { return (size_t)(2 * c->ntiles + 2 * c->ncell) * sizeof(int); }

@@ -40,6 +40,7 @@ struct NmArgs {
   float4* xfs;             // [N][Ps]
   int Ps, step_off, emit;
   double slow_h;           // factor of the slow kick this inner step (0: none)
+  qhp::BinGeom bins;       // SPME tile and list cell of every centroid (when emitting)
 };
 
 template <int P, bool BEADMAJOR>
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
   __syncthreads();
 
   // beads from modes: lane index n now stands for bead i = n
-  double db2 = 0, dc2 = 0;
+  double db2 = 0, dc2 = 0, cen[3] = {0.0, 0.0, 0.0};
   int moff = 0, mbad = 0;
   const bool emit = !RESPA || A.emit;
   if (live) {
@@ -220,14 +221,21 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
       if (F32 && !RESPA) A.xf[a * P + n] = o4;
       if (F32 && RESPA) A.xfs[a * Ps + n] = o4;
     }
-    if (emit && n == 0) {
-      A.cent[a] = make_double4(c[0], c[1], c[2], 0.0);
-      const double4 o = A.coff[a];
-      A.cwrap[a] = make_double4(c[0] - o.x, c[1] - o.y, c[2] - o.z, 0.0);
-      const double4 r = A.cref[a];
-      const double ex = c[0] - r.x, ey = c[1] - r.y, ez = c[2] - r.z;
-      dc2 = ex * ex + ey * ey + ez * ez;
-    }
+    cen[0] = c[0]; cen[1] = c[1]; cen[2] = c[2];
+  }
+  // largest bead-centroid distance of each atom (over its P lanes): the pair kernel's
+  // per-pair reach; stored in the w components of the centroid records
+  double adb2 = db2;
+  for (int o = 1; o < P; o <<= 1) adb2 = fmax(adb2, __shfl_xor(adb2, o));
+  if (live && emit && n == 0) {
+    const double adb = sqrt(adb2);
+    A.cent[a] = make_double4(cen[0], cen[1], cen[2], adb);
+    qhp::write_bins(A.bins, a, cen[0], cen[1], cen[2]);
+    const double4 o = A.coff[a];
+    A.cwrap[a] = make_double4(cen[0] - o.x, cen[1] - o.y, cen[2] - o.z, adb);
+    const double4 r = A.cref[a];
+    const double ex = cen[0] - r.x, ey = cen[1] - r.y, ez = cen[2] - r.z;
+    dc2 = ex * ex + ey * ey + ez * ez;
   }
   if (!emit) {                       // an inner step without slow forces after it
     if (bad) A.ctrl->nonfinite = 1;
@@ -402,6 +410,7 @@ struct CentArgs {
   double4* bmax;
   double KoL[3];
   int K[3], order;
+  qhp::BinGeom bins;
 };
 
 template <int P, bool BEADMAJOR>
@@ -417,7 +426,7 @@ __global__ __launch_bounds__(128) void k_centroid_beads(CentArgs A) {
       for (int b = 1; b < P; ++b) s = s + A.x[gidx<P, BEADMAJOR>(A.N, d, a, b)];
       c[d] = s / (double)P;
     }
-    A.cent[a] = make_double4(c[0], c[1], c[2], 0.0);
+    qhp::write_bins(A.bins, a, c[0], c[1], c[2]);
     for (int b = 0; b < P; ++b) {
       double xb[3];
       for (int d = 0; d < 3; ++d) xb[d] = A.x[gidx<P, BEADMAJOR>(A.N, d, a, b)];
@@ -432,6 +441,7 @@ __global__ __launch_bounds__(128) void k_centroid_beads(CentArgs A) {
           if (dl > QHP_TB || dl < A.order - 1 - QHP_TB) mbad = 1;
         }
     }
+    A.cent[a] = make_double4(c[0], c[1], c[2], sqrt(db2));
   }
   db2 = wave_max(db2);
   const double mo = wave_max((double)moff), mb = wave_max((double)mbad);
@@ -477,8 +487,12 @@ __global__ __launch_bounds__(NT) void k_contract(CentArgs A, int Ps, const doubl
       moff = max(moff, dl < 0 ? -dl : dl);
       if (dl > QHP_TB || dl < A.order - 1 - QHP_TB) mbad = 1;
     }
-    if (n == 0) A.cent[a] = make_double4(c[0], c[1], c[2], 0.0);
+    if (n == 0) qhp::write_bins(A.bins, a, c[0], c[1], c[2]);
   }
+  double adb2 = db2;                   // the atom's largest contracted-bead distance
+  for (int o = 1; o < P; o <<= 1) adb2 = fmax(adb2, __shfl_xor(adb2, o));
+  if (live && n == 0)
+    A.cent[a] = make_double4(sq[al][0][0], sq[al][1][0], sq[al][2][0], sqrt(adb2));
   db2 = wave_max(db2);
   const double mo = wave_max((double)moff), mb = wave_max((double)mbad);
   if ((tid & 63) == 0) { sm[0][tid >> 6] = db2; sm[1][tid >> 6] = mo; sm[2][tid >> 6] = mb; }
@@ -540,6 +554,7 @@ hipError_t launch_nm_step(qhp_ctx* c, int inner, double slow_h, bool emit) {
   A.qc1 = c->qtb.c1; A.qosd = c->qtb.osd;
   A.gs = c->gs; A.Cs = c->Cs; A.xs = c->xs; A.xfs = c->xfs; A.Ps = c->Ps;
   A.step_off = inner; A.emit = emit ? 1 : 0; A.slow_h = slow_h;
+  A.bins = bin_geom(c);
   const bool bm = c->p.exec == QHP_PLAIN;
   const bool f32 = c->p.precision == QHP_FP32_PAIRS && !bm;
   const unsigned nb = nblocks_atoms(c->N, c->P);
@@ -616,6 +631,7 @@ hipError_t launch_contract(qhp_ctx* c) {
   CentArgs A;
   A.N = c->N; A.x = c->Q; A.cent = c->cent; A.charge = c->d_charge; A.bmax = c->bmax;
   A.xf = c->p.precision == QHP_FP32_PAIRS ? c->xfs : nullptr;
+  A.bins = bin_geom(c);
   for (int d = 0; d < 3; ++d) { A.K[d] = c->K[d]; A.KoL[d] = c->K[d] / c->p.box[d]; }
   A.order = c->p.pme_order;
   const unsigned nb = nblocks_atoms(c->N, c->P);
@@ -630,6 +646,7 @@ hipError_t launch_centroid_of_beads(qhp_ctx* c) {
   CentArgs A;
   A.N = c->N; A.x = c->x; A.cent = c->cent; A.charge = c->d_charge; A.bmax = c->bmax;
   A.xf = (c->p.precision == QHP_FP32_PAIRS && !bm) ? c->xf : nullptr;
+  A.bins = bin_geom(c);
   for (int d = 0; d < 3; ++d) { A.K[d] = c->K[d]; A.KoL[d] = c->K[d] / c->p.box[d]; }
   A.order = c->p.pme_order;
   const unsigned nb = (c->N + 127) / 128;

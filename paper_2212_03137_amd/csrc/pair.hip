@@ -8,6 +8,9 @@
 // The neighbour row is consumed 64 entries at a time: lane l decodes entry l once (index,
 // type, charge, FP64 centroid difference with the stored image shift) into LDS, and the
 // bead lanes then read it from there, so the per-pair FP64 work is not repeated per bead.
+// The decode drops pairs whose centroids are further apart than rc plus both atoms'
+// largest bead-centroid distances (no bead can then be in range) and stores the pairs
+// with an LJ term first, so that the LJ arithmetic runs on those pairs only.
 //
 // FP32-pair mode: the displacement is the FP64 wrapped-centroid difference plus image
 // shift, rounded once to FP32, plus the FP32 bead offsets from the centroids; distance,
@@ -46,7 +49,6 @@ struct PairArgs {
   double lj_s6[QHP_MAX_TYPES * QHP_MAX_TYPES];
   double lj_e4[QHP_MAX_TYPES * QHP_MAX_TYPES];
   int ntypes;
-  int lj_any[QHP_MAX_TYPES];  // type t has a non-zero LJ epsilon with some type
   int nblocks;            // logical blocks
   const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
   double* energy;         // [P][NTERMS] (plain: the bead's row)
@@ -145,12 +147,13 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
   flush<P, ENERGY>(A, i, lane, gx, gy, gz, ec, elj);
 }
 
-// One chunk of compacted neighbours for the lane (slot s, bead b): neighbours s, s+S, ...
-// LJ = false when atom i's type has no LJ partner (a wavefront-uniform choice).
+// Compacted neighbours t0 + s, t0 + s + S, ... < cnt for the lane (slot s, bead b).
+// LJ = false for neighbours without an LJ term (a wavefront-uniform choice).
 template <int P, bool ENERGY, bool LJ>
 QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, const unsigned* sj,
-                   int cnt, int s, unsigned boff, float4 oi, float rc2, float alpha, float kexp,
-                   float c2a, float& fx, float& fy, float& fz, double& ec, double& elj) {
+                   int t0, int cnt, int s, unsigned boff, float4 oi, float rc2, float alpha,
+                   float kexp, float c2a, float& fx, float& fy, float& fz, double& ec,
+                   double& elj) {
   constexpr int S = 64 / P;
   const char* xf = reinterpret_cast<const char*>(A.xf);
   auto load = [&](int t) { return *reinterpret_cast<const float4*>(xf + (sj[t] + boff)); };
@@ -177,7 +180,7 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
     }
   };
   // four neighbours per lane per iteration: their loads are all issued before the math
-  int t = s;
+  int t = t0 + s;
   for (; t + 3 * S < cnt; t += 4 * S) {
     const float4 o0 = load(t), o1 = load(t + S), o2 = load(t + 2 * S), o3 = load(t + 3 * S);
     interact(scd[t], o0, slj[t]);
@@ -201,23 +204,21 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
   const float4 oi = A.xf[(size_t)i * P + b];
   const double4 ci = A.cwrap[i];
   const double qi = A.coulomb * A.charge[i];
-  const int ti = __builtin_amdgcn_readfirstlane(A.type[i]);
-  // hydrogen-like atoms (no LJ partner): the whole wavefront skips the LJ arithmetic
-  const bool ilj = __builtin_amdgcn_readfirstlane(A.lj_any[ti]) != 0;
+  const int ti = A.type[i];
   const unsigned boff = (unsigned)b * (unsigned)sizeof(float4);
   const float alpha = (float)A.alpha;
   const float kexp = (float)(-A.alpha * A.alpha * 1.4426950408889634);  // -alpha^2 log2(e)
   const float c2a = (float)(2.0 * A.alpha / sqrt(M_PI));
   const float rc2 = (float)A.rc2;
-  // no bead of a pair whose centroids are further apart than rc + 2 max|bead - centroid|
-  // can be within the cutoff (small margin for the FP32 rounding of the difference)
-  const double reach = sqrt(A.rc2) + 2.0 * A.ctrl->max_db + 1e-3;
-  const float reach2 = (float)(reach * reach);
+  // no bead of a pair whose centroids are further apart than rc + d_i + d_j can be within
+  // the cutoff, d = an atom's largest bead-centroid distance this step (kept in the w of
+  // its centroid record); small margin for the FP32 rounding of the difference
+  const double reach_i = sqrt(A.rc2) + ci.w + 1e-3;
   const int nn = A.nnbr[i];
   const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
   for (int k0 = 0; k0 < nn; k0 += 64) {
-    bool keep = false;
+    bool keep = false, haslj = false;
     float4 cdv;
     float2 ljv;
     unsigned jp = 0;
@@ -228,26 +229,31 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
       const float cx = (float)((cj.x - ci.x) + A.L[0] * (double)((int)((e >> 26) & 3) - 1));
       const float cy = (float)((cj.y - ci.y) + A.L[1] * (double)((int)((e >> 28) & 3) - 1));
       const float cz = (float)((cj.z - ci.z) + A.L[2] * (double)((int)((e >> 30) & 3) - 1));
-      keep = cx * cx + cy * cy + cz * cz < reach2;
+      const float reach = (float)(reach_i + cj.w);
+      keep = cx * cx + cy * cy + cz * cz < reach * reach;
       cdv = make_float4(cx, cy, cz, (float)(qi * A.charge[j]));
       const int tp = ti * A.ntypes + A.type[j];
       ljv = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
+      haslj = ljv.x != 0.f;
       jp = (unsigned)j * (unsigned)(P * sizeof(float4));
     }
-    const unsigned long long bal = __ballot(keep);
+    // compaction with the LJ pairs first: [0, nlj) carry LJ, [nlj, cnt) do not
+    const unsigned long long bl = __ballot(keep && haslj), bn = __ballot(keep && !haslj);
+    const int nlj = __popcll(bl), cnt = nlj + __popcll(bn);
     if (keep) {
-      const int slot = __popcll(bal & ((1ull << lane) - 1ull));
+      const unsigned long long below = (1ull << lane) - 1ull;
+      const int slot = haslj ? __popcll(bl & below) : nlj + __popcll(bn & below);
       scd[wv][slot] = cdv;
       slj[wv][slot] = ljv;
       sj[wv][slot] = jp;
     }
-    const int cnt = __popcll(bal);
     wave_sync();
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    if (ilj) chunk<P, ENERGY, true>(A, scd[wv], slj[wv], sj[wv], cnt, s, boff, oi, rc2, alpha,
-                                    kexp, c2a, fx, fy, fz, ec, elj);
-    else chunk<P, ENERGY, false>(A, scd[wv], slj[wv], sj[wv], cnt, s, boff, oi, rc2, alpha,
-                                 kexp, c2a, fx, fy, fz, ec, elj);
+    if (nlj > 0)
+      chunk<P, ENERGY, true>(A, scd[wv], slj[wv], sj[wv], 0, nlj, s, boff, oi, rc2, alpha, kexp,
+                             c2a, fx, fy, fz, ec, elj);
+    chunk<P, ENERGY, false>(A, scd[wv], slj[wv], sj[wv], nlj, cnt, s, boff, oi, rc2, alpha, kexp,
+                            c2a, fx, fy, fz, ec, elj);
     gx += (double)fx; gy += (double)fy; gz += (double)fz;
     wave_sync();
   }
@@ -288,11 +294,7 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
       A.lj_s6[a * A.ntypes + b] = s * s * s * s * s * s;
       A.lj_e4[a * A.ntypes + b] = 4.0 * e;
     }
-  for (int a = 0; a < QHP_MAX_TYPES; ++a) {
-    A.lj_any[a] = 0;
-    for (int b = 0; a < c->p.n_types && b < c->p.n_types; ++b)
-      if (A.lj_e4[a * A.ntypes + b] != 0.0) A.lj_any[a] = 1;
-  }
+
   A.energy = plain ? c->energy + (size_t)bead * QHP_NTERMS : B.energy;
   A.ctrl = c->ctrl;
   const int P = plain ? 1 : B.P;

@@ -169,6 +169,8 @@ struct qhp_ctx {
 // SPME spreading tiles: TB^3 grid points; a bead's grid base may differ from its centroid's
 // by at most TB points above and TB - order + 1 below (checked every step).
 constexpr int QHP_TB = 8;
+// complex values one FFT block transforms (series of length K times FFT_E / K series)
+constexpr int QHP_FFT_E = 2048;
 
 // ---------------------------------------------------------------------------------------
 // error plumbing
@@ -329,10 +331,11 @@ constexpr uint64_t STREAM_QTB_WHITE = 6;
 
 QHP_DEV unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
-// wrapped grid coordinate u = K * frac(x / L) in [0, K] and its integer base
+// wrapped grid coordinate u = K * frac(x / L) in [0, K] and its integer base (K is a power
+// of two, so 1/K is the exact power 2^-log2(K) and no division is needed)
 QHP_DEV double grid_coord(double x, double KoL, int K) {
   const double u = x * KoL;
-  return u - (double)K * floor(u * (1.0 / (double)K));
+  return u - (double)K * floor(u * ldexp(1.0, -__builtin_ctz((unsigned)K)));
 }
 QHP_DEV int base_of(double x, double KoL, int K) {
   const double fl = floor(grid_coord(x, KoL, K));
@@ -346,4 +349,39 @@ QHP_DEV int base_diff(int a, int b, int K) {
   return d;
 }
 
+// Bins of a centroid: its 8^3-point SPME spreading tile (by the grid base of each axis)
+// and its neighbour-list cell (fractional coordinate times the cell count, floored and
+// clamped; no contraction of the multiply-add, as in the list's reference form).
+struct BinGeom {
+  int* tile_of; int* cell_of;     // [N] outputs (nullptr: not written)
+  int K[3], nt1, nt2, nc[3];
+  double KoL[3], iL[3];
+};
+QHP_DEV int tile_of_centroid(const BinGeom& G, double cx, double cy, double cz) {
+  const double c[3] = {cx, cy, cz};
+  int t[3];
+  for (int d = 0; d < 3; ++d) t[d] = (base_of(c[d], G.KoL[d], G.K[d]) % G.K[d]) / QHP_TB;
+  return (t[0] * G.nt1 + t[1]) * G.nt2 + t[2];
+}
+#pragma clang fp contract(off)
+QHP_DEV int cell_coord(double x, double iL, int n) {
+  double f = x * iL;
+  f = f - floor(f);
+  if (!isfinite(f)) return 0;
+  const int i = (int)(f * (double)n);
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+QHP_DEV int cell_of_centroid(const BinGeom& G, double cx, double cy, double cz) {
+  return (cell_coord(cx, G.iL[0], G.nc[0]) * G.nc[1] + cell_coord(cy, G.iL[1], G.nc[1])) * G.nc[2] +
+         cell_coord(cz, G.iL[2], G.nc[2]);
+}
+#pragma clang fp contract(fast)
+QHP_DEV void write_bins(const BinGeom& G, int a, double cx, double cy, double cz) {
+  if (G.tile_of) G.tile_of[a] = tile_of_centroid(G, cx, cy, cz);
+  if (G.cell_of) G.cell_of[a] = cell_of_centroid(G, cx, cy, cz);
+}
+
 }  // namespace qhp
+
+// bin geometry of the context (tile and cell arrays, grid and cell counts)
+qhp::BinGeom bin_geom(const qhp_ctx* c);

@@ -10,10 +10,12 @@
 // (P = 1 leaves the imaginary part zero). Every FFT pass therefore reads 256-byte rows
 // (16 complex beads at P = 32) and needs no R2C/C2R bookkeeping.
 //
-// FFT: five passes over the grid; each pass loads 4096 complex values (4096/K series of
-// length K along one axis) into LDS and runs a radix-4 (+ final radix-2) Stockham FFT
-// there; the z pass does forward transform, multiplication by G and inverse transform in
-// one visit.
+// FFT: five passes over the grid; a block of each pass transforms 2048 complex values
+// (2048/K series of length K along one axis) by Stockham stages of radix 8 (then 4, 2).
+// The first stage reads its operands from the grid and the last writes the grid, so
+// for K = 64 (two radix-8 stages) the data cross LDS once; the z pass does the forward
+// transform, the multiplication by G (folded into the forward's last stage) and the
+// inverse transform in one visit.
 #include "qhp_internal.h"
 
 namespace {
@@ -357,30 +359,63 @@ QHP_DEV void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
   a3 = csub(t1, jt3);
 }
 
-// Element e of series s lives at buf[e * NS + s]; NS * K = 4096. Stockham stages of
-// radix 8 while at least 8 points remain per sub-transform, then 4, then 2.
-template <int K, int NS, bool INV, int NSTRIDE>
-QHP_DEV void fft_stages(double2* buf, const double2* tw, int tid) {
+struct FftArgs {
+  double2* grid;
+  const double2* tw;       // [K] exp(-2 pi i m / K)
+  const double* G;         // influence [K0][K1][K2] (fused z pass)
+  int lgI;                 // log2 of the complex elements below the axis (its stride)
+  int lgpc;                // log2 of the complex slots per grid point
+  int efast;               // the axis is (nearly) contiguous: stage through LDS instead
+};
+
+// Where one FFT pass reads and writes: series m, element e of the pass's axis sits at
+// (m / I) * K * I + (m % I) + e * I in the grid, I a power of two.
+template <int K>
+struct GridIO {
+  double2* grid;
+  long m0;                 // first series of the block
+  int lgI;
+  QHP_DEV long at(int s, int e) const {
+    constexpr int LGK = __builtin_ctz(K);
+    const long m = m0 + s;
+    return ((m >> lgI) << (lgI + LGK)) + (m & ((1l << lgI) - 1)) + ((long)e << lgI);
+  }
+};
+
+// Stockham stages of radix 8 while at least 8 points remain per sub-transform, then 4,
+// then 2, on NS series of length K held at buf[e * NS + s] (NS * K = FFT_E). With LOADG the
+// first stage takes its operands from the grid (no LDS copy-in; its twiddles are all 1),
+// with STOREG the last stage writes the grid; SCALE multiplies the last stage's outputs by
+// the influence function (forward half of the fused z pass).
+template <int K, int NS, bool INV, int NSTRIDE, bool LOADG, bool STOREG, bool SCALE>
+QHP_DEV void fft_stages(double2* buf, const double2* tw, int tid, const GridIO<K>& io,
+                        const double* G, int lgpc) {
   if constexpr (NSTRIDE < K) {
     constexpr int R = (K / NSTRIDE >= 8) ? 8 : ((K / NSTRIDE >= 4) ? 4 : 2);
     constexpr int BPT = NS * K / R / NT;
+    constexpr bool FIRST = NSTRIDE == 1, LAST = NSTRIDE * R == K;
     double2 v[BPT][R];
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       const int be = tid + i * NT, s = be % NS, j = be / NS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * (K / R)) * NS + s];
+      for (int r = 0; r < R; ++r) {
+        const int e = j + r * (K / R);
+        v[i][r] = (FIRST && LOADG) ? io.grid[io.at(s, e)] : buf[e * NS + s];
+      }
     }
-    __syncthreads();
+    if (!(FIRST && LOADG)) __syncthreads();
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       const int be = tid + i * NT, s = be % NS, j = be / NS;
       const int k = j % NSTRIDE;
+      if constexpr (!FIRST) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        double2 t = tw[r * k * (K / (NSTRIDE * R))];
-        if (INV) t.y = -t.y;
-        v[i][r] = cmul(v[i][r], t);
+        for (int r = 1; r < R; ++r) {
+          double2 t = tw[r * k * (K / (NSTRIDE * R))];
+          if (INV) t.y = -t.y;
+          v[i][r] = cmul(v[i][r], t);
+        }
       }
       if constexpr (R == 8) {
         // two radix-4 transforms of the even and odd inputs, joined by W8^q
@@ -406,64 +441,59 @@ QHP_DEV void fft_stages(double2* buf, const double2* tw, int tid) {
       }
       const int idx = (j / NSTRIDE) * NSTRIDE * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(idx + r * NSTRIDE) * NS + s] = v[i][r];
+      for (int r = 0; r < R; ++r) {
+        const int e = idx + r * NSTRIDE;
+        if constexpr (LAST && SCALE) {
+          const double gv = G[((io.m0 + s) >> lgpc) * K + e];
+          v[i][r].x *= gv; v[i][r].y *= gv;
+        }
+        if constexpr (LAST && STOREG) io.grid[io.at(s, e)] = v[i][r];
+        else buf[e * NS + s] = v[i][r];
+      }
     }
-    __syncthreads();
-    fft_stages<K, NS, INV, NSTRIDE * R>(buf, tw, tid);
+    if constexpr (!(LAST && STOREG)) __syncthreads();
+    fft_stages<K, NS, INV, NSTRIDE * R, LOADG, STOREG, SCALE>(buf, tw, tid, io, G, lgpc);
   }
 }
 
-struct FftArgs {
-  double2* grid;
-  const double2* tw;       // [K] exp(-2 pi i m / K)
-  const double* G;         // influence [K0][K1][K2] (fused z pass)
-  int lgI;                 // log2 of the complex elements below the axis (its stride)
-  int lgpc;                // log2 of the complex slots per grid point
-  int efast;               // load order
-};
+// MODE 0: forward, 1: inverse, 2: forward, x G, inverse (axis 2 only). With the series
+// as the fast index (every axis but a nearly contiguous innermost one) the first and last
+// stages read and write the grid directly; otherwise the block stages through LDS.
+constexpr int FFT_E = QHP_FFT_E;           // complex values per block (LDS 32 KB)
 
-// MODE 0: forward, 1: inverse, 2: forward, x G, inverse (axis 2 only)
 template <int K, int MODE>
 __global__ __launch_bounds__(NT) void k_fft_pass(FftArgs A) {
-  constexpr int NS = 4096 / K;
-  __shared__ double2 buf[4096];
+  constexpr int NS = FFT_E / K;
+  constexpr int LGK = __builtin_ctz(K);
+  __shared__ double2 buf[FFT_E];
   __shared__ double2 stw[K];
   const int tid = threadIdx.x;
   for (int m = tid; m < K; m += NT) stw[m] = A.tw[m];
-  constexpr int LGK = __builtin_ctz(K);
-  const long m0 = (long)blockIdx.x * NS;
-  const int lgI = A.lgI;
-  const long Imask = (1l << lgI) - 1;
-  // series m, element e -> (m / I) * K * I + (m % I) + e * I, with I a power of two
-  for (int l = tid; l < 4096; l += NT) {
-    const int e = A.efast ? (l & (K - 1)) : (l >> __builtin_ctz(NS));
-    const int s = A.efast ? (l >> LGK) : (l & (NS - 1));
-    const long m = m0 + s;
-    buf[e * NS + s] = A.grid[((m >> lgI) << (lgI + LGK)) + (m & Imask) + ((long)e << lgI)];
+  GridIO<K> io{A.grid, (long)blockIdx.x * NS, A.lgI};
+  if (!A.efast) {
+    __syncthreads();                                 // twiddles
+    if (MODE == 0) fft_stages<K, NS, false, 1, true, true, false>(buf, stw, tid, io, A.G, A.lgpc);
+    if (MODE == 1) fft_stages<K, NS, true, 1, true, true, false>(buf, stw, tid, io, A.G, A.lgpc);
+    if (MODE == 2) {
+      fft_stages<K, NS, false, 1, true, false, true>(buf, stw, tid, io, A.G, A.lgpc);
+      fft_stages<K, NS, true, 1, false, true, false>(buf, stw, tid, io, A.G, A.lgpc);
+    }
+    return;
+  }
+  for (int l = tid; l < FFT_E; l += NT) {
+    const int e = l & (K - 1), s = l >> LGK;
+    buf[e * NS + s] = A.grid[io.at(s, e)];
   }
   __syncthreads();
   if (MODE == 1) {
-    fft_stages<K, NS, true, 1>(buf, stw, tid);
+    fft_stages<K, NS, true, 1, false, false, false>(buf, stw, tid, io, A.G, A.lgpc);
   } else {
-    fft_stages<K, NS, false, 1>(buf, stw, tid);
+    fft_stages<K, NS, false, 1, false, false, MODE == 2>(buf, stw, tid, io, A.G, A.lgpc);
   }
-  if (MODE == 2) {
-    for (int l = tid; l < 4096; l += NT) {
-      const int e = l >> __builtin_ctz(NS), s = l & (NS - 1);
-      const long p = (m0 + s) >> A.lgpc;
-      const double gv = A.G[p * K + e];
-      double2 v = buf[e * NS + s];
-      v.x *= gv; v.y *= gv;
-      buf[e * NS + s] = v;
-    }
-    __syncthreads();
-    fft_stages<K, NS, true, 1>(buf, stw, tid);
-  }
-  for (int l = tid; l < 4096; l += NT) {
-    const int e = A.efast ? (l & (K - 1)) : (l >> __builtin_ctz(NS));
-    const int s = A.efast ? (l >> LGK) : (l & (NS - 1));
-    const long m = m0 + s;
-    A.grid[((m >> lgI) << (lgI + LGK)) + (m & Imask) + ((long)e << lgI)] = buf[e * NS + s];
+  if (MODE == 2) fft_stages<K, NS, true, 1, false, false, false>(buf, stw, tid, io, A.G, A.lgpc);
+  for (int l = tid; l < FFT_E; l += NT) {
+    const int e = l & (K - 1), s = l >> LGK;
+    A.grid[io.at(s, e)] = buf[e * NS + s];
   }
 }
 
@@ -507,7 +537,7 @@ static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc) {
   for (int d = axis + 1; d < 3; ++d) inner *= c->K[d];
   const long total = (long)c->K[0] * c->K[1] * c->K[2] * pc;
   const long series = total / K;
-  const int NS = 4096 / K;
+  const int NS = FFT_E / K;
   if (series % NS) return hipErrorInvalidValue;
   FftArgs A;
   A.grid = c->grid; A.tw = c->tw[axis]; A.G = c->influence;
