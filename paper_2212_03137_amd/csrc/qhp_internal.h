@@ -360,7 +360,7 @@ struct BinGeom {
 QHP_DEV int tile_of_centroid(const BinGeom& G, double cx, double cy, double cz) {
   const double c[3] = {cx, cy, cz};
   int t[3];
-  for (int d = 0; d < 3; ++d) t[d] = (base_of(c[d], G.KoL[d], G.K[d]) % G.K[d]) / QHP_TB;
+  for (int d = 0; d < 3; ++d) t[d] = (base_of(c[d], G.KoL[d], G.K[d]) & (G.K[d] - 1)) / QHP_TB;
   return (t[0] * G.nt1 + t[1]) * G.nt2 + t[2];
 }
 #pragma clang fp contract(off)

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void k_tile_bin(TileArgs A) {
   int bc[3];
   for (int d = 0; d < 3; ++d) {
     const double cd = A.cent ? (&A.cent[a].x)[d] : A.x[(size_t)d * A.N + a];
-    bc[d] = base_of(cd, A.KoL[d], K[d]) % K[d];
+    bc[d] = base_of(cd, A.KoL[d], K[d]) & (K[d] - 1);
   }
   const int t = (bc[0] / TB * A.nt1 + bc[1] / TB) * A.nt2 + bc[2] / TB;
   A.tile_of[a] = t;
@@ -213,9 +213,7 @@ struct TSpreadArgs {
 // lo = (base - ORDER + 1 - t0) mod K is the tile-relative position of the lowest point
 template <int ORDER>
 QHP_DEV int tile_lo(int base, int t0, int K) {
-  int r = base - (ORDER - 1) - t0;
-  r %= K;
-  return r < 0 ? r + K : r;
+  return (base - (ORDER - 1) - t0) & (K - 1);     // K is a power of two
 }
 
 template <int ORDER, int GB>
@@ -300,16 +298,23 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
       }
       if (!hit) continue;
       double w[3][ORDER], dw[3][ORDER];
-      int rel[3][ORDER];
+      int rel[2][ORDER], oz[ORDER];
+      double wz[ORDER];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         bspline<ORDER>(fr[d], w[d], dw[d]);
 #pragma unroll
         for (int t = 0; t < ORDER; ++t) {
           // stencil point base - t sits at tile-relative position lo + ORDER - 1 - t (mod K)
-          int r = lo[d] + ORDER - 1 - t;
-          if (r >= K[d]) r -= K[d];
-          rel[d][t] = r < TB ? r : -1;
+          const int r = (lo[d] + ORDER - 1 - t) & (K[d] - 1);
+          if (d < 2) {
+            rel[d][t] = r < TB ? r : -1;
+          } else {
+            // along z a point outside the tile adds zero to the row's first point, so the
+            // innermost loop has no branch
+            oz[t] = r < TB ? r * GB : 0;
+            wz[t] = r < TB ? w[2][t] : 0.0;
+          }
         }
       }
       const double qa = A.charge[a];
@@ -323,8 +328,7 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
           const double wab = wa * w[1][tb];
           double* row = acc + (rel[0][ta] * TB + rel[1][tb]) * TB * GB + bl;
 #pragma unroll
-          for (int tc = 0; tc < ORDER; ++tc)
-            if (rel[2][tc] >= 0) atomicAdd(row + rel[2][tc] * GB, wab * w[2][tc]);
+          for (int tc = 0; tc < ORDER; ++tc) atomicAdd(row + oz[tc], wab * wz[tc]);
         }
       }
     }
