@@ -28,6 +28,10 @@ Readings where the paper is silent (all stated here and used by both implementat
   2 N_seg points;
 * the finite-timestep and finite-friction corrections the paper cites are not applied
   (their form is not given): parity unpinned against the paper for that part;
+* RATIO scheme (eq. adapt_ratio with the exponentially decaying running means): the
+  running means start from zero, so the first update is the plain ratio of the first
+  segment's type-averaged spectra (the common factor 1 - e^{-N_seg dt / tau} cancels);
+  where the running C_vv is not positive gamma keeps its value; one tau for every type;
 * A_gamma is in 1/fs per kcal/mol and the first update happens at the end of segment 0:
   parity unpinned beyond the HIP path matching this oracle.
 """
@@ -79,22 +83,28 @@ def colored_segment(h_of_atom, seed, seg, nseg, n_atoms):
     return F
 
 
-def spectra_delta(v, F, gamma_of_atom, m, dt):
-    """Delta_FDT per atom and axis: [N][3][N_seg+1] from v, F: [N_seg][N][3]."""
+def spectra(v, F, dt):
+    """C_vv and Re C_vF per atom and axis, [N][3][N_seg+1], from v, F: [N_seg][N][3]."""
     nseg = v.shape[0]
     V = np.fft.rfft(v, n=2 * nseg, axis=0)
     Fk = np.fft.rfft(F, n=2 * nseg, axis=0)
     Cvv = dt / nseg * np.abs(V) ** 2
     CvF = dt / nseg * V * np.conj(Fk)
-    d = m[None, :, None] * gamma_of_atom.T[:, :, None] * Cvv - CvF.real
-    return np.transpose(d, (1, 2, 0))
+    return np.transpose(Cvv, (1, 2, 0)), np.transpose(CvF.real, (1, 2, 0))
+
+
+def spectra_delta(v, F, gamma_of_atom, m, dt):
+    """Delta_FDT per atom and axis: [N][3][N_seg+1] from v, F: [N_seg][N][3]."""
+    Cvv, CvFr = spectra(v, F, dt)
+    return m[:, None, None] * gamma_of_atom[:, None, :] * Cvv - CvFr
 
 
 class QTB:
     """adQTB run on P = 1 beads. ``grad_fn(x[1][N][3]) -> (E, grad[1][N][3])``."""
 
     def __init__(self, mass, types, n_types, kT, hbar, dt, gamma0, nseg, adapt_rate,
-                 gamma_min_frac, seed, grad_fn, classical_theta=False):
+                 gamma_min_frac, seed, grad_fn, classical_theta=False, scheme="SIMPLE",
+                 tau=None):
         self.m = np.asarray(mass, dtype=np.float64)
         self.types = np.asarray(types)
         self.n_types = n_types
@@ -108,6 +118,12 @@ class QTB:
         self.osd = math.sqrt((1.0 - self.c1 * self.c1) * dt / (2.0 * gamma0))
         self.gamma = np.full((n_types, nseg + 1), gamma0)
         self.type_mass = np.array([self.m[self.types == z][0] for z in range(n_types)])
+        if scheme not in ("SIMPLE", "RATIO"):
+            raise ValueError(scheme)
+        self.scheme = scheme
+        self.decay = math.exp(-nseg * dt / tau) if scheme == "RATIO" else 0.0
+        self.avg_vv = np.zeros((n_types, nseg + 1))
+        self.avg_vf = np.zeros((n_types, nseg + 1))
 
     def set_state(self, pos, vel, step=0):
         assert step % self.nseg == 0
@@ -142,7 +158,19 @@ class QTB:
         diss = spectra_delta(self.vrec, np.zeros_like(self.noise), self.gamma[self.types], self.m, self.dt)
         self.last_dissipation = np.stack([diss[self.types == z].mean(axis=(0, 1))
                                           for z in range(self.n_types)])
-        self.gamma = self.gamma - self.A * dbar
+        if self.scheme == "SIMPLE":
+            self.gamma = self.gamma - self.A * dbar
+            return
+        # RATIO: gamma = Re <C_vF> / (m <C_vv>) over exponentially decaying running means
+        Cvv, CvFr = spectra(self.vrec, self.noise, self.dt)
+        vv = np.stack([Cvv[self.types == z].mean(axis=(0, 1)) for z in range(self.n_types)])
+        vf = np.stack([CvFr[self.types == z].mean(axis=(0, 1)) for z in range(self.n_types)])
+        self.avg_vv = self.avg_vv * self.decay + vv * (1.0 - self.decay)
+        self.avg_vf = self.avg_vf * self.decay + vf * (1.0 - self.decay)
+        ok = self.avg_vv > 0.0
+        ratio = np.where(ok, self.avg_vf / (self.type_mass[:, None] * np.where(ok, self.avg_vv, 1.0)),
+                         self.gamma)
+        self.gamma = ratio
 
     def step(self, n=1):
         for _ in range(n):

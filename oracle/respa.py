@@ -81,12 +81,13 @@ class RPMDRespa(RPMD):
     """
 
     def __init__(self, n_beads, mass, kT, hbar, dt, gamma0, trpmd_c, seed, grad_fast,
-                 grad_slow, n_contract, n_alt):
+                 grad_slow, n_contract, n_alt, integrator="BAOAB"):
         if not 1 <= n_contract <= n_beads:
             raise ValueError("n_contract must be in 1..P")
         if n_alt < 1:
             raise ValueError("n_alt must be >= 1")
-        super().__init__(n_beads, mass, kT, hbar, dt, gamma0, trpmd_c, seed, grad_fn=None)
+        super().__init__(n_beads, mass, kT, hbar, dt, gamma0, trpmd_c, seed, grad_fn=None,
+                         integrator=integrator)
         self.grad_fast, self.grad_slow = grad_fast, grad_slow
         self.Pc, self.n_alt = n_contract, n_alt
 

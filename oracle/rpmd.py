@@ -15,6 +15,13 @@ calls it critical damping, the workloads ask for the optimal value 2 omega_n, so
 parameter (2 in every workload). xi is the Philox noise of ``oracle/philox.py`` with
 counter (step, atom, mode). The first B of a step uses the forces of the current state,
 which are computed once when the state is set.
+
+BCOCB variant (the option named at the end of Sec. "Integration Scheme", after Korol,
+Bou-Rabee and Miller): the exact A(h) rotation of each internal mode is replaced by its
+Cayley form, the implicit midpoint rule of the free ring-polymer flow,
+    Q' - Q = h (P + P') / (2m),   P' - P = -h m omega^2 (Q + Q') / 2,
+i.e. with a = omega h / 2: Q' = ((1 - a^2) Q + (h/m) P) / (1 + a^2),
+P' = (-m omega^2 h Q + (1 - a^2) P) / (1 + a^2). The centroid still moves freely.
 """
 import math
 
@@ -27,7 +34,8 @@ from . import philox
 class RPMD:
     """State (Q, P) in modes, [P][N][3]; ``grad_fn(x) -> (E[P][T], grad[P][N][3])``."""
 
-    def __init__(self, n_beads, mass, kT, hbar, dt, gamma0, trpmd_c, seed, grad_fn):
+    def __init__(self, n_beads, mass, kT, hbar, dt, gamma0, trpmd_c, seed, grad_fn,
+                 integrator="BAOAB"):
         self.P = n_beads
         self.m = np.asarray(mass, dtype=np.float64)
         self.kT, self.hbar, self.dt = kT, hbar, dt
@@ -39,6 +47,9 @@ class RPMD:
         self.gamma = np.maximum(gamma0, trpmd_c * self.omega)
         self.c1 = np.exp(-self.gamma * dt)
         self.c2 = np.sqrt(1.0 - self.c1 * self.c1)
+        if integrator not in ("BAOAB", "BCOCB"):
+            raise ValueError(integrator)
+        self.cayley = integrator == "BCOCB"
         self.step_index = 0
 
     # -- state --------------------------------------------------------------------
@@ -69,6 +80,11 @@ class RPMD:
         Q[0] = self.Q[0] + h * self.Pm[0] / self.m[:, None]
         for n in range(1, self.P):
             w = self.omega[n]
+            if self.cayley:
+                a2 = (0.5 * w * h) ** 2
+                Q[n] = ((1.0 - a2) * self.Q[n] + h / m[0] * self.Pm[n]) / (1.0 + a2)
+                Pm[n] = (-m[0] * w * w * h * self.Q[n] + (1.0 - a2) * self.Pm[n]) / (1.0 + a2)
+                continue
             c, s = math.cos(w * h), math.sin(w * h)
             Q[n] = c * self.Q[n] + s / (m[0] * w) * self.Pm[n]
             Pm[n] = -m[0] * w * s * self.Q[n] + c * self.Pm[n]

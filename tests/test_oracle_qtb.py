@@ -162,3 +162,61 @@ def test_adaptation_clamps_at_gamma_min():
     q.step(nseg)
     assert np.all(q.gamma >= 0.01 * g0)
     assert np.any(q.gamma == 0.01 * g0) and np.any(q.gamma > g0)
+
+
+# ---------------------------------------------------------------- RATIO adaptation
+def _free_qtb(scheme, tau, n=300, nseg=64, classical=True, seed=9):
+    from oracle import qtb as oq
+    m = np.full(n, 2.0 * synth.AMU)
+    types = np.zeros(n, dtype=int)
+    types[n // 2:] = 1
+    m[n // 2:] = 12.0 * synth.AMU
+    Q = oq.QTB(m, types, 2, synth.KB * 300.0, synth.HBAR, 1.0, 0.02, nseg, 1e-3, 0.01, seed,
+               lambda x: (None, np.zeros_like(x)), classical_theta=classical, scheme=scheme,
+               tau=tau)
+    rng = np.random.default_rng(seed)
+    vel = rng.standard_normal((1, n, 3)) * np.sqrt(synth.KB * 300.0 / m)[None, :, None]
+    Q.set_state(np.zeros((1, n, 3)), vel, 0)
+    return Q
+
+
+def test_ratio_without_memory_is_gamma_minus_delta_over_m_cvv():
+    # tau -> 0: gamma_new = Re C_vF / (m C_vv) = gamma - Delta / (m C_vv), the SIMPLE form with
+    # a frequency-dependent rate; m C_vv is the dissipation term over gamma
+    Q = _free_qtb("RATIO", tau=1e-9)
+    g_before = Q.gamma.copy()
+    Q.step(Q.nseg)
+    diss, dbar = Q.last_dissipation, Q.last_delta
+    ok = diss > 1e-12 * diss.max()
+    expect = g_before - dbar * g_before / np.where(ok, diss, 1.0)
+    expect = np.maximum(expect, Q.gmin)          # the clamp before the next segment
+    got = Q.gamma
+    assert np.allclose(got[ok], expect[ok], rtol=1e-9)
+
+
+def test_ratio_keeps_the_classical_white_noise_bath_at_gamma0():
+    # classical bath on free particles satisfies the FDT, Re C_vF = m gamma0 C_vv in
+    # expectation: the RATIO estimate stays at gamma0 where the spectra have weight
+    Q = _free_qtb("RATIO", tau=200.0, n=600, nseg=64)
+    Q.step(Q.nseg * 6)
+    g = Q.gamma
+    band = slice(0, 8)           # omega_k = pi k / (N dt): the low-frequency part
+    rel = g[:, band] / 0.02
+    assert np.all(np.abs(rel - 1.0) < 0.15), rel
+
+
+def test_ratio_running_mean_recursion():
+    # <C>_k = <C>_{k-1} e^{-N dt / tau} + C_k (1 - e^{-N dt / tau}), started from zero, with
+    # C_k the type-averaged spectra of segment k
+    from oracle import qtb as oq
+    tau = 150.0
+    Q = _free_qtb("RATIO", tau=tau, n=60, nseg=32)
+    decay = math.exp(-Q.nseg * Q.dt / tau)
+    prev = np.zeros_like(Q.avg_vv)
+    for _ in range(3):
+        noise = Q.noise.copy()
+        Q.step(Q.nseg)
+        Cvv, _ = oq.spectra(Q.vrec, noise, Q.dt)
+        vv = np.stack([Cvv[Q.types == z].mean(axis=(0, 1)) for z in range(2)])
+        assert np.allclose(Q.avg_vv, prev * decay + vv * (1.0 - decay), rtol=1e-12, atol=0)
+        prev = Q.avg_vv.copy()

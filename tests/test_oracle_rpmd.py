@@ -121,3 +121,63 @@ def test_A_block_is_exact_free_ring_polymer():
         assert np.allclose(R.Q[n], exact.real, atol=1e-12)
         assert np.allclose(R.Pm[n] / (MH * wn), exact.imag, atol=1e-12)
     assert np.allclose(R.Q[0], Q0[0] + 3.7 * P0[0] / MH)
+
+
+# ---------------------------------------------------------------- BCOCB (Cayley A step)
+def _free_modes(P=8, N=5, seed=4):
+    rng = np.random.default_rng(seed)
+    m = rng.uniform(1.0, 16.0, N) * synth.AMU
+    R = rpmd.RPMD(P, m, KT, HBAR, 0.5, 0.001, 2.0, 1, lambda x: (None, np.zeros_like(x)),
+                  integrator="BCOCB")
+    R.Q = rng.standard_normal((P, N, 3)) * 0.1
+    R.Pm = rng.standard_normal((P, N, 3)) * np.sqrt(m * KT)[None, :, None]
+    return R, m
+
+
+def test_cayley_step_is_the_implicit_midpoint_rule():
+    # Q' - Q = h (P + P') / 2m and P' - P = -h m w^2 (Q + Q') / 2 for every internal mode
+    R, m = _free_modes()
+    h = 0.7
+    Q0, P0 = R.Q.copy(), R.Pm.copy()
+    R.A(h)
+    w = R.omega[:, None, None]
+    mm = m[None, :, None]
+    lhs_q, rhs_q = R.Q - Q0, h * (P0 + R.Pm) / (2 * mm)
+    lhs_p, rhs_p = R.Pm - P0, -h * mm * w * w * (Q0 + R.Q) / 2
+    assert np.allclose(lhs_q, rhs_q, rtol=1e-12, atol=1e-15)
+    assert np.allclose(lhs_p[1:], rhs_p[1:], rtol=1e-12, atol=1e-15 * np.abs(P0).max())
+    assert np.allclose(lhs_p[0], 0.0) and np.allclose(R.Q[0], Q0[0] + h * P0[0] / m[:, None])
+
+
+def test_cayley_step_conserves_each_mode_energy_even_for_large_steps():
+    # the implicit midpoint rule conserves the quadratic invariant of a linear flow exactly,
+    # whatever w h is (where the exact rotation would simply be periodic)
+    R, m = _free_modes(P=32)
+    w = R.omega[:, None, None]
+    mm = m[None, :, None]
+
+    def energy():
+        return R.Pm ** 2 / (2 * mm) + 0.5 * mm * (w * R.Q) ** 2
+
+    e0 = energy()
+    for h in (0.1, 3.0, 50.0):
+        R.A(h)
+        assert np.allclose(energy()[1:], e0[1:], rtol=1e-12)
+
+
+def test_bcocb_samples_the_free_ring_polymer_exactly():
+    # C preserves the mode energy and O is exact: the internal modes sample kT / (m w^2)
+    P, N = 8, 1500
+    kT, hbar = 1.0, 1.0
+    m = np.ones(N)
+    R = rpmd.RPMD(P, m, kT, hbar, 0.4, 1.0, 2.0, 77, lambda x: (None, np.zeros_like(x)),
+                  integrator="BCOCB")
+    rng = np.random.default_rng(2)
+    R.set_state(rng.standard_normal((P, N, 3)) * 0.1, rng.standard_normal((P, N, 3)))
+    R.step(200)
+    acc = np.zeros(P)
+    for _ in range(40):
+        R.step(5)
+        acc += (R.Q ** 2).mean(axis=(1, 2))
+    got = acc / 40 * R.omega ** 2 / kT
+    assert np.allclose(got[1:], 1.0, atol=0.04), got
