@@ -72,6 +72,15 @@ extern "C" {
 #define QHP_TRPMD 0     /* white-noise Langevin on every normal mode                 */
 #define QHP_ADQTB 1     /* adaptive quantum thermal bath (requires P = 1)             */
 
+/* free ring-polymer step of the splitting (Sec. "Integration Scheme") */
+#define QHP_BAOAB 0     /* exact rotation of each internal mode                      */
+#define QHP_BCOCB 1     /* its Cayley form (implicit midpoint rule): stable for any
+                           omega_n dt, after Korol, Bou-Rabee and Miller              */
+
+/* adQTB adaptation (Sec. "Computation of the adQTB Spectra and Adaptation Procedure") */
+#define QHP_QTB_SIMPLE 0 /* gamma <- gamma - A_gamma Delta_FDT                        */
+#define QHP_QTB_RATIO  1 /* gamma <- Re<C_vF> / (m <C_vv>), running means over tau    */
+
 /* per-bead energy terms */
 #define QHP_E_BOND       0
 #define QHP_E_ANGLE      1
@@ -127,6 +136,11 @@ typedef struct qhp_params {
    * QHP_BATCHED and thermostat = QHP_TRPMD (else QHP_EUNSUPPORTED). */
   int32_t rpc_beads;        /* P~: a power of two <= P; 0 = P (no contraction)          */
   int32_t respa_nalt;       /* n: inner steps per outer step, 1..64; 0 = 1               */
+  int32_t integrator;       /* QHP_BAOAB | QHP_BCOCB                                      */
+  int32_t qtb_adapt_scheme; /* QHP_QTB_SIMPLE | QHP_QTB_RATIO                             */
+  double qtb_tau;           /* RATIO: running-mean time tau (same for every type), > 0.
+                               The means start from zero; where <C_vv> <= 0 gamma keeps
+                               its value; the gamma_min clamp follows either scheme.    */
 } qhp_params;
 
 typedef struct qhp_ctx qhp_ctx;

@@ -19,6 +19,8 @@ MEM_HOST, MEM_DEVICE = 0, 1
 FP64, FP32_PAIRS = 0, 1
 BATCHED, PLAIN = 0, 1
 TRPMD, ADQTB = 0, 1
+BAOAB, BCOCB = 0, 1
+QTB_SIMPLE, QTB_RATIO = 0, 1
 NTERMS = 7
 TERMS = ("bond", "angle", "coul_real", "lj", "coul_excl", "coul_self", "coul_recip")
 PROF = {"off": 0, "pair": 1, "spread": 2, "fft": 3, "gather": 4, "nm": 5}
@@ -52,6 +54,7 @@ class Params(C.Structure):
         ("qtb_gamma_min_frac", C.c_double), ("qtb_classical", C.c_int32),
         ("nbr_capacity", C.c_int32), ("use_graph", C.c_int32),
         ("rpc_beads", C.c_int32), ("respa_nalt", C.c_int32),
+        ("integrator", C.c_int32), ("qtb_adapt_scheme", C.c_int32), ("qtb_tau", C.c_double),
     ]
 
 
@@ -109,7 +112,8 @@ class Context:
                  pme_grid, pme_order, dt, kT, hbar, gamma_centroid=0.0, trpmd_c=2.0, seed=0,
                  precision=FP64, exec_mode=BATCHED, thermostat=TRPMD, qtb_gamma0=0.0,
                  qtb_nseg=1024, qtb_adapt_rate=0.0, qtb_gamma_min_frac=0.01, qtb_classical=False,
-                 nbr_capacity=0, use_graph=True, rpc_beads=0, respa_nalt=1, stream=None):
+                 nbr_capacity=0, use_graph=True, rpc_beads=0, respa_nalt=1, integrator=0,
+                 qtb_adapt_scheme=0, qtb_tau=0.0, stream=None):
         self._lib = load()
         self.N, self.P = int(n_atoms), int(n_beads)
         self.n_types = len(lj_sigma)
@@ -141,6 +145,7 @@ class Context:
         p.nbr_capacity = nbr_capacity
         p.use_graph = int(bool(use_graph))
         p.rpc_beads, p.respa_nalt = int(rpc_beads), int(respa_nalt)
+        p.integrator, p.qtb_adapt_scheme, p.qtb_tau = int(integrator), int(qtb_adapt_scheme), qtb_tau
         self.params = p
         h = C.c_void_p()
         rc = self._lib.qhp_create(C.byref(p), C.c_void_p(stream) if stream else None, C.byref(h))

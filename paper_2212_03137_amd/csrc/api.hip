@@ -108,7 +108,8 @@ void free_all(qhp_ctx* c) {
                   c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
                   c->nnbr, c->bmax, c->grid, c->tile_nbr, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
                   c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
-                  c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.d_tmass, c->qtb.d_inv_count,
+                  c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.vvsum, c->qtb.vfsum,
+                  c->qtb.avg_vv, c->qtb.avg_vf, c->qtb.d_tmass, c->qtb.d_inv_count,
                   c->qtb.tw2, c->qtb.tw4};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -170,6 +171,11 @@ int validate(const qhp_params* p, std::string& why) {
   if (p->rpc_beads < 0 || p->rpc_beads > p->n_beads || (p->rpc_beads > 0 && !pow2(p->rpc_beads)))
     return bad("rpc_beads must be 0 or a power of two <= n_beads");
   if (p->respa_nalt < 0 || p->respa_nalt > 64) return bad("respa_nalt must be in 0..64");
+  if (p->integrator != QHP_BAOAB && p->integrator != QHP_BCOCB) return bad("integrator");
+  if (p->qtb_adapt_scheme != QHP_QTB_SIMPLE && p->qtb_adapt_scheme != QHP_QTB_RATIO)
+    return bad("qtb_adapt_scheme");
+  if (p->thermostat == QHP_ADQTB && p->qtb_adapt_scheme == QHP_QTB_RATIO && !(p->qtb_tau > 0))
+    return bad("qtb_tau must be > 0 for RATIO adaptation");
   {
     const int ps = p->rpc_beads > 0 ? p->rpc_beads : p->n_beads;
     const int na = p->respa_nalt > 0 ? p->respa_nalt : 1;
@@ -253,9 +259,18 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   const double h = 0.5 * p->dt;
   std::vector<double> mc(P), msw(P), mws(P), mc1(P), mc2(P), mw2(P);
   for (int n = 0; n < P; ++n) {
-    mc[n] = std::cos(w[n] * h);
-    msw[n] = w[n] > 0 ? std::sin(w[n] * h) / w[n] : h;
-    mws[n] = w[n] * std::sin(w[n] * h);
+    if (p->integrator == QHP_BCOCB) {
+      // Cayley form of the rotation (implicit midpoint rule of the free ring-polymer flow):
+      // Q' = ((1 - a^2) Q + h P / m) / (1 + a^2), P' = (-m w^2 h Q + (1 - a^2) P) / (1 + a^2)
+      const double a2 = 0.25 * w[n] * w[n] * h * h;
+      mc[n] = (1.0 - a2) / (1.0 + a2);
+      msw[n] = h / (1.0 + a2);
+      mws[n] = w[n] * w[n] * h / (1.0 + a2);
+    } else {
+      mc[n] = std::cos(w[n] * h);
+      msw[n] = w[n] > 0 ? std::sin(w[n] * h) / w[n] : h;
+      mws[n] = w[n] * std::sin(w[n] * h);
+    }
     const double gam = std::max(p->gamma_centroid, p->trpmd_c * w[n]);
     mc1[n] = std::exp(-gam * p->dt);
     mc2[n] = std::sqrt(1.0 - mc1[n] * mc1[n]);
@@ -418,6 +433,11 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     const int nk = p->n_types * (q.nseg + 1);
     TRY(dalloc(&q.gamma, nk)); TRY(dalloc(&q.dsum, nk)); TRY(dalloc(&q.dbar, nk));
     TRY(hipMemset(q.dbar, 0, nk * sizeof(double)));
+    if (p->qtb_adapt_scheme == QHP_QTB_RATIO) {
+      TRY(dalloc(&q.vvsum, nk)); TRY(dalloc(&q.vfsum, nk));
+      TRY(dalloc(&q.avg_vv, nk)); TRY(dalloc(&q.avg_vf, nk));
+      for (double* z : {q.vvsum, q.vfsum, q.avg_vv, q.avg_vf}) TRY(hipMemset(z, 0, nk * sizeof(double)));
+    }
     TRY(dalloc(&q.hhat, (size_t)p->n_types * 4 * q.nseg));
     TRY(dalloc(&q.noise, (size_t)q.nseg * 3 * N));
     TRY(dalloc(&q.vrec, (size_t)q.nseg * 3 * N));

@@ -59,6 +59,10 @@ struct QtbState {
   double* vrec = nullptr;     // [nseg][3][N] recorded O-midpoint velocities
   double* dsum = nullptr;     // [n_types][nseg+1] summed Delta_FDT of the running segment
   double* dbar = nullptr;     // [n_types][nseg+1] type-averaged Delta_FDT of the last segment
+  double* vvsum = nullptr;    // [n_types][nseg+1] RATIO: summed C_vv of the running segment
+  double* vfsum = nullptr;    // [n_types][nseg+1] RATIO: summed Re C_vF
+  double* avg_vv = nullptr;   // [n_types][nseg+1] RATIO: running means (null for SIMPLE)
+  double* avg_vf = nullptr;
   double* d_tmass = nullptr;  // [n_types]
   double* d_inv_count = nullptr; // [n_types] 1 / (3 * atoms of the type)
   double2* tw2 = nullptr;     // twiddles of length 2 nseg

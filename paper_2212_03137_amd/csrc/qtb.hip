@@ -160,7 +160,10 @@ struct SpecArgs {
   const double* vrec; const double* noise;
   const double2* tw2;
   double dt;
-  double* dsum;           // [T][nseg+1]
+  double* dsum;           // [T][nseg+1] summed Delta_FDT
+  double* vvsum;          // [T][nseg+1] summed C_vv (RATIO only)
+  double* vfsum;          // [T][nseg+1] summed Re C_vF (RATIO only)
+  int ratio;
 };
 
 __global__ __launch_bounds__(NT) void k_qtb_spectra(SpecArgs A) {
@@ -168,8 +171,11 @@ __global__ __launch_bounds__(NT) void k_qtb_spectra(SpecArgs A) {
   const int Ns = A.nseg, L2 = 2 * Ns;
   double2* u = lds;
   double2* v = lds + L2;
-  double* acc = (double*)(lds + 2 * L2);     // [T][nseg+1]
-  for (int k = threadIdx.x; k < A.ntypes * (Ns + 1); k += blockDim.x) acc[k] = 0.0;
+  const int nk = A.ntypes * (Ns + 1);
+  double* acc = (double*)(lds + 2 * L2);     // [T][nseg+1] Delta; then C_vv, Re C_vF
+  double* avv = acc + nk;
+  double* avf = avv + nk;
+  for (int k = threadIdx.x; k < (A.ratio ? 3 : 1) * nk; k += blockDim.x) acc[k] = 0.0;
   const int ndof = 3 * A.N;
   const int d0 = blockIdx.x * A.dofs_per_block;
   const double sc = A.dt / Ns;
@@ -196,22 +202,52 @@ __global__ __launch_bounds__(NT) void k_qtb_spectra(SpecArgs A) {
       const double cvv = sc * (vr * vr + vi * vi);
       const double cvf = sc * (vr * fr + vi * fi);       // Re(V conj F)
       acc[ty * (Ns + 1) + k] += m * gz[k] * cvv - cvf;
+      if (A.ratio) {
+        avv[ty * (Ns + 1) + k] += cvv;
+        avf[ty * (Ns + 1) + k] += cvf;
+      }
     }
     __syncthreads();
   }
-  for (int k = threadIdx.x; k < A.ntypes * (Ns + 1); k += blockDim.x)
+  for (int k = threadIdx.x; k < nk; k += blockDim.x) {
     if (acc[k] != 0.0) atomicAdd(A.dsum + k, acc[k]);
+    if (A.ratio) {
+      if (avv[k] != 0.0) atomicAdd(A.vvsum + k, avv[k]);
+      if (avf[k] != 0.0) atomicAdd(A.vfsum + k, avf[k]);
+    }
+  }
 }
 
-// gamma <- max(gamma_min, gamma - A Delta_bar); keep Delta_bar for export; clear sums
-__global__ void k_qtb_adapt(int n, int nseg, double* gamma, double* dsum, double* dbar,
-                            const double* inv_count, double rate, double gmin) {
+// SIMPLE: gamma <- max(gamma_min, gamma - A Delta_bar). RATIO: the running means
+// <C> <- <C> decay + C_bar (1 - decay) of C_vv and Re C_vF, then gamma <- max(gamma_min,
+// Re<C_vF> / (m <C_vv>)) where <C_vv> > 0. Keep Delta_bar for export; clear the sums.
+struct AdaptArgs {
+  int n, nseg, ratio;
+  double* gamma; double* dsum; double* dbar; double* vvsum; double* vfsum;
+  double* avg_vv; double* avg_vf;
+  const double* inv_count; const double* tmass;
+  double rate, gmin, decay;
+};
+
+__global__ void k_qtb_adapt(AdaptArgs A) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double d = dsum[i] * inv_count[i / (nseg + 1)];
-  dbar[i] = d;
-  gamma[i] = fmax(gmin, gamma[i] - rate * d);
-  dsum[i] = 0.0;
+  if (i >= A.n) return;
+  const int z = i / (A.nseg + 1);
+  const double ic = A.inv_count[z];
+  const double d = A.dsum[i] * ic;
+  A.dbar[i] = d;
+  double g = A.gamma[i] - A.rate * d;
+  if (A.ratio) {
+    const double vv = A.avg_vv[i] * A.decay + A.vvsum[i] * ic * (1.0 - A.decay);
+    const double vf = A.avg_vf[i] * A.decay + A.vfsum[i] * ic * (1.0 - A.decay);
+    A.avg_vv[i] = vv;
+    A.avg_vf[i] = vf;
+    g = vv > 0.0 ? vf / (A.tmass[z] * vv) : A.gamma[i];
+    A.vvsum[i] = 0.0;
+    A.vfsum[i] = 0.0;
+  }
+  A.gamma[i] = fmax(A.gmin, g);
+  A.dsum[i] = 0.0;
 }
 
 __global__ void k_fill(double* p, int n, double v) {
@@ -249,14 +285,19 @@ hipError_t launch_qtb_adapt(qhp_ctx* c) {
   A.N = c->N; A.nseg = q.nseg; A.ntypes = c->p.n_types; A.dofs_per_block = 32;
   A.type = c->d_type; A.mass = c->d_mass; A.gamma = q.gamma; A.vrec = q.vrec; A.noise = q.noise;
   A.tw2 = q.tw2; A.dt = c->p.dt; A.dsum = q.dsum;
+  A.vvsum = q.vvsum; A.vfsum = q.vfsum;
+  A.ratio = c->p.qtb_adapt_scheme == QHP_QTB_RATIO;
   const int nb = (3 * c->N + A.dofs_per_block - 1) / A.dofs_per_block;
   const size_t lds = (size_t)4 * q.nseg * sizeof(double2) +
-                     (size_t)c->p.n_types * (q.nseg + 1) * sizeof(double);
+                     (size_t)(A.ratio ? 3 : 1) * c->p.n_types * (q.nseg + 1) * sizeof(double);
   hipLaunchKernelGGL(k_qtb_spectra, nb, NT, lds, c->stream, A);
-  const int n = c->p.n_types * (q.nseg + 1);
-  hipLaunchKernelGGL(k_qtb_adapt, (n + 255) / 256, 256, 0, c->stream, n, q.nseg, q.gamma, q.dsum,
-                     q.dbar, q.d_inv_count, c->p.qtb_adapt_rate,
-                     c->p.qtb_gamma_min_frac * c->p.qtb_gamma0);
+  AdaptArgs D;
+  D.n = c->p.n_types * (q.nseg + 1); D.nseg = q.nseg; D.ratio = A.ratio;
+  D.gamma = q.gamma; D.dsum = q.dsum; D.dbar = q.dbar; D.vvsum = q.vvsum; D.vfsum = q.vfsum;
+  D.avg_vv = q.avg_vv; D.avg_vf = q.avg_vf; D.inv_count = q.d_inv_count; D.tmass = q.d_tmass;
+  D.rate = c->p.qtb_adapt_rate; D.gmin = c->p.qtb_gamma_min_frac * c->p.qtb_gamma0;
+  D.decay = A.ratio ? std::exp(-q.nseg * c->p.dt / c->p.qtb_tau) : 0.0;
+  hipLaunchKernelGGL(k_qtb_adapt, (D.n + 255) / 256, 256, 0, c->stream, D);
   return hipGetLastError();
 }
 
@@ -264,5 +305,9 @@ hipError_t qtb_reset_gamma(qhp_ctx* c) {
   const int n = c->p.n_types * (c->qtb.nseg + 1);
   hipLaunchKernelGGL(k_fill, (n + 255) / 256, 256, 0, c->stream, c->qtb.gamma, n, c->p.qtb_gamma0);
   hipLaunchKernelGGL(k_fill, (n + 255) / 256, 256, 0, c->stream, c->qtb.dsum, n, 0.0);
+  if (c->qtb.avg_vv) {
+    for (double* p : {c->qtb.vvsum, c->qtb.vfsum, c->qtb.avg_vv, c->qtb.avg_vf})
+      hipLaunchKernelGGL(k_fill, (n + 255) / 256, 256, 0, c->stream, p, n, 0.0);
+  }
   return hipGetLastError();
 }

@@ -164,6 +164,32 @@ def test_rpmd_trajectory_small(small, nsteps):
     assert math.isclose(spr, R.spring(), rel_tol=tol * 100)
 
 
+@pytest.mark.parametrize("nsteps", [1, 60])
+def test_bcocb_trajectory_small(small, nsteps):
+    """The Cayley (BCOCB) free ring-polymer step against the oracle's implicit-midpoint form."""
+    import paper_2212_03137_amd as q
+    from oracle import rpmd
+    s, _ = small
+    say("bcocb trajectory", nsteps)
+    R = rpmd.RPMD(s.n_beads, s.mass, s.kT, s.hbar, s.dt, s.gamma_centroid, s.trpmd_c, s.seed,
+                  oracle_grad_fn(s), integrator="BCOCB")
+    R.set_state(s.pos, s.vel)
+    R.step(nsteps)
+    xr, vr, _ = R.get_state()
+    with ctx_for(s, integrator=q.BCOCB) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(nsteps)
+        x, v, st = c.get_state()
+    assert st == nsteps
+    tol = 1e-11 if nsteps == 1 else 1e-8
+    assert np.abs(x - xr).max() / np.abs(xr).max() < tol
+    assert np.abs(v - vr).max() / np.abs(vr).max() < tol * 100
+    # and it is a different integrator from BAOAB
+    R2 = _oracle_rpmd(s)
+    R2.step(nsteps)
+    assert np.abs(R2.get_state()[0] - xr).max() > 1e3 * tol * np.abs(xr).max()
+
+
 def test_rpmd_trajectory_plain_fp64_equals_batched(small):
     import paper_2212_03137_amd as q
     s, _ = small

@@ -94,3 +94,31 @@ def test_state_must_start_on_a_segment_boundary():
     with _ctx(s) as c:
         with pytest.raises(q.QhpError):
             c.set_state(s.pos, s.vel, 5)
+
+
+def test_ratio_adaptation_over_segments_matches_oracle():
+    import paper_2212_03137_amd as q
+    s = _system(64)
+    tau = 150.0
+    Q = oq.QTB(s.mass, s.types, s.n_types, s.kT, s.hbar, s.dt, s.qtb_gamma0, s.qtb_nseg,
+               s.qtb_adapt_rate, s.qtb_gamma_min_frac, s.seed, oracle_grad_fn(s),
+               scheme="RATIO", tau=tau)
+    Q.set_state(s.pos, s.vel, 0)
+    with _ctx(s, qtb_adapt_scheme=q.QTB_RATIO, qtb_tau=tau) as c:
+        c.set_state(s.pos, s.vel, 0)
+        for seg in range(3):
+            Q.step(64)
+            c.step(64)
+            g = c.qtb_gamma()
+            assert np.abs(g - Q.gamma).max() <= 1e-7 * np.abs(Q.gamma).max(), seg
+            assert np.abs(c.qtb_noise() - Q.noise).max() <= 1e-6 * np.abs(Q.noise).max()
+        x, v, _ = c.get_state()
+    xr, vr, _ = Q.get_state()
+    assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-7
+
+
+def test_ratio_needs_a_positive_tau():
+    import paper_2212_03137_amd as q
+    s = _system(32)
+    with pytest.raises(q.QhpError):
+        _ctx(s, qtb_adapt_scheme=q.QTB_RATIO, qtb_tau=0.0)
