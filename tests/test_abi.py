@@ -35,6 +35,7 @@ def test_params_struct_matches_header_fields():
     import paper_2212_03137_amd as q
     src = open(os.path.join(ROOT, "include", "qhp.h")).read()
     body = src[src.index("typedef struct qhp_params {"):src.index("} qhp_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)          # comments
     fields = re.findall(r"^\s*(?:const\s+)?[\w]+\**\s+\**([\w, ]+?)(?:\[\d\])?;", body, flags=re.M)
     names = []
     for f in fields:
