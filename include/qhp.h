@@ -164,6 +164,17 @@ QHP_API int qhp_destroy(qhp_ctx* ctx);
  * Does not change the propagated state (a later step rebuilds the list if it must). */
 QHP_API int qhp_eval(qhp_ctx* ctx, const double* pos, double* energy, double* forces, int mem_kind);
 
+/* Gradients of the summed bead energies E = sum_b V(x_b) (eq. PI_potential without the
+ * 1/P) at `pos` [P][N][3] with respect to the force-field parameters: `dq` [N] per-atom
+ * charges (real-space, exclusion, self and reciprocal terms; the reciprocal part is the
+ * SPME-interpolated potential at the atom), `deps` [n_types] and `dsig` [n_types] per-type
+ * LJ epsilon and sigma (Lorentz-Berthelot combination; the epsilon derivative of a type
+ * with epsilon = 0 is unbounded and returned as 0). Pair terms in FP64 whatever
+ * `precision` is. Builds the list of these positions like qhp_eval and leaves the
+ * propagated state alone. QHP_EUNSUPPORTED for exec = QHP_PLAIN. */
+QHP_API int qhp_param_grad(qhp_ctx* ctx, const double* pos, double* dq, double* deps,
+                           double* dsig, int mem_kind);
+
 /* Set the propagated state from bead positions and bead velocities [P][N][3] and the
  * step counter (which indexes the noise streams). Computes the normal modes
  * Q = T^T x / sqrt(P), P_n = m T^T v / sqrt(P) and the forces of this state (under

@@ -28,7 +28,7 @@ PROF = {"off": 0, "pair": 1, "spread": 2, "fft": 3, "gather": 4, "nm": 5}
 EXPORTS = ("qhp_create", "qhp_destroy", "qhp_eval", "qhp_set_state", "qhp_get_state",
            "qhp_step", "qhp_mode_energies", "qhp_nlist_export", "qhp_nlist_stats", "qhp_noise_export",
            "qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta",
-           "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error")
+           "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error", "qhp_param_grad")
 
 
 class QhpError(RuntimeError):
@@ -82,6 +82,7 @@ def load():
     lib.qhp_nlist_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]
     lib.qhp_noise_export.argtypes = [vp, C.c_int32, C.c_int64, vp]
+    lib.qhp_param_grad.argtypes = [vp, vp, vp, vp, vp, I]
     for f in ("qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta"):
         getattr(lib, f).argtypes = [vp, vp]
     lib.qhp_profile.argtypes = [vp, I]
@@ -198,6 +199,16 @@ class Context:
         F = np.zeros((self.P, self.N, 3))
         self._check(self._lib.qhp_eval(self._h, _ptr(pos), _ptr(E), _ptr(F), MEM_HOST))
         return E, F
+
+    def param_grad(self, pos):
+        """d(sum of bead energies) / d(charges [N], lj_epsilon [T], lj_sigma [T])."""
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        dq = np.zeros(self.N)
+        de = np.zeros(self.n_types)
+        ds = np.zeros(self.n_types)
+        self._check(self._lib.qhp_param_grad(self._h, _ptr(pos), _ptr(dq), _ptr(de), _ptr(ds),
+                                             MEM_HOST))
+        return dq, de, ds
 
     def set_state(self, pos, vel, step=0):
         pos = np.ascontiguousarray(pos, dtype=np.float64)

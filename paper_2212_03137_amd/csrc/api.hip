@@ -107,7 +107,8 @@ void free_all(qhp_ctx* c) {
                   c->Q, c->Pa, c->x, c->g, c->cent, c->cref, c->coff, c->cwrap, c->xf, c->ctrl,
                   c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
                   c->nnbr, c->bmax, c->grid, c->tile_nbr, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
-                  c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
+                  c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->pg_dq, c->pg_lj,
+                  c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.vvsum, c->qtb.vfsum,
                   c->qtb.avg_vv, c->qtb.avg_vf, c->qtb.d_tmass, c->qtb.d_inv_count,
                   c->qtb.tw2, c->qtb.tw4};
@@ -302,6 +303,7 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   TRY(dalloc(&c->cent, N)); TRY(dalloc(&c->cref, N)); TRY(dalloc(&c->coff, N)); TRY(dalloc(&c->cwrap, N));
   TRY(dalloc(&c->xf, (size_t)N * P));
   TRY(dalloc(&c->io_a, NP3)); TRY(dalloc(&c->io_b, NP3)); TRY(dalloc(&c->g_eval, NP3));
+  TRY(dalloc(&c->pg_dq, N)); TRY(dalloc(&c->pg_lj, 2 * QHP_MAX_TYPES));
   TRY(dalloc(&c->energy, (size_t)P * QHP_NTERMS));
   // ---- multiple time stepping / ring-polymer contraction ----
   c->Ps = p->rpc_beads > 0 ? p->rpc_beads : P;
@@ -562,6 +564,39 @@ extern "C" int qhp_eval(qhp_ctx* c, const double* pos, double* energy, double* f
   }
   if ((r = copy_out_energy(c, energy, mem_kind))) return r;
   if (mem_kind == QHP_MEM_HOST) return check_ctrl(c);
+  return QHP_OK;
+}
+
+extern "C" int qhp_param_grad(qhp_ctx* c, const double* pos, double* dq, double* deps,
+                              double* dsig, int mem_kind) {
+  if (!c || !pos || !dq || !deps || !dsig) return qhp_fail(c, QHP_EINVAL, "null argument");
+  if (c->p.exec == QHP_PLAIN)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients need exec = QHP_BATCHED");
+  int r = copy_in(c, pos, mem_kind, c->x);
+  if (r) return r;
+  QHP_HIP(c, launch_centroid_of_beads(c));
+  QHP_HIP(c, launch_zero(c, c->pg_dq, (size_t)c->N * sizeof(double)));
+  QHP_HIP(c, launch_zero(c, c->pg_lj, 2 * QHP_MAX_TYPES * sizeof(double)));
+  // forces go to scratch (c->g holds the propagated state's); the pair terms always take
+  // the FP64 kernel here
+  std::swap(c->g, c->g_eval);
+  BeadSet B = full_beads(c);
+  B.pgrad = 1;
+  hipError_t e = launch_nlist(c, false);
+  if (e == hipSuccess) e = launch_bonded(c, false, -1, &B);
+  if (e == hipSuccess) e = launch_pair(c, false, -1, &B);
+  if (e == hipSuccess) e = launch_spme(c, false, -1, &B);
+  std::swap(c->g, c->g_eval);
+  QHP_HIP(c, e);
+  const int T = c->p.n_types;
+  const hipMemcpyKind k = mem_kind == QHP_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  QHP_HIP(c, hipMemcpyAsync(dq, c->pg_dq, (size_t)c->N * sizeof(double), k, c->stream));
+  QHP_HIP(c, hipMemcpyAsync(deps, c->pg_lj, T * sizeof(double), k, c->stream));
+  QHP_HIP(c, hipMemcpyAsync(dsig, c->pg_lj + QHP_MAX_TYPES, T * sizeof(double), k, c->stream));
+  if (mem_kind == QHP_MEM_HOST) {
+    QHP_HIP(c, hipStreamSynchronize(c->stream));
+    return check_ctrl(c);
+  }
   return QHP_OK;
 }
 

@@ -19,6 +19,7 @@ struct BondArgs {
   double L[3], invL[3];
   double r0, kb, th0, kth, alpha, coulomb;
   double* energy;
+  double* dq;              // parameter gradients: d/d charge (exclusion and self terms)
 };
 
 template <int P>
@@ -34,13 +35,17 @@ QHP_DEV void reduce_energy_by_bead(double* sred, int tid, double v, double* dst)
   __syncthreads();
 }
 
-template <int P, bool ENERGY, int TERMS>
+// PG: also add the charge derivatives of the exclusion correction (-C q_b erf(alpha r)/r
+// for atom a of each excluded pair, and symmetrically) and of the self term
+// (-2 C alpha / sqrt(pi) q per bead), summed over the beads of each water.
+template <int P, bool ENERGY, int TERMS, bool PG = false>
 __global__ __launch_bounds__(NT) void k_bonded(BondArgs A) {
   constexpr int AT = NT / P;
   __shared__ double sred[NT];
   const int tid = threadIdx.x, b = tid % P;
   const int w = blockIdx.x * AT + tid / P;
   double eb = 0, ea = 0, ex = 0;
+  double pq[3] = {0.0, 0.0, 0.0};
   if (w < A.NW) {
     const int N = A.N;
     double X[3][3], G[3][3];
@@ -95,6 +100,10 @@ __global__ __launch_bounds__(NT) void k_bonded(BondArgs A) {
       const double qq = A.coulomb * A.charge[3 * w + pa[e]] * A.charge[3 * w + pb[e]];
       const double erfv = erf(A.alpha * rr);
       if (ENERGY) ex += -qq * erfv / rr;
+      if (PG) {
+        pq[pa[e]] += -A.coulomb * A.charge[3 * w + pb[e]] * erfv / rr;
+        pq[pb[e]] += -A.coulomb * A.charge[3 * w + pa[e]] * erfv / rr;
+      }
       const double dEdr = -qq * (c2a * exp(-A.alpha * A.alpha * r2) / rr - erfv / r2);
       const double s = dEdr / rr;
       for (int d = 0; d < 3; ++d) {
@@ -105,6 +114,14 @@ __global__ __launch_bounds__(NT) void k_bonded(BondArgs A) {
     }
     for (int k = 0; k < 3; ++k)
       for (int d = 0; d < 3; ++d) A.g[(d * N + 3 * w + k) * P + b] = G[k][d];
+    if (PG)
+      for (int k = 0; k < 3; ++k) pq[k] += -2.0 * A.coulomb * A.alpha / sqrt(M_PI) * A.charge[3 * w + k];
+  }
+  if (PG) {                          // sum over the P bead lanes of the water
+    for (int o = 1; o < P; o <<= 1)
+      for (int k = 0; k < 3; ++k) pq[k] += __shfl_xor(pq[k], o);
+    if (w < A.NW && b == 0)
+      for (int k = 0; k < 3; ++k) A.dq[3 * w + k] += pq[k];
   }
   if (ENERGY && (TERMS & QHP_TERMS_BONDED)) {
     reduce_energy_by_bead<P>(sred, tid, eb, A.energy + QHP_E_BOND);
@@ -153,6 +170,7 @@ hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   A.r0 = c->p.bond_r0; A.kb = c->p.bond_k; A.th0 = c->p.angle_theta0; A.kth = c->p.angle_k;
   A.alpha = c->p.ewald_alpha; A.coulomb = c->p.coulomb;
   A.energy = (plain ? c->energy : B.energy) + (plain ? (size_t)bead * QHP_NTERMS : 0);
+  A.dq = c->pg_dq;
   const int P = plain ? 1 : B.P;
   const int terms = plain ? QHP_TERMS_ALL : B.terms;
   // the launch that carries the bonds initialises the energy rows of the whole step; under
@@ -167,7 +185,9 @@ hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
 #define BONDED_CALL(TT)                                                                           \
   QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_bonded<PP, true, TT>), nb, NT, 0, c->stream, A); \
                else hipLaunchKernelGGL((k_bonded<PP, false, TT>), nb, NT, 0, c->stream, A))
-  if (terms == QHP_TERMS_BONDED) { BONDED_CALL(QHP_TERMS_BONDED); }
+  if (!plain && B.pgrad && terms == QHP_TERMS_ALL) {
+    QHP_SWITCH_P(P, hipLaunchKernelGGL((k_bonded<PP, false, QHP_TERMS_ALL, true>), nb, NT, 0, c->stream, A));
+  } else if (terms == QHP_TERMS_BONDED) { BONDED_CALL(QHP_TERMS_BONDED); }
   else if (terms == QHP_TERMS_EXCL) { BONDED_CALL(QHP_TERMS_EXCL); }
   else { BONDED_CALL(QHP_TERMS_ALL); }
 #undef BONDED_CALL

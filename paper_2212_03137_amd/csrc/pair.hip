@@ -49,6 +49,9 @@ struct PairArgs {
   double lj_s6[QHP_MAX_TYPES * QHP_MAX_TYPES];
   double lj_e4[QHP_MAX_TYPES * QHP_MAX_TYPES];
   int ntypes;
+  double lj_sig[QHP_MAX_TYPES * QHP_MAX_TYPES];   // sigma_ij (parameter gradients)
+  double eps_of[QHP_MAX_TYPES];                    // epsilon of each type
+  double* dq; double* deps; double* dsig;          // parameter-gradient outputs (FP64 path)
   int nblocks;            // logical blocks
   const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
   double* energy;         // [P][NTERMS] (plain: the bead's row)
@@ -88,7 +91,11 @@ QHP_DEV void flush(const PairArgs& A, int i, int lane, double gx, double gy, dou
   }
 }
 
-template <int P, bool ENERGY>
+// PG: also accumulate the derivatives of the summed bead energies with respect to the
+// charge of atom i (C q_j erfc(alpha r)/r per in-range pair, visited from i's end) and to
+// the LJ epsilon and sigma of i's type (the i-side halves of d e_ij and d s_ij; the j side
+// is added when the pair is visited from j).
+template <int P, bool ENERGY, bool PG = false>
 __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
   constexpr int S = 64 / P;
   __shared__ int sj[WPB][64];
@@ -107,6 +114,9 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
   const int nn = A.nnbr[i];
   const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
+  double pq = 0, pe = 0, ps = 0;                  // parameter gradients (PG)
+  __shared__ double ssig[PG ? WPB : 1][PG ? 64 : 1];
+  const double half_over_eps = PG && A.eps_of[ti] > 0.0 ? 0.5 / A.eps_of[ti] : 0.0;
   for (int k0 = 0; k0 < nn; k0 += 64) {
     const int cnt = min(64, nn - k0);
     if (lane < cnt) {
@@ -115,6 +125,7 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
       sq[wv][lane] = qi * A.charge[j];
       const int tp = ti * A.ntypes + A.type[j];
       slj[wv][lane] = make_double2(A.lj_e4[tp], A.lj_s6[tp]);
+      if (PG) ssig[wv][lane] = A.lj_sig[tp];
     }
     wave_sync();
     for (int t = s; t < cnt; t += S) {
@@ -132,12 +143,17 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
         const double erfcv = erfc(A.alpha * r);
         double sc = qq * (erfcv * ir + c2a * exp(-A.alpha * A.alpha * r2)) * ir2;
         if (ENERGY) ec += qq * erfcv * ir;
+        if (PG) pq += A.coulomb * A.charge[j] * erfcv * ir;
         const double2 lj = slj[wv][t];
         const double e4 = lj.x;
         if (e4 != 0.0) {
           const double s6 = lj.y * ir2 * ir2 * ir2;
           sc += e4 * (12.0 * s6 * s6 - 6.0 * s6) * ir2;
           if (ENERGY) elj += e4 * (s6 * s6 - s6);
+          if (PG) {
+            pe += (s6 * s6 - s6) * e4 * half_over_eps;            // dE/de_ij * e_ij / (2 eps_i)
+            ps += 0.5 * e4 * (12.0 * s6 * s6 - 6.0 * s6) / ssig[wv][t];
+          }
         }
         gx += sc * dx; gy += sc * dy; gz += sc * dz;
       }
@@ -145,6 +161,18 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
     wave_sync();
   }
   flush<P, ENERGY>(A, i, lane, gx, gy, gz, ec, elj);
+  if (PG) {
+    for (int o = 1; o < 64; o <<= 1) {
+      pq += __shfl_xor(pq, o);
+      pe += __shfl_xor(pe, o);
+      ps += __shfl_xor(ps, o);
+    }
+    if (lane == 0) {
+      A.dq[i] += pq;
+      if (pe != 0.0) atomicAdd(A.deps + ti, pe);
+      if (ps != 0.0) atomicAdd(A.dsig + ti, ps);
+    }
+  }
 }
 
 // Compacted neighbours t0 + s, t0 + s + S, ... < cnt for the lane (slot s, bead b).
@@ -293,7 +321,10 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
       const double e = sqrt(c->eps[a] * c->eps[b]);
       A.lj_s6[a * A.ntypes + b] = s * s * s * s * s * s;
       A.lj_e4[a * A.ntypes + b] = 4.0 * e;
+      A.lj_sig[a * A.ntypes + b] = s;
     }
+  for (int a = 0; a < c->p.n_types; ++a) A.eps_of[a] = c->eps[a];
+  A.dq = c->pg_dq; A.deps = c->pg_lj; A.dsig = c->pg_lj + QHP_MAX_TYPES;
 
   A.energy = plain ? c->energy + (size_t)bead * QHP_NTERMS : B.energy;
   A.ctrl = c->ctrl;
@@ -302,14 +333,16 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   const unsigned nb = (unsigned)((A.nblocks + 7) / 8 * 8);
   const double Lmin = fmin(c->p.box[0], fmin(c->p.box[1], c->p.box[2]));
   const bool minimg = !(2.0 * (c->p.cutoff + c->p.skin) < Lmin);
-  const bool f32 = c->p.precision == QHP_FP32_PAIRS && !plain && !minimg;
+  const bool pg = bs && bs->pgrad;     // parameter gradients: always the FP64 kernel
+  const bool f32 = c->p.precision == QHP_FP32_PAIRS && !plain && !minimg && !pg;
   hipEvent_t ev = nullptr;
   prof_begin(c, QHP_PROF_PAIR, &ev);
   if (f32) {
     QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair32<PP, true>), nb, NT, 0, c->stream, A);
                  else hipLaunchKernelGGL((k_pair32<PP, false>), nb, NT, 0, c->stream, A));
   } else {
-    QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair64<PP, true>), nb, NT, 0, c->stream, A);
+    QHP_SWITCH_P(P, if (pg) hipLaunchKernelGGL((k_pair64<PP, false, true>), nb, NT, 0, c->stream, A);
+                 else if (energy) hipLaunchKernelGGL((k_pair64<PP, true>), nb, NT, 0, c->stream, A);
                  else hipLaunchKernelGGL((k_pair64<PP, false>), nb, NT, 0, c->stream, A));
   }
   prof_end(c, QHP_PROF_PAIR, ev);

@@ -45,6 +45,7 @@ struct BeadSet {
   const float4* xf;           // [N][P] FP32 bead - centroid offsets and charge
   double* energy;             // [P][QHP_NTERMS]
   int terms;                  // QHP_TERMS_* for launch_bonded
+  int pgrad = 0;              // also accumulate the parameter gradients (FP64 kernels)
 };
 #define QHP_TERMS_BONDED 1    // O-H bonds and H-O-H angles (V_f)
 #define QHP_TERMS_EXCL   2    // intramolecular Ewald exclusion correction (part of V_s)
@@ -158,6 +159,10 @@ struct qhp_ctx {
   double* Cs = nullptr;       // [Ps][Ps] contraction matrix C[j][n]
   double* pa_tmp = nullptr;   // [3][N][P] scratch momenta
   double* g_eval = nullptr;   // [3][N][P] gradient target of qhp_eval
+
+  // parameter gradients of the summed bead energies
+  double* pg_dq = nullptr;    // [N] d/d charge
+  double* pg_lj = nullptr;    // [2][QHP_MAX_TYPES] d/d epsilon, d/d sigma per type
 
   QtbState qtb;
 

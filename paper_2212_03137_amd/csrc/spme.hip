@@ -33,6 +33,7 @@ struct SpmeArgs {
   const double* charge;
   double L[3];
   double* energy;
+  double* dq;              // parameter gradients: d E_recip / d q = interpolated potential
 };
 
 template <int ORDER>
@@ -78,7 +79,9 @@ QHP_DEV int wrapk(int k, int K) { return k < 0 ? k + K : (k >= K ? k - K : k); }
 // physical block -> logical block so that XCD k (blocks k, k+8, ...) gets a contiguous range
 QHP_DEV int xcd_block(int bid, int nphys) { return (bid & 7) * (nphys >> 3) + (bid >> 3); }
 
-template <int P, int ORDER, bool ENERGY>
+// PG: also add the interpolated potential sum_k theta(k) phi(k) of every bead, summed over
+// the beads, to dq of the atom (the charge derivative of the reciprocal energy).
+template <int P, int ORDER, bool ENERGY, bool PG = false>
 __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
   __shared__ double sred[NT];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -111,13 +114,18 @@ __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
         f0 += dw[0][t0] * w[1][t1] * s;
         f1 += w[0][t0] * dw[1][t1] * s;
         f2 += w[0][t0] * w[1][t1] * sd;
-        if (ENERGY) e += w[0][t0] * w[1][t1] * s;
+        if (ENERGY || PG) e += w[0][t0] * w[1][t1] * s;
       }
     }
     const double q = A.charge[a];
     A.g[(0 * A.N + a) * P + b] += q * f0 * (double)A.K0 / A.L[0];
     A.g[(1 * A.N + a) * P + b] += q * f1 * (double)A.K1 / A.L[1];
     A.g[(2 * A.N + a) * P + b] += q * f2 * (double)A.K2 / A.L[2];
+    if (PG) {
+      double phi = e;                  // the P lanes of an atom are consecutive
+      for (int o = 1; o < P; o <<= 1) phi += __shfl_xor(phi, o);
+      if (b == 0) A.dq[a] += phi;
+    }
     e *= 0.5 * q;
   }
   if (ENERGY) {
@@ -568,6 +576,8 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   A.grid = (double*)c->grid; A.charge = c->d_charge;
   for (int d = 0; d < 3; ++d) A.L[d] = c->p.box[d];
   A.energy = plain ? c->energy + (size_t)bead * QHP_NTERMS : B.energy;
+  A.dq = c->pg_dq;
+  const bool pg = !plain && B.pgrad;
   const unsigned nb = (unsigned)(((size_t)N * P + NT - 1) / NT);
   hipEvent_t ev = nullptr;
   prof_begin(c, QHP_PROF_SPREAD, &ev);
@@ -620,7 +630,8 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   A.nblocks = (int)nb;
   const unsigned nb8 = (nb + 7) / 8 * 8;
   QHP_SWITCH_P(P, QHP_SWITCH_ORDER(c->p.pme_order,
-               if (energy) hipLaunchKernelGGL((k_gather<PP, OO, true>), nb8, NT, 0, c->stream, A);
+               if (pg) hipLaunchKernelGGL((k_gather<PP, OO, false, true>), nb8, NT, 0, c->stream, A);
+               else if (energy) hipLaunchKernelGGL((k_gather<PP, OO, true>), nb8, NT, 0, c->stream, A);
                else hipLaunchKernelGGL((k_gather<PP, OO, false>), nb8, NT, 0, c->stream, A)));
   prof_end(c, QHP_PROF_GATHER, ev);
   return hipGetLastError();
