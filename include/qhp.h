@@ -175,6 +175,18 @@ QHP_API int qhp_eval(qhp_ctx* ctx, const double* pos, double* energy, double* fo
 QHP_API int qhp_param_grad(qhp_ctx* ctx, const double* pos, double* dq, double* deps,
                            double* dsig, int mem_kind);
 
+/* Hessian-vector product of every bead's potential at `pos` [P][N][3] along `dir`
+ * [P][N][3]: out[b] = (d^2 V / dx^2)(x_b) dir_b, [P][N][3]. Exact analytic second
+ * derivatives (all terms: bonds, angle and exclusion by forward differentiation of their
+ * gradient; real-space pairs by the pair Hessian blocks; the SPME sum by spreading the
+ * tangent charge density, one more convolution and a gather with second-derivative
+ * B-splines), pair terms in FP64 whatever `precision` is, on the list of these positions.
+ * The potential is the truncated one: pairs crossing the cutoff contribute no delta
+ * terms. Leaves the propagated state alone; the first call allocates a second SPME grid
+ * and an output buffer that the context keeps. QHP_EUNSUPPORTED for exec = QHP_PLAIN. */
+QHP_API int qhp_hvp(qhp_ctx* ctx, const double* pos, const double* dir, double* out,
+                    int mem_kind);
+
 /* Set the propagated state from bead positions and bead velocities [P][N][3] and the
  * step counter (which indexes the noise streams). Computes the normal modes
  * Q = T^T x / sqrt(P), P_n = m T^T v / sqrt(P) and the forces of this state (under

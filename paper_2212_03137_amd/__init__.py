@@ -28,7 +28,8 @@ PROF = {"off": 0, "pair": 1, "spread": 2, "fft": 3, "gather": 4, "nm": 5}
 EXPORTS = ("qhp_create", "qhp_destroy", "qhp_eval", "qhp_set_state", "qhp_get_state",
            "qhp_step", "qhp_mode_energies", "qhp_nlist_export", "qhp_nlist_stats", "qhp_noise_export",
            "qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta",
-           "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error", "qhp_param_grad")
+           "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error", "qhp_param_grad",
+           "qhp_hvp")
 
 
 class QhpError(RuntimeError):
@@ -83,6 +84,7 @@ def load():
                                     C.POINTER(C.c_int32)]
     lib.qhp_noise_export.argtypes = [vp, C.c_int32, C.c_int64, vp]
     lib.qhp_param_grad.argtypes = [vp, vp, vp, vp, vp, I]
+    lib.qhp_hvp.argtypes = [vp, vp, vp, vp, I]
     for f in ("qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta"):
         getattr(lib, f).argtypes = [vp, vp]
     lib.qhp_profile.argtypes = [vp, I]
@@ -209,6 +211,14 @@ class Context:
         self._check(self._lib.qhp_param_grad(self._h, _ptr(pos), _ptr(dq), _ptr(de), _ptr(ds),
                                              MEM_HOST))
         return dq, de, ds
+
+    def hvp(self, pos, direction):
+        """Hessian-vector product of every bead's potential, [P][N][3]."""
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        d = np.ascontiguousarray(direction, dtype=np.float64)
+        out = np.zeros((self.P, self.N, 3))
+        self._check(self._lib.qhp_hvp(self._h, _ptr(pos), _ptr(d), _ptr(out), MEM_HOST))
+        return out
 
     def set_state(self, pos, vel, step=0):
         pos = np.ascontiguousarray(pos, dtype=np.float64)

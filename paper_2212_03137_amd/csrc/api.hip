@@ -106,8 +106,9 @@ void free_all(qhp_ctx* c) {
                   c->d_type, c->d_mass, c->d_charge, c->d_sqrt_mkT, c->d_sigma, c->d_eps,
                   c->Q, c->Pa, c->x, c->g, c->cent, c->cref, c->coff, c->cwrap, c->xf, c->ctrl,
                   c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
-                  c->nnbr, c->bmax, c->grid, c->tile_nbr, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
+                  c->nnbr, c->bmax, c->grid, c->grid2, c->tile_nbr, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
                   c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->pg_dq, c->pg_lj,
+                  c->hvp_out,
                   c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.vvsum, c->qtb.vfsum,
                   c->qtb.avg_vv, c->qtb.avg_vf, c->qtb.d_tmass, c->qtb.d_inv_count,
@@ -597,6 +598,38 @@ extern "C" int qhp_param_grad(qhp_ctx* c, const double* pos, double* dq, double*
     QHP_HIP(c, hipStreamSynchronize(c->stream));
     return check_ctrl(c);
   }
+  return QHP_OK;
+}
+
+extern "C" int qhp_hvp(qhp_ctx* c, const double* pos, const double* dir, double* out,
+                       int mem_kind) {
+  if (!c || !pos || !dir || !out) return qhp_fail(c, QHP_EINVAL, "null argument");
+  if (c->p.exec == QHP_PLAIN)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products need exec = QHP_BATCHED");
+  const size_t n = (size_t)c->P * c->N * 3;
+  if (!c->hvp_out) QHP_HIP(c, hipMalloc((void**)&c->hvp_out, n * sizeof(double)));
+  int r = copy_in(c, dir, mem_kind, c->io_b);
+  if (!r) r = copy_in(c, pos, mem_kind, c->x);
+  if (r) return r;
+  QHP_HIP(c, launch_centroid_of_beads(c));
+  // the potential grid of these positions (and forces, into scratch)
+  std::swap(c->g, c->g_eval);
+  r = forces_all(c, false, false);
+  std::swap(c->g, c->g_eval);
+  if (r) return r;
+  QHP_HIP(c, launch_bonded_hvp(c, c->io_b, c->hvp_out));
+  BeadSet B = full_beads(c);
+  B.g = c->hvp_out;
+  B.hvp_u = c->io_b;
+  QHP_HIP(c, launch_pair(c, false, -1, &B));
+  QHP_HIP(c, launch_spme_hvp(c, c->io_b, c->hvp_out));
+  if (mem_kind == QHP_MEM_HOST) {
+    QHP_HIP(c, launch_transpose_out(c, c->hvp_out, c->io_a, 1.0));
+    QHP_HIP(c, hipMemcpyAsync(out, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    QHP_HIP(c, hipStreamSynchronize(c->stream));
+    return check_ctrl(c);
+  }
+  QHP_HIP(c, launch_transpose_out(c, c->hvp_out, out, 1.0));
   return QHP_OK;
 }
 

@@ -131,6 +131,97 @@ __global__ __launch_bounds__(NT) void k_bonded(BondArgs A) {
 }
 
 // zero [rows][NTERMS] and put the self term on the first self_rows rows
+// ---- Hessian-vector products of the intramolecular terms by forward differentiation ----
+// A dual number (v, d) carries a value and its derivative along the direction u; running
+// the gradient of the bond, angle and exclusion terms on dual positions x + eps u gives
+// the gradient's derivative along u, H u, exactly (no truncation).
+struct Dual {
+  double v, d;
+};
+QHP_DEV Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+QHP_DEV Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+QHP_DEV Dual operator-(Dual a) { return {-a.v, -a.d}; }
+QHP_DEV Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+QHP_DEV Dual operator*(double s, Dual a) { return {s * a.v, s * a.d}; }
+QHP_DEV Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+QHP_DEV Dual dsqrt(Dual a) {
+  const double s = sqrt(a.v);
+  return {s, 0.5 * a.d / s};
+}
+QHP_DEV Dual dacos(Dual a) { return {acos(a.v), -a.d / sqrt(1.0 - a.v * a.v)}; }
+QHP_DEV Dual derf(Dual a) { return {erf(a.v), a.d * (2.0 / sqrt(M_PI)) * exp(-a.v * a.v)}; }
+QHP_DEV Dual dexp(Dual a) {
+  const double e = exp(a.v);
+  return {e, a.d * e};
+}
+
+template <int P>
+__global__ __launch_bounds__(NT) void k_bonded_hvp(BondArgs A, const double* u, double* hu) {
+  constexpr int AT = NT / P;
+  const int tid = threadIdx.x, b = tid % P;
+  const int w = blockIdx.x * AT + tid / P;
+  if (w >= A.NW) return;
+  const int N = A.N;
+  Dual X[3][3], G[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) {
+      const size_t i = (size_t)(d * N + 3 * w + k) * P + b;
+      X[k][d] = {A.x[i], u[i]};
+      G[k][d] = {0.0, 0.0};
+    }
+  auto sep = [&](int a0, int a1, Dual* dd) {   // minimum-image difference X[a1] - X[a0]
+    for (int d = 0; d < 3; ++d) {
+      dd[d] = X[a1][d] - X[a0][d];
+      dd[d].v -= A.L[d] * rint(dd[d].v * A.invL[d]);   // the shift is locally constant
+    }
+  };
+  Dual uu[2][3], r[2];
+  for (int h = 0; h < 2; ++h) {                     // O-H bonds
+    Dual dd[3];
+    sep(0, h + 1, dd);
+    r[h] = dsqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+    const Dual s = A.kb * ((r[h] - Dual{A.r0, 0.0}) / r[h]);
+    for (int d = 0; d < 3; ++d) {
+      uu[h][d] = dd[d] / r[h];
+      G[h + 1][d] = G[h + 1][d] + s * dd[d];
+      G[0][d] = G[0][d] - s * dd[d];
+    }
+  }
+  {                                                 // H-O-H angle
+    Dual cs = uu[0][0] * uu[1][0] + uu[0][1] * uu[1][1] + uu[0][2] * uu[1][2];
+    const Dual th = dacos(cs), sn = dsqrt(Dual{1.0, 0.0} - cs * cs);
+    const Dual de = A.kth * (th - Dual{A.th0, 0.0});
+    for (int d = 0; d < 3; ++d) {
+      const Dual g1 = -(de / (r[0] * sn)) * (uu[1][d] - cs * uu[0][d]);
+      const Dual g2 = -(de / (r[1] * sn)) * (uu[0][d] - cs * uu[1][d]);
+      G[1][d] = G[1][d] + g1;
+      G[2][d] = G[2][d] + g2;
+      G[0][d] = G[0][d] - (g1 + g2);
+    }
+  }
+  const double c2a = 2.0 * A.alpha / sqrt(M_PI);
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+  for (int e = 0; e < 3; ++e) {                     // exclusion correction
+    Dual dd[3];
+    sep(pa[e], pb[e], dd);
+    const Dual r2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+    const Dual rr = dsqrt(r2);
+    const double qq = A.coulomb * A.charge[3 * w + pa[e]] * A.charge[3 * w + pb[e]];
+    const Dual erfv = derf(A.alpha * rr);
+    const Dual dEdr = (-qq) * (c2a * (dexp((-A.alpha * A.alpha) * r2) / rr) - erfv / r2);
+    const Dual s = dEdr / rr;
+    for (int d = 0; d < 3; ++d) {
+      G[pb[e]][d] = G[pb[e]][d] + s * dd[d];
+      G[pa[e]][d] = G[pa[e]][d] - s * dd[d];
+    }
+  }
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) hu[(size_t)(d * N + 3 * w + k) * P + b] = G[k][d].d;
+}
+
 __global__ void k_energy_init(double* energy, int rows, int self_rows, double self) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < rows * QHP_NTERMS)
@@ -191,6 +282,18 @@ hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   else if (terms == QHP_TERMS_EXCL) { BONDED_CALL(QHP_TERMS_EXCL); }
   else { BONDED_CALL(QHP_TERMS_ALL); }
 #undef BONDED_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_bonded_hvp(qhp_ctx* c, const double* u, double* hu) {
+  BondArgs A;
+  A.N = c->N; A.NW = c->NW; A.x = c->x; A.g = nullptr; A.charge = c->d_charge;
+  for (int d = 0; d < 3; ++d) { A.L[d] = c->p.box[d]; A.invL[d] = 1.0 / c->p.box[d]; }
+  A.r0 = c->p.bond_r0; A.kb = c->p.bond_k; A.th0 = c->p.angle_theta0; A.kth = c->p.angle_k;
+  A.alpha = c->p.ewald_alpha; A.coulomb = c->p.coulomb; A.energy = nullptr; A.dq = nullptr;
+  const int P = c->P;
+  const unsigned nb = (unsigned)((c->NW + NT / P - 1) / (NT / P));
+  QHP_SWITCH_P(P, hipLaunchKernelGGL((k_bonded_hvp<PP>), nb, NT, 0, c->stream, A, u, hu));
   return hipGetLastError();
 }
 

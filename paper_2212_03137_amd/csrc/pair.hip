@@ -52,6 +52,7 @@ struct PairArgs {
   double lj_sig[QHP_MAX_TYPES * QHP_MAX_TYPES];   // sigma_ij (parameter gradients)
   double eps_of[QHP_MAX_TYPES];                    // epsilon of each type
   double* dq; double* deps; double* dsig;          // parameter-gradient outputs (FP64 path)
+  const double* u; double* hu;                     // Hessian-vector product: direction, output
   int nblocks;            // logical blocks
   const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
   double* energy;         // [P][NTERMS] (plain: the bead's row)
@@ -95,7 +96,10 @@ QHP_DEV void flush(const PairArgs& A, int i, int lane, double gx, double gy, dou
 // charge of atom i (C q_j erfc(alpha r)/r per in-range pair, visited from i's end) and to
 // the LJ epsilon and sigma of i's type (the i-side halves of d e_ij and d s_ij; the j side
 // is added when the pair is visited from j).
-template <int P, bool ENERGY, bool PG = false>
+// HVP: instead of the gradient, add M (u_i - u_j) per in-range pair to hu_i, with
+// M = phi'' r^ r^T + (phi'/r)(I - r^ r^T) the pair's Hessian block (phi the screened
+// Coulomb plus LJ pair potential of r).
+template <int P, bool ENERGY, bool PG = false, bool HVP = false>
 __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
   constexpr int S = 64 / P;
   __shared__ int sj[WPB][64];
@@ -115,6 +119,12 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
   const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
   double pq = 0, pe = 0, ps = 0;                  // parameter gradients (PG)
+  double uix = 0, uiy = 0, uiz = 0;
+  if (HVP) {
+    uix = A.u[(0 * (size_t)N + i) * P + b];
+    uiy = A.u[(1 * (size_t)N + i) * P + b];
+    uiz = A.u[(2 * (size_t)N + i) * P + b];
+  }
   __shared__ double ssig[PG ? WPB : 1][PG ? 64 : 1];
   const double half_over_eps = PG && A.eps_of[ti] > 0.0 ? 0.5 / A.eps_of[ti] : 0.0;
   for (int k0 = 0; k0 < nn; k0 += 64) {
@@ -155,10 +165,36 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
             ps += 0.5 * e4 * (12.0 * s6 * s6 - 6.0 * s6) / ssig[wv][t];
           }
         }
-        gx += sc * dx; gy += sc * dy; gz += sc * dz;
+        if (HVP) {
+          // phi' and phi'' of the pair: -sc r is phi'; phi'' below
+          const double ex2 = exp(-A.alpha * A.alpha * r2);
+          double d1 = -sc * r;
+          double d2 = qq * (2.0 * erfcv * ir2 * ir + c2a * ex2 * (2.0 * ir2 + 2.0 * A.alpha * A.alpha));
+          if (e4 != 0.0) {
+            const double s6 = lj.y * ir2 * ir2 * ir2;
+            d2 += e4 * (156.0 * s6 * s6 - 42.0 * s6) * ir2;
+          }
+          const double ux = uix - A.u[(0 * (size_t)N + j) * P + b];
+          const double uy = uiy - A.u[(1 * (size_t)N + j) * P + b];
+          const double uz = uiz - A.u[(2 * (size_t)N + j) * P + b];
+          const double dd = dx * ux + dy * uy + dz * uz;
+          const double c1 = (d2 - d1 * ir) * ir2 * dd, c0 = d1 * ir;
+          gx += c1 * dx + c0 * ux; gy += c1 * dy + c0 * uy; gz += c1 * dz + c0 * uz;
+        } else {
+          gx += sc * dx; gy += sc * dy; gz += sc * dz;
+        }
       }
     }
     wave_sync();
+  }
+  if (HVP) {
+    gx = slot_sum<P>(gx); gy = slot_sum<P>(gy); gz = slot_sum<P>(gz);
+    if (lane < P) {
+      A.hu[(0 * (size_t)N + i) * P + lane] += gx;
+      A.hu[(1 * (size_t)N + i) * P + lane] += gy;
+      A.hu[(2 * (size_t)N + i) * P + lane] += gz;
+    }
+    return;
   }
   flush<P, ENERGY>(A, i, lane, gx, gy, gz, ec, elj);
   if (PG) {
@@ -334,14 +370,17 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   const double Lmin = fmin(c->p.box[0], fmin(c->p.box[1], c->p.box[2]));
   const bool minimg = !(2.0 * (c->p.cutoff + c->p.skin) < Lmin);
   const bool pg = bs && bs->pgrad;     // parameter gradients: always the FP64 kernel
-  const bool f32 = c->p.precision == QHP_FP32_PAIRS && !plain && !minimg && !pg;
+  const bool hvp = bs && bs->hvp_u;    // Hessian-vector product: FP64 kernel
+  const bool f32 = c->p.precision == QHP_FP32_PAIRS && !plain && !minimg && !pg && !hvp;
+  if (hvp) { A.u = bs->hvp_u; A.hu = bs->g; }
   hipEvent_t ev = nullptr;
   prof_begin(c, QHP_PROF_PAIR, &ev);
   if (f32) {
     QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair32<PP, true>), nb, NT, 0, c->stream, A);
                  else hipLaunchKernelGGL((k_pair32<PP, false>), nb, NT, 0, c->stream, A));
   } else {
-    QHP_SWITCH_P(P, if (pg) hipLaunchKernelGGL((k_pair64<PP, false, true>), nb, NT, 0, c->stream, A);
+    QHP_SWITCH_P(P, if (hvp) hipLaunchKernelGGL((k_pair64<PP, false, false, true>), nb, NT, 0, c->stream, A);
+                 else if (pg) hipLaunchKernelGGL((k_pair64<PP, false, true>), nb, NT, 0, c->stream, A);
                  else if (energy) hipLaunchKernelGGL((k_pair64<PP, true>), nb, NT, 0, c->stream, A);
                  else hipLaunchKernelGGL((k_pair64<PP, false>), nb, NT, 0, c->stream, A));
   }

@@ -46,6 +46,7 @@ struct BeadSet {
   double* energy;             // [P][QHP_NTERMS]
   int terms;                  // QHP_TERMS_* for launch_bonded
   int pgrad = 0;              // also accumulate the parameter gradients (FP64 kernels)
+  const double* hvp_u = nullptr;  // Hessian-vector product along u [3][N][P]: g receives H u
 };
 #define QHP_TERMS_BONDED 1    // O-H bonds and H-O-H angles (V_f)
 #define QHP_TERMS_EXCL   2    // intramolecular Ewald exclusion correction (part of V_s)
@@ -132,6 +133,7 @@ struct qhp_ctx {
   // SPME
   int K[3];
   double2* grid = nullptr;    // [K0][K1][K2][Pc] (plain: [K0][K1][K2])
+  double2* grid2 = nullptr;   // tangent grid of Hessian-vector products (allocated on use)
   double* influence = nullptr;// [K0][K1][K2]
   int ntiles = 0;             // 8^3-point spreading tiles
   int* tile_of = nullptr;     // [N]
@@ -163,6 +165,7 @@ struct qhp_ctx {
   // parameter gradients of the summed bead energies
   double* pg_dq = nullptr;    // [N] d/d charge
   double* pg_lj = nullptr;    // [2][QHP_MAX_TYPES] d/d epsilon, d/d sigma per type
+  double* hvp_out = nullptr;  // [3][N][P] Hessian-vector product (allocated on use)
 
   QtbState qtb;
 
@@ -218,6 +221,11 @@ hipError_t launch_centroid_of_beads(qhp_ctx* c);
 
 hipError_t launch_nlist(qhp_ctx* c, bool from_step);
 hipError_t launch_zero(qhp_ctx* c, void* ptr, size_t bytes);
+// H u of the intramolecular terms (bonds, angle, exclusion) at c->x: writes (initialises) hu
+hipError_t launch_bonded_hvp(qhp_ctx* c, const double* u, double* hu);
+// H u of the reciprocal sum at c->x, added to hu; c->grid must hold the potential grid
+// of c->x (left there by launch_spme)
+hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu);
 // bead >= 0: one bead of the plain (bead-major) layout; bead < 0: the bead set `bs`
 // (nullptr: the full ring polymer of the context)
 hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);

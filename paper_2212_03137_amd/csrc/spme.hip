@@ -60,6 +60,39 @@ QHP_DEV void bspline(double frac, double* w, double* dw) {
   for (int t = 0; t < ORDER; ++t) w[t] = m[t];
 }
 
+// Values, first and second derivatives of the order-n B-spline weights (the second
+// derivative is M_{n-2}(u) - 2 M_{n-2}(u-1) + M_{n-2}(u-2)).
+template <int ORDER>
+QHP_DEV void bspline2(double frac, double* w, double* dw, double* ddw) {
+  double m[ORDER];
+#pragma unroll
+  for (int t = 0; t < ORDER; ++t) m[t] = 0.0;
+  m[0] = frac;
+  m[1] = 1.0 - frac;
+  auto second = [&]() {
+#pragma unroll
+    for (int t = 0; t < ORDER; ++t)
+      ddw[t] = m[t] - (t >= 1 ? 2.0 * m[t - 1] : 0.0) + (t >= 2 ? m[t - 2] : 0.0);
+  };
+  if (ORDER == 3) second();
+#pragma unroll
+  for (int k = 3; k <= ORDER; ++k) {
+    if (k == ORDER - 1) second();
+    if (k == ORDER) {
+      dw[0] = m[0];
+#pragma unroll
+      for (int t = 1; t < ORDER; ++t) dw[t] = m[t] - m[t - 1];
+    }
+    const double inv = 1.0 / (double)(k - 1);
+#pragma unroll
+    for (int t = k - 1; t >= 1; --t)
+      m[t] = ((frac + t) * m[t] + ((double)k - frac - t) * m[t - 1]) * inv;
+    m[0] = frac * m[0] * inv;
+  }
+#pragma unroll
+  for (int t = 0; t < ORDER; ++t) w[t] = m[t];
+}
+
 template <int ORDER>
 QHP_DEV void stencil(const double* xb, const double* L, const int* K, int* i0, double (*w)[ORDER],
                      double (*dw)[ORDER]) {
@@ -141,6 +174,66 @@ __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
   }
 }
 
+// Hessian-vector product of the reciprocal energy: with phi the potential grid of x and
+// dphi the potential of the tangent density sum_b q_b grad W_b . u_b,
+//   (H u)_a = q_a [ sum_k (grad grad W_a(k)) u_a phi(k) + sum_k grad W_a(k) dphi(k) ].
+template <int P, int ORDER>
+__global__ __launch_bounds__(NT) void k_gather_hvp(SpmeArgs A, const double* dgrid,
+                                                   const double* u, double* hu) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int tid = lb * NT + threadIdx.x;
+  const int k = tid / P, b = tid % P;
+  const int a = (lb < A.nblocks && k < A.N) ? A.order[k] : A.N;
+  if (a >= A.N) return;
+  const int K[3] = {A.K0, A.K1, A.K2};
+  int i0[3];
+  double w[3][ORDER], dw[3][ORDER], ddw[3][ORDER], KoL[3];
+  for (int d = 0; d < 3; ++d) {
+    KoL[d] = (double)K[d] / A.L[d];
+    double sfr = A.x[(d * A.N + a) * P + b] / A.L[d];
+    sfr = sfr - floor(sfr);
+    const double uu = sfr * (double)K[d];
+    const double fl = floor(uu);
+    i0[d] = isfinite(fl) ? min(max((int)fl, 0), K[d]) : 0;
+    bspline2<ORDER>(uu - fl, w[d], dw[d], ddw[d]);
+  }
+  double h00 = 0, h11 = 0, h22 = 0, h01 = 0, h02 = 0, h12 = 0, g0 = 0, g1 = 0, g2 = 0;
+  for (int t0 = 0; t0 < ORDER; ++t0) {
+    const int k0 = wrapk(i0[0] - t0, A.K0);
+#pragma unroll
+    for (int t1 = 0; t1 < ORDER; ++t1) {
+      const int k1 = wrapk(i0[1] - t1, A.K1);
+      const size_t ro = ((size_t)(k0 * A.K1 + k1) * A.K2) * A.Pc2 + b;
+      double sv = 0, sd = 0, sdd = 0, tv = 0, td = 0;
+#pragma unroll
+      for (int t2 = 0; t2 < ORDER; ++t2) {
+        const size_t o = ro + (size_t)wrapk(i0[2] - t2, A.K2) * A.Pc2;
+        const double ph = A.grid[o], dph = dgrid[o];
+        sv += w[2][t2] * ph;
+        sd += dw[2][t2] * ph;
+        sdd += ddw[2][t2] * ph;
+        tv += w[2][t2] * dph;
+        td += dw[2][t2] * dph;
+      }
+      h00 += ddw[0][t0] * w[1][t1] * sv;
+      h11 += w[0][t0] * ddw[1][t1] * sv;
+      h22 += w[0][t0] * w[1][t1] * sdd;
+      h01 += dw[0][t0] * dw[1][t1] * sv;
+      h02 += dw[0][t0] * w[1][t1] * sd;
+      h12 += w[0][t0] * dw[1][t1] * sd;
+      g0 += dw[0][t0] * w[1][t1] * tv;
+      g1 += w[0][t0] * dw[1][t1] * tv;
+      g2 += w[0][t0] * w[1][t1] * td;
+    }
+  }
+  const double q = A.charge[a];
+  const double u0 = u[(0 * A.N + a) * P + b] * KoL[0], u1 = u[(1 * A.N + a) * P + b] * KoL[1],
+               u2 = u[(2 * A.N + a) * P + b] * KoL[2];
+  hu[(0 * A.N + a) * P + b] += q * KoL[0] * (h00 * u0 + h01 * u1 + h02 * u2 + g0);
+  hu[(1 * A.N + a) * P + b] += q * KoL[1] * (h01 * u0 + h11 * u1 + h12 * u2 + g1);
+  hu[(2 * A.N + a) * P + b] += q * KoL[2] * (h02 * u0 + h12 * u1 + h22 * u2 + g2);
+}
+
 // ------------------------------- owner-computes spreading ------------------------------
 // The grid is cut into TB^3-point tiles. Atoms are binned every step by the tile of their
 // centroid's stencil base; one block per (tile, group of GB beads) accumulates in LDS the
@@ -215,6 +308,7 @@ struct TSpreadArgs {
   double L[3], KoL[3];        // box and K / L per axis
   const NlCtrl* ctrl;         // spread_m: largest bead-centroid base offset this step
   const int* tile_start; const int* tile_atoms; const int* tile_nbr;   // [ntiles][27]
+  const double* u;            // tangent spreading: direction [3][N][P]
 };
 
 // in-tile range of the stencil points base - t, t = 0..ORDER-1, along one axis:
@@ -224,7 +318,9 @@ QHP_DEV int tile_lo(int base, int t0, int K) {
   return (base - (ORDER - 1) - t0) & (K - 1);     // K is a power of two
 }
 
-template <int ORDER, int GB>
+// TAN: spread the derivative of the charge density along the direction u instead,
+// sum_a q_a grad W_a(k) . u_a (the tangent grid of a Hessian-vector product).
+template <int ORDER, int GB, bool TAN = false>
 __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
   constexpr int CAP = 1024;                // compacted atoms per round
   __shared__ double acc[TB * TB * TB * GB];
@@ -307,7 +403,7 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
       if (!hit) continue;
       double w[3][ORDER], dw[3][ORDER];
       int rel[2][ORDER], oz[ORDER];
-      double wz[ORDER];
+      double wz[ORDER], mz[ORDER];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         bspline<ORDER>(fr[d], w[d], dw[d]);
@@ -322,10 +418,38 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
             // innermost loop has no branch
             oz[t] = r < TB ? r * GB : 0;
             wz[t] = r < TB ? w[2][t] : 0.0;
+            mz[t] = r < TB ? 1.0 : 0.0;
           }
         }
       }
       const double qa = A.charge[a];
+      if (TAN) {
+        // grad W . u = u0 K0/L0 W0' W1 W2 + u1 K1/L1 W0 W1' W2 + u2 K2/L2 W0 W1 W2'
+        double t[3][ORDER];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double ud = A.u[((size_t)d * A.N + a) * P + b] * A.KoL[d];
+#pragma unroll
+          for (int q = 0; q < ORDER; ++q) t[d][q] = ud * dw[d][q];
+        }
+        double tz[ORDER];
+#pragma unroll
+        for (int q = 0; q < ORDER; ++q) tz[q] = mz[q] * t[2][q];
+#pragma unroll
+        for (int ta = 0; ta < ORDER; ++ta) {
+          if (rel[0][ta] < 0) continue;
+#pragma unroll
+          for (int tb = 0; tb < ORDER; ++tb) {
+            if (rel[1][tb] < 0) continue;
+            const double c1 = qa * (t[0][ta] * w[1][tb] + w[0][ta] * t[1][tb]);
+            const double c2 = qa * w[0][ta] * w[1][tb];
+            double* row = acc + (rel[0][ta] * TB + rel[1][tb]) * TB * GB + bl;
+#pragma unroll
+            for (int tc = 0; tc < ORDER; ++tc) atomicAdd(row + oz[tc], c1 * wz[tc] + c2 * tz[tc]);
+          }
+        }
+        continue;
+      }
 #pragma unroll
       for (int ta = 0; ta < ORDER; ++ta) {
         if (rel[0][ta] < 0) continue;
@@ -543,7 +667,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(FftArgs A) {
     default: return hipErrorInvalidValue;              \
   }
 
-static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc) {
+static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc, double2* grid) {
   const int K = c->K[axis];
   long inner = pc;
   for (int d = axis + 1; d < 3; ++d) inner *= c->K[d];
@@ -552,7 +676,7 @@ static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc) {
   const int NS = FFT_E / K;
   if (series % NS) return hipErrorInvalidValue;
   FftArgs A;
-  A.grid = c->grid; A.tw = c->tw[axis]; A.G = c->influence;
+  A.grid = grid; A.tw = c->tw[axis]; A.G = c->influence;
   A.lgI = __builtin_ctzl((unsigned long)inner); A.lgpc = __builtin_ctz((unsigned)pc);
   A.efast = inner < 16;
   const unsigned nb = (unsigned)(series / NS);
@@ -620,11 +744,11 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   prof_begin(c, QHP_PROF_FFT, &ev);
-  if ((e = fft_pass(c, 0, 0, pc)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 1, 0, pc)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 2, 2, pc)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 1, 1, pc)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 0, 1, pc)) != hipSuccess) return e;
+  if ((e = fft_pass(c, 0, 0, pc, c->grid)) != hipSuccess) return e;
+  if ((e = fft_pass(c, 1, 0, pc, c->grid)) != hipSuccess) return e;
+  if ((e = fft_pass(c, 2, 2, pc, c->grid)) != hipSuccess) return e;
+  if ((e = fft_pass(c, 1, 1, pc, c->grid)) != hipSuccess) return e;
+  if ((e = fft_pass(c, 0, 1, pc, c->grid)) != hipSuccess) return e;
   prof_end(c, QHP_PROF_FFT, ev);
   prof_begin(c, QHP_PROF_GATHER, &ev);
   A.nblocks = (int)nb;
@@ -634,5 +758,53 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
                else if (energy) hipLaunchKernelGGL((k_gather<PP, OO, true>), nb8, NT, 0, c->stream, A);
                else hipLaunchKernelGGL((k_gather<PP, OO, false>), nb8, NT, 0, c->stream, A)));
   prof_end(c, QHP_PROF_GATHER, ev);
+  return hipGetLastError();
+}
+
+hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu) {
+  const int P = c->P, pc = c->Pc, N = c->N;
+  if (!c->grid2) {
+    const size_t n = (size_t)c->K[0] * c->K[1] * c->K[2] * pc;
+    hipError_t e = hipMalloc((void**)&c->grid2, n * sizeof(double2));
+    if (e != hipSuccess) { c->grid2 = nullptr; return e; }
+  }
+  TSpreadArgs S;
+  S.N = N; S.P = P; S.K0 = c->K[0]; S.K1 = c->K[1]; S.K2 = c->K[2];
+  S.nt1 = c->K[1] / TB; S.nt2 = c->K[2] / TB; S.Pc2 = 2 * pc;
+  S.x = c->x; S.grid = (double*)c->grid2; S.charge = c->d_charge;
+  S.cent = c->cent; S.ctrl = c->ctrl; S.u = u;
+  for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
+  S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms; S.tile_nbr = c->tile_nbr;
+  const int gbeads = P < 8 ? P : 8;
+  const dim3 grid(c->ntiles, P / gbeads);
+#define SPREAD_CALL(GBV)                                                                     \
+  QHP_SWITCH_ORDER(c->p.pme_order,                                                           \
+                   hipLaunchKernelGGL((k_spread_tiles<OO, GBV, true>), grid, NT, 0, c->stream, S))
+  switch (gbeads) {
+    case 1: SPREAD_CALL(1); break;
+    case 2: SPREAD_CALL(2); break;
+    case 4: SPREAD_CALL(4); break;
+    default: SPREAD_CALL(8); break;
+  }
+#undef SPREAD_CALL
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = fft_pass(c, 0, 0, pc, c->grid2)) != hipSuccess) return e;
+  if ((e = fft_pass(c, 1, 0, pc, c->grid2)) != hipSuccess) return e;
+  if ((e = fft_pass(c, 2, 2, pc, c->grid2)) != hipSuccess) return e;
+  if ((e = fft_pass(c, 1, 1, pc, c->grid2)) != hipSuccess) return e;
+  if ((e = fft_pass(c, 0, 1, pc, c->grid2)) != hipSuccess) return e;
+  SpmeArgs A;
+  A.N = N; A.K0 = c->K[0]; A.K1 = c->K[1]; A.K2 = c->K[2]; A.Pc2 = 2 * pc;
+  A.order = c->tile_atoms; A.x = c->x; A.g = nullptr; A.grid = (double*)c->grid;
+  A.charge = c->d_charge;
+  for (int d = 0; d < 3; ++d) A.L[d] = c->p.box[d];
+  A.energy = nullptr; A.dq = nullptr;
+  const unsigned nb = (unsigned)(((size_t)N * P + NT - 1) / NT);
+  A.nblocks = (int)nb;
+  const unsigned nb8 = (nb + 7) / 8 * 8;
+  QHP_SWITCH_P(P, QHP_SWITCH_ORDER(c->p.pme_order,
+               hipLaunchKernelGGL((k_gather_hvp<PP, OO>), nb8, NT, 0, c->stream, A,
+                                  (const double*)c->grid2, u, hu)));
   return hipGetLastError();
 }

@@ -44,3 +44,58 @@ def test_parameter_gradients_match_the_oracle(which):
         assert np.allclose(ds, ds_r, rtol=1e-10, atol=1e-10 * np.abs(ds_r).max())
         # the propagated state is left alone
         assert np.abs(x - s.pos).max() <= 1e-12 * np.abs(s.pos).max()
+
+
+@pytest.mark.parametrize("which", ["small", "medium"])
+def test_hessian_vector_products_match_the_oracle(which):
+    import paper_2212_03137_amd as q
+    s = _small() if which == "small" else medium_box(P=4)
+    say("hvp", which, s.n_atoms, s.n_beads)
+    rng = np.random.default_rng(11)
+    u = rng.standard_normal(s.pos.shape)
+    ref = derivs.hvp(s.pos, s, u)
+    for prec in (q.FP64, q.FP32_PAIRS):
+        with ctx_for(s, precision=prec) as c:
+            c.set_state(s.pos, s.vel, 0)
+            got = c.hvp(s.pos, u)
+            x, _, _ = c.get_state()
+        # the oracle's central difference carries O(h^2) and rounding errors of ~1e-8
+        err = np.abs(got - ref).max() / np.sqrt(np.mean(ref ** 2))
+        assert err <= 1e-6, (prec, err)
+        assert np.abs(x - s.pos).max() <= 1e-12 * np.abs(s.pos).max()
+
+
+def test_hessian_vector_products_are_linear_and_symmetric_at_full_size():
+    # properties that hold exactly for the analytic operator at any size
+    s = synth.large_rpmd()
+    say("hvp large", s.n_atoms, s.n_beads)
+    rng = np.random.default_rng(12)
+    u = rng.standard_normal(s.pos.shape) * 0.01
+    v = rng.standard_normal(s.pos.shape) * 0.01
+    with ctx_for(s) as c:
+        Hu = c.hvp(s.pos, u)
+        Hv = c.hvp(s.pos, v)
+        Huv = c.hvp(s.pos, 2.0 * u - 3.0 * v)
+    assert np.all(np.isfinite(Hu))
+    scale = np.abs(Huv).max()
+    assert np.abs(Huv - (2.0 * Hu - 3.0 * Hv)).max() <= 1e-10 * scale
+    a, b = float(np.sum(v * Hu)), float(np.sum(u * Hv))
+    assert abs(a - b) <= 1e-9 * max(abs(a), abs(b))
+
+
+def test_hessian_vector_product_on_one_bead_of_the_large_box():
+    # the oracle's central difference on one bead of the 4,096-water box
+    from oracle import forces
+    s = synth.large_rpmd()
+    rng = np.random.default_rng(13)
+    u = rng.standard_normal(s.pos.shape)
+    with ctx_for(s) as c:
+        got = c.hvp(s.pos, u)
+    b, h = 7, 1e-5
+    pairs = forces.pair_list(forces.centroids_of(s.pos), s.box, s.cutoff + s.skin)
+    _, gp = forces.bead_potential(s.pos[b] + h * u[b], s, pairs)
+    _, gm = forces.bead_potential(s.pos[b] - h * u[b], s, pairs)
+    ref = (gp - gm) / (2.0 * h)
+    err = np.abs(got[b] - ref).max() / np.sqrt(np.mean(ref ** 2))
+    say("hvp large bead", b, err)
+    assert err <= 1e-6
