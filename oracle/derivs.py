@@ -14,7 +14,10 @@ PI_potential without the 1/P), with V the water model of ``forces.py``:
   eps_t = 0 (the geometric mean), so those entries are reported as 0;
 * Hessian-vector products H u = d/dh grad V(x + h u) at h = 0, taken here by its
   definition as the central difference (grad V(x + h u) - grad V(x - h u)) / 2h of the
-  analytic gradient, h = 1e-5 A (truncation error O(h^2), far below the test bounds).
+  analytic gradient, h = 1e-5 A (truncation error O(h^2), far below the test bounds),
+  with the set of pairs inside the cutoff frozen at x: the truncated potential has no
+  second derivative across the cutoff, and a pair that crosses it between x - hu and
+  x + hu would add a jump of order 1/h (the analytic operator has no such term).
 """
 import math
 
@@ -110,15 +113,27 @@ def param_gradients(pos, s, r_list=None):
     return dq, de, ds
 
 
-def hvp(pos, s, u, h=1e-5, r_list=None):
-    """H u per bead [P][N][3]: central difference of the analytic gradient along u (the
-    pair list is that of pos, shared by both evaluations)."""
+def _grad_frozen(x, s, pairs_in):
+    """grad V at x with the real-space terms over the given pairs (no cutoff test)."""
+    _, _, g_in = forces.intramolecular(x, s.box, s.bond_r0, s.bond_k, s.angle_theta0, s.angle_k)
+    _, _, g_rs = forces.real_space(x, pairs_in, s.charge, s.types, s.lj_sigma, s.lj_epsilon,
+                                   s.box, s.ewald_alpha, np.inf, s.coulomb)
+    _, g_x = forces.excluded_correction(x, s.charge, s.box, s.ewald_alpha, s.coulomb)
+    _, g_r = _spme.spme(x, s.charge, s.box, s.pme_grid, s.pme_order, s.ewald_alpha, s.coulomb)
+    return g_in + g_rs + g_x + g_r
+
+
+def hvp(pos, s, u, h=1e-5, r_list=None, beads=None):
+    """H u per bead [P][N][3] (only the listed beads if given; the others are zero):
+    central difference of the analytic gradient along u, pairs in range frozen at pos."""
     if r_list is None:
         r_list = s.cutoff + s.skin
     pairs = forces.pair_list(forces.centroids_of(pos), s.box, r_list)
     out = np.zeros_like(pos)
-    for b in range(pos.shape[0]):
-        _, gp = forces.bead_potential(pos[b] + h * u[b], s, pairs)
-        _, gm = forces.bead_potential(pos[b] - h * u[b], s, pairs)
+    for b in (range(pos.shape[0]) if beads is None else beads):
+        d = forces.min_image(pos[b][pairs[:, 1]] - pos[b][pairs[:, 0]], s.box)
+        inside = pairs[np.einsum("ij,ij->i", d, d) < s.cutoff * s.cutoff]
+        gp = _grad_frozen(pos[b] + h * u[b], s, inside)
+        gm = _grad_frozen(pos[b] - h * u[b], s, inside)
         out[b] = (gp - gm) / (2.0 * h)
     return out
