@@ -287,6 +287,31 @@ def main():
                         "beads every 2 fs"}
         except Exception as e:                      # reported, not fatal to the headline
             comp["rpc4_respa4_fp32"] = {"error": str(e)}
+        # derivatives beyond the forces, on the same configuration (device tensors): a
+        # Hessian-vector product of all 32 beads and the parameter gradients
+        try:
+            from paper_2212_03137_amd import autograd as qa
+            c = make(q.FP32_PAIRS, q.BATCHED, graph=False)
+            pos_d = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+            v_d = torch.randn_like(pos_d)
+            qa._hvp(c, pos_d, v_d)
+            qa._param_grad(c, pos_d)
+            reps = 20
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                qa._hvp(c, pos_d, v_d)
+            t_h = (time.perf_counter() - t0) / reps
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                qa._param_grad(c, pos_d)
+            t_p = (time.perf_counter() - t0) / reps
+            c.close()
+            comp["derivatives"] = {"hvp_ms": t_h * 1e3, "param_grad_ms": t_p * 1e3,
+                                   "note": "one call each on all 32 beads, FP64 pair terms, "
+                                           "list rebuilt and forces evaluated inside"}
+        except Exception as e:
+            comp["derivatives"] = {"error": str(e)}
         out["compare"] = comp
         out["speedup_vs_plain_fp64"] = ns_day / comp["plain_fp64"]["ns_per_day"]
 

@@ -95,3 +95,29 @@ def test_hessian_vector_product_on_one_bead_of_the_large_box():
     err = np.abs(got[b] - ref).max() / np.sqrt(np.mean(ref ** 2))
     say("hvp large bead", b, err)
     assert err <= 1e-6
+
+
+def test_torch_autograd_gradients_and_double_backward():
+    import torch
+    from paper_2212_03137_amd.autograd import bead_energy
+    s = _small()
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(14)
+    v = rng.standard_normal(s.pos.shape)
+    dq_r, de_r, ds_r = derivs.param_gradients(s.pos, s)
+    hv_r = derivs.hvp(s.pos, s, v)
+    with ctx_for(s) as c:
+        _, F = c.eval(s.pos)
+        pos = torch.tensor(s.pos, dtype=torch.float64, device=dev, requires_grad=True)
+        q = torch.tensor(s.charge, dtype=torch.float64, device=dev, requires_grad=True)
+        eps = torch.tensor(s.lj_epsilon, dtype=torch.float64, device=dev, requires_grad=True)
+        sig = torch.tensor(s.lj_sigma, dtype=torch.float64, device=dev, requires_grad=True)
+        E = bead_energy(c, pos, q, eps, sig)
+        g, gq, ge, gs = torch.autograd.grad(E, (pos, q, eps, sig), create_graph=True)
+        hv = torch.autograd.grad((g * torch.tensor(v, device=dev)).sum(), pos)[0]
+    assert np.abs(g.detach().cpu().numpy() + F).max() <= 1e-12 * np.abs(F).max()
+    assert np.abs(gq.detach().cpu().numpy() - dq_r).max() <= 1e-10 * np.abs(dq_r).max()
+    assert np.allclose(ge.detach().cpu().numpy(), de_r, rtol=1e-10, atol=1e-12)
+    assert np.allclose(gs.detach().cpu().numpy(), ds_r, rtol=1e-10, atol=1e-12)
+    err = np.abs(hv.cpu().numpy() - hv_r).max() / np.sqrt(np.mean(hv_r ** 2))
+    assert err <= 1e-6, err
