@@ -182,10 +182,13 @@ QHP_API int qhp_param_grad(qhp_ctx* ctx, const double* pos, double* dq, double* 
  * tangent charge density, one more convolution and a gather with second-derivative
  * B-splines), pair terms in FP64 whatever `precision` is, on the list of these positions.
  * The potential is the truncated one: pairs crossing the cutoff contribute no delta
- * terms. Leaves the propagated state alone; the first call allocates a second SPME grid
- * and an output buffer that the context keeps. QHP_EUNSUPPORTED for exec = QHP_PLAIN. */
+ * terms. With `dq` [N], `deps` [n_types], `dsig` [n_types] (all three or none), also the
+ * mixed derivatives d(dir . grad E)/d(q, epsilon, sigma) of the summed bead energies
+ * (as qhp_param_grad differentiates E): the parameter gradient of a loss on forces.
+ * Leaves the propagated state alone; the first call allocates a second SPME grid and an
+ * output buffer that the context keeps. QHP_EUNSUPPORTED for exec = QHP_PLAIN. */
 QHP_API int qhp_hvp(qhp_ctx* ctx, const double* pos, const double* dir, double* out,
-                    int mem_kind);
+                    double* dq, double* deps, double* dsig, int mem_kind);
 
 /* Set the propagated state from bead positions and bead velocities [P][N][3] and the
  * step counter (which indexes the noise streams). Computes the normal modes

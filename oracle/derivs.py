@@ -137,3 +137,33 @@ def hvp(pos, s, u, h=1e-5, r_list=None, beads=None):
         gm = _grad_frozen(pos[b] - h * u[b], s, inside)
         out[b] = (gp - gm) / (2.0 * h)
     return out
+
+
+def mixed(pos, s, u, h=1e-5, r_list=None):
+    """d/dh of the parameter gradients at pos + h u (h = 0): the derivatives of u . grad E
+    with respect to the charges [N], lj_epsilon [T] and lj_sigma [T], by the central
+    difference of ``param_gradients`` with the in-range pair set frozen at pos."""
+    if r_list is None:
+        r_list = s.cutoff + s.skin
+    pairs = forces.pair_list(forces.centroids_of(pos), s.box, r_list)
+    dq = np.zeros(s.n_atoms)
+    de = np.zeros(len(s.lj_sigma))
+    ds = np.zeros(len(s.lj_sigma))
+    for b in range(pos.shape[0]):
+        d = forces.min_image(pos[b][pairs[:, 1]] - pos[b][pairs[:, 0]], s.box)
+        inside = pairs[np.einsum("ij,ij->i", d, d) < s.cutoff * s.cutoff]
+        sp, sm = _frozen_cut(s), _frozen_cut(s)
+        qp = _charge_grad_bead(pos[b] + h * u[b], sp, inside)
+        qm = _charge_grad_bead(pos[b] - h * u[b], sm, inside)
+        ep, gp = _lj_grad_bead(pos[b] + h * u[b], sp, inside)
+        em, gm = _lj_grad_bead(pos[b] - h * u[b], sm, inside)
+        dq += (qp - qm) / (2.0 * h)
+        de += (ep - em) / (2.0 * h)
+        ds += (gp - gm) / (2.0 * h)
+    return dq, de, ds
+
+
+def _frozen_cut(s):
+    """The system with an infinite cutoff (the caller passes the frozen in-range pairs)."""
+    import dataclasses
+    return dataclasses.replace(s, cutoff=np.inf)

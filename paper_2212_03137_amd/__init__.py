@@ -84,7 +84,7 @@ def load():
                                     C.POINTER(C.c_int32)]
     lib.qhp_noise_export.argtypes = [vp, C.c_int32, C.c_int64, vp]
     lib.qhp_param_grad.argtypes = [vp, vp, vp, vp, vp, I]
-    lib.qhp_hvp.argtypes = [vp, vp, vp, vp, I]
+    lib.qhp_hvp.argtypes = [vp, vp, vp, vp, vp, vp, vp, I]
     for f in ("qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta"):
         getattr(lib, f).argtypes = [vp, vp]
     lib.qhp_profile.argtypes = [vp, I]
@@ -212,13 +212,16 @@ class Context:
                                              MEM_HOST))
         return dq, de, ds
 
-    def hvp(self, pos, direction):
-        """Hessian-vector product of every bead's potential, [P][N][3]."""
+    def hvp(self, pos, direction, mixed=False):
+        """Hessian-vector product of every bead's potential, [P][N][3]; with mixed, also
+        d(direction . grad E)/d(charges, lj_epsilon, lj_sigma)."""
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         d = np.ascontiguousarray(direction, dtype=np.float64)
         out = np.zeros((self.P, self.N, 3))
-        self._check(self._lib.qhp_hvp(self._h, _ptr(pos), _ptr(d), _ptr(out), MEM_HOST))
-        return out
+        m = [np.zeros(self.N), np.zeros(self.n_types), np.zeros(self.n_types)] if mixed else [None] * 3
+        self._check(self._lib.qhp_hvp(self._h, _ptr(pos), _ptr(d), _ptr(out), _ptr(m[0]),
+                                      _ptr(m[1]), _ptr(m[2]), MEM_HOST))
+        return (out, *m) if mixed else out
 
     def set_state(self, pos, vel, step=0):
         pos = np.ascontiguousarray(pos, dtype=np.float64)

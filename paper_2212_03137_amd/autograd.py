@@ -3,10 +3,12 @@ without the 1/P) of a context.
 
 ``bead_energy(ctx, pos, charge, lj_epsilon, lj_sigma)`` returns E as a 0-d tensor. Its
 gradient in positions is the library's forces (qhp_eval), its gradients in the charges and
-per-type LJ parameters are qhp_param_grad, and the gradient of the position gradient (a
-second backward pass, ``create_graph=True``) is qhp_hvp, the exact Hessian-vector product
-(the Hessian is symmetric, so the vector-Jacobian product of the gradient is H v). This
-module only marshals tensors to the C ABI: every derivative is computed by the library.
+per-type LJ parameters are qhp_param_grad, and the backward of the position gradient (a
+second backward pass, ``create_graph=True``) is qhp_hvp: the exact Hessian-vector product
+(the Hessian is symmetric, so the vector-Jacobian product of the gradient is H v) and the
+mixed derivatives d(v . grad E)/d(q, epsilon, sigma), so a loss on forces can be
+differentiated with respect to the parameters. This module only marshals tensors to the C
+ABI: every derivative is computed by the library.
 
 Tensors live on the context's device (``mem_kind`` device) or on the host (CPU tensors,
 copied through host memory). The parameters are inputs so that autograd can route their
@@ -38,14 +40,19 @@ def _eval(context, pos):
     return E, F
 
 
-def _hvp(context, pos, v):
+def _hvp(context, pos, v, mixed=False):
     pos = pos.detach().contiguous().to(torch.float64)
     v = v.detach().contiguous().to(torch.float64)
     out = torch.zeros_like(pos)
-    context._check(context._lib.qhp_hvp(context._h, _arg(pos), _arg(v), _arg(out), _mem(pos)))
+    kw = dict(dtype=torch.float64, device=pos.device)
+    m = ([torch.zeros(context.N, **kw), torch.zeros(context.n_types, **kw),
+          torch.zeros(context.n_types, **kw)] if mixed else [None, None, None])
+    args = [_arg(t) if t is not None else None for t in m]
+    context._check(context._lib.qhp_hvp(context._h, _arg(pos), _arg(v), _arg(out), args[0],
+                                        args[1], args[2], _mem(pos)))
     if pos.is_cuda:
         context.sync()
-    return out
+    return (out, *m) if mixed else out
 
 
 def _param_grad(context, pos):
@@ -62,10 +69,11 @@ def _param_grad(context, pos):
 
 
 class _Gradient(torch.autograd.Function):
-    """grad E in positions; its backward is the Hessian-vector product."""
+    """grad E in positions; its backward is the Hessian-vector product and the mixed
+    parameter derivatives."""
 
     @staticmethod
-    def forward(ctx, pos, context):
+    def forward(ctx, pos, charge, lj_epsilon, lj_sigma, context):
         ctx.context = context
         ctx.save_for_backward(pos)
         _, F = _eval(context, pos)
@@ -74,22 +82,25 @@ class _Gradient(torch.autograd.Function):
     @staticmethod
     def backward(ctx, v):
         (pos,) = ctx.saved_tensors
-        return _hvp(ctx.context, pos, v), None
+        if any(ctx.needs_input_grad[1:4]):
+            hv, dq, de, ds = _hvp(ctx.context, pos, v, mixed=True)
+            return hv, dq, de, ds, None
+        return _hvp(ctx.context, pos, v), None, None, None, None
 
 
 class _Energy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, pos, charge, lj_epsilon, lj_sigma, context):
         ctx.context = context
-        ctx.save_for_backward(pos)
+        ctx.save_for_backward(pos, charge, lj_epsilon, lj_sigma)
         E, _ = _eval(context, pos)
         return E.sum()
 
     @staticmethod
     def backward(ctx, gE):
-        (pos,) = ctx.saved_tensors
+        pos, charge, lj_epsilon, lj_sigma = ctx.saved_tensors
         context = ctx.context
-        grad_pos = gE * _Gradient.apply(pos, context)
+        grad_pos = gE * _Gradient.apply(pos, charge, lj_epsilon, lj_sigma, context)
         dq = de = ds = None
         if any(ctx.needs_input_grad[1:4]):
             dq, de, ds = _param_grad(context, pos)
@@ -112,3 +123,10 @@ def bead_energy(context, pos, charge=None, lj_epsilon=None, lj_sigma=None):
             raise ValueError("parameter values must equal the context's (copied at creation)")
         out.append(t)
     return _Energy.apply(pos, out[0], out[1], out[2], context)
+
+
+def forces(context, pos, charge=None, lj_epsilon=None, lj_sigma=None):
+    """-grad E at pos, differentiable with respect to pos (H v) and the parameters."""
+    E = bead_energy(context, pos, charge, lj_epsilon, lj_sigma)
+    (g,) = torch.autograd.grad(E, pos, create_graph=True)
+    return -g

@@ -602,8 +602,10 @@ extern "C" int qhp_param_grad(qhp_ctx* c, const double* pos, double* dq, double*
 }
 
 extern "C" int qhp_hvp(qhp_ctx* c, const double* pos, const double* dir, double* out,
-                       int mem_kind) {
+                       double* dq, double* deps, double* dsig, int mem_kind) {
   if (!c || !pos || !dir || !out) return qhp_fail(c, QHP_EINVAL, "null argument");
+  const bool mix = dq != nullptr;
+  if (mix && (!deps || !dsig)) return qhp_fail(c, QHP_EINVAL, "dq, deps and dsig go together");
   if (c->p.exec == QHP_PLAIN)
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products need exec = QHP_BATCHED");
   const size_t n = (size_t)c->P * c->N * 3;
@@ -617,12 +619,24 @@ extern "C" int qhp_hvp(qhp_ctx* c, const double* pos, const double* dir, double*
   r = forces_all(c, false, false);
   std::swap(c->g, c->g_eval);
   if (r) return r;
-  QHP_HIP(c, launch_bonded_hvp(c, c->io_b, c->hvp_out));
+  if (mix) {
+    QHP_HIP(c, launch_zero(c, c->pg_dq, (size_t)c->N * sizeof(double)));
+    QHP_HIP(c, launch_zero(c, c->pg_lj, 2 * QHP_MAX_TYPES * sizeof(double)));
+  }
+  QHP_HIP(c, launch_bonded_hvp(c, c->io_b, c->hvp_out, mix));
   BeadSet B = full_beads(c);
   B.g = c->hvp_out;
   B.hvp_u = c->io_b;
+  B.pgrad = mix ? 1 : 0;
   QHP_HIP(c, launch_pair(c, false, -1, &B));
-  QHP_HIP(c, launch_spme_hvp(c, c->io_b, c->hvp_out));
+  QHP_HIP(c, launch_spme_hvp(c, c->io_b, c->hvp_out, mix));
+  const hipMemcpyKind k = mem_kind == QHP_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (mix) {
+    const int T = c->p.n_types;
+    QHP_HIP(c, hipMemcpyAsync(dq, c->pg_dq, (size_t)c->N * sizeof(double), k, c->stream));
+    QHP_HIP(c, hipMemcpyAsync(deps, c->pg_lj, T * sizeof(double), k, c->stream));
+    QHP_HIP(c, hipMemcpyAsync(dsig, c->pg_lj + QHP_MAX_TYPES, T * sizeof(double), k, c->stream));
+  }
   if (mem_kind == QHP_MEM_HOST) {
     QHP_HIP(c, launch_transpose_out(c, c->hvp_out, c->io_a, 1.0));
     QHP_HIP(c, hipMemcpyAsync(out, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));

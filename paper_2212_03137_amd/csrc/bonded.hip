@@ -158,12 +158,15 @@ QHP_DEV Dual dexp(Dual a) {
   return {e, a.d * e};
 }
 
+// With A.dq set, also add the exclusion term's part of d(u . grad E)/dq: the derivative
+// along u of -C q_b erf(alpha r)/r (and symmetrically), summed over the beads.
 template <int P>
 __global__ __launch_bounds__(NT) void k_bonded_hvp(BondArgs A, const double* u, double* hu) {
   constexpr int AT = NT / P;
   const int tid = threadIdx.x, b = tid % P;
   const int w = blockIdx.x * AT + tid / P;
-  if (w >= A.NW) return;
+  double mq[3] = {0.0, 0.0, 0.0};
+  if (w < A.NW) {
   const int N = A.N;
   Dual X[3][3], G[3][3];
   for (int k = 0; k < 3; ++k)
@@ -217,9 +220,19 @@ __global__ __launch_bounds__(NT) void k_bonded_hvp(BondArgs A, const double* u, 
       G[pb[e]][d] = G[pb[e]][d] + s * dd[d];
       G[pa[e]][d] = G[pa[e]][d] - s * dd[d];
     }
+    const double dh = (erfv / rr).d;                 // d/dh of erf(alpha r)/r along u
+    mq[pa[e]] += -A.coulomb * A.charge[3 * w + pb[e]] * dh;
+    mq[pb[e]] += -A.coulomb * A.charge[3 * w + pa[e]] * dh;
   }
   for (int k = 0; k < 3; ++k)
     for (int d = 0; d < 3; ++d) hu[(size_t)(d * N + 3 * w + k) * P + b] = G[k][d].d;
+  }
+  if (A.dq) {                          // sum over the P bead lanes of the water
+    for (int o = 1; o < P; o <<= 1)
+      for (int k = 0; k < 3; ++k) mq[k] += __shfl_xor(mq[k], o);
+    if (w < A.NW && b == 0)
+      for (int k = 0; k < 3; ++k) A.dq[3 * w + k] += mq[k];
+  }
 }
 
 __global__ void k_energy_init(double* energy, int rows, int self_rows, double self) {
@@ -285,12 +298,13 @@ hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   return hipGetLastError();
 }
 
-hipError_t launch_bonded_hvp(qhp_ctx* c, const double* u, double* hu) {
+hipError_t launch_bonded_hvp(qhp_ctx* c, const double* u, double* hu, bool mix) {
   BondArgs A;
   A.N = c->N; A.NW = c->NW; A.x = c->x; A.g = nullptr; A.charge = c->d_charge;
   for (int d = 0; d < 3; ++d) { A.L[d] = c->p.box[d]; A.invL[d] = 1.0 / c->p.box[d]; }
   A.r0 = c->p.bond_r0; A.kb = c->p.bond_k; A.th0 = c->p.angle_theta0; A.kth = c->p.angle_k;
-  A.alpha = c->p.ewald_alpha; A.coulomb = c->p.coulomb; A.energy = nullptr; A.dq = nullptr;
+  A.alpha = c->p.ewald_alpha; A.coulomb = c->p.coulomb; A.energy = nullptr;
+  A.dq = mix ? c->pg_dq : nullptr;
   const int P = c->P;
   const unsigned nb = (unsigned)((c->NW + NT / P - 1) / (NT / P));
   QHP_SWITCH_P(P, hipLaunchKernelGGL((k_bonded_hvp<PP>), nb, NT, 0, c->stream, A, u, hu));

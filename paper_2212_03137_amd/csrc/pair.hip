@@ -53,6 +53,7 @@ struct PairArgs {
   double eps_of[QHP_MAX_TYPES];                    // epsilon of each type
   double* dq; double* deps; double* dsig;          // parameter-gradient outputs (FP64 path)
   const double* u; double* hu;                     // Hessian-vector product: direction, output
+  int mix;                                         // HVP: also d(u . grad E)/d(q, eps, sigma)
   int nblocks;            // logical blocks
   const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
   double* energy;         // [P][NTERMS] (plain: the bead's row)
@@ -125,8 +126,9 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
     uiy = A.u[(1 * (size_t)N + i) * P + b];
     uiz = A.u[(2 * (size_t)N + i) * P + b];
   }
-  __shared__ double ssig[PG ? WPB : 1][PG ? 64 : 1];
-  const double half_over_eps = PG && A.eps_of[ti] > 0.0 ? 0.5 / A.eps_of[ti] : 0.0;
+  __shared__ double ssig[PG || HVP ? WPB : 1][PG || HVP ? 64 : 1];
+  const double half_over_eps = (PG || HVP) && A.eps_of[ti] > 0.0 ? 0.5 / A.eps_of[ti] : 0.0;
+  const bool mix = HVP && A.mix;
   for (int k0 = 0; k0 < nn; k0 += 64) {
     const int cnt = min(64, nn - k0);
     if (lane < cnt) {
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
       sq[wv][lane] = qi * A.charge[j];
       const int tp = ti * A.ntypes + A.type[j];
       slj[wv][lane] = make_double2(A.lj_e4[tp], A.lj_s6[tp]);
-      if (PG) ssig[wv][lane] = A.lj_sig[tp];
+      if (PG || HVP) ssig[wv][lane] = A.lj_sig[tp];
     }
     wave_sync();
     for (int t = s; t < cnt; t += S) {
@@ -180,6 +182,16 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
           const double dd = dx * ux + dy * uy + dz * uz;
           const double c1 = (d2 - d1 * ir) * ir2 * dd, c0 = d1 * ir;
           gx += c1 * dx + c0 * ux; gy += c1 * dy + c0 * uy; gz += c1 * dz + c0 * uz;
+          if (mix) {
+            // d r / dh along u is r^ . (u_j - u_i) = -dd / r; the i-side parameter terms
+            const double drdh = -dd * ir;
+            pq += A.coulomb * A.charge[j] * -(erfcv * ir2 + c2a * ex2 * ir) * drdh;
+            if (e4 != 0.0) {
+              const double s6 = lj.y * ir2 * ir2 * ir2;
+              pe += (-12.0 * s6 * s6 + 6.0 * s6) * ir * e4 * half_over_eps * drdh;
+              ps += 0.5 * e4 * (-144.0 * s6 * s6 + 36.0 * s6) * ir / ssig[wv][t] * drdh;
+            }
+          }
         } else {
           gx += sc * dx; gy += sc * dy; gz += sc * dz;
         }
@@ -194,10 +206,10 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
       A.hu[(1 * (size_t)N + i) * P + lane] += gy;
       A.hu[(2 * (size_t)N + i) * P + lane] += gz;
     }
-    return;
+    if (!mix) return;
   }
-  flush<P, ENERGY>(A, i, lane, gx, gy, gz, ec, elj);
-  if (PG) {
+  if (!HVP) flush<P, ENERGY>(A, i, lane, gx, gy, gz, ec, elj);
+  if (PG || mix) {
     for (int o = 1; o < 64; o <<= 1) {
       pq += __shfl_xor(pq, o);
       pe += __shfl_xor(pe, o);
@@ -372,7 +384,8 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   const bool pg = bs && bs->pgrad;     // parameter gradients: always the FP64 kernel
   const bool hvp = bs && bs->hvp_u;    // Hessian-vector product: FP64 kernel
   const bool f32 = c->p.precision == QHP_FP32_PAIRS && !plain && !minimg && !pg && !hvp;
-  if (hvp) { A.u = bs->hvp_u; A.hu = bs->g; }
+  A.mix = 0;
+  if (hvp) { A.u = bs->hvp_u; A.hu = bs->g; A.mix = bs->pgrad; }
   hipEvent_t ev = nullptr;
   prof_begin(c, QHP_PROF_PAIR, &ev);
   if (f32) {

@@ -221,11 +221,12 @@ hipError_t launch_centroid_of_beads(qhp_ctx* c);
 
 hipError_t launch_nlist(qhp_ctx* c, bool from_step);
 hipError_t launch_zero(qhp_ctx* c, void* ptr, size_t bytes);
-// H u of the intramolecular terms (bonds, angle, exclusion) at c->x: writes (initialises) hu
-hipError_t launch_bonded_hvp(qhp_ctx* c, const double* u, double* hu);
+// H u of the intramolecular terms (bonds, angle, exclusion) at c->x: writes (initialises)
+// hu; with mix, adds the exclusion part of d(u . grad E)/dq to c->pg_dq
+hipError_t launch_bonded_hvp(qhp_ctx* c, const double* u, double* hu, bool mix);
 // H u of the reciprocal sum at c->x, added to hu; c->grid must hold the potential grid
-// of c->x (left there by launch_spme)
-hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu);
+// of c->x (left there by launch_spme); with mix, adds d(u . grad E_recip)/dq to c->pg_dq
+hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu, bool mix);
 // bead >= 0: one bead of the plain (bead-major) layout; bead < 0: the bead set `bs`
 // (nullptr: the full ring polymer of the context)
 hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);

@@ -177,6 +177,8 @@ __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
 // Hessian-vector product of the reciprocal energy: with phi the potential grid of x and
 // dphi the potential of the tangent density sum_b q_b grad W_b . u_b,
 //   (H u)_a = q_a [ sum_k (grad grad W_a(k)) u_a phi(k) + sum_k grad W_a(k) dphi(k) ].
+// With A.dq set, also add d(u . grad E_recip)/dq_a = sum_k grad W_a(k) . u_a phi(k) +
+// sum_k W_a(k) dphi(k), summed over the beads.
 template <int P, int ORDER>
 __global__ __launch_bounds__(NT) void k_gather_hvp(SpmeArgs A, const double* dgrid,
                                                    const double* u, double* hu) {
@@ -198,6 +200,7 @@ __global__ __launch_bounds__(NT) void k_gather_hvp(SpmeArgs A, const double* dgr
     bspline2<ORDER>(uu - fl, w[d], dw[d], ddw[d]);
   }
   double h00 = 0, h11 = 0, h22 = 0, h01 = 0, h02 = 0, h12 = 0, g0 = 0, g1 = 0, g2 = 0;
+  double f0 = 0, f1 = 0, f2 = 0, wd = 0;
   for (int t0 = 0; t0 < ORDER; ++t0) {
     const int k0 = wrapk(i0[0] - t0, A.K0);
 #pragma unroll
@@ -224,6 +227,10 @@ __global__ __launch_bounds__(NT) void k_gather_hvp(SpmeArgs A, const double* dgr
       g0 += dw[0][t0] * w[1][t1] * tv;
       g1 += w[0][t0] * dw[1][t1] * tv;
       g2 += w[0][t0] * w[1][t1] * td;
+      f0 += dw[0][t0] * w[1][t1] * sv;
+      f1 += w[0][t0] * dw[1][t1] * sv;
+      f2 += w[0][t0] * w[1][t1] * sd;
+      wd += w[0][t0] * w[1][t1] * tv;
     }
   }
   const double q = A.charge[a];
@@ -232,6 +239,11 @@ __global__ __launch_bounds__(NT) void k_gather_hvp(SpmeArgs A, const double* dgr
   hu[(0 * A.N + a) * P + b] += q * KoL[0] * (h00 * u0 + h01 * u1 + h02 * u2 + g0);
   hu[(1 * A.N + a) * P + b] += q * KoL[1] * (h01 * u0 + h11 * u1 + h12 * u2 + g1);
   hu[(2 * A.N + a) * P + b] += q * KoL[2] * (h02 * u0 + h12 * u1 + h22 * u2 + g2);
+  if (A.dq) {                          // the P lanes of an atom are consecutive
+    double m = u0 * f0 + u1 * f1 + u2 * f2 + wd;
+    for (int o = 1; o < P; o <<= 1) m += __shfl_xor(m, o);
+    if (b == 0) A.dq[a] += m;
+  }
 }
 
 // ------------------------------- owner-computes spreading ------------------------------
@@ -761,7 +773,7 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   return hipGetLastError();
 }
 
-hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu) {
+hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu, bool mix) {
   const int P = c->P, pc = c->Pc, N = c->N;
   if (!c->grid2) {
     const size_t n = (size_t)c->K[0] * c->K[1] * c->K[2] * pc;
@@ -799,7 +811,7 @@ hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu) {
   A.order = c->tile_atoms; A.x = c->x; A.g = nullptr; A.grid = (double*)c->grid;
   A.charge = c->d_charge;
   for (int d = 0; d < 3; ++d) A.L[d] = c->p.box[d];
-  A.energy = nullptr; A.dq = nullptr;
+  A.energy = nullptr; A.dq = mix ? c->pg_dq : nullptr;
   const unsigned nb = (unsigned)(((size_t)N * P + NT - 1) / NT);
   A.nblocks = (int)nb;
   const unsigned nb8 = (nb + 7) / 8 * 8;

@@ -121,3 +121,60 @@ def test_torch_autograd_gradients_and_double_backward():
     assert np.allclose(gs.detach().cpu().numpy(), ds_r, rtol=1e-10, atol=1e-12)
     err = np.abs(hv.cpu().numpy() - hv_r).max() / np.sqrt(np.mean(hv_r ** 2))
     assert err <= 1e-6, err
+
+
+def test_parameter_gradient_of_a_force_loss():
+    # loss = mean (F(theta) - F_ref)^2 with F_ref from perturbed charges (the workload's
+    # fitting objective): d loss / d theta = -2/n sum r . d(grad E)/d theta, the mixed
+    # derivatives along the residual r, against central differences of the oracle's loss
+    import dataclasses
+    import torch
+    from paper_2212_03137_amd.autograd import forces as tforces
+    from oracle import forces as ofo
+    s = _small()
+    rng = np.random.default_rng(15)
+    pert = dataclasses.replace(s, charge=s.charge * (1.0 + 0.05 * rng.uniform(-1, 1, s.n_atoms)))
+    pert = dataclasses.replace(pert, charge=pert.charge - pert.charge.mean())
+    _, F_ref = ofo.evaluate(s.pos, pert)
+    dev = torch.device("cuda")
+    with ctx_for(s) as c:
+        pos = torch.tensor(s.pos, dtype=torch.float64, device=dev, requires_grad=True)
+        q = torch.tensor(s.charge, dtype=torch.float64, device=dev, requires_grad=True)
+        eps = torch.tensor(s.lj_epsilon, dtype=torch.float64, device=dev, requires_grad=True)
+        sig = torch.tensor(s.lj_sigma, dtype=torch.float64, device=dev, requires_grad=True)
+        F = tforces(c, pos, q, eps, sig)
+        loss = ((F - torch.tensor(F_ref, device=dev)) ** 2).mean()
+        gq, ge, gs = torch.autograd.grad(loss, (q, eps, sig))
+
+    def oracle_loss(sys):
+        _, Fo = ofo.evaluate(s.pos, sys)
+        return float(((Fo - F_ref) ** 2).mean())
+
+    h = 1e-6
+    for a in (0, 4, 50):
+        qp, qm = s.charge.copy(), s.charge.copy()
+        qp[a] += h
+        qm[a] -= h
+        fd = (oracle_loss(dataclasses.replace(s, charge=qp))
+              - oracle_loss(dataclasses.replace(s, charge=qm))) / (2 * h)
+        assert fd == pytest.approx(float(gq[a]), rel=1e-5, abs=1e-7)
+    for name, g in (("lj_epsilon", ge), ("lj_sigma", gs)):
+        base = getattr(s, name).astype(float)
+        p, m = base.copy(), base.copy()
+        p[0] += h
+        m[0] -= h
+        fd = (oracle_loss(dataclasses.replace(s, **{name: p}))
+              - oracle_loss(dataclasses.replace(s, **{name: m}))) / (2 * h)
+        assert fd == pytest.approx(float(g[0]), rel=1e-5, abs=1e-7)
+
+
+def test_mixed_derivatives_match_the_oracle():
+    s = medium_box(P=4)
+    rng = np.random.default_rng(16)
+    u = rng.standard_normal(s.pos.shape)
+    dq_r, de_r, ds_r = derivs.mixed(s.pos, s, u)
+    with ctx_for(s) as c:
+        _, dq, de, ds = c.hvp(s.pos, u, mixed=True)
+    assert np.abs(dq - dq_r).max() <= 1e-6 * np.abs(dq_r).max()
+    assert np.allclose(de, de_r, rtol=1e-6, atol=1e-8 * np.abs(de_r).max())
+    assert np.allclose(ds, ds_r, rtol=1e-6, atol=1e-8 * np.abs(ds_r).max())

@@ -97,3 +97,33 @@ def test_hvp_is_symmetric(small):
     Hu, Hv = derivs.hvp(s.pos, s, u), derivs.hvp(s.pos, s, v)
     a, b = float(np.sum(v * Hu)), float(np.sum(u * Hv))
     assert a == pytest.approx(b, rel=1e-6)
+
+
+def test_mixed_derivatives_are_the_directional_derivative_of_the_parameter_gradient(small):
+    # d(u . grad E)/d theta: check against the parameter-gradient of u . grad E by central
+    # differences in the parameters (the other order of the mixed derivative)
+    s = small
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal(s.pos.shape)
+    dq, de, ds = derivs.mixed(s.pos, s, u)
+
+    def u_dot_grad(sys):
+        _, F = forces.evaluate(s.pos, sys)
+        return -float(np.sum(u * F))
+
+    h = 1e-6
+    for a in (0, 5, 41):
+        qp, qm = s.charge.copy(), s.charge.copy()
+        qp[a] += h
+        qm[a] -= h
+        fd = (u_dot_grad(dataclasses.replace(s, charge=qp))
+              - u_dot_grad(dataclasses.replace(s, charge=qm))) / (2 * h)
+        assert fd == pytest.approx(dq[a], rel=1e-5, abs=1e-5)
+    for arr, g in (("lj_epsilon", de), ("lj_sigma", ds)):
+        base = getattr(s, arr).astype(float)
+        p, m = base.copy(), base.copy()
+        p[0] += h
+        m[0] -= h
+        fd = (u_dot_grad(dataclasses.replace(s, **{arr: p}))
+              - u_dot_grad(dataclasses.replace(s, **{arr: m}))) / (2 * h)
+        assert fd == pytest.approx(g[0], rel=1e-5, abs=1e-6)
