@@ -113,6 +113,45 @@ def algorithmic_work(cls, s, counts):
     raise ValueError(cls)
 
 
+def force_loss_timing(q, qa, n_configs=8):
+    """Differentiation workload: 1,024-water P=16 configurations, loss = mean squared force
+    error against the forces of perturbed parameters, gradient with respect to the charges
+    and LJ parameters by the library's mixed derivatives (torch autograd, device tensors)."""
+    import torch
+    import synth
+    boxes = [synth.diff_box(k) for k in range(n_configs)]
+    s0 = boxes[0]
+    qp, sp, ep = synth.perturbed_parameters(s0, 1)
+    ref = q.Context.from_system(s0, charge=qp, lj_sigma=sp, lj_epsilon=ep, precision=q.FP32_PAIRS)
+    c = q.Context.from_system(s0, precision=q.FP32_PAIRS)
+    dev = torch.device("cuda")
+    refs = [torch.tensor(ref.eval(b.pos)[1], device=dev) for b in boxes]
+    ref.close()
+    prm = [torch.tensor(v, dtype=torch.float64, device=dev, requires_grad=True)
+           for v in (s0.charge, s0.lj_epsilon, s0.lj_sigma)]
+
+    def one(b, Fr):
+        pos = torch.tensor(b.pos, dtype=torch.float64, device=dev, requires_grad=True)
+        F = qa.forces(c, pos, *prm)
+        loss = ((F - Fr) ** 2).mean()
+        return torch.autograd.grad(loss, prm)
+
+    one(boxes[0], refs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, Fr in zip(boxes, refs):
+        one(b, Fr)
+    torch.cuda.synchronize()
+    dt_cfg = (time.perf_counter() - t0) / n_configs
+    c.close()
+    return {"workload": "1,024 waters, 31.3 A, P=16, SPME 32^3 order 5; loss = mean squared "
+                        "force error vs perturbed parameters (charges +-5%, sigma/epsilon +-3%)",
+            "ms_per_configuration": dt_cfg * 1e3, "configurations_timed": n_configs,
+            "projected_64_configurations_s": 64 * dt_cfg,
+            "calls_per_configuration": "forces (eval), mixed parameter derivatives + H v (hvp), "
+                                       "parameter gradients (param_grad)"}
+
+
 def cpu_baseline(s, budget_s=20.0):
     """The oracle as it stands, on a bounded sample: the centroid pair list and the full
     per-bead potential of as many beads as fit in about `budget_s` seconds."""
@@ -310,6 +349,7 @@ def main():
             comp["derivatives"] = {"hvp_ms": t_h * 1e3, "param_grad_ms": t_p * 1e3,
                                    "note": "one call each on all 32 beads, FP64 pair terms, "
                                            "list rebuilt and forces evaluated inside"}
+            comp["derivatives"]["force_loss"] = force_loss_timing(q, qa)
         except Exception as e:
             comp["derivatives"] = {"error": str(e)}
         out["compare"] = comp

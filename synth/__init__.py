@@ -206,3 +206,22 @@ def adqtb_box(seed_offset=0, n_waters=21952, edge=87.3):
     return water_box(n_waters, 1, edge, SEED_BASE + 2 + seed_offset, cutoff=9.0,
                      ewald_alpha=0.35, pme_grid=128, pme_order=5, qtb_gamma0=0.02,
                      qtb_nseg=1024, qtb_adapt_rate=1e-3, name=f"water{n_waters}_adqtb")
+
+
+def diff_box(config=0):
+    """One of the seeded configurations of the differentiation workload: 1,024 waters
+    (3,072 atoms), 31.3 A cube, P = 16; rc 9 A, alpha 0.35 /A, SPME 32^3 order 5 (about
+    1 A spacing: the workload leaves the grid open)."""
+    return water_box(1024, 16, 31.3, SEED_BASE + 4 + 1000 * config, cutoff=9.0,
+                     ewald_alpha=0.35, pme_grid=32, pme_order=5, name=f"water1024_P16_c{config}")
+
+
+def perturbed_parameters(s, seed):
+    """The workload's reference parameters: charges scaled by U(-5%, +5%) per atom (then
+    shifted to keep the total at zero), LJ sigma and epsilon by U(-3%, +3%) per type."""
+    rng = np.random.default_rng([seed, 77])
+    q = s.charge * (1.0 + rng.uniform(-0.05, 0.05, s.n_atoms))
+    q = q - q.mean()
+    sig = s.lj_sigma * (1.0 + rng.uniform(-0.03, 0.03, len(s.lj_sigma)))
+    eps = s.lj_epsilon * (1.0 + rng.uniform(-0.03, 0.03, len(s.lj_epsilon)))
+    return q, sig, eps
