@@ -42,7 +42,7 @@ def measured_traffic(cls):
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{cls}_water4096_P32.json")
     if not os.path.exists(path):
-        return None, None
+        return None, None, None
     with open(path) as f:
         rec = json.load(f)
     h = hashlib.sha256()
@@ -50,10 +50,10 @@ def measured_traffic(cls):
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
     if h.hexdigest() != rec["source_sha256"]:
-        return None, "kernel sources changed since the counters were taken"
+        return None, "kernel sources changed since the counters were taken", None
     b = (rec["fetch_size_kib_per_dispatch"] * 1024 * rec["fetch_scale"]
          + rec["write_size_kib_per_dispatch"] * 1024 * rec["write_scale"])
-    return b, os.path.relpath(path, ROOT)
+    return b, os.path.relpath(path, ROOT), rec.get("l2_hit_rate")
 
 
 def parse():
@@ -269,7 +269,7 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"], roof["traffic_source"] = measured_traffic(dominant)
+    roof["traffic"], roof["traffic_source"], roof["l2_hit_rate"] = measured_traffic(dominant)
     roof["traffic_unit"] = "HBM bytes per launch"
     roof["kernel"] = dominant
     roof["avg_launch_ms"] = dom_ms / dom_n if dom_n else None
