@@ -130,19 +130,29 @@ __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
     double w[3][ORDER], dw[3][ORDER];
     stencil<ORDER>(xb, A.L, K, i0, w, dw);
     double f0 = 0, f1 = 0, f2 = 0;
+    int o2[ORDER];                    // offsets of the z stencil points within a grid row
+#pragma unroll
+    for (int t2 = 0; t2 < ORDER; ++t2) o2[t2] = wrapk(i0[2] - t2, A.K2) * A.Pc2;
+    const double* gb = A.grid + b;
+#pragma unroll 1
     for (int t0 = 0; t0 < ORDER; ++t0) {
       const int k0 = wrapk(i0[0] - t0, A.K0);
+      // issue the ORDER x ORDER loads of this x plane together, then reduce
+      double ph[ORDER][ORDER];
 #pragma unroll
       for (int t1 = 0; t1 < ORDER; ++t1) {
-        const int k1 = wrapk(i0[1] - t1, A.K1);
-        const double* row = A.grid + ((size_t)(k0 * A.K1 + k1) * A.K2) * A.Pc2 + b;
+        const double* row = gb + (size_t)((k0 * A.K1 + wrapk(i0[1] - t1, A.K1)) * A.K2) * A.Pc2;
+#pragma unroll
+        for (int t2 = 0; t2 < ORDER; ++t2) ph[t1][t2] = row[o2[t2]];
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep the loads in flight together
+#pragma unroll
+      for (int t1 = 0; t1 < ORDER; ++t1) {
         double s = 0, sd = 0;
 #pragma unroll
         for (int t2 = 0; t2 < ORDER; ++t2) {
-          const int k2 = wrapk(i0[2] - t2, A.K2);
-          const double ph = row[(size_t)k2 * A.Pc2];
-          s += w[2][t2] * ph;
-          sd += dw[2][t2] * ph;
+          s += w[2][t2] * ph[t1][t2];
+          sd += dw[2][t2] * ph[t1][t2];
         }
         f0 += dw[0][t0] * w[1][t1] * s;
         f1 += w[0][t0] * dw[1][t1] * s;
