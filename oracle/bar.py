@@ -1,0 +1,53 @@
+"""Bennett acceptance ratio free-energy estimators on per-window energy samples (Sec.
+"Hydration free energies", eqs. PIBAR1-PIBAR2, and the appendix "Single-bead PI-BAR
+Estimator"). TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Notation as in the paper: states A and B, Delta F_AB = beta^-1 ln(Z_A / Z_B), the Fermi
+function f(x) = 1 / (1 + exp(beta x)), and
+
+    Delta F_AB = C + beta^-1 ln( <f(U_A - U_B + C)>_B / <f(U_B - U_A - C)>_A ),
+    C = Delta F_AB + beta^-1 ln(n_B / n_A),
+
+solved by iterating the pair of equations from C = beta^-1 ln(n_B / n_A) until C stops
+moving. The inputs are the energy differences sampled in each state:
+``du_a[k] = U_B(x_k) - U_A(x_k)`` for configurations x_k of state A and
+``du_b[k] = U_B(x_k) - U_A(x_k)`` for configurations of state B (the same sign
+convention for both). PI-BAR takes U = the bead-averaged potential U_P = (1/P) sum_b
+V(x_b) (eq. PI_potential); the single-bead estimator takes V at one bead instead.
+"""
+import numpy as np
+
+
+def fermi(x, beta):
+    """f(x) = 1 / (1 + exp(beta x)), evaluated without overflow."""
+    return 0.5 * (1.0 - np.tanh(0.5 * beta * np.asarray(x, dtype=np.float64)))
+
+
+def bar(du_a, du_b, beta, tol=1e-12, max_iter=10000):
+    """Delta F_AB from the two samples (see the module docstring) -> (dF, iterations)."""
+    du_a = np.asarray(du_a, dtype=np.float64)
+    du_b = np.asarray(du_b, dtype=np.float64)
+    n_a, n_b = len(du_a), len(du_b)
+    shift = np.log(n_b / n_a) / beta
+    C = shift
+    dF = 0.0
+    for it in range(1, max_iter + 1):
+        # <f(U_A - U_B + C)>_B and <f(U_B - U_A - C)>_A
+        num = np.mean(fermi(-du_b + C, beta))
+        den = np.mean(fermi(du_a - C, beta))
+        dF = C + np.log(num / den) / beta
+        C_new = dF + shift
+        if abs(C_new - C) <= tol * max(1.0, abs(C)):
+            return dF, it
+        C = C_new
+    return dF, max_iter
+
+
+def window_differences(E_a_at_a, E_b_at_a, E_a_at_b, E_b_at_b, estimator="pi"):
+    """Energy differences for ``bar`` from per-sample, per-bead potentials [n][P]:
+    E_x_at_y = V of state x at the configurations sampled in state y. ``pi``: the
+    bead-averaged U_P; ``single``: bead 0 only."""
+    def U(E):
+        E = np.asarray(E, dtype=np.float64)
+        return E.mean(axis=1) if estimator == "pi" else E[:, 0]
+    return U(E_b_at_a) - U(E_a_at_a), U(E_b_at_b) - U(E_a_at_b)

@@ -1,4 +1,5 @@
-"""Per-bead potential V(x) of the flexible 3-site water model and its gradient.
+"""Per-bead potential V(x) of the flexible 3-site water model and its gradient (with, for
+alchemical runs, a solute coupled to the water through scaled charges and soft-core LJ).
 
 The paper leaves V to the force field (Sec. "Massively Parallel Implementation": the
 force evaluation is done independently on each bead). The model here is the one the
@@ -67,8 +68,13 @@ def centroids_of(pos):
     return c / pos.shape[0]
 
 
-def real_space(x, pairs, charge, types, sigma, eps, box, alpha, rc, coulomb):
-    """Ewald real-space Coulomb and O-O LJ over listed pairs whose bead distance < rc."""
+def real_space(x, pairs, charge, types, sigma, eps, box, alpha, rc, coulomb, soft=None,
+               lam_vdw=1.0, sc_alpha=0.5):
+    """Ewald real-space Coulomb and LJ over listed pairs whose bead distance < rc.
+
+    ``soft`` (per type, optional) marks the solute types of an alchemical run: a pair with
+    exactly one solute atom takes the soft-core form of its LJ term (see ``soft_core``)
+    at coupling ``lam_vdw``; every other pair keeps the plain form."""
     i, j = pairs[:, 0], pairs[:, 1]
     d = min_image(x[j] - x[i], box)
     r2 = np.einsum("ij,ij->i", d, d)
@@ -84,12 +90,46 @@ def real_space(x, pairs, charge, types, sigma, eps, box, alpha, rc, coulomb):
     sr6 = (s * s / r2) ** 3
     e_lj = 4.0 * e * (sr6 * sr6 - sr6)
     de_lj = 4.0 * e * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r
+    if soft is not None:
+        soft = np.asarray(soft, dtype=bool)
+        mixed = (soft[types[i]] != soft[types[j]]) & (e > 0)
+        e_lj[mixed], de_lj[mixed] = soft_core(r[mixed], s[mixed], e[mixed], lam_vdw, sc_alpha)
     # gradient wrt x_j is dE/dr * d/r, wrt x_i the opposite
     gj = ((de_c + de_lj) / r)[:, None] * d
     grad = np.zeros_like(x)
     np.add.at(grad, j, gj)
     np.add.at(grad, i, -gj)
     return e_c.sum(), e_lj.sum(), grad
+
+
+def soft_core(r, s, e, lam, sc_alpha):
+    """Soft-core LJ of a solute-environment pair (the free-energy decoupling path of Sec.
+    "Hydration free energies", soft-core van der Waals with Beutler's form):
+    E = lam 4 e [1/D^2 - 1/D] with D = sc_alpha (1 - lam) + (r/s)^6; at lam = 1 this is
+    plain LJ, at lam = 0 it vanishes, and for lam < 1 it stays finite as r -> 0.
+    -> (E, dE/dr) per pair."""
+    x6 = (r / s) ** 6
+    D = sc_alpha * (1.0 - lam) + x6
+    E = lam * 4.0 * e * (1.0 / (D * D) - 1.0 / D)
+    dE_dD = lam * 4.0 * e * (-2.0 / D ** 3 + 1.0 / (D * D))
+    return E, dE_dD * 6.0 * x6 / r
+
+
+def charges_of(s):
+    """Charges entering every electrostatic term: a solute atom's charge is scaled by the
+    electrostatic coupling lambda_elec (the solute's charges are scaled down, Sec.
+    "Hydration free energies"), so solute-solvent terms scale with lambda_elec and the
+    solute's internal ones with its square; no solute -> the charges as given."""
+    soft = getattr(s, "type_soft", None)
+    if soft is None:
+        return s.charge
+    return s.charge * np.where(np.asarray(soft, dtype=bool)[s.types], s.lambda_elec, 1.0)
+
+
+def _lj_soft(s):
+    soft = getattr(s, "type_soft", None)
+    return dict(soft=soft, lam_vdw=getattr(s, "lambda_vdw", 1.0),
+                sc_alpha=getattr(s, "sc_alpha", 0.5))
 
 
 def intramolecular(x, box, r0, kb, theta0, ktheta):
@@ -149,12 +189,13 @@ def self_energy(charge, alpha, coulomb):
 def bead_potential(x, s, pairs):
     """All terms of V at one bead configuration x [N][3] -> (energies[7], grad [N][3])."""
     box = s.box
+    q = charges_of(s)
     e_b, e_a, g_in = intramolecular(x, box, s.bond_r0, s.bond_k, s.angle_theta0, s.angle_k)
-    e_c, e_lj, g_rs = real_space(x, pairs, s.charge, s.types, s.lj_sigma, s.lj_epsilon,
-                                 box, s.ewald_alpha, s.cutoff, s.coulomb)
-    e_x, g_x = excluded_correction(x, s.charge, box, s.ewald_alpha, s.coulomb)
-    e_s = self_energy(s.charge, s.ewald_alpha, s.coulomb)
-    e_r, g_r = _spme.spme(x, s.charge, box, s.pme_grid, s.pme_order, s.ewald_alpha, s.coulomb)
+    e_c, e_lj, g_rs = real_space(x, pairs, q, s.types, s.lj_sigma, s.lj_epsilon,
+                                 box, s.ewald_alpha, s.cutoff, s.coulomb, **_lj_soft(s))
+    e_x, g_x = excluded_correction(x, q, box, s.ewald_alpha, s.coulomb)
+    e_s = self_energy(q, s.ewald_alpha, s.coulomb)
+    e_r, g_r = _spme.spme(x, q, box, s.pme_grid, s.pme_order, s.ewald_alpha, s.coulomb)
     E = np.array([e_b, e_a, e_c, e_lj, e_x, e_s, e_r])
     return E, g_in + g_rs + g_x + g_r
 
@@ -199,13 +240,14 @@ def evaluate_slow(pos, s, r_list=None):
     P = pos.shape[0]
     E = np.zeros((P, len(TERMS)))
     G = np.zeros_like(pos)
+    q = charges_of(s)
     for b in range(P):
         x = pos[b]
-        e_c, e_lj, g_rs = real_space(x, pairs, s.charge, s.types, s.lj_sigma, s.lj_epsilon,
-                                     s.box, s.ewald_alpha, s.cutoff, s.coulomb)
-        e_x, g_x = excluded_correction(x, s.charge, s.box, s.ewald_alpha, s.coulomb)
-        e_s = self_energy(s.charge, s.ewald_alpha, s.coulomb)
-        e_r, g_r = _spme.spme(x, s.charge, s.box, s.pme_grid, s.pme_order, s.ewald_alpha,
+        e_c, e_lj, g_rs = real_space(x, pairs, q, s.types, s.lj_sigma, s.lj_epsilon,
+                                     s.box, s.ewald_alpha, s.cutoff, s.coulomb, **_lj_soft(s))
+        e_x, g_x = excluded_correction(x, q, s.box, s.ewald_alpha, s.coulomb)
+        e_s = self_energy(q, s.ewald_alpha, s.coulomb)
+        e_r, g_r = _spme.spme(x, q, s.box, s.pme_grid, s.pme_order, s.ewald_alpha,
                               s.coulomb)
         E[b] = [0.0, 0.0, e_c, e_lj, e_x, e_s, e_r]
         G[b] = g_rs + g_x + g_r

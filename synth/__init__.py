@@ -79,6 +79,11 @@ class System:
     pos: np.ndarray = None     # [P][N][3]
     vel: np.ndarray = None     # [P][N][3]
     name: str = ""
+    # alchemical runs: per-type solute flags (None: no solute), couplings, soft-core alpha
+    type_soft: np.ndarray = None
+    lambda_elec: float = 1.0
+    lambda_vdw: float = 1.0
+    sc_alpha: float = 0.5
 
     @property
     def n_atoms(self) -> int:
@@ -117,7 +122,7 @@ def _min_intermolecular_distance(xyz, box, mol):
 def water_box(n_waters, n_beads, box_edge=None, seed=0, temperature=300.0, *,
               cutoff=9.0, ewald_alpha=0.35, pme_grid=64, pme_order=5, skin=2.0,
               dt=0.5, gamma_centroid=1e-3, trpmd_c=2.0, qtb_gamma0=0.0,
-              qtb_nseg=1024, qtb_adapt_rate=1e-3, bead_spread=True, name=""):
+              qtb_nseg=1024, qtb_adapt_rate=1e-3, bead_spread=True, name="", solute=0):
     """Jittered-lattice water box with random orientations and thermal beads.
 
     Recipe: molecules on the first ``n_waters`` sites (seeded permutation when the cube is
@@ -155,8 +160,12 @@ def water_box(n_waters, n_beads, box_edge=None, seed=0, temperature=300.0, *,
     N = 3 * n_waters
     types = np.tile(np.array([0, 1, 1], dtype=np.int32), n_waters)
     mass_amu = np.where(types == 0, MASS_O_AMU, MASS_H_AMU)
-    mass = mass_amu * AMU
     charge = np.where(types == 0, Q_O, Q_H).astype(np.float64)
+    lj_sigma, lj_epsilon, type_soft = np.array([SIGMA_OO, 0.0]), np.array([EPS_OO, 0.0]), None
+    if solute:
+        types, mass_amu, charge, lj_sigma, lj_epsilon, type_soft = _solute(
+            rng, xyz, box, solute, types, mass_amu, charge)
+    mass = mass_amu * AMU
     kT = KB * temperature
     P = n_beads
 
@@ -173,8 +182,8 @@ def water_box(n_waters, n_beads, box_edge=None, seed=0, temperature=300.0, *,
     vel -= vcm
 
     return System(n_waters=n_waters, n_beads=P, box=box, types=types, mass=mass,
-                  charge=charge, lj_sigma=np.array([SIGMA_OO, 0.0]),
-                  lj_epsilon=np.array([EPS_OO, 0.0]), bond_r0=BOND_R0, bond_k=BOND_K,
+                  charge=charge, lj_sigma=lj_sigma, type_soft=type_soft,
+                  lj_epsilon=lj_epsilon, bond_r0=BOND_R0, bond_k=BOND_K,
                   angle_theta0=ANGLE_THETA0, angle_k=ANGLE_K, coulomb=COULOMB,
                   ewald_alpha=ewald_alpha, cutoff=cutoff, skin=skin,
                   pme_grid=(pme_grid,) * 3 if np.isscalar(pme_grid) else tuple(pme_grid),
@@ -182,6 +191,56 @@ def water_box(n_waters, n_beads, box_edge=None, seed=0, temperature=300.0, *,
                   gamma_centroid=gamma_centroid, trpmd_c=trpmd_c, seed=seed,
                   qtb_gamma0=qtb_gamma0, qtb_nseg=qtb_nseg, qtb_adapt_rate=qtb_adapt_rate,
                   pos=pos, vel=vel, name=name)
+
+
+# --- alchemical solute ------------------------------------------------------------------
+SOLUTE_TYPES = 6                  # types 2..7; type t + 2 is solute type t
+SOLUTE_MASS_AMU = (12.011, 14.007, 15.999)   # centre, first and second outer atom
+
+
+def _solute(rng, xyz, box, n_mol, types, mass_amu, charge):
+    """Turn the ``n_mol`` molecules nearest the box centre into the solute: triatomic
+    fragments (the water's bonded geometry and force constants) whose 3 n_mol atoms take
+    solute types 2.. (molecule k uses types 2 + 3 (k % 2) + {0, 1, 2}); per type a sigma
+    U(2.5, 3.8) A and an epsilon U(0.05, 0.2) kcal/mol; per atom a charge U(-0.6, 0.6),
+    shifted to a zero total and scaled back into the range if the shift left it."""
+    O = xyz[0::3]
+    d = O - 0.5 * box
+    pick = np.sort(np.argsort(np.einsum("ij,ij->i", d, d), kind="stable")[:n_mol])
+    types = types.copy(); mass_amu = mass_amu.astype(np.float64).copy(); charge = charge.copy()
+    sig = np.concatenate([[SIGMA_OO, 0.0], rng.uniform(2.5, 3.8, SOLUTE_TYPES)])
+    eps = np.concatenate([[EPS_OO, 0.0], rng.uniform(0.05, 0.2, SOLUTE_TYPES)])
+    q = rng.uniform(-0.6, 0.6, 3 * n_mol)
+    q -= q.mean()
+    if np.abs(q).max() > 0.6:
+        q *= 0.6 / np.abs(q).max()
+    for k, m in enumerate(pick):
+        for a in range(3):
+            types[3 * m + a] = 2 + 3 * (k % 2) + a
+            mass_amu[3 * m + a] = SOLUTE_MASS_AMU[a]
+            charge[3 * m + a] = q[3 * k + a]
+    soft = np.zeros(2 + SOLUTE_TYPES, dtype=np.int32)
+    soft[2:] = 1
+    return types, mass_amu, charge, sig, eps, soft
+
+
+def alchemical_window(i, n_windows=16, n_beads=None, n_waters=None):
+    """Instance i of the batched free-energy workload: 16 windows lambda = i / 15 of a
+    12-atom solute (4 triatomic fragments) in n_w = [256, 512, 1024, 2048][i % 4] waters
+    with P = [8, 16, 32][i % 3]; lambda_elec = max(0, 2 lambda - 1), lambda_vdw =
+    min(1, 2 lambda) (lambda = 1 fully coupled), soft-core alpha 0.5. Box edge
+    (n_w / 0.03337)^(1/3) (19.7 to 39.4 A) holding the n_w + 4 molecules, rc 9 A, alpha
+    0.35 /A, SPME order 5 on a 32^3 grid (64^3 for 2,048 waters): 0.6 to 1 A spacing."""
+    n_w = [256, 512, 1024, 2048][i % 4] if n_waters is None else n_waters
+    P = [8, 16, 32][i % 3] if n_beads is None else n_beads
+    lam = i / (n_windows - 1)
+    L = (n_w / WATER_DENSITY) ** (1.0 / 3.0)
+    grid = 32 if n_w <= 1024 else 64
+    s = water_box(n_w + 4, P, L, SEED_BASE + 3 + 1000 * i, cutoff=9.0, ewald_alpha=0.35,
+                  pme_grid=grid, pme_order=5, solute=4, name=f"alchem{i}_w{n_w}_P{P}")
+    s.lambda_elec = max(0.0, 2.0 * lam - 1.0)
+    s.lambda_vdw = min(1.0, 2.0 * lam)
+    return s
 
 
 # --- the named workloads ---------------------------------------------------------------
