@@ -8,8 +8,12 @@ function f(x) = 1 / (1 + exp(beta x)), and
     Delta F_AB = C + beta^-1 ln( <f(U_A - U_B + C)>_B / <f(U_B - U_A - C)>_A ),
     C = Delta F_AB + beta^-1 ln(n_B / n_A),
 
-solved by iterating the pair of equations from C = beta^-1 ln(n_B / n_A) until C stops
-moving. The inputs are the energy differences sampled in each state:
+a self-consistent pair of equations. Substituting the second into the first, the pair
+holds exactly when sum_B f(C - du) = sum_A f(du - C) (a reading: the paper says only that
+the set is solved iteratively). The left side falls and the right side rises with C, so
+the root is unique; it is found here by bisection, which converges whatever the overlap of
+the two samples (plain fixed-point iteration of the pair can stall when it is poor).
+The inputs are the energy differences sampled in each state:
 ``du_a[k] = U_B(x_k) - U_A(x_k)`` for configurations x_k of state A and
 ``du_b[k] = U_B(x_k) - U_A(x_k)`` for configurations of state B (the same sign
 convention for both). PI-BAR takes U = the bead-averaged potential U_P = (1/P) sum_b
@@ -23,24 +27,28 @@ def fermi(x, beta):
     return 0.5 * (1.0 - np.tanh(0.5 * beta * np.asarray(x, dtype=np.float64)))
 
 
-def bar(du_a, du_b, beta, tol=1e-12, max_iter=10000):
+def bar(du_a, du_b, beta, max_iter=400):
     """Delta F_AB from the two samples (see the module docstring) -> (dF, iterations)."""
     du_a = np.asarray(du_a, dtype=np.float64)
     du_b = np.asarray(du_b, dtype=np.float64)
     n_a, n_b = len(du_a), len(du_b)
-    shift = np.log(n_b / n_a) / beta
-    C = shift
-    dF = 0.0
+
+    def h(C):                      # decreasing in C; zero at the self-consistent C
+        return np.sum(fermi(C - du_b, beta)) - np.sum(fermi(du_a - C, beta))
+
+    lo = min(du_a.min(), du_b.min()) - 40.0 / beta
+    hi = max(du_a.max(), du_b.max()) + 40.0 / beta
+    it = 0
     for it in range(1, max_iter + 1):
-        # <f(U_A - U_B + C)>_B and <f(U_B - U_A - C)>_A
-        num = np.mean(fermi(-du_b + C, beta))
-        den = np.mean(fermi(du_a - C, beta))
-        dF = C + np.log(num / den) / beta
-        C_new = dF + shift
-        if abs(C_new - C) <= tol * max(1.0, abs(C)):
-            return dF, it
-        C = C_new
-    return dF, max_iter
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            break
+        if h(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    C = 0.5 * (lo + hi)
+    return C - np.log(n_b / n_a) / beta, it
 
 
 def window_differences(E_a_at_a, E_b_at_a, E_a_at_b, E_b_at_b, estimator="pi"):
