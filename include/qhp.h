@@ -141,6 +141,19 @@ typedef struct qhp_params {
   double qtb_tau;           /* RATIO: running-mean time tau (same for every type), > 0.
                                The means start from zero; where <C_vv> <= 0 gamma keeps
                                its value; the gamma_min clamp follows either scheme.    */
+  /* Alchemical coupling of a solute (Sec. "Hydration free energies": the solute is
+   * decoupled from the solvent by scaling its charges down, then its van der Waals
+   * interactions through a soft-core potential). The solute is the set of atoms whose type
+   * has type_soft = 1. Every solute charge is multiplied by lambda_elec in all
+   * electrostatic terms (so solute-solvent terms scale with lambda_elec and the solute's
+   * internal ones with its square). The LJ term of a pair with exactly one solute atom
+   * takes Beutler's soft-core form lambda_vdw 4 eps [1/D^2 - 1/D], D = sc_alpha
+   * (1 - lambda_vdw) + (r/sigma)^6; solute-solute and solvent-solvent pairs keep the plain
+   * form. type_soft = NULL: no solute, and the three numbers below are ignored.         */
+  const int32_t* type_soft; /* [n_types] 0/1, or NULL                                   */
+  double lambda_elec;       /* in [0, 1]; 1 = fully coupled                               */
+  double lambda_vdw;        /* in [0, 1]; 1 = fully coupled                               */
+  double sc_alpha;          /* soft-core alpha >= 0 (0.5 in the free-energy workload)    */
 } qhp_params;
 
 typedef struct qhp_ctx qhp_ctx;
@@ -232,6 +245,48 @@ QHP_API int qhp_nlist_stats(qhp_ctx* ctx, int64_t* builds, int32_t* max_count, i
  * stream 6 = adQTB white noise of global step `step`, out [N][3]. Device computation,
  * host output. */
 QHP_API int qhp_noise_export(qhp_ctx* ctx, int32_t stream, int64_t step, double* out);
+
+/* Alchemical runs (type_soft set): change the couplings of the propagated system
+ * (both in [0, 1]; the solute charges are rescaled from the ones given at creation).
+ * QHP_EINVAL without a solute. Takes effect for the next step or evaluation. */
+QHP_API int qhp_set_lambda(qhp_ctx* ctx, double lambda_elec, double lambda_vdw);
+
+/* qhp_eval at other couplings, for the energy differences of free-energy estimators
+ * (Sec. "Hydration free energies": each window's samples are evaluated in the neighbouring
+ * states): `pos` [P][N][3] -> `energy` [P][QHP_NTERMS] (nullable) and `forces`
+ * (nullable) of the system at (lambda_elec, lambda_vdw). The propagated state and its
+ * couplings are left alone. QHP_EINVAL without a solute. */
+QHP_API int qhp_eval_lambda(qhp_ctx* ctx, const double* pos, double lambda_elec,
+                            double lambda_vdw, double* energy, double* forces, int mem_kind);
+
+/* Bennett acceptance ratio (Sec. "Hydration free energies", eqs. PIBAR1-PIBAR2): with
+ * du_a[k] = U_B - U_A at the n_a configurations sampled in state A and du_b[k] =
+ * U_B - U_A at the n_b configurations of state B (host arrays), solves the self-consistent
+ *   dF = C + (1/beta) ln( <f(-du + C)>_B / <f(du - C)>_A ),  C = dF + (1/beta) ln(n_b/n_a),
+ * f(x) = 1/(1 + exp(beta x)). The pair holds exactly when sum_B f(C - du) = sum_A f(du - C),
+ * a monotone equation in C with one root, found by safeguarded Newton steps to 1e-13
+ * relative (at most 500). *dF = Delta F_AB = (1/beta) ln(Z_A/Z_B), the paper's sign. PI-BAR takes U = the bead average of V
+ * (eq. PI_potential); the single-bead estimator V at one bead. Host code only: needs no
+ * device. QHP_EINVAL for null pointers, n_a or n_b < 1, beta <= 0; QHP_ENONFINITE for
+ * non-finite input or no convergence. `iterations` is nullable. */
+QHP_API int qhp_bar(const double* du_a, int64_t n_a, const double* du_b, int64_t n_b,
+                    double beta, double* dF, int32_t* iterations);
+
+/* A group of contexts stepped together (batched uneven instances: free-energy windows of
+ * different sizes and bead counts). qhp_group_step advances every member by `nsteps`
+ * steps; each step of all members is one captured HIP graph, launched once, in which each
+ * member's kernels form an independent branch (on its own stream, which must differ from
+ * the other members' for the branches to overlap). The group keeps pointers to the
+ * members, which the caller keeps alive and does not step otherwise while the group is in
+ * use; members need use_graph = 1 and a state (qhp_set_state) before the first group
+ * step. qhp_group_create copies the member list; QHP_EINVAL for n < 1, a null member or a
+ * member twice. A member's qhp_set_lambda or qhp_set_state is picked up by recapturing at
+ * the next group step. Work is queued on the first member's stream. */
+typedef struct qhp_group qhp_group;
+QHP_API int qhp_group_create(qhp_ctx* const* members, int32_t n, qhp_group** out);
+QHP_API int qhp_group_step(qhp_group* group, int32_t nsteps);
+QHP_API int qhp_group_destroy(qhp_group* group);
+QHP_API const char* qhp_group_last_error(qhp_group* group);
 
 /* adQTB: gamma_z(omega_k), k = 0..N_seg, for every type: [n_types][N_seg + 1] (host). */
 QHP_API int qhp_qtb_get_gamma(qhp_ctx* ctx, double* gamma);

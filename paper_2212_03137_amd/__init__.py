@@ -29,7 +29,8 @@ EXPORTS = ("qhp_create", "qhp_destroy", "qhp_eval", "qhp_set_state", "qhp_get_st
            "qhp_step", "qhp_mode_energies", "qhp_nlist_export", "qhp_nlist_stats", "qhp_noise_export",
            "qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta",
            "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error", "qhp_param_grad",
-           "qhp_hvp")
+           "qhp_hvp", "qhp_set_lambda", "qhp_eval_lambda", "qhp_bar", "qhp_group_create",
+           "qhp_group_step", "qhp_group_destroy", "qhp_group_last_error")
 
 
 class QhpError(RuntimeError):
@@ -56,6 +57,8 @@ class Params(C.Structure):
         ("nbr_capacity", C.c_int32), ("use_graph", C.c_int32),
         ("rpc_beads", C.c_int32), ("respa_nalt", C.c_int32),
         ("integrator", C.c_int32), ("qtb_adapt_scheme", C.c_int32), ("qtb_tau", C.c_double),
+        ("type_soft", C.POINTER(C.c_int32)), ("lambda_elec", C.c_double),
+        ("lambda_vdw", C.c_double), ("sc_alpha", C.c_double),
     ]
 
 
@@ -89,11 +92,19 @@ def load():
         getattr(lib, f).argtypes = [vp, vp]
     lib.qhp_profile.argtypes = [vp, I]
     lib.qhp_profile_read.argtypes = [vp, D, C.POINTER(C.c_int64)]
+    lib.qhp_set_lambda.argtypes = [vp, C.c_double, C.c_double]
+    lib.qhp_eval_lambda.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, I]
+    lib.qhp_bar.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_double, D, C.POINTER(C.c_int32)]
+    lib.qhp_group_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
+    lib.qhp_group_step.argtypes = [vp, C.c_int32]
+    lib.qhp_group_destroy.argtypes = [vp]
     lib.qhp_sync.argtypes = [vp]
     lib.qhp_last_error.argtypes = [vp]
     lib.qhp_last_error.restype = C.c_char_p
+    lib.qhp_group_last_error.argtypes = [vp]
+    lib.qhp_group_last_error.restype = C.c_char_p
     for f in EXPORTS:
-        if f != "qhp_last_error":
+        if f not in ("qhp_last_error", "qhp_group_last_error"):
             getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -116,7 +127,8 @@ class Context:
                  precision=FP64, exec_mode=BATCHED, thermostat=TRPMD, qtb_gamma0=0.0,
                  qtb_nseg=1024, qtb_adapt_rate=0.0, qtb_gamma_min_frac=0.01, qtb_classical=False,
                  nbr_capacity=0, use_graph=True, rpc_beads=0, respa_nalt=1, integrator=0,
-                 qtb_adapt_scheme=0, qtb_tau=0.0, stream=None):
+                 qtb_adapt_scheme=0, qtb_tau=0.0, type_soft=None, lambda_elec=1.0,
+                 lambda_vdw=1.0, sc_alpha=0.5, stream=None):
         self._lib = load()
         self.N, self.P = int(n_atoms), int(n_beads)
         self.n_types = len(lj_sigma)
@@ -149,6 +161,10 @@ class Context:
         p.use_graph = int(bool(use_graph))
         p.rpc_beads, p.respa_nalt = int(rpc_beads), int(respa_nalt)
         p.integrator, p.qtb_adapt_scheme, p.qtb_tau = int(integrator), int(qtb_adapt_scheme), qtb_tau
+        if type_soft is not None:
+            self._keep.append(np.ascontiguousarray(type_soft, dtype=np.int32))
+            p.type_soft = self._keep[-1].ctypes.data_as(C.POINTER(C.c_int32))
+            p.lambda_elec, p.lambda_vdw, p.sc_alpha = lambda_elec, lambda_vdw, sc_alpha
         self.params = p
         h = C.c_void_p()
         rc = self._lib.qhp_create(C.byref(p), C.c_void_p(stream) if stream else None, C.byref(h))
@@ -168,6 +184,9 @@ class Context:
                     trpmd_c=s.trpmd_c, seed=s.seed, qtb_gamma0=s.qtb_gamma0,
                     qtb_nseg=s.qtb_nseg, qtb_adapt_rate=s.qtb_adapt_rate,
                     qtb_gamma_min_frac=s.qtb_gamma_min_frac)
+        if getattr(s, "type_soft", None) is not None:
+            args.update(type_soft=s.type_soft, lambda_elec=s.lambda_elec,
+                        lambda_vdw=s.lambda_vdw, sc_alpha=s.sc_alpha)
         args.update(kw)
         return cls(**args)
 
@@ -200,6 +219,27 @@ class Context:
         E = np.zeros((self.P, NTERMS))
         F = np.zeros((self.P, self.N, 3))
         self._check(self._lib.qhp_eval(self._h, _ptr(pos), _ptr(E), _ptr(F), MEM_HOST))
+        return E, F
+
+    def set_lambda(self, lambda_elec, lambda_vdw):
+        """Couplings of the propagated alchemical system (qhp_set_lambda)."""
+        self._check(self._lib.qhp_set_lambda(self._h, float(lambda_elec), float(lambda_vdw)))
+
+    def eval_lambda(self, pos, lambda_elec, lambda_vdw, forces=True):
+        """qhp_eval of the system at other couplings: energies [P][7] (and forces)."""
+        E = np.zeros((self.P, NTERMS))
+        F = np.zeros((self.P, self.N, 3)) if forces else None
+        if hasattr(pos, "data_ptr"):           # torch tensor on the context's device
+            import torch
+            Et = torch.zeros((self.P, NTERMS), dtype=torch.float64, device=pos.device)
+            self._check(self._lib.qhp_eval_lambda(self._h, _ptr(pos), float(lambda_elec),
+                                                  float(lambda_vdw), _ptr(Et), None,
+                                                  MEM_DEVICE))
+            self.sync()
+            return Et.cpu().numpy(), None
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        self._check(self._lib.qhp_eval_lambda(self._h, _ptr(pos), float(lambda_elec),
+                                              float(lambda_vdw), _ptr(E), _ptr(F), MEM_HOST))
         return E, F
 
     def param_grad(self, pos):
@@ -299,3 +339,53 @@ class Context:
 
     def eval_device(self, pos, energy, forces):
         self._check(self._lib.qhp_eval(self._h, _ptr(pos), _ptr(energy), _ptr(forces), MEM_DEVICE))
+
+
+def bar(du_a, du_b, beta):
+    """Bennett acceptance ratio Delta F_AB (qhp_bar) -> (dF, iterations); du_a, du_b are
+    U_B - U_A sampled in states A and B."""
+    lib = load()
+    a = np.ascontiguousarray(du_a, dtype=np.float64)
+    b = np.ascontiguousarray(du_b, dtype=np.float64)
+    dF = C.c_double()
+    it = C.c_int32()
+    rc = lib.qhp_bar(_ptr(a), len(a), _ptr(b), len(b), float(beta), C.byref(dF), C.byref(it))
+    if rc != OK:
+        raise QhpError(rc, "qhp_bar failed")
+    return dF.value, it.value
+
+
+class Group:
+    """Contexts stepped together, one captured graph per step of all members."""
+
+    def __init__(self, contexts):
+        self._lib = load()
+        self.members = list(contexts)
+        arr = (C.c_void_p * len(self.members))(*[c._h.value for c in self.members])
+        h = C.c_void_p()
+        rc = self._lib.qhp_group_create(arr, len(self.members), C.byref(h))
+        if rc != OK:
+            raise QhpError(rc, "qhp_group_create failed")
+        self._h = h
+
+    def step(self, nsteps=1):
+        rc = self._lib.qhp_group_step(self._h, int(nsteps))
+        if rc != OK:
+            raise QhpError(rc, self._lib.qhp_group_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.qhp_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -108,7 +108,7 @@ void free_all(qhp_ctx* c) {
                   c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
                   c->nnbr, c->bmax, c->grid, c->grid2, c->tile_nbr, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
                   c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->pg_dq, c->pg_lj,
-                  c->hvp_out,
+                  c->hvp_out, c->d_charge_alt,
                   c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.vvsum, c->qtb.vfsum,
                   c->qtb.avg_vv, c->qtb.avg_vf, c->qtb.d_tmass, c->qtb.d_inv_count,
@@ -130,6 +130,19 @@ hipError_t upload_twiddles(double2** dst, int L) {
   hipError_t e = dalloc(dst, L);
   if (e != hipSuccess) return e;
   return hipMemcpy(*dst, t.data(), L * sizeof(double2), hipMemcpyHostToDevice);
+}
+
+// charges of the alchemical system at electrostatic coupling le: solute charges scaled
+void scaled_charges(const qhp_ctx* c, double le, std::vector<double>& out) {
+  out.resize(c->N);
+  for (int i = 0; i < c->N; ++i) out[i] = c->q_given[i] * (c->soft[c->type[i]] ? le : 1.0);
+}
+
+// Ewald self term -C alpha / sqrt(pi) sum q^2
+double self_of(const qhp_ctx* c, const std::vector<double>& q) {
+  double q2 = 0;
+  for (double v : q) q2 += v * v;
+  return -c->p.coulomb * c->p.ewald_alpha / std::sqrt(M_PI) * q2;
 }
 
 int validate(const qhp_params* p, std::string& why) {
@@ -186,6 +199,13 @@ int validate(const qhp_params* p, std::string& why) {
       return QHP_EUNSUPPORTED;
     }
   }
+  if (p->type_soft) {
+    for (int t = 0; t < p->n_types; ++t)
+      if (p->type_soft[t] != 0 && p->type_soft[t] != 1) return bad("type_soft must be 0 or 1");
+    if (!(p->lambda_elec >= 0 && p->lambda_elec <= 1) || !(p->lambda_vdw >= 0 && p->lambda_vdw <= 1))
+      return bad("lambda_elec and lambda_vdw must be in [0, 1]");
+    if (!(p->sc_alpha >= 0) || !std::isfinite(p->sc_alpha)) return bad("sc_alpha must be >= 0");
+  }
   if (p->thermostat == QHP_ADQTB) {
     if (p->n_beads != 1) return bad("adQTB requires n_beads = 1");
     if (!pow2(p->qtb_nseg) || p->qtb_nseg < 16 || p->qtb_nseg > 1024)
@@ -235,6 +255,14 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   c->type.assign(p->type, p->type + N);
   c->mass.assign(p->mass, p->mass + N);
   c->charge.assign(p->charge, p->charge + N);
+  c->q_given = c->charge;
+  if (p->type_soft) {
+    c->alch = true;
+    c->soft.assign(p->type_soft, p->type_soft + p->n_types);
+    c->lam_e = p->lambda_elec;
+    c->lam_v = p->lambda_vdw;
+    scaled_charges(c, c->lam_e, c->charge);
+  }
   c->sigma.assign(p->lj_sigma, p->lj_sigma + p->n_types);
   c->eps.assign(p->lj_epsilon, p->lj_epsilon + p->n_types);
   for (int d = 0; d < 3; ++d) c->K[d] = p->pme_grid[d];
@@ -294,9 +322,8 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   TRY(hipMemcpy(c->d_type, c->type.data(), N * sizeof(int), hipMemcpyHostToDevice));
   TRY(up(&c->d_mass, c->mass)); TRY(up(&c->d_charge, c->charge)); TRY(up(&c->d_sqrt_mkT, smkT));
   TRY(up(&c->d_sigma, c->sigma)); TRY(up(&c->d_eps, c->eps));
-  double q2 = 0;
-  for (int i = 0; i < N; ++i) q2 += c->charge[i] * c->charge[i];
-  c->self_energy = -p->coulomb * p->ewald_alpha / std::sqrt(M_PI) * q2;
+  if (c->alch) TRY(dalloc(&c->d_charge_alt, N));
+  c->self_energy = self_of(c, c->charge);
 
   // ---- state ----
   const size_t NP3 = (size_t)3 * N * P;
@@ -568,11 +595,111 @@ extern "C" int qhp_eval(qhp_ctx* c, const double* pos, double* energy, double* f
   return QHP_OK;
 }
 
+extern "C" int qhp_set_lambda(qhp_ctx* c, double lambda_elec, double lambda_vdw) {
+  if (!c) return QHP_EINVAL;
+  if (!c->alch) return qhp_fail(c, QHP_EINVAL, "no solute (type_soft was not given)");
+  if (!(lambda_elec >= 0 && lambda_elec <= 1) || !(lambda_vdw >= 0 && lambda_vdw <= 1))
+    return qhp_fail(c, QHP_EINVAL, "lambda_elec and lambda_vdw must be in [0, 1]");
+  // earlier queued work may still read the charges: let it finish before overwriting
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  c->lam_e = lambda_elec;
+  c->lam_v = lambda_vdw;
+  scaled_charges(c, c->lam_e, c->charge);
+  c->self_energy = self_of(c, c->charge);
+  QHP_HIP(c, hipMemcpy(c->d_charge, c->charge.data(), (size_t)c->N * sizeof(double),
+                       hipMemcpyHostToDevice));
+  // the captured step holds the old LJ tables and self energy in its kernel arguments
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  c->step_exec = nullptr;
+  ++c->graph_epoch;
+  return QHP_OK;
+}
+
+extern "C" int qhp_eval_lambda(qhp_ctx* c, const double* pos, double lambda_elec,
+                               double lambda_vdw, double* energy, double* forces, int mem_kind) {
+  if (!c || !pos) return qhp_fail(c, QHP_EINVAL, "null argument");
+  if (!c->alch) return qhp_fail(c, QHP_EINVAL, "no solute (type_soft was not given)");
+  if (!(lambda_elec >= 0 && lambda_elec <= 1) || !(lambda_vdw >= 0 && lambda_vdw <= 1))
+    return qhp_fail(c, QHP_EINVAL, "lambda_elec and lambda_vdw must be in [0, 1]");
+  // the other couplings' charges go to a second buffer (the propagated system's stay in
+  // place for captured steps); launches read the couplings when they are queued
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  scaled_charges(c, lambda_elec, c->charge_alt);
+  QHP_HIP(c, hipMemcpy(c->d_charge_alt, c->charge_alt.data(), (size_t)c->N * sizeof(double),
+                       hipMemcpyHostToDevice));
+  const double le = c->lam_e, lv = c->lam_v, self = c->self_energy;
+  std::swap(c->d_charge, c->d_charge_alt);
+  c->lam_e = lambda_elec;
+  c->lam_v = lambda_vdw;
+  c->self_energy = self_of(c, c->charge_alt);
+  int r = qhp_eval(c, pos, energy, forces, mem_kind);
+  std::swap(c->d_charge, c->d_charge_alt);
+  c->lam_e = le;
+  c->lam_v = lv;
+  c->self_energy = self;
+  if (r) return r;
+  // the alternative buffer is reused by the next call: finish reading it here
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  return QHP_OK;
+}
+
+extern "C" int qhp_bar(const double* du_a, int64_t n_a, const double* du_b, int64_t n_b,
+                       double beta, double* dF, int32_t* iterations) {
+  if (!du_a || !du_b || !dF || n_a < 1 || n_b < 1 || !(beta > 0)) return QHP_EINVAL;
+  double lo = du_a[0], hi = du_a[0];
+  for (int64_t k = 0; k < n_a; ++k) {
+    if (!std::isfinite(du_a[k])) return QHP_ENONFINITE;
+    lo = std::min(lo, du_a[k]); hi = std::max(hi, du_a[k]);
+  }
+  for (int64_t k = 0; k < n_b; ++k) {
+    if (!std::isfinite(du_b[k])) return QHP_ENONFINITE;
+    lo = std::min(lo, du_b[k]); hi = std::max(hi, du_b[k]);
+  }
+  // The pair of equations holds exactly when the self-consistent constant C solves
+  // h(C) = sum_B f(C - du) - sum_A f(du - C) = 0, with f(x) = 1 / (1 + e^{beta x}):
+  // h falls monotonically from n_b to -n_a, so its root is unique. Newton steps on h,
+  // kept inside a bracket that shrinks with every evaluation (bisection when a step
+  // would leave it).
+  auto fermi = [beta](double x) { return 0.5 - 0.5 * std::tanh(0.5 * beta * x); };
+  auto eval = [&](double C, double& h, double& dh) {
+    h = 0.0; dh = 0.0;
+    for (int64_t k = 0; k < n_b; ++k) {
+      const double f = fermi(C - du_b[k]);
+      h += f; dh -= beta * f * (1.0 - f);
+    }
+    for (int64_t k = 0; k < n_a; ++k) {
+      const double f = fermi(du_a[k] - C);
+      h -= f; dh -= beta * f * (1.0 - f);
+    }
+  };
+  lo -= 40.0 / beta;
+  hi += 40.0 / beta;
+  double C = 0.5 * (lo + hi);
+  for (int it = 1; it <= 500; ++it) {
+    double h, dh;
+    eval(C, h, dh);
+    if (h > 0) lo = C; else hi = C;
+    double next = dh < 0 ? C - h / dh : 0.5 * (lo + hi);
+    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+    const bool done = std::fabs(next - C) <= 1e-13 * std::max(1.0, std::fabs(C)) || h == 0.0 ||
+                      !(0.5 * (lo + hi) > lo && 0.5 * (lo + hi) < hi);
+    C = h == 0.0 ? C : next;
+    if (done) {
+      *dF = C - std::log((double)n_b / (double)n_a) / beta;
+      if (iterations) *iterations = it;
+      return std::isfinite(*dF) ? QHP_OK : QHP_ENONFINITE;
+    }
+  }
+  return QHP_ENONFINITE;
+}
+
 extern "C" int qhp_param_grad(qhp_ctx* c, const double* pos, double* dq, double* deps,
                               double* dsig, int mem_kind) {
   if (!c || !pos || !dq || !deps || !dsig) return qhp_fail(c, QHP_EINVAL, "null argument");
   if (c->p.exec == QHP_PLAIN)
     return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients need exec = QHP_BATCHED");
+  if (c->alch)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients of an alchemical system");
   int r = copy_in(c, pos, mem_kind, c->x);
   if (r) return r;
   QHP_HIP(c, launch_centroid_of_beads(c));
@@ -608,6 +735,8 @@ extern "C" int qhp_hvp(qhp_ctx* c, const double* pos, const double* dir, double*
   if (mix && (!deps || !dsig)) return qhp_fail(c, QHP_EINVAL, "dq, deps and dsig go together");
   if (c->p.exec == QHP_PLAIN)
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products need exec = QHP_BATCHED");
+  if (c->alch)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products of an alchemical system");
   const size_t n = (size_t)c->P * c->N * 3;
   if (!c->hvp_out) QHP_HIP(c, hipMalloc((void**)&c->hvp_out, n * sizeof(double)));
   int r = copy_in(c, dir, mem_kind, c->io_b);
@@ -919,3 +1048,138 @@ extern "C" int qhp_sync(qhp_ctx* c) {
 }
 
 extern "C" const char* qhp_last_error(qhp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+// ------------------------------- groups of contexts ------------------------------------
+struct qhp_group {
+  std::vector<qhp_ctx*> m;
+  std::vector<int64_t> epoch;        // members' graph epochs at the last capture
+  std::vector<hipEvent_t> ev;        // [0] fork, [1..n-1] joins
+  hipGraphExec_t exec = nullptr;
+  std::string err;
+};
+
+static int group_fail(qhp_group* g, int code, const std::string& msg) {
+  g->err = msg;
+  return code;
+}
+
+static void group_free(qhp_group* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  g->exec = nullptr;
+  for (hipEvent_t e : g->ev)
+    if (e) (void)hipEventDestroy(e);
+  g->ev.clear();
+}
+
+extern "C" int qhp_group_create(qhp_ctx* const* members, int32_t n, qhp_group** out) {
+  if (!out) return QHP_EINVAL;
+  *out = nullptr;
+  if (!members || n < 1) return QHP_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!members[i]) return QHP_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (members[j] == members[i]) return QHP_EINVAL;
+    if (members[i]->p.thermostat != QHP_TRPMD) return QHP_EUNSUPPORTED;
+  }
+  qhp_group* g = new (std::nothrow) qhp_group();
+  if (!g) return QHP_ENOMEM;
+  g->m.assign(members, members + n);
+  g->epoch.assign(n, -1);
+  g->ev.assign(n, nullptr);
+  for (int i = 0; i < n; ++i)
+    if (hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming) != hipSuccess) {
+      group_free(g);
+      delete g;
+      return QHP_EDEVICE;
+    }
+  *out = g;
+  return QHP_OK;
+}
+
+extern "C" int qhp_group_destroy(qhp_group* g) {
+  if (!g) return QHP_EINVAL;
+  group_free(g);
+  delete g;
+  return QHP_OK;
+}
+
+extern "C" const char* qhp_group_last_error(qhp_group* g) { return g ? g->err.c_str() : "null group"; }
+
+// One step of every member as one graph: member 0's stream is the origin; the others fork
+// from it by an event and join back by one event each, so their kernels form independent
+// branches of the graph.
+static int group_capture(qhp_group* g) {
+  const int n = (int)g->m.size();
+  hipStream_t s0 = g->m[0]->stream;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+  int r = QHP_OK;
+  std::string why;
+  e = hipEventRecord(g->ev[0], s0);
+  for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(g->m[i]->stream, g->ev[0], 0);
+  for (int i = 0; i < n && e == hipSuccess && r == QHP_OK; ++i) {
+    r = one_step(g->m[i], false);
+    if (r) why = "member " + std::to_string(i) + ": " + g->m[i]->err;
+  }
+  for (int i = 1; i < n && e == hipSuccess && r == QHP_OK; ++i) {
+    e = hipEventRecord(g->ev[i], g->m[i]->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s0, g->ev[i], 0);
+  }
+  hipError_t e2 = hipStreamEndCapture(s0, &graph);
+  if (r || e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (r) return group_fail(g, r, why);
+    return group_fail(g, QHP_EDEVICE, std::string("group capture: ") +
+                                          hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g->exec = nullptr;
+    return group_fail(g, QHP_EDEVICE, std::string("group instantiate: ") + hipGetErrorString(e));
+  }
+  for (int i = 0; i < n; ++i) g->epoch[i] = g->m[i]->graph_epoch;
+  return QHP_OK;
+}
+
+extern "C" int qhp_group_step(qhp_group* g, int32_t nsteps) {
+  if (!g) return QHP_EINVAL;
+  if (nsteps < 0) return group_fail(g, QHP_EINVAL, "nsteps must be >= 0");
+  const int n = (int)g->m.size();
+  for (int i = 0; i < n; ++i) {
+    qhp_ctx* c = g->m[i];
+    if (!c->have_state) return group_fail(g, QHP_EINVAL, "member " + std::to_string(i) + " has no state");
+    if (!c->use_graph) return group_fail(g, QHP_EINVAL, "members need use_graph = 1");
+    if (c->prof_which != QHP_PROF_OFF) return group_fail(g, QHP_EINVAL, "members must not be profiling");
+    if (g->epoch[i] != c->graph_epoch && g->exec) {
+      (void)hipGraphExecDestroy(g->exec);
+      g->exec = nullptr;
+    }
+  }
+  if (nsteps == 0) return QHP_OK;
+  // the members' own queued work must be done before the origin stream runs the graph
+  for (int i = 1; i < n; ++i) {
+    hipError_t e = hipEventRecord(g->ev[i], g->m[i]->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(g->m[0]->stream, g->ev[i], 0);
+    if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, hipGetErrorString(e));
+  }
+  if (!g->exec) {
+    int r = group_capture(g);
+    if (r) return r;
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    hipError_t e = hipGraphLaunch(g->exec, g->m[0]->stream);
+    if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, std::string("group launch: ") + hipGetErrorString(e));
+    for (int i = 0; i < n; ++i) g->m[i]->step += g->m[i]->nalt;
+  }
+  // later work queued on a member's own stream follows the group's steps
+  hipError_t e = hipEventRecord(g->ev[0], g->m[0]->stream);
+  for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(g->m[i]->stream, g->ev[0], 0);
+  if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, hipGetErrorString(e));
+  for (int i = 0; i < n; ++i) {
+    int r = check_ctrl(g->m[i]);
+    if (r) return group_fail(g, r, "member " + std::to_string(i) + ": " + g->m[i]->err);
+  }
+  return QHP_OK;
+}

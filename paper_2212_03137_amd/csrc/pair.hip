@@ -49,6 +49,7 @@ struct PairArgs {
   double lj_s6[QHP_MAX_TYPES * QHP_MAX_TYPES];
   double lj_e4[QHP_MAX_TYPES * QHP_MAX_TYPES];
   int ntypes;
+  double lj_a[QHP_MAX_TYPES * QHP_MAX_TYPES];     // soft-core alpha (1 - lambda_vdw), 0 = plain
   double lj_sig[QHP_MAX_TYPES * QHP_MAX_TYPES];   // sigma_ij (parameter gradients)
   double eps_of[QHP_MAX_TYPES];                    // epsilon of each type
   double* dq; double* deps; double* dsig;          // parameter-gradient outputs (FP64 path)
@@ -100,12 +101,18 @@ QHP_DEV void flush(const PairArgs& A, int i, int lane, double gx, double gy, dou
 // HVP: instead of the gradient, add M (u_i - u_j) per in-range pair to hu_i, with
 // M = phi'' r^ r^T + (phi'/r)(I - r^ r^T) the pair's Hessian block (phi the screened
 // Coulomb plus LJ pair potential of r).
-template <int P, bool ENERGY, bool PG = false, bool HVP = false>
+// SOFT: pairs with lj_a != 0 take the soft-core LJ form. With s6 = (sigma/r)^6 and
+// d = 1 + a s6, the soft-core term e4 [1/D^2 - 1/D] (D = a + (r/sigma)^6, e4 = 4 eps
+// lambda) is e4 (u^2 - u) with u = s6 / d, and -(dE/dr)/r = 6 e4 u (2u - 1) / (d r^2);
+// a = 0 gives plain LJ.
+template <int P, bool ENERGY, bool PG = false, bool HVP = false, bool SOFT = false>
 __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
+  static_assert(!SOFT || (!PG && !HVP), "soft-core pairs have forces and energies only");
   constexpr int S = 64 / P;
   __shared__ int sj[WPB][64];
   __shared__ double sq[WPB][64];
   __shared__ double2 slj[WPB][64];
+  __shared__ double ssa[SOFT ? WPB : 1][SOFT ? 64 : 1];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, s = lane / P, b = lane % P;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int i = lb * WPB + wv;
@@ -137,6 +144,7 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
       sq[wv][lane] = qi * A.charge[j];
       const int tp = ti * A.ntypes + A.type[j];
       slj[wv][lane] = make_double2(A.lj_e4[tp], A.lj_s6[tp]);
+      if (SOFT) ssa[wv][lane] = A.lj_a[tp];
       if (PG || HVP) ssig[wv][lane] = A.lj_sig[tp];
     }
     wave_sync();
@@ -158,7 +166,12 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
         if (PG) pq += A.coulomb * A.charge[j] * erfcv * ir;
         const double2 lj = slj[wv][t];
         const double e4 = lj.x;
-        if (e4 != 0.0) {
+        if (SOFT && e4 != 0.0) {
+          const double s6 = lj.y * ir2 * ir2 * ir2;
+          const double rd = 1.0 / (1.0 + ssa[wv][t] * s6), u = s6 * rd;
+          sc += 6.0 * e4 * u * (2.0 * u - 1.0) * rd * ir2;
+          if (ENERGY) elj += e4 * (u * u - u);
+        } else if (e4 != 0.0) {
           const double s6 = lj.y * ir2 * ir2 * ir2;
           sc += e4 * (12.0 * s6 * s6 - 6.0 * s6) * ir2;
           if (ENERGY) elj += e4 * (s6 * s6 - s6);
@@ -225,15 +238,16 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
 
 // Compacted neighbours t0 + s, t0 + s + S, ... < cnt for the lane (slot s, bead b).
 // LJ = false for neighbours without an LJ term (a wavefront-uniform choice).
-template <int P, bool ENERGY, bool LJ>
-QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, const unsigned* sj,
-                   int t0, int cnt, int s, unsigned boff, float4 oi, float rc2, float alpha,
-                   float kexp, float c2a, float& fx, float& fy, float& fz, double& ec,
-                   double& elj) {
+// SOFT: the LJ neighbours' soft-core alpha (1 - lambda) is in sa (the k_pair64 form).
+template <int P, bool ENERGY, bool LJ, bool SOFT = false>
+QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, const float* sa,
+                   const unsigned* sj, int t0, int cnt, int s, unsigned boff, float4 oi,
+                   float rc2, float alpha, float kexp, float c2a, float& fx, float& fy,
+                   float& fz, double& ec, double& elj) {
   constexpr int S = 64 / P;
   const char* xf = reinterpret_cast<const char*>(A.xf);
   auto load = [&](int t) { return *reinterpret_cast<const float4*>(xf + (sj[t] + boff)); };
-  auto interact = [&](const float4 cd, const float4 oj, const float2 lj) {
+  auto interact = [&](const float4 cd, const float4 oj, const float2 lj, const float a) {
     const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
     const float r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2) {
@@ -247,7 +261,12 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
       const float erfcv = tt * q * ex;
       float sc = cd.w * ir2 * (erfcv * ir + c2a * ex);
       if (ENERGY) ec += (double)(cd.w * erfcv * ir);
-      if (LJ) {
+      if (LJ && SOFT) {
+        const float s6 = lj.y * ir2 * ir2 * ir2;
+        const float rd = __builtin_amdgcn_rcpf(1.0f + a * s6), u = s6 * rd;
+        sc += 6.f * lj.x * u * (2.f * u - 1.f) * rd * ir2;
+        if (ENERGY) elj += (double)(lj.x * (u * u - u));
+      } else if (LJ) {
         const float s6 = lj.y * ir2 * ir2 * ir2;
         sc += lj.x * (12.f * s6 * s6 - 6.f * s6) * ir2;
         if (ENERGY) elj += (double)(lj.x * (s6 * s6 - s6));
@@ -259,19 +278,20 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
   int t = t0 + s;
   for (; t + 3 * S < cnt; t += 4 * S) {
     const float4 o0 = load(t), o1 = load(t + S), o2 = load(t + 2 * S), o3 = load(t + 3 * S);
-    interact(scd[t], o0, slj[t]);
-    interact(scd[t + S], o1, slj[t + S]);
-    interact(scd[t + 2 * S], o2, slj[t + 2 * S]);
-    interact(scd[t + 3 * S], o3, slj[t + 3 * S]);
+    interact(scd[t], o0, slj[t], SOFT ? sa[t] : 0.f);
+    interact(scd[t + S], o1, slj[t + S], SOFT ? sa[t + S] : 0.f);
+    interact(scd[t + 2 * S], o2, slj[t + 2 * S], SOFT ? sa[t + 2 * S] : 0.f);
+    interact(scd[t + 3 * S], o3, slj[t + 3 * S], SOFT ? sa[t + 3 * S] : 0.f);
   }
-  for (; t < cnt; t += S) interact(scd[t], load(t), slj[t]);
+  for (; t < cnt; t += S) interact(scd[t], load(t), slj[t], SOFT ? sa[t] : 0.f);
 }
 
-template <int P, bool ENERGY>
+template <int P, bool ENERGY, bool SOFT = false>
 __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
   constexpr int S = 64 / P;
   __shared__ float4 scd[WPB][64];   // centroid difference (x, y, z) and q_i q_j C
   __shared__ float2 slj[WPB][64];   // 4 eps_ij and sigma_ij^6 of the pair
+  __shared__ float ssa[SOFT ? WPB : 1][SOFT ? 64 : 1];   // soft-core alpha (1 - lambda)
   __shared__ unsigned sj[WPB][64];  // byte offset of atom j's bead-0 FP32 offset
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, s = lane / P, b = lane % P;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -297,6 +317,7 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
     bool keep = false, haslj = false;
     float4 cdv;
     float2 ljv;
+    float av = 0.f;
     unsigned jp = 0;
     if (k0 + lane < nn) {
       const unsigned e = (unsigned)row[k0 + lane];
@@ -310,6 +331,7 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
       cdv = make_float4(cx, cy, cz, (float)(qi * A.charge[j]));
       const int tp = ti * A.ntypes + A.type[j];
       ljv = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
+      if (SOFT) av = (float)A.lj_a[tp];
       haslj = ljv.x != 0.f;
       jp = (unsigned)j * (unsigned)(P * sizeof(float4));
     }
@@ -321,15 +343,16 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
       const int slot = haslj ? __popcll(bl & below) : nlj + __popcll(bn & below);
       scd[wv][slot] = cdv;
       slj[wv][slot] = ljv;
+      if (SOFT) ssa[wv][slot] = av;
       sj[wv][slot] = jp;
     }
     wave_sync();
     float fx = 0.f, fy = 0.f, fz = 0.f;
     if (nlj > 0)
-      chunk<P, ENERGY, true>(A, scd[wv], slj[wv], sj[wv], 0, nlj, s, boff, oi, rc2, alpha, kexp,
-                             c2a, fx, fy, fz, ec, elj);
-    chunk<P, ENERGY, false>(A, scd[wv], slj[wv], sj[wv], nlj, cnt, s, boff, oi, rc2, alpha, kexp,
-                            c2a, fx, fy, fz, ec, elj);
+      chunk<P, ENERGY, true, SOFT>(A, scd[wv], slj[wv], ssa[SOFT ? wv : 0], sj[wv], 0, nlj, s,
+                                   boff, oi, rc2, alpha, kexp, c2a, fx, fy, fz, ec, elj);
+    chunk<P, ENERGY, false>(A, scd[wv], slj[wv], nullptr, sj[wv], nlj, cnt, s, boff, oi, rc2,
+                            alpha, kexp, c2a, fx, fy, fz, ec, elj);
     gx += (double)fx; gy += (double)fy; gz += (double)fz;
     wave_sync();
   }
@@ -363,13 +386,21 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   for (int d = 0; d < 3; ++d) { A.L[d] = c->p.box[d]; A.invL[d] = 1.0 / c->p.box[d]; }
   A.rc2 = c->p.cutoff * c->p.cutoff; A.alpha = c->p.ewald_alpha; A.coulomb = c->p.coulomb;
   A.ntypes = c->p.n_types;
+  // solute-solvent pairs of an alchemical system: epsilon scaled by lambda_vdw and the
+  // soft-core alpha (1 - lambda_vdw) (the current couplings, read at launch)
+  bool soft = false;
   for (int a = 0; a < c->p.n_types; ++a)
     for (int b = 0; b < c->p.n_types; ++b) {
       const double s = 0.5 * (c->sigma[a] + c->sigma[b]);
       const double e = sqrt(c->eps[a] * c->eps[b]);
+      const bool mixed = c->alch && c->soft[a] != c->soft[b];
+      const double lam = mixed ? c->lam_v : 1.0;
+      const double sa = mixed ? c->p.sc_alpha * (1.0 - c->lam_v) : 0.0;
       A.lj_s6[a * A.ntypes + b] = s * s * s * s * s * s;
-      A.lj_e4[a * A.ntypes + b] = 4.0 * e;
+      A.lj_e4[a * A.ntypes + b] = 4.0 * e * lam;
+      A.lj_a[a * A.ntypes + b] = sa;
       A.lj_sig[a * A.ntypes + b] = s;
+      soft = soft || (sa != 0.0 && e * lam != 0.0);
     }
   for (int a = 0; a < c->p.n_types; ++a) A.eps_of[a] = c->eps[a];
   A.dq = c->pg_dq; A.deps = c->pg_lj; A.dsig = c->pg_lj + QHP_MAX_TYPES;
@@ -388,9 +419,16 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   if (hvp) { A.u = bs->hvp_u; A.hu = bs->g; A.mix = bs->pgrad; }
   hipEvent_t ev = nullptr;
   prof_begin(c, QHP_PROF_PAIR, &ev);
-  if (f32) {
+  if (f32 && soft) {
+    QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair32<PP, true, true>), nb, NT, 0, c->stream, A);
+                 else hipLaunchKernelGGL((k_pair32<PP, false, true>), nb, NT, 0, c->stream, A));
+  } else if (f32) {
     QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair32<PP, true>), nb, NT, 0, c->stream, A);
                  else hipLaunchKernelGGL((k_pair32<PP, false>), nb, NT, 0, c->stream, A));
+  } else if (soft) {
+    if (pg || hvp) return hipErrorInvalidValue;     // rejected by the entry points
+    QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair64<PP, true, false, false, true>), nb, NT, 0, c->stream, A);
+                 else hipLaunchKernelGGL((k_pair64<PP, false, false, false, true>), nb, NT, 0, c->stream, A));
   } else {
     QHP_SWITCH_P(P, if (hvp) hipLaunchKernelGGL((k_pair64<PP, false, false, true>), nb, NT, 0, c->stream, A);
                  else if (pg) hipLaunchKernelGGL((k_pair64<PP, false, true>), nb, NT, 0, c->stream, A);

@@ -85,9 +85,18 @@ struct qhp_ctx {
   bool have_state = false;
   int64_t step = 0;
 
-  // host copies of per-atom data
+  // host copies of per-atom data (charge: as used, i.e. solute charges times lambda_elec)
   std::vector<int32_t> type;
   std::vector<double> mass, charge, sigma, eps;
+
+  // alchemical coupling (type_soft given): solute types, couplings, unscaled charges
+  bool alch = false;
+  std::vector<int32_t> soft;
+  std::vector<double> q_given;
+  double lam_e = 1.0, lam_v = 1.0;
+  double* d_charge_alt = nullptr;   // charges at other couplings (qhp_eval_lambda)
+  std::vector<double> charge_alt;
+  int64_t graph_epoch = 0;          // bumped whenever captured kernel arguments go stale
 
   // normal modes
   double* T = nullptr;        // [P][P] T[bead][mode]
