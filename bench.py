@@ -152,6 +152,61 @@ def force_loss_timing(q, qa, n_configs=8):
                                        "parameter gradients (param_grad)"}
 
 
+def windows_timing(q, steps=20, warmup=3):
+    """The batched free-energy workload: 16 alchemical windows lambda = i/15 of the 12-atom
+    solute in 256-2,048 waters with P = 8/16/32 (780-6,156 atoms each), FP32 pairs, each
+    window's SPME spreading tile picked by qhp_autotune, stepped as one group (one captured
+    graph per step of all windows, one branch per window). Also: the same windows stepped
+    one after another (each its own graph per step), and the cost of one sample of the BAR
+    inputs (every window's bead energies at its two neighbours' couplings)."""
+    import torch
+    import synth
+    systems = [synth.alchemical_window(i) for i in range(16)]
+    ctxs = [q.Context.from_system(s, precision=q.FP32_PAIRS) for s in systems]
+    try:
+        for c, s in zip(ctxs, systems):
+            c.set_state(s.pos, s.vel, 0)
+        tiles = [c.autotune(5) for c in ctxs]
+        bead_atoms = sum(s.n_atoms * s.n_beads for s in systems)
+        with q.Group(ctxs) as g:
+            g.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(steps)
+            torch.cuda.synchronize()
+            t_group = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in ctxs:
+            c.step(steps)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        lam = [i / 15 for i in range(16)]
+        pos = [c.get_state()[0] for c in ctxs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, c in enumerate(ctxs):
+            for j in (i - 1, i + 1):
+                if 0 <= j < 16:
+                    c.eval_lambda(pos[i], max(0.0, 2 * lam[j] - 1), min(1.0, 2 * lam[j]),
+                                  forces=False)
+        t_bar = time.perf_counter() - t0
+    finally:
+        for c in ctxs:
+            c.close()
+    return {"windows": 16, "atoms": [s.n_atoms for s in systems],
+            "beads": [s.n_beads for s in systems], "bead_atoms_total": bead_atoms,
+            "spread_beads_autotuned": tiles,
+            "group_ms_per_step": t_group / steps * 1e3,
+            "group_bead_atom_steps_per_s": bead_atoms * steps / t_group,
+            "sequential_ms_per_step": t_seq / steps * 1e3,
+            "group_speedup_vs_sequential": t_seq / t_group,
+            "bar_sample_ms": t_bar * 1e3, "steps": steps,
+            "note": "FP32 pairs (the 256-water boxes, 19.7 A, take the FP64 pair kernel: "
+                    "2 (rc + skin) exceeds their edge); BAR sample = 30 evaluations at the "
+                    "neighbouring couplings from host positions"}
+
+
 def cpu_baseline(s, budget_s=20.0):
     """The oracle as it stands, on a bounded sample: the centroid pair list and the full
     per-bead potential of as many beads as fit in about `budget_s` seconds."""
@@ -352,6 +407,10 @@ def main():
             comp["derivatives"]["force_loss"] = force_loss_timing(q, qa)
         except Exception as e:
             comp["derivatives"] = {"error": str(e)}
+        try:
+            comp["alchemical_windows"] = windows_timing(q)
+        except Exception as e:
+            comp["alchemical_windows"] = {"error": str(e)}
         out["compare"] = comp
         out["speedup_vs_plain_fp64"] = ns_day / comp["plain_fp64"]["ns_per_day"]
 

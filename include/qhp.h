@@ -288,6 +288,14 @@ QHP_API int qhp_group_step(qhp_group* group, int32_t nsteps);
 QHP_API int qhp_group_destroy(qhp_group* group);
 QHP_API const char* qhp_group_last_error(qhp_group* group);
 
+/* Launch-shape autotuner: times the context's reciprocal-space pass on its current beads
+ * (`reps` launches per candidate, HIP events on the context's stream; the propagated state
+ * is not changed) for each SPME spreading tile of 1, 2, 4, 8 or 16 beads per block (up to
+ * the beads the pass covers), keeps the fastest for the context's later launches and
+ * returns it in `spread_beads` (nullable). Needs a state (qhp_set_state). Results do not
+ * depend on the choice beyond the order of floating-point additions. */
+QHP_API int qhp_autotune(qhp_ctx* ctx, int32_t reps, int32_t* spread_beads);
+
 /* adQTB: gamma_z(omega_k), k = 0..N_seg, for every type: [n_types][N_seg + 1] (host). */
 QHP_API int qhp_qtb_get_gamma(qhp_ctx* ctx, double* gamma);
 QHP_API int qhp_qtb_set_gamma(qhp_ctx* ctx, const double* gamma);

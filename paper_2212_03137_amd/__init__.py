@@ -30,7 +30,7 @@ EXPORTS = ("qhp_create", "qhp_destroy", "qhp_eval", "qhp_set_state", "qhp_get_st
            "qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta",
            "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error", "qhp_param_grad",
            "qhp_hvp", "qhp_set_lambda", "qhp_eval_lambda", "qhp_bar", "qhp_group_create",
-           "qhp_group_step", "qhp_group_destroy", "qhp_group_last_error")
+           "qhp_group_step", "qhp_group_destroy", "qhp_group_last_error", "qhp_autotune")
 
 
 class QhpError(RuntimeError):
@@ -95,6 +95,7 @@ def load():
     lib.qhp_set_lambda.argtypes = [vp, C.c_double, C.c_double]
     lib.qhp_eval_lambda.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, I]
     lib.qhp_bar.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_double, D, C.POINTER(C.c_int32)]
+    lib.qhp_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
     lib.qhp_group_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
     lib.qhp_group_step.argtypes = [vp, C.c_int32]
     lib.qhp_group_destroy.argtypes = [vp]
@@ -241,6 +242,12 @@ class Context:
         self._check(self._lib.qhp_eval_lambda(self._h, _ptr(pos), float(lambda_elec),
                                               float(lambda_vdw), _ptr(E), _ptr(F), MEM_HOST))
         return E, F
+
+    def autotune(self, reps=5):
+        """Pick the fastest SPME spreading tile for this context (qhp_autotune) -> beads."""
+        out = C.c_int32()
+        self._check(self._lib.qhp_autotune(self._h, int(reps), C.byref(out)))
+        return out.value
 
     def param_grad(self, pos):
         """d(sum of bead energies) / d(charges [N], lj_epsilon [T], lj_sigma [T])."""

@@ -693,6 +693,48 @@ extern "C" int qhp_bar(const double* du_a, int64_t n_a, const double* du_b, int6
   return QHP_ENONFINITE;
 }
 
+extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads) {
+  if (!c) return QHP_EINVAL;
+  if (reps < 1) return qhp_fail(c, QHP_EINVAL, "reps must be >= 1");
+  if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
+  if (c->p.exec == QHP_PLAIN) {          // one bead per launch: nothing to choose
+    if (spread_beads) *spread_beads = 1;
+    return QHP_OK;
+  }
+  // the reciprocal-space pass of the propagated beads (the contracted ones under RESPA),
+  // its gradient sent to scratch so that the state is untouched
+  BeadSet B = c->respa ? BeadSet{c->Ps, c->Ps == 1 ? 1 : c->Ps / 2, c->xs, c->g_eval, c->xfs,
+                                 c->energy, QHP_TERMS_EXCL}
+                       : full_beads(c);
+  B.g = c->g_eval;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  QHP_HIP(c, hipEventCreate(&t0));
+  QHP_HIP(c, hipEventCreate(&t1));
+  int best = 0;
+  float best_ms = 0.f;
+  hipError_t e = hipSuccess;
+  for (int gb = 1; gb <= 16 && gb <= B.P && e == hipSuccess; gb *= 2) {
+    c->spread_gb = gb;
+    e = launch_spme(c, false, -1, &B);                     // warm
+    if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_spme(c, false, -1, &B);
+    if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e == hipSuccess && (best == 0 || ms < best_ms)) { best = gb; best_ms = ms; }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  c->spread_gb = best;
+  QHP_HIP(c, e);
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  c->step_exec = nullptr;
+  ++c->graph_epoch;
+  if (spread_beads) *spread_beads = best;
+  return QHP_OK;
+}
+
 extern "C" int qhp_param_grad(qhp_ctx* c, const double* pos, double* dq, double* deps,
                               double* dsig, int mem_kind) {
   if (!c || !pos || !dq || !deps || !dsig) return qhp_fail(c, QHP_EINVAL, "null argument");

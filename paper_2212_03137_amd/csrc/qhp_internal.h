@@ -97,6 +97,7 @@ struct qhp_ctx {
   double* d_charge_alt = nullptr;   // charges at other couplings (qhp_eval_lambda)
   std::vector<double> charge_alt;
   int64_t graph_epoch = 0;          // bumped whenever captured kernel arguments go stale
+  int spread_gb = 0;                // SPME spreading: beads per block (0 = min(P, 8))
 
   // normal modes
   double* T = nullptr;        // [P][P] T[bead][mode]

@@ -748,7 +748,7 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
     S.ctrl = c->ctrl;
     for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
     S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms; S.tile_nbr = c->tile_nbr;
-    const int gbeads = P < 8 ? P : 8;
+    const int gbeads = c->spread_gb > 0 ? (c->spread_gb < P ? c->spread_gb : P) : (P < 8 ? P : 8);
     const dim3 grid(c->ntiles, P / gbeads);
 #define SPREAD_CALL(GBV)                                                                     \
     QHP_SWITCH_ORDER(c->p.pme_order,                                                         \
