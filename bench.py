@@ -291,6 +291,7 @@ def main():
     # --- which kernel class dominates the batched FP32-pair step (short untimed pass) ---
     main_ctx = make(q.FP32_PAIRS, q.BATCHED)
     main_ctx.step(args.warmup)
+    spread_beads = main_ctx.autotune(5)
     classes = ["pair", "spread", "fft", "gather", "nm"]
     per_class = {}
     for cl in classes:
@@ -348,7 +349,8 @@ def main():
         "config": {"workload": "water4096_P32: 4,096 flexible 3-site waters, 49.7 A cube, "
                                "rc 9 A, SPME 64^3 order 5, P=32, 300 K, dt 0.5 fs, "
                                "bead-batched FP32-pair path",
-                   "n_atoms": s.n_atoms, "n_beads": s.n_beads, "parallelism": "single GPU"},
+                   "n_atoms": s.n_atoms, "n_beads": s.n_beads, "parallelism": "single GPU",
+                   "spread_beads_autotuned": spread_beads},
         "roofline": roof,
         "breakdown_ms_per_step": per_class,
     }

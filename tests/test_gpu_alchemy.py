@@ -208,3 +208,46 @@ def test_autotune_keeps_results_and_the_state(medium):
     assert np.array_equal(x0, x1) and np.array_equal(v0, v1)
     assert rel_max(F1, F0) <= 1e-13
     assert np.allclose(E1, E0, rtol=1e-13, atol=1e-10)
+
+
+def test_bar_inputs_and_estimate_match_the_oracle(small):
+    # two neighbouring windows of the small box: configurations sampled by the HIP path,
+    # the energy differences U_B - U_A (bead-averaged for PI-BAR, bead 0 for the single-bead
+    # estimator) from qhp_eval_lambda against the oracle's on the same configurations, and
+    # the library's BAR against the oracle's on them
+    import paper_2212_03137_amd as q
+    from oracle import bar as obar
+    lam_a, lam_b = (0.0, 0.6), (0.0, 0.8)
+    samples = {}
+    for lam in (lam_a, lam_b):
+        s = dataclasses.replace(small, lambda_elec=lam[0], lambda_vdw=lam[1])
+        xs = []
+        with ctx_for(s) as c:
+            c.set_state(s.pos, s.vel, 0)
+            for _ in range(4):
+                c.step(5)
+                xs.append(c.get_state()[0])
+            E = {k: [c.eval_lambda(x, *l, forces=False)[0].sum(axis=1) for x in xs]
+                 for k, l in (("a", lam_a), ("b", lam_b))}
+        samples[lam] = (xs, E)
+    beta = 1.0 / small.kT
+    for est in ("pi", "single"):
+        du = []
+        du_ref = []
+        for lam in (lam_a, lam_b):
+            xs, E = samples[lam]
+            Ea, Eb = np.array(E["a"]), np.array(E["b"])       # [samples][P]
+            sa = dataclasses.replace(small, lambda_elec=lam_a[0], lambda_vdw=lam_a[1])
+            sb = dataclasses.replace(small, lambda_elec=lam_b[0], lambda_vdw=lam_b[1])
+            Era = np.array([forces.evaluate(x, sa)[0].sum(axis=1) for x in xs])
+            Erb = np.array([forces.evaluate(x, sb)[0].sum(axis=1) for x in xs])
+            pick = (lambda E: E.mean(axis=1)) if est == "pi" else (lambda E: E[:, 0])
+            du.append(pick(Eb) - pick(Ea))
+            du_ref.append(pick(Erb) - pick(Era))
+        scale = max(1.0, float(np.abs(du_ref[0]).max()))
+        assert np.abs(du[0] - du_ref[0]).max() <= 1e-9 * scale
+        assert np.abs(du[1] - du_ref[1]).max() <= 1e-9 * scale
+        dF, _ = q.bar(du[0], du[1], beta)
+        dF_ref, _ = obar.bar(du_ref[0], du_ref[1], beta)
+        say("BAR", est, dF, dF_ref)
+        assert dF == pytest.approx(dF_ref, abs=1e-8 * max(1.0, abs(dF_ref)))
