@@ -243,17 +243,9 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
   if (spill)
     for (int i = i0 + PREP_REG; i < i1; ++i) B.tile_atoms[atomicAdd(&tfill[B.tile_of[i]], 1)] = i;
   // ---- 3. centroid cells of a rebuild ----
+  // (the cell of each centroid was written with it; the build kernel records the frame)
   if (!go) return;
-  // the cell of each centroid was written with it; record the build frame
-  auto cell_bin = [&](int i, int id) {
-    const double4 c = A.cent[i];
-    A.cref[i] = c;
-    const double4 w = make_double4(wrapped(c.x, A.L0, A.iL0), wrapped(c.y, A.L1, A.iL1),
-                                   wrapped(c.z, A.L2, A.iL2), c.w);   // w: bead spread
-    A.cwrap[i] = w;
-    A.coff[i] = make_double4(c.x - w.x, c.y - w.y, c.z - w.z, 0.0);
-    atomicAdd(&ccount[id], 1);
-  };
+  auto cell_bin = [&](int i, int id) { atomicAdd(&ccount[id], 1); };
 #pragma unroll
   for (int k = 0; k < PREP_REG; ++k)
     if (i0 + k < i1) reg[k] = A.cell_of[i0 + k];
@@ -270,7 +262,11 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
     for (int i = i0 + PREP_REG; i < i1; ++i) A.cell_atoms[atomicAdd(&cfill[A.cell_of[i]], 1)] = i;
 }
 
-__global__ __launch_bounds__(256) void k_nl_build(NlArgs A) {
+// One block per cell, NL_THREADS / 64 wavefronts sharing the cell's atoms. Also records
+// the build frame of the cell's atoms: reference centroid, centroid wrapped into the box
+// (w: bead spread) and the offset between the two.
+constexpr int NL_THREADS = 1024;
+__global__ __launch_bounds__(NL_THREADS) void k_nl_build(NlArgs A) {
   if (!A.ctrl->do_build) return;
   __shared__ double sx[MAXM], sy[MAXM], sz[MAXM];
   __shared__ int sj[MAXM];
@@ -286,9 +282,18 @@ __global__ __launch_bounds__(256) void k_nl_build(NlArgs A) {
     sofs[tid + 1] = c >= 0 ? A.cell_start[c + 1] - A.cell_start[c] : 0;
   }
   __syncthreads();
-  if (tid == 0) {
-    sofs[0] = 0;
-    for (int k = 1; k <= A.nst; ++k) sofs[k] += sofs[k - 1];
+  if (tid < 64) {              // inclusive prefix sum of sofs[1..nst], two entries per lane
+    const int k0 = 1 + 2 * tid, k1 = k0 + 1;
+    const int a0 = k0 <= A.nst ? sofs[k0] : 0, a1 = k1 <= A.nst ? sofs[k1] : 0;
+    int t = a0 + a1;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(t, o);
+      if (lane >= o) t += u;
+    }
+    const int ex = t - a0 - a1;
+    if (k0 <= A.nst) sofs[k0] = ex + a0;
+    if (k1 <= A.nst) sofs[k1] = ex + a0 + a1;
+    if (tid == 0) sofs[0] = 0;
   }
   const int c0 = A.cell_start[cell], nin = A.cell_start[cell + 1] - c0;
   if (nin > MAXC) {                       // cannot happen at liquid densities
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(256) void k_nl_build(NlArgs A) {
       sx[p] = cj.x; sy[p] = cj.y; sz[p] = cj.z; sj[p] = j;
     }
     __syncthreads();
-    for (int ii = wv; ii < nin; ii += 4) {
+    for (int ii = wv; ii < nin; ii += NL_THREADS / 64) {
       const int i = A.cell_atoms[c0 + ii];
       const double4 ci = A.cent[i];
       const double wx = wrapped(ci.x, A.L0, A.iL0), wy = wrapped(ci.y, A.L1, A.iL1),
@@ -353,13 +358,22 @@ __global__ __launch_bounds__(256) void k_nl_build(NlArgs A) {
     }
     __syncthreads();
   }
+  int most = 0;                 // the block's largest count: one global atomic per block
   for (int ii = tid; ii < nin; ii += blockDim.x) {
     const int i = A.cell_atoms[c0 + ii];
     const int cnt = scnt[ii];
     A.nnbr[i] = cnt < A.cap ? cnt : A.cap;
     if (cnt > A.cap) A.ctrl->overflow = 1;
-    atomicMax(&A.ctrl->max_count, cnt);
+    most = max(most, cnt);
+    const double4 c = A.cent[i];
+    A.cref[i] = c;
+    const double4 w = make_double4(wrapped(c.x, A.L0, A.iL0), wrapped(c.y, A.L1, A.iL1),
+                                   wrapped(c.z, A.L2, A.iL2), c.w);
+    A.cwrap[i] = w;
+    A.coff[i] = make_double4(c.x - w.x, c.y - w.y, c.z - w.z, 0.0);
   }
+  for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+  if (lane == 0 && most > 0) atomicMax(&A.ctrl->max_count, most);
 }
 #pragma clang fp contract(fast)
 
@@ -405,13 +419,13 @@ hipError_t launch_nlist(qhp_ctx* c, bool from_step) {
     B.KoL0 = c->K[0] / c->p.box[0]; B.KoL1 = c->K[1] / c->p.box[1]; B.KoL2 = c->K[2] / c->p.box[2];
     B.tile_of = c->tile_of; B.tile_start = c->tile_start; B.tile_atoms = c->tile_atoms;
     hipLaunchKernelGGL(k_prep, 1, 1024, prep_lds_bytes(c), c->stream, B, from_step ? 0 : 1);
-    hipLaunchKernelGGL(k_nl_build, c->ncell, 256, 0, c->stream, A);
+    hipLaunchKernelGGL(k_nl_build, c->ncell, NL_THREADS, 0, c->stream, A);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_nl_check, 1, 256, 0, c->stream, A, from_step ? 0 : 1);
   hipLaunchKernelGGL(k_nl_assign, (c->N + 255) / 256, 256, 0, c->stream, A);
   hipLaunchKernelGGL(k_nl_scan, 1, 256, 0, c->stream, A);
   hipLaunchKernelGGL(k_nl_scatter, (c->N + 255) / 256, 256, 0, c->stream, A);
-  hipLaunchKernelGGL(k_nl_build, c->ncell, 256, 0, c->stream, A);
+  hipLaunchKernelGGL(k_nl_build, c->ncell, NL_THREADS, 0, c->stream, A);
   return hipGetLastError();
 }

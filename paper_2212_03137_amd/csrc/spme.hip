@@ -655,6 +655,248 @@ __global__ __launch_bounds__(NT) void k_fft_pass(FftArgs A) {
   }
 }
 
+// ------------------------- fused y-z convolution of one x plane ------------------------
+// After the forward x pass, everything the reciprocal sum does along y and z for a fixed
+// x frequency k0 is local to that plane: forward transforms along z and y, the product
+// with G(k0, k1, k2), inverse transforms along y and z. One block holds the K x K plane of
+// NB complex slots in LDS and does all of it, so the grid crosses HBM twice for the four
+// transforms instead of six times.
+
+// 8-point DFT in registers, natural order in and out (forward: exp(-2 pi i / 8)).
+template <bool INV>
+QHP_DEV void dft8(double2* v) {
+  dft4<INV>(v[0], v[2], v[4], v[6]);
+  dft4<INV>(v[1], v[3], v[5], v[7]);
+  const double h = 0.70710678118654752440;
+  const double sg = INV ? 1.0 : -1.0;
+  const double2 o0 = v[1];
+  const double2 o1 = cmul(v[3], make_double2(h, sg * h));
+  const double2 o2 = cmul(v[5], make_double2(0.0, sg));
+  const double2 o3 = cmul(v[7], make_double2(-h, sg * h));
+  const double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+// K-point transforms (K = 8 B, B = 4 or 8) of NSER series held in LDS, series q's element
+// e at buf[off(q) + e * es]. Cooley-Tukey with x[B n1 + n2]: DFT_8 over n1 for every n2,
+// twiddle W_K^(n2 k1), written back in place (element B k1 + n2); then DFT_B over n2 for
+// every k1, giving X[k1 + 8 k2]. NT_ threads; the second step's tasks stay in registers
+// across the barrier that separates its reads from its writes.
+template <int K, int NSER, int NT_, bool INV, class Off>
+QHP_DEV void lds_fft(double2* buf, const double2* tw, Off off, int es) {
+  constexpr int B = K / 8;
+  static_assert(B == 4 || B == 8, "K must be 32 or 64");
+  constexpr int TA = NSER * B, TB = NSER * 8;
+  constexpr int IA = (TA + NT_ - 1) / NT_, IB = (TB + NT_ - 1) / NT_;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int t = tid + i * NT_, n2 = t % B, q = t / B;
+    if (TA % NT_ != 0 && t >= TA) break;
+    double2* p = buf + off(q) + n2 * es;
+    double2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = p[r * B * es];
+    dft8<INV>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) {
+      double2 w = tw[n2 * k1];
+      if (INV) w.y = -w.y;
+      v[k1] = cmul(v[k1], w);
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) p[r * B * es] = v[r];
+  }
+  __syncthreads();
+  double2 v[IB][B];
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    const int t = tid + i * NT_, k1 = t % 8, q = t / 8;
+    if (TB % NT_ != 0 && t >= TB) break;
+    const double2* p = buf + off(q) + (B * k1) * es;
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) v[i][n2] = p[n2 * es];
+    if constexpr (B == 8) {
+      dft8<INV>(v[i]);
+    } else {
+      dft4<INV>(v[i][0], v[i][1], v[i][2], v[i][3]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    const int t = tid + i * NT_, k1 = t % 8, q = t / 8;
+    if (TB % NT_ != 0 && t >= TB) break;
+    double2* p = buf + off(q) + k1 * es;
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) p[(8 * k2) * es] = v[i][k2];
+  }
+  __syncthreads();
+}
+
+struct FftYZArgs {
+  double2* grid;           // [K0][K][K][pc]
+  const double2* tw;       // [K] exp(-2 pi i m / K) (y and z share it: K1 = K2)
+  const double* G;         // [K0][K][K]
+  int pc;                  // complex slots per grid point
+};
+
+constexpr int YZ_NT = 1024;
+
+template <int K, int NB>
+__global__ __launch_bounds__(YZ_NT) void k_fft_yz(FftYZArgs A) {
+  constexpr int ROW = K * NB + NB;        // one k1 row of LDS, padded against bank conflicts
+  __shared__ double2 buf[K * ROW];
+  __shared__ double2 stw[K];
+  const int tid = threadIdx.x;
+  const int groups = A.pc / NB;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);   // the slot groups of a plane: one XCD
+  const int k0 = lb / groups, s0 = (lb % groups) * NB;
+  for (int m = tid; m < K; m += YZ_NT) stw[m] = A.tw[m];
+  const size_t plane = (size_t)k0 * K * K;
+  constexpr int PER = K * K * NB / YZ_NT;            // values per thread (a power of two)
+  static_assert(PER * YZ_NT == K * K * NB, "plane size");
+  {
+    double2 r[PER];                                  // all loads in flight, then to LDS
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int l = tid + i * YZ_NT, s = l % NB, pt = l / NB;
+      r[i] = A.grid[(plane + pt) * A.pc + s0 + s];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int l = tid + i * YZ_NT, s = l % NB, k2 = (l / NB) % K, k1 = l / (NB * K);
+      buf[k1 * ROW + k2 * NB + s] = r[i];
+    }
+  }
+  __syncthreads();
+  // series along z: q = (k1, s); along y: q = (k2, s)
+  auto offz = [](int q) { return (q / NB) * ROW + q % NB; };
+  auto offy = [](int q) { return (q / NB) * NB + q % NB; };
+  lds_fft<K, K * NB, YZ_NT, false>(buf, stw, offz, NB);
+  lds_fft<K, K * NB, YZ_NT, false>(buf, stw, offy, ROW);
+  for (int l = tid; l < K * K * NB; l += YZ_NT) {
+    const int s = l % NB, k2 = (l / NB) % K, k1 = l / (NB * K);
+    const double g = A.G[plane + (size_t)k1 * K + k2];
+    double2& v = buf[k1 * ROW + k2 * NB + s];
+    v.x *= g; v.y *= g;
+  }
+  __syncthreads();
+  lds_fft<K, K * NB, YZ_NT, true>(buf, stw, offy, ROW);
+  lds_fft<K, K * NB, YZ_NT, true>(buf, stw, offz, NB);
+  double2 r[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int l = tid + i * YZ_NT, s = l % NB, k2 = (l / NB) % K, k1 = l / (NB * K);
+    r[i] = buf[k1 * ROW + k2 * NB + s];
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int l = tid + i * YZ_NT, s = l % NB, pt = l / NB;
+    A.grid[(plane + pt) * A.pc + s0 + s] = r[i];
+  }
+}
+
+// K = 64, two slots: the same transforms with one (series, index) task per thread and
+// each 8 x 8 step kept in registers where the data layout allows: the forward z step
+// reads the grid directly, the forward y step's second half, the product with G and the
+// inverse y step's first half run on the same registers (the eight outputs X[k1 + 8 k2]
+// of one thread are exactly the eight inputs x[8 n1 + n2], n2 = k1, of the inverse
+// step), and the last inverse z step writes the grid directly.
+__global__ __launch_bounds__(YZ_NT) void k_fft_yz64(FftYZArgs A) {
+  constexpr int K = 64, NB = 2, ROW = K * NB + NB;
+  __shared__ double2 buf[K * ROW];
+  __shared__ double2 stw[K];
+  const int tid = threadIdx.x, j = tid & 7, q = tid >> 3, s = q & 1, r = q >> 1;
+  const int groups = A.pc / NB;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int k0 = lb / groups, s0 = (lb % groups) * NB;
+  if (tid < K) stw[tid] = A.tw[tid];
+  const size_t plane = (size_t)k0 * K * K;
+  // z series of this thread: row k1 = r, slot s; y series: column k2 = r, slot s
+  double2* zs = buf + r * ROW + s;          // element e at zs[e * NB]
+  double2* ys = buf + r * NB + s;           // element e at ys[e * ROW]
+  auto tw8 = [&](double2* v, int n2, bool inv) {
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      double2 w = stw[n2 * k];
+      if (inv) w.y = -w.y;
+      v[k] = cmul(v[k], w);
+    }
+  };
+  double2 v[8];
+  // 1. forward z, first half, from the grid: x[8 n1 + j]
+  {
+    const double2* g = A.grid + (plane + (size_t)r * K + j) * A.pc + s0 + s;
+#pragma unroll
+    for (int n1 = 0; n1 < 8; ++n1) v[n1] = g[(size_t)(8 * n1) * A.pc];
+  }
+  __syncthreads();                          // twiddles
+  dft8<false>(v);
+  tw8(v, j, false);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) zs[(8 * k + j) * NB] = v[k];
+  __syncthreads();
+  // 2. forward z, second half: elements 8 j + n2 -> X[j + 8 k2]
+#pragma unroll
+  for (int n2 = 0; n2 < 8; ++n2) v[n2] = zs[(8 * j + n2) * NB];
+  dft8<false>(v);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) zs[(j + 8 * k) * NB] = v[k];
+  __syncthreads();
+  // 3. forward y, first half, in place
+#pragma unroll
+  for (int n1 = 0; n1 < 8; ++n1) v[n1] = ys[(8 * n1 + j) * ROW];
+  dft8<false>(v);
+  tw8(v, j, false);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ys[(8 * k + j) * ROW] = v[k];
+  __syncthreads();
+  // 4. forward y second half, x G, inverse y first half (n2 = j)
+#pragma unroll
+  for (int n2 = 0; n2 < 8; ++n2) v[n2] = ys[(8 * j + n2) * ROW];
+  dft8<false>(v);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {             // v[k] = X[k1 = j + 8 k] at column k2 = r
+    const double gv = A.G[plane + (size_t)(j + 8 * k) * K + r];
+    v[k].x *= gv; v[k].y *= gv;
+  }
+  dft8<true>(v);
+  tw8(v, j, true);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ys[(8 * k + j) * ROW] = v[k];
+  __syncthreads();
+  // 5. inverse y, second half
+#pragma unroll
+  for (int n2 = 0; n2 < 8; ++n2) v[n2] = ys[(8 * j + n2) * ROW];
+  dft8<true>(v);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ys[(j + 8 * k) * ROW] = v[k];
+  __syncthreads();
+  // 6. inverse z, first half, in place
+#pragma unroll
+  for (int n1 = 0; n1 < 8; ++n1) v[n1] = zs[(8 * n1 + j) * NB];
+  dft8<true>(v);
+  tw8(v, j, true);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) zs[(8 * k + j) * NB] = v[k];
+  __syncthreads();
+  // 7. inverse z, second half, to the grid: X[j + 8 k2]
+#pragma unroll
+  for (int n2 = 0; n2 < 8; ++n2) v[n2] = zs[(8 * j + n2) * NB];
+  dft8<true>(v);
+  double2* g = A.grid + (plane + (size_t)r * K + j) * A.pc + s0 + s;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) g[(size_t)(8 * k) * A.pc] = v[k];
+}
+
 }  // namespace
 
 #define QHP_SWITCH_P(P, CALL)                          \
@@ -706,6 +948,43 @@ static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc, double2* grid
   else if (mode == 1) { QHP_SWITCH_K(K, hipLaunchKernelGGL((k_fft_pass<KK, 1>), nb, NT, 0, c->stream, A)); }
   else { QHP_SWITCH_K(K, hipLaunchKernelGGL((k_fft_pass<KK, 2>), nb, NT, 0, c->stream, A)); }
   return hipGetLastError();
+}
+
+// The reciprocal-space convolution of a spread grid: forward 3D transform, product with
+// G, inverse transform (unnormalised: G carries the factors). Square y-z planes of 32 or
+// 64 points take the fused plane kernel between the two x passes; other grids take five
+// one-axis passes (the z pass fusing G).
+static hipError_t convolve(qhp_ctx* c, int pc, double2* grid) {
+  const int K = c->K[1];
+  int nb = 0;                                      // slots per plane block
+  if (K == c->K[2] && (K == 64 || K == 32)) {
+    const int cap = K == 64 ? 2 : 8;               // 8,192 complex values in LDS
+    nb = pc < cap ? pc : cap;
+  }
+  hipError_t e;
+  if ((e = fft_pass(c, 0, 0, pc, grid)) != hipSuccess) return e;
+  if (nb) {
+    FftYZArgs A;
+    A.grid = grid; A.tw = c->tw[1]; A.G = c->influence; A.pc = pc;
+    const unsigned blocks = (unsigned)(c->K[0] * (pc / nb));
+#define YZ_CALL(KK, NBV) hipLaunchKernelGGL((k_fft_yz<KK, NBV>), blocks, YZ_NT, 0, c->stream, A)
+    if (K == 64) {
+      if (nb == 1) YZ_CALL(64, 1);
+      else hipLaunchKernelGGL(k_fft_yz64, blocks, YZ_NT, 0, c->stream, A);
+    } else {
+      if (nb == 1) YZ_CALL(32, 1);
+      else if (nb == 2) YZ_CALL(32, 2);
+      else if (nb == 4) YZ_CALL(32, 4);
+      else YZ_CALL(32, 8);
+    }
+#undef YZ_CALL
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    if ((e = fft_pass(c, 1, 0, pc, grid)) != hipSuccess) return e;
+    if ((e = fft_pass(c, 2, 2, pc, grid)) != hipSuccess) return e;
+    if ((e = fft_pass(c, 1, 1, pc, grid)) != hipSuccess) return e;
+  }
+  return fft_pass(c, 0, 1, pc, grid);
 }
 
 hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
@@ -766,11 +1045,7 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   prof_begin(c, QHP_PROF_FFT, &ev);
-  if ((e = fft_pass(c, 0, 0, pc, c->grid)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 1, 0, pc, c->grid)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 2, 2, pc, c->grid)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 1, 1, pc, c->grid)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 0, 1, pc, c->grid)) != hipSuccess) return e;
+  if ((e = convolve(c, pc, c->grid)) != hipSuccess) return e;
   prof_end(c, QHP_PROF_FFT, ev);
   prof_begin(c, QHP_PROF_GATHER, &ev);
   A.nblocks = (int)nb;
@@ -811,11 +1086,7 @@ hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu, bool mix) {
 #undef SPREAD_CALL
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = fft_pass(c, 0, 0, pc, c->grid2)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 1, 0, pc, c->grid2)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 2, 2, pc, c->grid2)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 1, 1, pc, c->grid2)) != hipSuccess) return e;
-  if ((e = fft_pass(c, 0, 1, pc, c->grid2)) != hipSuccess) return e;
+  if ((e = convolve(c, pc, c->grid2)) != hipSuccess) return e;
   SpmeArgs A;
   A.N = N; A.K0 = c->K[0]; A.K1 = c->K[1]; A.K2 = c->K[2]; A.Pc2 = 2 * pc;
   A.order = c->tile_atoms; A.x = c->x; A.g = nullptr; A.grid = (double*)c->grid;
