@@ -693,12 +693,14 @@ extern "C" int qhp_bar(const double* du_a, int64_t n_a, const double* du_b, int6
   return QHP_ENONFINITE;
 }
 
-extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads) {
+extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
+                            int32_t* spread_ztiles) {
   if (!c) return QHP_EINVAL;
   if (reps < 1) return qhp_fail(c, QHP_EINVAL, "reps must be >= 1");
   if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
-  if (c->p.exec == QHP_PLAIN) {          // one bead per launch: nothing to choose
+  if (c->p.exec == QHP_PLAIN) {          // one bead per launch: keep the default tile
     if (spread_beads) *spread_beads = 1;
+    if (spread_ztiles) *spread_ztiles = 1;
     return QHP_OK;
   }
   // the reciprocal-space pass of the propagated beads (the contracted ones under RESPA),
@@ -710,28 +712,33 @@ extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads) {
   hipEvent_t t0 = nullptr, t1 = nullptr;
   QHP_HIP(c, hipEventCreate(&t0));
   QHP_HIP(c, hipEventCreate(&t1));
-  int best = 0;
+  int best_gb = 0, best_z = 0;
   float best_ms = 0.f;
   hipError_t e = hipSuccess;
-  for (int gb = 1; gb <= 16 && gb <= B.P && e == hipSuccess; gb *= 2) {
-    c->spread_gb = gb;
-    e = launch_spme(c, false, -1, &B);                     // warm
-    if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_spme(c, false, -1, &B);
-    if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(t1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-    if (e == hipSuccess && (best == 0 || ms < best_ms)) { best = gb; best_ms = ms; }
-  }
+  const int nt2 = c->K[2] / QHP_TB;
+  for (int gb = 1; gb <= 16 && gb <= B.P && e == hipSuccess; gb *= 2)
+    for (int z = 1; z <= 8 && z <= nt2 && gb * z <= 16 && e == hipSuccess; z *= 2) {
+      c->spread_gb = gb;
+      c->spread_z = z;
+      e = launch_spme(c, false, -1, &B);                   // warm
+      if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_spme(c, false, -1, &B);
+      if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e == hipSuccess && (best_gb == 0 || ms < best_ms)) { best_gb = gb; best_z = z; best_ms = ms; }
+    }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  c->spread_gb = best;
+  c->spread_gb = best_gb;
+  c->spread_z = best_z;
   QHP_HIP(c, e);
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   c->step_exec = nullptr;
   ++c->graph_epoch;
-  if (spread_beads) *spread_beads = best;
+  if (spread_beads) *spread_beads = best_gb;
+  if (spread_ztiles) *spread_ztiles = best_z;
   return QHP_OK;
 }
 

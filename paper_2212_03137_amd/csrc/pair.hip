@@ -258,9 +258,9 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
 #pragma unroll
       for (int k = 6; k >= 0; --k) q = q * tt + ERFC_Q[k];
       const float ex = __builtin_amdgcn_exp2f(kexp * r2);       // exp(-alpha^2 r^2)
-      const float erfcv = tt * q * ex;
-      float sc = cd.w * ir2 * (erfcv * ir + c2a * ex);
-      if (ENERGY) ec += (double)(cd.w * erfcv * ir);
+      const float tq = tt * q;                                   // erfc(alpha r) / ex
+      float sc = cd.w * ir2 * ex * (tq * ir + c2a);
+      if (ENERGY) ec += (double)(cd.w * tq * ex * ir);
       if (LJ && SOFT) {
         const float s6 = lj.y * ir2 * ir2 * ir2;
         const float rd = __builtin_amdgcn_rcpf(1.0f + a * s6), u = s6 * rd;

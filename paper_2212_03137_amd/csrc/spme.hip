@@ -342,33 +342,64 @@ QHP_DEV int tile_lo(int base, int t0, int K) {
 
 // TAN: spread the derivative of the charge density along the direction u instead,
 // sum_a q_a grad W_a(k) . u_a (the tangent grid of a Hessian-vector product).
-template <int ORDER, int GB, bool TAN = false>
+// Z: the block's tile spans Z consecutive tiles along z (TB x TB x Z TB points; atoms
+// binned per TB^3 tile, so the neighbourhood is 3 x 3 columns of Z + 2 tiles). A taller
+// tile splits fewer stencil rows between blocks.
+template <int ORDER, int GB, bool TAN = false, int Z = 1>
 __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
   constexpr int CAP = 1024;                // compacted atoms per round
-  __shared__ double acc[TB * TB * TB * GB];
+  constexpr int TZ = TB * Z;
+  constexpr int NR = 18;                   // neighbour ranges: 9 columns x 2 z pieces
+  __shared__ double acc[TB * TB * TZ * GB];
   __shared__ int cand[CAP];
   __shared__ int ncand;
-  __shared__ int tofs[28], tbeg[27];
+  __shared__ int tofs[NR + 1], tbeg[NR];
   const int tile = blockIdx.x, grp = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
-  for (int k = tid; k < TB * TB * TB * GB; k += NT) acc[k] = 0.0;
-  const int T2 = tile % A.nt2, T1 = (tile / A.nt2) % A.nt1, T0 = tile / (A.nt2 * A.nt1);
+  for (int k = tid; k < TB * TB * TZ * GB; k += NT) acc[k] = 0.0;
+  const int nz = A.nt2 / Z;
+  const int T2 = (tile % nz) * Z, T1 = (tile / nz) % A.nt1, T0 = tile / (nz * A.nt1);
   const int K[3] = {A.K0, A.K1, A.K2};
   const int t0[3] = {T0 * TB, T1 * TB, T2 * TB};
+  const int ext[3] = {TB, TB, TZ};
   const int P = A.P;
   const int m = A.cent ? A.ctrl->spread_m : 0;
-  // the atoms of the (up to) 27 neighbouring tiles, concatenated
-  if (tid < 27) {
-    const int src = A.tile_nbr[tile * 27 + tid];
-    tbeg[tid] = src >= 0 ? A.tile_start[src] : 0;
-    tofs[tid + 1] = src >= 0 ? A.tile_start[src + 1] - A.tile_start[src] : 0;
+  // the atoms of the distinct neighbouring columns' tiles T2 - 1 .. T2 + Z (wrapped:
+  // at most two contiguous pieces per column), concatenated
+  if (tid < NR) {
+    const int col = tid >> 1, part = tid & 1, dx = col / 3 - 1, dy = col % 3 - 1;
+    const int nt0 = A.K0 / TB, nt1 = A.nt1, nt2 = A.nt2;
+    const bool okx = nt0 >= 3 || (nt0 == 2 && dx != 1) || (nt0 == 1 && dx == 0);
+    const bool oky = nt1 >= 3 || (nt1 == 2 && dy != 1) || (nt1 == 1 && dy == 0);
+    int zlo = 0, zhi = 0;
+    if (Z + 2 >= nt2) {
+      if (part == 0) zhi = nt2;
+    } else {
+      const int z0 = (T2 - 1 + nt2) % nt2, n = Z + 2;
+      if (z0 + n <= nt2) {
+        if (part == 0) { zlo = z0; zhi = z0 + n; }
+      } else if (part == 0) {
+        zlo = z0; zhi = nt2;
+      } else {
+        zhi = z0 + n - nt2;
+      }
+    }
+    int beg = 0, len = 0;
+    if (okx && oky && zhi > zlo) {
+      const int cx = (T0 + dx + nt0) % nt0, cy = (T1 + dy + nt1) % nt1;
+      const int base = (cx * nt1 + cy) * nt2;
+      beg = A.tile_start[base + zlo];
+      len = A.tile_start[base + zhi] - beg;
+    }
+    tbeg[tid] = beg;
+    tofs[tid + 1] = len;
   }
   __syncthreads();
   if (tid == 0) {
     tofs[0] = 0;
-    for (int k = 1; k <= 27; ++k) tofs[k] += tofs[k - 1];
+    for (int k = 1; k <= NR; ++k) tofs[k] += tofs[k - 1];
   }
   __syncthreads();
-  const int total = tofs[27];
+  const int total = tofs[NR];
   int pos = 0;
   for (;;) {
     // 1) collect atoms whose centroid stencil, widened by m points, reaches the tile
@@ -379,7 +410,7 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
       bool hit = false;
       int a = -1;
       if (p < total) {
-        int lo = 0, hi = 27;
+        int lo = 0, hi = NR;
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
           if (tofs[mid] <= p) lo = mid; else hi = mid;
@@ -393,7 +424,7 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
           for (int d = 0; d < 3; ++d) {
             const int bc = base_of(cc[d], A.KoL[d], K[d]);
             const int l0 = tile_lo<ORDER>(bc - m, t0[d], K[d]);
-            if (!(l0 < TB || l0 > K[d] - (ORDER + 2 * m) || K[d] <= TB)) hit = false;
+            if (!(l0 < ext[d] || l0 > K[d] - (ORDER + 2 * m) || K[d] <= ext[d])) hit = false;
           }
         }
       }
@@ -420,7 +451,7 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
         const int base = isfinite(fl) ? min(max((int)fl, 0), K[d]) : 0;
         fr[d] = u - fl;
         lo[d] = tile_lo<ORDER>(base, t0[d], K[d]);
-        if (!(lo[d] < TB || lo[d] > K[d] - ORDER || K[d] <= TB)) hit = false;
+        if (!(lo[d] < ext[d] || lo[d] > K[d] - ORDER || K[d] <= ext[d])) hit = false;
       }
       if (!hit) continue;
       double w[3][ORDER], dw[3][ORDER];
@@ -438,9 +469,9 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
           } else {
             // along z a point outside the tile adds zero to the row's first point, so the
             // innermost loop has no branch
-            oz[t] = r < TB ? r * GB : 0;
-            wz[t] = r < TB ? w[2][t] : 0.0;
-            mz[t] = r < TB ? 1.0 : 0.0;
+            oz[t] = r < TZ ? r * GB : 0;
+            wz[t] = r < TZ ? w[2][t] : 0.0;
+            mz[t] = r < TZ ? 1.0 : 0.0;
           }
         }
       }
@@ -465,7 +496,7 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
             if (rel[1][tb] < 0) continue;
             const double c1 = qa * (t[0][ta] * w[1][tb] + w[0][ta] * t[1][tb]);
             const double c2 = qa * w[0][ta] * w[1][tb];
-            double* row = acc + (rel[0][ta] * TB + rel[1][tb]) * TB * GB + bl;
+            double* row = acc + (rel[0][ta] * TB + rel[1][tb]) * TZ * GB + bl;
 #pragma unroll
             for (int tc = 0; tc < ORDER; ++tc) atomicAdd(row + oz[tc], c1 * wz[tc] + c2 * tz[tc]);
           }
@@ -480,7 +511,7 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
         for (int tb = 0; tb < ORDER; ++tb) {
           if (rel[1][tb] < 0) continue;
           const double wab = wa * w[1][tb];
-          double* row = acc + (rel[0][ta] * TB + rel[1][tb]) * TB * GB + bl;
+          double* row = acc + (rel[0][ta] * TB + rel[1][tb]) * TZ * GB + bl;
 #pragma unroll
           for (int tc = 0; tc < ORDER; ++tc) atomicAdd(row + oz[tc], wab * wz[tc]);
         }
@@ -489,9 +520,9 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
     __syncthreads();
     if (!more) break;
   }
-  for (int k = tid; k < TB * TB * TB * GB; k += NT) {
+  for (int k = tid; k < TB * TB * TZ * GB; k += NT) {
     const int bb = k % GB, pt = k / GB;
-    const int r2 = pt % TB, r1 = (pt / TB) % TB, r0 = pt / (TB * TB);
+    const int r2 = pt % TZ, r1 = (pt / TZ) % TB, r0 = pt / (TZ * TB);
     const size_t g = ((size_t)((t0[0] + r0) * A.K1 + (t0[1] + r1)) * A.K2 + (t0[2] + r2)) * A.Pc2;
     A.grid[g + grp * GB + bb] = acc[k];
     if (P == 1) A.grid[g + 1] = 0.0;
@@ -817,9 +848,14 @@ __global__ __launch_bounds__(YZ_NT) void k_fft_yz64(FftYZArgs A) {
   const int k0 = lb / groups, s0 = (lb % groups) * NB;
   if (tid < K) stw[tid] = A.tw[tid];
   const size_t plane = (size_t)k0 * K * K;
+  // Point (k1, k2) of slot s sits at LDS row sw(k1), column sw(k2), sw(e) permuting the
+  // low three bits of e by its high three (e ^ (e >> 3) within each group of eight):
+  // every access below reads or writes elements 8a + b with one of a, b running over the
+  // eight lanes of a series, and the permutation spreads those over distinct banks.
+  auto sw = [](int e) { return (e & 56) | ((e ^ (e >> 3)) & 7); };
   // z series of this thread: row k1 = r, slot s; y series: column k2 = r, slot s
-  double2* zs = buf + r * ROW + s;          // element e at zs[e * NB]
-  double2* ys = buf + r * NB + s;           // element e at ys[e * ROW]
+  double2* zs = buf + sw(r) * ROW + s;      // element e at zs[sw(e) * NB]
+  double2* ys = buf + sw(r) * NB + s;       // element e at ys[sw(e) * ROW]
   auto tw8 = [&](double2* v, int n2, bool inv) {
 #pragma unroll
     for (int k = 1; k < 8; ++k) {
@@ -839,27 +875,27 @@ __global__ __launch_bounds__(YZ_NT) void k_fft_yz64(FftYZArgs A) {
   dft8<false>(v);
   tw8(v, j, false);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) zs[(8 * k + j) * NB] = v[k];
+  for (int k = 0; k < 8; ++k) zs[sw(8 * k + j) * NB] = v[k];
   __syncthreads();
   // 2. forward z, second half: elements 8 j + n2 -> X[j + 8 k2]
 #pragma unroll
-  for (int n2 = 0; n2 < 8; ++n2) v[n2] = zs[(8 * j + n2) * NB];
+  for (int n2 = 0; n2 < 8; ++n2) v[n2] = zs[sw(8 * j + n2) * NB];
   dft8<false>(v);
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 8; ++k) zs[(j + 8 * k) * NB] = v[k];
+  for (int k = 0; k < 8; ++k) zs[sw(j + 8 * k) * NB] = v[k];
   __syncthreads();
   // 3. forward y, first half, in place
 #pragma unroll
-  for (int n1 = 0; n1 < 8; ++n1) v[n1] = ys[(8 * n1 + j) * ROW];
+  for (int n1 = 0; n1 < 8; ++n1) v[n1] = ys[sw(8 * n1 + j) * ROW];
   dft8<false>(v);
   tw8(v, j, false);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) ys[(8 * k + j) * ROW] = v[k];
+  for (int k = 0; k < 8; ++k) ys[sw(8 * k + j) * ROW] = v[k];
   __syncthreads();
   // 4. forward y second half, x G, inverse y first half (n2 = j)
 #pragma unroll
-  for (int n2 = 0; n2 < 8; ++n2) v[n2] = ys[(8 * j + n2) * ROW];
+  for (int n2 = 0; n2 < 8; ++n2) v[n2] = ys[sw(8 * j + n2) * ROW];
   dft8<false>(v);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {             // v[k] = X[k1 = j + 8 k] at column k2 = r
@@ -870,27 +906,27 @@ __global__ __launch_bounds__(YZ_NT) void k_fft_yz64(FftYZArgs A) {
   tw8(v, j, true);
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 8; ++k) ys[(8 * k + j) * ROW] = v[k];
+  for (int k = 0; k < 8; ++k) ys[sw(8 * k + j) * ROW] = v[k];
   __syncthreads();
   // 5. inverse y, second half
 #pragma unroll
-  for (int n2 = 0; n2 < 8; ++n2) v[n2] = ys[(8 * j + n2) * ROW];
+  for (int n2 = 0; n2 < 8; ++n2) v[n2] = ys[sw(8 * j + n2) * ROW];
   dft8<true>(v);
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 8; ++k) ys[(j + 8 * k) * ROW] = v[k];
+  for (int k = 0; k < 8; ++k) ys[sw(j + 8 * k) * ROW] = v[k];
   __syncthreads();
   // 6. inverse z, first half, in place
 #pragma unroll
-  for (int n1 = 0; n1 < 8; ++n1) v[n1] = zs[(8 * n1 + j) * NB];
+  for (int n1 = 0; n1 < 8; ++n1) v[n1] = zs[sw(8 * n1 + j) * NB];
   dft8<true>(v);
   tw8(v, j, true);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) zs[(8 * k + j) * NB] = v[k];
+  for (int k = 0; k < 8; ++k) zs[sw(8 * k + j) * NB] = v[k];
   __syncthreads();
   // 7. inverse z, second half, to the grid: X[j + 8 k2]
 #pragma unroll
-  for (int n2 = 0; n2 < 8; ++n2) v[n2] = zs[(8 * j + n2) * NB];
+  for (int n2 = 0; n2 < 8; ++n2) v[n2] = zs[sw(8 * j + n2) * NB];
   dft8<true>(v);
   double2* g = A.grid + (plane + (size_t)r * K + j) * A.pc + s0 + s;
 #pragma unroll
@@ -1027,17 +1063,32 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
     S.ctrl = c->ctrl;
     for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
     S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms; S.tile_nbr = c->tile_nbr;
-    const int gbeads = c->spread_gb > 0 ? (c->spread_gb < P ? c->spread_gb : P) : (P < 8 ? P : 8);
-    const dim3 grid(c->ntiles, P / gbeads);
-#define SPREAD_CALL(GBV)                                                                     \
-    QHP_SWITCH_ORDER(c->p.pme_order,                                                         \
-                     hipLaunchKernelGGL((k_spread_tiles<OO, GBV>), grid, NT, 0, c->stream, S))
-    switch (gbeads) {
-      case 1: SPREAD_CALL(1); break;
-      case 2: SPREAD_CALL(2); break;
-      case 4: SPREAD_CALL(4); break;
-      case 8: SPREAD_CALL(8); break;
-      default: SPREAD_CALL(16); break;
+    // block shape: gb beads, z tiles along z (at most 16 x 8^3 points of LDS)
+    int gb = c->spread_gb > 0 ? c->spread_gb : 8;
+    if (gb > P) gb = P;
+    int z = c->spread_z > 0 ? c->spread_z : 1;
+    if (z > S.nt2) z = S.nt2;
+    while (z * gb > 16) z >>= 1;
+    const dim3 grid(c->ntiles / z, P / gb);
+#define SPREAD_CALL(GBV, ZV)                                                                 \
+    QHP_SWITCH_ORDER(c->p.pme_order, hipLaunchKernelGGL((k_spread_tiles<OO, GBV, false, ZV>),  \
+                                                        grid, NT, 0, c->stream, S))
+    switch (gb * 16 + z) {
+      case 16 + 1: SPREAD_CALL(1, 1); break;
+      case 16 + 2: SPREAD_CALL(1, 2); break;
+      case 16 + 4: SPREAD_CALL(1, 4); break;
+      case 16 + 8: SPREAD_CALL(1, 8); break;
+      case 32 + 1: SPREAD_CALL(2, 1); break;
+      case 32 + 2: SPREAD_CALL(2, 2); break;
+      case 32 + 4: SPREAD_CALL(2, 4); break;
+      case 32 + 8: SPREAD_CALL(2, 8); break;
+      case 64 + 1: SPREAD_CALL(4, 1); break;
+      case 64 + 2: SPREAD_CALL(4, 2); break;
+      case 64 + 4: SPREAD_CALL(4, 4); break;
+      case 128 + 1: SPREAD_CALL(8, 1); break;
+      case 128 + 2: SPREAD_CALL(8, 2); break;
+      case 256 + 1: SPREAD_CALL(16, 1); break;
+      default: return hipErrorInvalidValue;
     }
 #undef SPREAD_CALL
   }
