@@ -106,7 +106,7 @@ void free_all(qhp_ctx* c) {
                   c->d_type, c->d_mass, c->d_charge, c->d_sqrt_mkT, c->d_sigma, c->d_eps,
                   c->Q, c->Pa, c->x, c->g, c->cent, c->cref, c->coff, c->cwrap, c->xf, c->ctrl,
                   c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
-                  c->nnbr, c->bmax, c->grid, c->grid2, c->tile_nbr, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
+                  c->nnbr, c->bmax, c->grid, c->grid2, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
                   c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->pg_dq, c->pg_lj,
                   c->hvp_out, c->d_charge_alt,
                   c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
@@ -435,21 +435,6 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     int nt[3];
     for (int d = 0; d < 3; ++d) nt[d] = c->K[d] / 8;
     c->ntiles = nt[0] * nt[1] * nt[2];
-    std::vector<int> tn((size_t)c->ntiles * 27, -1);
-    for (int a = 0; a < nt[0]; ++a)
-      for (int b = 0; b < nt[1]; ++b)
-        for (int e = 0; e < nt[2]; ++e) {
-          std::set<int> s;
-          for (int da = -1; da <= 1; ++da)
-            for (int db = -1; db <= 1; ++db)
-              for (int de = -1; de <= 1; ++de)
-                s.insert((((a + da + nt[0]) % nt[0]) * nt[1] + (b + db + nt[1]) % nt[1]) * nt[2] +
-                         (e + de + nt[2]) % nt[2]);
-          int k = 0;
-          for (int v2 : s) tn[(size_t)((a * nt[1] + b) * nt[2] + e) * 27 + k++] = v2;
-        }
-    TRY(dalloc(&c->tile_nbr, tn.size()));
-    TRY(hipMemcpy(c->tile_nbr, tn.data(), tn.size() * sizeof(int), hipMemcpyHostToDevice));
     TRY(dalloc(&c->tile_of, N)); TRY(dalloc(&c->tile_atoms, N));
     TRY(dalloc(&c->tile_count, c->ntiles)); TRY(dalloc(&c->tile_fill, c->ntiles));
     TRY(dalloc(&c->tile_start, c->ntiles + 1));

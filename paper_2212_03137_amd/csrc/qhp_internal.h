@@ -152,7 +152,6 @@ struct qhp_ctx {
   int* tile_fill = nullptr;   // [ntiles]
   int* tile_start = nullptr;  // [ntiles + 1]
   int* tile_atoms = nullptr;  // [N]
-  int* tile_nbr = nullptr;    // [ntiles][27] distinct neighbouring tiles, -1 padded
   double2* tw[3] = {nullptr, nullptr, nullptr};
 
   // energies

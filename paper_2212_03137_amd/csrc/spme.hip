@@ -329,7 +329,7 @@ struct TSpreadArgs {
   const double4* cent;        // centroids (null for P = 1: the bead itself)
   double L[3], KoL[3];        // box and K / L per axis
   const NlCtrl* ctrl;         // spread_m: largest bead-centroid base offset this step
-  const int* tile_start; const int* tile_atoms; const int* tile_nbr;   // [ntiles][27]
+  const int* tile_start; const int* tile_atoms;   // tiles' atom ranges, atoms by tile
   const double* u;            // tangent spreading: direction [3][N][P]
 };
 
@@ -1062,7 +1062,7 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
     S.cent = plain ? nullptr : c->cent;
     S.ctrl = c->ctrl;
     for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
-    S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms; S.tile_nbr = c->tile_nbr;
+    S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms;
     // block shape: gb beads, z tiles along z (at most 16 x 8^3 points of LDS)
     int gb = c->spread_gb > 0 ? c->spread_gb : 8;
     if (gb > P) gb = P;
@@ -1122,7 +1122,7 @@ hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu, bool mix) {
   S.x = c->x; S.grid = (double*)c->grid2; S.charge = c->d_charge;
   S.cent = c->cent; S.ctrl = c->ctrl; S.u = u;
   for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
-  S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms; S.tile_nbr = c->tile_nbr;
+  S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms;
   const int gbeads = P < 8 ? P : 8;
   const dim3 grid(c->ntiles, P / gbeads);
 #define SPREAD_CALL(GBV)                                                                     \
