@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip plain and batched FP64")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel-class times")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of graphs")
+    ap.add_argument("--windows", action="store_true",
+                    help="only the 16-window free-energy workload (one JSON line)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for hardware counters: a 256 MiB device copy (calibration), then "
                          "--steps launched steps of the batched FP32-pair path; no JSON")
@@ -155,7 +157,7 @@ def force_loss_timing(q, qa, n_configs=8):
 def windows_timing(q, steps=20, warmup=3):
     """The batched free-energy workload: 16 alchemical windows lambda = i/15 of the 12-atom
     solute in 256-2,048 waters with P = 8/16/32 (780-6,156 atoms each), FP32 pairs, each
-    window's SPME spreading tile picked by qhp_autotune, stepped as one group (one captured
+    window's SPME spreading block picked by qhp_autotune, stepped as one group (one captured
     graph per step of all windows, one branch per window). Also: the same windows stepped
     one after another (each its own graph per step), and the cost of one sample of the BAR
     inputs (every window's bead energies at its two neighbours' couplings)."""
@@ -196,7 +198,7 @@ def windows_timing(q, steps=20, warmup=3):
             c.close()
     return {"windows": 16, "atoms": [s.n_atoms for s in systems],
             "beads": [s.n_beads for s in systems], "bead_atoms_total": bead_atoms,
-            "spread_beads_autotuned": tiles,
+            "spme_autotuned": tiles,
             "group_ms_per_step": t_group / steps * 1e3,
             "group_bead_atom_steps_per_s": bead_atoms * steps / t_group,
             "sequential_ms_per_step": t_seq / steps * 1e3,
@@ -273,6 +275,11 @@ def main():
             c.profile("off")
         return t, pr
 
+    if args.windows:
+        print(json.dumps({"alchemical_windows": windows_timing(q, steps=max(1, args.steps),
+                                                               warmup=args.warmup)}))
+        return
+
     if args.pmc_probe:
         # a plain copy of known size (256 MiB read, 256 MiB written) to scale the
         # FETCH_SIZE / WRITE_SIZE counters, then launched steps of the timed path
@@ -291,7 +298,7 @@ def main():
     # --- which kernel class dominates the batched FP32-pair step (short untimed pass) ---
     main_ctx = make(q.FP32_PAIRS, q.BATCHED)
     main_ctx.step(args.warmup)
-    spread_beads = main_ctx.autotune(5)
+    spread_block = main_ctx.autotune(5)
     classes = ["pair", "spread", "fft", "gather", "nm"]
     per_class = {}
     for cl in classes:
@@ -350,7 +357,9 @@ def main():
                                "rc 9 A, SPME 64^3 order 5, P=32, 300 K, dt 0.5 fs, "
                                "bead-batched FP32-pair path",
                    "n_atoms": s.n_atoms, "n_beads": s.n_beads, "parallelism": "single GPU",
-                   "spread_beads_autotuned": spread_beads},
+                   "spme_autotuned": {"spread_beads": spread_block[0],
+                                      "spread_z_tiles": spread_block[1],
+                                      "yz_plane_slots": spread_block[2]}},
         "roofline": roof,
         "breakdown_ms_per_step": per_class,
     }

@@ -290,11 +290,17 @@ QHP_API const char* qhp_group_last_error(qhp_group* group);
 
 /* Launch-shape autotuner: times the context's reciprocal-space pass on its current beads
  * (`reps` launches per candidate, HIP events on the context's stream; the propagated state
- * is not changed) for each SPME spreading tile of 1, 2, 4, 8 or 16 beads per block (up to
- * the beads the pass covers), keeps the fastest for the context's later launches and
- * returns it in `spread_beads` (nullable). Needs a state (qhp_set_state). Results do not
- * depend on the choice beyond the order of floating-point additions. */
-QHP_API int qhp_autotune(qhp_ctx* ctx, int32_t reps, int32_t* spread_beads);
+ * is not changed). First the SPME spreading block shape: 1, 2, 4, 8 or 16 beads per block
+ * (up to the beads the pass covers) times 1, 2, 4 or 8 grid tiles of 8^3 points along z
+ * (at most 16 bead-tiles per block, 64 KB of LDS); then, for square 32^2 or 64^2 y-z
+ * planes, the plane kernel of the y and z transforms with 1, 2, 4 or 8 complex grid slots
+ * per block (at most 2 at 64^2) against three one-axis passes (reported as -1). Keeps the
+ * fastest for the context's later launches and returns them in `spread_beads`,
+ * `spread_ztiles` and `fft_slots` (all nullable; 0 = no plane kernel applies). Needs a
+ * state (qhp_set_state). Results do not depend on the choice beyond the order of
+ * floating-point additions. */
+QHP_API int qhp_autotune(qhp_ctx* ctx, int32_t reps, int32_t* spread_beads,
+                         int32_t* spread_ztiles, int32_t* fft_slots);
 
 /* adQTB: gamma_z(omega_k), k = 0..N_seg, for every type: [n_types][N_seg + 1] (host). */
 QHP_API int qhp_qtb_get_gamma(qhp_ctx* ctx, double* gamma);

@@ -679,13 +679,14 @@ extern "C" int qhp_bar(const double* du_a, int64_t n_a, const double* du_b, int6
 }
 
 extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
-                            int32_t* spread_ztiles) {
+                            int32_t* spread_ztiles, int32_t* fft_slots) {
   if (!c) return QHP_EINVAL;
   if (reps < 1) return qhp_fail(c, QHP_EINVAL, "reps must be >= 1");
   if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
   if (c->p.exec == QHP_PLAIN) {          // one bead per launch: keep the default tile
     if (spread_beads) *spread_beads = 1;
     if (spread_ztiles) *spread_ztiles = 1;
+    if (fft_slots) *fft_slots = 0;
     return QHP_OK;
   }
   // the reciprocal-space pass of the propagated beads (the contracted ones under RESPA),
@@ -714,16 +715,36 @@ extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
       if (e == hipSuccess && (best_gb == 0 || ms < best_ms)) { best_gb = gb; best_z = z; best_ms = ms; }
     }
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
   c->spread_gb = best_gb;
   c->spread_z = best_z;
+  // then the reciprocal transforms: the y-z plane kernel with 1, 2, 4 or 8 slots per
+  // block (square 32^2 or 64^2 planes; up to 2 slots at 64) or five one-axis passes
+  int best_nb = 0;
+  best_ms = 0.f;
+  const bool planes = c->K[1] == c->K[2] && (c->K[1] == 32 || c->K[1] == 64);
+  const int cap = c->K[1] == 64 ? 2 : 8;
+  for (int nb = -1; nb <= 8 && e == hipSuccess; nb = nb < 0 ? 1 : 2 * nb) {
+    if (nb > 0 && (!planes || nb > cap || nb > B.Pc)) continue;
+    c->fft_nb = nb;
+    e = launch_spme(c, false, -1, &B);
+    if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_spme(c, false, -1, &B);
+    if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e == hipSuccess && (best_nb == 0 || ms < best_ms)) { best_nb = nb; best_ms = ms; }
+  }
+  c->fft_nb = best_nb;
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
   QHP_HIP(c, e);
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   c->step_exec = nullptr;
   ++c->graph_epoch;
   if (spread_beads) *spread_beads = best_gb;
   if (spread_ztiles) *spread_ztiles = best_z;
+  if (fft_slots) *fft_slots = best_nb;
   return QHP_OK;
 }
 

@@ -99,6 +99,8 @@ struct qhp_ctx {
   int64_t graph_epoch = 0;          // bumped whenever captured kernel arguments go stale
   int spread_gb = 0;                // SPME spreading: beads per block (0 = min(P, 8))
   int spread_z = 0;                 // SPME spreading: 8^3 tiles per block along z (0 = 1)
+  int fft_nb = 0;                   // y-z plane kernel: slots per block (0 = default,
+                                    // < 0 = one-axis passes instead)
 
   // normal modes
   double* T = nullptr;        // [P][P] T[bead][mode]

@@ -777,8 +777,13 @@ struct FftYZArgs {
 
 constexpr int YZ_NT = 1024;
 
+// threads of the generic plane kernel: one per second-step task, at most 1,024
 template <int K, int NB>
-__global__ __launch_bounds__(YZ_NT) void k_fft_yz(FftYZArgs A) {
+constexpr int yz_threads() { return K * NB * 8 < YZ_NT ? K * NB * 8 : YZ_NT; }
+
+template <int K, int NB>
+__global__ __launch_bounds__((yz_threads<K, NB>())) void k_fft_yz(FftYZArgs A) {
+  constexpr int NTH = yz_threads<K, NB>();
   constexpr int ROW = K * NB + NB;        // one k1 row of LDS, padded against bank conflicts
   __shared__ double2 buf[K * ROW];
   __shared__ double2 stw[K];
@@ -786,21 +791,21 @@ __global__ __launch_bounds__(YZ_NT) void k_fft_yz(FftYZArgs A) {
   const int groups = A.pc / NB;
   const int lb = xcd_block(blockIdx.x, gridDim.x);   // the slot groups of a plane: one XCD
   const int k0 = lb / groups, s0 = (lb % groups) * NB;
-  for (int m = tid; m < K; m += YZ_NT) stw[m] = A.tw[m];
+  for (int m = tid; m < K; m += NTH) stw[m] = A.tw[m];
   const size_t plane = (size_t)k0 * K * K;
-  constexpr int PER = K * K * NB / YZ_NT;            // values per thread (a power of two)
-  static_assert(PER * YZ_NT == K * K * NB, "plane size");
+  constexpr int PER = K * K * NB / NTH;            // values per thread (a power of two)
+  static_assert(PER * NTH == K * K * NB, "plane size");
   {
     double2 r[PER];                                  // all loads in flight, then to LDS
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int l = tid + i * YZ_NT, s = l % NB, pt = l / NB;
+      const int l = tid + i * NTH, s = l % NB, pt = l / NB;
       r[i] = A.grid[(plane + pt) * A.pc + s0 + s];
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int l = tid + i * YZ_NT, s = l % NB, k2 = (l / NB) % K, k1 = l / (NB * K);
+      const int l = tid + i * NTH, s = l % NB, k2 = (l / NB) % K, k1 = l / (NB * K);
       buf[k1 * ROW + k2 * NB + s] = r[i];
     }
   }
@@ -808,26 +813,26 @@ __global__ __launch_bounds__(YZ_NT) void k_fft_yz(FftYZArgs A) {
   // series along z: q = (k1, s); along y: q = (k2, s)
   auto offz = [](int q) { return (q / NB) * ROW + q % NB; };
   auto offy = [](int q) { return (q / NB) * NB + q % NB; };
-  lds_fft<K, K * NB, YZ_NT, false>(buf, stw, offz, NB);
-  lds_fft<K, K * NB, YZ_NT, false>(buf, stw, offy, ROW);
-  for (int l = tid; l < K * K * NB; l += YZ_NT) {
+  lds_fft<K, K * NB, NTH, false>(buf, stw, offz, NB);
+  lds_fft<K, K * NB, NTH, false>(buf, stw, offy, ROW);
+  for (int l = tid; l < K * K * NB; l += NTH) {
     const int s = l % NB, k2 = (l / NB) % K, k1 = l / (NB * K);
     const double g = A.G[plane + (size_t)k1 * K + k2];
     double2& v = buf[k1 * ROW + k2 * NB + s];
     v.x *= g; v.y *= g;
   }
   __syncthreads();
-  lds_fft<K, K * NB, YZ_NT, true>(buf, stw, offy, ROW);
-  lds_fft<K, K * NB, YZ_NT, true>(buf, stw, offz, NB);
+  lds_fft<K, K * NB, NTH, true>(buf, stw, offy, ROW);
+  lds_fft<K, K * NB, NTH, true>(buf, stw, offz, NB);
   double2 r[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    const int l = tid + i * YZ_NT, s = l % NB, k2 = (l / NB) % K, k1 = l / (NB * K);
+    const int l = tid + i * NTH, s = l % NB, k2 = (l / NB) % K, k1 = l / (NB * K);
     r[i] = buf[k1 * ROW + k2 * NB + s];
   }
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    const int l = tid + i * YZ_NT, s = l % NB, pt = l / NB;
+    const int l = tid + i * NTH, s = l % NB, pt = l / NB;
     A.grid[(plane + pt) * A.pc + s0 + s] = r[i];
   }
 }
@@ -988,14 +993,22 @@ static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc, double2* grid
 
 // The reciprocal-space convolution of a spread grid: forward 3D transform, product with
 // G, inverse transform (unnormalised: G carries the factors). Square y-z planes of 32 or
-// 64 points take the fused plane kernel between the two x passes; other grids take five
-// one-axis passes (the z pass fusing G).
+// 64 points take the fused plane kernel between the two x passes (unless the autotuner
+// found the one-axis passes faster: fft_nb < 0); other grids take five one-axis passes
+// (the z pass fusing G).
 static hipError_t convolve(qhp_ctx* c, int pc, double2* grid) {
   const int K = c->K[1];
-  int nb = 0;                                      // slots per plane block
+  int nb = 0;                                      // slots per plane block (0: five passes)
   if (K == c->K[2] && (K == 64 || K == 32)) {
     const int cap = K == 64 ? 2 : 8;               // 8,192 complex values in LDS
-    nb = pc < cap ? pc : cap;
+    if (c->fft_nb > 0) {
+      nb = c->fft_nb < cap ? c->fft_nb : cap;
+    } else if (c->fft_nb == 0) {                   // default: 64^2 planes two slots; 32^2
+      nb = K == 64 ? 2 : 1;                        // planes as many as keep 256 blocks
+      if (K == 32)
+        while (nb < cap && (long)c->K[0] * (pc / (2 * nb)) >= 256) nb *= 2;
+    }
+    if (nb > pc) nb = pc;
   }
   hipError_t e;
   if ((e = fft_pass(c, 0, 0, pc, grid)) != hipSuccess) return e;
@@ -1003,7 +1016,8 @@ static hipError_t convolve(qhp_ctx* c, int pc, double2* grid) {
     FftYZArgs A;
     A.grid = grid; A.tw = c->tw[1]; A.G = c->influence; A.pc = pc;
     const unsigned blocks = (unsigned)(c->K[0] * (pc / nb));
-#define YZ_CALL(KK, NBV) hipLaunchKernelGGL((k_fft_yz<KK, NBV>), blocks, YZ_NT, 0, c->stream, A)
+#define YZ_CALL(KK, NBV)                                                                    \
+    hipLaunchKernelGGL((k_fft_yz<KK, NBV>), blocks, (yz_threads<KK, NBV>()), 0, c->stream, A)
     if (K == 64) {
       if (nb == 1) YZ_CALL(64, 1);
       else hipLaunchKernelGGL(k_fft_yz64, blocks, YZ_NT, 0, c->stream, A);

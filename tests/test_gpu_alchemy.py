@@ -199,12 +199,14 @@ def test_autotune_keeps_results_and_the_state(medium):
         c.set_state(medium.pos, medium.vel, 0)
         E0, F0 = c.eval(medium.pos)
         x0, v0, _ = c.get_state()
-        gb = c.autotune(3)
+        gb, zt, nb = c.autotune(3)
         x1, v1, _ = c.get_state()
         E1, F1 = c.eval(medium.pos)
         c.step(2)
-    say("autotuned spread beads", gb)
+    say("autotuned spread block", gb, zt, "fft slots", nb)
+    assert nb in (-1, 1, 2)                            # 4 beads: two complex slots
     assert gb in (1, 2, 4) and gb <= medium.n_beads
+    assert zt in (1, 2, 4) and gb * zt <= 16          # 32^3 grid: four 8^3 tiles along z
     assert np.array_equal(x0, x1) and np.array_equal(v0, v1)
     assert rel_max(F1, F0) <= 1e-13
     assert np.allclose(E1, E0, rtol=1e-13, atol=1e-10)
