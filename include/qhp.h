@@ -302,6 +302,15 @@ QHP_API const char* qhp_group_last_error(qhp_group* group);
 QHP_API int qhp_autotune(qhp_ctx* ctx, int32_t reps, int32_t* spread_beads,
                          int32_t* spread_ztiles, int32_t* fft_slots);
 
+/* Set the same launch shapes by hand (the autotuner's search space): spreading beads per
+ * block (0 = min(P, 8), else a power of two <= 16, capped at the beads of the pass),
+ * spreading 8^3 tiles along z (0 = 1, else a power of two <= 8, capped so that beads x
+ * tiles <= 16 and at the grid's tiles), y-z plane kernel slots per block (0 = default,
+ * -1 = one-axis passes, else a power of two <= 8, capped at 2 for 64^2 planes and at the
+ * grid's slots; ignored where no plane kernel applies). QHP_EINVAL otherwise. */
+QHP_API int qhp_set_launch(qhp_ctx* ctx, int32_t spread_beads, int32_t spread_ztiles,
+                           int32_t fft_slots);
+
 /* adQTB: gamma_z(omega_k), k = 0..N_seg, for every type: [n_types][N_seg + 1] (host). */
 QHP_API int qhp_qtb_get_gamma(qhp_ctx* ctx, double* gamma);
 QHP_API int qhp_qtb_set_gamma(qhp_ctx* ctx, const double* gamma);

@@ -30,7 +30,8 @@ EXPORTS = ("qhp_create", "qhp_destroy", "qhp_eval", "qhp_set_state", "qhp_get_st
            "qhp_qtb_get_gamma", "qhp_qtb_set_gamma", "qhp_qtb_get_noise", "qhp_qtb_get_delta",
            "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error", "qhp_param_grad",
            "qhp_hvp", "qhp_set_lambda", "qhp_eval_lambda", "qhp_bar", "qhp_group_create",
-           "qhp_group_step", "qhp_group_destroy", "qhp_group_last_error", "qhp_autotune")
+           "qhp_group_step", "qhp_group_destroy", "qhp_group_last_error", "qhp_autotune",
+           "qhp_set_launch")
 
 
 class QhpError(RuntimeError):
@@ -97,6 +98,7 @@ def load():
     lib.qhp_bar.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_double, D, C.POINTER(C.c_int32)]
     lib.qhp_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32)]
+    lib.qhp_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     lib.qhp_group_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
     lib.qhp_group_step.argtypes = [vp, C.c_int32]
     lib.qhp_group_destroy.argtypes = [vp]
@@ -252,6 +254,11 @@ class Context:
         self._check(self._lib.qhp_autotune(self._h, int(reps), C.byref(gb), C.byref(z),
                                            C.byref(nb)))
         return gb.value, z.value, nb.value
+
+    def set_launch(self, spread_beads=0, spread_ztiles=0, fft_slots=0):
+        """Launch shapes by hand (qhp_set_launch); 0 = default."""
+        self._check(self._lib.qhp_set_launch(self._h, int(spread_beads), int(spread_ztiles),
+                                             int(fft_slots)))
 
     def param_grad(self, pos):
         """d(sum of bead energies) / d(charges [N], lj_epsilon [T], lj_sigma [T])."""

@@ -678,6 +678,25 @@ extern "C" int qhp_bar(const double* du_a, int64_t n_a, const double* du_b, int6
   return QHP_ENONFINITE;
 }
 
+extern "C" int qhp_set_launch(qhp_ctx* c, int32_t spread_beads, int32_t spread_ztiles,
+                              int32_t fft_slots) {
+  if (!c) return QHP_EINVAL;
+  auto p2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+  if (!(spread_beads == 0 || (p2(spread_beads) && spread_beads <= 16)))
+    return qhp_fail(c, QHP_EINVAL, "spread_beads must be 0 or a power of two <= 16");
+  if (!(spread_ztiles == 0 || (p2(spread_ztiles) && spread_ztiles <= 8)))
+    return qhp_fail(c, QHP_EINVAL, "spread_ztiles must be 0 or a power of two <= 8");
+  if (!(fft_slots == 0 || fft_slots == -1 || (p2(fft_slots) && fft_slots <= 8)))
+    return qhp_fail(c, QHP_EINVAL, "fft_slots must be -1, 0 or a power of two <= 8");
+  c->spread_gb = spread_beads;
+  c->spread_z = spread_ztiles;
+  c->fft_nb = fft_slots;
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  c->step_exec = nullptr;
+  ++c->graph_epoch;
+  return QHP_OK;
+}
+
 extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
                             int32_t* spread_ztiles, int32_t* fft_slots) {
   if (!c) return QHP_EINVAL;

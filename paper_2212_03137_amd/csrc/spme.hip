@@ -467,8 +467,8 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
           if (d < 2) {
             rel[d][t] = r < TB ? r : -1;
           } else {
-            // along z a point outside the tile adds zero to the row's first point, so the
-            // innermost loop has no branch
+            // along z a point outside the tile is skipped (lanes whose point lies outside
+            // issue no LDS atomic); the tangent spreading adds zero to the row's first point
             oz[t] = r < TZ ? r * GB : 0;
             wz[t] = r < TZ ? w[2][t] : 0.0;
             mz[t] = r < TZ ? 1.0 : 0.0;
@@ -513,7 +513,8 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
           const double wab = wa * w[1][tb];
           double* row = acc + (rel[0][ta] * TB + rel[1][tb]) * TZ * GB + bl;
 #pragma unroll
-          for (int tc = 0; tc < ORDER; ++tc) atomicAdd(row + oz[tc], wab * wz[tc]);
+          for (int tc = 0; tc < ORDER; ++tc)
+            if (mz[tc] != 0.0) atomicAdd(row + oz[tc], wab * wz[tc]);   // in-tile points only
         }
       }
     }
