@@ -107,7 +107,7 @@ void free_all(qhp_ctx* c) {
                   c->Q, c->Pa, c->x, c->g, c->cent, c->cref, c->coff, c->cwrap, c->xf, c->ctrl,
                   c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
                   c->nnbr, c->bmax, c->grid, c->grid2, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
-                  c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->pg_dq, c->pg_lj,
+                  c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->pg_dq, c->pg_lj, c->pair_tab,
                   c->hvp_out, c->d_charge_alt,
                   c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.vvsum, c->qtb.vfsum,
@@ -130,6 +130,33 @@ hipError_t upload_twiddles(double2** dst, int L) {
   hipError_t e = dalloc(dst, L);
   if (e != hipSuccess) return e;
   return hipMemcpy(*dst, t.data(), L * sizeof(double2), hipMemcpyHostToDevice);
+}
+
+// Tables of the FP32 pair kernel: on QHP_PAIR_TAB equal intervals of r in [0, rc], the
+// cubic through four equally spaced points (both ends included) of the force kernel
+// (erfc(a r)/r + 2a/sqrt(pi) exp(-a^2 r^2)) / r^2 and of the energy kernel erfc(a r)/r,
+// as float4 (c0, c1, c2, c3) of c0 + c1 f + c2 f^2 + c3 f^3, f the position in the
+// interval. Accurate to ~2e-9 relative above 0.9 A (below the kernel takes the formula).
+std::vector<float4> pair_tables(double a, double rc) {
+  const int n = QHP_PAIR_TAB;
+  const double h = rc / n, c2a = 2.0 * a / std::sqrt(M_PI);
+  std::vector<float4> t(2 * n);
+  for (int which = 0; which < 2; ++which)
+    for (int k = 0; k < n; ++k) {
+      double y[4];
+      for (int j = 0; j < 4; ++j) {
+        const double r = std::max((k + j / 3.0) * h, 0.25);
+        const double e = std::erfc(a * r) / r;
+        y[j] = which == 0 ? (e + c2a * std::exp(-a * a * r * r)) / (r * r) : e;
+      }
+      // the cubic through (0, y0), (1/3, y1), (2/3, y2), (1, y3) in monomial form
+      const double c0 = y[0];
+      const double c1 = (-11.0 * y[0] + 18.0 * y[1] - 9.0 * y[2] + 2.0 * y[3]) / 2.0;
+      const double c2 = 9.0 * (2.0 * y[0] - 5.0 * y[1] + 4.0 * y[2] - y[3]) / 2.0;
+      const double c3 = 27.0 * (-y[0] + 3.0 * y[1] - 3.0 * y[2] + y[3]) / 6.0;
+      t[(size_t)which * n + k] = make_float4((float)c0, (float)c1, (float)c2, (float)c3);
+    }
+  return t;
 }
 
 // charges of the alchemical system at electrostatic coupling le: solute charges scaled
@@ -332,6 +359,11 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   TRY(dalloc(&c->xf, (size_t)N * P));
   TRY(dalloc(&c->io_a, NP3)); TRY(dalloc(&c->io_b, NP3)); TRY(dalloc(&c->g_eval, NP3));
   TRY(dalloc(&c->pg_dq, N)); TRY(dalloc(&c->pg_lj, 2 * QHP_MAX_TYPES));
+  if (p->precision == QHP_FP32_PAIRS) {
+    const std::vector<float4> tab = pair_tables(p->ewald_alpha, p->cutoff);
+    TRY(dalloc(&c->pair_tab, tab.size()));
+    TRY(hipMemcpy(c->pair_tab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice));
+  }
   TRY(dalloc(&c->energy, (size_t)P * QHP_NTERMS));
   // ---- multiple time stepping / ring-polymer contraction ----
   c->Ps = p->rpc_beads > 0 ? p->rpc_beads : P;

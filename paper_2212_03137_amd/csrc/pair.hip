@@ -55,6 +55,9 @@ struct PairArgs {
   double* dq; double* deps; double* dsig;          // parameter-gradient outputs (FP64 path)
   const double* u; double* hu;                     // Hessian-vector product: direction, output
   int mix;                                         // HVP: also d(u . grad E)/d(q, eps, sigma)
+  const float4* tab;      // FP32 pairs: force and energy kernel tables ([2][QHP_PAIR_TAB])
+  float tab_scale;        // QHP_PAIR_TAB / rc
+  int tab_kmin;           // first interval the tables are used for (closer: the formula)
   int nblocks;            // logical blocks
   const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
   double* energy;         // [P][NTERMS] (plain: the bead's row)
@@ -239,28 +242,46 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
 // Compacted neighbours t0 + s, t0 + s + S, ... < cnt for the lane (slot s, bead b).
 // LJ = false for neighbours without an LJ term (a wavefront-uniform choice).
 // SOFT: the LJ neighbours' soft-core alpha (1 - lambda) is in sa (the k_pair64 form).
+// The screened Coulomb force and energy kernels come from cubic tables in r (stab: force,
+// stab + QHP_PAIR_TAB: energy); pairs closer than the tables' first used interval (none
+// in liquid water) take the erfc fit instead.
 template <int P, bool ENERGY, bool LJ, bool SOFT = false>
 QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, const float* sa,
-                   const unsigned* sj, int t0, int cnt, int s, unsigned boff, float4 oi,
-                   float rc2, float alpha, float kexp, float c2a, float& fx, float& fy,
-                   float& fz, double& ec, double& elj) {
+                   const unsigned* sj, const float4* stab, int t0, int cnt, int s,
+                   unsigned boff, float4 oi, float rc2, float alpha, float kexp, float c2a,
+                   float& fx, float& fy, float& fz, double& ec, double& elj) {
   constexpr int S = 64 / P;
   const char* xf = reinterpret_cast<const char*>(A.xf);
+  const float tscale = A.tab_scale;
+  const int kmin = A.tab_kmin;
   auto load = [&](int t) { return *reinterpret_cast<const float4*>(xf + (sj[t] + boff)); };
   auto interact = [&](const float4 cd, const float4 oj, const float2 lj, const float a) {
     const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
     const float r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2) {
       const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir;
-      const float x = alpha * (r2 * ir);
-      const float tt = __builtin_amdgcn_rcpf(1.0f + ERFC_P * x);
-      float q = ERFC_Q[7];
+      const float u = (r2 * ir) * tscale;
+      const int k = min((int)u, QHP_PAIR_TAB - 1);
+      float sc;
+      if (k >= kmin) {
+        const float f = u - (float)k;
+        const float4 c = stab[k];
+        sc = cd.w * fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
+        if (ENERGY) {
+          const float4 d = stab[QHP_PAIR_TAB + k];
+          ec += (double)(cd.w * fmaf(fmaf(fmaf(d.w, f, d.z), f, d.y), f, d.x));
+        }
+      } else {
+        const float x = alpha * (r2 * ir);
+        const float tt = __builtin_amdgcn_rcpf(1.0f + ERFC_P * x);
+        float q = ERFC_Q[7];
 #pragma unroll
-      for (int k = 6; k >= 0; --k) q = q * tt + ERFC_Q[k];
-      const float ex = __builtin_amdgcn_exp2f(kexp * r2);       // exp(-alpha^2 r^2)
-      const float tq = tt * q;                                   // erfc(alpha r) / ex
-      float sc = cd.w * ir2 * ex * (tq * ir + c2a);
-      if (ENERGY) ec += (double)(cd.w * tq * ex * ir);
+        for (int m = 6; m >= 0; --m) q = q * tt + ERFC_Q[m];
+        const float ex = __builtin_amdgcn_exp2f(kexp * r2);     // exp(-alpha^2 r^2)
+        const float tq = tt * q;                                 // erfc(alpha r) / ex
+        sc = cd.w * ir2 * ex * (tq * ir + c2a);
+        if (ENERGY) ec += (double)(cd.w * tq * ex * ir);
+      }
       if (LJ && SOFT) {
         const float s6 = lj.y * ir2 * ir2 * ir2;
         const float rd = __builtin_amdgcn_rcpf(1.0f + a * s6), u = s6 * rd;
@@ -293,6 +314,9 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
   __shared__ float2 slj[WPB][64];   // 4 eps_ij and sigma_ij^6 of the pair
   __shared__ float ssa[SOFT ? WPB : 1][SOFT ? 64 : 1];   // soft-core alpha (1 - lambda)
   __shared__ unsigned sj[WPB][64];  // byte offset of atom j's bead-0 FP32 offset
+  __shared__ float4 stab[(ENERGY ? 2 : 1) * QHP_PAIR_TAB];   // kernel tables
+  for (int k = threadIdx.x; k < (ENERGY ? 2 : 1) * QHP_PAIR_TAB; k += NT) stab[k] = A.tab[k];
+  __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, s = lane / P, b = lane % P;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int i = lb * WPB + wv;
@@ -349,10 +373,11 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
     wave_sync();
     float fx = 0.f, fy = 0.f, fz = 0.f;
     if (nlj > 0)
-      chunk<P, ENERGY, true, SOFT>(A, scd[wv], slj[wv], ssa[SOFT ? wv : 0], sj[wv], 0, nlj, s,
-                                   boff, oi, rc2, alpha, kexp, c2a, fx, fy, fz, ec, elj);
-    chunk<P, ENERGY, false>(A, scd[wv], slj[wv], nullptr, sj[wv], nlj, cnt, s, boff, oi, rc2,
-                            alpha, kexp, c2a, fx, fy, fz, ec, elj);
+      chunk<P, ENERGY, true, SOFT>(A, scd[wv], slj[wv], ssa[SOFT ? wv : 0], sj[wv], stab, 0,
+                                   nlj, s, boff, oi, rc2, alpha, kexp, c2a, fx, fy, fz, ec,
+                                   elj);
+    chunk<P, ENERGY, false>(A, scd[wv], slj[wv], nullptr, sj[wv], stab, nlj, cnt, s, boff, oi,
+                            rc2, alpha, kexp, c2a, fx, fy, fz, ec, elj);
     gx += (double)fx; gy += (double)fy; gz += (double)fz;
     wave_sync();
   }
@@ -404,6 +429,9 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
     }
   for (int a = 0; a < c->p.n_types; ++a) A.eps_of[a] = c->eps[a];
   A.dq = c->pg_dq; A.deps = c->pg_lj; A.dsig = c->pg_lj + QHP_MAX_TYPES;
+  A.tab = c->pair_tab;
+  A.tab_scale = (float)(QHP_PAIR_TAB / c->p.cutoff);
+  A.tab_kmin = (int)ceil(0.75 * QHP_PAIR_TAB / c->p.cutoff);   // tables from r = 0.75 A
 
   A.energy = plain ? c->energy + (size_t)bead * QHP_NTERMS : B.energy;
   A.ctrl = c->ctrl;

@@ -11,6 +11,7 @@
 #include "../../include/qhp.h"
 
 #define QHP_MAX_TYPES 8
+#define QHP_PAIR_TAB 1024           // intervals of the FP32 pair kernel's tables
 
 // ---------------------------------------------------------------------------------------
 // Device layout (all FP64 unless noted; "bead innermost"):
@@ -175,6 +176,8 @@ struct qhp_ctx {
   double* g_eval = nullptr;   // [3][N][P] gradient target of qhp_eval
 
   // parameter gradients of the summed bead energies
+  float4* pair_tab = nullptr; // FP32 pairs: [2][QHP_PAIR_TAB] cubic pieces of the screened
+                              // Coulomb force and energy kernels over [0, rc]
   double* pg_dq = nullptr;    // [N] d/d charge
   double* pg_lj = nullptr;    // [2][QHP_MAX_TYPES] d/d epsilon, d/d sigma per type
   double* hvp_out = nullptr;  // [3][N][P] Hessian-vector product (allocated on use)
