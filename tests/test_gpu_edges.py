@@ -1,0 +1,113 @@
+"""Edge cases of the HIP path against the FP64 oracle: the largest bead count (P = 64, one
+atom per wavefront in the pair and gather kernels), the classical P = 1 case, a single
+molecule (empty neighbour list), and host inputs rejected before any device work."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import has_gpu, oracle_grad_fn, rel_max, rel_rms
+from oracle import forces, rpmd
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not has_gpu(), reason="needs a HIP device")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ctx_for(s, **kw):
+    import paper_2212_03137_amd as q
+    return q.Context.from_system(s, **kw)
+
+
+def _trajectory(s, nsteps, **kw):
+    R = rpmd.RPMD(s.n_beads, s.mass, s.kT, s.hbar, s.dt, s.gamma_centroid, s.trpmd_c, s.seed,
+                  oracle_grad_fn(s))
+    R.set_state(s.pos, s.vel)
+    R.step(nsteps)
+    xr, vr, _ = R.get_state()
+    with ctx_for(s, **kw) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(nsteps)
+        x, v, st = c.get_state()
+    assert st == nsteps
+    return np.abs(x - xr).max() / np.abs(xr).max(), np.abs(v - vr).max() / np.abs(vr).max()
+
+
+def test_sixty_four_beads_fp64_eval_and_trajectory():
+    s = synth.water_box(64, 64, 12.42, seed=61, cutoff=6.0, pme_grid=16, pme_order=4)
+    say("P=64 small", s.n_atoms)
+    E_r, F_r = forces.evaluate(s.pos, s)
+    with ctx_for(s) as c:
+        E, F = c.eval(s.pos)
+    assert rel_max(F, F_r) <= 1e-11
+    assert np.allclose(E, E_r, rtol=1e-11, atol=1e-9)
+    ex, ev = _trajectory(s, 3)
+    assert ex < 1e-10 and ev < 1e-8, (ex, ev)
+
+
+def test_sixty_four_beads_fp32_pairs():
+    # 216 waters, 18.7 A: 2 (rc + skin) < L, so the FP32 pair kernel runs with one slot
+    s = synth.water_box(216, 64, 18.7, seed=62, cutoff=6.5, pme_grid=32, pme_order=5)
+    say("P=64 FP32", s.n_atoms)
+    import paper_2212_03137_amd as q
+    F_r = np.empty_like(s.pos)
+    E_r = np.empty((s.n_beads, 7))
+    for b in (0, 17, 63):                    # the oracle on three beads
+        e, f = forces.evaluate(s.pos[b:b + 1], s)
+        E_r[b], F_r[b] = e[0], f[0]
+    with ctx_for(s, precision=q.FP32_PAIRS) as c:
+        E, F = c.eval(s.pos)
+        c.set_state(s.pos, s.vel, 0)
+        c.step(5)
+        x, _, _ = c.get_state()
+    for b in (0, 17, 63):
+        assert rel_rms(F[b], F_r[b]) <= 1e-5, b
+        assert np.allclose(E[b], E_r[b], rtol=1e-5, atol=1e-4 * np.abs(E_r[b]).max())
+    assert np.all(np.isfinite(x))
+
+
+def test_classical_single_bead_eval_and_trajectory():
+    s = synth.water_box(64, 1, 12.42, seed=63, cutoff=6.0, pme_grid=16, pme_order=4)
+    E_r, F_r = forces.evaluate(s.pos, s)
+    with ctx_for(s) as c:
+        E, F = c.eval(s.pos)
+    assert rel_max(F, F_r) <= 1e-11
+    assert np.allclose(E, E_r, rtol=1e-11, atol=1e-9)
+    ex, ev = _trajectory(s, 3)
+    assert ex < 1e-10 and ev < 1e-8, (ex, ev)
+
+
+def test_single_molecule_has_no_pairs():
+    # one water in a 10 A box: the centroid list is empty; bonded, exclusion, self and
+    # reciprocal terms remain
+    s = synth.water_box(1, 4, 10.0, seed=64, cutoff=4.0, pme_grid=16, pme_order=4)
+    E_r, F_r = forces.evaluate(s.pos, s)
+    assert np.all(E_r[:, 2] == 0.0) and np.all(E_r[:, 3] == 0.0)
+    with ctx_for(s) as c:
+        E, F = c.eval(s.pos)
+        assert c.nlist().shape[0] == 0
+    assert rel_max(F, F_r) <= 1e-11
+    assert np.allclose(E, E_r, rtol=1e-11, atol=1e-9)
+    ex, ev = _trajectory(s, 3)
+    assert ex < 1e-10 and ev < 1e-8, (ex, ev)
+
+
+def test_non_finite_host_input_is_rejected_before_device_work():
+    import paper_2212_03137_amd as q
+    s = synth.water_box(8, 2, 10.0, seed=65, cutoff=4.0, pme_grid=16, pme_order=4)
+    pos = s.pos.copy()
+    pos[1, 5, 2] = np.nan
+    with ctx_for(s) as c:
+        with pytest.raises(q.QhpError) as e:
+            c.eval(pos)
+        assert e.value.code == q.ENONFINITE
+        with pytest.raises(q.QhpError) as e:
+            c.set_state(pos, s.vel, 0)
+        assert e.value.code == q.ENONFINITE
+        E, F = c.eval(s.pos)                 # the context still works
+    assert np.all(np.isfinite(F))
