@@ -838,17 +838,18 @@ __global__ __launch_bounds__((yz_threads<K, NB>())) void k_fft_yz(FftYZArgs A) {
   }
 }
 
-// K = 64, two slots: the same transforms with one (series, index) task per thread and
+// K = 64, one or two slots: the same transforms with one (series, index) task per thread and
 // each 8 x 8 step kept in registers where the data layout allows: the forward z step
 // reads the grid directly, the forward y step's second half, the product with G and the
 // inverse y step's first half run on the same registers (the eight outputs X[k1 + 8 k2]
 // of one thread are exactly the eight inputs x[8 n1 + n2], n2 = k1, of the inverse
 // step), and the last inverse z step writes the grid directly.
-__global__ __launch_bounds__(YZ_NT) void k_fft_yz64(FftYZArgs A) {
-  constexpr int K = 64, NB = 2, ROW = K * NB + NB;
+template <int NB>
+__global__ __launch_bounds__(512 * NB) void k_fft_yz64(FftYZArgs A) {
+  constexpr int K = 64, ROW = K * NB + 2;   // padded rows: conflict-free for NB = 1 and 2
   __shared__ double2 buf[K * ROW];
   __shared__ double2 stw[K];
-  const int tid = threadIdx.x, j = tid & 7, q = tid >> 3, s = q & 1, r = q >> 1;
+  const int tid = threadIdx.x, j = tid & 7, q = tid >> 3, s = q % NB, r = q / NB;
   const int groups = A.pc / NB;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int k0 = lb / groups, s0 = (lb % groups) * NB;
@@ -1020,8 +1021,8 @@ static hipError_t convolve(qhp_ctx* c, int pc, double2* grid) {
 #define YZ_CALL(KK, NBV)                                                                    \
     hipLaunchKernelGGL((k_fft_yz<KK, NBV>), blocks, (yz_threads<KK, NBV>()), 0, c->stream, A)
     if (K == 64) {
-      if (nb == 1) YZ_CALL(64, 1);
-      else hipLaunchKernelGGL(k_fft_yz64, blocks, YZ_NT, 0, c->stream, A);
+      if (nb == 1) hipLaunchKernelGGL(k_fft_yz64<1>, blocks, 512, 0, c->stream, A);
+      else hipLaunchKernelGGL(k_fft_yz64<2>, blocks, 1024, 0, c->stream, A);
     } else {
       if (nb == 1) YZ_CALL(32, 1);
       else if (nb == 2) YZ_CALL(32, 2);
