@@ -204,8 +204,8 @@ def windows_timing(q, steps=20, warmup=3):
             "sequential_ms_per_step": t_seq / steps * 1e3,
             "group_speedup_vs_sequential": t_seq / t_group,
             "bar_sample_ms": t_bar * 1e3, "steps": steps,
-            "note": "FP32 pairs (the 256-water boxes, 19.7 A, take the FP64 pair kernel: "
-                    "2 (rc + skin) exceeds their edge); BAR sample = 30 evaluations at the "
+            "note": "FP32 pairs (rc 7.8 A so that 2 (rc + skin) stays below the 19.7 A "
+                    "edge of the 256-water boxes); BAR sample = 30 evaluations at the "
                     "neighbouring couplings from host positions"}
 
 

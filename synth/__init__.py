@@ -229,14 +229,15 @@ def alchemical_window(i, n_windows=16, n_beads=None, n_waters=None):
     12-atom solute (4 triatomic fragments) in n_w = [256, 512, 1024, 2048][i % 4] waters
     with P = [8, 16, 32][i % 3]; lambda_elec = max(0, 2 lambda - 1), lambda_vdw =
     min(1, 2 lambda) (lambda = 1 fully coupled), soft-core alpha 0.5. Box edge
-    (n_w / 0.03337)^(1/3) (19.7 to 39.4 A) holding the n_w + 4 molecules, rc 9 A, alpha
-    0.35 /A, SPME order 5 on a 32^3 grid (64^3 for 2,048 waters): 0.6 to 1 A spacing."""
+    (n_w / 0.03337)^(1/3) (19.7 to 39.4 A) holding the n_w + 4 molecules, rc 7.8 A (so that
+    rc + skin stays below half the smallest edge), alpha 0.35 /A, SPME order 5 on a 32^3
+    grid (64^3 for 2,048 waters): 0.6 to 1 A spacing."""
     n_w = [256, 512, 1024, 2048][i % 4] if n_waters is None else n_waters
     P = [8, 16, 32][i % 3] if n_beads is None else n_beads
     lam = i / (n_windows - 1)
     L = (n_w / WATER_DENSITY) ** (1.0 / 3.0)
     grid = 32 if n_w <= 1024 else 64
-    s = water_box(n_w + 4, P, L, SEED_BASE + 3 + 1000 * i, cutoff=9.0, ewald_alpha=0.35,
+    s = water_box(n_w + 4, P, L, SEED_BASE + 3 + 1000 * i, cutoff=7.8, ewald_alpha=0.35,
                   pme_grid=grid, pme_order=5, solute=4, name=f"alchem{i}_w{n_w}_P{P}")
     s.lambda_elec = max(0.0, 2.0 * lam - 1.0)
     s.lambda_vdw = min(1.0, 2.0 * lam)
