@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
-# Algorithmic work per launch of each kernel class (definitions in DESIGN.md, "Roofline").
+# Algorithmic work per launch of each kernel class (the unit counts behind the roofline).
 #   pair   : FP32 flops; 30 per in-range pair-bead interaction (each pair once) and 8 per
 #            centroid-list candidate pair-bead test
 #   spread : bytes; bead positions read once + every grid value written once
@@ -245,7 +245,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
         sys.exit(2)
     import torch

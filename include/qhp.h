@@ -54,7 +54,7 @@ extern "C" {
 #define QHP_ENOMEM       -2   /* device allocation failed or a capacity was exceeded      */
 #define QHP_EDEVICE      -3   /* HIP runtime error; the HIP message is in qhp_last_error  */
 #define QHP_ENONFINITE   -4   /* non-finite input or state                                */
-#define QHP_EUNSUPPORTED -5   /* valid request this build does not implement             */
+#define QHP_EUNSUPPORTED -5   /* valid request the library does not implement            */
 
 /* memory kinds */
 #define QHP_MEM_HOST   0
@@ -160,7 +160,7 @@ typedef struct qhp_ctx qhp_ctx;
 
 /* Create a context on the current HIP device. `stream` is a hipStream_t; all work of the
  * context is queued on it (NULL: the library creates a private non-blocking stream).
- * Validates `p` (QHP_EINVAL; QHP_EUNSUPPORTED for valid settings this build does not run:
+ * Validates `p` (QHP_EINVAL; QHP_EUNSUPPORTED for valid settings the library does not run:
  * B-spline order 3 or 7, or more cells plus SPME tiles than the per-step bookkeeping block
  * holds in LDS, 2*(cells + (K0/8)(K1/8)(K2/8)) <= 24576), allocates device state
  * (QHP_ENOMEM) and precomputes the normal-mode transfer matrix, mode frequencies,

@@ -339,7 +339,7 @@ __global__ __launch_bounds__(NL_THREADS) void k_nl_build(NlArgs A) {
           d2 = d2 + dz * dz;
           keep = (j / 3 != mi) && (d2 < A.rl2);
           if (keep) {
-            // image shift of the two centroids in the frame wrapped at this build
+            // image shift of the two centroids in the frame wrapped at this list build
             const int sxi = -(int)rint((wrapped(sx[p], A.L0, A.iL0) - wx) * A.iL0);
             const int syi = -(int)rint((wrapped(sy[p], A.L1, A.iL1) - wy) * A.iL1);
             const int szi = -(int)rint((wrapped(sz[p], A.L2, A.iL2) - wz) * A.iL2);
