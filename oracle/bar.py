@@ -23,8 +23,11 @@ import numpy as np
 
 
 def fermi(x, beta):
-    """f(x) = 1 / (1 + exp(beta x)), evaluated without overflow."""
-    return 0.5 * (1.0 - np.tanh(0.5 * beta * np.asarray(x, dtype=np.float64)))
+    """f(x) = 1 / (1 + exp(beta x)), evaluated without overflow and with full relative
+    accuracy in both tails: exp(-y) / (1 + exp(-y)) for y = beta x > 0, else 1 / (1 + e^y)."""
+    y = beta * np.asarray(x, dtype=np.float64)
+    e = np.exp(-np.abs(y))
+    return np.where(y > 0, e / (1.0 + e), 1.0 / (1.0 + e))
 
 
 def bar(du_a, du_b, beta, max_iter=400):

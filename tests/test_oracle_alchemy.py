@@ -165,3 +165,33 @@ def test_pi_bar_recovers_the_ring_polymer_free_energy(P):
     du1_a, du1_b = bar.window_differences(EA_a, EB_a, EA_b, EB_b, "single")
     d1, _ = bar.bar(du1_a, du1_b, beta)
     assert d1 == pytest.approx(exact, abs=0.05 * abs(exact) + 5e-3)
+
+
+def test_fermi_identity():
+    # f(x) = f(-x) exp(-beta x), the property the estimators' derivation rests on
+    x = np.linspace(-30.0, 30.0, 601)
+    for beta in (0.3, 1.0, 1.7):
+        lhs = bar.fermi(x, beta)
+        rhs = bar.fermi(-x, beta) * np.exp(-beta * x)
+        assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-300)
+
+
+def test_estimators_under_cyclic_relabelling_of_the_beads():
+    # the bead average is invariant under a cyclic shift of the bead labels, and the
+    # single-bead estimator on bead k of shifted samples is the bead-0 estimator of the
+    # originals when the shift brings bead k to 0
+    rng = np.random.default_rng(9)
+    n, P = 400, 8
+    EA_a, EB_a = rng.normal(0, 1, (n, P)), rng.normal(0.3, 1, (n, P))
+    EA_b, EB_b = rng.normal(0.1, 1, (n, P)), rng.normal(0.2, 1, (n, P))
+    roll = lambda E, k: np.roll(E, k, axis=1)
+    d_pi, _ = bar.bar(*bar.window_differences(EA_a, EB_a, EA_b, EB_b, "pi"), 1.0)
+    d_pi3, _ = bar.bar(*bar.window_differences(roll(EA_a, 3), roll(EB_a, 3), roll(EA_b, 3),
+                                               roll(EB_b, 3), "pi"), 1.0)
+    assert d_pi == pytest.approx(d_pi3, abs=1e-12)
+    d_1, _ = bar.bar(*bar.window_differences(EA_a, EB_a, EA_b, EB_b, "single"), 1.0)
+    d_1k, _ = bar.bar(*bar.window_differences(roll(EA_a, 5), roll(EB_a, 5), roll(EA_b, 5),
+                                              roll(EB_b, 5), "single"), 1.0)
+    d_1ref, _ = bar.bar(EB_a[:, -5] - EA_a[:, -5], EB_b[:, -5] - EA_b[:, -5], 1.0)
+    assert d_1k == pytest.approx(d_1ref, abs=1e-12)
+    assert d_1 != pytest.approx(d_1k, abs=1e-6)       # a different bead: a different sample
