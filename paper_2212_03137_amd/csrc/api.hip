@@ -677,7 +677,10 @@ extern "C" int qhp_bar(const double* du_a, int64_t n_a, const double* du_b, int6
   // h falls monotonically from n_b to -n_a, so its root is unique. Newton steps on h,
   // kept inside a bracket that shrinks with every evaluation (bisection when a step
   // would leave it).
-  auto fermi = [beta](double x) { return 0.5 - 0.5 * std::tanh(0.5 * beta * x); };
+  auto fermi = [beta](double x) {                 // both tails to full relative accuracy
+    const double y = beta * x, e = std::exp(-std::fabs(y));
+    return y > 0 ? e / (1.0 + e) : 1.0 / (1.0 + e);
+  };
   auto eval = [&](double C, double& h, double& dh) {
     h = 0.0; dh = 0.0;
     for (int64_t k = 0; k < n_b; ++k) {
