@@ -111,3 +111,24 @@ def test_non_finite_host_input_is_rejected_before_device_work():
         assert e.value.code == q.ENONFINITE
         E, F = c.eval(s.pos)                 # the context still works
     assert np.all(np.isfinite(F))
+
+
+def test_microcanonical_ring_polymer_conserves_energy():
+    # no friction on any mode: BAOAB reduces to velocity Verlet in the normal modes, so
+    # H = sum_n P_n^2/2m + sum_n m w_n^2 Q_n^2 / 2 + (1/P) sum_b V(x_b) stays near its
+    # start (bounded O(dt^2) oscillation, no drift beyond the cutoff's small jumps)
+    import dataclasses
+    s = synth.water_box(64, 4, 12.42, seed=66, cutoff=6.0, pme_grid=16, pme_order=4, dt=0.25)
+    s = dataclasses.replace(s, gamma_centroid=0.0, trpmd_c=0.0)
+    hs, ks = [], []
+    with ctx_for(s) as c:
+        c.set_state(s.pos, s.vel, 0)
+        for _ in range(20):
+            E = c.step(20, energy=True)
+            k, sp = c.mode_energies()
+            hs.append(k + sp + E.sum() / s.n_beads)
+            ks.append(k)
+    hs, K = np.array(hs), float(np.mean(ks))
+    say("NVE H", hs.min(), hs.max(), "K", K)
+    assert np.max(np.abs(hs - hs[0])) <= 0.01 * K
+    assert abs(hs[-5:].mean() - hs[:5].mean()) <= 0.003 * K
