@@ -132,20 +132,28 @@ hipError_t upload_twiddles(double2** dst, int L) {
   return hipMemcpy(*dst, t.data(), L * sizeof(double2), hipMemcpyHostToDevice);
 }
 
-// Tables of the FP32 pair kernel: on QHP_PAIR_TAB equal intervals of r in [0, rc], the
-// cubic through four equally spaced points (both ends included) of the force kernel
-// (erfc(a r)/r + 2a/sqrt(pi) exp(-a^2 r^2)) / r^2 and of the energy kernel erfc(a r)/r,
-// as float4 (c0, c1, c2, c3) of c0 + c1 f + c2 f^2 + c3 f^3, f the position in the
-// interval. Accurate to ~2e-9 relative above 0.9 A (below the kernel takes the formula).
-std::vector<float4> pair_tables(double a, double rc) {
+// Tables of the FP32 pair kernel, indexed by s = r^2 so that a Coulomb-only interaction
+// needs no square root: QHP_PAIR_TAB equal intervals of s, interval k = [k, k + 1) / scale,
+// each holding the cubic through four equally spaced points (both ends included) of the
+// force kernel (erfc(a r)/r + 2a/sqrt(pi) exp(-a^2 r^2)) / r^2 and of the energy kernel
+// erfc(a r)/r, as float4 (c0, c1, c2, c3) of c0 + c1 f + c2 f^2 + c3 f^3, f the position in
+// the interval. scale = QHP_PAIR_TAB / (rc^2 (1 + 2^-18)), rounded to FP32: then
+// fl(r2 scale) < QHP_PAIR_TAB for every FP32 r2 below the FP32 rc^2, so the interval
+// index needs no clamp. FP32 evaluation is accurate to ~1.4e-6 relative from r = 1 A
+// (closer pairs take the formula) at rc = 9 A, alpha = 0.35 / A.
+float pair_table_scale(double rc) {
+  return (float)(QHP_PAIR_TAB / (rc * rc * (1.0 + std::ldexp(1.0, -18))));
+}
+
+std::vector<float4> pair_tables(double a, float scale) {
   const int n = QHP_PAIR_TAB;
-  const double h = rc / n, c2a = 2.0 * a / std::sqrt(M_PI);
+  const double h = 1.0 / (double)scale, c2a = 2.0 * a / std::sqrt(M_PI);
   std::vector<float4> t(2 * n);
   for (int which = 0; which < 2; ++which)
     for (int k = 0; k < n; ++k) {
       double y[4];
       for (int j = 0; j < 4; ++j) {
-        const double r = std::max((k + j / 3.0) * h, 0.25);
+        const double r = std::max(std::sqrt((k + j / 3.0) * h), 0.25);
         const double e = std::erfc(a * r) / r;
         y[j] = which == 0 ? (e + c2a * std::exp(-a * a * r * r)) / (r * r) : e;
       }
@@ -360,7 +368,9 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   TRY(dalloc(&c->io_a, NP3)); TRY(dalloc(&c->io_b, NP3)); TRY(dalloc(&c->g_eval, NP3));
   TRY(dalloc(&c->pg_dq, N)); TRY(dalloc(&c->pg_lj, 2 * QHP_MAX_TYPES));
   if (p->precision == QHP_FP32_PAIRS) {
-    const std::vector<float4> tab = pair_tables(p->ewald_alpha, p->cutoff);
+    c->pair_tab_scale = pair_table_scale(p->cutoff);
+    c->pair_tab_kmin = (int)std::ceil(1.0 * (double)c->pair_tab_scale);   // from r = 1 A
+    const std::vector<float4> tab = pair_tables(p->ewald_alpha, c->pair_tab_scale);
     TRY(dalloc(&c->pair_tab, tab.size()));
     TRY(hipMemcpy(c->pair_tab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice));
   }

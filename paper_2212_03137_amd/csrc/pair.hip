@@ -13,9 +13,10 @@
 // with an LJ term first, so that the LJ arithmetic runs on those pairs only.
 //
 // FP32-pair mode: the displacement is the FP64 wrapped-centroid difference plus image
-// shift, rounded once to FP32, plus the FP32 bead offsets from the centroids; distance,
-// erfc, exp and the force scalar are FP32; each lane sums forces in FP32 over one chunk
-// of neighbours, then in FP64; energies in FP64. erfc(x) = exp(-x^2) t Q(t) with
+// shift, rounded once to FP32, plus the FP32 bead offsets from the centroids; distance
+// and force scalar are FP32; each lane sums forces in FP32 over one chunk of neighbours,
+// then in FP64; energies in FP64. The screened Coulomb kernels come from cubic tables in
+// r^2; below 1 A they are evaluated directly, erfc(x) = exp(-x^2) t Q(t) with
 // t = 1/(1 + p x) (Hastings' form; p and Q fitted by gen_erfc_fit.py, relative error
 // 3e-8), sharing exp(-x^2) with the force term. The stored shift is the bead's minimum
 // image for every pair within the cutoff whenever 2 (rc + skin) < L (neighbour-list
@@ -56,7 +57,7 @@ struct PairArgs {
   const double* u; double* hu;                     // Hessian-vector product: direction, output
   int mix;                                         // HVP: also d(u . grad E)/d(q, eps, sigma)
   const float4* tab;      // FP32 pairs: force and energy kernel tables ([2][QHP_PAIR_TAB])
-  float tab_scale;        // QHP_PAIR_TAB / rc
+  float tab_scale;        // intervals per A^2 of r^2 (fl(r2 tab_scale) < QHP_PAIR_TAB in range)
   int tab_kmin;           // first interval the tables are used for (closer: the formula)
   int nblocks;            // logical blocks
   const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
@@ -242,9 +243,10 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
 // Compacted neighbours t0 + s, t0 + s + S, ... < cnt for the lane (slot s, bead b).
 // LJ = false for neighbours without an LJ term (a wavefront-uniform choice).
 // SOFT: the LJ neighbours' soft-core alpha (1 - lambda) is in sa (the k_pair64 form).
-// The screened Coulomb force and energy kernels come from cubic tables in r (stab: force,
-// stab + QHP_PAIR_TAB: energy); pairs closer than the tables' first used interval (none
-// in liquid water) take the erfc fit instead.
+// The screened Coulomb force and energy kernels come from cubic tables in r^2 (stab: force,
+// stab + QHP_PAIR_TAB: energy), so a pair without an LJ term takes no square root or
+// reciprocal; pairs closer than the tables' first used interval (1 A; none in liquid
+// water) take the erfc fit instead.
 template <int P, bool ENERGY, bool LJ, bool SOFT = false>
 QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, const float* sa,
                    const unsigned* sj, const float4* stab, int t0, int cnt, int s,
@@ -259,12 +261,11 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
     const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
     const float r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2) {
-      const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir;
-      const float u = (r2 * ir) * tscale;
-      const int k = min((int)u, QHP_PAIR_TAB - 1);
+      const float u = r2 * tscale;
+      const int k = (int)u;              // < QHP_PAIR_TAB for r2 < rc2 (see tab_scale)
       float sc;
       if (k >= kmin) {
-        const float f = u - (float)k;
+        const float f = __builtin_amdgcn_fractf(u);
         const float4 c = stab[k];
         sc = cd.w * fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
         if (ENERGY) {
@@ -272,6 +273,7 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
           ec += (double)(cd.w * fmaf(fmaf(fmaf(d.w, f, d.z), f, d.y), f, d.x));
         }
       } else {
+        const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir;
         const float x = alpha * (r2 * ir);
         const float tt = __builtin_amdgcn_rcpf(1.0f + ERFC_P * x);
         float q = ERFC_Q[7];
@@ -282,6 +284,7 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
         sc = cd.w * ir2 * ex * (tq * ir + c2a);
         if (ENERGY) ec += (double)(cd.w * tq * ex * ir);
       }
+      const float ir2 = LJ ? __builtin_amdgcn_rcpf(r2) : 0.f;
       if (LJ && SOFT) {
         const float s6 = lj.y * ir2 * ir2 * ir2;
         const float rd = __builtin_amdgcn_rcpf(1.0f + a * s6), u = s6 * rd;
@@ -295,16 +298,18 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
       fx += sc * dx; fy += sc * dy; fz += sc * dz;
     }
   };
-  // four neighbours per lane per iteration: their loads are all issued before the math
-  int t = t0 + s;
-  for (; t + 3 * S < cnt; t += 4 * S) {
+  // four neighbours per lane per iteration: their loads are all issued before the math;
+  // the trip count is the same for every lane (a scalar loop), the remainder follows
+  int tt = t0;
+  for (; tt + 4 * S <= cnt; tt += 4 * S) {
+    const int t = tt + s;
     const float4 o0 = load(t), o1 = load(t + S), o2 = load(t + 2 * S), o3 = load(t + 3 * S);
     interact(scd[t], o0, slj[t], SOFT ? sa[t] : 0.f);
     interact(scd[t + S], o1, slj[t + S], SOFT ? sa[t + S] : 0.f);
     interact(scd[t + 2 * S], o2, slj[t + 2 * S], SOFT ? sa[t + 2 * S] : 0.f);
     interact(scd[t + 3 * S], o3, slj[t + 3 * S], SOFT ? sa[t + 3 * S] : 0.f);
   }
-  for (; t < cnt; t += S) interact(scd[t], load(t), slj[t], SOFT ? sa[t] : 0.f);
+  for (int t = tt + s; t < cnt; t += S) interact(scd[t], load(t), slj[t], SOFT ? sa[t] : 0.f);
 }
 
 template <int P, bool ENERGY, bool SOFT = false>
@@ -430,8 +435,8 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   for (int a = 0; a < c->p.n_types; ++a) A.eps_of[a] = c->eps[a];
   A.dq = c->pg_dq; A.deps = c->pg_lj; A.dsig = c->pg_lj + QHP_MAX_TYPES;
   A.tab = c->pair_tab;
-  A.tab_scale = (float)(QHP_PAIR_TAB / c->p.cutoff);
-  A.tab_kmin = (int)ceil(0.75 * QHP_PAIR_TAB / c->p.cutoff);   // tables from r = 0.75 A
+  A.tab_scale = c->pair_tab_scale;
+  A.tab_kmin = c->pair_tab_kmin;
 
   A.energy = plain ? c->energy + (size_t)bead * QHP_NTERMS : B.energy;
   A.ctrl = c->ctrl;

@@ -175,9 +175,11 @@ struct qhp_ctx {
   double* pa_tmp = nullptr;   // [3][N][P] scratch momenta
   double* g_eval = nullptr;   // [3][N][P] gradient target of qhp_eval
 
-  // parameter gradients of the summed bead energies
   float4* pair_tab = nullptr; // FP32 pairs: [2][QHP_PAIR_TAB] cubic pieces of the screened
-                              // Coulomb force and energy kernels over [0, rc]
+                              // Coulomb force and energy kernels over r^2 in [0, rc^2]
+  float pair_tab_scale = 0.f; // intervals per A^2 (maps rc^2 just below QHP_PAIR_TAB)
+  int pair_tab_kmin = 0;      // first interval the tables serve (closer pairs: the formula)
+  // parameter gradients of the summed bead energies
   double* pg_dq = nullptr;    // [N] d/d charge
   double* pg_lj = nullptr;    // [2][QHP_MAX_TYPES] d/d epsilon, d/d sigma per type
   double* hvp_out = nullptr;  // [3][N][P] Hessian-vector product (allocated on use)
