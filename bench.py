@@ -28,7 +28,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 #   pair   : FP32 flops; 30 per in-range pair-bead interaction (each pair once) and 8 per
 #            centroid-list candidate pair-bead test
 #   spread : bytes; bead positions read once + every grid value written once
-#   fft    : bytes; the complex grid read and written once by each of the 5 passes
+#   fft    : bytes; the grid read once and written once for the whole forward transform,
+#            influence-function product and inverse transform (the kernels make three
+#            read + write passes, so the achieved figure is against that minimum)
 #   gather : bytes; grid read once + positions read + gradient read and written
 #   nm     : bytes; Q, P, grad V read, Q, P, x and the FP32 offsets written
 FLOPS_PER_PAIR = 30.0
@@ -107,12 +109,36 @@ def algorithmic_work(cls, s, counts):
     if cls == "spread":
         return "bytes", xb + grid
     if cls == "fft":
-        return "bytes", 5 * 2 * grid
+        return "bytes", 2 * grid
     if cls == "gather":
         return "bytes", grid + xb + 2 * xb
     if cls == "nm":
         return "bytes", 6 * xb + N * P * 16
     raise ValueError(cls)
+
+
+def phase_rooflines(s, per_class, counts, ms_step):
+    """Each timed kernel class against its own roofline (algorithmic work per step / its
+    measured time per step), and the step's roofline time: the sum over the classes of
+    work / peak, against the measured step."""
+    phases, t_roof = {}, 0.0
+    for cl, ms in per_class.items():
+        kind, work = algorithmic_work(cl, s, counts)
+        sec = ms * 1e-3
+        if kind == "bytes":
+            ach, peak, unit, bound = work / sec / 1e9, HBM_PEAK_GBS, "GB/s", "hbm"
+            t_roof += work / (HBM_PEAK_GBS * 1e9)
+        else:
+            ach, peak, unit, bound = (work / sec / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s",
+                                      "alu")
+            t_roof += work / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
+        phases[cl] = {"bound": bound, "ms_per_step": ms, "work": work,
+                      "work_unit": "bytes" if kind == "bytes" else "flops",
+                      "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak}
+    step = {"t_roof_ms": t_roof * 1e3, "t_measured_ms": ms_step, "frac": t_roof * 1e3 / ms_step,
+            "note": "roofline time of the five kernel classes (list, bonded and set-up kernels "
+                    "carry little algorithmic work) against the whole measured step"}
+    return phases, step
 
 
 def force_loss_timing(q, qa, n_configs=8):
@@ -363,6 +389,8 @@ def main():
         "roofline": roof,
         "breakdown_ms_per_step": per_class,
     }
+    out["phase_rooflines"], out["step_roofline"] = phase_rooflines(s, per_class, counts,
+                                                                   ms_step)
 
     if not args.no_compare:
         comp = {}

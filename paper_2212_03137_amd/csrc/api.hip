@@ -119,6 +119,11 @@ void free_all(qhp_ctx* c) {
   c->step_exec = nullptr;
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   c->stream = nullptr;
+  if (c->side) (void)hipStreamDestroy(c->side);
+  c->side = nullptr;
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  c->ev_fork = c->ev_join = nullptr;
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   c->ev_pool.clear();
   c->ev_pending.clear();
@@ -283,6 +288,15 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
       return QHP_EDEVICE;
     }
     c->own_stream = true;
+  }
+  if (p->exec != QHP_PLAIN) {
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      free_all(c);
+      delete c;
+      return QHP_EDEVICE;
+    }
   }
   c->use_graph = p->use_graph != 0;
   const int N = p->n_atoms, P = p->n_beads;
@@ -531,14 +545,39 @@ static int fast_forces(qhp_ctx* c, bool energy) {
   return QHP_OK;
 }
 
+// Bonded (initialises grad V of the bead set), real space and SPME of a bead set after
+// the list stage. The SPME spread and transforms depend only on the positions and the
+// tile bins of the list stage, so they run on the side stream while the bonded and pair
+// kernels run on the main stream; the gather, which adds into grad V, follows both. When
+// kernel classes are being timed one at a time, and inside a group's captured step (whose
+// members are already concurrent branches), everything stays on the main stream.
+static int batched_forces(qhp_ctx* c, bool energy, const BeadSet* bs) {
+  if (!c->side || c->serial_forces || c->prof_which != QHP_PROF_OFF) {
+    QHP_HIP(c, launch_bonded(c, energy, -1, bs));
+    QHP_HIP(c, launch_pair(c, energy, -1, bs));
+    QHP_HIP(c, launch_spme(c, energy, -1, bs));
+    return QHP_OK;
+  }
+  QHP_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+  QHP_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  const hipStream_t main = c->stream;
+  c->stream = c->side;               // the launchers queue on c->stream
+  hipError_t e = launch_spme(c, energy, -1, bs, SPME_FRONT);
+  if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side);
+  c->stream = main;
+  QHP_HIP(c, e);
+  QHP_HIP(c, launch_bonded(c, energy, -1, bs));
+  QHP_HIP(c, launch_pair(c, energy, -1, bs));
+  QHP_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  QHP_HIP(c, launch_spme(c, energy, -1, bs, SPME_GATHER));
+  return QHP_OK;
+}
+
 // V_s (exclusion correction, real space, SPME) on the contracted beads: initialises c->gs
 static int slow_forces(qhp_ctx* c, bool energy, bool from_step) {
   QHP_HIP(c, launch_nlist(c, from_step));
   BeadSet sl{c->Ps, c->Ps == 1 ? 1 : c->Ps / 2, c->xs, c->gs, c->xfs, c->energy, QHP_TERMS_EXCL};
-  QHP_HIP(c, launch_bonded(c, energy, -1, &sl));
-  QHP_HIP(c, launch_pair(c, energy, -1, &sl));
-  QHP_HIP(c, launch_spme(c, energy, -1, &sl));
-  return QHP_OK;
+  return batched_forces(c, energy, &sl);
 }
 
 // Bonded + exclusion (initialise grad V), centroid pair list, real space, SPME.
@@ -550,12 +589,9 @@ int forces_all(qhp_ctx* c, bool energy, bool from_step) {
       QHP_HIP(c, launch_pair(c, energy, b));
       QHP_HIP(c, launch_spme(c, energy, b));
     }
-  } else {
-    QHP_HIP(c, launch_bonded(c, energy, -1));
-    QHP_HIP(c, launch_pair(c, energy, -1));
-    QHP_HIP(c, launch_spme(c, energy, -1));
+    return QHP_OK;
   }
-  return QHP_OK;
+  return batched_forces(c, energy, nullptr);
 }
 
 static int copy_in(qhp_ctx* c, const double* src, int mem_kind, double* dst_internal) {
@@ -1238,7 +1274,9 @@ static int group_capture(qhp_group* g) {
   e = hipEventRecord(g->ev[0], s0);
   for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(g->m[i]->stream, g->ev[0], 0);
   for (int i = 0; i < n && e == hipSuccess && r == QHP_OK; ++i) {
+    g->m[i]->serial_forces = true;
     r = one_step(g->m[i], false);
+    g->m[i]->serial_forces = false;
     if (r) why = "member " + std::to_string(i) + ": " + g->m[i]->err;
   }
   for (int i = 1; i < n && e == hipSuccess && r == QHP_OK; ++i) {

@@ -80,6 +80,12 @@ struct qhp_ctx {
   int N, P, NW, Pc;           // atoms, beads, waters, complex grid batch
   hipStream_t stream;
   bool own_stream = false;    // created here because the caller passed none
+  // second stream of the bead-batched force evaluation (default priority): the SPME
+  // spread and transforms run on it, concurrent with the bonded and real-space kernels
+  // on `stream`, forked from and joined back to `stream` by the two events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool serial_forces = false; // set while a group captures the member's step: no side branch
   hipGraphExec_t step_exec = nullptr;   // one captured (outer) MD step (no energies)
   bool use_graph = true;
   std::string err;
@@ -248,7 +254,11 @@ hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu, bool mix);
 // (nullptr: the full ring polymer of the context)
 hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);
 hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);
-hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);
+// part: SPME_FRONT (tile binning of the plain layout, spread, transforms and influence
+// function), SPME_GATHER (forces into grad V, energies), or both
+enum { SPME_FRONT = 1, SPME_GATHER = 2, SPME_ALL = 3 };
+hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr,
+                       int part = SPME_ALL);
 BeadSet full_beads(qhp_ctx* c);
 hipError_t launch_noise_export(qhp_ctx* c, int stream, int64_t step, double* out);
 

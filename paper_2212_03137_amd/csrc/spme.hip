@@ -1039,7 +1039,7 @@ static hipError_t convolve(qhp_ctx* c, int pc, double2* grid) {
   return fft_pass(c, 0, 1, pc, grid);
 }
 
-hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
+hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int part) {
   const bool plain = bead >= 0;
   const BeadSet B = bs ? *bs : full_beads(c);
   const int P = plain ? 1 : B.P;
@@ -1057,63 +1057,66 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   const bool pg = !plain && B.pgrad;
   const unsigned nb = (unsigned)(((size_t)N * P + NT - 1) / NT);
   hipEvent_t ev = nullptr;
-  prof_begin(c, QHP_PROF_SPREAD, &ev);
-  {
-    TileArgs T;
-    T.N = N; T.P = P; T.K0 = c->K[0]; T.K1 = c->K[1]; T.K2 = c->K[2];
-    T.nt0 = c->K[0] / TB; T.nt1 = c->K[1] / TB; T.nt2 = c->K[2] / TB; T.order = c->p.pme_order;
-    T.x = A.x; T.cent = plain ? nullptr : c->cent;
-    for (int d = 0; d < 3; ++d) { T.L[d] = c->p.box[d]; T.KoL[d] = c->K[d] / c->p.box[d]; }
-    T.tile_of = c->tile_of; T.tile_count = c->tile_count; T.tile_fill = c->tile_fill;
-    T.tile_start = c->tile_start; T.tile_atoms = c->tile_atoms; T.ntiles = c->ntiles;
-    if (plain) {   // batched: the prep kernel of the neighbour-list stage has binned the atoms
-      hipLaunchKernelGGL(k_tile_bin, (N + 255) / 256, 256, 0, c->stream, T);
-      hipLaunchKernelGGL(k_tile_scan, 1, 256, 0, c->stream, T);
-      hipLaunchKernelGGL(k_tile_scatter, (N + 255) / 256, 256, 0, c->stream, T);
-    }
-    TSpreadArgs S;
-    S.N = N; S.P = P; S.K0 = c->K[0]; S.K1 = c->K[1]; S.K2 = c->K[2];
-    S.nt1 = T.nt1; S.nt2 = T.nt2; S.Pc2 = 2 * pc;
-    S.x = A.x; S.grid = A.grid; S.charge = c->d_charge;
-    S.cent = plain ? nullptr : c->cent;
-    S.ctrl = c->ctrl;
-    for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
-    S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms;
-    // block shape: gb beads, z tiles along z (at most 16 x 8^3 points of LDS)
-    int gb = c->spread_gb > 0 ? c->spread_gb : 8;
-    if (gb > P) gb = P;
-    int z = c->spread_z > 0 ? c->spread_z : 1;
-    if (z > S.nt2) z = S.nt2;
-    while (z * gb > 16) z >>= 1;
-    const dim3 grid(c->ntiles / z, P / gb);
+  if (part & SPME_FRONT) {
+    prof_begin(c, QHP_PROF_SPREAD, &ev);
+    {
+      TileArgs T;
+      T.N = N; T.P = P; T.K0 = c->K[0]; T.K1 = c->K[1]; T.K2 = c->K[2];
+      T.nt0 = c->K[0] / TB; T.nt1 = c->K[1] / TB; T.nt2 = c->K[2] / TB; T.order = c->p.pme_order;
+      T.x = A.x; T.cent = plain ? nullptr : c->cent;
+      for (int d = 0; d < 3; ++d) { T.L[d] = c->p.box[d]; T.KoL[d] = c->K[d] / c->p.box[d]; }
+      T.tile_of = c->tile_of; T.tile_count = c->tile_count; T.tile_fill = c->tile_fill;
+      T.tile_start = c->tile_start; T.tile_atoms = c->tile_atoms; T.ntiles = c->ntiles;
+      if (plain) {   // batched: the prep kernel of the neighbour-list stage has binned the atoms
+        hipLaunchKernelGGL(k_tile_bin, (N + 255) / 256, 256, 0, c->stream, T);
+        hipLaunchKernelGGL(k_tile_scan, 1, 256, 0, c->stream, T);
+        hipLaunchKernelGGL(k_tile_scatter, (N + 255) / 256, 256, 0, c->stream, T);
+      }
+      TSpreadArgs S;
+      S.N = N; S.P = P; S.K0 = c->K[0]; S.K1 = c->K[1]; S.K2 = c->K[2];
+      S.nt1 = T.nt1; S.nt2 = T.nt2; S.Pc2 = 2 * pc;
+      S.x = A.x; S.grid = A.grid; S.charge = c->d_charge;
+      S.cent = plain ? nullptr : c->cent;
+      S.ctrl = c->ctrl;
+      for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
+      S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms;
+      // block shape: gb beads, z tiles along z (at most 16 x 8^3 points of LDS)
+      int gb = c->spread_gb > 0 ? c->spread_gb : 8;
+      if (gb > P) gb = P;
+      int z = c->spread_z > 0 ? c->spread_z : 1;
+      if (z > S.nt2) z = S.nt2;
+      while (z * gb > 16) z >>= 1;
+      const dim3 grid(c->ntiles / z, P / gb);
 #define SPREAD_CALL(GBV, ZV)                                                                 \
-    QHP_SWITCH_ORDER(c->p.pme_order, hipLaunchKernelGGL((k_spread_tiles<OO, GBV, false, ZV>),  \
-                                                        grid, NT, 0, c->stream, S))
-    switch (gb * 16 + z) {
-      case 16 + 1: SPREAD_CALL(1, 1); break;
-      case 16 + 2: SPREAD_CALL(1, 2); break;
-      case 16 + 4: SPREAD_CALL(1, 4); break;
-      case 16 + 8: SPREAD_CALL(1, 8); break;
-      case 32 + 1: SPREAD_CALL(2, 1); break;
-      case 32 + 2: SPREAD_CALL(2, 2); break;
-      case 32 + 4: SPREAD_CALL(2, 4); break;
-      case 32 + 8: SPREAD_CALL(2, 8); break;
-      case 64 + 1: SPREAD_CALL(4, 1); break;
-      case 64 + 2: SPREAD_CALL(4, 2); break;
-      case 64 + 4: SPREAD_CALL(4, 4); break;
-      case 128 + 1: SPREAD_CALL(8, 1); break;
-      case 128 + 2: SPREAD_CALL(8, 2); break;
-      case 256 + 1: SPREAD_CALL(16, 1); break;
-      default: return hipErrorInvalidValue;
-    }
+      QHP_SWITCH_ORDER(c->p.pme_order, hipLaunchKernelGGL((k_spread_tiles<OO, GBV, false, ZV>),  \
+                                                          grid, NT, 0, c->stream, S))
+      switch (gb * 16 + z) {
+        case 16 + 1: SPREAD_CALL(1, 1); break;
+        case 16 + 2: SPREAD_CALL(1, 2); break;
+        case 16 + 4: SPREAD_CALL(1, 4); break;
+        case 16 + 8: SPREAD_CALL(1, 8); break;
+        case 32 + 1: SPREAD_CALL(2, 1); break;
+        case 32 + 2: SPREAD_CALL(2, 2); break;
+        case 32 + 4: SPREAD_CALL(2, 4); break;
+        case 32 + 8: SPREAD_CALL(2, 8); break;
+        case 64 + 1: SPREAD_CALL(4, 1); break;
+        case 64 + 2: SPREAD_CALL(4, 2); break;
+        case 64 + 4: SPREAD_CALL(4, 4); break;
+        case 128 + 1: SPREAD_CALL(8, 1); break;
+        case 128 + 2: SPREAD_CALL(8, 2); break;
+        case 256 + 1: SPREAD_CALL(16, 1); break;
+        default: return hipErrorInvalidValue;
+      }
 #undef SPREAD_CALL
+    }
+    prof_end(c, QHP_PROF_SPREAD, ev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    prof_begin(c, QHP_PROF_FFT, &ev);
+    if ((e = convolve(c, pc, c->grid)) != hipSuccess) return e;
+    prof_end(c, QHP_PROF_FFT, ev);
   }
-  prof_end(c, QHP_PROF_SPREAD, ev);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  prof_begin(c, QHP_PROF_FFT, &ev);
-  if ((e = convolve(c, pc, c->grid)) != hipSuccess) return e;
-  prof_end(c, QHP_PROF_FFT, ev);
+  if (!(part & SPME_GATHER)) return hipGetLastError();
   prof_begin(c, QHP_PROF_GATHER, &ev);
   A.nblocks = (int)nb;
   const unsigned nb8 = (nb + 7) / 8 * 8;
