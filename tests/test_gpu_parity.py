@@ -232,6 +232,34 @@ def test_large_box_forces_on_sampled_beads(large, precision):
             assert rel_rms(F[b], -g) <= 1e-5
 
 
+def test_large_box_timed_path_step_matches_the_oracle(large):
+    """One step of the path the benchmark times (FP32 pairs, autotuned launch shapes, the
+    step captured as a graph with the SPME spread and transforms on the second stream)
+    against one step of the FP64 oracle's integrator with the same Philox noise. The FP32
+    pair forces (<= 1e-5 relative RMS) enter through the two half kicks: positions move by
+    dt^2/2m of the force error, velocities by dt/m."""
+    import paper_2212_03137_amd as q
+    from oracle import rpmd
+    s = large
+    say("large timed-path step: oracle")
+    R = rpmd.RPMD(s.n_beads, s.mass, s.kT, s.hbar, s.dt, s.gamma_centroid, s.trpmd_c, s.seed,
+                  oracle_grad_fn(s))
+    R.set_state(s.pos, s.vel)
+    R.step(1)
+    xr, vr, _ = R.get_state()
+    say("large timed-path step: GPU")
+    with ctx_for(s, precision=q.FP32_PAIRS) as c:
+        c.set_state(s.pos, s.vel, 0)
+        shapes = c.autotune(3)
+        c.step(1)
+        x, v, st = c.get_state()
+    say("autotuned", shapes)
+    assert st == 1
+    assert np.abs(x - xr).max() <= 1e-7 * np.abs(xr).max()
+    assert rel_rms(v, vr) <= 1e-5
+    assert rel_max(v, vr) <= 1e-4
+
+
 def test_large_box_step_stays_finite_and_rebuilds(large):
     import paper_2212_03137_amd as q
     s = large
