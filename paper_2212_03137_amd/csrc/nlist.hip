@@ -222,7 +222,20 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
 #pragma unroll
   for (int k = 0; k < PREP_REG; ++k)
     if (i0 + k < i1) atomicAdd(&tcount[reg[k]], 1);
-  for (int i = i0 + PREP_REG; i < i1; ++i) atomicAdd(&tcount[B.tile_of[i]], 1);
+  // beyond the registers' atoms (large systems): the bins are loaded PREP_REG at a time,
+  // all loads of a batch issued before its atomics
+  auto batched = [&](const int* bin_of, auto&& use) {
+    for (int i = i0 + PREP_REG; i < i1; i += PREP_REG) {
+      int r[PREP_REG];
+#pragma unroll
+      for (int k = 0; k < PREP_REG; ++k)
+        if (i + k < i1) r[k] = bin_of[i + k];
+#pragma unroll
+      for (int k = 0; k < PREP_REG; ++k)
+        if (i + k < i1) use(i + k, r[k]);
+    }
+  };
+  if (spill) batched(B.tile_of, [&](int, int t) { atomicAdd(&tcount[t], 1); });
   __syncthreads();
   // exclusive scan of a count array of length n by the block (per-thread chunks)
   auto scan = [&](const int* cnt, int* start_g, int* fill, int n) {
@@ -241,7 +254,7 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
   for (int k = 0; k < PREP_REG; ++k)
     if (i0 + k < i1) B.tile_atoms[atomicAdd(&tfill[reg[k]], 1)] = i0 + k;
   if (spill)
-    for (int i = i0 + PREP_REG; i < i1; ++i) B.tile_atoms[atomicAdd(&tfill[B.tile_of[i]], 1)] = i;
+    batched(B.tile_of, [&](int i, int t) { B.tile_atoms[atomicAdd(&tfill[t], 1)] = i; });
   // ---- 3. centroid cells of a rebuild ----
   // (the cell of each centroid was written with it; the build kernel records the frame)
   if (!go) return;
@@ -252,14 +265,14 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
 #pragma unroll
   for (int k = 0; k < PREP_REG; ++k)
     if (i0 + k < i1) cell_bin(i0 + k, reg[k]);
-  for (int i = i0 + PREP_REG; i < i1; ++i) cell_bin(i, A.cell_of[i]);
+  if (spill) batched(A.cell_of, cell_bin);
   __syncthreads();
   scan(ccount, A.cell_start, cfill, A.ncell);
 #pragma unroll
   for (int k = 0; k < PREP_REG; ++k)
     if (i0 + k < i1) A.cell_atoms[atomicAdd(&cfill[reg[k]], 1)] = i0 + k;
   if (spill)
-    for (int i = i0 + PREP_REG; i < i1; ++i) A.cell_atoms[atomicAdd(&cfill[A.cell_of[i]], 1)] = i;
+    batched(A.cell_of, [&](int i, int t) { A.cell_atoms[atomicAdd(&cfill[t], 1)] = i; });
 }
 
 // One block per cell, NL_THREADS / 64 wavefronts sharing the cell's atoms. Also records

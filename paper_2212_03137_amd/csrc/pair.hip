@@ -256,7 +256,11 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
   const char* xf = reinterpret_cast<const char*>(A.xf);
   const float tscale = A.tab_scale;
   const int kmin = A.tab_kmin;
-  auto load = [&](int t) { return *reinterpret_cast<const float4*>(xf + (sj[t] + boff)); };
+  // one bead: the bead is its centroid and its stored offset is exactly zero
+  auto load = [&](int t) {
+    if constexpr (P == 1) return make_float4(0.f, 0.f, 0.f, 0.f);
+    else return *reinterpret_cast<const float4*>(xf + (sj[t] + boff));
+  };
   auto interact = [&](const float4 cd, const float4 oj, const float2 lj, const float a) {
     const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
     const float r2 = dx * dx + dy * dy + dz * dz;
@@ -342,14 +346,18 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
   const int nn = A.nnbr[i];
   const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
+  // list entries of the next chunk are loaded while the current one is processed
+  unsigned e_next = lane < nn ? (unsigned)row[lane] : 0u;
   for (int k0 = 0; k0 < nn; k0 += 64) {
     bool keep = false, haslj = false;
     float4 cdv;
     float2 ljv;
     float av = 0.f;
     unsigned jp = 0;
+    const unsigned e_cur = e_next;
+    if (k0 + 64 + lane < nn) e_next = (unsigned)row[k0 + 64 + lane];
     if (k0 + lane < nn) {
-      const unsigned e = (unsigned)row[k0 + lane];
+      const unsigned e = e_cur;
       const int j = e & 0x3FFFFFF;
       const double4 cj = A.cwrap[j];
       const float cx = (float)((cj.x - ci.x) + A.L[0] * (double)((int)((e >> 26) & 3) - 1));
