@@ -60,6 +60,29 @@ def pair_list(centroids, box, r_list, n_per_mol=3):
     return np.stack([I[order], J[order]], axis=1).astype(np.int64)
 
 
+def pair_list_rows(centroids, box, r_list, rows, n_per_mol=3):
+    """The pairs of ``pair_list`` that involve any atom of ``rows`` (sorted (i, j), i < j),
+    by the same canonical arithmetic (d = c_j - c_i for i < j), for sampled checks of
+    large systems."""
+    N = len(centroids)
+    mol = np.arange(N) // n_per_mol
+    r2max = r_list * r_list
+    inv = 1.0 / box
+    out = set()
+    for a in np.unique(np.asarray(rows, dtype=np.int64)):
+        j = np.arange(N)
+        lo = np.minimum(a, j)
+        hi = np.maximum(a, j)
+        d = centroids[hi] - centroids[lo]
+        d = d - box * np.rint(d * inv)
+        d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]
+        d2 = d2 + d[:, 2] * d[:, 2]
+        keep = (d2 < r2max) & (mol != mol[a]) & (j != a)
+        out.update(zip(lo[keep].tolist(), hi[keep].tolist()))
+    P = np.array(sorted(out), dtype=np.int64).reshape(-1, 2)
+    return P
+
+
 def centroids_of(pos):
     """Centroid of each atom's beads: beads summed in bead order, then divided by P."""
     c = pos[0].copy()

@@ -161,6 +161,37 @@ QHP_DEV int block_exclusive_scan(int v, int* swave, int* total) {
   return before + x - v;
 }
 
+// Bin counting and scattering by a whole wavefront whose lanes hold consecutive atoms
+// (bin t, or -1 for no atom): neighbouring atoms mostly share a bin, so each run of equal
+// bins takes one LDS atomic, issued by its first lane, instead of one per lane to the
+// same address. Every lane of the wavefront must take part.
+struct WaveRuns {
+  unsigned long long starts;   // lanes where a run begins
+  int lane, head, len;         // this lane's run: first lane and length (at the first lane)
+};
+QHP_DEV WaveRuns wave_runs(int t) {
+  WaveRuns w;
+  w.lane = threadIdx.x & 63;
+  const int prev = __shfl_up(t, 1);
+  w.starts = __ballot(w.lane == 0 || prev != t);
+  const unsigned long long upto = w.lane == 63 ? ~0ull : ((2ull << w.lane) - 1ull);
+  w.head = 63 - __clzll(w.starts & upto);
+  const unsigned long long after = w.lane == 63 ? 0ull : (w.starts >> (w.lane + 1));
+  w.len = (after ? w.lane + 1 + __ffsll((long long)after) - 1 : 64) - w.lane;
+  return w;
+}
+QHP_DEV void wave_count(int* cnt, int t) {
+  const WaveRuns w = wave_runs(t);
+  if (t >= 0 && w.head == w.lane) atomicAdd(&cnt[t], w.len);
+}
+QHP_DEV void wave_scatter(int* fill, int* out, int t, int atom) {
+  const WaveRuns w = wave_runs(t);
+  int b = 0;
+  if (t >= 0 && w.head == w.lane) b = atomicAdd(&fill[t], w.len);
+  b = __shfl(b, w.head);
+  if (t >= 0) out[b + (w.lane - w.head)] = atom;
+}
+
 QHP_DEV double wave_fmax(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -208,34 +239,40 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
     if (b) { c->n_builds += 1; c->max_count = 0; }
     go = b;
   }
-  // Each thread bins a contiguous run of atoms: neighbouring lanes then hold atoms a few
-  // molecules apart, which mostly fall in different bins (fewer same-address LDS atomics),
-  // and the bins of the first PREP_REG atoms stay in registers for the scatter.
+  // Up to PREP_REG atoms per thread, each thread bins a contiguous run of atoms:
+  // neighbouring lanes then hold atoms a few molecules apart, which mostly fall in
+  // different bins (fewer same-address LDS atomics), and the bins stay in registers for
+  // the scatter. Larger systems are binned with a strided map instead (atom tid + k nt),
+  // PREP_REG loads in flight per thread: a wavefront's loads then read two contiguous
+  // cache lines rather than 64 (this block runs on one compute unit).
   const int per = (A.N + nt - 1) / nt;
   const int i0 = min(A.N, tid * per), i1 = min(A.N, i0 + per);
-  const bool spill = per > PREP_REG;
-  // ---- 2. SPME tiles (each centroid's tile was written with the centroid) ----
-  int reg[PREP_REG];
-#pragma unroll
-  for (int k = 0; k < PREP_REG; ++k)
-    if (i0 + k < i1) reg[k] = B.tile_of[i0 + k];
-#pragma unroll
-  for (int k = 0; k < PREP_REG; ++k)
-    if (i0 + k < i1) atomicAdd(&tcount[reg[k]], 1);
-  // beyond the registers' atoms (large systems): the bins are loaded PREP_REG at a time,
-  // all loads of a batch issued before its atomics
-  auto batched = [&](const int* bin_of, auto&& use) {
-    for (int i = i0 + PREP_REG; i < i1; i += PREP_REG) {
+  const bool strided = per > PREP_REG;
+  // (all threads run every iteration: the wavefront-wide run aggregation needs them)
+  auto each_strided = [&](const int* bin_of, auto&& use) {
+    for (int base = 0; base < A.N; base += nt * PREP_REG) {
       int r[PREP_REG];
 #pragma unroll
-      for (int k = 0; k < PREP_REG; ++k)
-        if (i + k < i1) r[k] = bin_of[i + k];
+      for (int k = 0; k < PREP_REG; ++k) {
+        const int i = base + k * nt + tid;
+        r[k] = i < A.N ? bin_of[i] : -1;
+      }
 #pragma unroll
-      for (int k = 0; k < PREP_REG; ++k)
-        if (i + k < i1) use(i + k, r[k]);
+      for (int k = 0; k < PREP_REG; ++k) use(base + k * nt + tid, r[k]);
     }
   };
-  if (spill) batched(B.tile_of, [&](int, int t) { atomicAdd(&tcount[t], 1); });
+  // ---- 2. SPME tiles (each centroid's tile was written with the centroid) ----
+  int reg[PREP_REG];
+  if (strided) {
+    each_strided(B.tile_of, [&](int, int t) { wave_count(tcount, t); });
+  } else {
+#pragma unroll
+    for (int k = 0; k < PREP_REG; ++k)
+      if (i0 + k < i1) reg[k] = B.tile_of[i0 + k];
+#pragma unroll
+    for (int k = 0; k < PREP_REG; ++k)
+      if (i0 + k < i1) atomicAdd(&tcount[reg[k]], 1);
+  }
   __syncthreads();
   // exclusive scan of a count array of length n by the block (per-thread chunks)
   auto scan = [&](const int* cnt, int* start_g, int* fill, int n) {
@@ -250,29 +287,35 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
     __syncthreads();
   };
   scan(tcount, B.tile_start, tfill, B.ntiles);
+  if (strided) {
+    each_strided(B.tile_of, [&](int i, int t) { wave_scatter(tfill, B.tile_atoms, t, i); });
+  } else {
 #pragma unroll
-  for (int k = 0; k < PREP_REG; ++k)
-    if (i0 + k < i1) B.tile_atoms[atomicAdd(&tfill[reg[k]], 1)] = i0 + k;
-  if (spill)
-    batched(B.tile_of, [&](int i, int t) { B.tile_atoms[atomicAdd(&tfill[t], 1)] = i; });
+    for (int k = 0; k < PREP_REG; ++k)
+      if (i0 + k < i1) B.tile_atoms[atomicAdd(&tfill[reg[k]], 1)] = i0 + k;
+  }
   // ---- 3. centroid cells of a rebuild ----
   // (the cell of each centroid was written with it; the build kernel records the frame)
   if (!go) return;
-  auto cell_bin = [&](int i, int id) { atomicAdd(&ccount[id], 1); };
+  if (strided) {
+    each_strided(A.cell_of, [&](int, int id) { wave_count(ccount, id); });
+  } else {
 #pragma unroll
-  for (int k = 0; k < PREP_REG; ++k)
-    if (i0 + k < i1) reg[k] = A.cell_of[i0 + k];
+    for (int k = 0; k < PREP_REG; ++k)
+      if (i0 + k < i1) reg[k] = A.cell_of[i0 + k];
 #pragma unroll
-  for (int k = 0; k < PREP_REG; ++k)
-    if (i0 + k < i1) cell_bin(i0 + k, reg[k]);
-  if (spill) batched(A.cell_of, cell_bin);
+    for (int k = 0; k < PREP_REG; ++k)
+      if (i0 + k < i1) atomicAdd(&ccount[reg[k]], 1);
+  }
   __syncthreads();
   scan(ccount, A.cell_start, cfill, A.ncell);
+  if (strided) {
+    each_strided(A.cell_of, [&](int i, int t) { wave_scatter(cfill, A.cell_atoms, t, i); });
+  } else {
 #pragma unroll
-  for (int k = 0; k < PREP_REG; ++k)
-    if (i0 + k < i1) A.cell_atoms[atomicAdd(&cfill[reg[k]], 1)] = i0 + k;
-  if (spill)
-    batched(A.cell_of, [&](int i, int t) { A.cell_atoms[atomicAdd(&cfill[t], 1)] = i; });
+    for (int k = 0; k < PREP_REG; ++k)
+      if (i0 + k < i1) A.cell_atoms[atomicAdd(&cfill[reg[k]], 1)] = i0 + k;
+  }
 }
 
 // One block per cell, NL_THREADS / 64 wavefronts sharing the cell's atoms. Also records

@@ -346,8 +346,21 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
   const int nn = A.nnbr[i];
   const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
-  // list entries of the next chunk are loaded while the current one is processed
+  // list entries of the next chunk are loaded while the current one is processed; with
+  // one bead (a chunk is one interaction per lane) also the next chunk's centroid
+  // records, charges and types, and the list entries two chunks ahead
   unsigned e_next = lane < nn ? (unsigned)row[lane] : 0u;
+  double4 cj_n = make_double4(0.0, 0.0, 0.0, 0.0);
+  double qj_n = 0.0;
+  int tj_n = 0;
+  unsigned e_nn = 0u;
+  if constexpr (P == 1) {
+    if (lane < nn) {
+      const int j = e_next & 0x3FFFFFF;
+      cj_n = A.cwrap[j]; qj_n = A.charge[j]; tj_n = A.type[j];
+    }
+    if (64 + lane < nn) e_nn = (unsigned)row[64 + lane];
+  }
   for (int k0 = 0; k0 < nn; k0 += 64) {
     bool keep = false, haslj = false;
     float4 cdv;
@@ -355,18 +368,31 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
     float av = 0.f;
     unsigned jp = 0;
     const unsigned e_cur = e_next;
-    if (k0 + 64 + lane < nn) e_next = (unsigned)row[k0 + 64 + lane];
+    double4 cj_p = cj_n;
+    double qj_p = qj_n;
+    int tj_p = tj_n;
+    if constexpr (P == 1) {
+      e_next = e_nn;
+      if (k0 + 64 + lane < nn) {
+        const int jn = e_next & 0x3FFFFFF;
+        cj_n = A.cwrap[jn]; qj_n = A.charge[jn]; tj_n = A.type[jn];
+      }
+      if (k0 + 128 + lane < nn) e_nn = (unsigned)row[k0 + 128 + lane];
+    } else if (k0 + 64 + lane < nn) {
+      e_next = (unsigned)row[k0 + 64 + lane];
+    }
     if (k0 + lane < nn) {
       const unsigned e = e_cur;
       const int j = e & 0x3FFFFFF;
-      const double4 cj = A.cwrap[j];
+      if constexpr (P != 1) { cj_p = A.cwrap[j]; qj_p = A.charge[j]; tj_p = A.type[j]; }
+      const double4 cj = cj_p;
       const float cx = (float)((cj.x - ci.x) + A.L[0] * (double)((int)((e >> 26) & 3) - 1));
       const float cy = (float)((cj.y - ci.y) + A.L[1] * (double)((int)((e >> 28) & 3) - 1));
       const float cz = (float)((cj.z - ci.z) + A.L[2] * (double)((int)((e >> 30) & 3) - 1));
       const float reach = (float)(reach_i + cj.w);
       keep = cx * cx + cy * cy + cz * cz < reach * reach;
-      cdv = make_float4(cx, cy, cz, (float)(qi * A.charge[j]));
-      const int tp = ti * A.ntypes + A.type[j];
+      cdv = make_float4(cx, cy, cz, (float)(qi * qj_p));
+      const int tp = ti * A.ntypes + tj_p;
       ljv = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
       if (SOFT) av = (float)A.lj_a[tp];
       haslj = ljv.x != 0.f;

@@ -6,11 +6,9 @@ import numpy as np
 import pytest
 
 import synth
-from helpers import has_gpu, rel_max
-from oracle import forces as ofo
+from helpers import has_gpu, oracle_forces_on, rel_max
 from oracle import philox as oph
 from oracle import qtb as oq
-from oracle import spme as osp
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not has_gpu(), reason="needs a HIP device")]
@@ -21,28 +19,6 @@ def box():
     return synth.adqtb_box()
 
 
-def _oracle_forces_on(s, x, sample):
-    """-grad V at the sampled atoms: all real-space partners of the sample by brute force,
-    full intramolecular, exclusion and SPME terms."""
-    N = len(x)
-    mol = np.arange(N) // 3
-    I, J = [], []
-    for i in sample:
-        j = np.arange(N)
-        j = j[(mol[j] != mol[i]) & (j != i)]
-        I.append(np.full(len(j), i)); J.append(j)
-    I = np.concatenate(I); J = np.concatenate(J)
-    both = np.isin(J, sample)
-    keep = ~both | (I < J)
-    pairs = np.stack([I[keep], J[keep]], axis=1)
-    _, _, g_rs = ofo.real_space(x, pairs, s.charge, s.types, s.lj_sigma, s.lj_epsilon, s.box,
-                                s.ewald_alpha, s.cutoff, s.coulomb)
-    _, _, g_in = ofo.intramolecular(x, s.box, s.bond_r0, s.bond_k, s.angle_theta0, s.angle_k)
-    _, g_x = ofo.excluded_correction(x, s.charge, s.box, s.ewald_alpha, s.coulomb)
-    e_r, g_r = osp.spme(x, s.charge, s.box, s.pme_grid, s.pme_order, s.ewald_alpha, s.coulomb)
-    return -(g_rs + g_in + g_x + g_r)[sample], e_r
-
-
 def test_full_box_forces_noise_and_steps(box):
     import paper_2212_03137_amd as q
     s = box
@@ -51,7 +27,7 @@ def test_full_box_forces_noise_and_steps(box):
     sample = np.sort(rng.choice(s.n_atoms, 48, replace=False))
     with q.Context.from_system(s, thermostat=q.ADQTB, precision=q.FP32_PAIRS) as c:
         E, F = c.eval(s.pos)
-        Fref, e_rec = _oracle_forces_on(s, s.pos[0], sample)
+        Fref, e_rec = oracle_forces_on(s, s.pos[0], sample)
         assert np.sqrt(np.mean((F[0, sample] - Fref) ** 2)) / np.sqrt(np.mean(Fref ** 2)) <= 1e-5
         assert abs(E[0, 6] - e_rec) <= 1e-11 * abs(e_rec)
         c.set_state(s.pos, s.vel, 0)
@@ -79,6 +55,6 @@ def test_full_box_fp64_forces(box):
     sample = np.sort(rng.choice(s.n_atoms, 32, replace=False))
     with q.Context.from_system(s, thermostat=q.ADQTB, precision=q.FP64) as c:
         E, F = c.eval(s.pos)
-    Fref, _ = _oracle_forces_on(s, s.pos[0], sample)
+    Fref, _ = oracle_forces_on(s, s.pos[0], sample)
     scale = np.sqrt(np.mean(Fref ** 2))
     assert np.abs(F[0, sample] - Fref).max() / scale <= 1e-11

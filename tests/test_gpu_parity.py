@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import synth
-from helpers import has_gpu, medium_box, oracle_grad_fn, rel_max, rel_rms
+from helpers import has_gpu, medium_box, oracle_forces_on, oracle_grad_fn, rel_max, rel_rms
 from oracle import forces as ofo
 from oracle import philox as oph
 
@@ -63,6 +63,31 @@ def test_neighbour_list_bit_exact(n_w, L, P, rc):
         got = c.nlist()
     ref = ofo.pair_list(ofo.centroids_of(s.pos), s.box, s.cutoff + s.skin)
     assert got.shape == ref.shape and np.array_equal(got, ref)
+
+
+def test_list_and_forces_of_a_system_past_the_register_binning():
+    # 6,000 waters = 18,000 atoms: more than 16 atoms per thread of the one-block
+    # bookkeeping kernel, which then bins SPME tiles and list cells with its strided,
+    # run-aggregated path; the list rows of 300 sampled atoms are compared bit for bit
+    # with the oracle's (the full brute-force list takes the oracle minutes), the forces
+    # (which use the tiles) at both beads
+    s = synth.water_box(6000, 2, 56.4, seed=6000, cutoff=9.0, pme_grid=32, pme_order=4)
+    say("strided binning", s.n_atoms)
+    with ctx_for(s) as c:
+        E, F = c.eval(s.pos)
+        got = c.nlist()
+    cen = ofo.centroids_of(s.pos)
+    rows = np.random.default_rng(7).choice(s.n_atoms, 300, replace=False)
+    ref = ofo.pair_list_rows(cen, s.box, s.cutoff + s.skin, rows)
+    mine = got[np.isin(got[:, 0], rows) | np.isin(got[:, 1], rows)]
+    assert np.array_equal(mine, ref)
+    assert np.all(got[:, 0] < got[:, 1])
+    assert np.all(np.diff(got[:, 0] * s.n_atoms + got[:, 1]) > 0)
+    sample = np.sort(np.random.default_rng(8).choice(s.n_atoms, 32, replace=False))
+    for b in range(2):
+        Fref, e_rec = oracle_forces_on(s, s.pos[b], sample)
+        assert rel_max(F[b, sample], Fref) <= 1e-11
+        assert abs(E[b, 6] - e_rec) <= 1e-11 * abs(e_rec)
 
 
 # ---------------------------------------------------------------------------- forces

@@ -33,6 +33,17 @@ def test_pair_list_equals_kdtree(n_w, L, r):
     assert np.array_equal(mine, ref)
 
 
+@pytest.mark.parametrize("n_w,L,r", [(216, 18.7, 7.5), (343, 21.8, 11.0)])
+def test_pair_list_rows_are_the_kdtree_pairs_of_the_rows(n_w, L, r):
+    # the sampled variant against the k-d tree's pairs that involve the sampled atoms
+    s = synth.water_box(n_w, 4, L, seed=n_w + 1)
+    c = fo.centroids_of(s.pos)
+    rows = np.random.default_rng(n_w).choice(len(c), 40, replace=False)
+    ref = _kdtree_pairs(c, L, r)
+    ref = ref[np.isin(ref[:, 0], rows) | np.isin(ref[:, 1], rows)]
+    assert np.array_equal(fo.pair_list_rows(c, s.box, r, rows), ref)
+
+
 def _fd_check(energy_fn, grad, x, atoms, h=1e-5, rtol=1e-6, atol=1e-7):
     for a in atoms:
         for d in range(3):
