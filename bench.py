@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of graphs")
     ap.add_argument("--windows", action="store_true",
                     help="only the 16-window free-energy workload (one JSON line)")
+    ap.add_argument("--adqtb", action="store_true",
+                    help="only the 21,952-water adQTB workload (one JSON line)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for hardware counters: a 256 MiB device copy (calibration), then "
                          "--steps launched steps of the batched FP32-pair path; no JSON")
@@ -341,6 +343,9 @@ def main():
     if args.windows:
         print(json.dumps({"alchemical_windows": windows_timing(q, steps=max(1, args.steps),
                                                                warmup=args.warmup)}))
+        return
+    if args.adqtb:
+        print(json.dumps({"adqtb_box": adqtb_timing(q, stream)}))
         return
 
     if args.pmc_probe:
