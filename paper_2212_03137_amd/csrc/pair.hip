@@ -240,6 +240,66 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
   }
 }
 
+// Constants of the FP32 interaction, set once per atom.
+struct Pair32K {
+  float4 oi;              // the lane's bead offset from atom i's centroid
+  float rc2, tscale, alpha, kexp, c2a;
+  int kmin;
+  const float4* stab;     // the block's kernel tables
+};
+
+// One pair at the lane's bead: cd = FP32 centroid difference and q_i q_j C, oj = atom j's
+// bead offset, lj = (4 eps_ij, sigma_ij^6), a = soft-core alpha (1 - lambda); adds the
+// force on atom i to (fx, fy, fz) and the energies to ec, elj.
+template <bool ENERGY, bool LJ, bool SOFT>
+QHP_DEV void interact32(const Pair32K& K, const float4 cd, const float4 oj, const float2 lj,
+                        const float a, float& fx, float& fy, float& fz, double& ec,
+                        double& elj) {
+  const float4 oi = K.oi;
+  const float rc2 = K.rc2, tscale = K.tscale, alpha = K.alpha, kexp = K.kexp, c2a = K.c2a;
+  const int kmin = K.kmin;
+  const float4* stab = K.stab;
+  const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  if (r2 < rc2) {
+    const float u = r2 * tscale;
+    const int k = (int)u;              // < QHP_PAIR_TAB for r2 < rc2 (see tab_scale)
+    float sc;
+    if (k >= kmin) {
+      const float f = __builtin_amdgcn_fractf(u);
+      const float4 c = stab[k];
+      sc = cd.w * fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
+      if (ENERGY) {
+        const float4 d = stab[QHP_PAIR_TAB + k];
+        ec += (double)(cd.w * fmaf(fmaf(fmaf(d.w, f, d.z), f, d.y), f, d.x));
+      }
+    } else {
+      const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir;
+      const float x = alpha * (r2 * ir);
+      const float tt = __builtin_amdgcn_rcpf(1.0f + ERFC_P * x);
+      float q = ERFC_Q[7];
+#pragma unroll
+      for (int m = 6; m >= 0; --m) q = q * tt + ERFC_Q[m];
+      const float ex = __builtin_amdgcn_exp2f(kexp * r2);     // exp(-alpha^2 r^2)
+      const float tq = tt * q;                                 // erfc(alpha r) / ex
+      sc = cd.w * ir2 * ex * (tq * ir + c2a);
+      if (ENERGY) ec += (double)(cd.w * tq * ex * ir);
+    }
+    const float ir2 = LJ ? __builtin_amdgcn_rcpf(r2) : 0.f;
+    if (LJ && SOFT) {
+      const float s6 = lj.y * ir2 * ir2 * ir2;
+      const float rd = __builtin_amdgcn_rcpf(1.0f + a * s6), u = s6 * rd;
+      sc += 6.f * lj.x * u * (2.f * u - 1.f) * rd * ir2;
+      if (ENERGY) elj += (double)(lj.x * (u * u - u));
+    } else if (LJ) {
+      const float s6 = lj.y * ir2 * ir2 * ir2;
+      sc += lj.x * (12.f * s6 * s6 - 6.f * s6) * ir2;
+      if (ENERGY) elj += (double)(lj.x * (s6 * s6 - s6));
+    }
+    fx += sc * dx; fy += sc * dy; fz += sc * dz;
+  }
+}
+
 // Compacted neighbours t0 + s, t0 + s + S, ... < cnt for the lane (slot s, bead b).
 // LJ = false for neighbours without an LJ term (a wavefront-uniform choice).
 // SOFT: the LJ neighbours' soft-core alpha (1 - lambda) is in sa (the k_pair64 form).
@@ -261,46 +321,9 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
     if constexpr (P == 1) return make_float4(0.f, 0.f, 0.f, 0.f);
     else return *reinterpret_cast<const float4*>(xf + (sj[t] + boff));
   };
+  const Pair32K K{oi, rc2, tscale, alpha, kexp, c2a, kmin, stab};
   auto interact = [&](const float4 cd, const float4 oj, const float2 lj, const float a) {
-    const float dx = cd.x + (oj.x - oi.x), dy = cd.y + (oj.y - oi.y), dz = cd.z + (oj.z - oi.z);
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < rc2) {
-      const float u = r2 * tscale;
-      const int k = (int)u;              // < QHP_PAIR_TAB for r2 < rc2 (see tab_scale)
-      float sc;
-      if (k >= kmin) {
-        const float f = __builtin_amdgcn_fractf(u);
-        const float4 c = stab[k];
-        sc = cd.w * fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
-        if (ENERGY) {
-          const float4 d = stab[QHP_PAIR_TAB + k];
-          ec += (double)(cd.w * fmaf(fmaf(fmaf(d.w, f, d.z), f, d.y), f, d.x));
-        }
-      } else {
-        const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir;
-        const float x = alpha * (r2 * ir);
-        const float tt = __builtin_amdgcn_rcpf(1.0f + ERFC_P * x);
-        float q = ERFC_Q[7];
-#pragma unroll
-        for (int m = 6; m >= 0; --m) q = q * tt + ERFC_Q[m];
-        const float ex = __builtin_amdgcn_exp2f(kexp * r2);     // exp(-alpha^2 r^2)
-        const float tq = tt * q;                                 // erfc(alpha r) / ex
-        sc = cd.w * ir2 * ex * (tq * ir + c2a);
-        if (ENERGY) ec += (double)(cd.w * tq * ex * ir);
-      }
-      const float ir2 = LJ ? __builtin_amdgcn_rcpf(r2) : 0.f;
-      if (LJ && SOFT) {
-        const float s6 = lj.y * ir2 * ir2 * ir2;
-        const float rd = __builtin_amdgcn_rcpf(1.0f + a * s6), u = s6 * rd;
-        sc += 6.f * lj.x * u * (2.f * u - 1.f) * rd * ir2;
-        if (ENERGY) elj += (double)(lj.x * (u * u - u));
-      } else if (LJ) {
-        const float s6 = lj.y * ir2 * ir2 * ir2;
-        sc += lj.x * (12.f * s6 * s6 - 6.f * s6) * ir2;
-        if (ENERGY) elj += (double)(lj.x * (s6 * s6 - s6));
-      }
-      fx += sc * dx; fy += sc * dy; fz += sc * dz;
-    }
+    interact32<ENERGY, LJ, SOFT>(K, cd, oj, lj, a, fx, fy, fz, ec, elj);
   };
   // four neighbours per lane per iteration: their loads are all issued before the math;
   // the trip count is the same for every lane (a scalar loop), the remainder follows
@@ -397,6 +420,18 @@ __global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
       if (SOFT) av = (float)A.lj_a[tp];
       haslj = ljv.x != 0.f;
       jp = (unsigned)j * (unsigned)(P * sizeof(float4));
+    }
+    if constexpr (P == 1) {
+      // one bead: a lane's decoded entry is its only interaction in the chunk, so it is
+      // evaluated in place (no staging; the LJ term of a pair without LJ is zero)
+      float fx = 0.f, fy = 0.f, fz = 0.f;
+      if (keep) {
+        const Pair32K K{oi, rc2, A.tab_scale, alpha, kexp, c2a, A.tab_kmin, stab};
+        interact32<ENERGY, true, SOFT>(K, cdv, make_float4(0.f, 0.f, 0.f, 0.f), ljv, av,
+                                       fx, fy, fz, ec, elj);
+      }
+      gx += (double)fx; gy += (double)fy; gz += (double)fz;
+      continue;
     }
     // compaction with the LJ pairs first: [0, nlj) carry LJ, [nlj, cnt) do not
     const unsigned long long bl = __ballot(keep && haslj), bn = __ballot(keep && !haslj);

@@ -82,6 +82,23 @@ def test_classical_single_bead_eval_and_trajectory():
     assert ex < 1e-10 and ev < 1e-8, (ex, ev)
 
 
+def test_classical_single_bead_fp32_pairs():
+    # one bead, FP32 pairs (343 waters, 21.7 A: 2 (rc + skin) < L): the kernel evaluates
+    # each lane's list entry in place; the bar of the FP32-pair mode against the oracle
+    from helpers import medium_box
+    import paper_2212_03137_amd as q
+    s = medium_box(P=1)
+    E_r, F_r = forces.evaluate(s.pos, s)
+    with ctx_for(s, precision=q.FP32_PAIRS) as c:
+        E, F = c.eval(s.pos)
+        c.set_state(s.pos, s.vel, 0)
+        c.step(20)
+        x, _, st = c.get_state()
+    assert rel_rms(F, F_r) <= 1e-5
+    assert np.allclose(E, E_r, rtol=1e-5, atol=1e-4 * np.abs(E_r).max())
+    assert st == 20 and np.all(np.isfinite(x))
+
+
 def test_single_molecule_has_no_pairs():
     # one water in a 10 A box: the centroid list is empty; bonded, exclusion, self and
     # reciprocal terms remain
