@@ -18,6 +18,9 @@
 namespace {
 
 constexpr int NT = 256;
+// the segment kernels hold one or two whole transforms in LDS (64-128 KB), so a compute
+// unit runs one or two of their blocks: 1,024 threads keep 4-8 wavefronts per SIMD
+constexpr int NT_SEG = 1024;
 
 QHP_DEV double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -117,7 +120,7 @@ struct GenArgs {
 };
 
 // one block per (atom, slot): slot 0 carries x + i y, slot 1 carries z
-__global__ __launch_bounds__(NT) void k_qtb_generate(GenArgs A) {
+__global__ __launch_bounds__(NT_SEG) void k_qtb_generate(GenArgs A) {
   extern __shared__ double2 lds[];
   const int a = blockIdx.x >> 1, slot = blockIdx.x & 1;
   const int Ns = A.nseg, L4 = 4 * Ns;
@@ -166,7 +169,7 @@ struct SpecArgs {
   int ratio;
 };
 
-__global__ __launch_bounds__(NT) void k_qtb_spectra(SpecArgs A) {
+__global__ __launch_bounds__(NT_SEG) void k_qtb_spectra(SpecArgs A) {
   extern __shared__ double2 lds[];
   const int Ns = A.nseg, L2 = 2 * Ns;
   double2* u = lds;
@@ -275,7 +278,7 @@ hipError_t launch_qtb_generate(qhp_ctx* c, int64_t seg) {
   A.N = c->N; A.nseg = q.nseg; A.seed = c->p.seed; A.seg = seg; A.type = c->d_type;
   A.hhat = q.hhat; A.tw4 = q.tw4; A.noise = q.noise;
   const size_t lds = (size_t)8 * q.nseg * sizeof(double2);
-  hipLaunchKernelGGL(k_qtb_generate, 2 * c->N, NT, lds, c->stream, A);
+  hipLaunchKernelGGL(k_qtb_generate, 2 * c->N, NT_SEG, lds, c->stream, A);
   return hipGetLastError();
 }
 
@@ -290,7 +293,7 @@ hipError_t launch_qtb_adapt(qhp_ctx* c) {
   const int nb = (3 * c->N + A.dofs_per_block - 1) / A.dofs_per_block;
   const size_t lds = (size_t)4 * q.nseg * sizeof(double2) +
                      (size_t)(A.ratio ? 3 : 1) * c->p.n_types * (q.nseg + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_qtb_spectra, nb, NT, lds, c->stream, A);
+  hipLaunchKernelGGL(k_qtb_spectra, nb, NT_SEG, lds, c->stream, A);
   AdaptArgs D;
   D.n = c->p.n_types * (q.nseg + 1); D.nseg = q.nseg; D.ratio = A.ratio;
   D.gamma = q.gamma; D.dsum = q.dsum; D.dbar = q.dbar; D.vvsum = q.vvsum; D.vfsum = q.vfsum;
