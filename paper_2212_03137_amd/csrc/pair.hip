@@ -10,7 +10,9 @@
 // bead lanes then read it from there, so the per-pair FP64 work is not repeated per bead.
 // The decode drops pairs whose centroids are further apart than rc plus both atoms'
 // largest bead-centroid distances (no bead can then be in range) and stores the pairs
-// with an LJ term first, so that the LJ arithmetic runs on those pairs only.
+// with an LJ term first, so that the LJ arithmetic runs on those pairs only. With one
+// bead (64 slots, one interaction per lane per chunk) there is nothing to share: each
+// lane evaluates its own decoded entry in place.
 //
 // FP32-pair mode: the displacement is the FP64 wrapped-centroid difference plus image
 // shift, rounded once to FP32, plus the FP32 bead offsets from the centroids; distance
