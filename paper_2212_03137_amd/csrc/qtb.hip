@@ -119,39 +119,51 @@ struct GenArgs {
   double* noise;          // [nseg][3][N]
 };
 
-// one block per (atom, slot): slot 0 carries x + i y, slot 1 carries z
+// One block per atom: the window's white noise is drawn once (each Philox counter gives
+// the x, y and z Gaussians), then x + i y and z + 0 i are convolved with the type's
+// kernel in turn, in the same two LDS buffers; the z samples wait in a third array.
 __global__ __launch_bounds__(NT_SEG) void k_qtb_generate(GenArgs A) {
   extern __shared__ double2 lds[];
-  const int a = blockIdx.x >> 1, slot = blockIdx.x & 1;
+  const int a = blockIdx.x;
   const int Ns = A.nseg, L4 = 4 * Ns;
   double2* u = lds;
   double2* v = lds + L4;
+  double* zs = reinterpret_cast<double*>(lds + 2 * L4);   // [3 Ns]
   const uint64_t c0 = (uint64_t)(A.seg * Ns);   // counter of window sample 0
   for (int l = threadIdx.x; l < L4; l += blockDim.x) {
     double2 w = make_double2(0.0, 0.0);
     if (l < 3 * Ns) {
       double gs[3];
       qhp::gauss3(A.seed, qhp::STREAM_QTB_WHITE, c0 + (uint64_t)l, (uint64_t)a, 0ull, gs);
-      w = slot == 0 ? make_double2(gs[0], gs[1]) : make_double2(gs[2], 0.0);
+      w = make_double2(gs[0], gs[1]);
+      zs[l] = gs[2];
     }
     u[l] = w;
   }
   __syncthreads();
-  double2* W = fft_rt(u, v, L4, false, A.tw4);
   const double2* Hz = A.hhat + (size_t)A.type[a] * L4;
-  for (int l = threadIdx.x; l < L4; l += blockDim.x) W[l] = cmul(W[l], Hz[l]);
-  __syncthreads();
-  double2* other = (W == u) ? v : u;
-  double2* C = fft_rt(W, other, L4, true, A.tw4);
   const double inv = 1.0 / L4;
-  for (int t = threadIdx.x; t < Ns; t += blockDim.x) {
-    const double2 f = C[Ns + t];
-    if (slot == 0) {
-      A.noise[((size_t)t * 3 + 0) * A.N + a] = f.x * inv;
-      A.noise[((size_t)t * 3 + 1) * A.N + a] = f.y * inv;
-    } else {
-      A.noise[((size_t)t * 3 + 2) * A.N + a] = f.x * inv;
+  for (int slot = 0; slot < 2; ++slot) {
+    if (slot == 1) {
+      for (int l = threadIdx.x; l < L4; l += blockDim.x)
+        u[l] = l < 3 * Ns ? make_double2(zs[l], 0.0) : make_double2(0.0, 0.0);
+      __syncthreads();
     }
+    double2* W = fft_rt(u, v, L4, false, A.tw4);
+    for (int l = threadIdx.x; l < L4; l += blockDim.x) W[l] = cmul(W[l], Hz[l]);
+    __syncthreads();
+    double2* other = (W == u) ? v : u;
+    double2* C = fft_rt(W, other, L4, true, A.tw4);
+    for (int t = threadIdx.x; t < Ns; t += blockDim.x) {
+      const double2 f = C[Ns + t];
+      if (slot == 0) {
+        A.noise[((size_t)t * 3 + 0) * A.N + a] = f.x * inv;
+        A.noise[((size_t)t * 3 + 1) * A.N + a] = f.y * inv;
+      } else {
+        A.noise[((size_t)t * 3 + 2) * A.N + a] = f.x * inv;
+      }
+    }
+    __syncthreads();                  // C is read before u is refilled
   }
 }
 
@@ -277,8 +289,9 @@ hipError_t launch_qtb_generate(qhp_ctx* c, int64_t seg) {
   GenArgs A;
   A.N = c->N; A.nseg = q.nseg; A.seed = c->p.seed; A.seg = seg; A.type = c->d_type;
   A.hhat = q.hhat; A.tw4 = q.tw4; A.noise = q.noise;
-  const size_t lds = (size_t)8 * q.nseg * sizeof(double2);
-  hipLaunchKernelGGL(k_qtb_generate, 2 * c->N, NT_SEG, lds, c->stream, A);
+  // two transforms of 4 N_seg points and the window's z samples: 152 KB at N_seg = 1024
+  const size_t lds = (size_t)8 * q.nseg * sizeof(double2) + (size_t)3 * q.nseg * sizeof(double);
+  hipLaunchKernelGGL(k_qtb_generate, c->N, NT_SEG, lds, c->stream, A);
   return hipGetLastError();
 }
 
