@@ -154,6 +154,14 @@ typedef struct qhp_params {
   double lambda_elec;       /* in [0, 1]; 1 = fully coupled                               */
   double lambda_vdw;        /* in [0, 1]; 1 = fully coupled                               */
   double sc_alpha;          /* soft-core alpha >= 0 (0.5 in the free-energy workload)    */
+  /* Test-only harmonic tether (statistical checks against the closed-form P-bead
+   * harmonic oscillator of Sec. "Path Integrals and Ring Polymer Molecular Dynamics"):
+   * V += (k_h / 2) |x_b - a|^2 for every atom at every bead b, a = the atom's anchor;
+   * its energy is added to the bond term and its force to grad V. 0 = off. Not
+   * available with RESPA / contraction, parameter gradients or Hessian-vector products
+   * (QHP_EUNSUPPORTED). */
+  double tether_k;          /* k_h >= 0, kcal/mol/A^2                                     */
+  const double* tether_anchor; /* [N][3] anchors (host, copied at creation) when k_h > 0  */
 } qhp_params;
 
 typedef struct qhp_ctx qhp_ctx;

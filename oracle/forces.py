@@ -223,6 +223,14 @@ def bead_potential(x, s, pairs):
     return E, g_in + g_rs + g_x + g_r
 
 
+def tether(x, anchor, k):
+    """Test-only harmonic tether of one bead (not part of the paper's potential; it turns
+    free atoms into the harmonic oscillators of the closed-form checks): V = (k/2) sum over
+    atoms of |x - a|^2, the plain Cartesian difference. -> (energy, grad [N][3])."""
+    d = x - anchor
+    return 0.5 * k * float(np.sum(d * d)), k * d
+
+
 def evaluate(pos, s, r_list=None):
     """Energies [P][7] and forces -grad V [P][N][3] of every bead, pair list built on the
     centroids of ``pos`` with r_list = cutoff + skin (or the given r_list)."""
@@ -232,8 +240,13 @@ def evaluate(pos, s, r_list=None):
     P = pos.shape[0]
     E = np.zeros((P, len(TERMS)))
     F = np.zeros_like(pos)
+    k = getattr(s, "tether_k", 0.0)
     for b in range(P):
         E[b], g = bead_potential(pos[b], s, pairs)
+        if k:
+            e_t, g_t = tether(pos[b], s.tether_anchor, k)
+            E[b, 0] += e_t
+            g = g + g_t
         F[b] = -g
     return E, F
 

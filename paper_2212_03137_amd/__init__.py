@@ -60,6 +60,7 @@ class Params(C.Structure):
         ("integrator", C.c_int32), ("qtb_adapt_scheme", C.c_int32), ("qtb_tau", C.c_double),
         ("type_soft", C.POINTER(C.c_int32)), ("lambda_elec", C.c_double),
         ("lambda_vdw", C.c_double), ("sc_alpha", C.c_double),
+        ("tether_k", C.c_double), ("tether_anchor", C.POINTER(C.c_double)),
     ]
 
 
@@ -132,7 +133,7 @@ class Context:
                  qtb_nseg=1024, qtb_adapt_rate=0.0, qtb_gamma_min_frac=0.01, qtb_classical=False,
                  nbr_capacity=0, use_graph=True, rpc_beads=0, respa_nalt=1, integrator=0,
                  qtb_adapt_scheme=0, qtb_tau=0.0, type_soft=None, lambda_elec=1.0,
-                 lambda_vdw=1.0, sc_alpha=0.5, stream=None):
+                 lambda_vdw=1.0, sc_alpha=0.5, tether_k=0.0, tether_anchor=None, stream=None):
         self._lib = load()
         self.N, self.P = int(n_atoms), int(n_beads)
         self.n_types = len(lj_sigma)
@@ -169,6 +170,10 @@ class Context:
             self._keep.append(np.ascontiguousarray(type_soft, dtype=np.int32))
             p.type_soft = self._keep[-1].ctypes.data_as(C.POINTER(C.c_int32))
             p.lambda_elec, p.lambda_vdw, p.sc_alpha = lambda_elec, lambda_vdw, sc_alpha
+        p.tether_k = float(tether_k)
+        if tether_anchor is not None:
+            self._keep.append(np.ascontiguousarray(tether_anchor, dtype=np.float64))
+            p.tether_anchor = self._keep[-1].ctypes.data_as(C.POINTER(C.c_double))
         self.params = p
         h = C.c_void_p()
         rc = self._lib.qhp_create(C.byref(p), C.c_void_p(stream) if stream else None, C.byref(h))
@@ -191,6 +196,8 @@ class Context:
         if getattr(s, "type_soft", None) is not None:
             args.update(type_soft=s.type_soft, lambda_elec=s.lambda_elec,
                         lambda_vdw=s.lambda_vdw, sc_alpha=s.sc_alpha)
+        if getattr(s, "tether_k", 0.0):
+            args.update(tether_k=s.tether_k, tether_anchor=s.tether_anchor)
         args.update(kw)
         return cls(**args)
 

@@ -108,7 +108,7 @@ void free_all(qhp_ctx* c) {
                   c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
                   c->nnbr, c->bmax, c->grid, c->grid2, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
                   c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->pg_dq, c->pg_lj, c->pair_tab,
-                  c->hvp_out, c->d_charge_alt,
+                  c->hvp_out, c->d_charge_alt, c->d_anchor,
                   c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.vvsum, c->qtb.vfsum,
                   c->qtb.avg_vv, c->qtb.avg_vf, c->qtb.d_tmass, c->qtb.d_inv_count,
@@ -236,6 +236,17 @@ int validate(const qhp_params* p, std::string& why) {
     const int na = p->respa_nalt > 0 ? p->respa_nalt : 1;
     if ((ps < p->n_beads || na > 1) && (p->exec != QHP_BATCHED || p->thermostat != QHP_TRPMD)) {
       why = "ring-polymer contraction and RESPA need exec = QHP_BATCHED and thermostat = QHP_TRPMD";
+      return QHP_EUNSUPPORTED;
+    }
+  }
+  if (!(p->tether_k >= 0) || !std::isfinite(p->tether_k)) return bad("tether_k must be >= 0");
+  if (p->tether_k > 0) {
+    if (!p->tether_anchor) return bad("tether_k > 0 needs tether_anchor");
+    for (int i = 0; i < 3 * p->n_atoms; ++i)
+      if (!std::isfinite(p->tether_anchor[i])) return bad("tether_anchor must be finite");
+    const int ps = p->rpc_beads > 0 ? p->rpc_beads : p->n_beads;
+    if (ps < p->n_beads || p->respa_nalt > 1) {
+      why = "the tether is not available with ring-polymer contraction or RESPA";
       return QHP_EUNSUPPORTED;
     }
   }
@@ -389,6 +400,14 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     TRY(hipMemcpy(c->pair_tab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice));
   }
   TRY(dalloc(&c->energy, (size_t)P * QHP_NTERMS));
+  if (p->tether_k > 0) {           // anchors [N][3] -> [3][N]
+    std::vector<double> an((size_t)3 * N);
+    for (int i = 0; i < N; ++i)
+      for (int d = 0; d < 3; ++d) an[(size_t)d * N + i] = p->tether_anchor[3 * i + d];
+    c->tether_k = p->tether_k;
+    TRY(dalloc(&c->d_anchor, an.size()));
+    TRY(hipMemcpy(c->d_anchor, an.data(), an.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   // ---- multiple time stepping / ring-polymer contraction ----
   c->Ps = p->rpc_beads > 0 ? p->rpc_beads : P;
   c->nalt = p->respa_nalt > 0 ? p->respa_nalt : 1;
@@ -554,6 +573,7 @@ static int fast_forces(qhp_ctx* c, bool energy) {
 static int batched_forces(qhp_ctx* c, bool energy, const BeadSet* bs) {
   if (!c->side || c->serial_forces || c->prof_which != QHP_PROF_OFF) {
     QHP_HIP(c, launch_bonded(c, energy, -1, bs));
+    QHP_HIP(c, launch_tether(c, energy, -1, bs));
     QHP_HIP(c, launch_pair(c, energy, -1, bs));
     QHP_HIP(c, launch_spme(c, energy, -1, bs));
     return QHP_OK;
@@ -567,6 +587,7 @@ static int batched_forces(qhp_ctx* c, bool energy, const BeadSet* bs) {
   c->stream = main;
   QHP_HIP(c, e);
   QHP_HIP(c, launch_bonded(c, energy, -1, bs));
+  QHP_HIP(c, launch_tether(c, energy, -1, bs));
   QHP_HIP(c, launch_pair(c, energy, -1, bs));
   QHP_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   QHP_HIP(c, launch_spme(c, energy, -1, bs, SPME_GATHER));
@@ -586,6 +607,7 @@ int forces_all(qhp_ctx* c, bool energy, bool from_step) {
   if (c->p.exec == QHP_PLAIN) {
     for (int b = 0; b < c->P; ++b) {
       QHP_HIP(c, launch_bonded(c, energy, b));
+      QHP_HIP(c, launch_tether(c, energy, b));
       QHP_HIP(c, launch_pair(c, energy, b));
       QHP_HIP(c, launch_spme(c, energy, b));
     }
@@ -855,6 +877,8 @@ extern "C" int qhp_param_grad(qhp_ctx* c, const double* pos, double* dq, double*
     return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients need exec = QHP_BATCHED");
   if (c->alch)
     return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients of an alchemical system");
+  if (c->tether_k > 0)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients with the test tether");
   int r = copy_in(c, pos, mem_kind, c->x);
   if (r) return r;
   QHP_HIP(c, launch_centroid_of_beads(c));
@@ -892,6 +916,8 @@ extern "C" int qhp_hvp(qhp_ctx* c, const double* pos, const double* dir, double*
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products need exec = QHP_BATCHED");
   if (c->alch)
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products of an alchemical system");
+  if (c->tether_k > 0)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products with the test tether");
   const size_t n = (size_t)c->P * c->N * 3;
   if (!c->hvp_out) QHP_HIP(c, hipMalloc((void**)&c->hvp_out, n * sizeof(double)));
   int r = copy_in(c, dir, mem_kind, c->io_b);

@@ -261,6 +261,39 @@ __global__ void k_zero(double* p, size_t n) {
     default: return hipErrorInvalidValue;              \
   }
 
+// Test-only harmonic tether of every atom at every bead: grad V += k (x - a), and with
+// energies k/2 |x - a|^2 added to the bead's bond term. x, g: [3][N][P] (one bead of the
+// plain layout: P = 1 on the bead's slices); a: [3][N].
+__global__ __launch_bounds__(256) void k_tether(int N, int P, const double* x, double* g,
+                                                const double* anchor, double k,
+                                                double* energy) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * P) return;
+  const int a = t / P, b = t % P;
+  double e = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const size_t i = ((size_t)d * N + a) * P + b;
+    const double dd = x[i] - anchor[(size_t)d * N + a];
+    g[i] += k * dd;
+    e += dd * dd;
+  }
+  if (energy) atomicAdd(energy + (size_t)b * QHP_NTERMS + QHP_E_BOND, 0.5 * k * e);
+}
+
+hipError_t launch_tether(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
+  if (!(c->tether_k > 0)) return hipSuccess;
+  const int N = c->N;
+  const bool plain = bead >= 0;
+  const BeadSet B = bs ? *bs : full_beads(c);
+  const int P = plain ? 1 : B.P;
+  const double* x = plain ? c->x + (size_t)bead * 3 * N : B.x;
+  double* g = plain ? c->g + (size_t)bead * 3 * N : B.g;
+  double* e = energy ? (plain ? c->energy + (size_t)bead * QHP_NTERMS : B.energy) : nullptr;
+  const unsigned nb = (unsigned)(((size_t)N * P + 255) / 256);
+  hipLaunchKernelGGL(k_tether, nb, 256, 0, c->stream, N, P, x, g, c->d_anchor, c->tether_k, e);
+  return hipGetLastError();
+}
+
 hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   BondArgs A;
   const int N = c->N;

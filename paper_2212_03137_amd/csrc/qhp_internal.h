@@ -126,6 +126,8 @@ struct qhp_ctx {
   double* d_sqrt_mkT = nullptr;
   double* d_sigma = nullptr;
   double* d_eps = nullptr;
+  double tether_k = 0.0;      // test-only harmonic tether (0 = off)
+  double* d_anchor = nullptr; // its anchors [3][N]
 
   // state
   double *Q = nullptr, *Pa = nullptr, *x = nullptr, *g = nullptr;
@@ -253,6 +255,9 @@ hipError_t launch_spme_hvp(qhp_ctx* c, const double* u, double* hu, bool mix);
 // bead >= 0: one bead of the plain (bead-major) layout; bead < 0: the bead set `bs`
 // (nullptr: the full ring polymer of the context)
 hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);
+// test-only tether (after launch_bonded, which initialises grad V and the energy rows):
+// grad V += k (x - a), bond energy += k/2 |x - a|^2; nothing when tether_k = 0
+hipError_t launch_tether(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);
 hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs = nullptr);
 // part: SPME_FRONT (tile binning of the plain layout, spread, transforms and influence
 // function), SPME_GATHER (forces into grad V, energies), or both

@@ -84,6 +84,9 @@ class System:
     lambda_elec: float = 1.0
     lambda_vdw: float = 1.0
     sc_alpha: float = 0.5
+    # test-only harmonic tether: spring constant (0 = off) and per-atom anchors [N][3]
+    tether_k: float = 0.0
+    tether_anchor: np.ndarray = None
 
     @property
     def n_atoms(self) -> int:

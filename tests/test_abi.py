@@ -49,6 +49,8 @@ def test_params_struct_matches_header_fields():
     (dict(pme_order=7), -5),
     (dict(pme_grid=(16, 16, 12)), -1),
     (dict(exec_mode=7), -1),
+    (dict(tether_k=-1.0), -1),         # the test tether: k_h >= 0
+    (dict(tether_k=2.0), -1),          # k_h > 0 without anchors
 ])
 def test_invalid_parameters_rejected_before_device_use(change, code):
     import paper_2212_03137_amd as q

@@ -149,3 +149,53 @@ def test_microcanonical_ring_polymer_conserves_energy():
     say("NVE H", hs.min(), hs.max(), "K", K)
     assert np.max(np.abs(hs - hs[0])) <= 0.01 * K
     assert abs(hs[-5:].mean() - hs[:5].mean()) <= 0.003 * K
+
+
+def _tethered(s, k, **zero):
+    import dataclasses
+    return dataclasses.replace(s, tether_k=k, tether_anchor=s.pos[0].copy(), **zero)
+
+
+def test_tether_forces_and_energies_match_the_oracle():
+    s = synth.water_box(27, 2, 10.5, seed=71, cutoff=5.0, ewald_alpha=0.4, pme_grid=16,
+                        pme_order=5)
+    s = _tethered(s, 7.5)
+    s.tether_anchor = s.tether_anchor + 0.05          # the beads sit off their anchors
+    E_r, F_r = forces.evaluate(s.pos, s)
+    with ctx_for(s) as c:
+        E, F = c.eval(s.pos)
+    assert rel_max(F, F_r) <= 1e-11
+    assert np.allclose(E, E_r, rtol=1e-11, atol=1e-9)
+
+
+def test_tethered_free_atoms_sample_the_ring_polymer_oscillator():
+    # every interaction switched off and a harmonic tether k on each atom: independent
+    # 3-D oscillators, w^2 = k / m; per dof and bead <(x - a)^2> = (kT / m) sum_k
+    # 1 / (w^2 + w_k^2) with the free ring polymer's w_k (the P-bead closed form)
+    import dataclasses
+    from oracle import normal_modes as nm
+    s = synth.water_box(64, 8, 12.42, seed=72, cutoff=6.0, pme_grid=16, pme_order=4)
+    mH = s.mass[1]
+    w = 2.0 * s.kT / s.hbar                             # beta hbar w = 2 for hydrogen
+    k = mH * w * w
+    s = _tethered(s, k, charge=np.zeros_like(s.charge), lj_epsilon=np.zeros_like(s.lj_epsilon),
+                  bond_k=0.0, angle_k=0.0)
+    s = dataclasses.replace(s, gamma_centroid=0.01)
+    wk = nm.mode_frequencies(s.n_beads, 1.0 / s.kT, s.hbar)
+    acc = np.zeros(s.n_atoms)
+    n = 0
+    with ctx_for(s) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(2000)
+        for _ in range(1000):
+            c.step(20)
+            x, _, _ = c.get_state()
+            acc += ((x - s.tether_anchor[None]) ** 2).mean(axis=(0, 2))
+            n += 1
+    acc /= n
+    for t in (0, 1):                                    # O, H
+        m = s.mass[t]
+        ref = s.kT / m * np.sum(1.0 / (k / m + wk * wk))
+        got = acc[s.types == t].mean()
+        say("tether", t, got, ref)
+        assert abs(got / ref - 1) < 0.04

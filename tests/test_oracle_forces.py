@@ -44,6 +44,22 @@ def test_pair_list_rows_are_the_kdtree_pairs_of_the_rows(n_w, L, r):
     assert np.array_equal(fo.pair_list_rows(c, s.box, r, rows), ref)
 
 
+def test_tether_is_zero_at_the_anchors_and_its_gradient_is_the_energy_derivative():
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0, 10, (12, 3))
+    e0, g0 = fo.tether(a, a, 3.0)
+    assert e0 == 0.0 and np.all(g0 == 0.0)
+    x = a + rng.normal(0, 0.3, a.shape)
+    e, g = fo.tether(x, a, 3.0)
+    h = 1e-6
+    for i in (0, 5, 11):
+        for d in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, d] += h; xm[i, d] -= h
+            fd = (fo.tether(xp, a, 3.0)[0] - fo.tether(xm, a, 3.0)[0]) / (2 * h)
+            assert math.isclose(g[i, d], fd, rel_tol=1e-7, abs_tol=1e-9)
+
+
 def _fd_check(energy_fn, grad, x, atoms, h=1e-5, rtol=1e-6, atol=1e-7):
     for a in atoms:
         for d in range(3):
