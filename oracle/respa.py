@@ -12,8 +12,7 @@ eq. beads_positions, from the P~ lowest-frequency modes only,
     U_P(Q) ~ (1/P) sum_i V_f(x_i) + (1/P~) sum_j V_s(x~_j).
 
 The chain rule gives the slow force on mode n < P~ as -(1/sqrt(P~)) sum_j C_jn grad V_s(x~_j)
-(C = T~ up to the reading below: eq. force_normal_modes with P~ in place of P) and zero
-on modes n >= P~.
+(C = T~: eq. force_normal_modes with P~ in place of P) and zero on modes n >= P~.
 
 BAOAB-RESPA (paragraph "Path-integral RESPA integrator", the two-stage Trotter splitting):
 one outer step of length n_alt dt is
@@ -26,14 +25,11 @@ Readings (where the paper leaves the choice open):
   reciprocal sum). The exclusion correction stays with the rest of the electrostatics so
   that all of it is evaluated on the same (contracted) beads.
 * The n-th contracted mode is the n-th lowest of the full polymer in the ordering of
-  ``normal_modes.transfer_matrix`` (cos before sin within a pair).
-* Contracted beads are the samples at j / P~ of the trigonometric interpolant through
-  those modes (the construction behind the contraction scheme of Markland and
-  Manolopoulos). This is the equation above for odd P~ and for P~ = P. For even P~ < P the
-  last kept mode is the cosine of harmonic P~/2, whose samples are sqrt(2) (-1)^j Q_n,
-  while the alternating column of T~ alone would give (-1)^j Q_n; the contraction matrix
-  C below therefore scales that column by sqrt(2). With it the contraction reproduces
-  exactly every ring polymer band-limited to harmonics <= P~/2.
+  ``normal_modes.transfer_matrix`` (cos before sin within a pair). For even P~ < P the
+  last kept mode is therefore the cosine of harmonic P~/2 of the full polymer, which the
+  transfer matrix of P~ beads places on its alternating column (-1)^j / sqrt(P~): every
+  kept mode enters the contracted beads with unit weight, so that
+  (1/P~) sum_j x~_j^2 = sum_{n<P~} Q_n^2 for any polymer.
 * The step counter of the O-step noise counts inner steps (time = counter x dt).
 * With P~ = P and n_alt = 1 the scheme is the plain BAOAB step of ``oracle/rpmd.py``
   with the kick split in two, which the tests use as one of the pins.
@@ -47,12 +43,11 @@ from .rpmd import RPMD
 
 
 def contraction_matrix(P_full, P_c):
-    """C [P~][P~]: x~_j = sqrt(P~) sum_n C_jn Q_n over the P~ lowest modes (C = T~, with
-    the alternating column scaled by sqrt(2) when P~ is even and below P)."""
-    C = nm.transfer_matrix(P_c).copy()
-    if P_c % 2 == 0 and P_c < P_full:
-        C[:, P_c - 1] *= math.sqrt(2.0)
-    return C
+    """C [P~][P~]: x~_j = sqrt(P~) sum_n C_jn Q_n over the P~ lowest modes; C is the
+    transfer matrix of P~ beads (eq. beads_positions with P~ in place of P)."""
+    if not 1 <= P_c <= P_full:
+        raise ValueError("the contracted polymer needs 1 <= P~ <= P")
+    return nm.transfer_matrix(P_c)
 
 
 def contract(Q, P_c):

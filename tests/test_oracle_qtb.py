@@ -220,3 +220,50 @@ def test_ratio_running_mean_recursion():
         vv = np.stack([Cvv[Q.types == z].mean(axis=(0, 1)) for z in range(2)])
         assert np.allclose(Q.avg_vv, prev * decay + vv * (1.0 - decay), rtol=1e-12, atol=0)
         prev = Q.avg_vv.copy()
+
+
+@pytest.mark.parametrize("start", [2.0, 0.5])
+def test_simple_adaptation_returns_harmonic_oscillators_to_gamma0(start):
+    # Linear response of a harmonic oscillator with friction gamma_0 driven by a force of
+    # spectrum 2 m gamma Theta gives m gamma C_vv - Re C_vF = (2 gamma Theta w^2 / |D|^2)
+    # (gamma - gamma_0), |D|^2 = (w0^2 - w^2)^2 + gamma_0^2 w^2: Delta_FDT has the sign of
+    # gamma - gamma_0, and the SIMPLE update gamma <- gamma - A Delta moves gamma back to
+    # gamma_0 (its fixed point for a harmonic system). A sign error would push it away.
+    N, w0, nseg, dt, g0 = 200, 0.2, 128, 0.25, 0.02
+    types = np.zeros(N, dtype=int)
+    m = np.full(N, 1.008 * synth.AMU)
+    q = qtb.QTB(m, types, 1, KT, HBAR, dt, g0, nseg, 4e-3, 0.01, 4,
+                lambda x: (None, m[None, :, None] * w0 * w0 * x))
+    q.gamma[:] = start * g0
+    rng = np.random.default_rng(4)
+    th = qtb.theta(np.array([w0]), KT, HBAR)[0]
+    q.set_state(rng.standard_normal((1, N, 3)) * math.sqrt(th / (m[0] * w0 * w0)),
+                rng.standard_normal((1, N, 3)) * math.sqrt(th / m[0]))
+    band = np.abs(qtb.omega_grid(nseg, dt) - w0) < 0.05      # the grid point next to w0
+    assert band.sum() == 1
+    dev = [abs(start - 1.0)]
+    for _ in range(8):
+        q.step(nseg)
+        assert np.sign(q.last_delta[0][band][0]) == np.sign(start - 1.0)
+        dev.append(abs(q.gamma[0][band][0] / g0 - 1.0))
+    assert all(b < a for a, b in zip(dev, dev[1:]))          # monotone approach
+    assert dev[-1] < 0.75 * dev[0]
+
+
+def test_white_noise_force_spectrum_is_2_m_gamma0_kT():
+    # classical white-noise bath: F_t = sqrt(2 m gamma_0 kT / dt) w_t with w_t independent
+    # standard Gaussians, so E|sum_t F_t e^{-i w_k t dt}|^2 = N_seg 2 m gamma_0 kT / dt and
+    # C_FF = (dt / N_seg) |F_k|^2 has expectation 2 m gamma_0 kT at every frequency
+    # (the normalisation of the spectra that the adaptation compares against)
+    N, nseg, dt, g0 = 300, 64, 0.5, 0.02
+    types = np.zeros(N, dtype=int)
+    m = np.full(N, 15.999 * synth.AMU)
+    q = qtb.QTB(m, types, 1, KT, HBAR, dt, g0, nseg, 0.0, 0.01, 5,
+                lambda x: (None, np.zeros_like(x)), classical_theta=True)
+    q.set_state(np.zeros((1, N, 3)), np.zeros((1, N, 3)))
+    Cff, _ = qtb.spectra(q.noise, q.noise, dt)
+    ref = 2.0 * m[0] * g0 * KT
+    mean = Cff.mean(axis=(0, 1))                       # per frequency, over 900 dofs
+    # every interior frequency: |F_k|^2 / its mean is chi^2_2 / 2 (std 1 / sqrt(900))
+    assert np.all(np.abs(mean[1:-1] / ref - 1.0) < 5.0 / math.sqrt(3 * N))
+    assert abs(Cff[:, :, 1:-1].mean() / ref - 1.0) < 0.01

@@ -29,14 +29,44 @@ def bandlimited(P, kmax, rng, n_atoms=5):
 
 
 @pytest.mark.parametrize("P,Pc", [(16, 1), (16, 2), (16, 3), (16, 4), (16, 5), (16, 8),
-                                  (32, 4), (8, 8)])
+                                  (32, 4), (32, 5), (32, 7), (8, 8)])
 def test_contraction_samples_the_bandlimited_polymer(P, Pc):
-    # a polymer made of harmonics <= Pc/2 is reproduced exactly at tau_j = j / Pc
+    # a polymer made of harmonics below Pc/2 is reproduced exactly at tau_j = j / Pc
     rng = np.random.default_rng(P * 100 + Pc)
-    x, curve = bandlimited(P, Pc // 2, rng)
+    x, curve = bandlimited(P, (Pc - 1) // 2, rng)
     Q = nm.modes_from_beads(x, nm.transfer_matrix(P))
     xc = respa.contract(Q, Pc)
     assert np.allclose(xc, curve(np.arange(Pc) / Pc), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("P,Pc", [(8, 1), (8, 2), (8, 3), (8, 4), (8, 5), (8, 6), (8, 7),
+                                  (32, 5), (32, 12), (32, 32)])
+def test_every_kept_mode_enters_with_unit_weight(P, Pc):
+    # x~_j = Q_0 + sqrt(P~) sum_{1<=n<P~} T~_jn Q_n with T~ orthogonal: a unit amplitude on
+    # mode n < P~ gives contracted beads of mean square 1 (so (1/P~) sum_j x~_j^2 equals the
+    # sum of the kept modes' squares for any polymer), and modes n >= P~ do not enter
+    for n in range(P):
+        Q = np.zeros((P, 1, 1))
+        Q[n] = 1.0
+        xc = respa.contract(Q, Pc)
+        assert np.isclose((xc ** 2).mean(), 1.0 if n < Pc else 0.0, rtol=0, atol=1e-14), n
+    rng = np.random.default_rng(P + 7 * Pc)
+    Q = rng.standard_normal((P, 4, 3))
+    xc = respa.contract(Q, Pc)
+    assert np.allclose((xc ** 2).mean(axis=0), (Q[:Pc] ** 2).sum(axis=0), rtol=1e-13, atol=0)
+
+
+def test_even_contraction_keeps_the_full_polymers_cosine_mode_once():
+    # P = 8, P~ = 4: the kept modes are the centroid, (cos, sin) of harmonic 1 and the
+    # cosine of harmonic 2 of the full polymer; the contracted beads at tau_j = j/4 are
+    # Q_0 + sqrt(2) (Q_1 cos(pi j/2) + Q_2 sin(pi j/2)) + (-1)^j Q_3 (transfer matrix of 4
+    # beads: columns 1/2, (1/sqrt 2)(cos, sin)(pi j / 2), (-1)^j / 2, times sqrt(4))
+    rng = np.random.default_rng(5)
+    Q = rng.standard_normal((8, 3, 3))
+    j = np.arange(4)[:, None, None]
+    expect = (Q[0] + math.sqrt(2.0) * (Q[1] * np.cos(math.pi * j / 2) + Q[2] * np.sin(math.pi * j / 2))
+              + (-1.0) ** j * Q[3])
+    assert np.allclose(respa.contract(Q, 4), expect, rtol=0, atol=1e-14)
 
 
 def test_contraction_limits():
@@ -48,7 +78,8 @@ def test_contraction_limits():
     assert np.allclose(respa.contract(Q, 1)[0], x.mean(axis=0), atol=1e-14)  # centroid
 
 
-@pytest.mark.parametrize("P,Pc", [(8, 1), (8, 2), (8, 3), (8, 4), (8, 8), (16, 4)])
+@pytest.mark.parametrize("P,Pc", [(8, 1), (8, 2), (8, 3), (8, 4), (8, 5), (8, 8), (16, 4),
+                                  (16, 6)])
 def test_slow_mode_forces_are_the_gradient(P, Pc):
     # central differences of U_s(Q) = (1/Pc) sum_j V_s(x~_j(Q)) for an anharmonic V_s
     rng = np.random.default_rng(7 + P + Pc)
@@ -165,9 +196,11 @@ def test_frictionless_respa_is_time_reversible():
 def test_harmonic_mode_variances_under_contraction():
     # V_f = kf x^2/2 on the P beads and V_s = ks x^2/2 on the P~ contracted beads make every
     # mode an independent oscillator: <Q_n^2> = kT / (kf + ks w_n + m omega_n^2), with
-    # w_n = 1 for n < P~ (2 for the sqrt(2)-scaled alternating column) and 0 for n >= P~
+    # w_n = 1 for n < P~ and 0 for n >= P~
+    # (hbar large enough that the spring stiffness m omega_n^2 of the kept modes does not
+    # swamp ks, so a wrong weight w_n would show)
     P, Pc, nalt, N = 8, 4, 2, 1500
-    kT, hbar, m0 = 1.0, 1.0, 1.0
+    kT, hbar, m0 = 1.0, 4.0, 1.0
     kf, ks = 1.0, 1.5
     m = np.full(N, m0)
 
@@ -182,7 +215,6 @@ def test_harmonic_mode_variances_under_contraction():
     w = nm.mode_frequencies(P, 1.0 / kT, hbar)
     wn = np.zeros(P)
     wn[:Pc] = 1.0
-    wn[Pc - 1] = 2.0
     expect = kT / (kf + ks * wn + m0 * w * w)
     rng = np.random.default_rng(1)
     T = nm.transfer_matrix(P)
