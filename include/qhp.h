@@ -94,7 +94,9 @@ extern "C" {
 /* Parameters of a run. Host pointers; copied by qhp_create. */
 typedef struct qhp_params {
   int32_t n_atoms;          /* N, a multiple of 3                                         */
-  int32_t n_beads;          /* P in 1..64                                                 */
+  int32_t n_beads;          /* P in 1..64 (eq. isomorphism_RPMD); a count that is not a
+                               power of two runs in the lanes of the next one, whose extra
+                               "phantom" beads carry no mode and are never reported     */
   double box[3];            /* orthorhombic box edges                                     */
   int32_t n_types;          /* atom types (1..8)                                          */
   const int32_t* type;      /* [N] type of each atom                                      */
@@ -124,17 +126,19 @@ typedef struct qhp_params {
   double qtb_adapt_rate;    /* adQTB: SIMPLE rate A_gamma (same for every type)          */
   double qtb_gamma_min_frac;/* adQTB: gamma_min = frac * gamma_0 (paper default 0.01)    */
   int32_t qtb_classical;    /* adQTB test switch: Theta(omega) = kT (white-noise limit)  */
-  int32_t nbr_capacity;     /* neighbours per atom kept; 0 = sized from density          */
+  int32_t nbr_capacity;     /* initial neighbours per atom a row holds; 0 = sized from
+                               the density. Rows grow by themselves when a build finds
+                               more (qhp_eval, qhp_step, ...); see qhp_nlist_stats      */
   int32_t use_graph;        /* 1: replay each step as one captured HIP graph; 0: launch   */
-  /* Multiple time stepping with ring-polymer contraction (Sec. "Multi-timestep Methods"):
+  /* Multiple time stepping with ring-polymer contraction (Sec. "Multi-timestep Methods",
+   * paragraphs "Ring-polymer Contractions" and "Path-integral RESPA integrator"):
    * V = V_f + V_s with V_f = O-H bonds + H-O-H angles on the P beads and V_s = every other
-   * term on P~ contracted beads, the samples at j/P~ of the trigonometric interpolant
-   * through the P~ lowest modes (the paper's contraction equation; for even P~ < P the
-   * last kept cosine mode enters with weight sqrt(2), so that band-limited polymers are
-   * reproduced exactly). BAOAB-RESPA: one outer step is Bs(n dt/2) [Bf(dt/2) A(dt/2)
-   * O(dt) A(dt/2) Bf(dt/2)]^n Bs(n dt/2) with n = respa_nalt. Both need exec =
+   * term on P~ contracted beads x~_j = Q_0 + sqrt(P~) sum_{0<n<P~} T~_jn Q_n, T~ the
+   * transfer matrix of P~ beads (eq. beads_positions with P~ in place of P: the P~ lowest
+   * modes, each with unit weight). BAOAB-RESPA: one outer step is Bs(n dt/2) [Bf(dt/2)
+   * A(dt/2) O(dt) A(dt/2) Bf(dt/2)]^n Bs(n dt/2) with n = respa_nalt. Both need exec =
    * QHP_BATCHED and thermostat = QHP_TRPMD (else QHP_EUNSUPPORTED). */
-  int32_t rpc_beads;        /* P~: a power of two <= P; 0 = P (no contraction)          */
+  int32_t rpc_beads;        /* P~ in 1..P (any count; 0 = P, no contraction)             */
   int32_t respa_nalt;       /* n: inner steps per outer step, 1..64; 0 = 1               */
   int32_t integrator;       /* QHP_BAOAB | QHP_BCOCB                                      */
   int32_t qtb_adapt_scheme; /* QHP_QTB_SIMPLE | QHP_QTB_RATIO                             */
@@ -166,7 +170,10 @@ typedef struct qhp_params {
 
 typedef struct qhp_ctx qhp_ctx;
 
-/* Create a context on the current HIP device. `stream` is a hipStream_t; all work of the
+/* Create a context on the current HIP device (the set-up of Secs. "Ring-Polymer Molecular
+ * Dynamics" and "Integration Scheme": transfer matrix of eq. matrix_free_RP, mode
+ * frequencies, per-mode BAOAB coefficients; the SPME influence function of the Ewald sum
+ * the force field uses). `stream` is a hipStream_t; all work of the
  * context is queued on it (NULL: the library creates a private non-blocking stream).
  * Validates `p` (QHP_EINVAL; QHP_EUNSUPPORTED for valid settings the library does not run:
  * B-spline order 3 or 7, or more cells plus SPME tiles than the per-step bookkeeping block
@@ -175,15 +182,21 @@ typedef struct qhp_ctx qhp_ctx;
  * thermostat and A-block coefficients and the SPME influence function.
  * The state is undefined until qhp_set_state. */
 QHP_API int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out);
+/* Wait for the context's queued work, free its device memory and the context. */
 QHP_API int qhp_destroy(qhp_ctx* ctx);
 
 /* Stateless evaluation of V on every bead (eq. PI_potential summands): `pos` [P][N][3]
- * -> `energy` [P][QHP_NTERMS] (nullable) and `forces` = -grad V [P][N][3] (nullable).
- * Builds the centroid neighbour list of these positions (Sec. "Massively Parallel
- * Implementation": neighbours are found on ring-polymer centroids and shared by all
- * beads). The full potential on all P beads, whatever rpc_beads and respa_nalt are.
- * Does not change the propagated state (a later step rebuilds the list if it must). */
-QHP_API int qhp_eval(qhp_ctx* ctx, const double* pos, double* energy, double* forces, int mem_kind);
+ * in the orthorhombic box `box` [3] -> `energy` [P][QHP_NTERMS] (nullable) and `forces` =
+ * -grad V [P][N][3] (nullable). The box is fixed per context (cell grid, SPME influence
+ * function and tables depend on it): `box` must equal the context's edges to 1e-12
+ * relative, else QHP_EINVAL; NULL means the context's box. Builds the centroid neighbour
+ * list of these positions (Sec. "Massively Parallel Implementation": neighbours are found
+ * on ring-polymer centroids and shared by all beads), growing its rows if they are too
+ * short. The full potential on all P beads, whatever rpc_beads and respa_nalt are. Does
+ * not change the propagated state (a later step rebuilds the list if it must).
+ * Synchronises the stream for either memory kind (the list and state flags are read). */
+QHP_API int qhp_eval(qhp_ctx* ctx, const double* pos, const double box[3], double* energy,
+                     double* forces, int mem_kind);
 
 /* Gradients of the summed bead energies E = sum_b V(x_b) (eq. PI_potential without the
  * 1/P) at `pos` [P][N][3] with respect to the force-field parameters: `dq` [N] per-atom
@@ -219,15 +232,22 @@ QHP_API int qhp_hvp(qhp_ctx* ctx, const double* pos, const double* dir, double* 
  * of the current segment is generated. */
 QHP_API int qhp_set_state(qhp_ctx* ctx, const double* pos, const double* vel, int64_t step, int mem_kind);
 
-/* Read the state back as bead positions and velocities [P][N][3] (either nullable). */
+/* Read the state back as bead positions x = sqrt(P) T Q (eq. beads_positions) and bead
+ * velocities v = sqrt(P) T P_n / m [P][N][3] (either nullable), with the momenta after
+ * the step's final half kick. */
 QHP_API int qhp_get_state(qhp_ctx* ctx, double* pos, double* vel, int64_t* step, int mem_kind);
 
-/* Advance `nsteps` BAOAB steps (B(dt/2) A(dt/2) O(dt) A(dt/2) B(dt/2), one force
- * evaluation each). For adQTB the spectra, SIMPLE adaptation, clamp and the next noise
- * segment are computed after the last step of every segment. `energy` (nullable)
- * receives the per-bead energies of the final state [P][QHP_NTERMS]. Returns QHP_ENOMEM
- * if the neighbour capacity was exceeded during the call (the state is then invalid),
- * QHP_ENONFINITE if the state became non-finite.
+/* Advance `nsteps` BAOAB steps (Sec. "Integration Scheme": B(dt/2) A(dt/2) O(dt) A(dt/2)
+ * B(dt/2), one force evaluation each). For adQTB the spectra, SIMPLE (or RATIO)
+ * adaptation, clamp and the next noise segment are computed after the last step of every
+ * segment (Secs. "Colored Noise Generation", "Computation of the adQTB Spectra and
+ * Adaptation Procedure"). `energy` (nullable) receives the per-bead energies of the final
+ * state [P][QHP_NTERMS]. The centroid list is rebuilt on the device whenever the skin rule
+ * asks; if a build finds more neighbours than a row holds, the call restarts from the
+ * state it began with (kept on the device), with longer rows, so its result never depends
+ * on the row length. Returns QHP_ENONFINITE if the state became non-finite and
+ * QHP_ENOMEM only if the rows cannot grow (device memory).
+ * Synchronises the stream at the end (the list and state flags are read).
  * With respa_nalt = n > 1 or rpc_beads = P~ < P, `nsteps` counts outer steps of n inner
  * steps each; the step counter (qhp_get_state, noise counter) counts inner steps. The
  * energies are then: bond and angle columns on the P beads, the other columns on rows
@@ -236,19 +256,25 @@ QHP_API int qhp_get_state(qhp_ctx* ctx, double* pos, double* vel, int64_t* step,
 QHP_API int qhp_step(qhp_ctx* ctx, int32_t nsteps, double* energy, int mem_kind);
 
 /* Kinetic energy sum_n P_n^2 / 2m and free ring-polymer spring energy
- * sum_n m omega_n^2 Q_n^2 / 2 of the current state (host outputs). */
+ * sum_n m omega_n^2 Q_n^2 / 2 of the current state (the two quadratic terms of the
+ * ring-polymer Hamiltonian in normal modes, Sec. "Ring-Polymer Molecular Dynamics";
+ * host outputs). */
 QHP_API int qhp_mode_energies(qhp_ctx* ctx, double* kinetic, double* spring);
 
-/* The centroid pair list of the last build, canonical form: pairs (i, j), i < j,
+/* The centroid pair list of the last build (Sec. "Massively Parallel Implementation":
+ * pairs whose centroid distance is below rc + skin), canonical form: pairs (i, j), i < j,
  * different molecules, sorted by i then j, written to `pairs` [*npairs][2] (host).
  * If `capacity` (in pairs) is too small, *npairs is set and QHP_ENOMEM returned. */
 QHP_API int qhp_nlist_export(qhp_ctx* ctx, int32_t* pairs, int64_t capacity, int64_t* npairs);
 
-/* Neighbour-list bookkeeping: number of list builds since qhp_create, the largest
- * neighbour count of the last build and the per-atom capacity (host outputs). */
+/* Neighbour-list bookkeeping of the centroid list (Sec. "Massively Parallel
+ * Implementation"): number of list builds since qhp_create, the largest neighbour count
+ * of the last build and the current row length (host outputs). */
 QHP_API int qhp_nlist_stats(qhp_ctx* ctx, int64_t* builds, int32_t* max_count, int32_t* capacity);
 
-/* Gaussian noise as the kernels draw it (Philox-4x64-10, key (seed, stream), Box-Muller):
+/* Gaussian noise as the kernels draw it (the O step's white noise, Sec. "Integration
+ * Scheme"; the adQTB white noise, Sec. "Colored Noise Generation"; Philox-4x64-10 of
+ * Salmon et al. 2011, key (seed, stream), Box-Muller):
  * stream 5 = TRPMD O-step noise of step `step`, out [P][N][3] indexed [mode][atom][xyz];
  * stream 6 = adQTB white noise of global step `step`, out [N][3]. Device computation,
  * host output. */
@@ -319,17 +345,23 @@ QHP_API int qhp_autotune(qhp_ctx* ctx, int32_t reps, int32_t* spread_beads,
 QHP_API int qhp_set_launch(qhp_ctx* ctx, int32_t spread_beads, int32_t spread_ztiles,
                            int32_t fft_slots);
 
-/* adQTB: gamma_z(omega_k), k = 0..N_seg, for every type: [n_types][N_seg + 1] (host). */
+/* adQTB (Sec. "adQTB": the adapted friction gamma_z(omega) of each atom type):
+ * gamma_z(omega_k), omega_k = pi k / (N_seg dt), k = 0..N_seg, for every type:
+ * [n_types][N_seg + 1] (host). qhp_qtb_set_gamma replaces it and regenerates the current
+ * segment's coloured noise from it. */
 QHP_API int qhp_qtb_get_gamma(qhp_ctx* ctx, double* gamma);
 QHP_API int qhp_qtb_set_gamma(qhp_ctx* ctx, const double* gamma);
-/* adQTB: the coloured noise of the current segment [N_seg][N][3] and the type-averaged
- * Delta_FDT of the last completed segment [n_types][N_seg + 1] (host outputs). */
+/* adQTB: the coloured noise of the current segment [N_seg][N][3] (Sec. "Colored Noise
+ * Generation") and the type-averaged Delta_FDT of the last completed segment
+ * [n_types][N_seg + 1] (eq. QTB_spectra; host outputs). */
 QHP_API int qhp_qtb_get_noise(qhp_ctx* ctx, double* noise);
 QHP_API int qhp_qtb_get_delta(qhp_ctx* ctx, double* delta);
 
-/* Per-kernel timing with HIP events recorded on the context's stream around every launch
- * of the selected kernel class (0 = off). qhp_profile_read returns the summed milliseconds
- * and the number of launches since enabling. */
+/* Per-kernel timing (measurement of the step's phases, not part of the method): HIP
+ * events recorded on the context's stream around every launch of the selected kernel
+ * class (0 = off); steps are then launched kernel by kernel on one stream.
+ * qhp_profile_read returns the summed milliseconds and the number of launches since
+ * enabling. */
 #define QHP_PROF_OFF    0
 #define QHP_PROF_PAIR   1
 #define QHP_PROF_SPREAD 2
@@ -339,7 +371,9 @@ QHP_API int qhp_qtb_get_delta(qhp_ctx* ctx, double* delta);
 QHP_API int qhp_profile(qhp_ctx* ctx, int which);
 QHP_API int qhp_profile_read(qhp_ctx* ctx, double* ms, int64_t* launches);
 
+/* Wait for the context's queued work (results written to device memory are then valid). */
 QHP_API int qhp_sync(qhp_ctx* ctx);
+/* Message of the last failure on the context (valid until its next call). */
 QHP_API const char* qhp_last_error(qhp_ctx* ctx);
 
 #ifdef __cplusplus

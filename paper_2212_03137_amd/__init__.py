@@ -79,7 +79,7 @@ def load():
     P, I, D, vp = C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p
     lib.qhp_create.argtypes = [C.POINTER(Params), vp, C.POINTER(vp)]
     lib.qhp_destroy.argtypes = [vp]
-    lib.qhp_eval.argtypes = [vp, vp, vp, vp, I]
+    lib.qhp_eval.argtypes = [vp, vp, vp, vp, vp, I]
     lib.qhp_set_state.argtypes = [vp, vp, vp, C.c_int64, I]
     lib.qhp_get_state.argtypes = [vp, vp, vp, C.POINTER(C.c_int64), I]
     lib.qhp_step.argtypes = [vp, C.c_int32, vp, I]
@@ -224,12 +224,14 @@ class Context:
         self.close()
 
     # ------------------------------------------------------------------------------
-    def eval(self, pos):
-        """Per-bead energies [P][7] and forces -grad V [P][N][3] (host arrays)."""
+    def eval(self, pos, box=None):
+        """Per-bead energies [P][7] and forces -grad V [P][N][3] (host arrays); `box` (the
+        context's edges, which are fixed per context) is checked when given."""
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         E = np.zeros((self.P, NTERMS))
         F = np.zeros((self.P, self.N, 3))
-        self._check(self._lib.qhp_eval(self._h, _ptr(pos), _ptr(E), _ptr(F), MEM_HOST))
+        b = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
+        self._check(self._lib.qhp_eval(self._h, _ptr(pos), _ptr(b), _ptr(E), _ptr(F), MEM_HOST))
         return E, F
 
     def set_lambda(self, lambda_elec, lambda_vdw):
@@ -363,7 +365,8 @@ class Context:
         self._check(self._lib.qhp_step(self._h, int(n), _ptr(energy_tensor), MEM_DEVICE))
 
     def eval_device(self, pos, energy, forces):
-        self._check(self._lib.qhp_eval(self._h, _ptr(pos), _ptr(energy), _ptr(forces), MEM_DEVICE))
+        self._check(self._lib.qhp_eval(self._h, _ptr(pos), None, _ptr(energy), _ptr(forces),
+                                       MEM_DEVICE))
 
 
 def bar(du_a, du_b, beta):

@@ -34,7 +34,8 @@ def _eval(context, pos):
     pos = pos.detach().contiguous().to(torch.float64)
     E = torch.zeros((context.P, NTERMS), dtype=torch.float64, device=pos.device)
     F = torch.zeros_like(pos)
-    context._check(context._lib.qhp_eval(context._h, _arg(pos), _arg(E), _arg(F), _mem(pos)))
+    context._check(context._lib.qhp_eval(context._h, _arg(pos), None, _arg(E), _arg(F),
+                                         _mem(pos)))
     if pos.is_cuda:
         context.sync()
     return E, F

@@ -54,6 +54,7 @@ hipError_t dalloc(T** p, size_t n) {
 }
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int next_pow2(int v) { int p = 1; while (p < v) p *= 2; return p; }
 
 // Free ring-polymer modes: T[j][n] real Fourier basis (column 0 = 1/sqrt(P); pairs of
 // cos/sin columns for 1 <= k < P/2 with frequency 2 (P / beta hbar) sin(pi k / P); the
@@ -101,6 +102,14 @@ std::vector<double> bmod(int K, int n) {
   return out;
 }
 
+// n x n matrix in the top-left corner of an m x m zero matrix (row-major)
+std::vector<double> embed_square(const std::vector<double>& a, int n, int m) {
+  std::vector<double> out((size_t)m * m, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) out[(size_t)i * m + j] = a[(size_t)i * n + j];
+  return out;
+}
+
 void free_all(qhp_ctx* c) {
   void* ptrs[] = {c->T, c->mode_c, c->mode_s_w, c->mode_ws, c->mode_c1, c->mode_c2, c->mode_w2,
                   c->d_type, c->d_mass, c->d_charge, c->d_sqrt_mkT, c->d_sigma, c->d_eps,
@@ -112,7 +121,7 @@ void free_all(qhp_ctx* c) {
                   c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.vvsum, c->qtb.vfsum,
                   c->qtb.avg_vv, c->qtb.avg_vf, c->qtb.d_tmass, c->qtb.d_inv_count,
-                  c->qtb.tw2, c->qtb.tw4};
+                  c->qtb.tw2, c->qtb.tw4, c->snap, c->snap_ctrl};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
@@ -191,8 +200,7 @@ int validate(const qhp_params* p, std::string& why) {
   if (p->n_atoms < 3 || p->n_atoms % 3) return bad("n_atoms must be a positive multiple of 3");
   if (p->n_atoms >= (1 << 26)) return bad("n_atoms must be < 2^26");
   if (p->n_beads < 1 || p->n_beads > 64) return bad("n_beads must be in 1..64");
-  if (!pow2(p->n_beads)) { why = "n_beads must be a power of two"; return QHP_EUNSUPPORTED; }
-  if ((long long)p->n_atoms * p->n_beads > (1ll << 27)) {
+  if ((long long)p->n_atoms * next_pow2(p->n_beads) > (1ll << 27)) {
     why = "n_atoms * n_beads must be <= 2^27 (32-bit byte offsets of the bead arrays)";
     return QHP_EUNSUPPORTED;
   }
@@ -223,8 +231,8 @@ int validate(const qhp_params* p, std::string& why) {
     if (p->type[i] < 0 || p->type[i] >= p->n_types) return bad("atom type out of range");
     if (!(p->mass[i] > 0) || !std::isfinite(p->charge[i])) return bad("masses > 0, finite charges");
   }
-  if (p->rpc_beads < 0 || p->rpc_beads > p->n_beads || (p->rpc_beads > 0 && !pow2(p->rpc_beads)))
-    return bad("rpc_beads must be 0 or a power of two <= n_beads");
+  if (p->rpc_beads < 0 || p->rpc_beads > p->n_beads)
+    return bad("rpc_beads must be in 0..n_beads");
   if (p->respa_nalt < 0 || p->respa_nalt > 64) return bad("respa_nalt must be in 0..64");
   if (p->integrator != QHP_BAOAB && p->integrator != QHP_BCOCB) return bad("integrator");
   if (p->qtb_adapt_scheme != QHP_QTB_SIMPLE && p->qtb_adapt_scheme != QHP_QTB_RATIO)
@@ -262,10 +270,13 @@ int validate(const qhp_params* p, std::string& why) {
     if (!pow2(p->qtb_nseg) || p->qtb_nseg < 16 || p->qtb_nseg > 1024)
       return bad("qtb_nseg must be a power of two in 16..1024");
     if (!(p->qtb_gamma0 > 0) || !(p->qtb_gamma_min_frac >= 0)) return bad("qtb gamma");
-    for (int i = 0; i < p->n_atoms; ++i)
-      for (int j = 0; j < i; ++j)
-        if (p->type[i] == p->type[j] && p->mass[i] != p->mass[j])
-          return bad("adQTB needs one mass per atom type");
+    double tmass[QHP_MAX_TYPES];
+    bool seen[QHP_MAX_TYPES] = {};
+    for (int i = 0; i < p->n_atoms; ++i) {
+      const int t = p->type[i];
+      if (!seen[t]) { seen[t] = true; tmass[t] = p->mass[i]; }
+      else if (tmass[t] != p->mass[i]) return bad("adQTB needs one mass per atom type");
+    }
   }
   return QHP_OK;
 }
@@ -310,8 +321,11 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     }
   }
   c->use_graph = p->use_graph != 0;
-  const int N = p->n_atoms, P = p->n_beads;
-  c->N = N; c->P = P; c->NW = N / 3; c->Pc = P == 1 ? 1 : P / 2;
+  // a bead count that is not a power of two runs in the lanes of the next power of two:
+  // the extra (phantom) beads have zero rows and columns in the transfer matrix, so they
+  // stay at the centroid, carry no mode and feel no force, and nothing reports them
+  const int N = p->n_atoms, Pb = p->n_beads, P = next_pow2(Pb);
+  c->N = N; c->P = P; c->Pb = Pb; c->NW = N / 3; c->Pc = P == 1 ? 1 : P / 2;
   c->type.assign(p->type, p->type + N);
   c->mass.assign(p->mass, p->mass + N);
   c->charge.assign(p->charge, p->charge + N);
@@ -330,7 +344,7 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   const int Pc_grid = plain ? 1 : c->Pc;
   {
     // every FFT pass must split into whole blocks, for the beads and the contracted beads
-    const int ps = p->rpc_beads > 0 ? p->rpc_beads : P;
+    const int ps = p->rpc_beads > 0 ? next_pow2(p->rpc_beads) : P;
     const int pcs[2] = {Pc_grid, ps == 1 ? 1 : ps / 2};
     for (int pc : pcs)
       for (int d = 0; d < 3; ++d) {
@@ -343,12 +357,15 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   }
 
   // ---- normal modes and per-mode coefficients (host, FP64) ----
-  std::vector<double> T, w;
-  normal_modes(P, 1.0 / p->kT, p->hbar, T, w);
+  std::vector<double> Tb, w;
+  normal_modes(Pb, 1.0 / p->kT, p->hbar, Tb, w);
   c->h_omega = w;
+  std::vector<double> T = embed_square(Tb, Pb, P);
+  w.resize(P, 0.0);
   const double h = 0.5 * p->dt;
-  std::vector<double> mc(P), msw(P), mws(P), mc1(P), mc2(P), mw2(P);
-  for (int n = 0; n < P; ++n) {
+  // phantom modes (n >= Pb): no rotation, no friction, no noise: they stay zero
+  std::vector<double> mc(P, 1.0), msw(P, h), mws(P, 0.0), mc1(P, 1.0), mc2(P, 0.0), mw2(P, 0.0);
+  for (int n = 0; n < Pb; ++n) {
     if (p->integrator == QHP_BCOCB) {
       // Cayley form of the rotation (implicit midpoint rule of the free ring-polymer flow):
       // Q' = ((1 - a^2) Q + h P / m) / (1 + a^2), P' = (-m w^2 h Q + (1 - a^2) P) / (1 + a^2)
@@ -409,20 +426,19 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     TRY(hipMemcpy(c->d_anchor, an.data(), an.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   // ---- multiple time stepping / ring-polymer contraction ----
-  c->Ps = p->rpc_beads > 0 ? p->rpc_beads : P;
+  c->Psb = p->rpc_beads > 0 ? p->rpc_beads : Pb;
+  c->Ps = next_pow2(c->Psb);          // lanes of the contracted set (phantoms as above)
   c->nalt = p->respa_nalt > 0 ? p->respa_nalt : 1;
-  c->respa = c->Ps < P || c->nalt > 1;
+  c->respa = c->Psb < Pb || c->nalt > 1;
   if (c->respa) {
     const int Ps = c->Ps;
     TRY(dalloc(&c->xs, (size_t)3 * N * Ps)); TRY(dalloc(&c->gs, (size_t)3 * N * Ps));
     TRY(dalloc(&c->xfs, (size_t)N * Ps)); TRY(dalloc(&c->pa_tmp, NP3));
-    // C = T of Ps beads; for even Ps < P its alternating column carries the cosine mode of
-    // harmonic Ps/2 of the full polymer, whose samples at j/Ps are sqrt(2) (-1)^j Q
+    // C = the transfer matrix of Ps beads (eq. beads_positions with Ps in place of P): the
+    // Ps lowest modes of the full polymer, each with unit weight
     std::vector<double> Tc, wc;
-    normal_modes(Ps, 1.0 / p->kT, p->hbar, Tc, wc);
-    if (Ps % 2 == 0 && Ps < P)
-      for (int j = 0; j < Ps; ++j) Tc[j * Ps + Ps - 1] *= std::sqrt(2.0);
-    TRY(up(&c->Cs, Tc));
+    normal_modes(c->Psb, 1.0 / p->kT, p->hbar, Tc, wc);
+    TRY(up(&c->Cs, embed_square(Tc, c->Psb, Ps)));
   }
   TRY(hipMemset(c->energy, 0, (size_t)P * QHP_NTERMS * sizeof(double)));
   TRY(hipMemset(c->cref, 0, N * sizeof(double4)));
@@ -594,11 +610,16 @@ static int batched_forces(qhp_ctx* c, bool energy, const BeadSet* bs) {
   return QHP_OK;
 }
 
-// V_s (exclusion correction, real space, SPME) on the contracted beads: initialises c->gs
+// V_s (exclusion correction, real space, SPME) on the contracted beads: initialises c->gs.
+// Phantom contracted beads (lanes Psb..Ps-1) add their terms to energy rows that belong to
+// real beads of the full polymer; those terms are cleared again.
 static int slow_forces(qhp_ctx* c, bool energy, bool from_step) {
   QHP_HIP(c, launch_nlist(c, from_step));
   BeadSet sl{c->Ps, c->Ps == 1 ? 1 : c->Ps / 2, c->xs, c->gs, c->xfs, c->energy, QHP_TERMS_EXCL};
-  return batched_forces(c, energy, &sl);
+  int r = batched_forces(c, energy, &sl);
+  if (r || !energy || c->Psb == c->Ps) return r;
+  QHP_HIP(c, launch_clear_slow_energy(c, c->Psb, c->Ps));
+  return QHP_OK;
 }
 
 // Bonded + exclusion (initialise grad V), centroid pair list, real space, SPME.
@@ -617,7 +638,7 @@ int forces_all(qhp_ctx* c, bool energy, bool from_step) {
 }
 
 static int copy_in(qhp_ctx* c, const double* src, int mem_kind, double* dst_internal) {
-  const size_t n = (size_t)c->P * c->N * 3;
+  const size_t n = (size_t)c->Pb * c->N * 3;
   if (mem_kind == QHP_MEM_HOST) {
     for (size_t i = 0; i < n; ++i)
       if (!std::isfinite(src[i])) return qhp_fail(c, QHP_ENONFINITE, "non-finite input");
@@ -631,7 +652,7 @@ static int copy_in(qhp_ctx* c, const double* src, int mem_kind, double* dst_inte
 
 static int copy_out_energy(qhp_ctx* c, double* energy, int mem_kind) {
   if (!energy) return QHP_OK;
-  const size_t n = (size_t)c->P * QHP_NTERMS * sizeof(double);
+  const size_t n = (size_t)c->Pb * QHP_NTERMS * sizeof(double);
   if (mem_kind == QHP_MEM_HOST) {
     QHP_HIP(c, hipMemcpyAsync(energy, c->energy, n, hipMemcpyDeviceToHost, c->stream));
     QHP_HIP(c, hipStreamSynchronize(c->stream));
@@ -641,14 +662,16 @@ static int copy_out_energy(qhp_ctx* c, double* energy, int mem_kind) {
   return QHP_OK;
 }
 
-static int check_ctrl(qhp_ctx* c) {
-  NlCtrl h;
-  QHP_HIP(c, hipMemcpyAsync(&h, c->ctrl, sizeof(NlCtrl), hipMemcpyDeviceToHost, c->stream));
+static int read_ctrl(qhp_ctx* c, NlCtrl* h) {
+  QHP_HIP(c, hipMemcpyAsync(h, c->ctrl, sizeof(NlCtrl), hipMemcpyDeviceToHost, c->stream));
   QHP_HIP(c, hipStreamSynchronize(c->stream));
+  return QHP_OK;
+}
+
+static int ctrl_error(qhp_ctx* c, const NlCtrl& h) {
   if (h.overflow)
     return qhp_fail(c, QHP_ENOMEM, "neighbour capacity " + std::to_string(c->cap) +
-                                       " exceeded (max count " + std::to_string(h.max_count) +
-                                       "); raise nbr_capacity");
+                                       " exceeded (max count " + std::to_string(h.max_count) + ")");
   if (h.nonfinite) return qhp_fail(c, QHP_ENONFINITE, "state became non-finite");
   if (h.spread_margin)
     return qhp_fail(c, QHP_EUNSUPPORTED,
@@ -656,8 +679,54 @@ static int check_ctrl(qhp_ctx* c) {
   return QHP_OK;
 }
 
-extern "C" int qhp_eval(qhp_ctx* c, const double* pos, double* energy, double* forces, int mem_kind) {
-  if (!c || !pos) return qhp_fail(c, QHP_EINVAL, "null argument");
+static int check_ctrl(qhp_ctx* c) {
+  NlCtrl h;
+  int r = read_ctrl(c, &h);
+  return r ? r : ctrl_error(c, h);
+}
+
+// A list build found more neighbours than a row holds: grow the rows (at least 1.5 times,
+// and to the largest count seen plus a margin; at most N), clear the flag and have the
+// next list stage rebuild. Captured steps hold the old list buffer: they are recaptured.
+static int grow_list(qhp_ctx* c, int max_count) {
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  int cap = std::max(c->cap + c->cap / 2, max_count + max_count / 4 + 32);
+  cap = std::min((cap + 31) / 32 * 32, c->N);
+  if (cap <= c->cap) return qhp_fail(c, QHP_ENOMEM, "neighbour rows cannot grow further");
+  int* nbr = nullptr;
+  hipError_t e = hipMalloc((void**)&nbr, (size_t)cap * c->N * sizeof(int));
+  if (e != hipSuccess) return qhp_fail(c, QHP_ENOMEM, "neighbour rows: " + std::string(hipGetErrorString(e)));
+  (void)hipFree(c->nbr);
+  c->nbr = nbr;
+  c->cap = cap;
+  c->list_grown += 1;
+  NlCtrl h;
+  int r = read_ctrl(c, &h);
+  if (r) return r;
+  h.overflow = 0;
+  h.force_build = 1;
+  QHP_HIP(c, hipMemcpyAsync(c->ctrl, &h, sizeof(NlCtrl), hipMemcpyHostToDevice, c->stream));
+  QHP_HIP(c, hipStreamSynchronize(c->stream));
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  c->step_exec = nullptr;
+  ++c->graph_epoch;
+  return QHP_OK;
+}
+
+// Run a stateless evaluation (it builds its own list) until no list row overflows.
+template <class F>
+static int with_list_growth(qhp_ctx* c, F&& run) {
+  for (int attempt = 0;; ++attempt) {
+    int r = run();
+    if (r) return r;
+    NlCtrl h;
+    if ((r = read_ctrl(c, &h))) return r;
+    if (!h.overflow || attempt >= 16) return ctrl_error(c, h);
+    if ((r = grow_list(c, h.max_count))) return r;
+  }
+}
+
+static int eval_once(qhp_ctx* c, const double* pos, double* energy, double* forces, int mem_kind) {
   int r = copy_in(c, pos, mem_kind, c->x);
   if (r) return r;
   QHP_HIP(c, launch_centroid_of_beads(c));
@@ -667,7 +736,7 @@ extern "C" int qhp_eval(qhp_ctx* c, const double* pos, double* energy, double* f
   std::swap(c->g, c->g_eval);
   if (r) return r;
   if (forces) {
-    const size_t n = (size_t)c->P * c->N * 3;
+    const size_t n = (size_t)c->Pb * c->N * 3;
     if (mem_kind == QHP_MEM_HOST) {
       QHP_HIP(c, launch_transpose_out(c, c->g_eval, c->io_a, -1.0));
       QHP_HIP(c, hipMemcpyAsync(forces, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -675,9 +744,18 @@ extern "C" int qhp_eval(qhp_ctx* c, const double* pos, double* energy, double* f
       QHP_HIP(c, launch_transpose_out(c, c->g_eval, forces, -1.0));
     }
   }
-  if ((r = copy_out_energy(c, energy, mem_kind))) return r;
-  if (mem_kind == QHP_MEM_HOST) return check_ctrl(c);
-  return QHP_OK;
+  return copy_out_energy(c, energy, mem_kind);
+}
+
+extern "C" int qhp_eval(qhp_ctx* c, const double* pos, const double box[3], double* energy,
+                        double* forces, int mem_kind) {
+  if (!c || !pos) return qhp_fail(c, QHP_EINVAL, "null argument");
+  if (box)
+    for (int d = 0; d < 3; ++d)
+      if (!(std::fabs(box[d] - c->p.box[d]) <= 1e-12 * c->p.box[d]))
+        return qhp_fail(c, QHP_EINVAL, "the box differs from the context's (it is fixed per "
+                                       "context: create a context for another box)");
+  return with_list_growth(c, [&] { return eval_once(c, pos, energy, forces, mem_kind); });
 }
 
 extern "C" int qhp_set_lambda(qhp_ctx* c, double lambda_elec, double lambda_vdw) {
@@ -717,7 +795,7 @@ extern "C" int qhp_eval_lambda(qhp_ctx* c, const double* pos, double lambda_elec
   c->lam_e = lambda_elec;
   c->lam_v = lambda_vdw;
   c->self_energy = self_of(c, c->charge_alt);
-  int r = qhp_eval(c, pos, energy, forces, mem_kind);
+  int r = qhp_eval(c, pos, nullptr, energy, forces, mem_kind);
   std::swap(c->d_charge, c->d_charge_alt);
   c->lam_e = le;
   c->lam_v = lv;
@@ -879,31 +957,35 @@ extern "C" int qhp_param_grad(qhp_ctx* c, const double* pos, double* dq, double*
     return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients of an alchemical system");
   if (c->tether_k > 0)
     return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients with the test tether");
-  int r = copy_in(c, pos, mem_kind, c->x);
+  if (c->Pb != c->P)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients need a power-of-two bead count");
+  auto run = [&]() -> int {
+    int r = copy_in(c, pos, mem_kind, c->x);
+    if (r) return r;
+    QHP_HIP(c, launch_centroid_of_beads(c));
+    QHP_HIP(c, launch_zero(c, c->pg_dq, (size_t)c->N * sizeof(double)));
+    QHP_HIP(c, launch_zero(c, c->pg_lj, 2 * QHP_MAX_TYPES * sizeof(double)));
+    // forces go to scratch (c->g holds the propagated state's); the pair terms always take
+    // the FP64 kernel here
+    std::swap(c->g, c->g_eval);
+    BeadSet B = full_beads(c);
+    B.pgrad = 1;
+    hipError_t e = launch_nlist(c, false);
+    if (e == hipSuccess) e = launch_bonded(c, false, -1, &B);
+    if (e == hipSuccess) e = launch_pair(c, false, -1, &B);
+    if (e == hipSuccess) e = launch_spme(c, false, -1, &B);
+    std::swap(c->g, c->g_eval);
+    QHP_HIP(c, e);
+    return QHP_OK;
+  };
+  int r = with_list_growth(c, run);
   if (r) return r;
-  QHP_HIP(c, launch_centroid_of_beads(c));
-  QHP_HIP(c, launch_zero(c, c->pg_dq, (size_t)c->N * sizeof(double)));
-  QHP_HIP(c, launch_zero(c, c->pg_lj, 2 * QHP_MAX_TYPES * sizeof(double)));
-  // forces go to scratch (c->g holds the propagated state's); the pair terms always take
-  // the FP64 kernel here
-  std::swap(c->g, c->g_eval);
-  BeadSet B = full_beads(c);
-  B.pgrad = 1;
-  hipError_t e = launch_nlist(c, false);
-  if (e == hipSuccess) e = launch_bonded(c, false, -1, &B);
-  if (e == hipSuccess) e = launch_pair(c, false, -1, &B);
-  if (e == hipSuccess) e = launch_spme(c, false, -1, &B);
-  std::swap(c->g, c->g_eval);
-  QHP_HIP(c, e);
   const int T = c->p.n_types;
   const hipMemcpyKind k = mem_kind == QHP_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
   QHP_HIP(c, hipMemcpyAsync(dq, c->pg_dq, (size_t)c->N * sizeof(double), k, c->stream));
   QHP_HIP(c, hipMemcpyAsync(deps, c->pg_lj, T * sizeof(double), k, c->stream));
   QHP_HIP(c, hipMemcpyAsync(dsig, c->pg_lj + QHP_MAX_TYPES, T * sizeof(double), k, c->stream));
-  if (mem_kind == QHP_MEM_HOST) {
-    QHP_HIP(c, hipStreamSynchronize(c->stream));
-    return check_ctrl(c);
-  }
+  if (mem_kind == QHP_MEM_HOST) QHP_HIP(c, hipStreamSynchronize(c->stream));
   return QHP_OK;
 }
 
@@ -918,28 +1000,35 @@ extern "C" int qhp_hvp(qhp_ctx* c, const double* pos, const double* dir, double*
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products of an alchemical system");
   if (c->tether_k > 0)
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products with the test tether");
-  const size_t n = (size_t)c->P * c->N * 3;
+  if (c->Pb != c->P)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products need a power-of-two bead count");
+  const size_t n = (size_t)c->Pb * c->N * 3;
   if (!c->hvp_out) QHP_HIP(c, hipMalloc((void**)&c->hvp_out, n * sizeof(double)));
-  int r = copy_in(c, dir, mem_kind, c->io_b);
-  if (!r) r = copy_in(c, pos, mem_kind, c->x);
+  auto run = [&]() -> int {
+    int r = copy_in(c, dir, mem_kind, c->io_b);
+    if (!r) r = copy_in(c, pos, mem_kind, c->x);
+    if (r) return r;
+    QHP_HIP(c, launch_centroid_of_beads(c));
+    // the potential grid of these positions (and forces, into scratch)
+    std::swap(c->g, c->g_eval);
+    r = forces_all(c, false, false);
+    std::swap(c->g, c->g_eval);
+    if (r) return r;
+    if (mix) {
+      QHP_HIP(c, launch_zero(c, c->pg_dq, (size_t)c->N * sizeof(double)));
+      QHP_HIP(c, launch_zero(c, c->pg_lj, 2 * QHP_MAX_TYPES * sizeof(double)));
+    }
+    QHP_HIP(c, launch_bonded_hvp(c, c->io_b, c->hvp_out, mix));
+    BeadSet B = full_beads(c);
+    B.g = c->hvp_out;
+    B.hvp_u = c->io_b;
+    B.pgrad = mix ? 1 : 0;
+    QHP_HIP(c, launch_pair(c, false, -1, &B));
+    QHP_HIP(c, launch_spme_hvp(c, c->io_b, c->hvp_out, mix));
+    return QHP_OK;
+  };
+  int r = with_list_growth(c, run);
   if (r) return r;
-  QHP_HIP(c, launch_centroid_of_beads(c));
-  // the potential grid of these positions (and forces, into scratch)
-  std::swap(c->g, c->g_eval);
-  r = forces_all(c, false, false);
-  std::swap(c->g, c->g_eval);
-  if (r) return r;
-  if (mix) {
-    QHP_HIP(c, launch_zero(c, c->pg_dq, (size_t)c->N * sizeof(double)));
-    QHP_HIP(c, launch_zero(c, c->pg_lj, 2 * QHP_MAX_TYPES * sizeof(double)));
-  }
-  QHP_HIP(c, launch_bonded_hvp(c, c->io_b, c->hvp_out, mix));
-  BeadSet B = full_beads(c);
-  B.g = c->hvp_out;
-  B.hvp_u = c->io_b;
-  B.pgrad = mix ? 1 : 0;
-  QHP_HIP(c, launch_pair(c, false, -1, &B));
-  QHP_HIP(c, launch_spme_hvp(c, c->io_b, c->hvp_out, mix));
   const hipMemcpyKind k = mem_kind == QHP_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
   if (mix) {
     const int T = c->p.n_types;
@@ -951,7 +1040,7 @@ extern "C" int qhp_hvp(qhp_ctx* c, const double* pos, const double* dir, double*
     QHP_HIP(c, launch_transpose_out(c, c->hvp_out, c->io_a, 1.0));
     QHP_HIP(c, hipMemcpyAsync(out, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     QHP_HIP(c, hipStreamSynchronize(c->stream));
-    return check_ctrl(c);
+    return QHP_OK;
   }
   QHP_HIP(c, launch_transpose_out(c, c->hvp_out, out, 1.0));
   return QHP_OK;
@@ -962,29 +1051,35 @@ extern "C" int qhp_set_state(qhp_ctx* c, const double* pos, const double* vel, i
   if (step < 0) return qhp_fail(c, QHP_EINVAL, "step must be >= 0");
   if (c->p.thermostat == QHP_ADQTB && step % c->qtb.nseg)
     return qhp_fail(c, QHP_EINVAL, "adQTB state must start at a segment boundary");
-  // bead positions and velocities in the bead-innermost layout, whatever exec is
-  const int exec = c->p.exec;
-  c->p.exec = QHP_BATCHED;
-  int r = copy_in(c, pos, mem_kind, c->io_b);
-  if (!r) r = copy_in(c, vel, mem_kind, c->g);
-  c->p.exec = exec;
+  // everything from the inputs on is repeated if a list row overflows (the rows then grow)
+  auto run = [&]() -> int {
+    // bead positions and velocities in the bead-innermost layout, whatever exec is
+    const int exec = c->p.exec;
+    c->p.exec = QHP_BATCHED;
+    int r = copy_in(c, pos, mem_kind, c->io_b);
+    if (!r) r = copy_in(c, vel, mem_kind, c->g);
+    c->p.exec = exec;
+    if (r) return r;
+    QHP_HIP(c, launch_beads_to_modes(c, c->io_b, c->g));
+    // bead positions in the context's layout for the first force evaluation
+    r = copy_in(c, pos, mem_kind, c->x);
+    if (r) return r;
+    if (c->respa) {
+      // V_f on the beads, V_s on the contracted beads; Pa = P - (dt/2) f_f - (n dt/2) f_s
+      QHP_HIP(c, launch_contract(c));
+      if ((r = fast_forces(c, false))) return r;
+      if ((r = slow_forces(c, false, false))) return r;
+      QHP_HIP(c, launch_kick_back(c));
+      QHP_HIP(c, launch_kick_slow(c, c->Pa, c->Pa, -0.5 * c->nalt * c->p.dt));
+    } else {
+      QHP_HIP(c, launch_centroid_of_beads(c));
+      if ((r = forces_all(c, false, false))) return r;
+      QHP_HIP(c, launch_kick_back(c));          // store Pa = P - (dt/2) f
+    }
+    return QHP_OK;
+  };
+  int r = with_list_growth(c, run);
   if (r) return r;
-  QHP_HIP(c, launch_beads_to_modes(c, c->io_b, c->g));
-  // bead positions in the context's layout for the first force evaluation
-  r = copy_in(c, pos, mem_kind, c->x);
-  if (r) return r;
-  if (c->respa) {
-    // V_f on the beads, V_s on the contracted beads; Pa = P - (dt/2) f_f - (n dt/2) f_s
-    QHP_HIP(c, launch_contract(c));
-    if ((r = fast_forces(c, false))) return r;
-    if ((r = slow_forces(c, false, false))) return r;
-    QHP_HIP(c, launch_kick_back(c));
-    QHP_HIP(c, launch_kick_slow(c, c->Pa, c->Pa, -0.5 * c->nalt * c->p.dt));
-  } else {
-    QHP_HIP(c, launch_centroid_of_beads(c));
-    if ((r = forces_all(c, false, false))) return r;
-    QHP_HIP(c, launch_kick_back(c));          // store Pa = P - (dt/2) f
-  }
   c->step = step;
   {
     long long st = step;
@@ -1004,7 +1099,7 @@ extern "C" int qhp_get_state(qhp_ctx* c, double* pos, double* vel, int64_t* step
   if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
   if (step) *step = c->step;
   if (!pos && !vel) return QHP_OK;
-  const size_t n = (size_t)c->P * c->N * 3;
+  const size_t n = (size_t)c->Pb * c->N * 3;
   const double* pa = c->Pa;
   if (c->respa) {          // momenta with the pending slow kick (n dt/2) f_s
     QHP_HIP(c, launch_kick_slow(c, c->pa_tmp, c->Pa, 0.5 * c->nalt * c->p.dt));
@@ -1061,13 +1156,43 @@ static int capture_step(qhp_ctx* c) {
   return QHP_OK;
 }
 
-extern "C" int qhp_step(qhp_ctx* c, int32_t nsteps, double* energy, int mem_kind) {
-  if (!c) return QHP_EINVAL;
-  if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
-  if (nsteps < 0) return qhp_fail(c, QHP_EINVAL, "nsteps must be >= 0");
+// The propagated state a call to qhp_step starts from, kept on the device so that the call
+// can be repeated when a list build overflows its rows: modes, momenta, gradients, the
+// control block (step counter, build bookkeeping) and the adQTB adaptation state. The
+// coloured noise of the segment and the recorded velocities are rewritten by the repeat.
+static int snapshot(qhp_ctx* c, bool save) {
+  const size_t NP3 = (size_t)3 * c->N * c->P;
+  const size_t NS3 = c->respa ? (size_t)3 * c->N * c->Ps : 0;
+  const size_t nk = c->p.thermostat == QHP_ADQTB ? (size_t)c->p.n_types * (c->qtb.nseg + 1) : 0;
+  double* parts[] = {c->Q, c->Pa, c->g, c->gs, c->qtb.gamma, c->qtb.dbar, c->qtb.avg_vv,
+                     c->qtb.avg_vf};
+  const size_t sizes[] = {NP3, NP3, NP3, NS3, nk, nk, c->qtb.avg_vv ? nk : 0,
+                          c->qtb.avg_vf ? nk : 0};
+  size_t total = 0;
+  for (size_t z : sizes) total += z;
+  if (!c->snap) {
+    if (!save) return QHP_OK;
+    QHP_HIP(c, hipMalloc((void**)&c->snap, total * sizeof(double)));
+    QHP_HIP(c, hipMalloc((void**)&c->snap_ctrl, sizeof(NlCtrl)));
+  }
+  size_t off = 0;
+  for (int k = 0; k < 8; ++k) {
+    if (sizes[k] == 0) continue;
+    void* dst = save ? (void*)(c->snap + off) : (void*)parts[k];
+    const void* src = save ? (const void*)parts[k] : (const void*)(c->snap + off);
+    QHP_HIP(c, hipMemcpyAsync(dst, src, sizes[k] * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    off += sizes[k];
+  }
+  QHP_HIP(c, hipMemcpyAsync(save ? (void*)c->snap_ctrl : (void*)c->ctrl,
+                            save ? (const void*)c->ctrl : (const void*)c->snap_ctrl,
+                            sizeof(NlCtrl), hipMemcpyDeviceToDevice, c->stream));
+  return QHP_OK;
+}
+
+static int run_steps(qhp_ctx* c, int32_t nsteps, bool want_energy) {
   const bool qtb = c->p.thermostat == QHP_ADQTB;
   for (int s = 0; s < nsteps; ++s) {
-    const bool want_e = energy != nullptr && s == nsteps - 1;
+    const bool want_e = want_energy && s == nsteps - 1;
     const bool graph = c->use_graph && !want_e && c->prof_which == QHP_PROF_OFF;
     if (graph) {
       if (!c->step_exec) {
@@ -1085,9 +1210,37 @@ extern "C" int qhp_step(qhp_ctx* c, int32_t nsteps, double* energy, int mem_kind
       QHP_HIP(c, launch_qtb_generate(c, c->step / c->qtb.nseg));
     }
   }
-  int r = copy_out_energy(c, nsteps > 0 ? energy : nullptr, mem_kind);
-  if (r) return r;
-  return check_ctrl(c);
+  return QHP_OK;
+}
+
+extern "C" int qhp_step(qhp_ctx* c, int32_t nsteps, double* energy, int mem_kind) {
+  if (!c) return QHP_EINVAL;
+  if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
+  if (nsteps < 0) return qhp_fail(c, QHP_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return check_ctrl(c);
+  // rows of N entries cannot overflow; otherwise keep the starting state for a repeat
+  const bool guard = c->cap < c->N;
+  const int64_t step0 = c->step;
+  if (guard) {
+    int r = snapshot(c, true);
+    if (r) return r;
+  }
+  for (int attempt = 0;; ++attempt) {
+    int r = run_steps(c, nsteps, energy != nullptr);
+    if (r) return r;
+    NlCtrl h;
+    if ((r = read_ctrl(c, &h))) return r;
+    if (!h.overflow || !guard || attempt >= 16) {
+      if ((r = ctrl_error(c, h))) return r;
+      break;
+    }
+    // a build ran out of row space: back to the starting state, larger rows, again
+    if ((r = snapshot(c, false))) return r;
+    c->step = step0;
+    if ((r = grow_list(c, h.max_count))) return r;
+    if (c->p.thermostat == QHP_ADQTB) QHP_HIP(c, launch_qtb_generate(c, step0 / c->qtb.nseg));
+  }
+  return copy_out_energy(c, energy, mem_kind);
 }
 
 extern "C" int qhp_mode_energies(qhp_ctx* c, double* kinetic, double* spring) {
@@ -1146,7 +1299,7 @@ extern "C" int qhp_noise_export(qhp_ctx* c, int32_t stream, int64_t step, double
   if (stream == 5 && step < 0) return qhp_fail(c, QHP_EINVAL, "step must be >= 0");
   if (stream == 6 && step + c->p.qtb_nseg < 0)
     return qhp_fail(c, QHP_EINVAL, "white-noise step must be >= -N_seg");
-  const size_t n = (size_t)(stream == 5 ? c->P : 1) * c->N * 3;
+  const size_t n = (size_t)(stream == 5 ? c->Pb : 1) * c->N * 3;
   QHP_HIP(c, launch_noise_export(c, stream, step, c->io_a));
   QHP_HIP(c, hipMemcpyAsync(out, c->io_a, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   QHP_HIP(c, hipStreamSynchronize(c->stream));
@@ -1335,34 +1488,68 @@ extern "C" int qhp_group_step(qhp_group* g, int32_t nsteps) {
     if (!c->have_state) return group_fail(g, QHP_EINVAL, "member " + std::to_string(i) + " has no state");
     if (!c->use_graph) return group_fail(g, QHP_EINVAL, "members need use_graph = 1");
     if (c->prof_which != QHP_PROF_OFF) return group_fail(g, QHP_EINVAL, "members must not be profiling");
-    if (g->epoch[i] != c->graph_epoch && g->exec) {
-      (void)hipGraphExecDestroy(g->exec);
-      g->exec = nullptr;
-    }
   }
   if (nsteps == 0) return QHP_OK;
-  // the members' own queued work must be done before the origin stream runs the graph
-  for (int i = 1; i < n; ++i) {
-    hipError_t e = hipEventRecord(g->ev[i], g->m[i]->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(g->m[0]->stream, g->ev[i], 0);
-    if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, hipGetErrorString(e));
-  }
-  if (!g->exec) {
-    int r = group_capture(g);
-    if (r) return r;
-  }
-  for (int s = 0; s < nsteps; ++s) {
-    hipError_t e = hipGraphLaunch(g->exec, g->m[0]->stream);
-    if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, std::string("group launch: ") + hipGetErrorString(e));
-    for (int i = 0; i < n; ++i) g->m[i]->step += g->m[i]->nalt;
-  }
-  // later work queued on a member's own stream follows the group's steps
-  hipError_t e = hipEventRecord(g->ev[0], g->m[0]->stream);
-  for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(g->m[i]->stream, g->ev[0], 0);
-  if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, hipGetErrorString(e));
+  // if any member's rows can overflow, every member keeps its starting state: a repeat
+  // restarts all of them
+  bool guard = false;
+  for (int i = 0; i < n; ++i) guard = guard || g->m[i]->cap < g->m[i]->N;
+  std::vector<int64_t> step0(n);
   for (int i = 0; i < n; ++i) {
-    int r = check_ctrl(g->m[i]);
-    if (r) return group_fail(g, r, "member " + std::to_string(i) + ": " + g->m[i]->err);
+    qhp_ctx* c = g->m[i];
+    step0[i] = c->step;
+    if (guard) {
+      int r = snapshot(c, true);
+      if (r) return group_fail(g, r, "member " + std::to_string(i) + ": " + c->err);
+    }
   }
-  return QHP_OK;
+  for (int attempt = 0;; ++attempt) {
+    for (int i = 0; i < n; ++i)
+      if (g->epoch[i] != g->m[i]->graph_epoch && g->exec) {
+        (void)hipGraphExecDestroy(g->exec);
+        g->exec = nullptr;
+      }
+    // the members' own queued work must be done before the origin stream runs the graph
+    for (int i = 1; i < n; ++i) {
+      hipError_t e = hipEventRecord(g->ev[i], g->m[i]->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(g->m[0]->stream, g->ev[i], 0);
+      if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, hipGetErrorString(e));
+    }
+    if (!g->exec) {
+      int r = group_capture(g);
+      if (r) return r;
+    }
+    for (int s = 0; s < nsteps; ++s) {
+      hipError_t e = hipGraphLaunch(g->exec, g->m[0]->stream);
+      if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, std::string("group launch: ") + hipGetErrorString(e));
+      for (int i = 0; i < n; ++i) g->m[i]->step += g->m[i]->nalt;
+    }
+    // later work queued on a member's own stream follows the group's steps
+    hipError_t e = hipEventRecord(g->ev[0], g->m[0]->stream);
+    for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(g->m[i]->stream, g->ev[0], 0);
+    if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, hipGetErrorString(e));
+    bool again = false;
+    std::vector<NlCtrl> h(n);
+    for (int i = 0; i < n; ++i) {
+      int r = read_ctrl(g->m[i], &h[i]);
+      if (r) return group_fail(g, r, "member " + std::to_string(i) + ": " + g->m[i]->err);
+      if (h[i].overflow && guard && attempt < 16) again = true;
+    }
+    if (!again) {
+      for (int i = 0; i < n; ++i) {
+        int r = ctrl_error(g->m[i], h[i]);
+        if (r) return group_fail(g, r, "member " + std::to_string(i) + ": " + g->m[i]->err);
+      }
+      return QHP_OK;
+    }
+    // a member's list build ran out of row space: every member back to its starting
+    // state, larger rows where needed, the group step recaptured and repeated
+    for (int i = 0; i < n; ++i) {
+      qhp_ctx* c = g->m[i];
+      int r = snapshot(c, false);
+      c->step = step0[i];
+      if (!r && h[i].overflow) r = grow_list(c, h[i].max_count);
+      if (r) return group_fail(g, r, "member " + std::to_string(i) + ": " + c->err);
+    }
+  }
 }

@@ -241,6 +241,14 @@ __global__ void k_energy_init(double* energy, int rows, int self_rows, double se
     energy[i] = (i % QHP_NTERMS == QHP_E_COUL_SELF && i / QHP_NTERMS < self_rows) ? self : 0.0;
 }
 
+// zero the terms evaluated on the contracted beads (all but bonds and angles) in rows
+// [r0, r1) of the energy table
+__global__ void k_clear_slow_energy(double* energy, int r0, int r1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = r0 + i / QHP_NTERMS, t = i % QHP_NTERMS;
+  if (row < r1 && t != QHP_E_BOND && t != QHP_E_ANGLE) energy[(size_t)row * QHP_NTERMS + t] = 0.0;
+}
+
 __global__ void k_zero(double* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -314,7 +322,7 @@ hipError_t launch_bonded(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   // contraction the self term belongs to the contracted beads only
   if (energy && bead <= 0 && (terms & QHP_TERMS_BONDED)) {
     const int rows = plain ? c->P : B.P;
-    const int self_rows = terms == QHP_TERMS_ALL ? rows : c->Ps;
+    const int self_rows = terms == QHP_TERMS_ALL ? (plain ? c->Pb : B.P) : c->Psb;
     hipLaunchKernelGGL(k_energy_init, (rows * QHP_NTERMS + 511) / 512, 512, 0, c->stream,
                        plain ? c->energy : B.energy, rows, self_rows, c->self_energy);
   }
@@ -341,6 +349,13 @@ hipError_t launch_bonded_hvp(qhp_ctx* c, const double* u, double* hu, bool mix) 
   const int P = c->P;
   const unsigned nb = (unsigned)((c->NW + NT / P - 1) / (NT / P));
   QHP_SWITCH_P(P, hipLaunchKernelGGL((k_bonded_hvp<PP>), nb, NT, 0, c->stream, A, u, hu));
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_slow_energy(qhp_ctx* c, int r0, int r1) {
+  const int n = (r1 - r0) * QHP_NTERMS;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_clear_slow_energy, (n + 255) / 256, 256, 0, c->stream, c->energy, r0, r1);
   return hipGetLastError();
 }
 

@@ -38,7 +38,8 @@ struct NmArgs {
   const double* Cs;        // [Ps][Ps] contraction matrix C[j][n]
   double* xs;              // [3][N][Ps] contracted beads (written when emit)
   float4* xfs;             // [N][Ps]
-  int Ps, step_off, emit;
+  int Ps, step_off, emit;     // Ps: lanes of the contracted set (phantoms beyond Psb)
+  double sP, rsP, sPs, rsPs;  // sqrt and 1/sqrt of the real bead counts Pb and Psb
   double slow_h;           // factor of the slow kick this inner step (0: none)
   qhp::BinGeom bins;       // SPME tile and list cell of every centroid (when emitting)
 };
@@ -127,10 +128,10 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
   __syncthreads();
   double fT[3];
   contract3<P>(sTc, sh[al], n, fT);
-  const double rsP = 1.0 / sqrt((double)P);
+  const double rsP = A.rsP;
   double fsl[3] = {0.0, 0.0, 0.0};
   if (RESPA && A.slow_h != 0.0 && n < Ps) {
-    const double rsPs = 1.0 / sqrt((double)Ps);
+    const double rsPs = A.rsPs;
     for (int d = 0; d < 3; ++d) {
       double acc = 0.0;
       for (int j = 0; j < Ps; ++j) acc += sC[j * Ps + n] * sgs[al][d][j];
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
   int moff = 0, mbad = 0;
   const bool emit = !RESPA || A.emit;
   if (live) {
-    const double sP = sqrt((double)P);
+    const double sP = A.sP;
     double xb[3], c[3], sx[3];
     // x_n = Q_0 + sqrt(P) sum_{k>=1} T[n][k] Q_k (the k = 0 term enters as Q_0 itself)
     contract3<P>(sTr, sh[al], n, sx);
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
     if (RESPA && emit) {
       own = n < Ps;
       if (own) {
-        const double sPs = sqrt((double)Ps);
+        const double sPs = A.sPs;
         for (int d = 0; d < 3; ++d) {
           double acc = 0.0;
           for (int k = 1; k < Ps; ++k) acc += sC[n * Ps + k] * sh[al][d][k];
@@ -260,9 +261,9 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
 
 // Q = T^T x / sqrt(P), Pm = m T^T v / sqrt(P); inputs bead-innermost [3][N][P].
 template <int P>
-__global__ __launch_bounds__(NT) void k_to_modes(int N, const double* xb, const double* vb,
-                                                 const double* T, const double* mass,
-                                                 double* Q, double* Pm) {
+__global__ __launch_bounds__(NT) void k_to_modes(int N, double rsP, const double* xb,
+                                                 const double* vb, const double* T,
+                                                 const double* mass, double* Q, double* Pm) {
   constexpr int AT = NT / P;
   __shared__ double sT[P * P];
   __shared__ double sx[AT][6][P];
@@ -275,7 +276,6 @@ __global__ __launch_bounds__(NT) void k_to_modes(int N, const double* xb, const 
   }
   __syncthreads();
   if (!live) return;
-  const double rsP = 1.0 / sqrt((double)P);
   const double m = mass[a];
   for (int d = 0; d < 3; ++d) {
     double sq = 0, sv = 0;
@@ -290,8 +290,8 @@ __global__ __launch_bounds__(NT) void k_to_modes(int N, const double* xb, const 
 
 // Pa += s * f with f = -T^T g / sqrt(P) (g in the context's layout).
 template <int P, bool BEADMAJOR>
-__global__ __launch_bounds__(NT) void k_kick(int N, double* Pa, const double* g, const double* T,
-                                             double s) {
+__global__ __launch_bounds__(NT) void k_kick(int N, double rsP, double* Pa, const double* g,
+                                             const double* T, double s) {
   constexpr int AT = NT / P;
   __shared__ double sT[P * P];
   __shared__ double sg[AT][3][P];
@@ -301,7 +301,6 @@ __global__ __launch_bounds__(NT) void k_kick(int N, double* Pa, const double* g,
   for (int d = 0; d < 3; ++d) sg[al][d][n] = live ? g[gidx<P, BEADMAJOR>(N, d, a, n)] : 0.0;
   __syncthreads();
   if (!live) return;
-  const double rsP = 1.0 / sqrt((double)P);
   for (int d = 0; d < 3; ++d) {
     double f = 0;
     for (int i = 0; i < P; ++i) f += sT[i * P + n] * sg[al][d][i];
@@ -311,10 +310,10 @@ __global__ __launch_bounds__(NT) void k_kick(int N, double* Pa, const double* g,
 
 // Bead positions and velocities [P][N][3] from (Q, Pa + h f).
 template <int P, bool BEADMAJOR>
-__global__ __launch_bounds__(NT) void k_state_out(int N, const double* Q, const double* Pa,
-                                                  const double* g, const double* T,
-                                                  const double* mass, double h, double* xo,
-                                                  double* vo) {
+__global__ __launch_bounds__(NT) void k_state_out(int N, int Pb, double rsP, const double* Q,
+                                                  const double* Pa, const double* g,
+                                                  const double* T, const double* mass, double h,
+                                                  double* xo, double* vo) {
   constexpr int AT = NT / P;
   __shared__ double sT[P * P];
   __shared__ double sh[AT][6][P];
@@ -323,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_state_out(int N, const double* Q, const 
   const bool live = a < N;
   for (int d = 0; d < 3; ++d) sh[al][3 + d][n] = live ? g[gidx<P, BEADMAJOR>(N, d, a, n)] : 0.0;
   __syncthreads();
-  const double rsP = 1.0 / sqrt((double)P), sP = sqrt((double)P);
+  const double sP = 1.0 / rsP;
   double pn[3] = {0, 0, 0}, qn[3] = {0, 0, 0};
   if (live)
     for (int d = 0; d < 3; ++d) {
@@ -335,7 +334,7 @@ __global__ __launch_bounds__(NT) void k_state_out(int N, const double* Q, const 
   __syncthreads();
   for (int d = 0; d < 3; ++d) { sh[al][d][n] = qn[d]; sh[al][3 + d][n] = pn[d]; }
   __syncthreads();
-  if (!live) return;
+  if (!live || n >= Pb) return;      // phantom beads are not reported
   const double im = 1.0 / mass[a];
   for (int d = 0; d < 3; ++d) {
     double sx = 0, sv = 0;
@@ -350,10 +349,10 @@ __global__ __launch_bounds__(NT) void k_state_out(int N, const double* Q, const 
 
 // kinetic sum (Pa + h f)^2 / 2m and spring sum m w^2 Q^2 / 2 -> out[0], out[1]
 template <int P, bool BEADMAJOR>
-__global__ __launch_bounds__(NT) void k_mode_energy(int N, const double* Q, const double* Pa,
-                                                    const double* g, const double* T,
-                                                    const double* mass, const double* w2,
-                                                    double h, double* out) {
+__global__ __launch_bounds__(NT) void k_mode_energy(int N, double rsP, const double* Q,
+                                                    const double* Pa, const double* g,
+                                                    const double* T, const double* mass,
+                                                    const double* w2, double h, double* out) {
   constexpr int AT = NT / P;
   __shared__ double sT[P * P];
   __shared__ double sg[AT][3][P];
@@ -364,7 +363,7 @@ __global__ __launch_bounds__(NT) void k_mode_energy(int N, const double* Q, cons
   __syncthreads();
   double ek = 0, es = 0;
   if (live) {
-    const double rsP = 1.0 / sqrt((double)P), m = mass[a];
+    const double m = mass[a];
     for (int d = 0; d < 3; ++d) {
       double f = 0;
       for (int i = 0; i < P; ++i) f += sT[i * P + n] * sg[al][d][i];
@@ -381,8 +380,9 @@ __global__ __launch_bounds__(NT) void k_mode_energy(int N, const double* Q, cons
 // dst = src + s * f_s on the modes n < Ps, f_s = -(1/sqrt(Ps)) sum_j C[j][n] g_s(j) (the slow
 // forces of ring-polymer contraction); the other modes are copied.
 template <int P>
-__global__ __launch_bounds__(NT) void k_kick_slow(int N, int Ps, double* dst, const double* src,
-                                                  const double* gs, const double* C, double s) {
+__global__ __launch_bounds__(NT) void k_kick_slow(int N, int Ps, double rsPs, double* dst,
+                                                  const double* src, const double* gs,
+                                                  const double* C, double s) {
   constexpr int AT = NT / P;
   __shared__ double sC[P * P];
   __shared__ double sg[AT][3][P];
@@ -392,7 +392,6 @@ __global__ __launch_bounds__(NT) void k_kick_slow(int N, int Ps, double* dst, co
   for (int d = 0; d < 3; ++d) sg[al][d][n] = (live && n < Ps) ? gs[(d * N + a) * Ps + n] : 0.0;
   __syncthreads();
   if (!live) return;
-  const double rsPs = 1.0 / sqrt((double)Ps);
   for (int d = 0; d < 3; ++d) {
     double f = 0.0;
     if (n < Ps)
@@ -406,6 +405,8 @@ __global__ __launch_bounds__(NT) void k_kick_slow(int N, int Ps, double* dst, co
 // also the block maxima of the bead-centroid distance and grid-base offset
 struct CentArgs {
   int N;
+  int Pb;                   // real beads (the centroid is their mean; the others are phantoms)
+  double sPs;               // k_contract: sqrt of the real contracted bead count
   const double* x; double4* cent; float4* xf; const double* charge;
   double4* bmax;
   double KoL[3];
@@ -423,8 +424,8 @@ __global__ __launch_bounds__(128) void k_centroid_beads(CentArgs A) {
     double c[3];
     for (int d = 0; d < 3; ++d) {
       double s = A.x[gidx<P, BEADMAJOR>(A.N, d, a, 0)];
-      for (int b = 1; b < P; ++b) s = s + A.x[gidx<P, BEADMAJOR>(A.N, d, a, b)];
-      c[d] = s / (double)P;
+      for (int b = 1; b < A.Pb; ++b) s = s + A.x[gidx<P, BEADMAJOR>(A.N, d, a, b)];
+      c[d] = s / (double)A.Pb;
     }
     qhp::write_bins(A.bins, a, c[0], c[1], c[2]);
     for (int b = 0; b < P; ++b) {
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(NT) void k_contract(CentArgs A, int Ps, const doubl
   double db2 = 0;
   int moff = 0, mbad = 0;
   if (live && n < Ps) {
-    const double sPs = sqrt((double)Ps);
+    const double sPs = A.sPs;
     double xb[3], c[3];
     for (int d = 0; d < 3; ++d) {
       double acc = 0.0;
@@ -504,20 +505,24 @@ __global__ __launch_bounds__(NT) void k_contract(CentArgs A, int Ps, const doubl
   }
 }
 
-// boundary [P][N][3] <-> internal layout
+// boundary [Pb][N][3] <-> internal layout of P >= Pb bead lanes; phantom lanes (b >= Pb)
+// receive a copy of bead 0 (a valid position whose results nothing reads)
 template <bool BEADMAJOR>
-__global__ void k_transpose_in(int N, int P, const double* src, double* dst) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)P * N * 3) return;
-  const int d = i % 3, a = (i / 3) % N, b = i / (3 * (size_t)N);
-  const size_t o = BEADMAJOR ? ((size_t)b * 3 + d) * N + a : ((size_t)d * N + a) * P + b;
+__global__ void k_transpose_in(int N, int P, int Pb, const double* src, double* dst) {
+  const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= (size_t)P * N * 3) return;
+  int b, d, a;
+  if (BEADMAJOR) { a = o % N; d = (o / N) % 3; b = o / (3 * (size_t)N); }
+  else { b = o % P; a = (o / P) % N; d = o / ((size_t)P * N); }
+  const size_t i = ((size_t)(b < Pb ? b : 0) * N + a) * 3 + d;
   dst[o] = src[i];
 }
 
 template <bool BEADMAJOR>
-__global__ void k_transpose_out(int N, int P, const double* src, double* dst, double scale) {
+__global__ void k_transpose_out(int N, int P, int Pb, const double* src, double* dst,
+                                double scale) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)P * N * 3) return;
+  if (i >= (size_t)Pb * N * 3) return;
   const int d = i % 3, a = (i / 3) % N, b = i / (3 * (size_t)N);
   const size_t o = BEADMAJOR ? ((size_t)b * 3 + d) * N + a : ((size_t)d * N + a) * P + b;
   dst[i] = scale * src[o];
@@ -553,6 +558,8 @@ hipError_t launch_nm_step(qhp_ctx* c, int inner, double slow_h, bool emit) {
   A.nseg = qtb ? c->qtb.nseg : 1;
   A.qc1 = c->qtb.c1; A.qosd = c->qtb.osd;
   A.gs = c->gs; A.Cs = c->Cs; A.xs = c->xs; A.xfs = c->xfs; A.Ps = c->Ps;
+  A.sP = sqrt((double)c->Pb); A.rsP = 1.0 / A.sP;
+  A.sPs = sqrt((double)(c->Psb > 0 ? c->Psb : 1)); A.rsPs = 1.0 / A.sPs;
   A.step_off = inner; A.emit = emit ? 1 : 0; A.slow_h = slow_h;
   A.bins = bin_geom(c);
   const bool bm = c->p.exec == QHP_PLAIN;
@@ -581,55 +588,60 @@ hipError_t launch_nm_step(qhp_ctx* c, int inner, double slow_h, bool emit) {
 
 hipError_t launch_beads_to_modes(qhp_ctx* c, const double* xb, const double* vb) {
   const unsigned nb = nblocks_atoms(c->N, c->P);
-  QHP_SWITCH_P(c->P, hipLaunchKernelGGL((k_to_modes<PP>), nb, NT, 0, c->stream, c->N, xb, vb,
-                                        c->T, c->d_mass, c->Q, c->Pa));
+  const double rsP = 1.0 / sqrt((double)c->Pb);
+  QHP_SWITCH_P(c->P, hipLaunchKernelGGL((k_to_modes<PP>), nb, NT, 0, c->stream, c->N, rsP, xb,
+                                        vb, c->T, c->d_mass, c->Q, c->Pa));
   return hipGetLastError();
 }
 
 hipError_t launch_kick_back(qhp_ctx* c) {
   const unsigned nb = nblocks_atoms(c->N, c->P);
   const bool bm = c->p.exec == QHP_PLAIN;
-  const double s = -0.5 * c->p.dt;
+  const double s = -0.5 * c->p.dt, rsP = 1.0 / sqrt((double)c->Pb);
   QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_kick<PP, true>), nb, NT, 0, c->stream, c->N,
-                                                 c->Pa, c->g, c->T, s);
-               else hipLaunchKernelGGL((k_kick<PP, false>), nb, NT, 0, c->stream, c->N, c->Pa,
-                                       c->g, c->T, s));
+                                                 rsP, c->Pa, c->g, c->T, s);
+               else hipLaunchKernelGGL((k_kick<PP, false>), nb, NT, 0, c->stream, c->N, rsP,
+                                       c->Pa, c->g, c->T, s));
   return hipGetLastError();
 }
 
 hipError_t launch_state_out(qhp_ctx* c, double* xo, double* vo, const double* pa) {
   const unsigned nb = nblocks_atoms(c->N, c->P);
   const bool bm = c->p.exec == QHP_PLAIN;
-  const double h = 0.5 * c->p.dt;
+  const double h = 0.5 * c->p.dt, rsP = 1.0 / sqrt((double)c->Pb);
   QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_state_out<PP, true>), nb, NT, 0, c->stream,
-                                                 c->N, c->Q, pa, c->g, c->T, c->d_mass, h, xo, vo);
-               else hipLaunchKernelGGL((k_state_out<PP, false>), nb, NT, 0, c->stream, c->N, c->Q,
-                                       pa, c->g, c->T, c->d_mass, h, xo, vo));
+                                                 c->N, c->Pb, rsP, c->Q, pa, c->g, c->T,
+                                                 c->d_mass, h, xo, vo);
+               else hipLaunchKernelGGL((k_state_out<PP, false>), nb, NT, 0, c->stream, c->N,
+                                       c->Pb, rsP, c->Q, pa, c->g, c->T, c->d_mass, h, xo, vo));
   return hipGetLastError();
 }
 
 hipError_t launch_mode_energies(qhp_ctx* c, double* out2, const double* pa) {
   const unsigned nb = nblocks_atoms(c->N, c->P);
   const bool bm = c->p.exec == QHP_PLAIN;
-  const double h = 0.5 * c->p.dt;
+  const double h = 0.5 * c->p.dt, rsP = 1.0 / sqrt((double)c->Pb);
   QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_mode_energy<PP, true>), nb, NT, 0, c->stream,
-                                                 c->N, c->Q, pa, c->g, c->T, c->d_mass,
+                                                 c->N, rsP, c->Q, pa, c->g, c->T, c->d_mass,
                                                  c->mode_w2, h, out2);
                else hipLaunchKernelGGL((k_mode_energy<PP, false>), nb, NT, 0, c->stream, c->N,
-                                       c->Q, pa, c->g, c->T, c->d_mass, c->mode_w2, h, out2));
+                                       rsP, c->Q, pa, c->g, c->T, c->d_mass, c->mode_w2, h,
+                                       out2));
   return hipGetLastError();
 }
 
 hipError_t launch_kick_slow(qhp_ctx* c, double* dst, const double* src, double s) {
   const unsigned nb = nblocks_atoms(c->N, c->P);
+  const double rsPs = 1.0 / sqrt((double)c->Psb);
   QHP_SWITCH_P(c->P, hipLaunchKernelGGL((k_kick_slow<PP>), nb, NT, 0, c->stream, c->N, c->Ps,
-                                        dst, src, c->gs, c->Cs, s));
+                                        rsPs, dst, src, c->gs, c->Cs, s));
   return hipGetLastError();
 }
 
 hipError_t launch_contract(qhp_ctx* c) {
   CentArgs A;
   A.N = c->N; A.x = c->Q; A.cent = c->cent; A.charge = c->d_charge; A.bmax = c->bmax;
+  A.Pb = c->Pb; A.sPs = sqrt((double)c->Psb);
   A.xf = c->p.precision == QHP_FP32_PAIRS ? c->xfs : nullptr;
   A.bins = bin_geom(c);
   for (int d = 0; d < 3; ++d) { A.K[d] = c->K[d]; A.KoL[d] = c->K[d] / c->p.box[d]; }
@@ -645,6 +657,7 @@ hipError_t launch_centroid_of_beads(qhp_ctx* c) {
   const bool bm = c->p.exec == QHP_PLAIN;
   CentArgs A;
   A.N = c->N; A.x = c->x; A.cent = c->cent; A.charge = c->d_charge; A.bmax = c->bmax;
+  A.Pb = c->Pb; A.sPs = 1.0;
   A.xf = (c->p.precision == QHP_FP32_PAIRS && !bm) ? c->xf : nullptr;
   A.bins = bin_geom(c);
   for (int d = 0; d < 3; ++d) { A.K[d] = c->K[d]; A.KoL[d] = c->K[d] / c->p.box[d]; }
@@ -660,19 +673,21 @@ hipError_t launch_transpose_in(qhp_ctx* c, const double* src, double* dst) {
   const size_t n = (size_t)c->P * c->N * 3;
   const unsigned nb = (unsigned)((n + 255) / 256);
   if (c->p.exec == QHP_PLAIN)
-    hipLaunchKernelGGL(k_transpose_in<true>, nb, 256, 0, c->stream, c->N, c->P, src, dst);
+    hipLaunchKernelGGL(k_transpose_in<true>, nb, 256, 0, c->stream, c->N, c->P, c->Pb, src, dst);
   else
-    hipLaunchKernelGGL(k_transpose_in<false>, nb, 256, 0, c->stream, c->N, c->P, src, dst);
+    hipLaunchKernelGGL(k_transpose_in<false>, nb, 256, 0, c->stream, c->N, c->P, c->Pb, src, dst);
   return hipGetLastError();
 }
 
 hipError_t launch_transpose_out(qhp_ctx* c, const double* src, double* dst, double scale) {
-  const size_t n = (size_t)c->P * c->N * 3;
+  const size_t n = (size_t)c->Pb * c->N * 3;
   const unsigned nb = (unsigned)((n + 255) / 256);
   if (c->p.exec == QHP_PLAIN)
-    hipLaunchKernelGGL(k_transpose_out<true>, nb, 256, 0, c->stream, c->N, c->P, src, dst, scale);
+    hipLaunchKernelGGL(k_transpose_out<true>, nb, 256, 0, c->stream, c->N, c->P, c->Pb, src, dst,
+                       scale);
   else
-    hipLaunchKernelGGL(k_transpose_out<false>, nb, 256, 0, c->stream, c->N, c->P, src, dst, scale);
+    hipLaunchKernelGGL(k_transpose_out<false>, nb, 256, 0, c->stream, c->N, c->P, c->Pb, src,
+                       dst, scale);
   return hipGetLastError();
 }
 
@@ -691,7 +706,7 @@ __global__ void k_noise(uint64_t seed, uint64_t stream, uint64_t c0, int N, int 
 }  // namespace
 
 hipError_t launch_noise_export(qhp_ctx* c, int stream, int64_t step, double* out) {
-  const int P = stream == 5 ? c->P : 1;
+  const int P = stream == 5 ? c->Pb : 1;
   const uint64_t c0 = stream == 5 ? (uint64_t)step : (uint64_t)(step + c->p.qtb_nseg);
   hipLaunchKernelGGL(k_noise, (c->N * P + 255) / 256, 256, 0, c->stream, c->p.seed,
                      (uint64_t)stream, c0, c->N, P, out);

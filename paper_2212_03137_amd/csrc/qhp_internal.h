@@ -39,7 +39,7 @@ struct NlCtrl {               // device-side control block (neighbour list, step
 // The beads a force launch works on: the full ring polymer, or its contraction (V_s under
 // ring-polymer contraction), or a scratch gradient target (stateless evaluation).
 struct BeadSet {
-  int P;                      // beads (a power of two)
+  int P;                      // bead lanes (a power of two; phantom beads beyond the real ones)
   int Pc;                     // complex SPME grid slots, max(1, P / 2)
   const double* x;            // [3][N][P]
   double* g;                  // [3][N][P] grad V (initialised by launch_bonded)
@@ -77,7 +77,8 @@ struct QtbState {
 
 struct qhp_ctx {
   qhp_params p;
-  int N, P, NW, Pc;           // atoms, beads, waters, complex grid batch
+  int N, P, NW, Pc;           // atoms, bead lanes (a power of two), waters, complex grid batch
+  int Pb;                     // beads of the ring polymer (<= P; the rest are phantoms)
   hipStream_t stream;
   bool own_stream = false;    // created here because the caller passed none
   // second stream of the bead-batched force evaluation (default priority): the SPME
@@ -175,7 +176,8 @@ struct qhp_ctx {
 
   // multiple time stepping and ring-polymer contraction
   bool respa = false;         // rpc_beads < P or respa_nalt > 1
-  int Ps = 0, nalt = 1;       // contracted beads, inner steps per outer step
+  int Ps = 0, nalt = 1;       // contracted bead lanes (a power of two), inner steps per outer step
+  int Psb = 0;                // contracted beads (<= Ps; the rest are phantoms)
   double* xs = nullptr;       // [3][N][Ps] contracted beads
   double* gs = nullptr;       // [3][N][Ps] grad V_s there
   float4* xfs = nullptr;      // [N][Ps]
@@ -193,6 +195,11 @@ struct qhp_ctx {
   double* hvp_out = nullptr;  // [3][N][P] Hessian-vector product (allocated on use)
 
   QtbState qtb;
+
+  // state at the start of the current qhp_step call (repeated after a list-row overflow)
+  double* snap = nullptr;
+  NlCtrl* snap_ctrl = nullptr;
+  int list_grown = 0;         // times the neighbour rows were enlarged
 
   // profiling
   int prof_which = 0;
@@ -246,6 +253,8 @@ hipError_t launch_centroid_of_beads(qhp_ctx* c);
 
 hipError_t launch_nlist(qhp_ctx* c, bool from_step);
 hipError_t launch_zero(qhp_ctx* c, void* ptr, size_t bytes);
+// zero the contracted-bead terms (all but bonds and angles) of energy rows [r0, r1)
+hipError_t launch_clear_slow_energy(qhp_ctx* c, int r0, int r1);
 // H u of the intramolecular terms (bonds, angle, exclusion) at c->x: writes (initialises)
 // hu; with mix, adds the exclusion part of d(u . grad E)/dq to c->pg_dq
 hipError_t launch_bonded_hvp(qhp_ctx* c, const double* u, double* hu, bool mix);

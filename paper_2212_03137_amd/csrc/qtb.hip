@@ -13,6 +13,8 @@
 // x, y, z. Spectra at the end of a segment: X_k = DFT of the segment zero-padded to
 // 2 N_seg, C_XY = (dt/N_seg) X conj(Y), Delta = m gamma C_vv - Re C_vF, averaged over the
 // degrees of freedom of each type; gamma <- max(gamma_min, gamma - A_gamma Delta).
+#include <algorithm>
+
 #include "qhp_internal.h"
 
 namespace {
@@ -21,6 +23,7 @@ constexpr int NT = 256;
 // the segment kernels hold one or two whole transforms in LDS (64-128 KB), so a compute
 // unit runs one or two of their blocks: 1,024 threads keep 4-8 wavefronts per SIMD
 constexpr int NT_SEG = 1024;
+constexpr size_t QTB_LDS_MAX = 160 * 1024;   // LDS of one compute unit (gfx950)
 
 QHP_DEV double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -169,6 +172,7 @@ __global__ __launch_bounds__(NT_SEG) void k_qtb_generate(GenArgs A) {
 
 struct SpecArgs {
   int N, nseg, ntypes, dofs_per_block;
+  int z0;                 // the launch accumulates types z0 .. z0 + ntypes - 1 only
   const int* type;
   const double* mass;
   const double* gamma;
@@ -187,7 +191,7 @@ __global__ __launch_bounds__(NT_SEG) void k_qtb_spectra(SpecArgs A) {
   double2* u = lds;
   double2* v = lds + L2;
   const int nk = A.ntypes * (Ns + 1);
-  double* acc = (double*)(lds + 2 * L2);     // [T][nseg+1] Delta; then C_vv, Re C_vF
+  double* acc = (double*)(lds + 2 * L2);     // [types][nseg+1] Delta; then C_vv, Re C_vF
   double* avv = acc + nk;
   double* avf = avv + nk;
   for (int k = threadIdx.x; k < (A.ratio ? 3 : 1) * nk; k += blockDim.x) acc[k] = 0.0;
@@ -196,6 +200,8 @@ __global__ __launch_bounds__(NT_SEG) void k_qtb_spectra(SpecArgs A) {
   const double sc = A.dt / Ns;
   for (int dof = d0; dof < min(ndof, d0 + A.dofs_per_block); ++dof) {
     const int d = dof % 3, a = dof / 3;
+    const int ty = A.type[a] - A.z0;
+    if (ty < 0 || ty >= A.ntypes) continue;            // another launch's type (uniform)
     for (int t = threadIdx.x; t < L2; t += blockDim.x) {
       double2 z = make_double2(0.0, 0.0);
       if (t < Ns) {
@@ -206,9 +212,8 @@ __global__ __launch_bounds__(NT_SEG) void k_qtb_spectra(SpecArgs A) {
     }
     __syncthreads();
     double2* Z = fft_rt(u, v, L2, false, A.tw2);
-    const int ty = A.type[a];
     const double m = A.mass[a];
-    const double* gz = A.gamma + (size_t)ty * (Ns + 1);
+    const double* gz = A.gamma + (size_t)(ty + A.z0) * (Ns + 1);
     for (int k = threadIdx.x; k <= Ns; k += blockDim.x) {
       const double2 zk = Z[k], zm = Z[(L2 - k) % L2];
       // V = (Z_k + conj Z_-k) / 2, F = (Z_k - conj Z_-k) / 2i
@@ -224,11 +229,12 @@ __global__ __launch_bounds__(NT_SEG) void k_qtb_spectra(SpecArgs A) {
     }
     __syncthreads();
   }
+  const size_t o = (size_t)A.z0 * (Ns + 1);
   for (int k = threadIdx.x; k < nk; k += blockDim.x) {
-    if (acc[k] != 0.0) atomicAdd(A.dsum + k, acc[k]);
+    if (acc[k] != 0.0) atomicAdd(A.dsum + o + k, acc[k]);
     if (A.ratio) {
-      if (avv[k] != 0.0) atomicAdd(A.vvsum + k, avv[k]);
-      if (avf[k] != 0.0) atomicAdd(A.vfsum + k, avf[k]);
+      if (avv[k] != 0.0) atomicAdd(A.vvsum + o + k, avv[k]);
+      if (avf[k] != 0.0) atomicAdd(A.vfsum + o + k, avf[k]);
     }
   }
 }
@@ -298,15 +304,22 @@ hipError_t launch_qtb_generate(qhp_ctx* c, int64_t seg) {
 hipError_t launch_qtb_adapt(qhp_ctx* c) {
   QtbState& q = c->qtb;
   SpecArgs A;
-  A.N = c->N; A.nseg = q.nseg; A.ntypes = c->p.n_types; A.dofs_per_block = 32;
+  A.N = c->N; A.nseg = q.nseg; A.dofs_per_block = 32;
   A.type = c->d_type; A.mass = c->d_mass; A.gamma = q.gamma; A.vrec = q.vrec; A.noise = q.noise;
   A.tw2 = q.tw2; A.dt = c->p.dt; A.dsum = q.dsum;
   A.vvsum = q.vvsum; A.vfsum = q.vfsum;
   A.ratio = c->p.qtb_adapt_scheme == QHP_QTB_RATIO;
   const int nb = (3 * c->N + A.dofs_per_block - 1) / A.dofs_per_block;
-  const size_t lds = (size_t)4 * q.nseg * sizeof(double2) +
-                     (size_t)(A.ratio ? 3 : 1) * c->p.n_types * (q.nseg + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_qtb_spectra, nb, NT_SEG, lds, c->stream, A);
+  // the per-type accumulators share the block's LDS with the two transform buffers: types
+  // that do not fit together are accumulated by further launches (each skips the others)
+  const size_t fft_lds = (size_t)4 * q.nseg * sizeof(double2);
+  const size_t per_type = (size_t)(A.ratio ? 3 : 1) * (q.nseg + 1) * sizeof(double);
+  const int fit = (int)std::max<size_t>(1, (QTB_LDS_MAX - fft_lds) / per_type);
+  for (int z0 = 0; z0 < c->p.n_types; z0 += fit) {
+    A.z0 = z0;
+    A.ntypes = std::min(fit, c->p.n_types - z0);
+    hipLaunchKernelGGL(k_qtb_spectra, nb, NT_SEG, fft_lds + A.ntypes * per_type, c->stream, A);
+  }
   AdaptArgs D;
   D.n = c->p.n_types * (q.nseg + 1); D.nseg = q.nseg; D.ratio = A.ratio;
   D.gamma = q.gamma; D.dsum = q.dsum; D.dbar = q.dbar; D.vvsum = q.vvsum; D.vfsum = q.vfsum;

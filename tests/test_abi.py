@@ -45,7 +45,7 @@ def test_params_struct_matches_header_fields():
 
 @pytest.mark.parametrize("change,code", [
     (dict(cutoff=7.0), -1),            # rc >= L/2 for a 12.42 A box
-    (dict(n_beads=3), -5),             # not a power of two
+    (dict(n_beads=65), -1),            # more than 64 beads
     (dict(pme_order=7), -5),
     (dict(pme_grid=(16, 16, 12)), -1),
     (dict(exec_mode=7), -1),

@@ -30,7 +30,7 @@ def ctx_for(s, **kw):
 
 
 # ---------------------------------------------------------------------------- noise
-@pytest.mark.parametrize("P,NW", [(1, 3), (8, 64), (32, 111)])
+@pytest.mark.parametrize("P,NW", [(1, 3), (6, 20), (8, 64), (32, 111)])
 def test_rpmd_noise_bit_exact(P, NW):
     s = synth.water_box(NW, P, 20.0, seed=3)
     N = s.n_atoms
@@ -296,19 +296,145 @@ def test_large_box_step_stays_finite_and_rebuilds(large):
 
 
 def test_rebuild_rule_holds_over_a_trajectory(large):
-    """The list is rebuilt only when the skin is used up: count the builds and check the
-    forces after 200 steps against the oracle's list-free definition on one bead."""
+    """The list is rebuilt only when the skin is used up: count the builds, then check the
+    energies of the last step (evaluated with the list kept from the last skin-triggered
+    build) and the forces of a fresh evaluation against the oracle's definition (every
+    pair within the cutoff) on one bead."""
     import paper_2212_03137_amd as q
+    from helpers import oracle_forces_on
     s = large
     with ctx_for(s, precision=q.FP64) as c:
         c.set_state(s.pos, s.vel, 0)
-        c.step(200)
+        c.step(199)
+        E_step = c.step(1, energy=True)
         st = c.nlist_stats()
         x, _, _ = c.get_state()
         E, F = c.eval(x)
     say("nlist stats after 200 steps", st)
     assert 1 < st["builds"] < 120
     assert st["max_count"] <= st["capacity"]
+    b = 7
+    pairs = ofo.pair_list(ofo.centroids_of(x), s.box, s.cutoff + s.skin)
+    Eb, g = ofo.bead_potential(x[b], s, pairs)
+    assert np.abs(E_step[b] - Eb).max() <= 1e-11 * np.abs(Eb).max()
+    assert np.abs(E[b] - Eb).max() <= 1e-11 * np.abs(Eb).max()
+    assert rel_max(F[b], -g) <= 1e-11
+    sample = np.arange(0, s.n_atoms, 97)
+    Fs, _ = oracle_forces_on(s, x[b], sample)
+    assert np.abs(F[b][sample] - Fs).max() <= 1e-11 * np.sqrt(np.mean(g * g))
+
+
+def test_trajectory_through_skin_rebuilds_matches_the_oracle():
+    """343 waters (21.7 A) at P = 4 with rc + skin below L/2: the centroid list with its
+    image shifts is built on the device and kept until the skin rule fires. The oracle
+    finds every pair within the cutoff at every step, so a list kept too long or a wrong
+    stored image shift shows as a trajectory difference."""
+    import dataclasses
+    import paper_2212_03137_amd as q
+    s = dataclasses.replace(medium_box(P=4), skin=1.4)
+    say("skin-rebuild trajectory")
+    R = _oracle_rpmd(s)
+    R.step(80)
+    xr, vr, _ = R.get_state()
+    with ctx_for(s, precision=q.FP64) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(80)
+        x, v, st = c.get_state()
+        stats = c.nlist_stats()
+    say("builds", stats)
+    assert st == 80
+    assert stats["builds"] >= 4          # the build at set-up and at least three from the rule
+    assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-8
+    assert np.abs(v - vr).max() / np.abs(vr).max() < 1e-6
+
+
+def test_rows_grow_when_a_build_finds_more_neighbours():
+    """Rows that are too short for the list grow by themselves, in the stateless
+    evaluation (host and device memory) and in a trajectory: the propagation restarts from
+    the state the call began with. The trajectory's rows are sized to the largest count of
+    the first build, which a later build of the same seeded run exceeds."""
+    import dataclasses
+    import torch
+    import paper_2212_03137_amd as q
+    s = dataclasses.replace(medium_box(P=4), skin=1.4)
+    say("list growth")
+    with ctx_for(s, precision=q.FP64) as c:
+        c.set_state(s.pos, s.vel, 0)
+        m0 = c.nlist_stats()["max_count"]
+        mt = m0
+        for _ in range(60):
+            c.step(1)
+            mt = max(mt, c.nlist_stats()["max_count"])
+    say("largest counts", m0, mt)
+    assert mt > m0
+    R = _oracle_rpmd(s)
+    R.step(60)
+    xr, vr, _ = R.get_state()
+    with ctx_for(s, precision=q.FP64, nbr_capacity=m0) as c:
+        c.set_state(s.pos, s.vel, 0)
+        assert c.nlist_stats()["capacity"] == m0
+        c.step(60)
+        x, v, st = c.get_state()
+        grown = c.nlist_stats()["capacity"]
+    assert st == 60 and grown > m0
+    assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-8
+    assert np.abs(v - vr).max() / np.abs(vr).max() < 1e-6
+    Eref, Fref = ofo.evaluate(s.pos, s)
+    with ctx_for(s, precision=q.FP64, nbr_capacity=8) as c:
+        E, F = c.eval(s.pos, box=s.box)
+        _check_fp64(E, F, Eref, Fref)
+        assert c.nlist_stats()["capacity"] > 8
+    with ctx_for(s, precision=q.FP64, nbr_capacity=8) as c:
+        pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+        Et = torch.zeros((s.n_beads, q.NTERMS), dtype=torch.float64, device="cuda")
+        Ft = torch.zeros_like(pos)
+        c.eval_device(pos, Et, Ft)
+        c.sync()
+        _check_fp64(Et.cpu().numpy(), Ft.cpu().numpy(), Eref, Fref)
+        with pytest.raises(q.QhpError):
+            c.eval(s.pos, box=s.box * 1.01)
+
+
+@pytest.mark.parametrize("P", [3, 6])
+def test_bead_counts_that_are_not_powers_of_two(P):
+    """P = 3 and 6 run in the lanes of 4 and 8: forces, energies and a trajectory against
+    the oracle's P-bead ring polymer."""
+    import paper_2212_03137_amd as q
+    s = synth.water_box(64, P, 12.42, synth.SEED_BASE + 40 + P, cutoff=6.0, ewald_alpha=0.35,
+                        pme_grid=16, pme_order=4)
+    say("non-power-of-two P", P)
+    Eref, Fref = ofo.evaluate(s.pos, s)
+    R = _oracle_rpmd(s)
+    R.step(40)
+    xr, vr, _ = R.get_state()
+    for mode in (q.BATCHED, q.PLAIN):
+        with ctx_for(s, exec_mode=mode) as c:
+            E, F = c.eval(s.pos)
+            _check_fp64(E, F, Eref, Fref)
+            c.set_state(s.pos, s.vel, 0)
+            E = c.step(40, energy=True)
+            x, v, st = c.get_state()
+            kin, spr = c.mode_energies()
+            noise = c.noise(5, 3)
+        assert st == 40 and x.shape == (P, s.n_atoms, 3)
+        assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-8
+        assert np.abs(v - vr).max() / np.abs(vr).max() < 1e-6
+        assert np.abs(E - R.E).max() / np.abs(R.E).max() < 1e-6
+        assert math.isclose(kin, R.kinetic(), rel_tol=1e-6)
+        assert math.isclose(spr, R.spring(), rel_tol=1e-6)
+        assert noise.shape == (P, s.n_atoms, 3)
+
+
+def test_fp32_pairs_with_six_beads():
+    import paper_2212_03137_amd as q
+    s = medium_box(P=6)
+    say("fp32 P=6")
+    Eref, Fref = ofo.evaluate(s.pos, s)
+    with ctx_for(s, precision=q.FP32_PAIRS) as c:
+        E, F = c.eval(s.pos)
+    assert rel_rms(F, Fref) <= 1e-5, rel_rms(F, Fref)
+    for t in (0, 1, 4, 5, 6):
+        assert np.abs(E[:, t] - Eref[:, t]).max() <= 1e-11 * np.abs(Eref[:, t]).max()
 
 
 def test_graph_replay_equals_eager_launches(small):

@@ -75,6 +75,59 @@ def test_adaptation_over_segments_matches_oracle():
     assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-8
 
 
+def test_segment_end_at_the_workload_segment_length():
+    """N_seg = 1,024 (the adQTB workload's segments: 2,048-point spectra and 4,096-point
+    noise convolutions held in LDS): one full segment of 64 waters, then the segment-end
+    spectra, type-averaged Delta_FDT, SIMPLE update and the next segment's noise against
+    the oracle."""
+    s = _system(1024, n_w=64, L=12.42, rate=5e-3)
+    print("qtb segment end at N_seg 1024", flush=True)
+    Q = _oracle(s)
+    with _ctx(s) as c:
+        c.set_state(s.pos, s.vel, 0)
+        assert np.abs(c.qtb_noise() - Q.noise).max() <= 1e-11 * np.abs(Q.noise).max()
+        Q.step(1024)
+        c.step(1024)
+        g, d = c.qtb_gamma(), c.qtb_delta()
+        F = c.qtb_noise()
+        x, v, st = c.get_state()
+    assert st == 1024
+    scale = np.abs(Q.last_delta).max()
+    assert np.abs(d - Q.last_delta).max() <= 1e-7 * scale
+    assert np.abs(g - Q.gamma).max() <= 1e-9 * np.abs(Q.gamma).max()
+    assert np.any(g != s.qtb_gamma0)
+    assert np.abs(F - Q.noise).max() <= 1e-8 * np.abs(Q.noise).max()
+    xr, vr, _ = Q.get_state()
+    assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-8
+
+
+def test_ratio_with_eight_types_at_the_workload_segment_length():
+    """RATIO keeps three per-type spectra accumulators next to the transform in LDS; with
+    eight types at N_seg = 1,024 they do not fit together and are accumulated by several
+    launches. Molecules cycle through four copies of the water's (O, H) type pair."""
+    import dataclasses
+    import paper_2212_03137_amd as q
+    s = _system(1024, n_w=64, L=12.42, rate=5e-3)
+    mol = np.arange(s.n_atoms) // 3
+    types = (2 * (mol % 4) + (np.arange(s.n_atoms) % 3 != 0)).astype(np.int32)
+    s = dataclasses.replace(s, types=types, lj_sigma=np.tile(s.lj_sigma, 4),
+                            lj_epsilon=np.tile(s.lj_epsilon, 4))
+    assert s.n_types == 8
+    print("ratio with 8 types at N_seg 1024", flush=True)
+    tau = 800.0
+    Q = oq.QTB(s.mass, s.types, s.n_types, s.kT, s.hbar, s.dt, s.qtb_gamma0, s.qtb_nseg,
+               s.qtb_adapt_rate, s.qtb_gamma_min_frac, s.seed, oracle_grad_fn(s),
+               scheme="RATIO", tau=tau)
+    Q.set_state(s.pos, s.vel, 0)
+    with _ctx(s, qtb_adapt_scheme=q.QTB_RATIO, qtb_tau=tau) as c:
+        c.set_state(s.pos, s.vel, 0)
+        Q.step(1024)
+        c.step(1024)
+        g, d = c.qtb_gamma(), c.qtb_delta()
+    assert np.abs(d - Q.last_delta).max() <= 1e-7 * np.abs(Q.last_delta).max()
+    assert np.abs(g - Q.gamma).max() <= 1e-7 * np.abs(Q.gamma).max()
+
+
 def test_gamma_min_clamp_and_set_gamma():
     s = _system(32, rate=1e6)
     with _ctx(s) as c:

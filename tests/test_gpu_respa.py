@@ -44,10 +44,26 @@ def small():
     return synth.small_rpmd()
 
 
+@pytest.fixture(scope="module")
+def small32():
+    """64 waters at P = 32: room for the paper's contraction to about five beads."""
+    return synth.water_box(64, 32, 12.42, synth.SEED_BASE + 50, cutoff=6.0, ewald_alpha=0.35,
+                           pme_grid=16, pme_order=4)
+
+
 @pytest.mark.parametrize("Pc,nalt,nout", [(8, 2, 2), (4, 1, 2), (4, 3, 2), (2, 2, 2),
-                                           (1, 4, 2), (4, 2, 15)])
+                                           (1, 4, 2), (4, 2, 15), (3, 2, 2), (5, 2, 2),
+                                           (7, 1, 2), (5, 3, 15), (6, 2, 2)])
 def test_respa_trajectory_small(small, Pc, nalt, nout):
-    s = small
+    _respa_parity(small, Pc, nalt, nout)
+
+
+@pytest.mark.parametrize("Pc,nalt,nout", [(5, 4, 2), (5, 2, 8), (3, 2, 2), (16, 2, 2)])
+def test_respa_trajectory_32_beads(small32, Pc, nalt, nout):
+    _respa_parity(small32, Pc, nalt, nout)
+
+
+def _respa_parity(s, Pc, nalt, nout):
     say("respa trajectory", Pc, nalt, nout)
     R = oracle_respa(s, Pc, nalt)
     R.step(nout)
@@ -125,7 +141,7 @@ def test_respa_fp32_pairs_medium():
 def test_rejects_unsupported_combinations(small):
     import paper_2212_03137_amd as q
     s = small
-    for kw in (dict(rpc_beads=3), dict(rpc_beads=16), dict(respa_nalt=-1),
+    for kw in (dict(rpc_beads=9), dict(rpc_beads=16), dict(rpc_beads=-1), dict(respa_nalt=-1),
                dict(respa_nalt=65)):
         with pytest.raises(q.QhpError):
             ctx_for(s, **kw)
@@ -133,16 +149,31 @@ def test_rejects_unsupported_combinations(small):
         ctx_for(s, rpc_beads=4, exec_mode=q.PLAIN)
 
 
-def test_large_box_contracted_respa_runs():
+@pytest.mark.parametrize("Pc", [4, 5])
+def test_large_box_contracted_respa_energies(Pc):
+    """4,096 waters, P = 32, FP32 pairs, n = 4: after 10 outer steps (the list rebuilt from
+    the skin rule on the contracted beads) the step's energies are checked against the
+    oracle at the GPU's final state: bonds and angles on the 32 beads, the other terms on
+    the contracted beads the oracle builds from that state's modes."""
     import paper_2212_03137_amd as q
+    from oracle import normal_modes as nm
     s = synth.large_rpmd()
-    say("large respa", s.n_atoms, s.n_beads)
-    with ctx_for(s, rpc_beads=4, respa_nalt=4, precision=q.FP32_PAIRS) as c:
+    say("large respa", s.n_atoms, s.n_beads, Pc)
+    with ctx_for(s, rpc_beads=Pc, respa_nalt=4, precision=q.FP32_PAIRS) as c:
         c.set_state(s.pos, s.vel, 0)
         E = c.step(10, energy=True)
         x, v, st = c.get_state()
         stats = c.nlist_stats()
     assert st == 40
     assert np.all(np.isfinite(x)) and np.all(np.isfinite(v))
-    assert np.all(E[4:, 2:] == 0.0) and np.all(np.isfinite(E))
-    assert stats["max_count"] <= stats["capacity"]
+    assert np.all(E[Pc:, 2:] == 0.0) and np.all(np.isfinite(E))
+    assert stats["max_count"] <= stats["capacity"] and stats["builds"] >= 1
+    Ef, _ = ofo.evaluate_fast(x, s)
+    assert np.abs(E[:, :2] - Ef[:, :2]).max() <= 1e-9 * np.abs(Ef[:, :2]).max()
+    xc = respa.contract(nm.modes_from_beads(x, nm.transfer_matrix(s.n_beads)), Pc)
+    say("oracle slow terms on", xc.shape)
+    Es, _ = ofo.evaluate_slow(xc, s)
+    for t in (4, 5, 6):                  # exclusion, self, reciprocal: FP64 on both sides
+        assert np.abs(E[:Pc, t] - Es[:, t]).max() <= 1e-9 * np.abs(Es[:, t]).max(), t
+    for t in (2, 3):                     # real-space Coulomb and LJ: FP32 pairs
+        assert np.abs(E[:Pc, t] - Es[:, t]).max() <= 1e-5 * np.abs(Es[:, t]).max(), t
