@@ -198,4 +198,4 @@ def test_tethered_free_atoms_sample_the_ring_polymer_oscillator():
         ref = s.kT / m * np.sum(1.0 / (k / m + wk * wk))
         got = acc[s.types == t].mean()
         say("tether", t, got, ref)
-        assert abs(got / ref - 1) < 0.04
+        assert abs(got / ref - 1) < 0.02
