@@ -261,6 +261,16 @@ QHP_API int qhp_step(qhp_ctx* ctx, int32_t nsteps, double* energy, int mem_kind)
  * host outputs). */
 QHP_API int qhp_mode_energies(qhp_ctx* ctx, double* kinetic, double* spring);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): qhp_mode_energies with the two sums written to device
+ * memory `out` [2] (kinetic, spring) on the context's stream, without synchronising and
+ * without allocating. The per-block partial sums go to a 1 MiB file-scope device array
+ * that every call on a GPU shares (at most 65,536 blocks of 256 / P atoms, i.e. N P up to
+ * 16.7 million bead-atoms; beyond that QHP_ENOMEM); they are added in a fixed order, so the
+ * result does not depend on block scheduling. Calls that overlap on one GPU (two streams,
+ * or two host threads) race on that array and must be serialised by the caller. */
+QHP_API int qhp_mode_energies_noalloc(qhp_ctx* ctx, double* out);
+
 /* The centroid pair list of the last build (Sec. "Massively Parallel Implementation":
  * pairs whose centroid distance is below rc + skin), canonical form: pairs (i, j), i < j,
  * different molecules, sorted by i then j, written to `pairs` [*npairs][2] (host).

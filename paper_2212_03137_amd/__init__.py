@@ -31,7 +31,7 @@ EXPORTS = ("qhp_create", "qhp_destroy", "qhp_eval", "qhp_set_state", "qhp_get_st
            "qhp_profile", "qhp_profile_read", "qhp_sync", "qhp_last_error", "qhp_param_grad",
            "qhp_hvp", "qhp_set_lambda", "qhp_eval_lambda", "qhp_bar", "qhp_group_create",
            "qhp_group_step", "qhp_group_destroy", "qhp_group_last_error", "qhp_autotune",
-           "qhp_set_launch")
+           "qhp_set_launch", "qhp_mode_energies_noalloc")
 
 
 class QhpError(RuntimeError):
@@ -84,6 +84,7 @@ def load():
     lib.qhp_get_state.argtypes = [vp, vp, vp, C.POINTER(C.c_int64), I]
     lib.qhp_step.argtypes = [vp, C.c_int32, vp, I]
     lib.qhp_mode_energies.argtypes = [vp, D, D]
+    lib.qhp_mode_energies_noalloc.argtypes = [vp, vp]
     lib.qhp_nlist_export.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
     lib.qhp_nlist_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]

@@ -321,6 +321,11 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     }
   }
   c->use_graph = p->use_graph != 0;
+  if (scratch_address(&c->scratch) != hipSuccess) {
+    free_all(c);
+    delete c;
+    return QHP_EDEVICE;
+  }
   // a bead count that is not a power of two runs in the lanes of the next power of two:
   // the extra (phantom) beads have zero rows and columns in the transfer matrix, so they
   // stay at the centroid, carry no mode and feel no force, and nothing reports them
@@ -1258,6 +1263,21 @@ extern "C" int qhp_mode_energies(qhp_ctx* c, double* kinetic, double* spring) {
   QHP_HIP(c, hipStreamSynchronize(c->stream));
   *kinetic = h[0];
   *spring = h[1];
+  return QHP_OK;
+}
+
+extern "C" int qhp_mode_energies_noalloc(qhp_ctx* c, double* out) {
+  if (!c || !out) return QHP_EINVAL;
+  if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
+  if (mode_energy_parts(c) > QHP_SCRATCH_DOUBLES)
+    return qhp_fail(c, QHP_ENOMEM, "the partial sums of " + std::to_string(mode_energy_parts(c) / 2) +
+                                       " blocks exceed the 1 MiB scratch (65,536 blocks)");
+  const double* pa = c->Pa;
+  if (c->respa) {
+    QHP_HIP(c, launch_kick_slow(c, c->pa_tmp, c->Pa, 0.5 * c->nalt * c->p.dt));
+    pa = c->pa_tmp;
+  }
+  QHP_HIP(c, launch_mode_energies_noalloc(c, out, pa));
   return QHP_OK;
 }
 

@@ -12,6 +12,8 @@
 // before its final half kick) and g = grad V at the current beads. A step therefore
 // starts with P = Pa + dt * f(g): the previous step's final B and this step's first B,
 // which use the same forces.
+#include <mutex>
+
 #include "qhp_internal.h"
 
 namespace {
@@ -377,6 +379,65 @@ __global__ __launch_bounds__(NT) void k_mode_energy(int N, double rsP, const dou
   if ((tid & 63) == 0) { atomicAdd(out, ek); atomicAdd(out + 1, es); }
 }
 
+// The same sums without atomics: each block writes its two partial sums to parts[2 b],
+// parts[2 b + 1]; k_sum_parts adds them in block order (the result does not depend on the
+// order in which blocks ran).
+template <int P, bool BEADMAJOR>
+__global__ __launch_bounds__(NT) void k_mode_energy_parts(int N, double rsP, const double* Q,
+                                                          const double* Pa, const double* g,
+                                                          const double* T, const double* mass,
+                                                          const double* w2, double h,
+                                                          double* parts) {
+  constexpr int AT = NT / P;
+  __shared__ double sT[P * P];
+  __shared__ double sg[AT][3][P];
+  __shared__ double sred[2][NT / 64];
+  const int tid = threadIdx.x, al = tid / P, n = tid % P, a = blockIdx.x * AT + al;
+  for (int k = tid; k < P * P; k += NT) sT[k] = T[k];
+  const bool live = a < N;
+  for (int d = 0; d < 3; ++d) sg[al][d][n] = live ? g[gidx<P, BEADMAJOR>(N, d, a, n)] : 0.0;
+  __syncthreads();
+  double ek = 0, es = 0;
+  if (live) {
+    const double m = mass[a];
+    for (int d = 0; d < 3; ++d) {
+      double f = 0;
+      for (int i = 0; i < P; ++i) f += sT[i * P + n] * sg[al][d][i];
+      const double pn = Pa[(d * N + a) * P + n] + h * (-f * rsP);
+      const double qn = Q[(d * N + a) * P + n];
+      ek += pn * pn / (2.0 * m);
+      es += 0.5 * m * w2[n] * qn * qn;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) { ek += __shfl_xor(ek, o); es += __shfl_xor(es, o); }
+  if ((tid & 63) == 0) { sred[0][tid >> 6] = ek; sred[1][tid >> 6] = es; }
+  __syncthreads();
+  if (tid == 0) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int w = 0; w < NT / 64; ++w) { a0 += sred[0][w]; a1 += sred[1][w]; }
+    parts[2 * blockIdx.x] = a0;
+    parts[2 * blockIdx.x + 1] = a1;
+  }
+}
+
+// out[0..1] = sums of the nparts partial pairs (one block, fixed order)
+__global__ __launch_bounds__(256) void k_sum_parts(const double* parts, int nparts, double* out) {
+  __shared__ double s[2][256];
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 256) { a0 += parts[2 * k]; a1 += parts[2 * k + 1]; }
+  s[0][threadIdx.x] = a0;
+  s[1][threadIdx.x] = a1;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + st];
+      s[1][threadIdx.x] += s[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[0] = s[0][0]; out[1] = s[1][0]; }
+}
+
 // dst = src + s * f_s on the modes n < Ps, f_s = -(1/sqrt(Ps)) sum_j C[j][n] g_s(j) (the slow
 // forces of ring-polymer contraction); the other modes are copied.
 template <int P>
@@ -629,6 +690,49 @@ hipError_t launch_mode_energies(qhp_ctx* c, double* out2, const double* pa) {
                                        out2));
   return hipGetLastError();
 }
+
+// ---- allocation-free mode energies ----
+// File-scope scratch of the allocation-free entry point: the per-block partial sums of the
+// kinetic and spring energies. Every GPU the library runs on holds its own copy until the
+// process ends; its device address is looked up once per device (scratch_address) and the
+// kernels receive that address, never the array's host-side name.
+static __device__ __align__(256) double scratch[QHP_SCRATCH_DOUBLES];
+
+hipError_t scratch_address(void** ptr) {
+  static std::mutex mu;
+  static void* addr[QHP_MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= QHP_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_mode_energies_noalloc(qhp_ctx* c, double* out2, const double* pa) {
+  const unsigned nb = nblocks_atoms(c->N, c->P);
+  if ((size_t)2 * nb > QHP_SCRATCH_DOUBLES) return hipErrorInvalidValue;   // checked by the caller
+  double* parts = static_cast<double*>(c->scratch);
+  const bool bm = c->p.exec == QHP_PLAIN;
+  const double h = 0.5 * c->p.dt, rsP = 1.0 / sqrt((double)c->Pb);
+  QHP_SWITCH_P(c->P, if (bm) hipLaunchKernelGGL((k_mode_energy_parts<PP, true>), nb, NT, 0,
+                                                 c->stream, c->N, rsP, c->Q, pa, c->g, c->T,
+                                                 c->d_mass, c->mode_w2, h, parts);
+               else hipLaunchKernelGGL((k_mode_energy_parts<PP, false>), nb, NT, 0, c->stream,
+                                       c->N, rsP, c->Q, pa, c->g, c->T, c->d_mass, c->mode_w2,
+                                       h, parts));
+  hipLaunchKernelGGL(k_sum_parts, 1, 256, 0, c->stream, parts, (int)nb, out2);
+  return hipGetLastError();
+}
+
+size_t mode_energy_parts(const qhp_ctx* c) { return (size_t)2 * nblocks_atoms(c->N, c->P); }
 
 hipError_t launch_kick_slow(qhp_ctx* c, double* dst, const double* src, double s) {
   const unsigned nb = nblocks_atoms(c->N, c->P);

@@ -11,6 +11,8 @@
 #include "../../include/qhp.h"
 
 #define QHP_MAX_TYPES 8
+#define QHP_MAX_DEVICES 64
+#define QHP_SCRATCH_DOUBLES 131072   // 1 MiB file-scope scratch of the allocation-free call
 #define QHP_PAIR_TAB 1024           // intervals of the FP32 pair kernel's tables
 
 // ---------------------------------------------------------------------------------------
@@ -200,6 +202,7 @@ struct qhp_ctx {
   double* snap = nullptr;
   NlCtrl* snap_ctrl = nullptr;
   int list_grown = 0;         // times the neighbour rows were enlarged
+  void* scratch = nullptr;    // device address of the file-scope scratch on this context's GPU
 
   // profiling
   int prof_which = 0;
@@ -245,6 +248,12 @@ hipError_t launch_kick_slow(qhp_ctx* c, double* dst, const double* src, double s
 hipError_t launch_state_out(qhp_ctx* c, double* xb, double* vb, const double* pa);
 hipError_t launch_kick_back(qhp_ctx* c);
 hipError_t launch_mode_energies(qhp_ctx* c, double* out2, const double* pa);
+// the allocation-free variant: partial sums in the file-scope scratch (c->scratch), the
+// two totals written to device memory out2; mode_energy_parts gives the scratch doubles
+hipError_t launch_mode_energies_noalloc(qhp_ctx* c, double* out2, const double* pa);
+size_t mode_energy_parts(const qhp_ctx* c);
+// device address of the file-scope scratch on the current device (looked up once per device)
+hipError_t scratch_address(void** ptr);
 // contracted beads, their FP32 offsets, centroids and block maxima from the modes Q
 hipError_t launch_contract(qhp_ctx* c);
 hipError_t launch_transpose_in(qhp_ctx* c, const double* src, double* dst);
