@@ -115,10 +115,10 @@ void free_all(qhp_ctx* c) {
                   c->d_type, c->d_mass, c->d_charge, c->d_sqrt_mkT, c->d_sigma, c->d_eps,
                   c->Q, c->Pa, c->x, c->g, c->cent, c->cref, c->coff, c->cwrap, c->xf, c->ctrl,
                   c->cell_of, c->cell_count, c->cell_fill, c->cell_start, c->cell_atoms, c->stencil, c->nbr,
-                  c->nnbr, c->bmax, c->grid, c->grid2, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
+                  c->nnbr, c->bmax, c->grid, c->grid2, c->grid_l1, c->tile_of, c->tile_atoms, c->tile_count, c->tile_fill, c->tile_start, c->influence, c->tw[0], c->tw[1], c->tw[2], c->energy,
                   c->io_a, c->io_b, c->xs, c->gs, c->xfs, c->Cs, c->pa_tmp, c->g_eval, c->pg_dq, c->pg_lj, c->pair_tab,
                   c->hvp_out, c->d_charge_alt, c->d_anchor,
-                  c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise,
+                  c->qtb.gamma, c->qtb.hhat, c->qtb.hker, c->qtb.noise, c->qtb.noise_t, c->qtb.vrec_t,
                   c->qtb.vrec, c->qtb.dsum, c->qtb.dbar, c->qtb.vvsum, c->qtb.vfsum,
                   c->qtb.avg_vv, c->qtb.avg_vf, c->qtb.d_tmass, c->qtb.d_inv_count,
                   c->qtb.tw2, c->qtb.tw4, c->snap, c->snap_ctrl};
@@ -507,6 +507,7 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   // ---- SPME: influence function G(m) and FFT twiddles ----
   const size_t KKK = (size_t)c->K[0] * c->K[1] * c->K[2];
   TRY(dalloc(&c->grid, KKK * Pc_grid));
+  if (!plain && Pc_grid >= 2) TRY(dalloc(&c->grid_l1, KKK * Pc_grid));
   {
     std::vector<double> b0 = bmod(c->K[0], p->pme_order), b1 = bmod(c->K[1], p->pme_order),
                         b2 = bmod(c->K[2], p->pme_order);
@@ -552,6 +553,8 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     TRY(dalloc(&q.hhat, (size_t)p->n_types * 4 * q.nseg));
     TRY(dalloc(&q.noise, (size_t)q.nseg * 3 * N));
     TRY(dalloc(&q.vrec, (size_t)q.nseg * 3 * N));
+    TRY(dalloc(&q.noise_t, (size_t)q.nseg * 3 * N));
+    TRY(dalloc(&q.vrec_t, (size_t)q.nseg * 3 * N));
     TRY(upload_twiddles(&q.tw2, 2 * q.nseg));
     TRY(upload_twiddles(&q.tw4, 4 * q.nseg));
     std::vector<double> tm(p->n_types, 1.0), ic(p->n_types, 0.0);

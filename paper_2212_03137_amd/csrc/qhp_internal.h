@@ -60,8 +60,10 @@ struct QtbState {
   double* gamma = nullptr;    // [n_types][nseg+1]
   double2* hhat = nullptr;    // [n_types][4 nseg]  DFT of the embedded kernel h
   double2* hker = nullptr;    // [n_types][2 nseg]  scratch: H then h
-  double* noise = nullptr;    // [nseg][3][N] coloured force of the current segment
-  double* vrec = nullptr;     // [nseg][3][N] recorded O-midpoint velocities
+  double* noise = nullptr;    // [nseg][3][N] coloured force of the current segment (per step)
+  double* vrec = nullptr;     // [nseg][3][N] recorded O-midpoint velocities (per step)
+  double* noise_t = nullptr;  // the same two records in the segment kernels' layout
+  double* vrec_t = nullptr;   //   (qtb_rec: eight consecutive steps contiguous)
   double* dsum = nullptr;     // [n_types][nseg+1] summed Delta_FDT of the running segment
   double* dbar = nullptr;     // [n_types][nseg+1] type-averaged Delta_FDT of the last segment
   double* vvsum = nullptr;    // [n_types][nseg+1] RATIO: summed C_vv of the running segment
@@ -159,6 +161,7 @@ struct qhp_ctx {
   int K[3];
   double2* grid = nullptr;    // [K0][K1][K2][Pc] (plain: [K0][K1][K2])
   double2* grid2 = nullptr;   // tangent grid of Hessian-vector products (allocated on use)
+  double2* grid_l1 = nullptr; // the transforms' slot-pair planes [K0][Pc/2][K1][K2][2]
   double* influence = nullptr;// [K0][K1][K2]
   int ntiles = 0;             // 8^3-point spreading tiles
   int* tile_of = nullptr;     // [N]
@@ -393,6 +396,15 @@ QHP_DEV void gauss3(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1, ui
   g[2] = r1 * cs;
 }
 #pragma clang fp contract(fast)
+
+// Position of step t, axis d, atom a in the segment kernels' copy of the adQTB records
+// (coloured noise, recorded velocities): eight consecutive steps of one atom and axis are
+// contiguous ([t / 8][N][3][8]), so the kernels that work on one atom's whole segment read
+// and write 64-byte runs. The per-step copies are [t][3][N] (a step reads one contiguous
+// row per axis); a transpose converts between the two once per segment.
+QHP_DEV size_t qtb_rec(int t, int d, int a, int N) {
+  return (((size_t)(t >> 3) * N + a) * 3 + d) * 8 + (t & 7);
+}
 
 constexpr uint64_t STREAM_RPMD_O = 5;
 constexpr uint64_t STREAM_QTB_WHITE = 6;

@@ -16,6 +16,8 @@
 // for K = 64 (two radix-8 stages) the data cross LDS once; the z pass does the forward
 // transform, the multiplication by G (folded into the forward's last stage) and the
 // inverse transform in one visit.
+#include <algorithm>
+
 #include "qhp_internal.h"
 
 namespace {
@@ -577,17 +579,19 @@ struct GridIO {
 // first stage takes its operands from the grid (no LDS copy-in; its twiddles are all 1),
 // with STOREG the last stage writes the grid; SCALE multiplies the last stage's outputs by
 // the influence function (forward half of the fused z pass).
-template <int K, int NS, bool INV, int NSTRIDE, bool LOADG, bool STOREG, bool SCALE>
+template <int K, int NS, bool INV, int NSTRIDE, bool LOADG, bool STOREG, bool SCALE,
+          int NTH = NT>
 QHP_DEV void fft_stages(double2* buf, const double2* tw, int tid, const GridIO<K>& io,
                         const double* G, int lgpc) {
   if constexpr (NSTRIDE < K) {
     constexpr int R = (K / NSTRIDE >= 8) ? 8 : ((K / NSTRIDE >= 4) ? 4 : 2);
-    constexpr int BPT = NS * K / R / NT;
+    constexpr int BPT = NS * K / R / NTH;
+    static_assert(BPT * R * NTH == NS * K, "stage tasks must split evenly over the threads");
     constexpr bool FIRST = NSTRIDE == 1, LAST = NSTRIDE * R == K;
     double2 v[BPT][R];
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
-      const int be = tid + i * NT, s = be % NS, j = be / NS;
+      const int be = tid + i * NTH, s = be % NS, j = be / NS;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int e = j + r * (K / R);
@@ -597,7 +601,7 @@ QHP_DEV void fft_stages(double2* buf, const double2* tw, int tid, const GridIO<K
     if (!(FIRST && LOADG)) __syncthreads();
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
-      const int be = tid + i * NT, s = be % NS, j = be / NS;
+      const int be = tid + i * NTH, s = be % NS, j = be / NS;
       const int k = j % NSTRIDE;
       if constexpr (!FIRST) {
 #pragma unroll
@@ -642,7 +646,7 @@ QHP_DEV void fft_stages(double2* buf, const double2* tw, int tid, const GridIO<K
       }
     }
     if constexpr (!(LAST && STOREG)) __syncthreads();
-    fft_stages<K, NS, INV, NSTRIDE * R, LOADG, STOREG, SCALE>(buf, tw, tid, io, G, lgpc);
+    fft_stages<K, NS, INV, NSTRIDE * R, LOADG, STOREG, SCALE, NTH>(buf, tw, tid, io, G, lgpc);
   }
 }
 
@@ -685,6 +689,225 @@ __global__ __launch_bounds__(NT) void k_fft_pass(FftArgs A) {
     const int e = l & (K - 1), s = l >> LGK;
     A.grid[io.at(s, e)] = buf[e * NS + s];
   }
+}
+
+// --------------------- spreading fused with the forward x transform ---------------------
+// One block owns whole x lines: all K0 points along x of a yr x zr rectangle of (y, z)
+// lines for gc consecutive complex slots (2 gc beads), 8,192 complex values in LDS. It
+// accumulates the spline-weighted charges of every atom whose stencil reaches the
+// rectangle (FP64 LDS atomics; each grid value is owned by exactly one block), transforms
+// the lines along x in LDS and writes them: the forward x pass of the convolution happens
+// without a round trip of the grid through memory, and the plane kernels and inverse
+// passes that follow are unchanged. The rectangle's shape and the slots per block trade
+// the spline work repeated for atoms near the rectangle's edges against the length of the
+// contiguous pieces written (launch shapes picked by the autotuner).
+constexpr int SX_E = 8192;                  // complex values of one block
+constexpr int SX_NT = 1024;
+
+struct SpreadXArgs {
+  int N, P, K0, K1, K2, Pc, nt0, nt1, nt2;
+  int yr, zr, gc;             // rectangle of (y, z) lines and complex slots per block
+  int ny, nz;                 // rectangles along y and z
+  const double* x;            // [3][N][P]
+  double2* grid;              // [K0][K1][K2][Pc], written x-transformed
+  const double* charge;
+  const double4* cent;
+  double L[3], KoL[3];
+  const NlCtrl* ctrl;         // spread_m: largest bead-centroid base offset this step
+  const int* tile_start; const int* tile_atoms;
+  const double2* tw;          // [K0] twiddles of the x axis
+  int remap;                  // blocks are a multiple of 8: XCD-contiguous block order
+  int pairs;                  // write slot-pair planes [K0][Pc/2][K1][K2][2] instead
+};
+
+template <int ORDER, int K>
+__global__ __launch_bounds__(SX_NT) void k_spread_x(SpreadXArgs A) {
+  constexpr int CAP = 2048;                 // compacted atoms per round
+  constexpr int MAXR = 160;                 // candidate tile ranges (checked by the launcher)
+  __shared__ double2 buf[SX_E];
+  __shared__ double2 stw[K];
+  __shared__ int cand[CAP];
+  __shared__ int ncand;
+  __shared__ int tofs[MAXR + 1], tbeg[MAXR];
+  __shared__ int nranges;
+  double* acc = reinterpret_cast<double*>(buf);        // [x][yl][zl][2 gc]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int lb = A.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int yr = A.yr, zr = A.zr, gc = A.gc, gb = 2 * gc;
+  const int rect = lb % (A.ny * A.nz), grp = lb / (A.ny * A.nz);
+  const int y0 = (rect / A.nz) * yr, z0 = (rect % A.nz) * zr, c0 = grp * gc;
+  const int NSr = yr * zr * gc;             // series of the block (= SX_E / K)
+  for (int k = tid; k < SX_E; k += SX_NT) buf[k] = make_double2(0.0, 0.0);
+  for (int k = tid; k < K; k += SX_NT) stw[k] = A.tw[k];
+  const int m = A.ctrl->spread_m;
+  // a stencil with base b covers b - ORDER + 1 .. b: it reaches [lo, lo + n) when b lies in
+  // [lo, lo + n + ORDER - 2]; centroid bases widened by m points either way
+  const int ylo = y0 - m, yn = yr + ORDER - 1 + 2 * m;
+  const int zlo = z0 - m, zn = zr + ORDER - 1 + 2 * m;
+  if (tid == 0) {
+    // ranges of binned atoms: every x tile; the y tiles of [ylo, ylo + yn) (all if that
+    // spans the axis); for each, the z tiles of [zlo, zlo + zn) as one or two runs
+    const int ys = (ylo % A.K1 + A.K1) % A.K1, zs = (zlo % A.K2 + A.K2) % A.K2;
+    const int ty0 = yn >= A.K1 ? 0 : ys / QHP_TB;
+    const int tyn = yn >= A.K1 ? A.nt1 : min(A.nt1, (ys + yn - 1) / QHP_TB - ty0 + 1);
+    int zp0[2], zp1[2], nzp = 0;
+    if (zn >= A.K2) {
+      zp0[0] = 0; zp1[0] = A.nt2; nzp = 1;
+    } else {
+      const int za = zs / QHP_TB, zb = (zs + zn - 1) / QHP_TB;   // zb may pass the last tile
+      if (zb < A.nt2) { zp0[0] = za; zp1[0] = zb + 1; nzp = 1; }
+      else {
+        zp0[0] = za; zp1[0] = A.nt2;
+        zp0[1] = 0; zp1[1] = min(za, zb - A.nt2 + 1); nzp = 2;
+      }
+    }
+    int nr = 0, total = 0;
+    for (int tx = 0; tx < A.nt0; ++tx)
+      for (int q = 0; q < tyn; ++q) {
+        const int base = (tx * A.nt1 + (ty0 + q) % A.nt1) * A.nt2;
+        for (int pz = 0; pz < nzp; ++pz) {
+          const int beg = A.tile_start[base + zp0[pz]];
+          const int len = A.tile_start[base + zp1[pz]] - beg;
+          if (len > 0 && nr < MAXR) { tbeg[nr] = beg; tofs[nr] = total; total += len; ++nr; }
+        }
+      }
+    tofs[nr] = total;
+    nranges = nr;
+  }
+  __syncthreads();
+  const int nr = nranges, total = tofs[nr];
+  const int Kd[3] = {A.K0, A.K1, A.K2};
+  const int nb = min(gb, A.P - 2 * c0);     // beads of the block (P = 1: one)
+  int pos = 0;
+  for (;;) {
+    // 1) atoms whose centroid base lies in the widened y and z ranges
+    if (tid == 0) ncand = 0;
+    __syncthreads();
+    while (pos < total && ncand <= CAP - SX_NT) {
+      const int p = pos + tid;
+      bool hit = false;
+      int a = -1;
+      if (p < total) {
+        int lo = 0, hi = nr;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (tofs[mid] <= p) lo = mid; else hi = mid;
+        }
+        a = A.tile_atoms[tbeg[lo] + (p - tofs[lo])];
+        const double4 c = A.cent[a];
+        const int by = base_of(c.y, A.KoL[1], A.K1), bz = base_of(c.z, A.KoL[2], A.K2);
+        const int dy = ((by - ylo) % A.K1 + A.K1) % A.K1, dz = ((bz - zlo) % A.K2 + A.K2) % A.K2;
+        hit = (yn >= A.K1 || dy < yn) && (zn >= A.K2 || dz < zn);
+      }
+      const unsigned long long bal = __ballot(hit);
+      int off = 0;
+      if (lane == 0 && bal) off = atomicAdd(&ncand, __popcll(bal));
+      off = __shfl(off, 0);
+      if (hit) cand[off + __popcll(bal & ((1ull << lane) - 1ull))] = a;
+      pos += SX_NT;
+      __syncthreads();
+    }
+    const bool more = pos < total;
+    const int nc = ncand;
+    // 2) every compacted atom at every bead of the block: spline weights, the points of
+    //    its stencil on the block's lines
+    for (int it = tid; it < nc * gb; it += SX_NT) {
+      const int bl = it % gb, b = 2 * c0 + bl;
+      if (bl >= nb) continue;
+      const int a = cand[it / gb];
+      int base[3];
+      double fr[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double u = grid_coord(A.x[((size_t)d * A.N + a) * A.P + b], A.KoL[d], Kd[d]);
+        const double fl = floor(u);
+        base[d] = isfinite(fl) ? min(max((int)fl, 0), Kd[d]) : 0;
+        fr[d] = u - fl;
+      }
+      // the stencil rows on the rectangle (nothing to do for most beads of edge atoms)
+      int ry[ORDER], rz[ORDER];
+      bool any_y = false, any_z = false;
+#pragma unroll
+      for (int t = 0; t < ORDER; ++t) {
+        ry[t] = (base[1] - t - y0) & (A.K1 - 1);
+        rz[t] = (base[2] - t - z0) & (A.K2 - 1);
+        any_y = any_y || ry[t] < yr;
+        any_z = any_z || rz[t] < zr;
+      }
+      if (!(any_y && any_z)) continue;
+      double w[3][ORDER], dw[3][ORDER];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) bspline<ORDER>(fr[d], w[d], dw[d]);
+      const double qa = A.charge[a];
+      int xk[ORDER];
+#pragma unroll
+      for (int t = 0; t < ORDER; ++t) xk[t] = ((base[0] - t) & (A.K0 - 1)) * (NSr * 2);
+#pragma unroll
+      for (int ty = 0; ty < ORDER; ++ty) {
+        if (ry[ty] >= yr) continue;
+        const double wy = qa * w[1][ty];
+#pragma unroll
+        for (int tz = 0; tz < ORDER; ++tz) {
+          if (rz[tz] >= zr) continue;
+          const double wyz = wy * w[2][tz];
+          double* row = acc + (ry[ty] * zr + rz[tz]) * gb + bl;
+#pragma unroll
+          for (int tx = 0; tx < ORDER; ++tx) atomicAdd(row + xk[tx], wyz * w[0][tx]);
+        }
+      }
+    }
+    __syncthreads();
+    if (!more) break;
+  }
+  // 3) forward transform of every line along x in LDS, then the lines to the grid
+  GridIO<K> io{A.grid, 0, 0};
+  if (NSr == SX_E / K)
+    fft_stages<K, SX_E / K, false, 1, false, false, false, SX_NT>(buf, stw, tid, io, nullptr, 0);
+  const int KK = A.K1 * A.K2;
+  if (A.pairs) {
+    // slot-pair planes: consecutive threads take the two slots of a point, then z
+    const int Gg = A.Pc >> 1;
+    for (int k = tid; k < SX_E; k += SX_NT) {
+      const int s2 = k & 1, zl = (k >> 1) % zr, r = (k >> 1) / zr;
+      const int yl = r % yr, gl = (r / yr) % (gc >> 1), e = r / (yr * (gc >> 1));
+      const int c = c0 + 2 * gl + s2;
+      const size_t pl = (size_t)e * Gg + (c >> 1);
+      A.grid[(pl * KK + (size_t)(y0 + yl) * A.K2 + (z0 + zl)) * 2 + s2] =
+          buf[e * NSr + (yl * zr + zl) * gc + 2 * gl + s2];
+    }
+    return;
+  }
+  for (int k = tid; k < SX_E; k += SX_NT) {
+    const int e = k / NSr, sr = k % NSr;
+    const int cl = sr % gc, zl = (sr / gc) % zr, yl = sr / (gc * zr);
+    A.grid[((size_t)e * KK + (size_t)(y0 + yl) * A.K2 + (z0 + zl)) * A.Pc + c0 + cl] = buf[k];
+  }
+}
+
+// Inverse x transform from slot-pair planes [K0][Pc/2][K1][K2][2] to the point-major grid
+// [K0][K1][K2][Pc] the gather reads: one block holds a run of (y, z) lines for every slot
+// and all x (8,192 complex values); it reads 256-byte runs of each pair plane and writes
+// whole point rows. The layout change rides on the pass that reads and writes the grid
+// anyway.
+template <int K>
+__global__ __launch_bounds__(SX_NT) void k_fft_x_pairs(const double2* src, double2* dst,
+                                                       const double2* tw, int KK, int Pc,
+                                                       int lgI, int remap) {
+  constexpr int NS = SX_E / K;
+  __shared__ double2 buf[SX_E];
+  __shared__ double2 stw[K];
+  const int tid = threadIdx.x;
+  const int lb = remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int lines = NS / Pc, first = lb * lines, Gg = Pc >> 1;
+  for (int k = tid; k < K; k += SX_NT) stw[k] = tw[k];
+  for (int k = tid; k < SX_E; k += SX_NT) {
+    const int s2 = k & 1, l = (k >> 1) % lines, r = (k >> 1) / lines;
+    const int g = r % Gg, e = r / Gg;
+    buf[e * NS + l * Pc + 2 * g + s2] = src[(((size_t)e * Gg + g) * KK + first + l) * 2 + s2];
+  }
+  __syncthreads();
+  GridIO<K> io{dst, (long)first * Pc, lgI};
+  fft_stages<K, NS, true, 1, false, true, false, SX_NT>(buf, stw, tid, io, nullptr, 0);
 }
 
 // ------------------------- fused y-z convolution of one x plane ------------------------
@@ -770,10 +993,11 @@ QHP_DEV void lds_fft(double2* buf, const double2* tw, Off off, int es) {
 }
 
 struct FftYZArgs {
-  double2* grid;           // [K0][K][K][pc]
+  double2* grid;           // [planes][K][K][pc]
   const double2* tw;       // [K] exp(-2 pi i m / K) (y and z share it: K1 = K2)
   const double* G;         // [K0][K][K]
   int pc;                  // complex slots per grid point
+  int gdiv;                // grid planes per x frequency (1; slot-pair planes: Pc / 2)
 };
 
 constexpr int YZ_NT = 1024;
@@ -793,7 +1017,7 @@ __global__ __launch_bounds__((yz_threads<K, NB>())) void k_fft_yz(FftYZArgs A) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);   // the slot groups of a plane: one XCD
   const int k0 = lb / groups, s0 = (lb % groups) * NB;
   for (int m = tid; m < K; m += NTH) stw[m] = A.tw[m];
-  const size_t plane = (size_t)k0 * K * K;
+  const size_t plane = (size_t)k0 * K * K, gplane = (size_t)(k0 / A.gdiv) * K * K;
   constexpr int PER = K * K * NB / NTH;            // values per thread (a power of two)
   static_assert(PER * NTH == K * K * NB, "plane size");
   {
@@ -818,7 +1042,7 @@ __global__ __launch_bounds__((yz_threads<K, NB>())) void k_fft_yz(FftYZArgs A) {
   lds_fft<K, K * NB, NTH, false>(buf, stw, offy, ROW);
   for (int l = tid; l < K * K * NB; l += NTH) {
     const int s = l % NB, k2 = (l / NB) % K, k1 = l / (NB * K);
-    const double g = A.G[plane + (size_t)k1 * K + k2];
+    const double g = A.G[gplane + (size_t)k1 * K + k2];
     double2& v = buf[k1 * ROW + k2 * NB + s];
     v.x *= g; v.y *= g;
   }
@@ -854,7 +1078,7 @@ __global__ __launch_bounds__(512 * NB) void k_fft_yz64(FftYZArgs A) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int k0 = lb / groups, s0 = (lb % groups) * NB;
   if (tid < K) stw[tid] = A.tw[tid];
-  const size_t plane = (size_t)k0 * K * K;
+  const size_t plane = (size_t)k0 * K * K, gplane = (size_t)(k0 / A.gdiv) * K * K;
   // Point (k1, k2) of slot s sits at LDS row sw(k1), column sw(k2), sw(e) permuting the
   // low three bits of e by its high three (e ^ (e >> 3) within each group of eight):
   // every access below reads or writes elements 8a + b with one of a, b running over the
@@ -906,7 +1130,7 @@ __global__ __launch_bounds__(512 * NB) void k_fft_yz64(FftYZArgs A) {
   dft8<false>(v);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {             // v[k] = X[k1 = j + 8 k] at column k2 = r
-    const double gv = A.G[plane + (size_t)(j + 8 * k) * K + r];
+    const double gv = A.G[gplane + (size_t)(j + 8 * k) * K + r];
     v[k].x *= gv; v[k].y *= gv;
   }
   dft8<true>(v);
@@ -998,7 +1222,7 @@ static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc, double2* grid
 // 64 points take the fused plane kernel between the two x passes (unless the autotuner
 // found the one-axis passes faster: fft_nb < 0); other grids take five one-axis passes
 // (the z pass fusing G).
-static hipError_t convolve(qhp_ctx* c, int pc, double2* grid) {
+static hipError_t convolve(qhp_ctx* c, int pc, double2* grid, bool x_done = false) {
   const int K = c->K[1];
   int nb = 0;                                      // slots per plane block (0: five passes)
   if (K == c->K[2] && (K == 64 || K == 32)) {
@@ -1013,10 +1237,10 @@ static hipError_t convolve(qhp_ctx* c, int pc, double2* grid) {
     if (nb > pc) nb = pc;
   }
   hipError_t e;
-  if ((e = fft_pass(c, 0, 0, pc, grid)) != hipSuccess) return e;
+  if (!x_done && (e = fft_pass(c, 0, 0, pc, grid)) != hipSuccess) return e;
   if (nb) {
     FftYZArgs A;
-    A.grid = grid; A.tw = c->tw[1]; A.G = c->influence; A.pc = pc;
+    A.grid = grid; A.tw = c->tw[1]; A.G = c->influence; A.pc = pc; A.gdiv = 1;
     const unsigned blocks = (unsigned)(c->K[0] * (pc / nb));
 #define YZ_CALL(KK, NBV)                                                                    \
     hipLaunchKernelGGL((k_fft_yz<KK, NBV>), blocks, (yz_threads<KK, NBV>()), 0, c->stream, A)
@@ -1037,6 +1261,35 @@ static hipError_t convolve(qhp_ctx* c, int pc, double2* grid) {
     if ((e = fft_pass(c, 1, 1, pc, grid)) != hipSuccess) return e;
   }
   return fft_pass(c, 0, 1, pc, grid);
+}
+
+// Block shape of the fused spreading and forward x transform: gc complex slots (2 gc beads,
+// from the spreading beads per block of qhp_set_launch / the autotuner; default 4 slots)
+// and a yr x zr rectangle of (y, z) lines with yr zr gc K0 = 8,192, zr = 8 z tiles of the
+// launch shape (default one tile of 8 points) where that fits. Not applicable (false) when
+// the grid or the slots do not fill such blocks, or when the binned atoms a block scans
+// could exceed its list of tile ranges (centroid-bead base offsets up to one tile, which
+// the normal-mode kernel enforces).
+static bool spread_x_shape(const qhp_ctx* c, int P, int pc, SpreadXArgs& X) {
+  const int K0 = c->K[0], K1 = c->K[1], K2 = c->K[2];
+  if (c->spread_gb < 0) return false;                  // the tiled spreading was asked for
+  // one slot (a single bead): the tiled spreading with the separate x pass measured faster
+  if (pc < 2 || K0 < 16 || K0 > 128) return false;
+  int gc = c->spread_gb > 0 ? std::max(1, c->spread_gb / 2) : 4;
+  gc = std::min(gc, pc);
+  if ((long)K0 * gc > SX_E) return false;
+  const long lines = SX_E / ((long)K0 * gc);
+  if (lines > (long)K1 * K2) return false;
+  int zr = std::min<long>(lines, std::min(K2, QHP_TB * (c->spread_z > 0 ? c->spread_z : 1)));
+  long yr = lines / zr;
+  if (yr > K1) { yr = K1; zr = (int)(lines / K1); }
+  if (zr > K2 || yr * zr != lines) return false;
+  const int yn = (int)yr + c->p.pme_order - 1 + 2 * QHP_TB;
+  const int nt1 = K1 / QHP_TB, tyn = std::min(nt1, (yn + QHP_TB - 2) / QHP_TB + 1);
+  if ((K0 / QHP_TB) * tyn * 2 > 160) return false;
+  X.gc = gc; X.yr = (int)yr; X.zr = zr; X.ny = K1 / (int)yr; X.nz = K2 / zr;
+  (void)P;
+  return true;
 }
 
 hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int part) {
@@ -1071,6 +1324,68 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
         hipLaunchKernelGGL(k_tile_bin, (N + 255) / 256, 256, 0, c->stream, T);
         hipLaunchKernelGGL(k_tile_scan, 1, 256, 0, c->stream, T);
         hipLaunchKernelGGL(k_tile_scatter, (N + 255) / 256, 256, 0, c->stream, T);
+      }
+      SpreadXArgs X;
+      if (!plain && spread_x_shape(c, P, pc, X)) {
+        X.N = N; X.P = P; X.K0 = c->K[0]; X.K1 = c->K[1]; X.K2 = c->K[2]; X.Pc = pc;
+        X.nt0 = T.nt0; X.nt1 = T.nt1; X.nt2 = T.nt2;
+        X.x = A.x; X.charge = c->d_charge; X.cent = c->cent; X.ctrl = c->ctrl;
+        for (int d = 0; d < 3; ++d) { X.L[d] = c->p.box[d]; X.KoL[d] = c->K[d] / c->p.box[d]; }
+        X.tile_start = c->tile_start; X.tile_atoms = c->tile_atoms; X.tw = c->tw[0];
+        // slot-pair planes for the y-z plane kernel when it applies
+        const int K = c->K[1];
+        const bool pairs = c->grid_l1 && pc >= 2 && X.gc % 2 == 0 && K == c->K[2] &&
+                           (K == 64 || K == 32) && c->fft_nb >= 0 && SX_E % (c->K[0] * pc) == 0 &&
+                           (long)SX_E / (c->K[0] * pc) <= (long)K * K;
+        X.pairs = pairs;
+        X.grid = pairs ? c->grid_l1 : c->grid;
+        const unsigned blocks = (unsigned)(X.ny * X.nz * (pc / X.gc));
+        X.remap = blocks % 8 == 0;
+#define SPREADX_CALL(KK)                                                                      \
+        QHP_SWITCH_ORDER(c->p.pme_order, hipLaunchKernelGGL((k_spread_x<OO, KK>), blocks, SX_NT, 0, \
+                                                            c->stream, X))
+        switch (c->K[0]) {
+          case 16: SPREADX_CALL(16); break;
+          case 32: SPREADX_CALL(32); break;
+          case 64: SPREADX_CALL(64); break;
+          case 128: SPREADX_CALL(128); break;
+          default: return hipErrorInvalidValue;
+        }
+#undef SPREADX_CALL
+        prof_end(c, QHP_PROF_SPREAD, ev);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        prof_begin(c, QHP_PROF_FFT, &ev);
+        if (pairs) {
+          // y-z planes of slot pairs (contiguous 2-slot planes), then the inverse x pass
+          // that also returns the grid to the point-major layout
+          const int nbs = c->fft_nb == 1 ? 1 : 2;
+          FftYZArgs Y;
+          Y.grid = c->grid_l1; Y.tw = c->tw[1]; Y.G = c->influence; Y.pc = 2; Y.gdiv = pc / 2;
+          const unsigned yblocks = (unsigned)(c->K[0] * (pc / 2) * (2 / nbs));
+          if (K == 64) {
+            if (nbs == 1) hipLaunchKernelGGL(k_fft_yz64<1>, yblocks, 512, 0, c->stream, Y);
+            else hipLaunchKernelGGL(k_fft_yz64<2>, yblocks, 1024, 0, c->stream, Y);
+          } else {
+            if (nbs == 1) hipLaunchKernelGGL((k_fft_yz<32, 1>), yblocks, (yz_threads<32, 1>()), 0, c->stream, Y);
+            else hipLaunchKernelGGL((k_fft_yz<32, 2>), yblocks, (yz_threads<32, 2>()), 0, c->stream, Y);
+          }
+          const int KK = c->K[1] * c->K[2], lines = SX_E / (c->K[0] * pc);
+          const unsigned xblocks = (unsigned)(KK / lines);
+          const int lgI = __builtin_ctzl((unsigned long)KK * pc), remap = xblocks % 8 == 0;
+          switch (c->K[0]) {
+            case 16: hipLaunchKernelGGL(k_fft_x_pairs<16>, xblocks, SX_NT, 0, c->stream, c->grid_l1, c->grid, c->tw[0], KK, pc, lgI, remap); break;
+            case 32: hipLaunchKernelGGL(k_fft_x_pairs<32>, xblocks, SX_NT, 0, c->stream, c->grid_l1, c->grid, c->tw[0], KK, pc, lgI, remap); break;
+            case 64: hipLaunchKernelGGL(k_fft_x_pairs<64>, xblocks, SX_NT, 0, c->stream, c->grid_l1, c->grid, c->tw[0], KK, pc, lgI, remap); break;
+            case 128: hipLaunchKernelGGL(k_fft_x_pairs<128>, xblocks, SX_NT, 0, c->stream, c->grid_l1, c->grid, c->tw[0], KK, pc, lgI, remap); break;
+            default: return hipErrorInvalidValue;
+          }
+          if ((e = hipGetLastError()) != hipSuccess) return e;
+        } else if ((e = convolve(c, pc, c->grid, true)) != hipSuccess) {
+          return e;
+        }
+        prof_end(c, QHP_PROF_FFT, ev);
+        goto gather;
       }
       TSpreadArgs S;
       S.N = N; S.P = P; S.K0 = c->K[0]; S.K1 = c->K[1]; S.K2 = c->K[2];
@@ -1116,6 +1431,7 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
     if ((e = convolve(c, pc, c->grid)) != hipSuccess) return e;
     prof_end(c, QHP_PROF_FFT, ev);
   }
+gather:
   if (!(part & SPME_GATHER)) return hipGetLastError();
   prof_begin(c, QHP_PROF_GATHER, &ev);
   A.nblocks = (int)nb;
