@@ -700,7 +700,10 @@ __global__ __launch_bounds__(NT) void k_fft_pass(FftArgs A) {
 // without a round trip of the grid through memory, and the plane kernels and inverse
 // passes that follow are unchanged. The rectangle's shape and the slots per block trade
 // the spline work repeated for atoms near the rectangle's edges against the length of the
-// contiguous pieces written (launch shapes picked by the autotuner).
+// contiguous pieces written (launch shapes picked by the autotuner). The candidate atoms
+// are found from the tile bins (one thread per tile range, then a scan) and sorted by the
+// offset of their centroid's stencil base from the rectangle, so that the lanes of a
+// wavefront visit the same stencil rows.
 constexpr int SX_E = 8192;                  // complex values of one block
 constexpr int SX_NT = 1024;
 
@@ -724,12 +727,17 @@ template <int ORDER, int K>
 __global__ __launch_bounds__(SX_NT) void k_spread_x(SpreadXArgs A) {
   constexpr int CAP = 2048;                 // compacted atoms per round
   constexpr int MAXR = 160;                 // candidate tile ranges (checked by the launcher)
+  constexpr int NBIN = SX_NT;               // candidate classes of the sort
   __shared__ double2 buf[SX_E];
   __shared__ double2 stw[K];
   __shared__ int cand[CAP];
+  __shared__ int ckey[CAP];                 // class of each candidate, then the sorted atoms
+  __shared__ int hist[NBIN];
   __shared__ int ncand;
   __shared__ int tofs[MAXR + 1], tbeg[MAXR];
   __shared__ int nranges;
+  __shared__ int wsum[(MAXR + 63) / 64];
+  __shared__ int wtot[SX_NT / 64];
   double* acc = reinterpret_cast<double*>(buf);        // [x][yl][zl][2 gc]
   const int tid = threadIdx.x, lane = tid & 63;
   const int lb = A.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -739,45 +747,57 @@ __global__ __launch_bounds__(SX_NT) void k_spread_x(SpreadXArgs A) {
   const int NSr = yr * zr * gc;             // series of the block (= SX_E / K)
   for (int k = tid; k < SX_E; k += SX_NT) buf[k] = make_double2(0.0, 0.0);
   for (int k = tid; k < K; k += SX_NT) stw[k] = A.tw[k];
-  const int m = A.ctrl->spread_m;
+  const int m = min(A.ctrl->spread_m, QHP_TB);  // larger offsets are flagged by the binning
   // a stencil with base b covers b - ORDER + 1 .. b: it reaches [lo, lo + n) when b lies in
   // [lo, lo + n + ORDER - 2]; centroid bases widened by m points either way
   const int ylo = y0 - m, yn = yr + ORDER - 1 + 2 * m;
   const int zlo = z0 - m, zn = zr + ORDER - 1 + 2 * m;
-  if (tid == 0) {
+  {
     // ranges of binned atoms: every x tile; the y tiles of [ylo, ylo + yn) (all if that
-    // spans the axis); for each, the z tiles of [zlo, zlo + zn) as one or two runs
+    // spans the axis); for each, the z tiles of [zlo, zlo + zn) as one or two runs. One
+    // thread per range reads its bounds, an exclusive scan of the lengths places them
+    // (empty ranges are kept: the search below never lands on one).
     const int ys = (ylo % A.K1 + A.K1) % A.K1, zs = (zlo % A.K2 + A.K2) % A.K2;
     const int ty0 = yn >= A.K1 ? 0 : ys / QHP_TB;
     const int tyn = yn >= A.K1 ? A.nt1 : min(A.nt1, (ys + yn - 1) / QHP_TB - ty0 + 1);
-    int zp0[2], zp1[2], nzp = 0;
-    if (zn >= A.K2) {
-      zp0[0] = 0; zp1[0] = A.nt2; nzp = 1;
-    } else {
+    int zp0[2] = {0, 0}, zp1[2] = {A.nt2, A.nt2}, nzp = 1;
+    if (zn < A.K2) {
       const int za = zs / QHP_TB, zb = (zs + zn - 1) / QHP_TB;   // zb may pass the last tile
-      if (zb < A.nt2) { zp0[0] = za; zp1[0] = zb + 1; nzp = 1; }
-      else {
-        zp0[0] = za; zp1[0] = A.nt2;
-        zp0[1] = 0; zp1[1] = min(za, zb - A.nt2 + 1); nzp = 2;
-      }
+      if (zb < A.nt2) { zp0[0] = za; zp1[0] = zb + 1; }
+      else { zp0[0] = za; zp1[0] = A.nt2; zp1[1] = min(za, zb - A.nt2 + 1); nzp = 2; }
     }
-    int nr = 0, total = 0;
-    for (int tx = 0; tx < A.nt0; ++tx)
-      for (int q = 0; q < tyn; ++q) {
-        const int base = (tx * A.nt1 + (ty0 + q) % A.nt1) * A.nt2;
-        for (int pz = 0; pz < nzp; ++pz) {
-          const int beg = A.tile_start[base + zp0[pz]];
-          const int len = A.tile_start[base + zp1[pz]] - beg;
-          if (len > 0 && nr < MAXR) { tbeg[nr] = beg; tofs[nr] = total; total += len; ++nr; }
-        }
-      }
-    tofs[nr] = total;
-    nranges = nr;
+    // at most MAXR ranges (the launcher's bound on x tiles x y tiles x 2)
+    const int nr = min(A.nt0 * tyn * nzp, MAXR);
+    int len = 0, beg = 0;
+    if (tid < nr) {
+      const int pz = tid % nzp, q = (tid / nzp) % tyn, tx = tid / (nzp * tyn);
+      const int base = (tx * A.nt1 + (ty0 + q) % A.nt1) * A.nt2;
+      beg = A.tile_start[base + zp0[pz]];
+      len = A.tile_start[base + zp1[pz]] - beg;
+    }
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63 && (tid >> 6) < (MAXR + 63) / 64) wsum[tid >> 6] = incl;
+    __syncthreads();
+    if (tid < nr) {
+      int off = incl - len;
+      for (int w = 0; w < (tid >> 6); ++w) off += wsum[w];
+      tbeg[tid] = beg;
+      tofs[tid] = off;
+      if (tid == nr - 1) { tofs[nr] = off + len; nranges = nr; }
+    }
   }
   __syncthreads();
   const int nr = nranges, total = tofs[nr];
   const int Kd[3] = {A.K0, A.K1, A.K2};
   const int nb = min(gb, A.P - 2 * c0);     // beads of the block (P = 1: one)
+  // candidate classes: the centroid base's offsets (dy, dz) from (ylo, zlo), merged into
+  // NBIN ordered classes when there are more
+  const int nzk = min(zn, A.K2), nkey = max(min(yn, A.K1) * nzk, NBIN);
   int pos = 0;
   for (;;) {
     // 1) atoms whose centroid base lies in the widened y and z ranges
@@ -786,7 +806,7 @@ __global__ __launch_bounds__(SX_NT) void k_spread_x(SpreadXArgs A) {
     while (pos < total && ncand <= CAP - SX_NT) {
       const int p = pos + tid;
       bool hit = false;
-      int a = -1;
+      int a = -1, key = 0;
       if (p < total) {
         int lo = 0, hi = nr;
         while (hi - lo > 1) {
@@ -798,23 +818,62 @@ __global__ __launch_bounds__(SX_NT) void k_spread_x(SpreadXArgs A) {
         const int by = base_of(c.y, A.KoL[1], A.K1), bz = base_of(c.z, A.KoL[2], A.K2);
         const int dy = ((by - ylo) % A.K1 + A.K1) % A.K1, dz = ((bz - zlo) % A.K2 + A.K2) % A.K2;
         hit = (yn >= A.K1 || dy < yn) && (zn >= A.K2 || dz < zn);
+        key = (int)((long)(dy * nzk + dz) * NBIN / nkey);
       }
       const unsigned long long bal = __ballot(hit);
       int off = 0;
       if (lane == 0 && bal) off = atomicAdd(&ncand, __popcll(bal));
       off = __shfl(off, 0);
-      if (hit) cand[off + __popcll(bal & ((1ull << lane) - 1ull))] = a;
+      if (hit) {
+        const int k = off + __popcll(bal & ((1ull << lane) - 1ull));
+        cand[k] = a;
+        ckey[k] = key;
+      }
       pos += SX_NT;
       __syncthreads();
     }
     const bool more = pos < total;
     const int nc = ncand;
+    // counting sort of the candidates by the (y, z) offset of their centroid base from the
+    // rectangle: the lanes of a wavefront then mostly share which stencil rows fall on the
+    // block's lines, and the row loop below runs uniformly over those rows only
+    for (int k = tid; k < NBIN; k += SX_NT) hist[k] = 0;
+    __syncthreads();
+    for (int k = tid; k < nc; k += SX_NT) atomicAdd(&hist[ckey[k]], 1);
+    __syncthreads();
+    {
+      const int h = hist[tid];              // NBIN = SX_NT: one class per thread
+      int incl = h;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+      }
+      if (lane == 63) wtot[tid >> 6] = incl;
+      __syncthreads();
+      int off = incl - h;
+      for (int w = 0; w < (tid >> 6); ++w) off += wtot[w];
+      hist[tid] = off;
+    }
+    constexpr int PER = CAP / SX_NT;
+    int ka[PER], kk[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int k = tid + r * SX_NT;
+      ka[r] = k < nc ? cand[k] : -1;
+      kk[r] = k < nc ? ckey[k] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+      if (ka[r] >= 0) ckey[atomicAdd(&hist[kk[r]], 1)] = ka[r];
+    __syncthreads();
     // 2) every compacted atom at every bead of the block: spline weights, the points of
     //    its stencil on the block's lines
     for (int it = tid; it < nc * gb; it += SX_NT) {
       const int bl = it % gb, b = 2 * c0 + bl;
       if (bl >= nb) continue;
-      const int a = cand[it / gb];
+      const int a = ckey[it / gb];
       int base[3];
       double fr[3];
 #pragma unroll
