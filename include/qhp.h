@@ -176,8 +176,7 @@ typedef struct qhp_ctx qhp_ctx;
  * the force field uses). `stream` is a hipStream_t; all work of the
  * context is queued on it (NULL: the library creates a private non-blocking stream).
  * Validates `p` (QHP_EINVAL; QHP_EUNSUPPORTED for valid settings the library does not run:
- * B-spline order 3 or 7, or more cells plus SPME tiles than the per-step bookkeeping block
- * holds in LDS, 2*(cells + (K0/8)(K1/8)(K2/8)) <= 24576), allocates device state
+ * B-spline order 3 or 7), allocates device state
  * (QHP_ENOMEM) and precomputes the normal-mode transfer matrix, mode frequencies,
  * thermostat and A-block coefficients and the SPME influence function.
  * The state is undefined until qhp_set_state. */

@@ -489,11 +489,6 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     c->cap = (c->cap + 31) / 32 * 32;
   }
   c->cap = std::min(c->cap, N);
-  if ((size_t)(2 * c->ncell + 2 * (c->K[0] / 8) * (c->K[1] / 8) * (c->K[2] / 8)) * sizeof(int) >
-      96 * 1024) {
-    free_all(c); delete c;
-    return QHP_EUNSUPPORTED;      // the per-step prep block keeps its counters in LDS
-  }
   TRY(dalloc(&c->ctrl, 1));
   c->n_bmax = (N + 255) / 256 * 64;      // >= blocks of the normal-mode kernel for any P
   TRY(dalloc(&c->bmax, c->n_bmax));
@@ -501,6 +496,7 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   TRY(hipMemset(c->ctrl, 0, sizeof(NlCtrl)));
   TRY(dalloc(&c->cell_of, N)); TRY(dalloc(&c->cell_count, c->ncell)); TRY(dalloc(&c->cell_fill, c->ncell));
   TRY(dalloc(&c->cell_start, c->ncell + 1)); TRY(dalloc(&c->cell_atoms, N));
+  TRY(hipMemset(c->cell_count, 0, c->ncell * sizeof(int)));   // zero between steps
   TRY(dalloc(&c->nbr, (size_t)c->cap * N)); TRY(dalloc(&c->nnbr, N));
   TRY(hipMemset(c->nnbr, 0, N * sizeof(int)));
 

@@ -120,18 +120,20 @@ __global__ void k_nl_scatter(NlArgs A) {
   A.cell_atoms[A.cell_start[id] + slot] = a;
 }
 
-// One block per step (batched path): reduce the per-block maxima of the normal-mode (or
-// centroid) kernel and decide the rebuild; bin every atom into the SPME tile of its
-// centroid (counts, offsets, scatter, all in LDS); on a rebuild, scatter the atoms into
-// their centroid cells. The kernels that write the centroids also write each centroid's
-// tile and cell, so this block only counts and scatters. The order within a cell is not
-// significant (the exported list is canonical).
+// Batched path, two kernels per step. k_prep_count: every block reduces a share of the
+// per-block maxima written by the normal-mode (or centroid) kernel and counts its atoms
+// into their SPME tiles and centroid cells (the kernels that write the centroids also write
+// each centroid's tile and cell); the last block to finish decides the rebuild, turns the
+// counts into offsets and clears them for the next step. k_prep_scatter then places every
+// atom in its tile and, on a rebuild, in its cell. The order within a tile or a cell is
+// not significant (the exported list is canonical; spreading sums in LDS).
 struct PrepArgs {
   NlArgs nl;
-  int ntiles, nt1, nt2, K0, K1, K2;
-  double KoL0, KoL1, KoL2;
-  int* tile_of; int* tile_start; int* tile_atoms;
+  int ntiles;
+  int* tile_of; int* tile_count; int* tile_fill; int* tile_start; int* tile_atoms;
 };
+constexpr int PREP_NT = 512;              // threads of a prep block
+constexpr int PREP_ATOMS = 1024;          // atoms of a prep block
 
 // Exclusive prefix sum over the block of one value per thread (wavefront shuffles, then
 // the wavefront totals); *total receives the sum of all values.
@@ -163,8 +165,8 @@ QHP_DEV int block_exclusive_scan(int v, int* swave, int* total) {
 
 // Bin counting and scattering by a whole wavefront whose lanes hold consecutive atoms
 // (bin t, or -1 for no atom): neighbouring atoms mostly share a bin, so each run of equal
-// bins takes one LDS atomic, issued by its first lane, instead of one per lane to the
-// same address. Every lane of the wavefront must take part.
+// bins takes one atomic, issued by its first lane, instead of one per lane to the same
+// address. Every lane of the wavefront must take part.
 struct WaveRuns {
   unsigned long long starts;   // lanes where a run begins
   int lane, head, len;         // this lane's run: first lane and length (at the first lane)
@@ -198,36 +200,51 @@ QHP_DEV double wave_fmax(double v) {
   return v;
 }
 
-constexpr int PREP_REG = 16;              // atoms per thread whose bins stay in registers
+// non-negative doubles order like their bit patterns read as unsigned integers
+QHP_DEV unsigned long long max_bits(double v) { return (unsigned long long)__double_as_longlong(v); }
+QHP_DEV int load_agent(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
-__global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
-  extern __shared__ int lds[];
+__global__ __launch_bounds__(PREP_NT) void k_prep_count(PrepArgs B, int force) {
   NlArgs& A = B.nl;
-  int* tcount = lds;                          // [ntiles]
-  int* tfill = lds + B.ntiles;                // [ntiles]
-  int* ccount = lds + 2 * B.ntiles;           // [ncell]
-  int* cfill = ccount + A.ncell;              // [ncell]
-  __shared__ double sm[4][16];
-  __shared__ int swave[16];
-  __shared__ int go;
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6;
-  // ---- 1. rebuild decision and step bookkeeping ----
+  __shared__ double sm[4][PREP_NT / 64];
+  __shared__ int swave[PREP_NT / 64];
+  __shared__ int last, go;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nblk = gridDim.x;
+  // ---- 1. this block's share of the per-block maxima ----
   double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = tid; k < A.n_bmax; k += nt) {
+  for (int k = blockIdx.x * PREP_NT + tid; k < A.n_bmax; k += nblk * PREP_NT) {
     const double4 v = A.bmax[k];
     a[0] = fmax(a[0], v.x); a[1] = fmax(a[1], v.y); a[2] = fmax(a[2], v.z); a[3] = fmax(a[3], v.w);
   }
   for (int q = 0; q < 4; ++q) a[q] = wave_fmax(a[q]);
   if (lane == 0)
     for (int q = 0; q < 4; ++q) sm[q][wv] = a[q];
-  for (int k = tid; k < B.ntiles; k += nt) tcount[k] = 0;
-  for (int k = tid; k < A.ncell; k += nt) ccount[k] = 0;
+  // ---- 2. tile and cell counts of the block's atoms (consecutive atoms in consecutive
+  //         lanes: one atomic per run of equal bins) ----
+  for (int r = 0; r < PREP_ATOMS / PREP_NT; ++r) {
+    const int i = blockIdx.x * PREP_ATOMS + r * PREP_NT + tid;
+    wave_count(B.tile_count, i < A.N ? B.tile_of[i] : -1);
+    wave_count(A.cell_count, i < A.N ? A.cell_of[i] : -1);
+  }
+  __threadfence();
   __syncthreads();
   if (tid == 0) {
-    double m[4] = {sm[0][0], sm[1][0], sm[2][0], sm[3][0]};
-    for (int w = 1; w < nt / 64; ++w)
-      for (int q = 0; q < 4; ++q) m[q] = fmax(m[q], sm[q][w]);
+    for (int q = 0; q < 4; ++q) {
+      double m = sm[q][0];
+      for (int w = 1; w < PREP_NT / 64; ++w) m = fmax(m, sm[q][w]);
+      atomicMax(&A.ctrl->prep_max[q], max_bits(m));
+    }
+    __threadfence();
+    last = atomicAdd(&A.ctrl->prep_done, 1) == nblk - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  // ---- 3. the last block: rebuild decision and step bookkeeping ----
+  __threadfence();
+  if (tid == 0) {
     NlCtrl* c = A.ctrl;
+    double m[4];
+    for (int q = 0; q < 4; ++q) m[q] = __longlong_as_double((long long)atomicExch(&c->prep_max[q], 0ull));
     const double dc = sqrt(m[0]), db = sqrt(m[1]);
     const int b = force || c->force_build || !(2.0 * (dc + db) <= A.skin);
     c->do_build = b;
@@ -237,84 +254,38 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs B, int force) {
     c->max_db = db;
     if (m[3] != 0.0) c->spread_margin = 1;
     if (b) { c->n_builds += 1; c->max_count = 0; }
+    c->prep_done = 0;
     go = b;
   }
-  // Up to PREP_REG atoms per thread, each thread bins a contiguous run of atoms:
-  // neighbouring lanes then hold atoms a few molecules apart, which mostly fall in
-  // different bins (fewer same-address LDS atomics), and the bins stay in registers for
-  // the scatter. Larger systems are binned with a strided map instead (atom tid + k nt),
-  // PREP_REG loads in flight per thread: a wavefront's loads then read two contiguous
-  // cache lines rather than 64 (this block runs on one compute unit).
-  const int per = (A.N + nt - 1) / nt;
-  const int i0 = min(A.N, tid * per), i1 = min(A.N, i0 + per);
-  const bool strided = per > PREP_REG;
-  // (all threads run every iteration: the wavefront-wide run aggregation needs them)
-  auto each_strided = [&](const int* bin_of, auto&& use) {
-    for (int base = 0; base < A.N; base += nt * PREP_REG) {
-      int r[PREP_REG];
-#pragma unroll
-      for (int k = 0; k < PREP_REG; ++k) {
-        const int i = base + k * nt + tid;
-        r[k] = i < A.N ? bin_of[i] : -1;
-      }
-#pragma unroll
-      for (int k = 0; k < PREP_REG; ++k) use(base + k * nt + tid, r[k]);
-    }
-  };
-  // ---- 2. SPME tiles (each centroid's tile was written with the centroid) ----
-  int reg[PREP_REG];
-  if (strided) {
-    each_strided(B.tile_of, [&](int, int t) { wave_count(tcount, t); });
-  } else {
-#pragma unroll
-    for (int k = 0; k < PREP_REG; ++k)
-      if (i0 + k < i1) reg[k] = B.tile_of[i0 + k];
-#pragma unroll
-    for (int k = 0; k < PREP_REG; ++k)
-      if (i0 + k < i1) atomicAdd(&tcount[reg[k]], 1);
-  }
   __syncthreads();
-  // exclusive scan of a count array of length n by the block (per-thread chunks)
-  auto scan = [&](const int* cnt, int* start_g, int* fill, int n) {
-    const int pc = (n + nt - 1) / nt;
+  // ---- 4. offsets (start and the scatter's fill pointer) from the counts, which are
+  //         cleared for the next step; cell offsets only on a rebuild ----
+  auto scan = [&](int* cnt, int* start_g, int* fill, int n, bool write) {
+    const int pc = (n + PREP_NT - 1) / PREP_NT;
     const int b0 = min(n, tid * pc), b1 = min(n, b0 + pc);
     int s = 0;
-    for (int k = b0; k < b1; ++k) s += cnt[k];
+    for (int k = b0; k < b1; ++k) s += load_agent(cnt + k);
     int total;
     int acc = block_exclusive_scan(s, swave, &total);
-    for (int k = b0; k < b1; ++k) { start_g[k] = acc; fill[k] = acc; acc += cnt[k]; }
-    if (tid == 0) start_g[n] = total;
-    __syncthreads();
+    for (int k = b0; k < b1; ++k) {
+      const int v = load_agent(cnt + k);
+      if (write) { start_g[k] = acc; fill[k] = acc; }
+      acc += v;
+      cnt[k] = 0;
+    }
+    if (write && tid == 0) start_g[n] = total;
   };
-  scan(tcount, B.tile_start, tfill, B.ntiles);
-  if (strided) {
-    each_strided(B.tile_of, [&](int i, int t) { wave_scatter(tfill, B.tile_atoms, t, i); });
-  } else {
-#pragma unroll
-    for (int k = 0; k < PREP_REG; ++k)
-      if (i0 + k < i1) B.tile_atoms[atomicAdd(&tfill[reg[k]], 1)] = i0 + k;
-  }
-  // ---- 3. centroid cells of a rebuild ----
-  // (the cell of each centroid was written with it; the build kernel records the frame)
-  if (!go) return;
-  if (strided) {
-    each_strided(A.cell_of, [&](int, int id) { wave_count(ccount, id); });
-  } else {
-#pragma unroll
-    for (int k = 0; k < PREP_REG; ++k)
-      if (i0 + k < i1) reg[k] = A.cell_of[i0 + k];
-#pragma unroll
-    for (int k = 0; k < PREP_REG; ++k)
-      if (i0 + k < i1) atomicAdd(&ccount[reg[k]], 1);
-  }
-  __syncthreads();
-  scan(ccount, A.cell_start, cfill, A.ncell);
-  if (strided) {
-    each_strided(A.cell_of, [&](int i, int t) { wave_scatter(cfill, A.cell_atoms, t, i); });
-  } else {
-#pragma unroll
-    for (int k = 0; k < PREP_REG; ++k)
-      if (i0 + k < i1) A.cell_atoms[atomicAdd(&cfill[reg[k]], 1)] = i0 + k;
+  scan(B.tile_count, B.tile_start, B.tile_fill, B.ntiles, true);
+  scan(A.cell_count, A.cell_start, A.cell_fill, A.ncell, go);
+}
+
+__global__ __launch_bounds__(PREP_NT) void k_prep_scatter(PrepArgs B) {
+  NlArgs& A = B.nl;
+  const bool go = A.ctrl->do_build;
+  for (int r = 0; r < PREP_ATOMS / PREP_NT; ++r) {
+    const int i = blockIdx.x * PREP_ATOMS + r * PREP_NT + threadIdx.x;
+    wave_scatter(B.tile_fill, B.tile_atoms, i < A.N ? B.tile_of[i] : -1, i);
+    if (go) wave_scatter(A.cell_fill, A.cell_atoms, i < A.N ? A.cell_of[i] : -1, i);
   }
 }
 
@@ -461,20 +432,19 @@ qhp::BinGeom bin_geom(const qhp_ctx* c) {
   return G;
 }
 
-size_t prep_lds_bytes(const qhp_ctx* c) { return (size_t)(2 * c->ntiles + 2 * c->ncell) * sizeof(int); }
-
-// Batched path: one prep block (decision, SPME tiles, cells of a rebuild), then the build.
-// Plain path: the decision and cells by separate kernels (tiles are binned per bead).
+// Batched path: the prep kernels (decision, SPME tiles, cells of a rebuild), then the
+// build. Plain path: the decision and cells by separate kernels (tiles are binned per bead).
 hipError_t launch_nlist(qhp_ctx* c, bool from_step) {
   NlArgs A = nl_args(c);
   if (c->p.exec != QHP_PLAIN) {
     PrepArgs B;
     B.nl = A;
-    B.ntiles = c->ntiles; B.nt1 = c->K[1] / QHP_TB; B.nt2 = c->K[2] / QHP_TB;
-    B.K0 = c->K[0]; B.K1 = c->K[1]; B.K2 = c->K[2];
-    B.KoL0 = c->K[0] / c->p.box[0]; B.KoL1 = c->K[1] / c->p.box[1]; B.KoL2 = c->K[2] / c->p.box[2];
-    B.tile_of = c->tile_of; B.tile_start = c->tile_start; B.tile_atoms = c->tile_atoms;
-    hipLaunchKernelGGL(k_prep, 1, 1024, prep_lds_bytes(c), c->stream, B, from_step ? 0 : 1);
+    B.ntiles = c->ntiles;
+    B.tile_of = c->tile_of; B.tile_count = c->tile_count; B.tile_fill = c->tile_fill;
+    B.tile_start = c->tile_start; B.tile_atoms = c->tile_atoms;
+    const unsigned nb = (unsigned)((c->N + PREP_ATOMS - 1) / PREP_ATOMS);
+    hipLaunchKernelGGL(k_prep_count, nb, PREP_NT, 0, c->stream, B, from_step ? 0 : 1);
+    hipLaunchKernelGGL(k_prep_scatter, nb, PREP_NT, 0, c->stream, B);
     hipLaunchKernelGGL(k_nl_build, c->ncell, NL_THREADS, 0, c->stream, A);
     return hipGetLastError();
   }

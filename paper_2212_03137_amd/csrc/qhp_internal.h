@@ -36,6 +36,8 @@ struct NlCtrl {               // device-side control block (neighbour list, step
   int spread_margin;          // a bead left the SPME tile margin of its centroid
   int spread_m;               // largest bead-centroid grid-base offset this step
   double max_db;              // largest bead-centroid distance this step
+  unsigned long long prep_max[4];  // per-step maxima being reduced (zero between steps)
+  int prep_done;              // prep blocks finished this step (zero between steps)
 };
 
 // The beads a force launch works on: the full ring polymer, or its contraction (V_s under
