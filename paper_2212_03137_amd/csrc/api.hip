@@ -8,6 +8,8 @@
 #include <cstring>
 #include <new>
 #include <set>
+#include <unordered_map>
+#include <vector>
 
 #include "qhp_internal.h"
 
@@ -588,7 +590,7 @@ static int fast_forces(qhp_ctx* c, bool energy) {
 // the list stage. The SPME spread and transforms depend only on the positions and the
 // tile bins of the list stage, so they run on the side stream while the bonded and pair
 // kernels run on the main stream; the gather, which adds into grad V, follows both. When
-// kernel classes are being timed one at a time, and inside a group's captured step (whose
+// kernel classes are being timed one at a time, and in the steps a group captures (whose
 // members are already concurrent branches), everything stays on the main stream.
 static int batched_forces(qhp_ctx* c, bool energy, const BeadSet* bs) {
   if (!c->side || c->serial_forces || c->prof_which != QHP_PROF_OFF) {
@@ -1458,35 +1460,97 @@ extern "C" int qhp_group_destroy(qhp_group* g) {
 
 extern "C" const char* qhp_group_last_error(qhp_group* g) { return g ? g->err.c_str() : "null group"; }
 
-// One step of every member as one graph: member 0's stream is the origin; the others fork
-// from it by an event and join back by one event each, so their kernels form independent
-// branches of the graph.
+// Copy every node of a captured step graph (kernel, memcpy and empty nodes; anything else
+// is refused) into `dst` with the same edges, so that the copies form a branch of `dst`
+// with no dependence on its other nodes.
+static hipError_t graph_append(hipGraph_t dst, hipGraph_t src) {
+  size_t nn = 0, ne = 0;
+  hipError_t e = hipGraphGetNodes(src, nullptr, &nn);
+  if (e == hipSuccess) e = hipGraphGetEdges(src, nullptr, nullptr, &ne);
+  if (e != hipSuccess) return e;
+  std::vector<hipGraphNode_t> nodes(nn), from(ne), to(ne), copy(nn, nullptr);
+  if (nn) e = hipGraphGetNodes(src, nodes.data(), &nn);
+  if (e == hipSuccess && ne) e = hipGraphGetEdges(src, from.data(), to.data(), &ne);
+  if (e != hipSuccess) return e;
+  std::unordered_map<hipGraphNode_t, size_t> index;
+  for (size_t k = 0; k < nn; ++k) index[nodes[k]] = k;
+  std::vector<std::vector<size_t>> deps(nn);
+  for (size_t k = 0; k < ne; ++k) deps[index.at(to[k])].push_back(index.at(from[k]));
+  // nodes in an order where every node follows its dependencies
+  std::vector<int> state(nn, 0);
+  std::vector<size_t> order;
+  order.reserve(nn);
+  for (size_t r = 0; r < nn; ++r) {
+    if (state[r]) continue;
+    std::vector<std::pair<size_t, size_t>> st{{r, 0}};
+    state[r] = 1;
+    while (!st.empty()) {
+      auto& [v, i] = st.back();
+      if (i < deps[v].size()) {
+        const size_t u = deps[v][i++];
+        if (state[u] == 1) return hipErrorInvalidValue;   // not acyclic
+        if (!state[u]) { state[u] = 1; st.push_back({u, 0}); }
+      } else {
+        state[v] = 2;
+        order.push_back(v);
+        st.pop_back();
+      }
+    }
+  }
+  for (size_t v : order) {
+    std::vector<hipGraphNode_t> d;
+    for (size_t u : deps[v]) d.push_back(copy[u]);
+    hipGraphNodeType type;
+    e = hipGraphNodeGetType(nodes[v], &type);
+    if (e != hipSuccess) return e;
+    if (type == hipGraphNodeTypeKernel) {
+      hipKernelNodeParams kp;
+      e = hipGraphKernelNodeGetParams(nodes[v], &kp);
+      if (e == hipSuccess) e = hipGraphAddKernelNode(&copy[v], dst, d.data(), d.size(), &kp);
+    } else if (type == hipGraphNodeTypeMemcpy) {
+      hipMemcpy3DParms mp;
+      e = hipGraphMemcpyNodeGetParams(nodes[v], &mp);
+      if (e == hipSuccess) e = hipGraphAddMemcpyNode(&copy[v], dst, d.data(), d.size(), &mp);
+    } else if (type == hipGraphNodeTypeEmpty) {
+      e = hipGraphAddEmptyNode(&copy[v], dst, d.data(), d.size());
+    } else {
+      return hipErrorNotSupported;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// One step of every member as one graph: each member's step is captured on its own stream
+// (the member's stream is the origin of that capture) and its nodes are copied into the
+// group graph with their edges, so that the members form independent branches of one flat
+// graph; no capture is nested inside another. The members' forces stay on their own
+// stream: with each member's SPME work as a further branch, the 16-window group stepped
+// 1.83 ms instead of 1.21 ms (copies of the nodes, not child-graph nodes: those ran the
+// members one after another, 3.06 ms).
 static int group_capture(qhp_group* g) {
   const int n = (int)g->m.size();
-  hipStream_t s0 = g->m[0]->stream;
   hipGraph_t graph = nullptr;
-  hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
-  int r = QHP_OK;
-  std::string why;
-  e = hipEventRecord(g->ev[0], s0);
-  for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(g->m[i]->stream, g->ev[0], 0);
-  for (int i = 0; i < n && e == hipSuccess && r == QHP_OK; ++i) {
-    g->m[i]->serial_forces = true;
-    r = one_step(g->m[i], false);
-    g->m[i]->serial_forces = false;
-    if (r) why = "member " + std::to_string(i) + ": " + g->m[i]->err;
-  }
-  for (int i = 1; i < n && e == hipSuccess && r == QHP_OK; ++i) {
-    e = hipEventRecord(g->ev[i], g->m[i]->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s0, g->ev[i], 0);
-  }
-  hipError_t e2 = hipStreamEndCapture(s0, &graph);
-  if (r || e != hipSuccess || e2 != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    if (r) return group_fail(g, r, why);
-    return group_fail(g, QHP_EDEVICE, std::string("group capture: ") +
-                                          hipGetErrorString(e != hipSuccess ? e : e2));
+  hipError_t e = hipGraphCreate(&graph, 0);
+  if (e != hipSuccess) return group_fail(g, QHP_EDEVICE, std::string("graph create: ") + hipGetErrorString(e));
+  for (int i = 0; i < n; ++i) {
+    qhp_ctx* c = g->m[i];
+    hipGraph_t gi = nullptr;
+    e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    int r = QHP_OK;
+    if (e == hipSuccess) {
+      c->serial_forces = true;
+      r = one_step(c, false);
+      c->serial_forces = false;
+      e = hipStreamEndCapture(c->stream, &gi);
+    }
+    if (!r && e == hipSuccess) e = graph_append(graph, gi);
+    if (gi) (void)hipGraphDestroy(gi);
+    if (r || e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      if (r) return group_fail(g, r, "member " + std::to_string(i) + ": " + c->err);
+      return group_fail(g, QHP_EDEVICE, "member " + std::to_string(i) + " capture: " + hipGetErrorString(e));
+    }
   }
   e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);

@@ -92,9 +92,9 @@ struct qhp_ctx {
   // on `stream`, forked from and joined back to `stream` by the two events
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  bool serial_forces = false; // set while a group captures the member's step: no side branch
   hipGraphExec_t step_exec = nullptr;   // one captured (outer) MD step (no energies)
   bool use_graph = true;
+  bool serial_forces = false; // set while a group captures the member's step: no side branch
   std::string err;
   bool have_state = false;
   int64_t step = 0;
