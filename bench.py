@@ -185,7 +185,7 @@ def force_loss_timing(q, qa, n_configs=8):
 def windows_timing(q, steps=20, warmup=3):
     """The batched free-energy workload: 16 alchemical windows lambda = i/15 of the 12-atom
     solute in 256-2,048 waters with P = 8/16/32 (780-6,156 atoms each), FP32 pairs, each
-    window's SPME spreading block picked by qhp_autotune, stepped as one group (one captured
+    window's launch shapes picked by qhp_autotune, stepped as one group (one captured
     graph per step of all windows, one branch per window). Also: the same windows stepped
     one after another (each its own graph per step), and the cost of one sample of the BAR
     inputs (every window's bead energies at its two neighbours' couplings)."""
@@ -226,7 +226,9 @@ def windows_timing(q, steps=20, warmup=3):
             c.close()
     return {"windows": 16, "atoms": [s.n_atoms for s in systems],
             "beads": [s.n_beads for s in systems], "bead_atoms_total": bead_atoms,
-            "spme_autotuned": tiles,
+            "autotuned": tiles,
+            "autotuned_fields": ["spread_beads", "spread_z_tiles", "yz_plane_slots",
+                                 "pair_atoms_per_block"],
             "group_ms_per_step": t_group / steps * 1e3,
             "group_bead_atom_steps_per_s": bead_atoms * steps / t_group,
             "sequential_ms_per_step": t_seq / steps * 1e3,
@@ -271,7 +273,8 @@ def adqtb_timing(q, stream):
             "atom_steps_per_s": s.n_atoms / (ms * 1e-3),
             "ms_per_step_inside_a_segment": ms_in,
             "segment_end_ms": (ms - ms_in) * nseg,
-            "spme_autotuned": list(shapes)}
+            "autotuned": dict(zip(("spread_beads", "spread_z_tiles", "yz_plane_slots",
+                                   "pair_atoms_per_block"), shapes))}
 
 
 def cpu_baseline(s, budget_s=20.0):
@@ -425,9 +428,10 @@ def main():
                                "rc 9 A, SPME 64^3 order 5, P=32, 300 K, dt 0.5 fs, "
                                "bead-batched FP32-pair path",
                    "n_atoms": s.n_atoms, "n_beads": s.n_beads, "parallelism": "single GPU",
-                   "spme_autotuned": {"spread_beads": spread_block[0],
-                                      "spread_z_tiles": spread_block[1],
-                                      "yz_plane_slots": spread_block[2]}},
+                   "autotuned": {"spread_beads": spread_block[0],
+                                 "spread_z_tiles": spread_block[1],
+                                 "yz_plane_slots": spread_block[2],
+                                 "pair_atoms_per_block": spread_block[3]}},
         "roofline": roof,
         "breakdown_ms_per_step": per_class,
     }

@@ -99,8 +99,8 @@ def load():
     lib.qhp_eval_lambda.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, I]
     lib.qhp_bar.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_double, D, C.POINTER(C.c_int32)]
     lib.qhp_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                 C.POINTER(C.c_int32)]
-    lib.qhp_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.qhp_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     lib.qhp_group_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
     lib.qhp_group_step.argtypes = [vp, C.c_int32]
     lib.qhp_group_destroy.argtypes = [vp]
@@ -257,18 +257,18 @@ class Context:
         return E, F
 
     def autotune(self, reps=5):
-        """Pick the fastest SPME launch shapes for this context (qhp_autotune) -> (beads
-        per spreading block, 8^3 tiles along z per spreading block, complex slots per y-z
-        plane block or -1 for one-axis passes)."""
-        gb, z, nb = C.c_int32(), C.c_int32(), C.c_int32()
+        """Pick the fastest launch shapes for this context (qhp_autotune) -> (beads per
+        spreading block, 8^3 tiles along z per spreading block, complex slots per y-z plane
+        block or -1 for one-axis passes, FP32 pair kernel atoms per block or 0)."""
+        gb, z, nb, w = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         self._check(self._lib.qhp_autotune(self._h, int(reps), C.byref(gb), C.byref(z),
-                                           C.byref(nb)))
-        return gb.value, z.value, nb.value
+                                           C.byref(nb), C.byref(w)))
+        return gb.value, z.value, nb.value, w.value
 
-    def set_launch(self, spread_beads=0, spread_ztiles=0, fft_slots=0):
+    def set_launch(self, spread_beads=0, spread_ztiles=0, fft_slots=0, pair_atoms=0):
         """Launch shapes by hand (qhp_set_launch); 0 = default."""
         self._check(self._lib.qhp_set_launch(self._h, int(spread_beads), int(spread_ztiles),
-                                             int(fft_slots)))
+                                             int(fft_slots), int(pair_atoms)))
 
     def param_grad(self, pos):
         """d(sum of bead energies) / d(charges [N], lj_epsilon [T], lj_sigma [T])."""

@@ -866,7 +866,7 @@ extern "C" int qhp_bar(const double* du_a, int64_t n_a, const double* du_b, int6
 }
 
 extern "C" int qhp_set_launch(qhp_ctx* c, int32_t spread_beads, int32_t spread_ztiles,
-                              int32_t fft_slots) {
+                              int32_t fft_slots, int32_t pair_atoms) {
   if (!c) return QHP_EINVAL;
   auto p2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
   if (!(spread_beads == 0 || (p2(spread_beads) && spread_beads <= 16)))
@@ -875,6 +875,9 @@ extern "C" int qhp_set_launch(qhp_ctx* c, int32_t spread_beads, int32_t spread_z
     return qhp_fail(c, QHP_EINVAL, "spread_ztiles must be 0 or a power of two <= 8");
   if (!(fft_slots == 0 || fft_slots == -1 || (p2(fft_slots) && fft_slots <= 8)))
     return qhp_fail(c, QHP_EINVAL, "fft_slots must be -1, 0 or a power of two <= 8");
+  if (!(pair_atoms == 0 || pair_atoms == 2 || pair_atoms == 4 || pair_atoms == 8))
+    return qhp_fail(c, QHP_EINVAL, "pair_atoms must be 0, 2, 4 or 8");
+  c->pair_wpb = pair_atoms;
   c->spread_gb = spread_beads;
   c->spread_z = spread_ztiles;
   c->fft_nb = fft_slots;
@@ -885,7 +888,7 @@ extern "C" int qhp_set_launch(qhp_ctx* c, int32_t spread_beads, int32_t spread_z
 }
 
 extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
-                            int32_t* spread_ztiles, int32_t* fft_slots) {
+                            int32_t* spread_ztiles, int32_t* fft_slots, int32_t* pair_atoms) {
   if (!c) return QHP_EINVAL;
   if (reps < 1) return qhp_fail(c, QHP_EINVAL, "reps must be >= 1");
   if (!c->have_state) return qhp_fail(c, QHP_EINVAL, "no state set");
@@ -893,6 +896,7 @@ extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
     if (spread_beads) *spread_beads = 1;
     if (spread_ztiles) *spread_ztiles = 1;
     if (fft_slots) *fft_slots = 0;
+    if (pair_atoms) *pair_atoms = 0;
     return QHP_OK;
   }
   // the reciprocal-space pass of the propagated beads (the contracted ones under RESPA),
@@ -942,6 +946,25 @@ extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
     if (e == hipSuccess && (best_nb == 0 || ms < best_ms)) { best_nb = nb; best_ms = ms; }
   }
   c->fft_nb = best_nb;
+  // then the FP32 pair kernel of the same beads: 2, 4 or 8 atoms (wavefronts) per block
+  // (FP64 pairs have one shape)
+  int best_w = 0;
+  const double Lmin = std::min(c->p.box[0], std::min(c->p.box[1], c->p.box[2]));
+  if (c->p.precision == QHP_FP32_PAIRS && 2.0 * (c->p.cutoff + c->p.skin) < Lmin) {
+    best_ms = 0.f;
+    for (int w = 2; w <= 8 && e == hipSuccess; w *= 2) {
+      c->pair_wpb = w;
+      e = launch_pair(c, false, -1, &B);
+      if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_pair(c, false, -1, &B);
+      if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e == hipSuccess && (best_w == 0 || ms < best_ms)) { best_w = w; best_ms = ms; }
+    }
+    c->pair_wpb = best_w;
+  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   QHP_HIP(c, e);
@@ -951,6 +974,7 @@ extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
   if (spread_beads) *spread_beads = best_gb;
   if (spread_ztiles) *spread_ztiles = best_z;
   if (fft_slots) *fft_slots = best_nb;
+  if (pair_atoms) *pair_atoms = best_w;
   return QHP_OK;
 }
 

@@ -341,19 +341,20 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
   for (int t = tt + s; t < cnt; t += S) interact(scd[t], load(t), slj[t], SOFT ? sa[t] : 0.f);
 }
 
-template <int P, bool ENERGY, bool SOFT = false>
-__global__ __launch_bounds__(NT) void k_pair32(PairArgs A) {
+// W atoms (wavefronts) per block: the launch shape the autotuner picks
+template <int P, bool ENERGY, bool SOFT = false, int W = WPB>
+__global__ __launch_bounds__(64 * W) void k_pair32(PairArgs A) {
   constexpr int S = 64 / P;
-  __shared__ float4 scd[WPB][64];   // centroid difference (x, y, z) and q_i q_j C
-  __shared__ float2 slj[WPB][64];   // 4 eps_ij and sigma_ij^6 of the pair
-  __shared__ float ssa[SOFT ? WPB : 1][SOFT ? 64 : 1];   // soft-core alpha (1 - lambda)
-  __shared__ unsigned sj[WPB][64];  // byte offset of atom j's bead-0 FP32 offset
+  __shared__ float4 scd[W][64];     // centroid difference (x, y, z) and q_i q_j C
+  __shared__ float2 slj[W][64];     // 4 eps_ij and sigma_ij^6 of the pair
+  __shared__ float ssa[SOFT ? W : 1][SOFT ? 64 : 1];   // soft-core alpha (1 - lambda)
+  __shared__ unsigned sj[W][64];    // byte offset of atom j's bead-0 FP32 offset
   __shared__ float4 stab[(ENERGY ? 2 : 1) * QHP_PAIR_TAB];   // kernel tables
-  for (int k = threadIdx.x; k < (ENERGY ? 2 : 1) * QHP_PAIR_TAB; k += NT) stab[k] = A.tab[k];
+  for (int k = threadIdx.x; k < (ENERGY ? 2 : 1) * QHP_PAIR_TAB; k += 64 * W) stab[k] = A.tab[k];
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, s = lane / P, b = lane % P;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int i = lb * WPB + wv;
+  const int i = lb * W + wv;
   if (lb >= A.nblocks || i >= A.N) return;       // whole wavefront leaves together
   const float4 oi = A.xf[(size_t)i * P + b];
   const double4 ci = A.cwrap[i];
@@ -514,6 +515,10 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   const int P = plain ? 1 : B.P;
   A.nblocks = (N + WPB - 1) / WPB;
   const unsigned nb = (unsigned)((A.nblocks + 7) / 8 * 8);
+  // FP32 force launches: c->pair_wpb atoms per block (2, 4 or 8)
+  const int w = c->pair_wpb == 2 || c->pair_wpb == 8 ? c->pair_wpb : WPB;
+  const int nlw = (N + w - 1) / w;
+  const unsigned nbw = (unsigned)((nlw + 7) / 8 * 8);
   const double Lmin = fmin(c->p.box[0], fmin(c->p.box[1], c->p.box[2]));
   const bool minimg = !(2.0 * (c->p.cutoff + c->p.skin) < Lmin);
   const bool pg = bs && bs->pgrad;     // parameter gradients: always the FP64 kernel
@@ -523,12 +528,20 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   if (hvp) { A.u = bs->hvp_u; A.hu = bs->g; A.mix = bs->pgrad; }
   hipEvent_t ev = nullptr;
   prof_begin(c, QHP_PROF_PAIR, &ev);
-  if (f32 && soft) {
-    QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair32<PP, true, true>), nb, NT, 0, c->stream, A);
+  if (f32 && soft && !energy) {
+    A.nblocks = nlw;
+    QHP_SWITCH_P(P, if (w == 2) hipLaunchKernelGGL((k_pair32<PP, false, true, 2>), nbw, 128, 0, c->stream, A);
+                 else if (w == 8) hipLaunchKernelGGL((k_pair32<PP, false, true, 8>), nbw, 512, 0, c->stream, A);
                  else hipLaunchKernelGGL((k_pair32<PP, false, true>), nb, NT, 0, c->stream, A));
-  } else if (f32) {
-    QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair32<PP, true>), nb, NT, 0, c->stream, A);
+  } else if (f32 && soft) {
+    QHP_SWITCH_P(P, hipLaunchKernelGGL((k_pair32<PP, true, true>), nb, NT, 0, c->stream, A));
+  } else if (f32 && !energy) {
+    A.nblocks = nlw;
+    QHP_SWITCH_P(P, if (w == 2) hipLaunchKernelGGL((k_pair32<PP, false, false, 2>), nbw, 128, 0, c->stream, A);
+                 else if (w == 8) hipLaunchKernelGGL((k_pair32<PP, false, false, 8>), nbw, 512, 0, c->stream, A);
                  else hipLaunchKernelGGL((k_pair32<PP, false>), nb, NT, 0, c->stream, A));
+  } else if (f32) {
+    QHP_SWITCH_P(P, hipLaunchKernelGGL((k_pair32<PP, true>), nb, NT, 0, c->stream, A));
   } else if (soft) {
     if (pg || hvp) return hipErrorInvalidValue;     // rejected by the entry points
     QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair64<PP, true, false, false, true>), nb, NT, 0, c->stream, A);

@@ -199,11 +199,12 @@ def test_autotune_keeps_results_and_the_state(medium):
         c.set_state(medium.pos, medium.vel, 0)
         E0, F0 = c.eval(medium.pos)
         x0, v0, _ = c.get_state()
-        gb, zt, nb = c.autotune(3)
+        gb, zt, nb, w = c.autotune(3)
         x1, v1, _ = c.get_state()
         E1, F1 = c.eval(medium.pos)
         c.step(2)
-    say("autotuned spread block", gb, zt, "fft slots", nb)
+    say("autotuned spread block", gb, zt, "fft slots", nb, "pair atoms", w)
+    assert w in (0, 2, 4, 8)
     assert nb in (-1, 1, 2)                            # 4 beads: two complex slots
     assert gb in (1, 2, 4) and gb <= medium.n_beads
     assert zt in (1, 2, 4) and gb * zt <= 16          # 32^3 grid: four 8^3 tiles along z

@@ -1,11 +1,12 @@
 """Every launch shape the autotuner can pick (SPME spreading block, y-z plane kernel
-slots or one-axis passes) gives the oracle's forces and energies, set by qhp_set_launch."""
+slots or one-axis passes, FP32 pair kernel atoms per block) gives the oracle's forces and
+energies, set by qhp_set_launch."""
 import sys
 
 import numpy as np
 import pytest
 
-from helpers import has_gpu, medium_box, rel_max
+from helpers import has_gpu, medium_box, rel_max, rel_rms
 from oracle import forces
 
 pytestmark = [pytest.mark.gpu,
@@ -63,6 +64,33 @@ def test_plane_kernel_slots_and_one_axis_passes(case):
             _check(c, s, E_r, F_r, (name, nb))
 
 
+def test_pair_kernel_atoms_per_block(case):
+    # the FP32 pair kernel of the propagation step (no energies) with 2, 4 or 8 atoms per
+    # block: each atom's sums do not depend on the block, so three steps from the same
+    # state agree up to the order of additions that is not fixed in any case (the order of
+    # a cell's atoms, hence of a list row, and the SPME spreading's LDS sums): FP32 force
+    # differences of ~1e-7 relative move positions by ~1e-8 A and velocities by ~1e-5 A/ps
+    import paper_2212_03137_amd as q
+    name, s, E_r, F_r = case
+    with q.Context.from_system(s, precision=q.FP32_PAIRS) as c:
+        out = {}
+        for w in (2, 4, 8):
+            say(name, "pair atoms per block", w)
+            c.set_launch(0, 0, 0, w)
+            c.set_state(s.pos, s.vel, 0)
+            c.step(3)
+            out[w] = c.get_state()
+        x4, v4, _ = out[4]
+        for w in (2, 8):
+            x, v, st = out[w]
+            assert st == 3
+            assert rel_max(x, x4) <= 1e-8, (name, w)
+            assert rel_max(v, v4) <= 1e-5, (name, w)
+        c.set_launch(0, 0, 0, 8)
+        E, F = c.eval(s.pos)
+    assert rel_rms(F, F_r) <= 1e-5
+
+
 def test_plain_path_on_a_64_point_grid():
     # one bead per launch: the 64^2 plane kernel with one slot
     import paper_2212_03137_amd as q
@@ -76,7 +104,8 @@ def test_set_launch_rejects_bad_shapes():
     import paper_2212_03137_amd as q
     s = medium_box(P=4, K=32)
     with q.Context.from_system(s) as c:
-        for bad in ((3, 0, 0), (0, 16, 0), (0, 0, 3), (32, 0, 0), (0, 0, -2)):
+        for bad in ((3, 0, 0, 0), (0, 16, 0, 0), (0, 0, 3, 0), (32, 0, 0, 0), (0, 0, -2, 0),
+                    (0, 0, 0, 3), (0, 0, 0, 16), (0, 0, 0, -1)):
             with pytest.raises(q.QhpError) as e:
                 c.set_launch(*bad)
             assert e.value.code == q.EINVAL
