@@ -33,6 +33,9 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int WPB = NT / 64;      // atoms (wavefronts) per block
+#ifndef QHP_PAIR_PF
+#define QHP_PAIR_PF 1
+#endif
 
 // p = 0.418649012, max relative error of exp(x^2) erfc(x) on [0, 6]: 2.94e-08
 constexpr float ERFC_P = 0.418649012f;
@@ -341,6 +344,86 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
   for (int t = tt + s; t < cnt; t += S) interact(scd[t], load(t), slj[t], SOFT ? sa[t] : 0.f);
 }
 
+// One bead (P = 1): a lane's list entry is its only interaction in a chunk of 64, so the
+// decoded entry is evaluated in place (no staging, no compaction). The centroid records of
+// the next PF chunks are kept in flight and the list entries one chunk further (PF = 1, 2
+// and 3 measured the same on the 21,952-water box).
+template <bool SOFT, int W, int PF>
+__global__ __launch_bounds__(64 * W) void k_pair32_one(PairArgs A) {
+  __shared__ float4 stab[QHP_PAIR_TAB];
+  for (int k = threadIdx.x; k < QHP_PAIR_TAB; k += 64 * W) stab[k] = A.tab[k];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int i = lb * W + wv;
+  if (lb >= A.nblocks || i >= A.N) return;       // whole wavefront leaves together
+  const double4 ci = A.cwrap[i];
+  const double qi = A.coulomb * A.charge[i];
+  const int ti = A.type[i];
+  const float alpha = (float)A.alpha;
+  const float kexp = (float)(-A.alpha * A.alpha * 1.4426950408889634);  // -alpha^2 log2(e)
+  const float c2a = (float)(2.0 * A.alpha / sqrt(M_PI));
+  const float rc2 = (float)A.rc2;
+  const float reach2 = (float)((sqrt(A.rc2) + 1e-3) * (sqrt(A.rc2) + 1e-3));
+  const int nn = A.nnbr[i];
+  const int* row = A.nbr + (size_t)i * A.cap;
+  const Pair32K K{make_float4(0.f, 0.f, 0.f, 0.f), rc2, A.tab_scale, alpha, kexp, c2a,
+                  A.tab_kmin, stab};
+  // ring of prefetched chunks: centroid records of chunks k .. k + PF - 1, the list entry
+  // of chunk k + PF
+  unsigned e[PF + 1];
+  double4 cj[PF];
+  double qj[PF];
+  int tj[PF];
+#pragma unroll
+  for (int p = 0; p <= PF; ++p) e[p] = p * 64 + lane < nn ? (unsigned)row[p * 64 + lane] : 0u;
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    cj[p] = make_double4(0.0, 0.0, 0.0, 0.0); qj[p] = 0.0; tj[p] = 0;
+    if (p * 64 + lane < nn) {
+      const int j = e[p] & 0x3FFFFFF;
+      cj[p] = A.cwrap[j]; qj[p] = A.charge[j]; tj[p] = A.type[j];
+    }
+  }
+  double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
+  for (int k0 = 0; k0 < nn; k0 += 64) {
+    const unsigned ec0 = e[0];
+    const double4 c = cj[0];
+    const double qq = qj[0];
+    const int tt = tj[0];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) e[p] = e[p + 1];
+#pragma unroll
+    for (int p = 0; p + 1 < PF; ++p) { cj[p] = cj[p + 1]; qj[p] = qj[p + 1]; tj[p] = tj[p + 1]; }
+    // chunk k + PF from the entry loaded one chunk ago; the entry of chunk k + PF + 1
+    {
+      const int t = k0 + PF * 64 + lane;
+      cj[PF - 1] = make_double4(0.0, 0.0, 0.0, 0.0); qj[PF - 1] = 0.0; tj[PF - 1] = 0;
+      if (t < nn) {
+        const int j = e[PF - 1] & 0x3FFFFFF;
+        cj[PF - 1] = A.cwrap[j]; qj[PF - 1] = A.charge[j]; tj[PF - 1] = A.type[j];
+      }
+      e[PF] = t + 64 < nn ? (unsigned)row[t + 64] : 0u;
+    }
+    if (k0 + lane < nn) {
+      const float cx = (float)((c.x - ci.x) + A.L[0] * (double)((int)((ec0 >> 26) & 3) - 1));
+      const float cy = (float)((c.y - ci.y) + A.L[1] * (double)((int)((ec0 >> 28) & 3) - 1));
+      const float cz = (float)((c.z - ci.z) + A.L[2] * (double)((int)((ec0 >> 30) & 3) - 1));
+      if (cx * cx + cy * cy + cz * cz < reach2) {
+        const int tp = ti * A.ntypes + tt;
+        const float2 ljv = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
+        const float av = SOFT ? (float)A.lj_a[tp] : 0.f;
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        interact32<false, true, SOFT>(K, make_float4(cx, cy, cz, (float)(qi * qq)),
+                                      make_float4(0.f, 0.f, 0.f, 0.f), ljv, av, fx, fy, fz,
+                                      ec, elj);
+        gx += (double)fx; gy += (double)fy; gz += (double)fz;
+      }
+    }
+  }
+  flush<1, false>(A, i, lane, gx, gy, gz, ec, elj);
+}
+
 // W atoms (wavefronts) per block: the launch shape the autotuner picks
 template <int P, bool ENERGY, bool SOFT = false, int W = WPB>
 __global__ __launch_bounds__(64 * W) void k_pair32(PairArgs A) {
@@ -535,6 +618,11 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
                  else hipLaunchKernelGGL((k_pair32<PP, false, true>), nb, NT, 0, c->stream, A));
   } else if (f32 && soft) {
     QHP_SWITCH_P(P, hipLaunchKernelGGL((k_pair32<PP, true, true>), nb, NT, 0, c->stream, A));
+  } else if (f32 && !energy && P == 1) {
+    A.nblocks = nlw;
+    if (w == 2) hipLaunchKernelGGL((k_pair32_one<false, 2, QHP_PAIR_PF>), nbw, 128, 0, c->stream, A);
+    else if (w == 8) hipLaunchKernelGGL((k_pair32_one<false, 8, QHP_PAIR_PF>), nbw, 512, 0, c->stream, A);
+    else hipLaunchKernelGGL((k_pair32_one<false, 4, QHP_PAIR_PF>), nb, NT, 0, c->stream, A);
   } else if (f32 && !energy) {
     A.nblocks = nlw;
     QHP_SWITCH_P(P, if (w == 2) hipLaunchKernelGGL((k_pair32<PP, false, false, 2>), nbw, 128, 0, c->stream, A);

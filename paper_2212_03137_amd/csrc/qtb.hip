@@ -331,6 +331,9 @@ __global__ __launch_bounds__(NTH) void k_qtb_spectra(SpecArgs A) {
   double* avf = avv + nk;
   load_twiddles<L2>(hi, lo, A.tw2);
   for (int k = tid; k < (A.ratio ? 3 : 1) * nk; k += NTH) acc[k] = 0.0;
+  // the accumulators are cleared and read back by different threads (a block whose atoms
+  // all belong to another launch's types runs no barrier in the loop below)
+  __syncthreads();
   const double sc = A.dt / NS;
   const int atoms_per_block = (A.N + gridDim.x - 1) / gridDim.x;
   const int a0 = blockIdx.x * atoms_per_block, a1 = min(A.N, a0 + atoms_per_block);
@@ -368,6 +371,7 @@ __global__ __launch_bounds__(NTH) void k_qtb_spectra(SpecArgs A) {
       __syncthreads();
     }
   }
+  __syncthreads();
   const size_t o = (size_t)A.z0 * (NS + 1);
   for (int k = tid; k < nk; k += NTH) {
     if (acc[k] != 0.0) atomicAdd(A.dsum + o + k, acc[k]);
