@@ -26,6 +26,7 @@ struct NmArgs {
   const double* T; const double* cc; const double* csw; const double* cws;
   const double* c1; const double* c2;
   const double* mass; const double* sqrt_mkT; const double* charge;
+  const int* type; int pack_qt;   // one-bead centroid records: charge and type in w
   double4* cent; const double4* cref; const double4* coff; double4* cwrap; float4* xf;
   NlCtrl* ctrl;
   double4* bmax;
@@ -235,7 +236,8 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
     A.cent[a] = make_double4(cen[0], cen[1], cen[2], adb);
     qhp::write_bins(A.bins, a, cen[0], cen[1], cen[2]);
     const double4 o = A.coff[a];
-    A.cwrap[a] = make_double4(cen[0] - o.x, cen[1] - o.y, cen[2] - o.z, adb);
+    A.cwrap[a] = make_double4(cen[0] - o.x, cen[1] - o.y, cen[2] - o.z,
+                              A.pack_qt ? qhp::pack_charge_type(A.charge[a], A.type[a]) : adb);
     const double4 r = A.cref[a];
     const double ex = cen[0] - r.x, ey = cen[1] - r.y, ez = cen[2] - r.z;
     dc2 = ex * ex + ey * ey + ez * ez;
@@ -610,6 +612,7 @@ hipError_t launch_nm_step(qhp_ctx* c, int inner, double slow_h, bool emit) {
   A.N = c->N; A.Q = c->Q; A.Pa = c->Pa; A.x = c->x; A.g = c->g; A.T = c->T;
   A.cc = c->mode_c; A.csw = c->mode_s_w; A.cws = c->mode_ws; A.c1 = c->mode_c1; A.c2 = c->mode_c2;
   A.mass = c->d_mass; A.sqrt_mkT = c->d_sqrt_mkT; A.charge = c->d_charge;
+  A.type = c->d_type; A.pack_qt = c->pack_qt ? 1 : 0;
   A.cent = c->cent; A.cref = c->cref; A.coff = c->coff; A.cwrap = c->cwrap; A.xf = c->xf; A.ctrl = c->ctrl; A.bmax = c->bmax;
   for (int d = 0; d < 3; ++d) { A.K[d] = c->K[d]; A.KoL[d] = c->K[d] / c->p.box[d]; }
   A.order = c->p.pme_order;

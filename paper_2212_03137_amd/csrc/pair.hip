@@ -65,6 +65,7 @@ struct PairArgs {
   float tab_scale;        // intervals per A^2 of r^2 (fl(r2 tab_scale) < QHP_PAIR_TAB in range)
   int tab_kmin;           // first interval the tables are used for (closer: the formula)
   int nblocks;            // logical blocks
+  int pack_qt;            // centroid records carry charge and type (one-bead contexts)
   const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
   double* energy;         // [P][NTERMS] (plain: the bead's row)
 };
@@ -382,15 +383,16 @@ __global__ __launch_bounds__(64 * W) void k_pair32_one(PairArgs A) {
     cj[p] = make_double4(0.0, 0.0, 0.0, 0.0); qj[p] = 0.0; tj[p] = 0;
     if (p * 64 + lane < nn) {
       const int j = e[p] & 0x3FFFFFF;
-      cj[p] = A.cwrap[j]; qj[p] = A.charge[j]; tj[p] = A.type[j];
+      cj[p] = A.cwrap[j];
+      if (!A.pack_qt) { qj[p] = A.charge[j]; tj[p] = A.type[j]; }
     }
   }
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
   for (int k0 = 0; k0 < nn; k0 += 64) {
     const unsigned ec0 = e[0];
     const double4 c = cj[0];
-    const double qq = qj[0];
-    const int tt = tj[0];
+    const double qq = A.pack_qt ? (double)qhp::packed_charge(c.w) : qj[0];
+    const int tt = A.pack_qt ? qhp::packed_type(c.w) : tj[0];
 #pragma unroll
     for (int p = 0; p < PF; ++p) e[p] = e[p + 1];
 #pragma unroll
@@ -401,7 +403,8 @@ __global__ __launch_bounds__(64 * W) void k_pair32_one(PairArgs A) {
       cj[PF - 1] = make_double4(0.0, 0.0, 0.0, 0.0); qj[PF - 1] = 0.0; tj[PF - 1] = 0;
       if (t < nn) {
         const int j = e[PF - 1] & 0x3FFFFFF;
-        cj[PF - 1] = A.cwrap[j]; qj[PF - 1] = A.charge[j]; tj[PF - 1] = A.type[j];
+        cj[PF - 1] = A.cwrap[j];
+        if (!A.pack_qt) { qj[PF - 1] = A.charge[j]; tj[PF - 1] = A.type[j]; }
       }
       e[PF] = t + 64 < nn ? (unsigned)row[t + 64] : 0u;
     }
@@ -451,7 +454,7 @@ __global__ __launch_bounds__(64 * W) void k_pair32(PairArgs A) {
   // no bead of a pair whose centroids are further apart than rc + d_i + d_j can be within
   // the cutoff, d = an atom's largest bead-centroid distance this step (kept in the w of
   // its centroid record); small margin for the FP32 rounding of the difference
-  const double reach_i = sqrt(A.rc2) + ci.w + 1e-3;
+  const double reach_i = sqrt(A.rc2) + (P == 1 ? 0.0 : ci.w) + 1e-3;   // one bead: w is no spread
   const int nn = A.nnbr[i];
   const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
@@ -498,7 +501,7 @@ __global__ __launch_bounds__(64 * W) void k_pair32(PairArgs A) {
       const float cx = (float)((cj.x - ci.x) + A.L[0] * (double)((int)((e >> 26) & 3) - 1));
       const float cy = (float)((cj.y - ci.y) + A.L[1] * (double)((int)((e >> 28) & 3) - 1));
       const float cz = (float)((cj.z - ci.z) + A.L[2] * (double)((int)((e >> 30) & 3) - 1));
-      const float reach = (float)(reach_i + cj.w);
+      const float reach = (float)(reach_i + (P == 1 ? 0.0 : cj.w));
       keep = cx * cx + cy * cy + cz * cz < reach * reach;
       cdv = make_float4(cx, cy, cz, (float)(qi * qj_p));
       const int tp = ti * A.ntypes + tj_p;
@@ -595,6 +598,7 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
 
   A.energy = plain ? c->energy + (size_t)bead * QHP_NTERMS : B.energy;
   A.ctrl = c->ctrl;
+  A.pack_qt = c->pack_qt ? 1 : 0;
   const int P = plain ? 1 : B.P;
   A.nblocks = (N + WPB - 1) / WPB;
   const unsigned nb = (unsigned)((A.nblocks + 7) / 8 * 8);

@@ -184,6 +184,7 @@ struct qhp_ctx {
 
   // multiple time stepping and ring-polymer contraction
   bool respa = false;         // rpc_beads < P or respa_nalt > 1
+  bool pack_qt = false;       // centroid records carry charge and type (one-bead pairs)
   int Ps = 0, nalt = 1;       // contracted bead lanes (a power of two), inner steps per outer step
   int Psb = 0;                // contracted beads (<= Ps; the rest are phantoms)
   double* xs = nullptr;       // [3][N][Ps] contracted beads
@@ -420,6 +421,13 @@ QHP_DEV double grid_coord(double x, double KoL, int K) {
   const double u = x * KoL;
   return u - (double)K * floor(u * ldexp(1.0, -__builtin_ctz((unsigned)K)));
 }
+// Contexts whose pair kernel runs on one bead lane (P = 1, no contraction): the w of a
+// centroid record, otherwise the atom's largest bead-centroid distance (always zero with
+// one bead), carries the atom's charge as FP32 and its type, so that the pair kernel reads
+// one 32-byte record per neighbour. Only moved, never computed with.
+QHP_DEV double pack_charge_type(double q, int t) { return __hiloint2double(t, __float_as_int((float)q)); }
+QHP_DEV float packed_charge(double w) { return __int_as_float(__double2loint(w)); }
+QHP_DEV int packed_type(double w) { return __double2hiint(w); }
 QHP_DEV int base_of(double x, double KoL, int K) {
   const double fl = floor(grid_coord(x, KoL, K));
   return isfinite(fl) ? min(max((int)fl, 0), K) : 0;
