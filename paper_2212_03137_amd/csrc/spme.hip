@@ -186,6 +186,83 @@ __global__ __launch_bounds__(NT) void k_gather(SpmeArgs A) {
   }
 }
 
+// One bead (P = 1): a group of 8 lanes per atom, lane t0 < ORDER taking the x plane t0 of
+// the stencil (ORDER^2 loads instead of ORDER^3 per lane), the group summed by shuffles:
+// eight times the wavefronts of one lane per atom, enough to hide the latency of the
+// scattered grid loads.
+template <int ORDER, bool ENERGY, bool PG = false>
+__global__ __launch_bounds__(NT) void k_gather_one(SpmeArgs A) {
+  static_assert(ORDER <= 8, "one x plane per lane of a group of eight");
+  __shared__ double sred[NT / 64];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int tid = lb * NT + threadIdx.x;
+  const int k = tid >> 3, t0 = tid & 7;
+  const int a = (lb < A.nblocks && k < A.N) ? A.order[k] : A.N;
+  double f0 = 0, f1 = 0, f2 = 0, e = 0;
+  if (a < A.N && t0 < ORDER) {
+    double xb[3];
+    for (int d = 0; d < 3; ++d) xb[d] = A.x[d * A.N + a];
+    const int K[3] = {A.K0, A.K1, A.K2};
+    int i0[3];
+    double w[3][ORDER], dw[3][ORDER];
+    stencil<ORDER>(xb, A.L, K, i0, w, dw);
+    int o2[ORDER];
+#pragma unroll
+    for (int t2 = 0; t2 < ORDER; ++t2) o2[t2] = wrapk(i0[2] - t2, A.K2) * A.Pc2;
+    const int k0 = wrapk(i0[0] - t0, A.K0);
+    double ph[ORDER][ORDER];
+#pragma unroll
+    for (int t1 = 0; t1 < ORDER; ++t1) {
+      const double* row = A.grid + (size_t)((k0 * A.K1 + wrapk(i0[1] - t1, A.K1)) * A.K2) * A.Pc2;
+#pragma unroll
+      for (int t2 = 0; t2 < ORDER; ++t2) ph[t1][t2] = row[o2[t2]];
+    }
+    // this lane's plane: the weights of x point t0 (selected without indexing by t0)
+    double wx = 0, dwx = 0;
+#pragma unroll
+    for (int t = 0; t < ORDER; ++t)
+      if (t == t0) { wx = w[0][t]; dwx = dw[0][t]; }
+#pragma unroll
+    for (int t1 = 0; t1 < ORDER; ++t1) {
+      double sm = 0, sd = 0;
+#pragma unroll
+      for (int t2 = 0; t2 < ORDER; ++t2) {
+        sm += w[2][t2] * ph[t1][t2];
+        sd += dw[2][t2] * ph[t1][t2];
+      }
+      f0 += dwx * w[1][t1] * sm;
+      f1 += wx * dw[1][t1] * sm;
+      f2 += wx * w[1][t1] * sd;
+      if (ENERGY || PG) e += wx * w[1][t1] * sm;
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    f0 += __shfl_xor(f0, o); f1 += __shfl_xor(f1, o); f2 += __shfl_xor(f2, o);
+    if (ENERGY || PG) e += __shfl_xor(e, o);
+  }
+  double eq = 0.0;
+  if (a < A.N && t0 == 0) {
+    const double q = A.charge[a];
+    A.g[0 * A.N + a] += q * f0 * (double)A.K0 / A.L[0];
+    A.g[1 * A.N + a] += q * f1 * (double)A.K1 / A.L[1];
+    A.g[2 * A.N + a] += q * f2 * (double)A.K2 / A.L[2];
+    if (PG) A.dq[a] += e;
+    eq = 0.5 * q * e;
+  }
+  if (ENERGY) {
+#pragma unroll
+    for (int o = 8; o < 64; o <<= 1) eq += __shfl_xor(eq, o);
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = eq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < NT / 64; ++w) sum += sred[w];
+      atomicAdd(A.energy + QHP_E_COUL_RECIP, sum);
+    }
+  }
+}
+
 // Hessian-vector product of the reciprocal energy: with phi the potential grid of x and
 // dphi the potential of the tangent density sum_b q_b grad W_b . u_b,
 //   (H u)_a = q_a [ sum_k (grad grad W_a(k)) u_a phi(k) + sum_k grad W_a(k) dphi(k) ].
@@ -1493,6 +1570,17 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
 gather:
   if (!(part & SPME_GATHER)) return hipGetLastError();
   prof_begin(c, QHP_PROF_GATHER, &ev);
+  if (P == 1) {
+    const unsigned nbo = (unsigned)(((size_t)N * 8 + NT - 1) / NT);
+    A.nblocks = (int)nbo;
+    const unsigned nbo8 = (nbo + 7) / 8 * 8;
+    QHP_SWITCH_ORDER(c->p.pme_order,
+                     if (pg) hipLaunchKernelGGL((k_gather_one<OO, false, true>), nbo8, NT, 0, c->stream, A);
+                     else if (energy) hipLaunchKernelGGL((k_gather_one<OO, true>), nbo8, NT, 0, c->stream, A);
+                     else hipLaunchKernelGGL((k_gather_one<OO, false>), nbo8, NT, 0, c->stream, A));
+    prof_end(c, QHP_PROF_GATHER, ev);
+    return hipGetLastError();
+  }
   A.nblocks = (int)nb;
   const unsigned nb8 = (nb + 7) / 8 * 8;
   QHP_SWITCH_P(P, QHP_SWITCH_ORDER(c->p.pme_order,
