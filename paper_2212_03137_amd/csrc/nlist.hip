@@ -203,7 +203,6 @@ QHP_DEV double wave_fmax(double v) {
 
 // non-negative doubles order like their bit patterns read as unsigned integers
 QHP_DEV unsigned long long max_bits(double v) { return (unsigned long long)__double_as_longlong(v); }
-QHP_DEV int load_agent(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 __global__ __launch_bounds__(PREP_NT) void k_prep_count(PrepArgs B, int force) {
   NlArgs& A = B.nl;
@@ -261,18 +260,32 @@ __global__ __launch_bounds__(PREP_NT) void k_prep_count(PrepArgs B, int force) {
   __syncthreads();
   // ---- 4. offsets (start and the scatter's fill pointer) from the counts, which are
   //         cleared for the next step; cell offsets only on a rebuild ----
+  // (the fence above made the other blocks' counts visible to plain loads: they were
+  // added at device scope, and this block's cache lines were invalidated)
   auto scan = [&](int* cnt, int* start_g, int* fill, int n, bool write) {
     const int pc = (n + PREP_NT - 1) / PREP_NT;
     const int b0 = min(n, tid * pc), b1 = min(n, b0 + pc);
     int s = 0;
-    for (int k = b0; k < b1; ++k) s += load_agent(cnt + k);
+    for (int k0 = b0; k0 < b1; k0 += 8) {           // eight loads in flight at a time
+      int v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = k0 + u < b1 ? cnt[k0 + u] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
     int total;
     int acc = block_exclusive_scan(s, swave, &total);
-    for (int k = b0; k < b1; ++k) {
-      const int v = load_agent(cnt + k);
-      if (write) { start_g[k] = acc; fill[k] = acc; }
-      acc += v;
-      cnt[k] = 0;
+    for (int k0 = b0; k0 < b1; k0 += 8) {
+      int v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = k0 + u < b1 ? cnt[k0 + u] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (k0 + u >= b1) break;
+        if (write) { start_g[k0 + u] = acc; fill[k0 + u] = acc; }
+        acc += v[u];
+        cnt[k0 + u] = 0;
+      }
     }
     if (write && tid == 0) start_g[n] = total;
   };
