@@ -1205,7 +1205,7 @@ __global__ __launch_bounds__((yz_threads<K, NB>())) void k_fft_yz(FftYZArgs A) {
 // of one thread are exactly the eight inputs x[8 n1 + n2], n2 = k1, of the inverse
 // step), and the last inverse z step writes the grid directly.
 template <int NB>
-__global__ __launch_bounds__(512 * NB) void k_fft_yz64(FftYZArgs A) {
+__global__ __launch_bounds__(512 * NB) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_yz64(FftYZArgs A) {
   constexpr int K = 64, ROW = K * NB + 2;   // padded rows: conflict-free for NB = 1 and 2
   __shared__ double2 buf[K * ROW];
   __shared__ double2 stw[K];
@@ -1223,14 +1223,6 @@ __global__ __launch_bounds__(512 * NB) void k_fft_yz64(FftYZArgs A) {
   // z series of this thread: row k1 = r, slot s; y series: column k2 = r, slot s
   double2* zs = buf + sw(r) * ROW + s;      // element e at zs[sw(e) * NB]
   double2* ys = buf + sw(r) * NB + s;       // element e at ys[sw(e) * ROW]
-  auto tw8 = [&](double2* v, int n2, bool inv) {
-#pragma unroll
-    for (int k = 1; k < 8; ++k) {
-      double2 w = stw[n2 * k];
-      if (inv) w.y = -w.y;
-      v[k] = cmul(v[k], w);
-    }
-  };
   double2 v[8];
   // 1. forward z, first half, from the grid: x[8 n1 + j]
   {
@@ -1239,6 +1231,18 @@ __global__ __launch_bounds__(512 * NB) void k_fft_yz64(FftYZArgs A) {
     for (int n1 = 0; n1 < 8; ++n1) v[n1] = g[(size_t)(8 * n1) * A.pc];
   }
   __syncthreads();                          // twiddles
+  // every twiddle step of this thread uses W^(j k), k = 1..7: kept in registers
+  double2 wj[8];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) wj[k] = stw[j * k];
+  auto tw8 = [&](double2* v, int, bool inv) {
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      double2 w = wj[k];
+      if (inv) w.y = -w.y;
+      v[k] = cmul(v[k], w);
+    }
+  };
   dft8<false>(v);
   tw8(v, j, false);
 #pragma unroll
