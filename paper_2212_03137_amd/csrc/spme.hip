@@ -834,7 +834,7 @@ __global__ __launch_bounds__(SX_NT) void k_spread_x(SpreadXArgs A) {
     // spans the axis); for each, the z tiles of [zlo, zlo + zn) as one or two runs. One
     // thread per range reads its bounds, an exclusive scan of the lengths places them
     // (empty ranges are kept: the search below never lands on one).
-    const int ys = (ylo % A.K1 + A.K1) % A.K1, zs = (zlo % A.K2 + A.K2) % A.K2;
+    const int ys = ylo & (A.K1 - 1), zs = zlo & (A.K2 - 1);
     const int ty0 = yn >= A.K1 ? 0 : ys / QHP_TB;
     const int tyn = yn >= A.K1 ? A.nt1 : min(A.nt1, (ys + yn - 1) / QHP_TB - ty0 + 1);
     int zp0[2] = {0, 0}, zp1[2] = {A.nt2, A.nt2}, nzp = 1;
@@ -875,6 +875,7 @@ __global__ __launch_bounds__(SX_NT) void k_spread_x(SpreadXArgs A) {
   // candidate classes: the centroid base's offsets (dy, dz) from (ylo, zlo), merged into
   // NBIN ordered classes when there are more
   const int nzk = min(zn, A.K2), nkey = max(min(yn, A.K1) * nzk, NBIN);
+  const int lgb = __builtin_ctz((unsigned)gb);
   int pos = 0;
   for (;;) {
     // 1) atoms whose centroid base lies in the widened y and z ranges
@@ -893,7 +894,7 @@ __global__ __launch_bounds__(SX_NT) void k_spread_x(SpreadXArgs A) {
         a = A.tile_atoms[tbeg[lo] + (p - tofs[lo])];
         const double4 c = A.cent[a];
         const int by = base_of(c.y, A.KoL[1], A.K1), bz = base_of(c.z, A.KoL[2], A.K2);
-        const int dy = ((by - ylo) % A.K1 + A.K1) % A.K1, dz = ((bz - zlo) % A.K2 + A.K2) % A.K2;
+        const int dy = (by - ylo) & (A.K1 - 1), dz = (bz - zlo) & (A.K2 - 1);   // K powers of two
         hit = (yn >= A.K1 || dy < yn) && (zn >= A.K2 || dz < zn);
         key = (int)((long)(dy * nzk + dz) * NBIN / nkey);
       }
@@ -948,9 +949,9 @@ __global__ __launch_bounds__(SX_NT) void k_spread_x(SpreadXArgs A) {
     // 2) every compacted atom at every bead of the block: spline weights, the points of
     //    its stencil on the block's lines
     for (int it = tid; it < nc * gb; it += SX_NT) {
-      const int bl = it % gb, b = 2 * c0 + bl;
+      const int bl = it & (gb - 1), b = 2 * c0 + bl;       // gb: a power of two
       if (bl >= nb) continue;
-      const int a = ckey[it / gb];
+      const int a = ckey[it >> lgb];
       int base[3];
       double fr[3];
 #pragma unroll
