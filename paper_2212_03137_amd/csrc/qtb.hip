@@ -243,13 +243,14 @@ struct GenArgs {
   double* noise;          // qtb_rec layout
 };
 
-// One block per atom (two blocks per compute unit: 64 KB of LDS at N_seg = 1,024). The
+// One block per atom (two blocks per compute unit: 64 KB of LDS at N_seg = 1,024, and at
+// most 128 VGPRs so that two 512-thread blocks fit the register file as well). The
 // window's white noise is drawn once (each Philox counter gives the x, y and z Gaussians;
 // z waits in registers), then x + i y and z + 0 i are convolved with the type's kernel in
 // turn: forward transform of length 4 N_seg, product with the kernel's transform, inverse
 // transform, the middle N_seg samples written as 64-byte runs of the segment record.
 template <int L4, int NTH>
-__global__ __launch_bounds__(NTH) void k_qtb_generate(GenArgs A) {
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void k_qtb_generate(GenArgs A) {
   constexpr int NS = L4 / 4, LG = tw_lg<L4>(), EPT = L4 / NTH;
   __shared__ double2 buf[L4];
   __shared__ double2 hi[L4 >> LG], lo[1 << LG];
