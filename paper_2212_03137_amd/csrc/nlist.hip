@@ -241,10 +241,12 @@ __global__ __launch_bounds__(PREP_NT) void k_prep_count(PrepArgs B, int force) {
   if (!last) return;
   // ---- 3. the last block: rebuild decision and step bookkeeping ----
   __threadfence();
+  __shared__ double smax[4];
+  if (tid < 4) smax[tid] = __longlong_as_double((long long)atomicExch(&A.ctrl->prep_max[tid], 0ull));
+  __syncthreads();
   if (tid == 0) {
     NlCtrl* c = A.ctrl;
-    double m[4];
-    for (int q = 0; q < 4; ++q) m[q] = __longlong_as_double((long long)atomicExch(&c->prep_max[q], 0ull));
+    const double m[4] = {smax[0], smax[1], smax[2], smax[3]};
     const double dc = sqrt(m[0]), db = sqrt(m[1]);
     const int b = force || c->force_build || !(2.0 * (dc + db) <= A.skin);
     c->do_build = b;
@@ -307,14 +309,13 @@ __global__ __launch_bounds__(PREP_NT) void k_prep_scatter(PrepArgs B) {
 // the build frame of the cell's atoms: reference centroid, centroid wrapped into the box
 // (w: bead spread) and the offset between the two.
 constexpr int NL_THREADS = 1024;
-__global__ __launch_bounds__(NL_THREADS) void k_nl_build(NlArgs A) {
-  if (!A.ctrl->do_build) return;
+QHP_DEV void nl_build_cell(const NlArgs& A, const int cell) {
   __shared__ double sx[MAXM], sy[MAXM], sz[MAXM];
   __shared__ int sj[MAXM];
   __shared__ int sofs[126];
   __shared__ int scnt[MAXC];
   __shared__ int sbeg[126];
-  const int cell = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int* st = A.stencil + (size_t)cell * A.nst;
   // sizes and first entries of the neighbouring cells, loaded in parallel, then a prefix sum
   if (tid < A.nst) {
@@ -416,6 +417,17 @@ __global__ __launch_bounds__(NL_THREADS) void k_nl_build(NlArgs A) {
   for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
   if (lane == 0 && most > 0) atomicMax(&A.ctrl->max_count, most);
 }
+
+// A fixed grid of blocks takes the cells in turn, so a step without a rebuild costs the
+// start and exit of a few hundred blocks rather than of one block per cell.
+constexpr int NL_BLOCKS = 512;   // two blocks of 74 KB of LDS per compute unit
+__global__ __launch_bounds__(NL_THREADS) void k_nl_build(NlArgs A) {
+  if (!A.ctrl->do_build) return;
+  for (int cell = blockIdx.x; cell < A.ncell; cell += gridDim.x) {
+    nl_build_cell(A, cell);
+    __syncthreads();                 // the block's LDS is reused by the next cell
+  }
+}
 #pragma clang fp contract(fast)
 
 }  // namespace
@@ -460,13 +472,13 @@ hipError_t launch_nlist(qhp_ctx* c, bool from_step) {
     const unsigned nb = (unsigned)((c->N + PREP_ATOMS - 1) / PREP_ATOMS);
     hipLaunchKernelGGL(k_prep_count, nb, PREP_NT, 0, c->stream, B, from_step ? 0 : 1);
     hipLaunchKernelGGL(k_prep_scatter, nb, PREP_NT, 0, c->stream, B);
-    hipLaunchKernelGGL(k_nl_build, c->ncell, NL_THREADS, 0, c->stream, A);
+    hipLaunchKernelGGL(k_nl_build, std::min(c->ncell, NL_BLOCKS), NL_THREADS, 0, c->stream, A);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_nl_check, 1, 256, 0, c->stream, A, from_step ? 0 : 1);
   hipLaunchKernelGGL(k_nl_assign, (c->N + 255) / 256, 256, 0, c->stream, A);
   hipLaunchKernelGGL(k_nl_scan, 1, 256, 0, c->stream, A);
   hipLaunchKernelGGL(k_nl_scatter, (c->N + 255) / 256, 256, 0, c->stream, A);
-  hipLaunchKernelGGL(k_nl_build, c->ncell, NL_THREADS, 0, c->stream, A);
+  hipLaunchKernelGGL(k_nl_build, std::min(c->ncell, NL_BLOCKS), NL_THREADS, 0, c->stream, A);
   return hipGetLastError();
 }
