@@ -360,7 +360,10 @@ def main():
         torch.cuda.synchronize()
         c = make(q.FP32_PAIRS, q.BATCHED, graph=False)
         c.step(args.warmup)
-        c.autotune(3)                 # the launch shapes of the timed path
+        # one fixed launch shape that the autotuner picks for this box (its choice between
+        # close candidates varies from run to run), so that every counter pass sees the
+        # same kernels
+        c.set_launch(16, 1, 1, 4)
         c.step(args.steps)
         c.close()
         torch.cuda.synchronize()

@@ -226,7 +226,9 @@ __global__ __launch_bounds__(PREP_NT) void k_prep_count(PrepArgs B, int force) {
     wave_count(B.tile_count, i < A.N ? B.tile_of[i] : -1);
     wave_count(A.cell_count, i < A.N ? A.cell_of[i] : -1);
   }
-  __threadfence();
+  // every wavefront's atomics are complete at the barrier; one device-scope release fence
+  // of the block then orders them before its arrival is counted (a fence in every thread
+  // costs a device-wide write-back per wavefront on a chip of eight L2 caches)
   __syncthreads();
   if (tid == 0) {
     for (int q = 0; q < 4; ++q) {
@@ -236,11 +238,11 @@ __global__ __launch_bounds__(PREP_NT) void k_prep_count(PrepArgs B, int force) {
     }
     __threadfence();
     last = atomicAdd(&A.ctrl->prep_done, 1) == nblk - 1;
+    if (last) __threadfence();                      // acquire: the other blocks' counts
   }
   __syncthreads();
   if (!last) return;
   // ---- 3. the last block: rebuild decision and step bookkeeping ----
-  __threadfence();
   __shared__ double smax[4];
   if (tid < 4) smax[tid] = __longlong_as_double((long long)atomicExch(&A.ctrl->prep_max[tid], 0ull));
   __syncthreads();
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(PREP_NT) void k_prep_count(PrepArgs B, int force) {
   // ---- 4. offsets (start and the scatter's fill pointer) from the counts, which are
   //         cleared for the next step; cell offsets only on a rebuild ----
   // (the fence above made the other blocks' counts visible to plain loads: they were
-  // added at device scope, and this block's cache lines were invalidated)
+  // added at device scope, and the acquire invalidated this compute unit's caches)
   auto scan = [&](int* cnt, int* start_g, int* fill, int n, bool write) {
     const int pc = (n + PREP_NT - 1) / PREP_NT;
     const int b0 = min(n, tid * pc), b1 = min(n, b0 + pc);
