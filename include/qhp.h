@@ -333,33 +333,29 @@ QHP_API const char* qhp_group_last_error(qhp_group* group);
 
 /* Launch-shape autotuner: times the context's force kernels on its current beads (`reps`
  * launches per candidate, HIP events on the context's stream; the propagated state is not
- * changed). First the SPME spreading: with two or more complex grid slots, the spreading
- * fused with the x transform (its slots per block are the beads / 2, at least 1, and its
- * rectangle of grid lines extends over the z tiles) and the tiled spreading (one block per
- * group of 8^3-point tiles and beads) are both timed, each with 1, 2, 4, 8 or 16 beads per
- * block (up to the beads the pass covers) times 1, 2, 4 or 8 tiles of 8^3 points along z
- * (at most 16 bead-tiles); with one slot the tiled spreading only. Then, for square 32^2
- * or 64^2 y-z planes, the plane kernel of the y and z transforms with 1, 2, 4 or 8 complex
- * grid slots per block (at most 2 at 64^2) against three one-axis passes (reported as
- * -1). Then, where the FP32 pair kernel applies (precision = QHP_FP32_PAIRS and
- * 2 (cutoff + skin) below the shortest box edge), 2, 4 or 8 atoms per block of that kernel
- * (one wavefront per atom). Keeps the fastest of each for the context's later launches and
- * returns them in `spread_beads` (negative: the tiled spreading chosen where the fused one
- * applies), `spread_ztiles`, `fft_slots` and `pair_atoms` (all nullable; 0 = no choice
- * applies). Needs a state (qhp_set_state). Results do not depend on the choice beyond the
- * order of floating-point additions in the SPME sums; the pair kernel's results do not
- * depend on it at all. */
+ * changed). First the SPME spreading block: 1, 2, 4, 8 or 16 beads per block (up to the
+ * beads the pass covers) times 1, 2, 4 or 8 grid tiles of 8^3 points along z; with two or
+ * more complex grid slots the spreading fused with the x transform uses these as its slots
+ * per block (beads / 2, at least 1) and the z extent of its rectangle of grid lines. Then,
+ * for square 32^2 or 64^2 y-z planes, the plane kernel of the y and z transforms with 1, 2,
+ * 4 or 8 complex grid slots per block (at most 2 at 64^2) against three one-axis passes
+ * (reported as -1). Then, where the FP32 pair kernel applies (precision = QHP_FP32_PAIRS
+ * and 2 (cutoff + skin) below the shortest box edge), 2, 4 or 8 atoms per block of that
+ * kernel (one wavefront per atom). Keeps the fastest of each for the context's later
+ * launches and returns them in `spread_beads`, `spread_ztiles`, `fft_slots` and
+ * `pair_atoms` (all nullable; 0 = no choice applies). Needs a state (qhp_set_state).
+ * Results do not depend on the choice beyond the order of floating-point additions in the
+ * SPME sums; the pair kernel's results do not depend on it at all. */
 QHP_API int qhp_autotune(qhp_ctx* ctx, int32_t reps, int32_t* spread_beads,
                          int32_t* spread_ztiles, int32_t* fft_slots, int32_t* pair_atoms);
 
 /* Set the same launch shapes by hand (the autotuner's search space): spreading beads per
- * block (0 = min(P, 8), else +-(a power of two <= 16), capped at the beads of the pass;
- * negative selects the tiled spreading where the fused one would apply), spreading 8^3
- * tiles along z (0 = 1, else a power of two <= 8, capped so that beads x tiles <= 16 and at
- * the grid's tiles), y-z plane kernel slots per block (0 = default, -1 = one-axis passes,
- * else a power of two <= 8, capped at 2 for 64^2 planes and at the grid's slots; ignored
- * where no plane kernel applies), FP32 pair kernel atoms per block (0 = 4, else 2, 4 or
- * 8). QHP_EINVAL otherwise. */
+ * block (0 = min(P, 8), else a power of two <= 16, capped at the beads of the pass),
+ * spreading 8^3 tiles along z (0 = 1, else a power of two <= 8, capped so that beads x
+ * tiles <= 16 and at the grid's tiles), y-z plane kernel slots per block (0 = default,
+ * -1 = one-axis passes, else a power of two <= 8, capped at 2 for 64^2 planes and at the
+ * grid's slots; ignored where no plane kernel applies), FP32 pair kernel atoms per block
+ * (0 = 4, else 2, 4 or 8). QHP_EINVAL otherwise. */
 QHP_API int qhp_set_launch(qhp_ctx* ctx, int32_t spread_beads, int32_t spread_ztiles,
                            int32_t fft_slots, int32_t pair_atoms);
 

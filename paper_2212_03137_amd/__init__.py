@@ -258,9 +258,8 @@ class Context:
 
     def autotune(self, reps=5):
         """Pick the fastest launch shapes for this context (qhp_autotune) -> (beads per
-        spreading block, negative for the tiled spreading where the fused one applies; 8^3
-        tiles along z per spreading block; complex slots per y-z plane block or -1 for
-        one-axis passes; FP32 pair kernel atoms per block or 0)."""
+        spreading block, 8^3 tiles along z per spreading block, complex slots per y-z plane
+        block or -1 for one-axis passes, FP32 pair kernel atoms per block or 0)."""
         gb, z, nb, w = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         self._check(self._lib.qhp_autotune(self._h, int(reps), C.byref(gb), C.byref(z),
                                            C.byref(nb), C.byref(w)))

@@ -870,9 +870,8 @@ extern "C" int qhp_set_launch(qhp_ctx* c, int32_t spread_beads, int32_t spread_z
                               int32_t fft_slots, int32_t pair_atoms) {
   if (!c) return QHP_EINVAL;
   auto p2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
-  const int gbeads = spread_beads < 0 ? -spread_beads : spread_beads;
-  if (!(spread_beads == 0 || (p2(gbeads) && gbeads <= 16)))
-    return qhp_fail(c, QHP_EINVAL, "spread_beads must be 0 or +-(a power of two <= 16)");
+  if (!(spread_beads == 0 || (p2(spread_beads) && spread_beads <= 16)))
+    return qhp_fail(c, QHP_EINVAL, "spread_beads must be 0 or a power of two <= 16");
   if (!(spread_ztiles == 0 || (p2(spread_ztiles) && spread_ztiles <= 8)))
     return qhp_fail(c, QHP_EINVAL, "spread_ztiles must be 0 or a power of two <= 8");
   if (!(fft_slots == 0 || fft_slots == -1 || (p2(fft_slots) && fft_slots <= 8)))
@@ -880,8 +879,7 @@ extern "C" int qhp_set_launch(qhp_ctx* c, int32_t spread_beads, int32_t spread_z
   if (!(pair_atoms == 0 || pair_atoms == 2 || pair_atoms == 4 || pair_atoms == 8))
     return qhp_fail(c, QHP_EINVAL, "pair_atoms must be 0, 2, 4 or 8");
   c->pair_wpb = pair_atoms;
-  c->spread_gb = gbeads;
-  c->spread_tiled = spread_beads < 0 ? 1 : 0;
+  c->spread_gb = spread_beads;
   c->spread_z = spread_ztiles;
   c->fft_nb = fft_slots;
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
@@ -911,31 +909,25 @@ extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
   hipEvent_t t0 = nullptr, t1 = nullptr;
   QHP_HIP(c, hipEventCreate(&t0));
   QHP_HIP(c, hipEventCreate(&t1));
-  int best_gb = 0, best_z = 0, best_tiled = 0;
+  int best_gb = 0, best_z = 0;
   float best_ms = 0.f;
   hipError_t e = hipSuccess;
   const int nt2 = c->K[2] / QHP_TB;
-  // the fused spreading (two or more slots) and the tiled one, each over its shapes
-  for (int tiled = B.Pc >= 2 ? 0 : 1; tiled <= 1 && e == hipSuccess; ++tiled)
-    for (int gb = 1; gb <= 16 && gb <= B.P && e == hipSuccess; gb *= 2)
-      for (int z = 1; z <= 8 && z <= nt2 && gb * z <= 16 && e == hipSuccess; z *= 2) {
-        c->spread_gb = gb;
-        c->spread_z = z;
-        c->spread_tiled = tiled;
-        e = launch_spme(c, false, -1, &B);                 // warm
-        if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_spme(c, false, -1, &B);
-        if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(t1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-        if (e == hipSuccess && (best_gb == 0 || ms < best_ms)) {
-          best_gb = gb; best_z = z; best_tiled = tiled; best_ms = ms;
-        }
-      }
+  for (int gb = 1; gb <= 16 && gb <= B.P && e == hipSuccess; gb *= 2)
+    for (int z = 1; z <= 8 && z <= nt2 && gb * z <= 16 && e == hipSuccess; z *= 2) {
+      c->spread_gb = gb;
+      c->spread_z = z;
+      e = launch_spme(c, false, -1, &B);                   // warm
+      if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_spme(c, false, -1, &B);
+      if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e == hipSuccess && (best_gb == 0 || ms < best_ms)) { best_gb = gb; best_z = z; best_ms = ms; }
+    }
   c->spread_gb = best_gb;
   c->spread_z = best_z;
-  c->spread_tiled = best_tiled;
   // then the reciprocal transforms: the y-z plane kernel with 1, 2, 4 or 8 slots per
   // block (square 32^2 or 64^2 planes; up to 2 slots at 64) or five one-axis passes
   int best_nb = 0;
@@ -980,7 +972,7 @@ extern "C" int qhp_autotune(qhp_ctx* c, int32_t reps, int32_t* spread_beads,
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   c->step_exec = nullptr;
   ++c->graph_epoch;
-  if (spread_beads) *spread_beads = best_tiled && B.Pc >= 2 ? -best_gb : best_gb;
+  if (spread_beads) *spread_beads = best_gb;
   if (spread_ztiles) *spread_ztiles = best_z;
   if (fft_slots) *fft_slots = best_nb;
   if (pair_atoms) *pair_atoms = best_w;

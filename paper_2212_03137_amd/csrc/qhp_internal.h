@@ -113,7 +113,6 @@ struct qhp_ctx {
   int64_t graph_epoch = 0;          // bumped whenever captured kernel arguments go stale
   int pair_wpb = 0;                 // FP32 pair kernel: atoms per block (0 = 4; 2, 4, 8)
   int spread_gb = 0;                // SPME spreading: beads per block (0 = min(P, 8))
-  int spread_tiled = 0;             // SPME spreading: the tiled kernel even where the fused one applies
   int spread_z = 0;                 // SPME spreading: 8^3 tiles per block along z (0 = 1)
   int fft_nb = 0;                   // y-z plane kernel: slots per block (0 = default,
                                     // < 0 = one-axis passes instead)

@@ -1413,7 +1413,7 @@ static hipError_t convolve(qhp_ctx* c, int pc, double2* grid, bool x_done = fals
 // the normal-mode kernel enforces).
 static bool spread_x_shape(const qhp_ctx* c, int P, int pc, SpreadXArgs& X) {
   const int K0 = c->K[0], K1 = c->K[1], K2 = c->K[2];
-  if (c->spread_tiled) return false;                   // the tiled spreading was asked for
+  if (c->spread_gb < 0) return false;                  // the tiled spreading was asked for
   // one slot (a single bead): the tiled spreading with the separate x pass measured faster
   if (pc < 2 || K0 < 16 || K0 > 128) return false;
   int gc = c->spread_gb > 0 ? std::max(1, c->spread_gb / 2) : 4;

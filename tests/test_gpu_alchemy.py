@@ -206,8 +206,8 @@ def test_autotune_keeps_results_and_the_state(medium):
     say("autotuned spread block", gb, zt, "fft slots", nb, "pair atoms", w)
     assert w in (0, 2, 4, 8)
     assert nb in (-1, 1, 2)                            # 4 beads: two complex slots
-    assert abs(gb) in (1, 2, 4) and abs(gb) <= medium.n_beads
-    assert zt in (1, 2, 4) and abs(gb) * zt <= 16     # 32^3 grid: four 8^3 tiles along z
+    assert gb in (1, 2, 4) and gb <= medium.n_beads
+    assert zt in (1, 2, 4) and gb * zt <= 16          # 32^3 grid: four 8^3 tiles along z
     assert np.array_equal(x0, x1) and np.array_equal(v0, v1)
     assert rel_max(F1, F0) <= 1e-13
     assert np.allclose(E1, E0, rtol=1e-13, atol=1e-10)
