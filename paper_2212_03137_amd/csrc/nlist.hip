@@ -267,6 +267,10 @@ __global__ __launch_bounds__(PREP_NT) void k_prep_count(PrepArgs B, int force) {
   // (the fence above made the other blocks' counts visible to plain loads: they were
   // added at device scope, and the acquire invalidated this compute unit's caches)
   auto scan = [&](int* cnt, int* start_g, int* fill, int n, bool write) {
+    if (!write) {                                   // counts only to be cleared
+      for (int k = tid; k < n; k += PREP_NT) cnt[k] = 0;
+      return;
+    }
     const int pc = (n + PREP_NT - 1) / PREP_NT;
     const int b0 = min(n, tid * pc), b1 = min(n, b0 + pc);
     int s = 0;
