@@ -31,7 +31,10 @@ Readings where the paper is silent (all stated here and used by both implementat
 * RATIO scheme (eq. adapt_ratio with the exponentially decaying running means): the
   running means start from zero, so the first update is the plain ratio of the first
   segment's type-averaged spectra (the common factor 1 - e^{-N_seg dt / tau} cancels);
-  where the running C_vv is not positive gamma keeps its value; one tau for every type;
+  where the running C_vv is not positive gamma keeps its value;
+* per type z (the same section): each type has its own running-mean time tau_z, and the
+  two schemes can be mixed by type (SIMPLE for some types, RATIO for others); a type's
+  update uses only its own spectra, scheme and tau_z;
 * A_gamma is in 1/fs per kcal/mol and the first update happens at the end of segment 0:
   parity unpinned beyond the HIP path matching this oracle.
 """
@@ -100,7 +103,11 @@ def spectra_delta(v, F, gamma_of_atom, m, dt):
 
 
 class QTB:
-    """adQTB run on P = 1 beads. ``grad_fn(x[1][N][3]) -> (E, grad[1][N][3])``."""
+    """adQTB run on P = 1 beads. ``grad_fn(x[1][N][3]) -> (E, grad[1][N][3])``.
+
+    ``scheme``: "SIMPLE" or "RATIO" for every type, or a sequence of one per type;
+    ``tau``: the RATIO running-mean time, one number or one per type (read for the RATIO
+    types only)."""
 
     def __init__(self, mass, types, n_types, kT, hbar, dt, gamma0, nseg, adapt_rate,
                  gamma_min_frac, seed, grad_fn, classical_theta=False, scheme="SIMPLE",
@@ -118,10 +125,16 @@ class QTB:
         self.osd = math.sqrt((1.0 - self.c1 * self.c1) * dt / (2.0 * gamma0))
         self.gamma = np.full((n_types, nseg + 1), gamma0)
         self.type_mass = np.array([self.m[self.types == z][0] for z in range(n_types)])
-        if scheme not in ("SIMPLE", "RATIO"):
+        schemes = [scheme] * n_types if isinstance(scheme, str) else list(scheme)
+        taus = list(tau) if np.ndim(tau) == 1 else [tau] * n_types
+        if len(schemes) != n_types or len(taus) != n_types:
+            raise ValueError("one scheme and one tau per type")
+        if any(sz not in ("SIMPLE", "RATIO") for sz in schemes):
             raise ValueError(scheme)
-        self.scheme = scheme
-        self.decay = math.exp(-nseg * dt / tau) if scheme == "RATIO" else 0.0
+        self.ratio_of = np.array([sz == "RATIO" for sz in schemes])
+        # running-mean factor e^{-N_seg dt / tau_z} of each RATIO type
+        self.decay = np.array([math.exp(-nseg * dt / tz) if rz else 0.0
+                               for rz, tz in zip(self.ratio_of, taus)])
         self.avg_vv = np.zeros((n_types, nseg + 1))
         self.avg_vf = np.zeros((n_types, nseg + 1))
 
@@ -158,19 +171,22 @@ class QTB:
         diss = spectra_delta(self.vrec, np.zeros_like(self.noise), self.gamma[self.types], self.m, self.dt)
         self.last_dissipation = np.stack([diss[self.types == z].mean(axis=(0, 1))
                                           for z in range(self.n_types)])
-        if self.scheme == "SIMPLE":
-            self.gamma = self.gamma - self.A * dbar
+        # SIMPLE: gamma <- gamma - A_gamma Delta_bar
+        simple = self.gamma - self.A * dbar
+        if not self.ratio_of.any():
+            self.gamma = simple
             return
         # RATIO: gamma = Re <C_vF> / (m <C_vv>) over exponentially decaying running means
         Cvv, CvFr = spectra(self.vrec, self.noise, self.dt)
         vv = np.stack([Cvv[self.types == z].mean(axis=(0, 1)) for z in range(self.n_types)])
         vf = np.stack([CvFr[self.types == z].mean(axis=(0, 1)) for z in range(self.n_types)])
-        self.avg_vv = self.avg_vv * self.decay + vv * (1.0 - self.decay)
-        self.avg_vf = self.avg_vf * self.decay + vf * (1.0 - self.decay)
+        d = self.decay[:, None]
+        self.avg_vv = np.where(self.ratio_of[:, None], self.avg_vv * d + vv * (1.0 - d), 0.0)
+        self.avg_vf = np.where(self.ratio_of[:, None], self.avg_vf * d + vf * (1.0 - d), 0.0)
         ok = self.avg_vv > 0.0
         ratio = np.where(ok, self.avg_vf / (self.type_mass[:, None] * np.where(ok, self.avg_vv, 1.0)),
                          self.gamma)
-        self.gamma = ratio
+        self.gamma = np.where(self.ratio_of[:, None], ratio, simple)
 
     def step(self, n=1):
         for _ in range(n):

@@ -222,6 +222,31 @@ def test_ratio_running_mean_recursion():
         prev = Q.avg_vv.copy()
 
 
+def test_per_type_schemes_and_times_act_type_by_type():
+    # Free atoms do not interact, and each atom's coloured noise depends only on its own
+    # type's gamma and its own Philox stream, so the atoms of one type follow the same
+    # trajectory whatever the other type's adaptation is. Mixing the schemes by type
+    # (SIMPLE for type 0, RATIO for type 1) therefore gives type 0 the all-SIMPLE gamma and
+    # type 1 the all-RATIO gamma, bit for bit; per-type times likewise match the runs with
+    # one time each. A swapped type index or a scheme applied to the wrong type fails.
+    runs = {}
+    for key, scheme, tau in (("simple", "SIMPLE", None), ("ratio150", "RATIO", 150.0),
+                             ("ratio40", "RATIO", 40.0), ("mixed", ["SIMPLE", "RATIO"], 150.0),
+                             ("taus", "RATIO", [150.0, 40.0])):
+        Q = _free_qtb(scheme, tau, n=60, nseg=32)
+        Q.step(Q.nseg * 3)
+        runs[key] = Q
+    assert np.array_equal(runs["mixed"].gamma[0], runs["simple"].gamma[0])
+    assert np.array_equal(runs["mixed"].gamma[1], runs["ratio150"].gamma[1])
+    assert np.array_equal(runs["taus"].gamma[0], runs["ratio150"].gamma[0])
+    assert np.array_equal(runs["taus"].gamma[1], runs["ratio40"].gamma[1])
+    # the two times give different updates (the test above is not vacuous)
+    assert not np.array_equal(runs["ratio150"].gamma[1], runs["ratio40"].gamma[1])
+    assert not np.array_equal(runs["simple"].gamma[1], runs["ratio150"].gamma[1])
+    with pytest.raises(ValueError):
+        _free_qtb(["SIMPLE"], 1.0)
+
+
 @pytest.mark.parametrize("start", [2.0, 0.5])
 def test_simple_adaptation_returns_harmonic_oscillators_to_gamma0(start):
     # Linear response of a harmonic oscillator with friction gamma_0 driven by a force of
