@@ -141,8 +141,8 @@ typedef struct qhp_params {
   int32_t rpc_beads;        /* P~ in 1..P (any count; 0 = P, no contraction)             */
   int32_t respa_nalt;       /* n: inner steps per outer step, 1..64; 0 = 1               */
   int32_t integrator;       /* QHP_BAOAB | QHP_BCOCB                                      */
-  int32_t qtb_adapt_scheme; /* QHP_QTB_SIMPLE | QHP_QTB_RATIO                             */
-  double qtb_tau;           /* RATIO: running-mean time tau (same for every type), > 0.
+  int32_t qtb_adapt_scheme; /* QHP_QTB_SIMPLE | QHP_QTB_RATIO (every type; see below)     */
+  double qtb_tau;           /* RATIO: running-mean time tau (every type; see below), > 0.
                                The means start from zero; where <C_vv> <= 0 gamma keeps
                                its value; the gamma_min clamp follows either scheme.    */
   /* Alchemical coupling of a solute (Sec. "Hydration free energies": the solute is
@@ -166,6 +166,13 @@ typedef struct qhp_params {
    * (QHP_EUNSUPPORTED). */
   double tether_k;          /* k_h >= 0, kcal/mol/A^2                                     */
   const double* tether_anchor; /* [N][3] anchors (host, copied at creation) when k_h > 0  */
+  /* adQTB adaptation per atom type (Sec. "Computation of the adQTB Spectra and Adaptation
+   * Procedure": every type z has its own running-mean time tau_z, and the two schemes may
+   * be combined, e.g. SIMPLE for a solute's types and RATIO for the solvent's). A type's
+   * update reads only its own spectra. NULL: every type takes qtb_adapt_scheme and
+   * qtb_tau. Host arrays, read at creation. Bad entries: QHP_EINVAL.                    */
+  const int32_t* qtb_scheme_of; /* [n_types] QHP_QTB_SIMPLE | QHP_QTB_RATIO, or NULL    */
+  const double* qtb_tau_of;     /* [n_types] tau_z, > 0 for RATIO types, or NULL        */
 } qhp_params;
 
 typedef struct qhp_ctx qhp_ctx;

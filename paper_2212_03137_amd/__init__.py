@@ -61,6 +61,7 @@ class Params(C.Structure):
         ("type_soft", C.POINTER(C.c_int32)), ("lambda_elec", C.c_double),
         ("lambda_vdw", C.c_double), ("sc_alpha", C.c_double),
         ("tether_k", C.c_double), ("tether_anchor", C.POINTER(C.c_double)),
+        ("qtb_scheme_of", C.POINTER(C.c_int32)), ("qtb_tau_of", C.POINTER(C.c_double)),
     ]
 
 
@@ -134,7 +135,8 @@ class Context:
                  qtb_nseg=1024, qtb_adapt_rate=0.0, qtb_gamma_min_frac=0.01, qtb_classical=False,
                  nbr_capacity=0, use_graph=True, rpc_beads=0, respa_nalt=1, integrator=0,
                  qtb_adapt_scheme=0, qtb_tau=0.0, type_soft=None, lambda_elec=1.0,
-                 lambda_vdw=1.0, sc_alpha=0.5, tether_k=0.0, tether_anchor=None, stream=None):
+                 lambda_vdw=1.0, sc_alpha=0.5, tether_k=0.0, tether_anchor=None,
+                 qtb_scheme_of=None, qtb_tau_of=None, stream=None):
         self._lib = load()
         self.N, self.P = int(n_atoms), int(n_beads)
         self.n_types = len(lj_sigma)
@@ -175,6 +177,15 @@ class Context:
         if tether_anchor is not None:
             self._keep.append(np.ascontiguousarray(tether_anchor, dtype=np.float64))
             p.tether_anchor = self._keep[-1].ctypes.data_as(C.POINTER(C.c_double))
+        for arr in (qtb_scheme_of, qtb_tau_of):
+            if arr is not None and len(arr) != self.n_types:
+                raise ValueError("qtb_scheme_of and qtb_tau_of take one entry per type")
+        if qtb_scheme_of is not None:
+            self._keep.append(np.ascontiguousarray(qtb_scheme_of, dtype=np.int32))
+            p.qtb_scheme_of = self._keep[-1].ctypes.data_as(C.POINTER(C.c_int32))
+        if qtb_tau_of is not None:
+            self._keep.append(np.ascontiguousarray(qtb_tau_of, dtype=np.float64))
+            p.qtb_tau_of = self._keep[-1].ctypes.data_as(C.POINTER(C.c_double))
         self.params = p
         h = C.c_void_p()
         rc = self._lib.qhp_create(C.byref(p), C.c_void_p(stream) if stream else None, C.byref(h))

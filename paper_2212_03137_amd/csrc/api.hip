@@ -239,8 +239,13 @@ int validate(const qhp_params* p, std::string& why) {
   if (p->integrator != QHP_BAOAB && p->integrator != QHP_BCOCB) return bad("integrator");
   if (p->qtb_adapt_scheme != QHP_QTB_SIMPLE && p->qtb_adapt_scheme != QHP_QTB_RATIO)
     return bad("qtb_adapt_scheme");
-  if (p->thermostat == QHP_ADQTB && p->qtb_adapt_scheme == QHP_QTB_RATIO && !(p->qtb_tau > 0))
-    return bad("qtb_tau must be > 0 for RATIO adaptation");
+  for (int z = 0; z < p->n_types; ++z) {
+    const int sz = p->qtb_scheme_of ? p->qtb_scheme_of[z] : p->qtb_adapt_scheme;
+    const double tz = p->qtb_tau_of ? p->qtb_tau_of[z] : p->qtb_tau;
+    if (sz != QHP_QTB_SIMPLE && sz != QHP_QTB_RATIO) return bad("qtb_scheme_of");
+    if (p->thermostat == QHP_ADQTB && sz == QHP_QTB_RATIO && !(tz > 0))
+      return bad("qtb_tau must be > 0 for RATIO adaptation");
+  }
   {
     const int ps = p->rpc_beads > 0 ? p->rpc_beads : p->n_beads;
     const int na = p->respa_nalt > 0 ? p->respa_nalt : 1;
@@ -304,6 +309,15 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   qhp_ctx* c = new (std::nothrow) qhp_ctx();
   if (!c) return QHP_ENOMEM;
   c->p = *p;
+  // per-type adaptation: the scheme and running-mean time of every type, kept here (the
+  // caller's arrays are read at creation only)
+  for (int z = 0; z < p->n_types; ++z) {
+    c->qtb.ratio_of[z] = (p->qtb_scheme_of ? p->qtb_scheme_of[z] : p->qtb_adapt_scheme) == QHP_QTB_RATIO;
+    c->qtb.tau_of[z] = p->qtb_tau_of ? p->qtb_tau_of[z] : p->qtb_tau;
+    c->qtb.any_ratio = c->qtb.any_ratio || c->qtb.ratio_of[z];
+  }
+  c->p.qtb_scheme_of = nullptr;
+  c->p.qtb_tau_of = nullptr;
   c->stream = (hipStream_t)stream;
   if (!c->stream) {
     // a private stream (default priority): the null stream cannot be captured into a graph
@@ -544,7 +558,7 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
     const int nk = p->n_types * (q.nseg + 1);
     TRY(dalloc(&q.gamma, nk)); TRY(dalloc(&q.dsum, nk)); TRY(dalloc(&q.dbar, nk));
     TRY(hipMemset(q.dbar, 0, nk * sizeof(double)));
-    if (p->qtb_adapt_scheme == QHP_QTB_RATIO) {
+    if (q.any_ratio) {
       TRY(dalloc(&q.vvsum, nk)); TRY(dalloc(&q.vfsum, nk));
       TRY(dalloc(&q.avg_vv, nk)); TRY(dalloc(&q.avg_vf, nk));
       for (double* z : {q.vvsum, q.vfsum, q.avg_vv, q.avg_vf}) TRY(hipMemset(z, 0, nk * sizeof(double)));

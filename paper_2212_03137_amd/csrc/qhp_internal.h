@@ -79,6 +79,9 @@ struct QtbState {
   int type_count[QHP_MAX_TYPES];
   double type_mass[QHP_MAX_TYPES];
   double c1, osd;             // O step: p <- c1 p + osd F
+  int ratio_of[QHP_MAX_TYPES] = {};   // adaptation of each type: 1 = RATIO, 0 = SIMPLE
+  double tau_of[QHP_MAX_TYPES] = {};  // RATIO running-mean time of each type
+  bool any_ratio = false;             // the RATIO accumulators exist
 };
 
 struct qhp_ctx {

@@ -383,15 +383,18 @@ __global__ __launch_bounds__(NTH) void k_qtb_spectra(SpecArgs A) {
   }
 }
 
-// SIMPLE: gamma <- max(gamma_min, gamma - A Delta_bar). RATIO: the running means
-// <C> <- <C> decay + C_bar (1 - decay) of C_vv and Re C_vF, then gamma <- max(gamma_min,
-// Re<C_vF> / (m <C_vv>)) where <C_vv> > 0. Keep Delta_bar for export; clear the sums.
+// Per type z, by its scheme: SIMPLE: gamma <- max(gamma_min, gamma - A Delta_bar). RATIO:
+// the running means <C> <- <C> decay_z + C_bar (1 - decay_z) of C_vv and Re C_vF,
+// decay_z = exp(-N_seg dt / tau_z), then gamma <- max(gamma_min, Re<C_vF> / (m <C_vv>))
+// where <C_vv> > 0. Keep Delta_bar for export; clear the sums.
 struct AdaptArgs {
-  int n, nseg, ratio;
+  int n, nseg, any_ratio;
   double* gamma; double* dsum; double* dbar; double* vvsum; double* vfsum;
   double* avg_vv; double* avg_vf;
   const double* inv_count; const double* tmass;
-  double rate, gmin, decay;
+  double rate, gmin;
+  int ratio_of[QHP_MAX_TYPES];
+  double decay[QHP_MAX_TYPES];
 };
 
 __global__ void k_qtb_adapt(AdaptArgs A) {
@@ -402,12 +405,15 @@ __global__ void k_qtb_adapt(AdaptArgs A) {
   const double d = A.dsum[i] * ic;
   A.dbar[i] = d;
   double g = A.gamma[i] - A.rate * d;
-  if (A.ratio) {
-    const double vv = A.avg_vv[i] * A.decay + A.vvsum[i] * ic * (1.0 - A.decay);
-    const double vf = A.avg_vf[i] * A.decay + A.vfsum[i] * ic * (1.0 - A.decay);
-    A.avg_vv[i] = vv;
-    A.avg_vf[i] = vf;
-    g = vv > 0.0 ? vf / (A.tmass[z] * vv) : A.gamma[i];
+  if (A.any_ratio) {
+    if (A.ratio_of[z]) {
+      const double dz = A.decay[z];
+      const double vv = A.avg_vv[i] * dz + A.vvsum[i] * ic * (1.0 - dz);
+      const double vf = A.avg_vf[i] * dz + A.vfsum[i] * ic * (1.0 - dz);
+      A.avg_vv[i] = vv;
+      A.avg_vf[i] = vf;
+      g = vv > 0.0 ? vf / (A.tmass[z] * vv) : A.gamma[i];
+    }
     A.vvsum[i] = 0.0;
     A.vfsum[i] = 0.0;
   }
@@ -475,7 +481,7 @@ hipError_t launch_qtb_adapt(qhp_ctx* c) {
   }
   A.tw2 = q.tw2; A.dt = c->p.dt; A.dsum = q.dsum;
   A.vvsum = q.vvsum; A.vfsum = q.vfsum;
-  A.ratio = c->p.qtb_adapt_scheme == QHP_QTB_RATIO;
+  A.ratio = q.any_ratio;
   // a few atoms per block, several blocks per compute unit; the per-type accumulators are
   // dynamic LDS next to the transform: types that do not fit together are accumulated by
   // further launches (each skips the others' atoms)
@@ -491,11 +497,14 @@ hipError_t launch_qtb_adapt(qhp_ctx* c) {
                                                c->stream, A));
   }
   AdaptArgs D;
-  D.n = c->p.n_types * (q.nseg + 1); D.nseg = q.nseg; D.ratio = A.ratio;
+  D.n = c->p.n_types * (q.nseg + 1); D.nseg = q.nseg; D.any_ratio = A.ratio;
   D.gamma = q.gamma; D.dsum = q.dsum; D.dbar = q.dbar; D.vvsum = q.vvsum; D.vfsum = q.vfsum;
   D.avg_vv = q.avg_vv; D.avg_vf = q.avg_vf; D.inv_count = q.d_inv_count; D.tmass = q.d_tmass;
   D.rate = c->p.qtb_adapt_rate; D.gmin = c->p.qtb_gamma_min_frac * c->p.qtb_gamma0;
-  D.decay = A.ratio ? std::exp(-q.nseg * c->p.dt / c->p.qtb_tau) : 0.0;
+  for (int z = 0; z < QHP_MAX_TYPES; ++z) {
+    D.ratio_of[z] = z < c->p.n_types ? q.ratio_of[z] : 0;
+    D.decay[z] = D.ratio_of[z] ? std::exp(-q.nseg * c->p.dt / q.tau_of[z]) : 0.0;
+  }
   hipLaunchKernelGGL(k_qtb_adapt, (D.n + 255) / 256, 256, 0, c->stream, D);
   return hipGetLastError();
 }

@@ -60,3 +60,28 @@ def test_invalid_parameters_rejected_before_device_use(change, code):
     with pytest.raises(q.QhpError) as e:
         q.Context.from_system(s, **change)
     assert e.value.code == code
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(qtb_scheme_of=[0, 1], qtb_tau_of=[1.0, 0.0]), -1),   # a RATIO type without a time
+    (dict(qtb_scheme_of=[0, 7]), -1),                           # no such scheme
+    (dict(qtb_scheme_of=[0, 1], qtb_tau_of=[0.0, 1.0]), None),  # a SIMPLE type needs none
+    (dict(qtb_adapt_scheme=1, qtb_tau_of=[5.0, 1.0]), None),    # every type RATIO, own times
+])
+def test_per_type_adaptation_validated_before_device_use(change, code):
+    # the adQTB per-type schemes and times; a valid set reaches the device (which this
+    # container lacks: QHP_EDEVICE)
+    import paper_2212_03137_amd as q
+    if not os.path.exists(q.LIB_PATH):
+        pytest.skip("libqhp.so not built")
+    s = synth.water_box(27, 1, 12.0, seed=9, cutoff=5.5, ewald_alpha=0.4, pme_grid=16,
+                        pme_order=4, qtb_gamma0=0.02, qtb_nseg=32, qtb_adapt_rate=1e-3)
+    try:
+        c = q.Context.from_system(s, thermostat=q.ADQTB, **change)
+    except q.QhpError as e:
+        assert e.code == (q.EINVAL if code is not None else q.EDEVICE), e.code
+    else:
+        c.close()
+        assert code is None
+    with pytest.raises(ValueError):
+        q.Context.from_system(s, thermostat=q.ADQTB, qtb_tau_of=[1.0])

@@ -170,6 +170,41 @@ def test_ratio_adaptation_over_segments_matches_oracle():
     assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-7
 
 
+def test_per_type_schemes_and_times_match_oracle():
+    """SIMPLE for the oxygens and RATIO for the hydrogens, then RATIO for both with a time
+    of its own per type (Sec. "Computation of the adQTB Spectra and Adaptation
+    Procedure"): gamma and the noise over three segments against the oracle."""
+    import paper_2212_03137_amd as q
+    s = _system(64, rate=2e-3)
+    for schemes, taus in ((["SIMPLE", "RATIO"], [150.0, 150.0]), (["RATIO", "RATIO"], [60.0, 400.0])):
+        print("per-type adaptation", schemes, taus, flush=True)
+        Q = oq.QTB(s.mass, s.types, s.n_types, s.kT, s.hbar, s.dt, s.qtb_gamma0, s.qtb_nseg,
+                   s.qtb_adapt_rate, s.qtb_gamma_min_frac, s.seed, oracle_grad_fn(s),
+                   scheme=schemes, tau=taus)
+        Q.set_state(s.pos, s.vel, 0)
+        code = {"SIMPLE": q.QTB_SIMPLE, "RATIO": q.QTB_RATIO}
+        with _ctx(s, qtb_scheme_of=[code[x] for x in schemes], qtb_tau_of=taus) as c:
+            c.set_state(s.pos, s.vel, 0)
+            for seg in range(3):
+                Q.step(64)
+                c.step(64)
+                g = c.qtb_gamma()
+                assert np.abs(g - Q.gamma).max() <= 1e-7 * np.abs(Q.gamma).max(), seg
+                assert np.abs(c.qtb_noise() - Q.noise).max() <= 1e-6 * np.abs(Q.noise).max()
+            x, v, _ = c.get_state()
+        xr, vr, _ = Q.get_state()
+        assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-7
+
+
+def test_a_simple_type_needs_no_time():
+    import paper_2212_03137_amd as q
+    s = _system(32)
+    with _ctx(s, qtb_scheme_of=[q.QTB_SIMPLE, q.QTB_RATIO], qtb_tau_of=[0.0, 50.0]) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(32)
+        assert np.all(np.isfinite(c.qtb_gamma()))
+
+
 def test_ratio_needs_a_positive_tau():
     import paper_2212_03137_amd as q
     s = _system(32)
