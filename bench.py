@@ -491,7 +491,8 @@ def main():
             t_p = (time.perf_counter() - t0) / reps
             c.close()
             comp["derivatives"] = {"hvp_ms": t_h * 1e3, "param_grad_ms": t_p * 1e3,
-                                   "note": "one call each on all 32 beads, FP64 pair terms, "
+                                   "note": "one call each on all 32 beads, FP32 pair terms "
+                                           "(r, 1/r, erfc, exp) with FP64 products and sums, "
                                            "list rebuilt and forces evaluated inside"}
             comp["derivatives"]["force_loss"] = force_loss_timing(q, qa)
         except Exception as e:

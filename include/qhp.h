@@ -209,8 +209,10 @@ QHP_API int qhp_eval(qhp_ctx* ctx, const double* pos, const double box[3], doubl
  * charges (real-space, exclusion, self and reciprocal terms; the reciprocal part is the
  * SPME-interpolated potential at the atom), `deps` [n_types] and `dsig` [n_types] per-type
  * LJ epsilon and sigma (Lorentz-Berthelot combination; the epsilon derivative of a type
- * with epsilon = 0 is unbounded and returned as 0). Pair terms in FP64 whatever
- * `precision` is. Builds the list of these positions like qhp_eval and leaves the
+ * with epsilon = 0 is unbounded and returned as 0). Pair terms: with precision =
+ * QHP_FP32_PAIRS, r, 1/r, erfc(alpha r) and exp(-alpha^2 r^2) are FP32 values computed
+ * from the FP64 displacement and every product and sum is FP64; else all FP64. Builds
+ * the list of these positions like qhp_eval and leaves the
  * propagated state alone. QHP_EUNSUPPORTED for exec = QHP_PLAIN. */
 QHP_API int qhp_param_grad(qhp_ctx* ctx, const double* pos, double* dq, double* deps,
                            double* dsig, int mem_kind);
@@ -220,7 +222,8 @@ QHP_API int qhp_param_grad(qhp_ctx* ctx, const double* pos, double* dq, double* 
  * derivatives (all terms: bonds, angle and exclusion by forward differentiation of their
  * gradient; real-space pairs by the pair Hessian blocks; the SPME sum by spreading the
  * tangent charge density, one more convolution and a gather with second-derivative
- * B-splines), pair terms in FP64 whatever `precision` is, on the list of these positions.
+ * B-splines), pair terms at `precision` as for qhp_param_grad, on the list of these
+ * positions.
  * The potential is the truncated one: pairs crossing the cutoff contribute no delta
  * terms. With `dq` [N], `deps` [n_types], `dsig` [n_types] (all three or none), also the
  * mixed derivatives d(dir . grad E)/d(q, epsilon, sigma) of the summed bead energies

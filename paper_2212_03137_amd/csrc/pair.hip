@@ -115,9 +115,14 @@ QHP_DEV void flush(const PairArgs& A, int i, int lane, double gx, double gy, dou
 // d = 1 + a s6, the soft-core term e4 [1/D^2 - 1/D] (D = a + (r/sigma)^6, e4 = 4 eps
 // lambda) is e4 (u^2 - u) with u = s6 / d, and -(dE/dr)/r = 6 e4 u (2u - 1) / (d r^2);
 // a = 0 gives plain LJ.
-template <int P, bool ENERGY, bool PG = false, bool HVP = false, bool SOFT = false>
+// F32 (parameter gradients and Hessian-vector products with FP32 pairs): the displacement
+// and r^2 stay FP64; r, 1/r, erfc(alpha r) (the Hastings form of the FP32 force kernel) and
+// exp(-alpha^2 r^2) are FP32 values; every product and sum after them is FP64.
+template <int P, bool ENERGY, bool PG = false, bool HVP = false, bool SOFT = false,
+          bool F32 = false>
 __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
   static_assert(!SOFT || (!PG && !HVP), "soft-core pairs have forces and energies only");
+  static_assert(!F32 || PG || HVP, "FP32 pair forces have their own kernel");
   constexpr int S = 64 / P;
   __shared__ int sj[WPB][64];
   __shared__ double sq[WPB][64];
@@ -168,10 +173,25 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
       dz -= A.L[2] * rint(dz * A.invL[2]);
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (r2 < A.rc2) {
-        const double r = sqrt(r2), ir = 1.0 / r, ir2 = ir * ir;
+        double r, ir, erfcv, ex2;
+        if constexpr (F32) {
+          const float r2f = (float)r2;
+          const float irf = __builtin_amdgcn_rsqf(r2f), rf = r2f * irf;
+          const float tt = __builtin_amdgcn_rcpf(1.0f + ERFC_P * ((float)A.alpha * rf));
+          float qf = ERFC_Q[7];
+#pragma unroll
+          for (int m = 6; m >= 0; --m) qf = qf * tt + ERFC_Q[m];
+          const float exf = __builtin_amdgcn_exp2f(
+              (float)(-A.alpha * A.alpha * 1.4426950408889634) * r2f);
+          r = (double)rf; ir = (double)irf;
+          ex2 = (double)exf; erfcv = (double)(tt * qf * exf);
+        } else {
+          r = sqrt(r2); ir = 1.0 / r;
+          erfcv = erfc(A.alpha * r); ex2 = exp(-A.alpha * A.alpha * r2);
+        }
+        const double ir2 = ir * ir;
         const double qq = sq[wv][t];
-        const double erfcv = erfc(A.alpha * r);
-        double sc = qq * (erfcv * ir + c2a * exp(-A.alpha * A.alpha * r2)) * ir2;
+        double sc = qq * (erfcv * ir + c2a * ex2) * ir2;
         if (ENERGY) ec += qq * erfcv * ir;
         if (PG) pq += A.coulomb * A.charge[j] * erfcv * ir;
         const double2 lj = slj[wv][t];
@@ -192,7 +212,6 @@ __global__ __launch_bounds__(NT) void k_pair64(PairArgs A) {
         }
         if (HVP) {
           // phi' and phi'' of the pair: -sc r is phi'; phi'' below
-          const double ex2 = exp(-A.alpha * A.alpha * r2);
           double d1 = -sc * r;
           double d2 = qq * (2.0 * erfcv * ir2 * ir + c2a * ex2 * (2.0 * ir2 + 2.0 * A.alpha * A.alpha));
           if (e4 != 0.0) {
@@ -608,8 +627,8 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
   const unsigned nbw = (unsigned)((nlw + 7) / 8 * 8);
   const double Lmin = fmin(c->p.box[0], fmin(c->p.box[1], c->p.box[2]));
   const bool minimg = !(2.0 * (c->p.cutoff + c->p.skin) < Lmin);
-  const bool pg = bs && bs->pgrad;     // parameter gradients: always the FP64 kernel
-  const bool hvp = bs && bs->hvp_u;    // Hessian-vector product: FP64 kernel
+  const bool pg = bs && bs->pgrad;     // parameter gradients: the k_pair64 kernels
+  const bool hvp = bs && bs->hvp_u;    // Hessian-vector product: the k_pair64 kernels
   const bool f32 = c->p.precision == QHP_FP32_PAIRS && !plain && !minimg && !pg && !hvp;
   A.mix = 0;
   if (hvp) { A.u = bs->hvp_u; A.hu = bs->g; A.mix = bs->pgrad; }
@@ -638,6 +657,9 @@ hipError_t launch_pair(qhp_ctx* c, bool energy, int bead, const BeadSet* bs) {
     if (pg || hvp) return hipErrorInvalidValue;     // rejected by the entry points
     QHP_SWITCH_P(P, if (energy) hipLaunchKernelGGL((k_pair64<PP, true, false, false, true>), nb, NT, 0, c->stream, A);
                  else hipLaunchKernelGGL((k_pair64<PP, false, false, false, true>), nb, NT, 0, c->stream, A));
+  } else if (c->p.precision == QHP_FP32_PAIRS && (pg || hvp)) {
+    QHP_SWITCH_P(P, if (hvp) hipLaunchKernelGGL((k_pair64<PP, false, false, true, false, true>), nb, NT, 0, c->stream, A);
+                 else hipLaunchKernelGGL((k_pair64<PP, false, true, false, false, true>), nb, NT, 0, c->stream, A));
   } else {
     QHP_SWITCH_P(P, if (hvp) hipLaunchKernelGGL((k_pair64<PP, false, false, true>), nb, NT, 0, c->stream, A);
                  else if (pg) hipLaunchKernelGGL((k_pair64<PP, false, true>), nb, NT, 0, c->stream, A);

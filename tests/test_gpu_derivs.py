@@ -34,14 +34,17 @@ def test_parameter_gradients_match_the_oracle(which):
     s = _small() if which == "small" else medium_box(P=4)
     say("param grad", which, s.n_atoms, s.n_beads)
     dq_r, de_r, ds_r = derivs.param_gradients(s.pos, s)
-    for prec in (q.FP64, q.FP32_PAIRS):
+    # FP32 pairs: r, 1/r, erfc and the exponential of each pair term are FP32 values
+    # (relative error ~1e-7 each), summed in FP64 over terms of both signs
+    for prec, tol in ((q.FP64, 1e-10), (q.FP32_PAIRS, 1e-5)):
         with ctx_for(s, precision=prec) as c:
             c.set_state(s.pos, s.vel, 0)
             dq, de, ds = c.param_grad(s.pos)
             x, _, _ = c.get_state()
-        assert np.abs(dq - dq_r).max() <= 1e-10 * np.abs(dq_r).max(), prec
-        assert np.allclose(de, de_r, rtol=1e-10, atol=1e-10 * np.abs(de_r).max())
-        assert np.allclose(ds, ds_r, rtol=1e-10, atol=1e-10 * np.abs(ds_r).max())
+        say("param grad", prec, np.abs(dq - dq_r).max() / np.abs(dq_r).max())
+        assert np.abs(dq - dq_r).max() <= tol * np.abs(dq_r).max(), prec
+        assert np.allclose(de, de_r, rtol=tol, atol=tol * np.abs(de_r).max())
+        assert np.allclose(ds, ds_r, rtol=tol, atol=tol * np.abs(ds_r).max())
         # the propagated state is left alone
         assert np.abs(x - s.pos).max() <= 1e-12 * np.abs(s.pos).max()
 
@@ -54,14 +57,15 @@ def test_hessian_vector_products_match_the_oracle(which):
     rng = np.random.default_rng(11)
     u = rng.standard_normal(s.pos.shape)
     ref = derivs.hvp(s.pos, s, u)
-    for prec in (q.FP64, q.FP32_PAIRS):
+    for prec, tol in ((q.FP64, 1e-6), (q.FP32_PAIRS, 1e-5)):
         with ctx_for(s, precision=prec) as c:
             c.set_state(s.pos, s.vel, 0)
             got = c.hvp(s.pos, u)
             x, _, _ = c.get_state()
         # the oracle's central difference carries O(h^2) and rounding errors of ~1e-8
         err = np.abs(got - ref).max() / np.sqrt(np.mean(ref ** 2))
-        assert err <= 1e-6, (prec, err)
+        say("hvp", prec, err)
+        assert err <= tol, (prec, err)
         assert np.abs(x - s.pos).max() <= 1e-12 * np.abs(s.pos).max()
 
 
@@ -173,8 +177,11 @@ def test_mixed_derivatives_match_the_oracle():
     rng = np.random.default_rng(16)
     u = rng.standard_normal(s.pos.shape)
     dq_r, de_r, ds_r = derivs.mixed(s.pos, s, u)
-    with ctx_for(s) as c:
-        _, dq, de, ds = c.hvp(s.pos, u, mixed=True)
-    assert np.abs(dq - dq_r).max() <= 1e-6 * np.abs(dq_r).max()
-    assert np.allclose(de, de_r, rtol=1e-6, atol=1e-8 * np.abs(de_r).max())
-    assert np.allclose(ds, ds_r, rtol=1e-6, atol=1e-8 * np.abs(ds_r).max())
+    import paper_2212_03137_amd as q
+    for prec, tol in ((q.FP64, 1e-6), (q.FP32_PAIRS, 1e-5)):
+        with ctx_for(s, precision=prec) as c:
+            _, dq, de, ds = c.hvp(s.pos, u, mixed=True)
+        say("mixed", prec, np.abs(dq - dq_r).max() / np.abs(dq_r).max())
+        assert np.abs(dq - dq_r).max() <= tol * np.abs(dq_r).max(), prec
+        assert np.allclose(de, de_r, rtol=tol, atol=1e-2 * tol * np.abs(de_r).max())
+        assert np.allclose(ds, ds_r, rtol=tol, atol=1e-2 * tol * np.abs(ds_r).max())
