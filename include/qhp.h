@@ -122,7 +122,9 @@ typedef struct qhp_params {
   double trpmd_c;           /* TRPMD: internal-mode friction max(gamma_0, c * omega_n)   */
   uint64_t seed;            /* Philox-4x64-10 key word 0                                  */
   double qtb_gamma0;        /* adQTB: friction gamma_0                                   */
-  int32_t qtb_nseg;         /* adQTB: segment length N_seg (power of two, 16..1024)      */
+  int32_t qtb_nseg;         /* adQTB: segment length N_seg: 16..1024, a multiple of 8
+                               whose prime factors are 2, 3, 5, 7 (powers of two take
+                               the fastest transforms)                                  */
   double qtb_adapt_rate;    /* adQTB: SIMPLE rate A_gamma (same for every type)          */
   double qtb_gamma_min_frac;/* adQTB: gamma_min = frac * gamma_0 (paper default 0.01)    */
   int32_t qtb_classical;    /* adQTB test switch: Theta(omega) = kT (white-noise limit)  */

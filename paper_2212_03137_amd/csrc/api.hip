@@ -274,8 +274,13 @@ int validate(const qhp_params* p, std::string& why) {
   }
   if (p->thermostat == QHP_ADQTB) {
     if (p->n_beads != 1) return bad("adQTB requires n_beads = 1");
-    if (!pow2(p->qtb_nseg) || p->qtb_nseg < 16 || p->qtb_nseg > 1024)
-      return bad("qtb_nseg must be a power of two in 16..1024");
+    // 16..1024, a multiple of 8 (the segment record keeps eight steps together) with no
+    // prime factor above 7 (the transforms' radices)
+    int rest = p->qtb_nseg;
+    for (int f : {2, 3, 5, 7})
+      while (rest > 1 && rest % f == 0) rest /= f;
+    if (p->qtb_nseg < 16 || p->qtb_nseg > 1024 || p->qtb_nseg % 8 || rest != 1)
+      return bad("qtb_nseg must be a multiple of 8 in 16..1024 with prime factors 2, 3, 5, 7");
     if (!(p->qtb_gamma0 > 0) || !(p->qtb_gamma_min_frac >= 0)) return bad("qtb gamma");
     double tmass[QHP_MAX_TYPES];
     bool seen[QHP_MAX_TYPES] = {};

@@ -26,38 +26,70 @@ QHP_DEV double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Single-block Stockham FFT of runtime length L (power of two) between two LDS buffers.
+// One Stockham stage of radix R (Ns = product of the earlier radices): butterfly j takes
+// a[j + r L/R], r = 0..R-1, multiplies operand r by w^(r k L/(Ns R)), k = j mod Ns, takes
+// their DFT of length R and writes it to b[(j / Ns) Ns R + k + q Ns] (natural order after
+// the last stage). w^m = tw[m] = exp(-2 pi i m / L); the DFT of length R uses the same
+// table at multiples of L/R (R = 3, 5, 7: the direct sum).
+template <int R>
+QHP_DEV void rt_stage(const double2* a, double2* b, int L, int Ns, bool inv, const double2* tw) {
+  const int nb = L / R;
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+    const int k = j % Ns;
+    double2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[r] = a[j + r * nb];
+      if (r) {
+        double2 t = tw[r * k * (L / (Ns * R))];
+        if (inv) t.y = -t.y;
+        v[r] = cmul(v[r], t);
+      }
+    }
+    const int idx = (j / Ns) * Ns * R + k;
+    if constexpr (R == 4) {
+      const double2 t0 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+      const double2 t1 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+      const double2 t2 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+      const double2 t3 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+      const double2 jt3 = inv ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
+      b[idx] = make_double2(t0.x + t2.x, t0.y + t2.y);
+      b[idx + 2 * Ns] = make_double2(t0.x - t2.x, t0.y - t2.y);
+      b[idx + Ns] = make_double2(t1.x + jt3.x, t1.y + jt3.y);
+      b[idx + 3 * Ns] = make_double2(t1.x - jt3.x, t1.y - jt3.y);
+    } else if constexpr (R == 2) {
+      b[idx] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
+      b[idx + Ns] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double2 acc = v[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          double2 w = tw[((q * r) % R) * nb];
+          if (inv) w.y = -w.y;
+          const double2 u = cmul(v[r], w);
+          acc.x += u.x; acc.y += u.y;
+        }
+        b[idx + q * Ns] = acc;
+      }
+    }
+  }
+}
+
+// Single-block Stockham FFT of runtime length L between two LDS buffers: radix 4 while
+// four divides what is left, then 2, 3, 5 and 7 (L must have no other prime factor).
 // tw[m] = exp(-2 pi i m / L). Returns the buffer holding the result.
 QHP_DEV double2* fft_rt(double2* a, double2* b, int L, bool inv, const double2* tw) {
   for (int Ns = 1; Ns < L;) {
-    const int R = (L / Ns >= 4) ? 4 : 2;
-    const int nb = L / R;
-    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-      const int k = j % Ns;
-      double2 v[4];
-      for (int r = 0; r < R; ++r) {
-        v[r] = a[j + r * nb];
-        if (r) {
-          double2 t = tw[r * k * (L / (Ns * R))];
-          if (inv) t.y = -t.y;
-          v[r] = cmul(v[r], t);
-        }
-      }
-      const int idx = (j / Ns) * Ns * R + k;
-      if (R == 4) {
-        const double2 t0 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
-        const double2 t1 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
-        const double2 t2 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
-        const double2 t3 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
-        const double2 jt3 = inv ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
-        b[idx] = make_double2(t0.x + t2.x, t0.y + t2.y);
-        b[idx + 2 * Ns] = make_double2(t0.x - t2.x, t0.y - t2.y);
-        b[idx + Ns] = make_double2(t1.x + jt3.x, t1.y + jt3.y);
-        b[idx + 3 * Ns] = make_double2(t1.x - jt3.x, t1.y - jt3.y);
-      } else {
-        b[idx] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
-        b[idx + Ns] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
-      }
+    const int left = L / Ns;
+    const int R = left % 4 == 0 ? 4 : left % 2 == 0 ? 2 : left % 3 == 0 ? 3 : left % 5 == 0 ? 5 : 7;
+    switch (R) {
+      case 4: rt_stage<4>(a, b, L, Ns, inv, tw); break;
+      case 2: rt_stage<2>(a, b, L, Ns, inv, tw); break;
+      case 3: rt_stage<3>(a, b, L, Ns, inv, tw); break;
+      case 5: rt_stage<5>(a, b, L, Ns, inv, tw); break;
+      default: rt_stage<7>(a, b, L, Ns, inv, tw); break;
     }
     __syncthreads();
     double2* t = a; a = b; b = t;
@@ -301,6 +333,47 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
+// N_seg that is not a power of two (any multiple of 8 with no prime factor above 7): the
+// same convolution, one atom per block, between two dynamic LDS buffers of 4 N_seg with the
+// runtime mixed-radix transform. The z Gaussians are drawn again for the second series.
+__global__ __launch_bounds__(NT) void k_qtb_generate_rt(GenArgs A) {
+  extern __shared__ double2 lds[];
+  const int NS = A.nseg, L4 = 4 * NS;
+  double2* a = lds;
+  double2* b = lds + L4;
+  const int at = blockIdx.x, tid = threadIdx.x;
+  const uint64_t c0 = (uint64_t)(A.seg * NS);   // counter of window sample 0
+  const double2* Hz = A.hhat + (size_t)A.type[at] * L4;
+  const double inv = 1.0 / L4;
+  for (int slot = 0; slot < 2; ++slot) {
+    for (int l = tid; l < L4; l += NT) {
+      double2 w = make_double2(0.0, 0.0);
+      if (l < 3 * NS) {
+        double gs[3];
+        qhp::gauss3(A.seed, qhp::STREAM_QTB_WHITE, c0 + (uint64_t)l, (uint64_t)at, 0ull, gs);
+        w = slot == 0 ? make_double2(gs[0], gs[1]) : make_double2(gs[2], 0.0);
+      }
+      a[l] = w;
+    }
+    __syncthreads();
+    double2* X = fft_rt(a, b, L4, false, A.tw4);
+    double2* Y = X == a ? b : a;
+    for (int l = tid; l < L4; l += NT) X[l] = cmul(X[l], Hz[l]);
+    __syncthreads();
+    double2* f = fft_rt(X, Y, L4, true, A.tw4);
+    for (int t = tid; t < NS; t += NT) {
+      const double2 v = f[NS + t];
+      if (slot == 0) {
+        A.noise[qhp::qtb_rec(t, 0, at, A.N)] = v.x * inv;
+        A.noise[qhp::qtb_rec(t, 1, at, A.N)] = v.y * inv;
+      } else {
+        A.noise[qhp::qtb_rec(t, 2, at, A.N)] = v.x * inv;
+      }
+    }
+    __syncthreads();                  // the buffers are read before they are refilled
+  }
+}
+
 struct SpecArgs {
   int N, nseg, ntypes;
   int z0;                 // the launch accumulates types z0 .. z0 + ntypes - 1 only
@@ -375,6 +448,64 @@ __global__ __launch_bounds__(NTH) void k_qtb_spectra(SpecArgs A) {
   __syncthreads();
   const size_t o = (size_t)A.z0 * (NS + 1);
   for (int k = tid; k < nk; k += NTH) {
+    if (acc[k] != 0.0) atomicAdd(A.dsum + o + k, acc[k]);
+    if (A.ratio) {
+      if (avv[k] != 0.0) atomicAdd(A.vvsum + o + k, avv[k]);
+      if (avf[k] != 0.0) atomicAdd(A.vfsum + o + k, avf[k]);
+    }
+  }
+}
+
+// Spectra for N_seg that is not a power of two: as k_qtb_spectra, with two dynamic LDS
+// buffers of 2 N_seg and the runtime mixed-radix transform; the accumulators follow them.
+__global__ __launch_bounds__(NT) void k_qtb_spectra_rt(SpecArgs A) {
+  extern __shared__ double2 lds[];
+  const int NS = A.nseg, L2 = 2 * NS, tid = threadIdx.x;
+  double2* a = lds;
+  double2* b = lds + L2;
+  double* acc = reinterpret_cast<double*>(lds + 2 * L2);   // [types][NS+1] Delta; C_vv; Re C_vF
+  const int nk = A.ntypes * (NS + 1);
+  double* avv = acc + nk;
+  double* avf = avv + nk;
+  for (int k = tid; k < (A.ratio ? 3 : 1) * nk; k += NT) acc[k] = 0.0;
+  __syncthreads();
+  const double sc = A.dt / NS;
+  const int atoms_per_block = (A.N + gridDim.x - 1) / gridDim.x;
+  const int a0 = blockIdx.x * atoms_per_block, a1 = min(A.N, a0 + atoms_per_block);
+  for (int at = a0; at < a1; ++at) {
+    const int ty = A.type[at] - A.z0;
+    if (ty < 0 || ty >= A.ntypes) continue;            // another launch's type (uniform)
+    const double m = A.mass[at];
+    const double* gz = A.gamma + (size_t)(ty + A.z0) * (NS + 1);
+    for (int d = 0; d < 3; ++d) {
+      for (int t = tid; t < L2; t += NT) {
+        double2 z = make_double2(0.0, 0.0);
+        if (t < NS) {
+          const size_t r = qhp::qtb_rec(t, d, at, A.N);
+          z = make_double2(A.vrec[r], A.noise[r]);
+        }
+        a[t] = z;
+      }
+      __syncthreads();
+      const double2* Z = fft_rt(a, b, L2, false, A.tw2);
+      for (int k = tid; k <= NS; k += NT) {
+        const double2 zk = Z[k], zm = Z[(L2 - k) % L2];
+        const double vr = 0.5 * (zk.x + zm.x), vi = 0.5 * (zk.y - zm.y);
+        const double fr = 0.5 * (zk.y + zm.y), fi = -0.5 * (zk.x - zm.x);
+        const double cvv = sc * (vr * vr + vi * vi);
+        const double cvf = sc * (vr * fr + vi * fi);
+        acc[ty * (NS + 1) + k] += m * gz[k] * cvv - cvf;
+        if (A.ratio) {
+          avv[ty * (NS + 1) + k] += cvv;
+          avf[ty * (NS + 1) + k] += cvf;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  const size_t o = (size_t)A.z0 * (NS + 1);
+  for (int k = tid; k < nk; k += NT) {
     if (acc[k] != 0.0) atomicAdd(A.dsum + o + k, acc[k]);
     if (A.ratio) {
       if (avv[k] != 0.0) atomicAdd(A.vvsum + o + k, avv[k]);
@@ -462,8 +593,13 @@ hipError_t launch_qtb_generate(qhp_ctx* c, int64_t seg) {
   GenArgs A;
   A.N = c->N; A.nseg = q.nseg; A.seed = c->p.seed; A.seg = seg; A.type = c->d_type;
   A.hhat = q.hhat; A.tw4 = q.tw4; A.noise = q.noise_t;
-  QHP_SWITCH_NSEG(q.nseg, hipLaunchKernelGGL((k_qtb_generate<4 * SS, seg_threads<4 * SS>()>),
-                                             c->N, seg_threads<4 * SS>(), 0, c->stream, A));
+  if (q.nseg & (q.nseg - 1)) {
+    hipLaunchKernelGGL(k_qtb_generate_rt, c->N, NT, (size_t)8 * q.nseg * sizeof(double2),
+                       c->stream, A);
+  } else {
+    QHP_SWITCH_NSEG(q.nseg, hipLaunchKernelGGL((k_qtb_generate<4 * SS, seg_threads<4 * SS>()>),
+                                               c->N, seg_threads<4 * SS>(), 0, c->stream, A));
+  }
   // the per-step copy (the segment kernels keep theirs for the spectra)
   const dim3 tg((c->N + 63) / 64, q.nseg / 8);
   hipLaunchKernelGGL(k_qtb_transpose<false>, tg, 256, 0, c->stream, q.noise_t, q.noise, c->N);
@@ -486,15 +622,21 @@ hipError_t launch_qtb_adapt(qhp_ctx* c) {
   // dynamic LDS next to the transform: types that do not fit together are accumulated by
   // further launches (each skips the others' atoms)
   const int nb = std::max(1, std::min(c->N, 4096));
-  const size_t fft_lds = (size_t)(2 * q.nseg + 64) * sizeof(double2);
+  const bool rt = (q.nseg & (q.nseg - 1)) != 0;        // not a power of two
+  const size_t fft_lds = rt ? (size_t)4 * q.nseg * sizeof(double2)
+                            : (size_t)(2 * q.nseg + 64) * sizeof(double2);
   const size_t per_type = (size_t)(A.ratio ? 3 : 1) * (q.nseg + 1) * sizeof(double);
   const int fit = (int)std::max<size_t>(1, (QTB_LDS_MAX / 2 - fft_lds) / per_type);
   for (int z0 = 0; z0 < c->p.n_types; z0 += fit) {
     A.z0 = z0;
     A.ntypes = std::min(fit, c->p.n_types - z0);
-    QHP_SWITCH_NSEG(q.nseg, hipLaunchKernelGGL((k_qtb_spectra<2 * SS, seg_threads<2 * SS>()>), nb,
-                                               seg_threads<2 * SS>(), A.ntypes * per_type,
-                                               c->stream, A));
+    if (rt) {
+      hipLaunchKernelGGL(k_qtb_spectra_rt, nb, NT, fft_lds + A.ntypes * per_type, c->stream, A);
+    } else {
+      QHP_SWITCH_NSEG(q.nseg, hipLaunchKernelGGL((k_qtb_spectra<2 * SS, seg_threads<2 * SS>()>), nb,
+                                                 seg_threads<2 * SS>(), A.ntypes * per_type,
+                                                 c->stream, A));
+    }
   }
   AdaptArgs D;
   D.n = c->p.n_types * (q.nseg + 1); D.nseg = q.nseg; D.any_ratio = A.ratio;

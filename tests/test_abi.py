@@ -85,3 +85,21 @@ def test_per_type_adaptation_validated_before_device_use(change, code):
         assert code is None
     with pytest.raises(ValueError):
         q.Context.from_system(s, thermostat=q.ADQTB, qtb_tau_of=[1.0])
+
+
+@pytest.mark.parametrize("nseg,ok", [(8, False), (20, False), (88, False), (2048, False),
+                                     (24, True), (120, True), (1000, True), (1024, True)])
+def test_segment_lengths_validated_before_device_use(nseg, ok):
+    # N_seg: 16..1024, a multiple of 8, prime factors 2, 3, 5, 7 only (88 = 8 x 11 is not)
+    import paper_2212_03137_amd as q
+    if not os.path.exists(q.LIB_PATH):
+        pytest.skip("libqhp.so not built")
+    s = synth.water_box(27, 1, 12.0, seed=9, cutoff=5.5, ewald_alpha=0.4, pme_grid=16,
+                        pme_order=4, qtb_gamma0=0.02, qtb_nseg=nseg, qtb_adapt_rate=1e-3)
+    try:
+        c = q.Context.from_system(s, thermostat=q.ADQTB)
+    except q.QhpError as e:
+        assert e.code == (q.EDEVICE if ok else q.EINVAL), e.code
+    else:
+        c.close()
+        assert ok

@@ -29,8 +29,9 @@ def _oracle(s, classical=False):
     return Q
 
 
-@pytest.mark.parametrize("nseg", [16, 64, 256])
+@pytest.mark.parametrize("nseg", [16, 64, 256, 24, 40, 56, 120, 1000])
 def test_first_noise_segment(nseg):
+    # powers of two and segment lengths with factors 3, 5 and 7 (mixed-radix transforms)
     s = _system(nseg)
     print("qtb segment", nseg, flush=True)
     Q = _oracle(s)
@@ -57,14 +58,16 @@ def test_classical_limit_trajectory_matches_oracle():
     assert np.abs(v - vr).max() / np.abs(vr).max() < 1e-7
 
 
-def test_adaptation_over_segments_matches_oracle():
-    s = _system(64, rate=5e-3)
+@pytest.mark.parametrize("nseg", [64, 120])
+def test_adaptation_over_segments_matches_oracle(nseg):
+    s = _system(nseg, rate=5e-3)
+    print("qtb adaptation", nseg, flush=True)
     Q = _oracle(s)
     with _ctx(s) as c:
         c.set_state(s.pos, s.vel, 0)
         for seg in range(3):
-            Q.step(64)
-            c.step(64)
+            Q.step(nseg)
+            c.step(nseg)
             g, d = c.qtb_gamma(), c.qtb_delta()
             scale = np.abs(Q.last_delta).max()
             assert np.abs(d - Q.last_delta).max() <= 1e-7 * scale, seg
@@ -149,9 +152,11 @@ def test_state_must_start_on_a_segment_boundary():
             c.set_state(s.pos, s.vel, 5)
 
 
-def test_ratio_adaptation_over_segments_matches_oracle():
+@pytest.mark.parametrize("nseg", [64, 56])
+def test_ratio_adaptation_over_segments_matches_oracle(nseg):
     import paper_2212_03137_amd as q
-    s = _system(64)
+    s = _system(nseg)
+    print("qtb ratio", nseg, flush=True)
     tau = 150.0
     Q = oq.QTB(s.mass, s.types, s.n_types, s.kT, s.hbar, s.dt, s.qtb_gamma0, s.qtb_nseg,
                s.qtb_adapt_rate, s.qtb_gamma_min_frac, s.seed, oracle_grad_fn(s),
@@ -160,8 +165,8 @@ def test_ratio_adaptation_over_segments_matches_oracle():
     with _ctx(s, qtb_adapt_scheme=q.QTB_RATIO, qtb_tau=tau) as c:
         c.set_state(s.pos, s.vel, 0)
         for seg in range(3):
-            Q.step(64)
-            c.step(64)
+            Q.step(nseg)
+            c.step(nseg)
             g = c.qtb_gamma()
             assert np.abs(g - Q.gamma).max() <= 1e-7 * np.abs(Q.gamma).max(), seg
             assert np.abs(c.qtb_noise() - Q.noise).max() <= 1e-6 * np.abs(Q.noise).max()
