@@ -371,7 +371,13 @@ QHP_DEV void chunk(const PairArgs& A, const float4* scd, const float2* slj, cons
 template <bool SOFT, int W, int PF>
 __global__ __launch_bounds__(64 * W) void k_pair32_one(PairArgs A) {
   __shared__ float4 stab[QHP_PAIR_TAB];
+  __shared__ float2 sljt[QHP_MAX_TYPES * QHP_MAX_TYPES];   // (4 eps, sigma^6) per type pair
+  __shared__ float slja[SOFT ? QHP_MAX_TYPES * QHP_MAX_TYPES : 1];
   for (int k = threadIdx.x; k < QHP_PAIR_TAB; k += 64 * W) stab[k] = A.tab[k];
+  for (int k = threadIdx.x; k < A.ntypes * A.ntypes; k += 64 * W) {
+    sljt[k] = make_float2((float)A.lj_e4[k], (float)A.lj_s6[k]);
+    if (SOFT) slja[k] = (float)A.lj_a[k];
+  }
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -433,8 +439,8 @@ __global__ __launch_bounds__(64 * W) void k_pair32_one(PairArgs A) {
       const float cz = (float)((c.z - ci.z) + A.L[2] * (double)((int)((ec0 >> 30) & 3) - 1));
       if (cx * cx + cy * cy + cz * cz < reach2) {
         const int tp = ti * A.ntypes + tt;
-        const float2 ljv = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
-        const float av = SOFT ? (float)A.lj_a[tp] : 0.f;
+        const float2 ljv = sljt[tp];
+        const float av = SOFT ? slja[tp] : 0.f;
         float fx = 0.f, fy = 0.f, fz = 0.f;
         interact32<false, true, SOFT>(K, make_float4(cx, cy, cz, (float)(qi * qq)),
                                       make_float4(0.f, 0.f, 0.f, 0.f), ljv, av, fx, fy, fz,
@@ -455,7 +461,13 @@ __global__ __launch_bounds__(64 * W) void k_pair32(PairArgs A) {
   __shared__ float ssa[SOFT ? W : 1][SOFT ? 64 : 1];   // soft-core alpha (1 - lambda)
   __shared__ unsigned sj[W][64];    // byte offset of atom j's bead-0 FP32 offset
   __shared__ float4 stab[(ENERGY ? 2 : 1) * QHP_PAIR_TAB];   // kernel tables
+  __shared__ float2 sljt[QHP_MAX_TYPES * QHP_MAX_TYPES];   // (4 eps, sigma^6) per type pair
+  __shared__ float slja[SOFT ? QHP_MAX_TYPES * QHP_MAX_TYPES : 1];
   for (int k = threadIdx.x; k < (ENERGY ? 2 : 1) * QHP_PAIR_TAB; k += 64 * W) stab[k] = A.tab[k];
+  for (int k = threadIdx.x; k < A.ntypes * A.ntypes; k += 64 * W) {
+    sljt[k] = make_float2((float)A.lj_e4[k], (float)A.lj_s6[k]);
+    if (SOFT) slja[k] = (float)A.lj_a[k];
+  }
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, s = lane / P, b = lane % P;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -524,8 +536,8 @@ __global__ __launch_bounds__(64 * W) void k_pair32(PairArgs A) {
       keep = cx * cx + cy * cy + cz * cz < reach * reach;
       cdv = make_float4(cx, cy, cz, (float)(qi * qj_p));
       const int tp = ti * A.ntypes + tj_p;
-      ljv = make_float2((float)A.lj_e4[tp], (float)A.lj_s6[tp]);
-      if (SOFT) av = (float)A.lj_a[tp];
+      ljv = sljt[tp];
+      if (SOFT) av = slja[tp];
       haslj = ljv.x != 0.f;
       jp = (unsigned)j * (unsigned)(P * sizeof(float4));
     }
