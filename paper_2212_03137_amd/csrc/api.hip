@@ -456,7 +456,7 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   c->Ps = next_pow2(c->Psb);          // lanes of the contracted set (phantoms as above)
   c->nalt = p->respa_nalt > 0 ? p->respa_nalt : 1;
   c->respa = c->Psb < Pb || c->nalt > 1;
-  c->pack_qt = p->exec != QHP_PLAIN && !c->respa && P == 1;
+  c->pack_qt = p->exec != QHP_PLAIN && !c->respa;
   if (c->respa) {
     const int Ps = c->Ps;
     TRY(dalloc(&c->xs, (size_t)3 * N * Ps)); TRY(dalloc(&c->gs, (size_t)3 * N * Ps));

@@ -34,7 +34,7 @@ struct NlArgs {
   NlCtrl* ctrl;
   const double4* bmax;
   int n_bmax;
-  const double* charge; const int* type; int pack_qt;   // one-bead records: see qhp_internal.h
+  const double* charge; const int* type; int pack_qt;   // packed records: see qhp_internal.h
 };
 
 __global__ __launch_bounds__(256) void k_nl_check(NlArgs A, int force) {
@@ -86,7 +86,7 @@ __global__ void k_nl_assign(NlArgs A) {
   A.cref[a] = c;
   const double4 w = make_double4(wrapped(c.x, A.L0, A.iL0), wrapped(c.y, A.L1, A.iL1),
                                  wrapped(c.z, A.L2, A.iL2), c.w);
-  A.cwrap[a] = A.pack_qt ? make_double4(w.x, w.y, w.z, qhp::pack_charge_type(A.charge[a], A.type[a])) : w;
+  A.cwrap[a] = A.pack_qt ? make_double4(w.x, w.y, w.z, qhp::pack_record(A.charge[a], A.type[a], c.w)) : w;
   A.coff[a] = make_double4(c.x - w.x, c.y - w.y, c.z - w.z, 0.0);
   atomicAdd(&A.cell_count[id], 1);
 }
@@ -417,7 +417,7 @@ QHP_DEV void nl_build_cell(const NlArgs& A, const int cell) {
     A.cref[i] = c;
     const double4 w = make_double4(wrapped(c.x, A.L0, A.iL0), wrapped(c.y, A.L1, A.iL1),
                                    wrapped(c.z, A.L2, A.iL2), c.w);
-    A.cwrap[i] = A.pack_qt ? make_double4(w.x, w.y, w.z, qhp::pack_charge_type(A.charge[i], A.type[i])) : w;
+    A.cwrap[i] = A.pack_qt ? make_double4(w.x, w.y, w.z, qhp::pack_record(A.charge[i], A.type[i], c.w)) : w;
     A.coff[i] = make_double4(c.x - w.x, c.y - w.y, c.z - w.z, 0.0);
   }
   for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));

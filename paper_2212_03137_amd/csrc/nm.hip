@@ -26,7 +26,7 @@ struct NmArgs {
   const double* T; const double* cc; const double* csw; const double* cws;
   const double* c1; const double* c2;
   const double* mass; const double* sqrt_mkT; const double* charge;
-  const int* type; int pack_qt;   // one-bead centroid records: charge and type in w
+  const int* type; int pack_qt;   // packed centroid records: charge, type and spread in w
   double4* cent; const double4* cref; const double4* coff; double4* cwrap; float4* xf;
   NlCtrl* ctrl;
   double4* bmax;
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_nm_step(NmArgs A) {
     qhp::write_bins(A.bins, a, cen[0], cen[1], cen[2]);
     const double4 o = A.coff[a];
     A.cwrap[a] = make_double4(cen[0] - o.x, cen[1] - o.y, cen[2] - o.z,
-                              A.pack_qt ? qhp::pack_charge_type(A.charge[a], A.type[a]) : adb);
+                              A.pack_qt ? qhp::pack_record(A.charge[a], A.type[a], adb) : adb);
     const double4 r = A.cref[a];
     const double ex = cen[0] - r.x, ey = cen[1] - r.y, ez = cen[2] - r.z;
     dc2 = ex * ex + ey * ey + ez * ez;

@@ -65,7 +65,7 @@ struct PairArgs {
   float tab_scale;        // intervals per A^2 of r^2 (fl(r2 tab_scale) < QHP_PAIR_TAB in range)
   int tab_kmin;           // first interval the tables are used for (closer: the formula)
   int nblocks;            // logical blocks
-  int pack_qt;            // centroid records carry charge and type (one-bead contexts)
+  int pack_qt;            // centroid records carry charge, type and spread (see qhp_internal.h)
   const NlCtrl* ctrl;     // max_db: largest bead-centroid distance this step
   double* energy;         // [P][NTERMS] (plain: the bead's row)
 };
@@ -485,7 +485,8 @@ __global__ __launch_bounds__(64 * W) void k_pair32(PairArgs A) {
   // no bead of a pair whose centroids are further apart than rc + d_i + d_j can be within
   // the cutoff, d = an atom's largest bead-centroid distance this step (kept in the w of
   // its centroid record); small margin for the FP32 rounding of the difference
-  const double reach_i = sqrt(A.rc2) + (P == 1 ? 0.0 : ci.w) + 1e-3;   // one bead: w is no spread
+  const double di = P == 1 ? 0.0 : (A.pack_qt ? (double)qhp::packed_spread(ci.w) : ci.w);
+  const double reach_i = sqrt(A.rc2) + di + 1e-3;
   const int nn = A.nnbr[i];
   const int* row = A.nbr + (size_t)i * A.cap;
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
@@ -527,12 +528,16 @@ __global__ __launch_bounds__(64 * W) void k_pair32(PairArgs A) {
     if (k0 + lane < nn) {
       const unsigned e = e_cur;
       const int j = e & 0x3FFFFFF;
-      if constexpr (P != 1) { cj_p = A.cwrap[j]; qj_p = A.charge[j]; tj_p = A.type[j]; }
+      if constexpr (P != 1) {
+        cj_p = A.cwrap[j];
+        if (A.pack_qt) { qj_p = (double)qhp::packed_charge(cj_p.w); tj_p = qhp::packed_type(cj_p.w); }
+        else { qj_p = A.charge[j]; tj_p = A.type[j]; }
+      }
       const double4 cj = cj_p;
       const float cx = (float)((cj.x - ci.x) + A.L[0] * (double)((int)((e >> 26) & 3) - 1));
       const float cy = (float)((cj.y - ci.y) + A.L[1] * (double)((int)((e >> 28) & 3) - 1));
       const float cz = (float)((cj.z - ci.z) + A.L[2] * (double)((int)((e >> 30) & 3) - 1));
-      const float reach = (float)(reach_i + (P == 1 ? 0.0 : cj.w));
+      const float reach = (float)(reach_i + (P == 1 ? 0.0 : (A.pack_qt ? (double)qhp::packed_spread(cj.w) : cj.w)));
       keep = cx * cx + cy * cy + cz * cz < reach * reach;
       cdv = make_float4(cx, cy, cz, (float)(qi * qj_p));
       const int tp = ti * A.ntypes + tj_p;

@@ -187,7 +187,7 @@ struct qhp_ctx {
 
   // multiple time stepping and ring-polymer contraction
   bool respa = false;         // rpc_beads < P or respa_nalt > 1
-  bool pack_qt = false;       // centroid records carry charge and type (one-bead pairs)
+  bool pack_qt = false;       // centroid records carry charge, type and spread (no contraction)
   int Ps = 0, nalt = 1;       // contracted bead lanes (a power of two), inner steps per outer step
   int Psb = 0;                // contracted beads (<= Ps; the rest are phantoms)
   double* xs = nullptr;       // [3][N][Ps] contracted beads
@@ -424,13 +424,19 @@ QHP_DEV double grid_coord(double x, double KoL, int K) {
   const double u = x * KoL;
   return u - (double)K * floor(u * ldexp(1.0, -__builtin_ctz((unsigned)K)));
 }
-// Contexts whose pair kernel runs on one bead lane (P = 1, no contraction): the w of a
-// centroid record, otherwise the atom's largest bead-centroid distance (always zero with
-// one bead), carries the atom's charge as FP32 and its type, so that the pair kernel reads
-// one 32-byte record per neighbour. Only moved, never computed with.
-QHP_DEV double pack_charge_type(double q, int t) { return __hiloint2double(t, __float_as_int((float)q)); }
+// Packed centroid records (FP32-pair contexts without contraction): the w of a centroid
+// record, otherwise the atom's largest bead-centroid distance d, carries the atom's charge
+// as FP32 (low word) and, in the high word, d as FP32 rounded up to a multiple of 8 ulp
+// with the type (0..7) in those three low bits, so that the pair kernel reads one 32-byte
+// record per neighbour. d only widens the pair reach (rounding it up keeps the test
+// conservative); the charge and type are only moved.
+QHP_DEV double pack_record(double q, int t, double d) {
+  const unsigned db = (__float_as_uint(__double2float_ru(d)) + 7u) & ~7u;
+  return __hiloint2double((int)(db | (unsigned)t), __float_as_int((float)q));
+}
 QHP_DEV float packed_charge(double w) { return __int_as_float(__double2loint(w)); }
-QHP_DEV int packed_type(double w) { return __double2hiint(w); }
+QHP_DEV int packed_type(double w) { return __double2hiint(w) & 7; }
+QHP_DEV float packed_spread(double w) { return __uint_as_float((unsigned)__double2hiint(w) & ~7u); }
 QHP_DEV int base_of(double x, double KoL, int K) {
   const double fl = floor(grid_coord(x, KoL, K));
   return isfinite(fl) ? min(max((int)fl, 0), K) : 0;
