@@ -36,6 +36,9 @@ constexpr int WPB = NT / 64;      // atoms (wavefronts) per block
 #ifndef QHP_PAIR_PF
 #define QHP_PAIR_PF 1
 #endif
+#ifndef QHP_ONE_ACC
+#define QHP_ONE_ACC 8
+#endif
 
 // p = 0.418649012, max relative error of exp(x^2) erfc(x) on [0, 6]: 2.94e-08
 constexpr float ERFC_P = 0.418649012f;
@@ -412,7 +415,10 @@ __global__ __launch_bounds__(64 * W) void k_pair32_one(PairArgs A) {
       if (!A.pack_qt) { qj[p] = A.charge[j]; tj[p] = A.type[j]; }
     }
   }
+  // each lane sums its forces in FP32 over QHP_ONE_ACC chunks (one interaction each), then
+  // in FP64
   double gx = 0, gy = 0, gz = 0, ec = 0, elj = 0;
+  float fx = 0.f, fy = 0.f, fz = 0.f;
   for (int k0 = 0; k0 < nn; k0 += 64) {
     const unsigned ec0 = e[0];
     const double4 c = cj[0];
@@ -441,14 +447,17 @@ __global__ __launch_bounds__(64 * W) void k_pair32_one(PairArgs A) {
         const int tp = ti * A.ntypes + tt;
         const float2 ljv = sljt[tp];
         const float av = SOFT ? slja[tp] : 0.f;
-        float fx = 0.f, fy = 0.f, fz = 0.f;
         interact32<false, true, SOFT>(K, make_float4(cx, cy, cz, (float)(qi * qq)),
                                       make_float4(0.f, 0.f, 0.f, 0.f), ljv, av, fx, fy, fz,
                                       ec, elj);
-        gx += (double)fx; gy += (double)fy; gz += (double)fz;
       }
     }
+    if (((k0 >> 6) & (QHP_ONE_ACC - 1)) == QHP_ONE_ACC - 1) {    // same chunk for every lane
+      gx += (double)fx; gy += (double)fy; gz += (double)fz;
+      fx = fy = fz = 0.f;
+    }
   }
+  gx += (double)fx; gy += (double)fy; gz += (double)fz;
   flush<1, false>(A, i, lane, gx, gy, gz, ec, elj);
 }
 
