@@ -218,10 +218,23 @@ int validate(const qhp_params* p, std::string& why) {
     why = "pme_order must be 4, 5, 6 or 8";
     return p->pme_order >= 3 && p->pme_order <= 8 ? QHP_EUNSUPPORTED : QHP_EINVAL;
   }
+  bool grid_pow2 = true;
   for (int d = 0; d < 3; ++d) {
     const int K = p->pme_grid[d];
-    if (!pow2(K) || K < 8 || K > 128) return bad("pme_grid must be powers of two in 8..128");
+    // powers of two, or multiples of 8 (the spreading tiles the atoms are binned in) whose
+    // prime factors are 2, 3, 5 and 7 (the radices of the plain path's transforms)
+    int rest = K;
+    for (int f : {2, 3, 5, 7})
+      while (rest > 1 && rest % f == 0) rest /= f;
+    if (K < 8 || K > 128 || !(pow2(K) || (K % 8 == 0 && rest == 1)))
+      return bad("pme_grid must be in 8..128: powers of two, or multiples of 8 with prime "
+                 "factors 2, 3, 5, 7");
     if (K < 2 * p->pme_order) return bad("pme_grid must be >= 2 * pme_order");
+    grid_pow2 = grid_pow2 && pow2(K);
+  }
+  if (!grid_pow2 && p->exec == QHP_PLAIN) {
+    why = "SPME grids that are not powers of two need exec = QHP_BATCHED";
+    return QHP_EUNSUPPORTED;
   }
   if (p->precision != QHP_FP64 && p->precision != QHP_FP32_PAIRS) return bad("precision");
   if (p->exec != QHP_BATCHED && p->exec != QHP_PLAIN) return bad("exec");
@@ -366,9 +379,10 @@ extern "C" int qhp_create(const qhp_params* p, void* stream, qhp_ctx** out) {
   c->sigma.assign(p->lj_sigma, p->lj_sigma + p->n_types);
   c->eps.assign(p->lj_epsilon, p->lj_epsilon + p->n_types);
   for (int d = 0; d < 3; ++d) c->K[d] = p->pme_grid[d];
+  c->spme_generic = !(pow2(c->K[0]) && pow2(c->K[1]) && pow2(c->K[2]));
   const bool plain = p->exec == QHP_PLAIN;
   const int Pc_grid = plain ? 1 : c->Pc;
-  {
+  if (!c->spme_generic) {
     // every FFT pass must split into whole blocks, for the beads and the contracted beads
     const int ps = p->rpc_beads > 0 ? next_pow2(p->rpc_beads) : P;
     const int pcs[2] = {Pc_grid, ps == 1 ? 1 : ps / 2};
@@ -1009,6 +1023,8 @@ extern "C" int qhp_param_grad(qhp_ctx* c, const double* pos, double* dq, double*
     return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients with the test tether");
   if (c->Pb != c->P)
     return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients need a power-of-two bead count");
+  if (c->spme_generic)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients need power-of-two SPME grid edges");
   auto run = [&]() -> int {
     int r = copy_in(c, pos, mem_kind, c->x);
     if (r) return r;
@@ -1052,6 +1068,8 @@ extern "C" int qhp_hvp(qhp_ctx* c, const double* pos, const double* dir, double*
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products with the test tether");
   if (c->Pb != c->P)
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products need a power-of-two bead count");
+  if (c->spme_generic)
+    return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products need power-of-two SPME grid edges");
   const size_t n = (size_t)c->Pb * c->N * 3;
   if (!c->hvp_out) QHP_HIP(c, hipMalloc((void**)&c->hvp_out, n * sizeof(double)));
   auto run = [&]() -> int {

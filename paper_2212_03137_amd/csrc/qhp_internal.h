@@ -98,6 +98,7 @@ struct qhp_ctx {
   hipGraphExec_t step_exec = nullptr;   // one captured (outer) MD step (no energies)
   bool use_graph = true;
   bool serial_forces = false; // set while a group captures the member's step: no side branch
+  bool spme_generic = false;  // an SPME grid edge is not a power of two: the plain SPME path
   std::string err;
   bool have_state = false;
   int64_t step = 0;
@@ -413,16 +414,97 @@ QHP_DEV size_t qtb_rec(int t, int d, int a, int N) {
   return (((size_t)(t >> 3) * N + a) * 3 + d) * 8 + (t & 7);
 }
 
+// ---- runtime-length transforms in LDS (lengths with prime factors 2, 3, 5, 7) ----
+// One Stockham stage of radix R over nser series of length L stored one after another
+// (Ns = product of the earlier radices): butterfly j of a series takes a[j + r L/R],
+// r = 0..R-1, multiplies operand r by w^(r k L/(Ns R)), k = j mod Ns, takes their DFT of
+// length R and writes it to b[(j / Ns) Ns R + k + q Ns] (natural order after the last
+// stage). w^m = tw[m] = exp(-2 pi i m / L); the DFT of length R uses the same table at
+// multiples of L/R (R = 3, 5, 7: the direct sum).
+template <int R>
+QHP_DEV void rt_stage(const double2* a, double2* b, int L, int nser, int Ns, bool inv,
+                      const double2* tw) {
+  const int nb = L / R;
+  for (int jj = threadIdx.x; jj < nb * nser; jj += blockDim.x) {
+    const int ser = jj / nb, j = jj - ser * nb;
+    const double2* as = a + (size_t)ser * L;
+    double2* bs = b + (size_t)ser * L;
+    const int k = j % Ns;
+    double2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[r] = as[j + r * nb];
+      if (r) {
+        double2 t = tw[r * k * (L / (Ns * R))];
+        if (inv) t.y = -t.y;
+        v[r] = make_double2(v[r].x * t.x - v[r].y * t.y, v[r].x * t.y + v[r].y * t.x);
+      }
+    }
+    const int idx = (j / Ns) * Ns * R + k;
+    if constexpr (R == 4) {
+      const double2 t0 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+      const double2 t1 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+      const double2 t2 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+      const double2 t3 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+      const double2 jt3 = inv ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
+      bs[idx] = make_double2(t0.x + t2.x, t0.y + t2.y);
+      bs[idx + 2 * Ns] = make_double2(t0.x - t2.x, t0.y - t2.y);
+      bs[idx + Ns] = make_double2(t1.x + jt3.x, t1.y + jt3.y);
+      bs[idx + 3 * Ns] = make_double2(t1.x - jt3.x, t1.y - jt3.y);
+    } else if constexpr (R == 2) {
+      bs[idx] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
+      bs[idx + Ns] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double2 acc = v[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          double2 w = tw[((q * r) % R) * nb];
+          if (inv) w.y = -w.y;
+          acc.x += v[r].x * w.x - v[r].y * w.y;
+          acc.y += v[r].x * w.y + v[r].y * w.x;
+        }
+        bs[idx + q * Ns] = acc;
+      }
+    }
+  }
+}
+
+// Unnormalised transforms (exp(+...) when inv) of nser series of runtime length L between
+// two LDS buffers: radix 4 while four divides what is left, then 2, 3, 5 and 7 (L must have
+// no other prime factor). Every thread of the block takes part. Returns the buffer
+// holding the result.
+QHP_DEV double2* fft_rt(double2* a, double2* b, int L, int nser, bool inv, const double2* tw) {
+  for (int Ns = 1; Ns < L;) {
+    const int left = L / Ns;
+    const int R = left % 4 == 0 ? 4 : left % 2 == 0 ? 2 : left % 3 == 0 ? 3 : left % 5 == 0 ? 5 : 7;
+    switch (R) {
+      case 4: rt_stage<4>(a, b, L, nser, Ns, inv, tw); break;
+      case 2: rt_stage<2>(a, b, L, nser, Ns, inv, tw); break;
+      case 3: rt_stage<3>(a, b, L, nser, Ns, inv, tw); break;
+      case 5: rt_stage<5>(a, b, L, nser, Ns, inv, tw); break;
+      default: rt_stage<7>(a, b, L, nser, Ns, inv, tw); break;
+    }
+    __syncthreads();
+    double2* t = a; a = b; b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
 constexpr uint64_t STREAM_RPMD_O = 5;
 constexpr uint64_t STREAM_QTB_WHITE = 6;
 
 QHP_DEV unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
-// wrapped grid coordinate u = K * frac(x / L) in [0, K] and its integer base (K is a power
-// of two, so 1/K is the exact power 2^-log2(K) and no division is needed)
+// wrapped grid coordinate u = K * frac(x / L) in [0, K] and its integer base (for K a power
+// of two 1/K is the exact power 2^-log2(K) and no division is needed)
 QHP_DEV double grid_coord(double x, double KoL, int K) {
   const double u = x * KoL;
-  return u - (double)K * floor(u * ldexp(1.0, -__builtin_ctz((unsigned)K)));
+  const double f = (K & (K - 1)) ? floor(u / (double)K)
+                                 : floor(u * ldexp(1.0, -__builtin_ctz((unsigned)K)));
+  return u - (double)K * f;
 }
 // Packed centroid records (FP32-pair contexts without contraction): the w of a centroid
 // record, otherwise the atom's largest bead-centroid distance d, carries the atom's charge
@@ -460,7 +542,10 @@ struct BinGeom {
 QHP_DEV int tile_of_centroid(const BinGeom& G, double cx, double cy, double cz) {
   const double c[3] = {cx, cy, cz};
   int t[3];
-  for (int d = 0; d < 3; ++d) t[d] = (base_of(c[d], G.KoL[d], G.K[d]) & (G.K[d] - 1)) / QHP_TB;
+  for (int d = 0; d < 3; ++d) {
+    const int b = base_of(c[d], G.KoL[d], G.K[d]);
+    t[d] = (b >= G.K[d] ? b - G.K[d] : b) / QHP_TB;
+  }
   return (t[0] * G.nt1 + t[1]) * G.nt2 + t[2];
 }
 #pragma clang fp contract(off)

@@ -26,78 +26,6 @@ QHP_DEV double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// One Stockham stage of radix R (Ns = product of the earlier radices): butterfly j takes
-// a[j + r L/R], r = 0..R-1, multiplies operand r by w^(r k L/(Ns R)), k = j mod Ns, takes
-// their DFT of length R and writes it to b[(j / Ns) Ns R + k + q Ns] (natural order after
-// the last stage). w^m = tw[m] = exp(-2 pi i m / L); the DFT of length R uses the same
-// table at multiples of L/R (R = 3, 5, 7: the direct sum).
-template <int R>
-QHP_DEV void rt_stage(const double2* a, double2* b, int L, int Ns, bool inv, const double2* tw) {
-  const int nb = L / R;
-  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-    const int k = j % Ns;
-    double2 v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      v[r] = a[j + r * nb];
-      if (r) {
-        double2 t = tw[r * k * (L / (Ns * R))];
-        if (inv) t.y = -t.y;
-        v[r] = cmul(v[r], t);
-      }
-    }
-    const int idx = (j / Ns) * Ns * R + k;
-    if constexpr (R == 4) {
-      const double2 t0 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
-      const double2 t1 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
-      const double2 t2 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
-      const double2 t3 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
-      const double2 jt3 = inv ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
-      b[idx] = make_double2(t0.x + t2.x, t0.y + t2.y);
-      b[idx + 2 * Ns] = make_double2(t0.x - t2.x, t0.y - t2.y);
-      b[idx + Ns] = make_double2(t1.x + jt3.x, t1.y + jt3.y);
-      b[idx + 3 * Ns] = make_double2(t1.x - jt3.x, t1.y - jt3.y);
-    } else if constexpr (R == 2) {
-      b[idx] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
-      b[idx + Ns] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
-    } else {
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double2 acc = v[0];
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          double2 w = tw[((q * r) % R) * nb];
-          if (inv) w.y = -w.y;
-          const double2 u = cmul(v[r], w);
-          acc.x += u.x; acc.y += u.y;
-        }
-        b[idx + q * Ns] = acc;
-      }
-    }
-  }
-}
-
-// Single-block Stockham FFT of runtime length L between two LDS buffers: radix 4 while
-// four divides what is left, then 2, 3, 5 and 7 (L must have no other prime factor).
-// tw[m] = exp(-2 pi i m / L). Returns the buffer holding the result.
-QHP_DEV double2* fft_rt(double2* a, double2* b, int L, bool inv, const double2* tw) {
-  for (int Ns = 1; Ns < L;) {
-    const int left = L / Ns;
-    const int R = left % 4 == 0 ? 4 : left % 2 == 0 ? 2 : left % 3 == 0 ? 3 : left % 5 == 0 ? 5 : 7;
-    switch (R) {
-      case 4: rt_stage<4>(a, b, L, Ns, inv, tw); break;
-      case 2: rt_stage<2>(a, b, L, Ns, inv, tw); break;
-      case 3: rt_stage<3>(a, b, L, Ns, inv, tw); break;
-      case 5: rt_stage<5>(a, b, L, Ns, inv, tw); break;
-      default: rt_stage<7>(a, b, L, Ns, inv, tw); break;
-    }
-    __syncthreads();
-    double2* t = a; a = b; b = t;
-    Ns *= R;
-  }
-  return a;
-}
-
 struct KerArgs {
   int nseg;
   const double* gamma;    // [T][nseg+1]
@@ -127,7 +55,7 @@ __global__ __launch_bounds__(NT) void k_qtb_kernel(KerArgs A) {
     a[k] = make_double2(sqrt(2.0 * m * gz[kk] * th / A.dt), 0.0);
   }
   __syncthreads();
-  double2* h = fft_rt(a, b, L2, true, A.tw2);       // unnormalised inverse
+  double2* h = qhp::fft_rt(a, b, L2, 1, true, A.tw2);       // unnormalised inverse
   double2* o = (h == a) ? b : a;
   for (int l = threadIdx.x; l < L4; l += blockDim.x) {
     double v = 0.0;
@@ -137,7 +65,7 @@ __global__ __launch_bounds__(NT) void k_qtb_kernel(KerArgs A) {
   }
   __syncthreads();
   double2* other = (o == a) ? b : a;
-  double2* H = fft_rt(o, other, L4, false, A.tw4);
+  double2* H = qhp::fft_rt(o, other, L4, 1, false, A.tw4);
   for (int l = threadIdx.x; l < L4; l += blockDim.x) A.hhat[(size_t)z * L4 + l] = H[l];
 }
 
@@ -356,11 +284,11 @@ __global__ __launch_bounds__(NT) void k_qtb_generate_rt(GenArgs A) {
       a[l] = w;
     }
     __syncthreads();
-    double2* X = fft_rt(a, b, L4, false, A.tw4);
+    double2* X = qhp::fft_rt(a, b, L4, 1, false, A.tw4);
     double2* Y = X == a ? b : a;
     for (int l = tid; l < L4; l += NT) X[l] = cmul(X[l], Hz[l]);
     __syncthreads();
-    double2* f = fft_rt(X, Y, L4, true, A.tw4);
+    double2* f = qhp::fft_rt(X, Y, L4, 1, true, A.tw4);
     for (int t = tid; t < NS; t += NT) {
       const double2 v = f[NS + t];
       if (slot == 0) {
@@ -487,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_qtb_spectra_rt(SpecArgs A) {
         a[t] = z;
       }
       __syncthreads();
-      const double2* Z = fft_rt(a, b, L2, false, A.tw2);
+      const double2* Z = qhp::fft_rt(a, b, L2, 1, false, A.tw2);
       for (int k = tid; k <= NS; k += NT) {
         const double2 zk = Z[k], zm = Z[(L2 - k) % L2];
         const double vr = 0.5 * (zk.x + zm.x), vi = 0.5 * (zk.y - zm.y);

@@ -1305,6 +1305,74 @@ __global__ __launch_bounds__(512 * NB) __attribute__((amdgpu_waves_per_eu(4))) v
   for (int k = 0; k < 8; ++k) g[(size_t)(8 * k) * A.pc] = v[k];
 }
 
+
+// ---------- grids whose edges are not powers of two (prime factors 2, 3, 5, 7) ----------
+// A plain path with the same grid layout ([k0][k1][k2] points, the complex slots of a
+// point contiguous): spreading by device-scope atomic additions (one thread per bead and
+// atom, after the grid is cleared), each axis transformed line by line in LDS by runtime
+// mixed-radix stages, the product with G, and the same gather kernels.
+__global__ __launch_bounds__(NT) void k_grid_zero(double* grid, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT)
+    grid[i] = 0.0;
+}
+
+template <int ORDER>
+__global__ __launch_bounds__(NT) void k_spread_gen(SpmeArgs A, int P) {
+  const size_t tid = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (tid >= (size_t)A.N * P) return;
+  const int a = (int)(tid / P), b = (int)(tid % P);
+  double xb[3];
+  for (int d = 0; d < 3; ++d) xb[d] = A.x[((size_t)d * A.N + a) * P + b];
+  const int K[3] = {A.K0, A.K1, A.K2};
+  int i0[3];
+  double w[3][ORDER], dw[3][ORDER];
+  stencil<ORDER>(xb, A.L, K, i0, w, dw);
+  const double q = A.charge[a];
+  for (int t0 = 0; t0 < ORDER; ++t0) {
+    const int k0 = wrapk(i0[0] - t0, A.K0);
+    for (int t1 = 0; t1 < ORDER; ++t1) {
+      const int k1 = wrapk(i0[1] - t1, A.K1);
+      const double wq = q * w[0][t0] * w[1][t1];
+      double* row = A.grid + (size_t)(k0 * A.K1 + k1) * A.K2 * A.Pc2 + b;
+#pragma unroll
+      for (int t2 = 0; t2 < ORDER; ++t2)
+        unsafeAtomicAdd(row + (size_t)wrapk(i0[2] - t2, A.K2) * A.Pc2, wq * w[2][t2]);
+    }
+  }
+}
+
+// One block per line along an axis: the pc complex slots of its K points (point stride
+// `inner` points, the slots contiguous at each point) to LDS as pc series, transformed,
+// and back. Line l covers the points (l / inner) K inner + (l mod inner) + e inner.
+__global__ __launch_bounds__(NT) void k_fft_line_gen(double2* grid, const double2* tw, int K,
+                                                     int pc, long inner, int inv) {
+  extern __shared__ double2 lbuf[];
+  double2* a = lbuf;
+  double2* b = lbuf + (size_t)K * pc;
+  const long l = blockIdx.x;
+  const long base = (l / inner) * K * inner + (l % inner);
+  for (int i = threadIdx.x; i < K * pc; i += NT) {
+    const int e = i / pc, sl = i - e * pc;
+    a[(size_t)sl * K + e] = grid[(base + (long)e * inner) * pc + sl];
+  }
+  __syncthreads();
+  const double2* r = qhp::fft_rt(a, b, K, pc, inv != 0, tw);
+  for (int i = threadIdx.x; i < K * pc; i += NT) {
+    const int e = i / pc, sl = i - e * pc;
+    grid[(base + (long)e * inner) * pc + sl] = r[(size_t)sl * K + e];
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_scale_g(double2* grid, const double* G, size_t npts,
+                                               int pc) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < npts * pc;
+       i += (size_t)gridDim.x * NT) {
+    const double g = G[i / pc];
+    grid[i].x *= g;
+    grid[i].y *= g;
+  }
+}
+
 }  // namespace
 
 #define QHP_SWITCH_P(P, CALL)                          \
@@ -1451,7 +1519,33 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
   const bool pg = !plain && B.pgrad;
   const unsigned nb = (unsigned)(((size_t)N * P + NT - 1) / NT);
   hipEvent_t ev = nullptr;
-  if (part & SPME_FRONT) {
+  if ((part & SPME_FRONT) && c->spme_generic) {
+    // grid edges that are not powers of two: the plain path
+    prof_begin(c, QHP_PROF_SPREAD, &ev);
+    const size_t npts = (size_t)c->K[0] * c->K[1] * c->K[2];
+    const size_t nd = npts * 2 * pc;
+    hipLaunchKernelGGL(k_grid_zero, (unsigned)std::min<size_t>((nd + NT - 1) / NT, 65536), NT, 0,
+                       c->stream, A.grid, nd);
+    QHP_SWITCH_ORDER(c->p.pme_order, hipLaunchKernelGGL((k_spread_gen<OO>), nb, NT, 0, c->stream, A, P));
+    prof_end(c, QHP_PROF_SPREAD, ev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    prof_begin(c, QHP_PROF_FFT, &ev);
+    auto pass = [&](int axis, int inv) {
+      long inner = 1;
+      for (int d = axis + 1; d < 3; ++d) inner *= c->K[d];
+      const int K = c->K[axis];
+      const unsigned lines = (unsigned)(npts / K);
+      hipLaunchKernelGGL(k_fft_line_gen, lines, NT, (size_t)2 * K * pc * sizeof(double2),
+                         c->stream, c->grid, c->tw[axis], K, pc, inner, inv);
+    };
+    for (int d = 0; d < 3; ++d) pass(d, 0);
+    hipLaunchKernelGGL(k_scale_g, (unsigned)std::min<size_t>((npts * pc + NT - 1) / NT, 65536), NT,
+                       0, c->stream, c->grid, c->influence, npts, pc);
+    for (int d = 2; d >= 0; --d) pass(d, 1);
+    prof_end(c, QHP_PROF_FFT, ev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else if (part & SPME_FRONT) {
     prof_begin(c, QHP_PROF_SPREAD, &ev);
     {
       TileArgs T;

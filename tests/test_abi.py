@@ -103,3 +103,22 @@ def test_segment_lengths_validated_before_device_use(nseg, ok):
     else:
         c.close()
         assert ok
+
+
+@pytest.mark.parametrize("grid,code", [((24, 24, 24), "device"), ((40, 16, 56), "device"),
+                                       ((20, 16, 16), "inval"), ((88, 16, 16), "inval"),
+                                       ((136, 16, 16), "inval")])
+def test_spme_grids_validated_before_device_use(grid, code):
+    # grid edges: powers of two, or multiples of 8 with prime factors 2, 3, 5, 7, up to 128
+    import dataclasses
+    import paper_2212_03137_amd as q
+    if not os.path.exists(q.LIB_PATH):
+        pytest.skip("libqhp.so not built")
+    s = dataclasses.replace(synth.small_rpmd(), pme_grid=grid)
+    with pytest.raises(q.QhpError) as e:
+        q.Context.from_system(s)
+    assert e.value.code == (q.EDEVICE if code == "device" else q.EINVAL), e.value.code
+    if code == "device":
+        with pytest.raises(q.QhpError) as e:
+            q.Context.from_system(s, exec_mode=q.PLAIN)
+        assert e.value.code == q.EUNSUPPORTED

@@ -1,0 +1,97 @@
+"""SPME grids whose edges are not powers of two (multiples of 8 with prime factors 2, 3, 5,
+7: the plain path of atomic spreading, line-by-line mixed-radix transforms and the usual
+gather) against the FP64 oracle, whose transforms take any length."""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import has_gpu, oracle_grad_fn, rel_max
+from oracle import forces as ofo
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not has_gpu(), reason="needs a HIP device")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _box(grid, n_beads, order=4):
+    s = synth.small_rpmd()
+    s = dataclasses.replace(s, pme_grid=tuple(grid), pme_order=order)
+    if n_beads != s.n_beads:
+        s = dataclasses.replace(s, n_beads=n_beads, pos=s.pos[:n_beads].copy(),
+                                vel=s.vel[:n_beads].copy())
+    return s
+
+
+@pytest.mark.parametrize("grid,n_beads,order", [((24, 24, 24), 8, 4), ((40, 24, 56), 8, 5),
+                                                ((24, 48, 40), 1, 5), ((56, 56, 24), 2, 6)])
+def test_eval_on_grids_that_are_not_powers_of_two(grid, n_beads, order):
+    import paper_2212_03137_amd as q
+    s = _box(grid, n_beads, order)
+    say("spme grid", grid, "beads", n_beads, "order", order)
+    Eref, Fref = ofo.evaluate(s.pos, s)
+    for prec in (q.FP64, q.FP32_PAIRS):
+        with q.Context.from_system(s, precision=prec) as c:
+            E, F = c.eval(s.pos)
+        # the reciprocal energy and every force against the oracle's own FFT of the same grid
+        recip = np.abs(E[:, 6] - Eref[:, 6]).max() / np.abs(Eref[:, 6]).max()
+        say(" prec", prec, "recip", recip, "F", rel_max(F, Fref))
+        assert recip <= 1e-11
+        assert rel_max(F, Fref) <= (1e-11 if prec == q.FP64 else 1e-5)
+
+
+def test_centroid_list_box_on_a_grid_that_is_not_a_power_of_two():
+    # 343 waters (21.8 A, rc 8 A: the centroid-list regime, so FP32 pairs take the FP32
+    # kernels) with a 40^3 grid, P = 4
+    import paper_2212_03137_amd as q
+    from helpers import medium_box, rel_rms
+    s = medium_box(P=4, K=40)
+    say("spme grid medium", s.pme_grid)
+    Eref, Fref = ofo.evaluate(s.pos, s)
+    with q.Context.from_system(s) as c:
+        E, F = c.eval(s.pos)
+    assert rel_max(F, Fref) <= 1e-11
+    assert np.abs(E - Eref).max() <= 1e-11 * np.abs(Eref).max()
+    with q.Context.from_system(s, precision=q.FP32_PAIRS) as c:
+        E, F = c.eval(s.pos)
+        c.set_state(s.pos, s.vel, 0)
+        c.step(10)
+        x, _, _ = c.get_state()
+    assert rel_rms(F, Fref) <= 1e-5
+    assert np.abs(E[:, 6] - Eref[:, 6]).max() <= 1e-11 * np.abs(Eref[:, 6]).max()
+    assert np.all(np.isfinite(x))
+
+
+def test_trajectory_on_a_grid_that_is_not_a_power_of_two():
+    import paper_2212_03137_amd as q
+    from oracle import rpmd
+    s = _box((24, 40, 24), 8, 4)
+    say("spme grid trajectory", s.pme_grid)
+    R = rpmd.RPMD(s.n_beads, s.mass, s.kT, s.hbar, s.dt, s.gamma_centroid, s.trpmd_c, s.seed,
+                  oracle_grad_fn(s))
+    R.set_state(s.pos, s.vel)
+    R.step(20)
+    xr, vr, _ = R.get_state()
+    with q.Context.from_system(s) as c:
+        c.set_state(s.pos, s.vel, 0)
+        c.step(20)
+        x, v, st = c.get_state()
+    assert st == 20
+    assert np.abs(x - xr).max() / np.abs(xr).max() < 1e-8
+    assert np.abs(v - vr).max() / np.abs(vr).max() < 1e-6
+
+
+def test_derivatives_need_power_of_two_grids():
+    import paper_2212_03137_amd as q
+    s = _box((24, 24, 24), 8, 4)
+    with q.Context.from_system(s) as c:
+        with pytest.raises(q.QhpError) as e:
+            c.param_grad(s.pos)
+        assert e.value.code == q.EUNSUPPORTED
