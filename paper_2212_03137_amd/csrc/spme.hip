@@ -414,9 +414,12 @@ struct TSpreadArgs {
 
 // in-tile range of the stencil points base - t, t = 0..ORDER-1, along one axis:
 // lo = (base - ORDER + 1 - t0) mod K is the tile-relative position of the lowest point
+// v mod K in [0, K) (a mask when K is a power of two)
+QHP_DEV int wrap_mod(int v, int K) { return (K & (K - 1)) ? ((v % K) + K) % K : (v & (K - 1)); }
+
 template <int ORDER>
 QHP_DEV int tile_lo(int base, int t0, int K) {
-  return (base - (ORDER - 1) - t0) & (K - 1);     // K is a power of two
+  return wrap_mod(base - (ORDER - 1) - t0, K);
 }
 
 // TAN: spread the derivative of the charge density along the direction u instead,
@@ -542,7 +545,7 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
 #pragma unroll
         for (int t = 0; t < ORDER; ++t) {
           // stencil point base - t sits at tile-relative position lo + ORDER - 1 - t (mod K)
-          const int r = (lo[d] + ORDER - 1 - t) & (K[d] - 1);
+          const int r = wrap_mod(lo[d] + ORDER - 1 - t, K[d]);
           if (d < 2) {
             rel[d][t] = r < TB ? r : -1;
           } else {
@@ -1307,59 +1310,52 @@ __global__ __launch_bounds__(512 * NB) __attribute__((amdgpu_waves_per_eu(4))) v
 
 
 // ---------- grids whose edges are not powers of two (prime factors 2, 3, 5, 7) ----------
-// A plain path with the same grid layout ([k0][k1][k2] points, the complex slots of a
-// point contiguous): spreading by device-scope atomic additions (one thread per bead and
-// atom, after the grid is cleared), each axis transformed line by line in LDS by runtime
-// mixed-radix stages, the product with G, and the same gather kernels.
-__global__ __launch_bounds__(NT) void k_grid_zero(double* grid, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT)
-    grid[i] = 0.0;
-}
-
-template <int ORDER>
-__global__ __launch_bounds__(NT) void k_spread_gen(SpmeArgs A, int P) {
-  const size_t tid = (size_t)blockIdx.x * NT + threadIdx.x;
-  if (tid >= (size_t)A.N * P) return;
-  const int a = (int)(tid / P), b = (int)(tid % P);
-  double xb[3];
-  for (int d = 0; d < 3; ++d) xb[d] = A.x[((size_t)d * A.N + a) * P + b];
-  const int K[3] = {A.K0, A.K1, A.K2};
-  int i0[3];
-  double w[3][ORDER], dw[3][ORDER];
-  stencil<ORDER>(xb, A.L, K, i0, w, dw);
-  const double q = A.charge[a];
-  for (int t0 = 0; t0 < ORDER; ++t0) {
-    const int k0 = wrapk(i0[0] - t0, A.K0);
-    for (int t1 = 0; t1 < ORDER; ++t1) {
-      const int k1 = wrapk(i0[1] - t1, A.K1);
-      const double wq = q * w[0][t0] * w[1][t1];
-      double* row = A.grid + (size_t)(k0 * A.K1 + k1) * A.K2 * A.Pc2 + b;
-#pragma unroll
-      for (int t2 = 0; t2 < ORDER; ++t2)
-        unsafeAtomicAdd(row + (size_t)wrapk(i0[2] - t2, A.K2) * A.Pc2, wq * w[2][t2]);
-    }
+// The same grid layout ([k0][k1][k2] points, the complex slots of a point contiguous) and
+// the tiled spreading and gather kernels (which wrap their offsets for any edge); each
+// axis transformed a few lines at a time in LDS by runtime mixed-radix stages, and the
+// product with G between the forward and inverse passes.
+// nl lines along an axis per block: the pc complex slots of their K points to LDS as
+// nl pc series, transformed, and back. Line l covers the points
+// (l / inner) K inner + (l mod inner) + e inner (point stride `inner`, the slots of a point
+// contiguous). With inner > 1 the block's lines are nl neighbouring points of one plane
+// (nl divides inner), so the slots of the nl lines at one e are contiguous; with
+// inner = 1 each line is contiguous. Consecutive threads take consecutive addresses.
+QHP_DEV void line_point(int i, int K, int pc, int nl, long inner, long l0, long base0, int& j,
+                        int& e, int& sl, long& pt) {
+  sl = i % pc;
+  const int r = i / pc;
+  if (inner > 1) {
+    j = r % nl; e = r / nl;
+    pt = base0 + j + (long)e * inner;
+  } else {
+    e = r % K; j = r / K;
+    pt = (l0 + j) * K + e;
   }
 }
 
-// One block per line along an axis: the pc complex slots of its K points (point stride
-// `inner` points, the slots contiguous at each point) to LDS as pc series, transformed,
-// and back. Line l covers the points (l / inner) K inner + (l mod inner) + e inner.
 __global__ __launch_bounds__(NT) void k_fft_line_gen(double2* grid, const double2* tw, int K,
-                                                     int pc, long inner, int inv) {
+                                                     int pc, long inner, int nl, int inv) {
   extern __shared__ double2 lbuf[];
+  const int ns = nl * pc, n = K * ns;
   double2* a = lbuf;
-  double2* b = lbuf + (size_t)K * pc;
-  const long l = blockIdx.x;
-  const long base = (l / inner) * K * inner + (l % inner);
-  for (int i = threadIdx.x; i < K * pc; i += NT) {
-    const int e = i / pc, sl = i - e * pc;
-    a[(size_t)sl * K + e] = grid[(base + (long)e * inner) * pc + sl];
+  double2* b = lbuf + (size_t)n;
+  double2* stw = lbuf + 2 * (size_t)n;     // the axis' twiddles
+  for (int k = threadIdx.x; k < K; k += NT) stw[k] = tw[k];
+  const long l0 = (long)blockIdx.x * nl;
+  const long base0 = (l0 / inner) * K * inner + (l0 % inner);
+  for (int i = threadIdx.x; i < n; i += NT) {
+    int j, e, sl;
+    long pt;
+    line_point(i, K, pc, nl, inner, l0, base0, j, e, sl, pt);
+    a[(size_t)(j * pc + sl) * K + e] = grid[pt * pc + sl];
   }
   __syncthreads();
-  const double2* r = qhp::fft_rt(a, b, K, pc, inv != 0, tw);
-  for (int i = threadIdx.x; i < K * pc; i += NT) {
-    const int e = i / pc, sl = i - e * pc;
-    grid[(base + (long)e * inner) * pc + sl] = r[(size_t)sl * K + e];
+  const double2* r = qhp::fft_rt(a, b, K, ns, inv != 0, stw);
+  for (int i = threadIdx.x; i < n; i += NT) {
+    int j, e, sl;
+    long pt;
+    line_point(i, K, pc, nl, inner, l0, base0, j, e, sl, pt);
+    grid[pt * pc + sl] = r[(size_t)(j * pc + sl) * K + e];
   }
 }
 
@@ -1523,10 +1519,43 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
     // grid edges that are not powers of two: the plain path
     prof_begin(c, QHP_PROF_SPREAD, &ev);
     const size_t npts = (size_t)c->K[0] * c->K[1] * c->K[2];
-    const size_t nd = npts * 2 * pc;
-    hipLaunchKernelGGL(k_grid_zero, (unsigned)std::min<size_t>((nd + NT - 1) / NT, 65536), NT, 0,
-                       c->stream, A.grid, nd);
-    QHP_SWITCH_ORDER(c->p.pme_order, hipLaunchKernelGGL((k_spread_gen<OO>), nb, NT, 0, c->stream, A, P));
+    {
+      // the tiled spreading (atoms binned by the list stage; every grid point written once):
+      // gb beads per block, z tiles along z dividing the tile count
+      TSpreadArgs S;
+      S.N = N; S.P = P; S.K0 = c->K[0]; S.K1 = c->K[1]; S.K2 = c->K[2];
+      S.nt1 = c->K[1] / TB; S.nt2 = c->K[2] / TB; S.Pc2 = 2 * pc;
+      S.x = A.x; S.grid = A.grid; S.charge = c->d_charge;
+      S.cent = c->cent; S.ctrl = c->ctrl;
+      for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
+      S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms;
+      int gb = c->spread_gb > 0 ? c->spread_gb : 8;
+      if (gb > P) gb = P;
+      int z = c->spread_z > 0 ? c->spread_z : 1;
+      while (z > 1 && (S.nt2 % z || z * gb > 16)) z >>= 1;
+      const dim3 sgrid(c->ntiles / z, P / gb);
+#define SPREAD_GEN(GBV, ZV)                                                                  \
+      QHP_SWITCH_ORDER(c->p.pme_order, hipLaunchKernelGGL((k_spread_tiles<OO, GBV, false, ZV>),  \
+                                                          sgrid, NT, 0, c->stream, S))
+      switch (gb * 16 + z) {
+        case 16 + 1: SPREAD_GEN(1, 1); break;
+        case 16 + 2: SPREAD_GEN(1, 2); break;
+        case 16 + 4: SPREAD_GEN(1, 4); break;
+        case 16 + 8: SPREAD_GEN(1, 8); break;
+        case 32 + 1: SPREAD_GEN(2, 1); break;
+        case 32 + 2: SPREAD_GEN(2, 2); break;
+        case 32 + 4: SPREAD_GEN(2, 4); break;
+        case 32 + 8: SPREAD_GEN(2, 8); break;
+        case 64 + 1: SPREAD_GEN(4, 1); break;
+        case 64 + 2: SPREAD_GEN(4, 2); break;
+        case 64 + 4: SPREAD_GEN(4, 4); break;
+        case 128 + 1: SPREAD_GEN(8, 1); break;
+        case 128 + 2: SPREAD_GEN(8, 2); break;
+        case 256 + 1: SPREAD_GEN(16, 1); break;
+        default: return hipErrorInvalidValue;
+      }
+#undef SPREAD_GEN
+    }
     prof_end(c, QHP_PROF_SPREAD, ev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1535,9 +1564,15 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
       long inner = 1;
       for (int d = axis + 1; d < 3; ++d) inner *= c->K[d];
       const int K = c->K[axis];
-      const unsigned lines = (unsigned)(npts / K);
-      hipLaunchKernelGGL(k_fft_line_gen, lines, NT, (size_t)2 * K * pc * sizeof(double2),
-                         c->stream, c->grid, c->tw[axis], K, pc, inner, inv);
+      const long lines = (long)(npts / K);
+      // lines per block: a power of two dividing the plane's points (or the line count),
+      // at most 2,048 complex values per LDS buffer
+      const long div = inner > 1 ? inner : lines;
+      int nl = 1;
+      while ((long)2 * nl * K * pc <= 2048 && div % (2 * nl) == 0) nl *= 2;
+      hipLaunchKernelGGL(k_fft_line_gen, (unsigned)(lines / nl), NT,
+                         ((size_t)2 * nl * K * pc + K) * sizeof(double2), c->stream, c->grid,
+                         c->tw[axis], K, pc, inner, nl, inv);
     };
     for (int d = 0; d < 3; ++d) pass(d, 0);
     hipLaunchKernelGGL(k_scale_g, (unsigned)std::min<size_t>((npts * pc + NT - 1) / NT, 65536), NT,

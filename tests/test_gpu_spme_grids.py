@@ -1,6 +1,6 @@
 """SPME grids whose edges are not powers of two (multiples of 8 with prime factors 2, 3, 5,
-7: the plain path of atomic spreading, line-by-line mixed-radix transforms and the usual
-gather) against the FP64 oracle, whose transforms take any length."""
+7: the tiled spreading and gathers with wrapped offsets, and line-by-line mixed-radix
+transforms) against the FP64 oracle, whose transforms take any length."""
 import dataclasses
 import math
 import sys
