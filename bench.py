@@ -264,6 +264,23 @@ def adqtb_timing(q, stream):
         t_in = time.perf_counter() - t0
     finally:
         c.close()
+    # the same box on a 112^3 grid (0.78 A spacing: grid edges that are not powers of two
+    # take the plain transform path), 300 steps inside the first segment
+    import dataclasses
+    s112 = dataclasses.replace(s, pme_grid=(112, 112, 112))
+    c = q.Context.from_system(s112, precision=q.FP32_PAIRS, thermostat=q.ADQTB, stream=stream)
+    try:
+        c.set_state(s112.pos, s112.vel, 0)
+        c.autotune(3)
+        c.set_state(s112.pos, s112.vel, 0)
+        c.step(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(300)
+        torch.cuda.synchronize()
+        ms_112 = (time.perf_counter() - t0) / 300 * 1e3
+    finally:
+        c.close()
     ms = t_seg / (2 * nseg) * 1e3
     ms_in = t_in / 500 * 1e3
     return {"workload": "water21952_adqtb: 21,952 waters, 87.3 A, P=1, rc 9 A, SPME 128^3 "
@@ -274,7 +291,10 @@ def adqtb_timing(q, stream):
             "ms_per_step_inside_a_segment": ms_in,
             "segment_end_ms": (ms - ms_in) * nseg,
             "autotuned": dict(zip(("spread_beads", "spread_z_tiles", "yz_plane_slots",
-                                   "pair_atoms_per_block"), shapes))}
+                                   "pair_atoms_per_block"), shapes)),
+            "grid_112": {"ms_per_step_inside_a_segment": ms_112, "steps": 300,
+                         "note": "SPME 112^3 (0.78 A spacing), the plain path for grid "
+                                 "edges that are not powers of two"}}
 
 
 def cpu_baseline(s, budget_s=20.0):
