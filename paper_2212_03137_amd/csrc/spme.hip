@@ -1312,8 +1312,8 @@ __global__ __launch_bounds__(512 * NB) __attribute__((amdgpu_waves_per_eu(4))) v
 // ---------- grids whose edges are not powers of two (prime factors 2, 3, 5, 7) ----------
 // The same grid layout ([k0][k1][k2] points, the complex slots of a point contiguous) and
 // the tiled spreading and gather kernels (which wrap their offsets for any edge); each
-// axis transformed a few lines at a time in LDS by runtime mixed-radix stages, and the
-// product with G between the forward and inverse passes.
+// axis transformed a few lines at a time in LDS by runtime mixed-radix stages, the last
+// axis forward, times G and inverse in one visit.
 // nl lines along an axis per block: the pc complex slots of their K points to LDS as
 // nl pc series, transformed, and back. Line l covers the points
 // (l / inner) K inner + (l mod inner) + e inner (point stride `inner`, the slots of a point
@@ -1333,8 +1333,10 @@ QHP_DEV void line_point(int i, int K, int pc, int nl, long inner, long l0, long 
   }
 }
 
-__global__ __launch_bounds__(NT) void k_fft_line_gen(double2* grid, const double2* tw, int K,
-                                                     int pc, long inner, int nl, int inv) {
+// mode 0: forward, 1: inverse, 2: forward, times G, inverse (one visit of the last axis)
+__global__ __launch_bounds__(NT) void k_fft_line_gen(double2* grid, const double2* tw,
+                                                     const double* G, int K, int pc, long inner,
+                                                     int nl, int mode) {
   extern __shared__ double2 lbuf[];
   const int ns = nl * pc, n = K * ns;
   double2* a = lbuf;
@@ -1350,22 +1352,25 @@ __global__ __launch_bounds__(NT) void k_fft_line_gen(double2* grid, const double
     a[(size_t)(j * pc + sl) * K + e] = grid[pt * pc + sl];
   }
   __syncthreads();
-  const double2* r = qhp::fft_rt(a, b, K, ns, inv != 0, stw);
+  double2* r = qhp::fft_rt(a, b, K, ns, mode == 1, stw);
+  if (mode == 2) {
+    for (int i = threadIdx.x; i < n; i += NT) {
+      int j, e, sl;
+      long pt;
+      line_point(i, K, pc, nl, inner, l0, base0, j, e, sl, pt);
+      double2& v = r[(size_t)(j * pc + sl) * K + e];
+      const double g = G[pt];
+      v.x *= g;
+      v.y *= g;
+    }
+    __syncthreads();
+    r = qhp::fft_rt(r, r == a ? b : a, K, ns, true, stw);
+  }
   for (int i = threadIdx.x; i < n; i += NT) {
     int j, e, sl;
     long pt;
     line_point(i, K, pc, nl, inner, l0, base0, j, e, sl, pt);
     grid[pt * pc + sl] = r[(size_t)(j * pc + sl) * K + e];
-  }
-}
-
-__global__ __launch_bounds__(NT) void k_scale_g(double2* grid, const double* G, size_t npts,
-                                               int pc) {
-  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < npts * pc;
-       i += (size_t)gridDim.x * NT) {
-    const double g = G[i / pc];
-    grid[i].x *= g;
-    grid[i].y *= g;
   }
 }
 
@@ -1560,7 +1565,7 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     prof_begin(c, QHP_PROF_FFT, &ev);
-    auto pass = [&](int axis, int inv) {
+    auto pass = [&](int axis, int mode) {
       long inner = 1;
       for (int d = axis + 1; d < 3; ++d) inner *= c->K[d];
       const int K = c->K[axis];
@@ -1573,12 +1578,13 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
       while ((long)2 * nl * K * pc <= 1024 && div % (2 * nl) == 0) nl *= 2;
       hipLaunchKernelGGL(k_fft_line_gen, (unsigned)(lines / nl), NT,
                          ((size_t)2 * nl * K * pc + K) * sizeof(double2), c->stream, c->grid,
-                         c->tw[axis], K, pc, inner, nl, inv);
+                         c->tw[axis], c->influence, K, pc, inner, nl, mode);
     };
-    for (int d = 0; d < 3; ++d) pass(d, 0);
-    hipLaunchKernelGGL(k_scale_g, (unsigned)std::min<size_t>((npts * pc + NT - 1) / NT, 65536), NT,
-                       0, c->stream, c->grid, c->influence, npts, pc);
-    for (int d = 2; d >= 0; --d) pass(d, 1);
+    pass(0, 0);
+    pass(1, 0);
+    pass(2, 2);                      // forward z, the product with G, inverse z
+    pass(1, 1);
+    pass(0, 1);
     prof_end(c, QHP_PROF_FFT, ev);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else if (part & SPME_FRONT) {
