@@ -545,7 +545,8 @@ __global__ __launch_bounds__(NT) void k_spread_tiles(TSpreadArgs A) {
 #pragma unroll
         for (int t = 0; t < ORDER; ++t) {
           // stencil point base - t sits at tile-relative position lo + ORDER - 1 - t (mod K)
-          const int r = wrap_mod(lo[d] + ORDER - 1 - t, K[d]);
+          const int r0 = lo[d] + ORDER - 1 - t;            // in [0, K + ORDER - 2]
+          const int r = r0 >= K[d] ? r0 - K[d] : r0;
           if (d < 2) {
             rel[d][t] = r < TB ? r : -1;
           } else {
