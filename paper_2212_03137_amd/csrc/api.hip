@@ -1023,8 +1023,6 @@ extern "C" int qhp_param_grad(qhp_ctx* c, const double* pos, double* dq, double*
     return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients with the test tether");
   if (c->Pb != c->P)
     return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients need a power-of-two bead count");
-  if (c->spme_generic)
-    return qhp_fail(c, QHP_EUNSUPPORTED, "parameter gradients need power-of-two SPME grid edges");
   auto run = [&]() -> int {
     int r = copy_in(c, pos, mem_kind, c->x);
     if (r) return r;
@@ -1068,8 +1066,6 @@ extern "C" int qhp_hvp(qhp_ctx* c, const double* pos, const double* dir, double*
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products with the test tether");
   if (c->Pb != c->P)
     return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products need a power-of-two bead count");
-  if (c->spme_generic)
-    return qhp_fail(c, QHP_EUNSUPPORTED, "Hessian-vector products need power-of-two SPME grid edges");
   const size_t n = (size_t)c->Pb * c->N * 3;
   if (!c->hvp_out) QHP_HIP(c, hipMalloc((void**)&c->hvp_out, n * sizeof(double)));
   auto run = [&]() -> int {

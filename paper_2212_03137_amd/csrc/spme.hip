@@ -1433,7 +1433,35 @@ static hipError_t fft_pass(qhp_ctx* c, int axis, int mode, int pc, double2* grid
 // 64 points take the fused plane kernel between the two x passes (unless the autotuner
 // found the one-axis passes faster: fft_nb < 0); other grids take five one-axis passes
 // (the z pass fusing G).
+// Grid edges that are not powers of two: five passes of a few lines per block (the last
+// axis forward, times G and inverse in one visit).
+static hipError_t convolve_lines(qhp_ctx* c, int pc, double2* grid) {
+  const size_t npts = (size_t)c->K[0] * c->K[1] * c->K[2];
+  auto pass = [&](int axis, int mode) {
+    long inner = 1;
+    for (int d = axis + 1; d < 3; ++d) inner *= c->K[d];
+    const int K = c->K[axis];
+    const long lines = (long)(npts / K);
+    // lines per block: a power of two dividing the plane's points (or the line count),
+    // at most 1,024 complex values per LDS buffer (2,048: 181 against 153 us for the
+    // 112^3 transforms of the one-bead 21,952-water box, 512: 176 us)
+    const long div = inner > 1 ? inner : lines;
+    int nl = 1;
+    while ((long)2 * nl * K * pc <= 1024 && div % (2 * nl) == 0) nl *= 2;
+    hipLaunchKernelGGL(k_fft_line_gen, (unsigned)(lines / nl), NT,
+                       ((size_t)2 * nl * K * pc + K) * sizeof(double2), c->stream, grid,
+                       c->tw[axis], c->influence, K, pc, inner, nl, mode);
+  };
+  pass(0, 0);
+  pass(1, 0);
+  pass(2, 2);                        // forward z, the product with G, inverse z
+  pass(1, 1);
+  pass(0, 1);
+  return hipGetLastError();
+}
+
 static hipError_t convolve(qhp_ctx* c, int pc, double2* grid, bool x_done = false) {
+  if (c->spme_generic) return convolve_lines(c, pc, grid);
   const int K = c->K[1];
   int nb = 0;                                      // slots per plane block (0: five passes)
   if (K == c->K[2] && (K == 64 || K == 32)) {
@@ -1524,7 +1552,6 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
   if ((part & SPME_FRONT) && c->spme_generic) {
     // grid edges that are not powers of two: the plain path
     prof_begin(c, QHP_PROF_SPREAD, &ev);
-    const size_t npts = (size_t)c->K[0] * c->K[1] * c->K[2];
     {
       // the tiled spreading (atoms binned by the list stage; every grid point written once):
       // gb beads per block, z tiles along z dividing the tile count
@@ -1566,26 +1593,7 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     prof_begin(c, QHP_PROF_FFT, &ev);
-    auto pass = [&](int axis, int mode) {
-      long inner = 1;
-      for (int d = axis + 1; d < 3; ++d) inner *= c->K[d];
-      const int K = c->K[axis];
-      const long lines = (long)(npts / K);
-      // lines per block: a power of two dividing the plane's points (or the line count),
-      // at most 1,024 complex values per LDS buffer (2,048: 181 against 153 us for the
-      // 112^3 transforms of the one-bead 21,952-water box, 512: 176 us)
-      const long div = inner > 1 ? inner : lines;
-      int nl = 1;
-      while ((long)2 * nl * K * pc <= 1024 && div % (2 * nl) == 0) nl *= 2;
-      hipLaunchKernelGGL(k_fft_line_gen, (unsigned)(lines / nl), NT,
-                         ((size_t)2 * nl * K * pc + K) * sizeof(double2), c->stream, c->grid,
-                         c->tw[axis], c->influence, K, pc, inner, nl, mode);
-    };
-    pass(0, 0);
-    pass(1, 0);
-    pass(2, 2);                      // forward z, the product with G, inverse z
-    pass(1, 1);
-    pass(0, 1);
+    if ((e = convolve(c, pc, c->grid)) != hipSuccess) return e;
     prof_end(c, QHP_PROF_FFT, ev);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else if (part & SPME_FRONT) {

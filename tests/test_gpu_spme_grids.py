@@ -88,13 +88,26 @@ def test_trajectory_on_a_grid_that_is_not_a_power_of_two():
     assert np.abs(v - vr).max() / np.abs(vr).max() < 1e-6
 
 
-def test_derivatives_need_power_of_two_grids():
+def test_derivatives_on_a_grid_that_is_not_a_power_of_two():
+    # parameter gradients and Hessian-vector products (tangent spreading, the same plain
+    # transforms on the second grid, the second-derivative gather) against the oracle
     import paper_2212_03137_amd as q
-    s = _box((24, 24, 24), 8, 4)
+    from oracle import derivs
+    s = _box((24, 40, 24), 2, 5)
+    say("spme grid derivatives", s.pme_grid)
+    dq_r, de_r, ds_r = derivs.param_gradients(s.pos, s)
+    u = np.random.default_rng(7).standard_normal(s.pos.shape)
+    ref = derivs.hvp(s.pos, s, u)
     with q.Context.from_system(s) as c:
-        with pytest.raises(q.QhpError) as e:
-            c.param_grad(s.pos)
-        assert e.value.code == q.EUNSUPPORTED
+        c.set_state(s.pos, s.vel, 0)
+        dq, de, ds = c.param_grad(s.pos)
+        got = c.hvp(s.pos, u)
+    assert np.abs(dq - dq_r).max() <= 1e-10 * np.abs(dq_r).max()
+    assert np.allclose(de, de_r, rtol=1e-10, atol=1e-10 * np.abs(de_r).max())
+    assert np.allclose(ds, ds_r, rtol=1e-10, atol=1e-10 * np.abs(ds_r).max())
+    err = np.abs(got - ref).max() / np.sqrt(np.mean(ref ** 2))
+    say(" hvp", err)
+    assert err <= 1e-6
 
 
 @pytest.mark.parametrize("Pc,nalt", [(4, 2), (5, 2)])
