@@ -112,8 +112,7 @@ typedef struct qhp_params {
   double skin;              /* neighbour-list skin: r_list = rc + skin                    */
   int32_t pme_grid[3];      /* SPME grid, each in 8..128 and >= 2*pme_order: powers of
                                two (the tuned kernels), or multiples of 8 with prime
-                               factors 2, 3, 5, 7 (a plainer, slower transform path;
-                               exec = QHP_BATCHED)                                      */
+                               factors 2, 3, 5, 7 (a plainer, slower transform path)   */
   int32_t pme_order;        /* B-spline order n: 4, 5, 6 or 8 (3 and 7: EUNSUPPORTED)    */
   int32_t precision;        /* QHP_FP64 | QHP_FP32_PAIRS                                  */
   int32_t exec;             /* QHP_BATCHED | QHP_PLAIN                                    */

@@ -218,7 +218,6 @@ int validate(const qhp_params* p, std::string& why) {
     why = "pme_order must be 4, 5, 6 or 8";
     return p->pme_order >= 3 && p->pme_order <= 8 ? QHP_EUNSUPPORTED : QHP_EINVAL;
   }
-  bool grid_pow2 = true;
   for (int d = 0; d < 3; ++d) {
     const int K = p->pme_grid[d];
     // powers of two, or multiples of 8 (the spreading tiles the atoms are binned in) whose
@@ -230,12 +229,8 @@ int validate(const qhp_params* p, std::string& why) {
       return bad("pme_grid must be in 8..128: powers of two, or multiples of 8 with prime "
                  "factors 2, 3, 5, 7");
     if (K < 2 * p->pme_order) return bad("pme_grid must be >= 2 * pme_order");
-    grid_pow2 = grid_pow2 && pow2(K);
   }
-  if (!grid_pow2 && p->exec == QHP_PLAIN) {
-    why = "SPME grids that are not powers of two need exec = QHP_BATCHED";
-    return QHP_EUNSUPPORTED;
-  }
+
   if (p->precision != QHP_FP64 && p->precision != QHP_FP32_PAIRS) return bad("precision");
   if (p->exec != QHP_BATCHED && p->exec != QHP_PLAIN) return bad("exec");
   if (p->thermostat != QHP_TRPMD && p->thermostat != QHP_ADQTB) return bad("thermostat");

@@ -363,7 +363,8 @@ __global__ __launch_bounds__(256) void k_tile_bin(TileArgs A) {
   int bc[3];
   for (int d = 0; d < 3; ++d) {
     const double cd = A.cent ? (&A.cent[a].x)[d] : A.x[(size_t)d * A.N + a];
-    bc[d] = base_of(cd, A.KoL[d], K[d]) & (K[d] - 1);
+    const int b = base_of(cd, A.KoL[d], K[d]);
+    bc[d] = b >= K[d] ? b - K[d] : b;
   }
   const int t = (bc[0] / TB * A.nt1 + bc[1] / TB) * A.nt2 + bc[2] / TB;
   A.tile_of[a] = t;
@@ -1552,6 +1553,18 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
   if ((part & SPME_FRONT) && c->spme_generic) {
     // grid edges that are not powers of two: the plain path
     prof_begin(c, QHP_PROF_SPREAD, &ev);
+    if (plain) {     // one bead of the plain mode: bin its atoms here (as below)
+      TileArgs T;
+      T.N = N; T.P = 1; T.K0 = c->K[0]; T.K1 = c->K[1]; T.K2 = c->K[2];
+      T.nt0 = c->K[0] / TB; T.nt1 = c->K[1] / TB; T.nt2 = c->K[2] / TB; T.order = c->p.pme_order;
+      T.x = A.x; T.cent = nullptr;
+      for (int d = 0; d < 3; ++d) { T.L[d] = c->p.box[d]; T.KoL[d] = c->K[d] / c->p.box[d]; }
+      T.tile_of = c->tile_of; T.tile_count = c->tile_count; T.tile_fill = c->tile_fill;
+      T.tile_start = c->tile_start; T.tile_atoms = c->tile_atoms; T.ntiles = c->ntiles;
+      hipLaunchKernelGGL(k_tile_bin, (N + 255) / 256, 256, 0, c->stream, T);
+      hipLaunchKernelGGL(k_tile_scan, 1, 256, 0, c->stream, T);
+      hipLaunchKernelGGL(k_tile_scatter, (N + 255) / 256, 256, 0, c->stream, T);
+    }
     {
       // the tiled spreading (atoms binned by the list stage; every grid point written once):
       // gb beads per block, z tiles along z dividing the tile count
@@ -1559,7 +1572,7 @@ hipError_t launch_spme(qhp_ctx* c, bool energy, int bead, const BeadSet* bs, int
       S.N = N; S.P = P; S.K0 = c->K[0]; S.K1 = c->K[1]; S.K2 = c->K[2];
       S.nt1 = c->K[1] / TB; S.nt2 = c->K[2] / TB; S.Pc2 = 2 * pc;
       S.x = A.x; S.grid = A.grid; S.charge = c->d_charge;
-      S.cent = c->cent; S.ctrl = c->ctrl;
+      S.cent = plain ? nullptr : c->cent; S.ctrl = c->ctrl;
       for (int d = 0; d < 3; ++d) { S.L[d] = c->p.box[d]; S.KoL[d] = c->K[d] / c->p.box[d]; }
       S.tile_start = c->tile_start; S.tile_atoms = c->tile_atoms;
       int gb = c->spread_gb > 0 ? c->spread_gb : 8;

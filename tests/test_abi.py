@@ -121,4 +121,4 @@ def test_spme_grids_validated_before_device_use(grid, code):
     if code == "device":
         with pytest.raises(q.QhpError) as e:
             q.Context.from_system(s, exec_mode=q.PLAIN)
-        assert e.value.code == q.EUNSUPPORTED
+        assert e.value.code == q.EDEVICE

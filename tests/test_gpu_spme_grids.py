@@ -37,12 +37,12 @@ def test_eval_on_grids_that_are_not_powers_of_two(grid, n_beads, order):
     s = _box(grid, n_beads, order)
     say("spme grid", grid, "beads", n_beads, "order", order)
     Eref, Fref = ofo.evaluate(s.pos, s)
-    for prec in (q.FP64, q.FP32_PAIRS):
-        with q.Context.from_system(s, precision=prec) as c:
+    for prec, mode in ((q.FP64, q.BATCHED), (q.FP32_PAIRS, q.BATCHED), (q.FP64, q.PLAIN)):
+        with q.Context.from_system(s, precision=prec, exec_mode=mode) as c:
             E, F = c.eval(s.pos)
         # the reciprocal energy and every force against the oracle's own FFT of the same grid
         recip = np.abs(E[:, 6] - Eref[:, 6]).max() / np.abs(Eref[:, 6]).max()
-        say(" prec", prec, "recip", recip, "F", rel_max(F, Fref))
+        say(" prec", prec, "mode", mode, "recip", recip, "F", rel_max(F, Fref))
         assert recip <= 1e-11
         assert rel_max(F, Fref) <= (1e-11 if prec == q.FP64 else 1e-5)
 
