@@ -230,7 +230,6 @@ int validate(const qhp_params* p, std::string& why) {
                  "factors 2, 3, 5, 7");
     if (K < 2 * p->pme_order) return bad("pme_grid must be >= 2 * pme_order");
   }
-
   if (p->precision != QHP_FP64 && p->precision != QHP_FP32_PAIRS) return bad("precision");
   if (p->exec != QHP_BATCHED && p->exec != QHP_PLAIN) return bad("exec");
   if (p->thermostat != QHP_TRPMD && p->thermostat != QHP_ADQTB) return bad("thermostat");
