@@ -194,7 +194,8 @@ def test_bspline_partition_of_unity():
 
 
 @pytest.mark.parametrize("K,n,tol", [((16, 16, 16), 4, 5e-3), ((32, 32, 32), 6, 2e-6),
-                                     ((40, 36, 32), 8, 1e-6)])
+                                     ((40, 36, 32), 8, 1e-6), ((56, 24, 40), 6, 1e-6),
+                                     ((24, 24, 24), 4, 5e-4)])
 def test_spme_converges_to_classic_ewald(box64, K, n, tol):
     s = box64
     x = s.pos[0]
