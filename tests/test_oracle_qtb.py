@@ -21,8 +21,10 @@ def test_theta_limits():
     assert np.all(qtb.theta(om, KT, HBAR, classical=True) == KT)
 
 
-def test_kernel_white_limit_is_delta_and_parseval():
-    m, g0, dt, nseg = 16.0 * synth.AMU, 0.02, 0.5, 64
+@pytest.mark.parametrize("nseg", [64, 40, 56])
+def test_kernel_white_limit_is_delta_and_parseval(nseg):
+    # also at segment lengths with factors 5 and 7
+    m, g0, dt = 16.0 * synth.AMU, 0.02, 0.5
     h = qtb.kernel(np.full(nseg + 1, g0), m, KT, HBAR, dt, classical=True)
     d = np.zeros(2 * nseg); d[nseg] = math.sqrt(2 * m * g0 * KT / dt)
     assert np.allclose(h, d, atol=1e-12 * d.max())
@@ -37,9 +39,10 @@ def test_kernel_white_limit_is_delta_and_parseval():
     assert math.isclose((h ** 2).sum(), (Hf ** 2).sum() / (2 * nseg), rel_tol=1e-12)
 
 
-def test_segmented_noise_equals_one_long_convolution():
+@pytest.mark.parametrize("nseg", [16, 24])
+def test_segmented_noise_equals_one_long_convolution(nseg):
     # the three-segment window keeps the noise consistent across segment boundaries
-    nseg, N, seed = 16, 3, 9
+    N, seed = 3, 9
     rng = np.random.default_rng(0)
     h = rng.standard_normal((N, 2 * nseg))
     segs = [qtb.colored_segment(h, seed, s, nseg, N) for s in range(3)]
