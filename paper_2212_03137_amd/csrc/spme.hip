@@ -1322,24 +1322,32 @@ __global__ __launch_bounds__(512 * NB) __attribute__((amdgpu_waves_per_eu(4))) v
 // contiguous). With inner > 1 the block's lines are nl neighbouring points of one plane
 // (nl divides inner), so the slots of the nl lines at one e are contiguous; with
 // inner = 1 each line is contiguous. Consecutive threads take consecutive addresses.
-QHP_DEV void line_point(int i, int K, int pc, int nl, long inner, long l0, long base0, int& j,
-                        int& e, int& sl, long& pt) {
-  sl = i % pc;
-  const int r = i / pc;
+// PC (slots) and nl (lines, 2^lgnl) are powers of two: shifts and masks; the one division
+// left, by K, is a double-precision multiply by 1/K (exact for these small integers)
+template <int PC>
+QHP_DEV void line_point(int i, int K, double invK, int lgnl, long inner, long l0, long base0,
+                        int& j, int& e, int& sl, long& pt) {
+  constexpr int LGPC = __builtin_ctz(PC);
+  sl = i & (PC - 1);
+  const int r = i >> LGPC;
   if (inner > 1) {
-    j = r % nl; e = r / nl;
+    j = r & ((1 << lgnl) - 1); e = r >> lgnl;
     pt = base0 + j + (long)e * inner;
   } else {
-    e = r % K; j = r / K;
-    pt = (l0 + j) * K + e;
+    j = (int)(((double)r + 0.5) * invK); e = r - j * K;
+    pt = l0 * K + r;
   }
 }
 
 // mode 0: forward, 1: inverse, 2: forward, times G, inverse (one visit of the last axis)
+template <int PC>
 __global__ __launch_bounds__(NT) void k_fft_line_gen(double2* grid, const double2* tw,
-                                                     const double* G, int K, int pc, long inner,
-                                                     int nl, int mode) {
+                                                     const double* G, int K, long inner,
+                                                     int lgnl, int mode) {
   extern __shared__ double2 lbuf[];
+  constexpr int pc = PC;
+  const int nl = 1 << lgnl;
+  const double invK = 1.0 / K;
   const int ns = nl * pc, n = K * ns;
   double2* a = lbuf;
   double2* b = lbuf + (size_t)n;
@@ -1350,7 +1358,7 @@ __global__ __launch_bounds__(NT) void k_fft_line_gen(double2* grid, const double
   for (int i = threadIdx.x; i < n; i += NT) {
     int j, e, sl;
     long pt;
-    line_point(i, K, pc, nl, inner, l0, base0, j, e, sl, pt);
+    line_point<PC>(i, K, invK, lgnl, inner, l0, base0, j, e, sl, pt);
     a[(size_t)(j * pc + sl) * K + e] = grid[pt * pc + sl];
   }
   __syncthreads();
@@ -1359,7 +1367,7 @@ __global__ __launch_bounds__(NT) void k_fft_line_gen(double2* grid, const double
     for (int i = threadIdx.x; i < n; i += NT) {
       int j, e, sl;
       long pt;
-      line_point(i, K, pc, nl, inner, l0, base0, j, e, sl, pt);
+      line_point<PC>(i, K, invK, lgnl, inner, l0, base0, j, e, sl, pt);
       double2& v = r[(size_t)(j * pc + sl) * K + e];
       const double g = G[pt];
       v.x *= g;
@@ -1371,7 +1379,7 @@ __global__ __launch_bounds__(NT) void k_fft_line_gen(double2* grid, const double
   for (int i = threadIdx.x; i < n; i += NT) {
     int j, e, sl;
     long pt;
-    line_point(i, K, pc, nl, inner, l0, base0, j, e, sl, pt);
+    line_point<PC>(i, K, invK, lgnl, inner, l0, base0, j, e, sl, pt);
     grid[pt * pc + sl] = r[(size_t)(j * pc + sl) * K + e];
   }
 }
@@ -1447,11 +1455,22 @@ static hipError_t convolve_lines(qhp_ctx* c, int pc, double2* grid) {
     // at most 1,024 complex values per LDS buffer (2,048: 181 against 153 us for the
     // 112^3 transforms of the one-bead 21,952-water box, 512: 176 us)
     const long div = inner > 1 ? inner : lines;
-    int nl = 1;
-    while ((long)2 * nl * K * pc <= 1024 && div % (2 * nl) == 0) nl *= 2;
-    hipLaunchKernelGGL(k_fft_line_gen, (unsigned)(lines / nl), NT,
-                       ((size_t)2 * nl * K * pc + K) * sizeof(double2), c->stream, grid,
-                       c->tw[axis], c->influence, K, pc, inner, nl, mode);
+    int lgnl = 0;
+    while ((long)2 * (2 << lgnl) * K * pc <= 2048 && div % (2 << lgnl) == 0) ++lgnl;
+    const unsigned blocks = (unsigned)(lines >> lgnl);
+    const size_t lds = ((size_t)2 * (1 << lgnl) * K * pc + K) * sizeof(double2);
+#define LINE_CALL(PCV)                                                                        \
+    hipLaunchKernelGGL((k_fft_line_gen<PCV>), blocks, NT, lds, c->stream, grid, c->tw[axis], \
+                       c->influence, K, inner, lgnl, mode)
+    switch (pc) {
+      case 1: LINE_CALL(1); break;
+      case 2: LINE_CALL(2); break;
+      case 4: LINE_CALL(4); break;
+      case 8: LINE_CALL(8); break;
+      case 16: LINE_CALL(16); break;
+      default: LINE_CALL(32); break;
+    }
+#undef LINE_CALL
   };
   pass(0, 0);
   pass(1, 0);
